@@ -1,0 +1,201 @@
+/*
+ * fem.h -- C ABI of libfem.so: element-based P1 finite-element operators and
+ * solvers for -Laplace(u) + nu u = f on MI355X (gfx950).
+ *
+ * Method (Marcinkowski & Valdman, "MATLAB Implementation of Element-based
+ * Solvers"): the local stiffness and mass matrices K_e, M_e of every element
+ * are built at once and kept as element arrays (Section 1, eq. (2)-(3));
+ * the residual r = b - A x with A = sum_e C_e^T (K_e + nu M_e) C_e is formed
+ * element by element without ever assembling a sparse matrix (Section 2,
+ * eq. (4), Algorithm 1), and iterative solvers are driven by it.
+ *
+ * Conventions shared by every entry point
+ *  - Device memory: every d_* pointer is caller-owned device memory on the
+ *    current HIP device.  The library never frees it.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  All
+ *    calls only enqueue work on it and return before it runs, except
+ *    fem_plan_create and the solvers, which synchronise `stream` before
+ *    returning.
+ *  - Layouts (structure of arrays, n_b = dim + 1):
+ *      coordinates      double [dim][n_nodes]
+ *      connectivity     int32  [n_b][n_elems], 0-based node ids
+ *      element matrices [n_b*n_b][n_elems]: entry (i,j) of element e at
+ *                       (i*n_b + j)*n_elems + e, element order as given to
+ *                       fem_plan_create.
+ *      dtype FEM_F64    double entries
+ *      dtype FEM_F32    float entries
+ *      dtype FEM_F32X2  float [2][n_b*n_b][n_elems]: first block hi = fl32(a),
+ *                       second block lo = fl32(a - hi); hi + lo represents the
+ *                       FP64 value to about 2^-48 relative.
+ *      nodal vectors    double [n_nodes] unless the name says f32.
+ *  - Errors: every function returns a fem_status; nothing is launched when
+ *    argument validation fails.  fem_last_error() returns a thread-local
+ *    message for the last failure.  No C++ exception crosses this boundary.
+ *  - Determinism: no floating-point atomics are used; each node's sum is
+ *    taken in a fixed order, so repeated calls give bitwise identical results.
+ */
+#ifndef FEM_H
+#define FEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FEM_OK = 0,
+    FEM_EINVAL = -1,      /* bad size, pointer, index, element or parameter */
+    FEM_EHIP = -2,        /* a HIP runtime call failed */
+    FEM_ENOCONV = -3,     /* iteration limit reached; last iterate kept */
+    FEM_ESINGULAR = -4,   /* nu = 0 without Dirichlet nodes (Section 1) */
+    FEM_EBREAKDOWN = -5,  /* p^T A p <= 0 or a non-finite scalar in CG */
+    FEM_ENOMEM = -6       /* device or host allocation failed */
+} fem_status;
+
+typedef enum { FEM_F64 = 0, FEM_F32 = 1, FEM_F32X2 = 2 } fem_dtype;
+
+typedef enum { FEM_PRECOND_NONE = 0, FEM_PRECOND_JACOBI = 1 } fem_precond;
+
+typedef struct fem_plan fem_plan; /* opaque */
+
+typedef struct {
+    int dim, n_b;
+    int64_t n_nodes, n_elems;
+    int64_t n_dirichlet;
+    int chunk_elems;          /* elements per chunk (one workgroup pass) */
+    int64_t n_chunks;
+    int64_t n_local;          /* sum over chunks of distinct nodes touched */
+    int64_t n_shared;         /* nodes touched by more than one chunk */
+    int64_t n_partials;       /* (chunk, shared node) pairs */
+    int64_t index_bytes;      /* device bytes of the plan's index arrays */
+} fem_plan_stats;
+
+/* Build the device plan of a simplicial mesh (Section 1: the element -> node
+ * tables that replace the Boolean C_e / R_e of eq. (3) and Algorithm 1).
+ *  dim            2 (triangles, n_b = 3) or 3 (tetrahedra, n_b = 4)
+ *  d_coords       double [dim][n_nodes]   (read; not kept)
+ *  d_conn         int32  [n_b][n_elems]   (read; not kept)
+ *  d_dirichlet    int32  [n_dirichlet] node ids of the Dirichlet part nd
+ *                 (duplicates allowed; may be NULL when n_dirichlet = 0)
+ *  chunk_elems    elements per chunk, 0 = default; 64 <= chunk_elems <= 8192
+ *                 and a multiple of 64
+ * The plan partitions the element list into chunks of consecutive elements;
+ * element orders with spatial locality (e.g. a Morton order of the cells)
+ * give compact chunks and the fewest shared nodes.  Errors: FEM_EINVAL for a
+ * node id out of range, repeated nodes in an element, a Dirichlet id out of
+ * range or a degenerate (zero-volume) element; FEM_ENOMEM; FEM_EHIP. */
+int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_coords,
+                    const int32_t *d_conn, const int32_t *d_dirichlet, int64_t n_dirichlet,
+                    int chunk_elems, void *stream, fem_plan **out);
+
+/* Host-only dry run of fem_plan_create on host arrays (coords double
+ * [dim][n_nodes], conn int32 [n_b][n_elems], dirichlet int32 [n_dirichlet]):
+ * the same validation and chunking, no device memory and no HIP call.  Fills
+ * *out (index_bytes counts the arrays that fem_plan_create would upload).
+ * Useful to validate a mesh or size a plan on a machine without a GPU. */
+int fem_plan_check_host(int dim, int64_t n_nodes, int64_t n_elems, const double *coords,
+                        const int32_t *conn, const int32_t *dirichlet, int64_t n_dirichlet,
+                        int chunk_elems, fem_plan_stats *out);
+
+/* Free the plan and all device memory it owns.  NULL is accepted. */
+int fem_plan_destroy(fem_plan *plan);
+
+/* Sizes of the plan (host struct, caller-owned). */
+int fem_plan_get_stats(const fem_plan *plan, fem_plan_stats *out);
+
+/* Local matrices of every element (Section 1, eq. (2) restricted to one
+ * element, computed for all elements at once as in Section 1):
+ *   vol  = |det B| / dim!,  B = [p_1 - p_0, ..., p_dim - p_0]
+ *   K_e  = vol * G G^T,  G = D_ref B^{-1},  D_ref = [-1 ... -1 ; I]
+ *   M_e  = vol / ((dim+1)(dim+2)) * (1 + delta_ij)
+ * computed in FP64 and stored in `dtype`.  d_K_e / d_M_e / d_vol (double
+ * [n_elems]) may each be NULL to skip that output. */
+int fem_build_local_matrices(const fem_plan *plan, int dtype, void *d_K_e, void *d_M_e,
+                             double *d_vol, void *stream);
+
+/* A_e = K_e + nu M_e (definition under Algorithm 1), evaluated in FP64 from
+ * inputs of dtype_in and stored as dtype_out.  d_M_e may be NULL (A_e = K_e).
+ * Output must not alias the inputs. */
+int fem_combine_local(const fem_plan *plan, int dtype_in, const void *d_K_e, const void *d_M_e,
+                      double nu, int dtype_out, void *d_A_e, void *stream);
+
+/* Residual r = b - sum_e C_e^T (K_e + nu M_e) C_e x  (eq. (4), Algorithm 1),
+ * computed in FP64 from local matrices of `dtype` (FEM_F32X2 uses hi + lo).
+ * d_M_e may be NULL (then A_e = K_e and nu is ignored); d_b may be NULL
+ * (b = 0, i.e. r = -A x).  With mask_dirichlet != 0 the rows of the Dirichlet
+ * nodes are set to 0 (r(nd) = 0 in the Section 2 listings).  d_r must not
+ * alias d_x or d_b. */
+int fem_element_residual(const fem_plan *plan, int dtype, const void *d_K_e, const void *d_M_e,
+                         double nu, const double *d_b, const double *d_x, double *d_r,
+                         int mask_dirichlet, void *stream);
+
+/* The same residual entirely in FP32: combined local matrices d_A_e (float,
+ * [n_b*n_b][n_elems]), float vectors and float accumulation.  This is the
+ * inner operator of the mixed-precision solver.  d_b may be NULL. */
+int fem_element_residual_f32(const fem_plan *plan, const float *d_A_e, const float *d_b,
+                             const float *d_x, float *d_r, int mask_dirichlet, void *stream);
+
+/* Diagonal of the assembled operator, d_i = sum_{e contains i} (A_e)_{ii},
+ * A_e = K_e + nu M_e (Jacobi preconditioner).  Rows of Dirichlet nodes are
+ * not masked. */
+int fem_jacobi_diag(const fem_plan *plan, int dtype, const void *d_K_e, const void *d_M_e,
+                    double nu, double *d_diag, void *stream);
+
+/* Right-hand side b = sum_e C_e^T M_e f_e (eq. (2) with f replaced by its
+ * nodal interpolant d_f, eq. (3) assembly), FP64. */
+int fem_assemble_rhs(const fem_plan *plan, int dtype, const void *d_M_e, const double *d_f,
+                     double *d_b, void *stream);
+
+typedef struct {
+    int dtype;          /* FEM_F64: FP64 throughout.  FEM_F32X2 or FEM_F32:
+                           FP32 inner CG (FP32 matrices and vectors, FP64 dot
+                           products and alpha/beta) inside FP64 iterative
+                           refinement whose residual uses the full inputs. */
+    double nu;          /* >= 0 */
+    double rtol;        /* stop at ||b - A x||_2 <= rtol ||b - A x0||_2 */
+    int max_iter;       /* cap on CG iterations (inner ones summed) */
+    int precond;        /* fem_precond */
+    double inner_rtol;  /* mixed precision: inner relative tolerance */
+    int max_outer;      /* mixed precision: cap on refinement steps */
+    int check_every;    /* host reads the convergence flag every k iterations */
+    int profile;        /* record HIP events around every `profile`-th matvec */
+} fem_solve_opts;
+
+typedef struct {
+    int status;          /* fem_status of the solve */
+    int iters;           /* CG iterations performed (all inner ones) */
+    int outer;           /* refinement steps (mixed precision), else 0 */
+    int replacements;    /* FP64 residual replacements after the recursive
+                            residual met rtol but the true one did not */
+    double relres;       /* true FP64 ||b - A x||_2 / ||b - A x0||_2 (masked) */
+    double r0;           /* ||b - A x0||_2 (masked) */
+    double seconds;      /* host wall time of the call */
+    double matvec_ms;    /* profile: summed time of the timed matvecs */
+    int matvec_samples;  /* profile: number of timed matvecs */
+    int matvec_calls;    /* matvecs issued (inner + outer residuals) */
+} fem_solve_info;
+
+void fem_solve_opts_default(fem_solve_opts *o);
+
+/* Preconditioned conjugate gradients for (K + nu M) u = b with the Dirichlet
+ * rows masked (Section 1 problem, residual of eq. (4) with r(nd) = 0).
+ * d_K_e, d_M_e are the local matrices in opts->dtype layout (d_M_e may be NULL
+ * when nu = 0).  d_x holds x0 on entry, including the Dirichlet values on nd,
+ * and the last iterate on exit.  Returns FEM_OK, FEM_ENOCONV (iteration cap;
+ * d_x holds the last iterate and info is filled), FEM_EBREAKDOWN,
+ * FEM_ESINGULAR (nu == 0 and no Dirichlet node), FEM_EINVAL.  The plan keeps
+ * per-dtype workspace that is allocated on the first solve; the iterations
+ * themselves allocate nothing.  Synchronises `stream` before returning. */
+int fem_pcg_solve(const fem_plan *plan, const fem_solve_opts *opts, const void *d_K_e,
+                  const void *d_M_e, const double *d_b, double *d_x, fem_solve_info *info,
+                  void *stream);
+
+/* Thread-local message describing the last failure ("" if none). */
+const char *fem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEM_H */

@@ -1,0 +1,425 @@
+// api.hip -- the C ABI of libfem (declared in include/fem.h): argument
+// validation, plan ownership and dispatch to the kernels.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "chunk.h"
+#include "fem.h"
+#include "kernels.h"
+#include "plan.h"
+#include "solver.h"
+
+namespace fem {
+
+std::string &last_error() {
+    static thread_local std::string msg;
+    return msg;
+}
+
+int set_error(int code, const std::string &msg) {
+    last_error() = msg;
+    return code;
+}
+
+}  // namespace fem
+
+struct fem_plan {
+    fem::DevPlan dev{};
+    fem_plan_stats stats{};
+    void *arena = nullptr;
+    double *scratch64 = nullptr;
+    float *scratch32 = nullptr;
+    int64_t n_isolated_free = 0;
+    fem::SolverWork work[2];  // [0] FP64 solver, [1] mixed precision
+};
+
+namespace {
+
+using fem::set_error;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct ArenaLayout {
+    size_t total = 0;
+    size_t add(size_t bytes) {
+        size_t off = total;
+        total = align_up(total + std::max<size_t>(bytes, 1));
+        return off;
+    }
+};
+
+bool valid_dtype(int t) { return t == FEM_F64 || t == FEM_F32 || t == FEM_F32X2; }
+
+int check_plan(const fem_plan *p) {
+    if (!p) return set_error(FEM_EINVAL, "plan is NULL");
+    return FEM_OK;
+}
+
+hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+int alloc_work(fem_plan *plan, int slot, int dtype) {
+    fem::SolverWork &w = plan->work[slot];
+    if (w.arena) return FEM_OK;
+    const fem::DevPlan &P = plan->dev;
+    const int64_t n = P.n_nodes;
+    const int64_t ent = (int64_t)P.nb * P.nb * P.n_elems;
+    const bool mixed = slot == 1;
+    const fem::Grids gr = fem::solver_grids(P, fem::chunk_lds_bytes<3, double>(P.E) / 3 * P.nb);
+    ArenaLayout L;
+    size_t oA = L.add(mixed ? (size_t)ent * 2 * sizeof(float) : (size_t)ent * sizeof(double));
+    size_t od = L.add(n * sizeof(double));
+    size_t odi64 = L.add(mixed ? 0 : n * sizeof(double));
+    size_t or64 = L.add(n * sizeof(double));
+    size_t op64 = L.add(mixed ? 0 : n * sizeof(double));
+    size_t oq64 = L.add(n * sizeof(double));
+    size_t odi32 = L.add(mixed ? n * sizeof(float) : 0);
+    size_t or32 = L.add(mixed ? n * sizeof(float) : 0);
+    size_t op32 = L.add(mixed ? n * sizeof(float) : 0);
+    size_t oq32 = L.add(mixed ? n * sizeof(float) : 0);
+    size_t oxc = L.add(mixed ? n * sizeof(float) : 0);
+    size_t opart64 = L.add(std::max<int64_t>(P.n_partials, 1) * sizeof(double));
+    size_t opart32 = L.add(mixed ? std::max<int64_t>(P.n_partials, 1) * sizeof(float) : 0);
+    size_t oupd = L.add((size_t)3 * 1024 * sizeof(double));
+    // p.q partials: the main grid is at most 8 blocks per CU whatever the
+    // vector precision, plus the fix-up grid
+    size_t omv = L.add((size_t)(8 * fem::device_cu_count() + gr.gf + 8) * sizeof(double));
+    size_t ost = L.add(sizeof(fem::SolveState));
+    size_t obad = L.add(sizeof(int));
+    void *arena = nullptr;
+    if (hipMalloc(&arena, L.total) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(FEM_ENOMEM, "device allocation of the solver workspace failed");
+    }
+    char *b = static_cast<char *>(arena);
+    w.arena = arena;
+    w.bytes = L.total;
+    w.kind = dtype;
+    w.A = b + oA;
+    w.d64 = reinterpret_cast<double *>(b + od);
+    w.dinv64 = reinterpret_cast<double *>(b + odi64);
+    w.r64 = reinterpret_cast<double *>(b + or64);
+    w.p64 = reinterpret_cast<double *>(b + op64);
+    w.q64 = reinterpret_cast<double *>(b + oq64);
+    w.dinv32 = reinterpret_cast<float *>(b + odi32);
+    w.r32 = reinterpret_cast<float *>(b + or32);
+    w.p32 = reinterpret_cast<float *>(b + op32);
+    w.q32 = reinterpret_cast<float *>(b + oq32);
+    w.xc32 = reinterpret_cast<float *>(b + oxc);
+    w.part64 = reinterpret_cast<double *>(b + opart64);
+    w.part32 = reinterpret_cast<float *>(b + opart32);
+    w.upd = reinterpret_cast<double *>(b + oupd);
+    w.mv = reinterpret_cast<double *>(b + omv);
+    w.st = reinterpret_cast<fem::SolveState *>(b + ost);
+    w.bad = reinterpret_cast<int *>(b + obad);
+    return FEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fem_last_error(void) { return fem::last_error().c_str(); }
+
+void fem_solve_opts_default(fem_solve_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->dtype = FEM_F64;
+    o->nu = 0.0;
+    o->rtol = 1e-8;
+    o->max_iter = 100000;
+    o->precond = FEM_PRECOND_JACOBI;
+    o->inner_rtol = 0.1;
+    o->max_outer = 200;
+    o->check_every = 32;
+    o->profile = 0;
+}
+
+int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_coords, const int32_t *d_conn,
+                    const int32_t *d_dirichlet, int64_t n_dirichlet, int chunk_elems, void *stream,
+                    fem_plan **out) {
+    fem::last_error().clear();
+    if (!out) return set_error(FEM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (dim != 2 && dim != 3) return set_error(FEM_EINVAL, "dim must be 2 or 3");
+    if (n_nodes < 1 || n_nodes > INT32_MAX) return set_error(FEM_EINVAL, "n_nodes must be in [1, 2^31)");
+    if (n_elems < 0 || n_elems > INT32_MAX) return set_error(FEM_EINVAL, "n_elems must be in [0, 2^31)");
+    if (!d_coords) return set_error(FEM_EINVAL, "coords is NULL");
+    if (n_elems > 0 && !d_conn) return set_error(FEM_EINVAL, "conn is NULL");
+    if (n_dirichlet < 0 || (n_dirichlet > 0 && !d_dirichlet)) return set_error(FEM_EINVAL, "bad Dirichlet list");
+    const int nb = dim + 1;
+    if (chunk_elems == 0) chunk_elems = fem::default_chunk_elems(nb);
+    if (chunk_elems < 64 || chunk_elems % 64 != 0 || chunk_elems > fem::max_chunk_elems(nb))
+        return set_error(FEM_EINVAL, "chunk_elems must be a multiple of 64 in [64, " +
+                                         std::to_string(fem::max_chunk_elems(nb)) + "]");
+    hipStream_t s = S(stream);
+    std::vector<double> coords((size_t)dim * n_nodes);
+    std::vector<int32_t> conn((size_t)nb * n_elems);
+    std::vector<int32_t> dir((size_t)n_dirichlet);
+    FEM_HIP_CHECK(hipMemcpyAsync(coords.data(), d_coords, coords.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (n_elems)
+        FEM_HIP_CHECK(hipMemcpyAsync(conn.data(), d_conn, conn.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (n_dirichlet)
+        FEM_HIP_CHECK(
+            hipMemcpyAsync(dir.data(), d_dirichlet, dir.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    FEM_HIP_CHECK(hipStreamSynchronize(s));
+    for (double c : coords)
+        if (!std::isfinite(c)) return set_error(FEM_EINVAL, "non-finite coordinate");
+    fem::HostPlan H;
+    std::string err;
+    try {
+        if (fem::build_host_plan(dim, n_nodes, n_elems, coords.data(), conn.data(), dir.data(), n_dirichlet,
+                                 chunk_elems, H, err) != 0)
+            return set_error(FEM_EINVAL, err);
+    } catch (const std::bad_alloc &) {
+        return set_error(FEM_ENOMEM, "host allocation failed while building the plan");
+    }
+    ArenaLayout L;
+    const size_t o_coords = L.add(coords.size() * sizeof(double));
+    const size_t o_conn = L.add(conn.size() * sizeof(int32_t));
+    const size_t o_cno = L.add(H.chunk_node_off.size() * sizeof(int32_t));
+    const size_t o_cin = L.add(H.chunk_info.size() * sizeof(int32_t));
+    const size_t o_ln = L.add(H.loc_nodes.size() * sizeof(int32_t));
+    const size_t o_le = L.add(H.loc_end.size() * sizeof(uint16_t));
+    const size_t o_sl = L.add(H.slots.size() * sizeof(uint16_t));
+    const size_t o_fn = L.add(H.fix_nodes.size() * sizeof(int32_t));
+    const size_t o_fo = L.add(H.fix_off.size() * sizeof(int32_t));
+    const size_t o_fp = L.add(H.fix_parts.size() * sizeof(int32_t));
+    const size_t o_mask = L.add(H.mask.size());
+    const size_t o_s64 = L.add(std::max<int64_t>(H.n_partials, 1) * sizeof(double));
+    const size_t o_s32 = L.add(std::max<int64_t>(H.n_partials, 1) * sizeof(float));
+    fem_plan *plan = new (std::nothrow) fem_plan();
+    if (!plan) return set_error(FEM_ENOMEM, "host allocation failed");
+    if (hipMalloc(&plan->arena, L.total) != hipSuccess) {
+        (void)hipGetLastError();
+        delete plan;
+        return set_error(FEM_ENOMEM, "device allocation of the plan failed");
+    }
+    char *b = static_cast<char *>(plan->arena);
+    auto up = [&](size_t off, const void *src, size_t bytes) -> int {
+        if (bytes == 0) return 0;
+        return hipMemcpyAsync(b + off, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess ? 0 : -1;
+    };
+    int bad = 0;
+    bad |= up(o_coords, coords.data(), coords.size() * sizeof(double));
+    bad |= up(o_conn, conn.data(), conn.size() * sizeof(int32_t));
+    bad |= up(o_cno, H.chunk_node_off.data(), H.chunk_node_off.size() * sizeof(int32_t));
+    bad |= up(o_cin, H.chunk_info.data(), H.chunk_info.size() * sizeof(int32_t));
+    bad |= up(o_ln, H.loc_nodes.data(), H.loc_nodes.size() * sizeof(int32_t));
+    bad |= up(o_le, H.loc_end.data(), H.loc_end.size() * sizeof(uint16_t));
+    bad |= up(o_sl, H.slots.data(), H.slots.size() * sizeof(uint16_t));
+    bad |= up(o_fn, H.fix_nodes.data(), H.fix_nodes.size() * sizeof(int32_t));
+    bad |= up(o_fo, H.fix_off.data(), H.fix_off.size() * sizeof(int32_t));
+    bad |= up(o_fp, H.fix_parts.data(), H.fix_parts.size() * sizeof(int32_t));
+    bad |= up(o_mask, H.mask.data(), H.mask.size());
+    if (bad || hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(plan->arena);
+        delete plan;
+        return set_error(FEM_EHIP, "upload of the plan failed");
+    }
+    fem::DevPlan &D = plan->dev;
+    D.dim = dim;
+    D.nb = nb;
+    D.E = chunk_elems;
+    D.n_nodes = n_nodes;
+    D.n_elems = n_elems;
+    D.n_chunks = H.n_chunks;
+    D.n_local = H.n_local;
+    D.n_shared = H.n_shared;
+    D.n_partials = H.n_partials;
+    D.coords = reinterpret_cast<const double *>(b + o_coords);
+    D.conn = reinterpret_cast<const int32_t *>(b + o_conn);
+    D.chunk_node_off = reinterpret_cast<const int32_t *>(b + o_cno);
+    D.chunk_info = reinterpret_cast<const int32_t *>(b + o_cin);
+    D.loc_nodes = reinterpret_cast<const int32_t *>(b + o_ln);
+    D.loc_end = reinterpret_cast<const uint16_t *>(b + o_le);
+    D.slots = reinterpret_cast<const uint16_t *>(b + o_sl);
+    D.fix_nodes = reinterpret_cast<const int32_t *>(b + o_fn);
+    D.fix_off = reinterpret_cast<const int32_t *>(b + o_fo);
+    D.fix_parts = reinterpret_cast<const int32_t *>(b + o_fp);
+    D.mask = reinterpret_cast<const uint8_t *>(b + o_mask);
+    plan->scratch64 = reinterpret_cast<double *>(b + o_s64);
+    plan->scratch32 = reinterpret_cast<float *>(b + o_s32);
+    plan->n_isolated_free = H.n_isolated_free;
+    fem_plan_stats &st = plan->stats;
+    st.dim = dim;
+    st.n_b = nb;
+    st.n_nodes = n_nodes;
+    st.n_elems = n_elems;
+    st.n_dirichlet = H.n_dirichlet;
+    st.chunk_elems = chunk_elems;
+    st.n_chunks = H.n_chunks;
+    st.n_local = H.n_local;
+    st.n_shared = H.n_shared;
+    st.n_partials = H.n_partials;
+    st.index_bytes = (int64_t)(o_s64 - o_cno);
+    *out = plan;
+    return FEM_OK;
+}
+
+int fem_plan_check_host(int dim, int64_t n_nodes, int64_t n_elems, const double *coords, const int32_t *conn,
+                        const int32_t *dirichlet, int64_t n_dirichlet, int chunk_elems, fem_plan_stats *out) {
+    fem::last_error().clear();
+    if (!out) return set_error(FEM_EINVAL, "out is NULL");
+    if (dim != 2 && dim != 3) return set_error(FEM_EINVAL, "dim must be 2 or 3");
+    if (n_nodes < 1 || n_nodes > INT32_MAX) return set_error(FEM_EINVAL, "n_nodes must be in [1, 2^31)");
+    if (n_elems < 0 || n_elems > INT32_MAX) return set_error(FEM_EINVAL, "n_elems must be in [0, 2^31)");
+    if (!coords || (n_elems > 0 && !conn)) return set_error(FEM_EINVAL, "NULL argument");
+    if (n_dirichlet < 0 || (n_dirichlet > 0 && !dirichlet)) return set_error(FEM_EINVAL, "bad Dirichlet list");
+    const int nb = dim + 1;
+    if (chunk_elems == 0) chunk_elems = fem::default_chunk_elems(nb);
+    if (chunk_elems < 64 || chunk_elems % 64 != 0 || chunk_elems > fem::max_chunk_elems(nb))
+        return set_error(FEM_EINVAL, "chunk_elems must be a multiple of 64 in [64, " +
+                                         std::to_string(fem::max_chunk_elems(nb)) + "]");
+    for (int64_t i = 0; i < (int64_t)dim * n_nodes; ++i)
+        if (!std::isfinite(coords[i])) return set_error(FEM_EINVAL, "non-finite coordinate");
+    fem::HostPlan H;
+    std::string err;
+    try {
+        if (fem::build_host_plan(dim, n_nodes, n_elems, coords, conn, dirichlet, n_dirichlet, chunk_elems, H, err))
+            return set_error(FEM_EINVAL, err);
+    } catch (const std::bad_alloc &) {
+        return set_error(FEM_ENOMEM, "host allocation failed while building the plan");
+    }
+    std::memset(out, 0, sizeof(*out));
+    out->dim = dim;
+    out->n_b = nb;
+    out->n_nodes = n_nodes;
+    out->n_elems = n_elems;
+    out->n_dirichlet = H.n_dirichlet;
+    out->chunk_elems = chunk_elems;
+    out->n_chunks = H.n_chunks;
+    out->n_local = H.n_local;
+    out->n_shared = H.n_shared;
+    out->n_partials = H.n_partials;
+    out->index_bytes = (int64_t)(H.chunk_node_off.size() * 4 + H.chunk_info.size() * 4 + H.loc_nodes.size() * 4 +
+                                 H.loc_end.size() * 2 + H.slots.size() * 2 + H.fix_nodes.size() * 4 +
+                                 H.fix_off.size() * 4 + H.fix_parts.size() * 4 + H.mask.size());
+    return FEM_OK;
+}
+
+int fem_plan_destroy(fem_plan *plan) {
+    if (!plan) return FEM_OK;
+    int rc = FEM_OK;
+    for (auto &w : plan->work)
+        if (w.arena && hipFree(w.arena) != hipSuccess) rc = FEM_EHIP;
+    if (plan->arena && hipFree(plan->arena) != hipSuccess) rc = FEM_EHIP;
+    delete plan;
+    if (rc) set_error(rc, "hipFree failed");
+    return rc;
+}
+
+int fem_plan_get_stats(const fem_plan *plan, fem_plan_stats *out) {
+    if (int rc = check_plan(plan)) return rc;
+    if (!out) return set_error(FEM_EINVAL, "out is NULL");
+    *out = plan->stats;
+    return FEM_OK;
+}
+
+int fem_build_local_matrices(const fem_plan *plan, int dtype, void *d_K_e, void *d_M_e, double *d_vol,
+                             void *stream) {
+    if (int rc = check_plan(plan)) return rc;
+    if (!valid_dtype(dtype)) return set_error(FEM_EINVAL, "unknown dtype");
+    if (plan->dev.n_elems == 0 || (!d_K_e && !d_M_e && !d_vol)) return FEM_OK;
+    return fem::launch_local_matrices(plan->dev, dtype, d_K_e, d_M_e, d_vol, S(stream));
+}
+
+int fem_combine_local(const fem_plan *plan, int dtype_in, const void *d_K_e, const void *d_M_e, double nu,
+                      int dtype_out, void *d_A_e, void *stream) {
+    if (int rc = check_plan(plan)) return rc;
+    if (!valid_dtype(dtype_in) || !valid_dtype(dtype_out)) return set_error(FEM_EINVAL, "unknown dtype");
+    if (!d_K_e || !d_A_e) return set_error(FEM_EINVAL, "K_e and A_e must not be NULL");
+    if (!std::isfinite(nu) || nu < 0.0) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
+    if (d_A_e == d_K_e || d_A_e == d_M_e) return set_error(FEM_EINVAL, "A_e must not alias K_e or M_e");
+    if (plan->dev.n_elems == 0) return FEM_OK;
+    return fem::launch_combine(plan->dev, dtype_in, d_K_e, nu != 0.0 ? d_M_e : nullptr, nu, dtype_out, d_A_e,
+                               S(stream));
+}
+
+int fem_element_residual(const fem_plan *plan, int dtype, const void *d_K_e, const void *d_M_e, double nu,
+                         const double *d_b, const double *d_x, double *d_r, int mask_dirichlet, void *stream) {
+    if (int rc = check_plan(plan)) return rc;
+    if (!valid_dtype(dtype)) return set_error(FEM_EINVAL, "unknown dtype");
+    if ((!d_K_e && plan->dev.n_elems > 0) || !d_x || !d_r) return set_error(FEM_EINVAL, "NULL argument");
+    if (d_M_e && (!std::isfinite(nu) || nu < 0.0)) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
+    if ((const void *)d_r == (const void *)d_x || (d_b && (const void *)d_r == (const void *)d_b))
+        return set_error(FEM_EINVAL, "r must not alias x or b");
+    return fem::launch_apply64(plan->dev, dtype, d_K_e, (d_M_e && nu != 0.0) ? d_M_e : nullptr, nu, d_x, d_b, d_r,
+                               -1.0, mask_dirichlet ? 1 : 0, plan->scratch64, S(stream));
+}
+
+int fem_element_residual_f32(const fem_plan *plan, const float *d_A_e, const float *d_b, const float *d_x,
+                             float *d_r, int mask_dirichlet, void *stream) {
+    if (int rc = check_plan(plan)) return rc;
+    if ((!d_A_e && plan->dev.n_elems > 0) || !d_x || !d_r) return set_error(FEM_EINVAL, "NULL argument");
+    if (d_r == d_x || (d_b && d_r == d_b)) return set_error(FEM_EINVAL, "r must not alias x or b");
+    return fem::launch_apply32(plan->dev, d_A_e, d_x, d_b, d_r, -1.0f, mask_dirichlet ? 1 : 0, plan->scratch32,
+                               S(stream));
+}
+
+int fem_jacobi_diag(const fem_plan *plan, int dtype, const void *d_K_e, const void *d_M_e, double nu,
+                    double *d_diag, void *stream) {
+    if (int rc = check_plan(plan)) return rc;
+    if (!valid_dtype(dtype)) return set_error(FEM_EINVAL, "unknown dtype");
+    if ((!d_K_e && plan->dev.n_elems > 0) || !d_diag) return set_error(FEM_EINVAL, "NULL argument");
+    if (d_M_e && (!std::isfinite(nu) || nu < 0.0)) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
+    return fem::launch_diag64(plan->dev, dtype, d_K_e, (d_M_e && nu != 0.0) ? d_M_e : nullptr, nu, d_diag,
+                              plan->scratch64, S(stream));
+}
+
+int fem_assemble_rhs(const fem_plan *plan, int dtype, const void *d_M_e, const double *d_f, double *d_b,
+                     void *stream) {
+    if (int rc = check_plan(plan)) return rc;
+    if (!valid_dtype(dtype)) return set_error(FEM_EINVAL, "unknown dtype");
+    if ((!d_M_e && plan->dev.n_elems > 0) || !d_f || !d_b) return set_error(FEM_EINVAL, "NULL argument");
+    if ((const void *)d_b == (const void *)d_f) return set_error(FEM_EINVAL, "b must not alias f");
+    return fem::launch_apply64(plan->dev, dtype, d_M_e, nullptr, 0.0, d_f, nullptr, d_b, 1.0, 0, plan->scratch64,
+                               S(stream));
+}
+
+int fem_pcg_solve(const fem_plan *plan_c, const fem_solve_opts *o, const void *d_K_e, const void *d_M_e,
+                  const double *d_b, double *d_x, fem_solve_info *info, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (int rc = check_plan(plan_c)) return rc;
+    fem_plan *plan = const_cast<fem_plan *>(plan_c);
+    if (!o || !info) return set_error(FEM_EINVAL, "opts and info must not be NULL");
+    std::memset(info, 0, sizeof(*info));
+    if (!valid_dtype(o->dtype)) return set_error(FEM_EINVAL, "unknown dtype");
+    if (!std::isfinite(o->nu) || o->nu < 0.0) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
+    if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) return set_error(FEM_EINVAL, "rtol must be in (0, 1)");
+    if (o->max_iter < 1) return set_error(FEM_EINVAL, "max_iter must be >= 1");
+    if (o->check_every < 1 || o->check_every > 4096) return set_error(FEM_EINVAL, "check_every must be in [1, 4096]");
+    if (o->precond != FEM_PRECOND_NONE && o->precond != FEM_PRECOND_JACOBI)
+        return set_error(FEM_EINVAL, "unknown preconditioner");
+    if (o->dtype != FEM_F64 && (!(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0) || o->max_outer < 1))
+        return set_error(FEM_EINVAL, "mixed precision needs inner_rtol in (0,1) and max_outer >= 1");
+    if (o->profile < 0) return set_error(FEM_EINVAL, "profile must be >= 0");
+    if ((!d_K_e && plan->dev.n_elems > 0) || !d_b || !d_x) return set_error(FEM_EINVAL, "NULL argument");
+    if (o->nu != 0.0 && !d_M_e) return set_error(FEM_EINVAL, "nu > 0 needs M_e");
+    if ((const void *)d_x == (const void *)d_b) return set_error(FEM_EINVAL, "x must not alias b");
+    if (o->nu == 0.0 && plan->stats.n_dirichlet == 0)
+        return set_error(FEM_ESINGULAR, "nu = 0 needs a Dirichlet part of positive measure");
+    if (plan->n_isolated_free > 0)
+        return set_error(FEM_ESINGULAR, "a node outside every element is not a Dirichlet node");
+    const int slot = o->dtype == FEM_F64 ? 0 : 1;
+    if (int rc = alloc_work(plan, slot, o->dtype)) return rc;
+    hipStream_t s = S(stream);
+    int rc = fem::solve_pcg(plan->dev, plan->work[slot], o->dtype, d_K_e, d_M_e, o->nu, d_b, d_x, o->rtol,
+                            o->max_iter, o->precond == FEM_PRECOND_JACOBI, o->inner_rtol, o->max_outer,
+                            o->check_every, o->profile, info, s);
+    if (hipStreamSynchronize(s) != hipSuccess && rc == FEM_OK) rc = set_error(FEM_EHIP, "stream synchronisation failed");
+    info->status = rc;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rc == FEM_ENOCONV) set_error(rc, "iteration limit reached before rtol");
+    if (rc == FEM_EBREAKDOWN) set_error(rc, "CG breakdown (p^T A p <= 0 or non-finite scalar)");
+    return rc;
+}
+
+}  // extern "C"

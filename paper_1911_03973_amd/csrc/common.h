@@ -1,0 +1,70 @@
+// common.h -- shared device helpers of libfem (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "plan.h"
+
+namespace fem {
+
+constexpr int kBlock = 256;  // 4 wave64 per workgroup
+constexpr int kWave = 64;
+
+enum MatKind { MAT_F64 = 0, MAT_F32 = 1, MAT_F32X2 = 2 };
+
+// Element-matrix entry (i*nb+j) of element e, promoted to double.
+// `blk` is the size of one [nb*nb][n_elems] block (for the lo half of a pair).
+template <int KIND>
+__device__ __forceinline__ double load_entry(const void *base, int64_t idx, int64_t blk) {
+    if constexpr (KIND == MAT_F64) {
+        return __builtin_nontemporal_load(static_cast<const double *>(base) + idx);
+    } else if constexpr (KIND == MAT_F32) {
+        return (double)__builtin_nontemporal_load(static_cast<const float *>(base) + idx);
+    } else {
+        const float *p = static_cast<const float *>(base);
+        return (double)__builtin_nontemporal_load(p + idx) + (double)__builtin_nontemporal_load(p + idx + blk);
+    }
+}
+
+// Deterministic wave64 sum: fixed xor butterfly, every lane ends with the total.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Deterministic block sum of one value per thread (blockDim == kBlock).
+// Every thread receives the same total.  `red` must hold kBlock/kWave doubles.
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < kBlock / kWave; ++k) t += red[k];
+    return t;
+}
+
+// Sum n partials (fixed assignment and order; identical result in every block).
+__device__ __forceinline__ double reduce_partials(const double *part, int n, double *red) {
+    double v = 0.0;
+    for (int k = threadIdx.x; k < n; k += kBlock) v += part[k];
+    return block_sum(v, red);
+}
+
+std::string &last_error();
+int set_error(int code, const std::string &msg);
+
+}  // namespace fem
+
+#define FEM_HIP_CHECK(expr)                                                                  \
+    do {                                                                                     \
+        hipError_t _e = (expr);                                                              \
+        if (_e != hipSuccess)                                                                \
+            return ::fem::set_error(-2, std::string(#expr " failed: ") + hipGetErrorString(_e)); \
+    } while (0)

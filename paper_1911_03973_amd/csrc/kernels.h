@@ -1,0 +1,33 @@
+// kernels.h -- launchers of the device kernels (internal to libfem).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace fem {
+
+// Largest chunk the kernels accept: the FP64 slot buffer plus the uint16 slot
+// list of one chunk must fit in 64 KiB of LDS.
+constexpr int kMaxChunkLds = 65536;
+
+int max_chunk_elems(int nb);
+int default_chunk_elems(int nb);
+int device_cu_count();
+
+int launch_local_matrices(const DevPlan &P, int kind, void *K, void *M, double *vol, hipStream_t s);
+int launch_combine(const DevPlan &P, int kin, const void *K, const void *M, double nu, int kout, void *A,
+                   hipStream_t s);
+
+// out = (b ? b : 0) + sign * sum_e C_e^T A_e C_e x, optionally masked (out(nd) = 0).
+// scratch: n_partials doubles.
+int launch_apply64(const DevPlan &P, int kind, const void *K, const void *M, double nu, const double *x,
+                   const double *b, double *out, double sign, int use_mask, double *scratch, hipStream_t s);
+// the same with float matrices, vectors and accumulation; scratch: n_partials floats
+int launch_apply32(const DevPlan &P, const float *A, const float *x, const float *b, float *out, float sign,
+                   int use_mask, float *scratch, hipStream_t s);
+// d = sum_e C_e^T diag(A_e)
+int launch_diag64(const DevPlan &P, int kind, const void *K, const void *M, double nu, double *d,
+                  double *scratch, hipStream_t s);
+
+}  // namespace fem

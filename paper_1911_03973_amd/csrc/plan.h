@@ -1,0 +1,47 @@
+// plan.h -- chunked element -> node index (host side) and its device mirror.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace fem {
+
+struct HostPlan {
+    int dim = 0, nb = 0, E = 0;
+    int64_t n_nodes = 0, n_elems = 0, n_chunks = 0;
+    int64_t n_local = 0, n_shared = 0, n_partials = 0, n_dirichlet = 0;
+    int64_t n_isolated = 0, n_isolated_free = 0;
+    std::vector<int32_t> chunk_node_off;  // [n_chunks+1] into loc_nodes / loc_end
+    std::vector<int32_t> chunk_info;      // [n_chunks][2]: n_complete, partial_base
+    std::vector<int32_t> loc_nodes;       // [n_local] global node ids
+    std::vector<uint16_t> loc_end;        // [n_local] end of the node's slot run
+    std::vector<uint16_t> slots;          // [n_chunks][nb*E] slot ids grouped by node
+    std::vector<int32_t> fix_nodes;       // [n_shared] nodes in != 1 chunk (incl. isolated)
+    std::vector<int32_t> fix_off;         // [n_shared+1]
+    std::vector<int32_t> fix_parts;       // [n_partials]
+    std::vector<uint8_t> mask;            // [n_nodes] Dirichlet flags
+};
+
+// Device-resident index (raw pointers into plan-owned allocations).
+struct DevPlan {
+    int dim, nb, E;
+    int64_t n_nodes, n_elems, n_chunks, n_local, n_shared, n_partials;
+    const double *coords;        // [dim][n_nodes]
+    const int32_t *conn;         // [nb][n_elems]
+    const int32_t *chunk_node_off;
+    const int32_t *chunk_info;
+    const int32_t *loc_nodes;
+    const uint16_t *loc_end;
+    const uint16_t *slots;
+    const int32_t *fix_nodes;
+    const int32_t *fix_off;
+    const int32_t *fix_parts;
+    const uint8_t *mask;
+};
+
+int build_host_plan(int dim, int64_t n_nodes, int64_t n_elems, const double *coords,
+                    const int32_t *conn, const int32_t *dirichlet, int64_t n_dir, int chunk_elems,
+                    HostPlan &P, std::string &err);
+
+}  // namespace fem

@@ -1,0 +1,290 @@
+"""Thin ctypes binding of libfem.so (the C ABI of include/fem.h).
+
+Only argument marshalling lives here: torch tensors provide device memory and
+the current HIP stream, every computation runs in the library's HIP kernels.
+Importing this module loads the library and raises ``ImportError`` if it has
+not been built (``python paper_1911_03973_amd/build.py``) -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libfem.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libfem.so is not built ({LIB_PATH}); run paper_1911_03973_amd/build.py")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FEM_OK, FEM_EINVAL, FEM_EHIP, FEM_ENOCONV, FEM_ESINGULAR, FEM_EBREAKDOWN, FEM_ENOMEM = 0, -1, -2, -3, -4, -5, -6
+F64, F32, F32X2 = 0, 1, 2
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
+
+_STATUS = {
+    FEM_EINVAL: "FEM_EINVAL",
+    FEM_EHIP: "FEM_EHIP",
+    FEM_ENOCONV: "FEM_ENOCONV",
+    FEM_ESINGULAR: "FEM_ESINGULAR",
+    FEM_EBREAKDOWN: "FEM_EBREAKDOWN",
+    FEM_ENOMEM: "FEM_ENOMEM",
+}
+
+
+class FemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n_b", ctypes.c_int),
+        ("n_nodes", ctypes.c_int64), ("n_elems", ctypes.c_int64), ("n_dirichlet", ctypes.c_int64),
+        ("chunk_elems", ctypes.c_int), ("n_chunks", ctypes.c_int64), ("n_local", ctypes.c_int64),
+        ("n_shared", ctypes.c_int64), ("n_partials", ctypes.c_int64), ("index_bytes", ctypes.c_int64),
+    ]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int), ("nu", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int),
+        ("precond", ctypes.c_int), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int),
+        ("check_every", ctypes.c_int), ("profile", ctypes.c_int),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int), ("iters", ctypes.c_int), ("outer", ctypes.c_int), ("replacements", ctypes.c_int),
+        ("relres", ctypes.c_double), ("r0", ctypes.c_double), ("seconds", ctypes.c_double),
+        ("matvec_ms", ctypes.c_double), ("matvec_samples", ctypes.c_int), ("matvec_calls", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp, _i64, _int, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+_SIGS = {
+    "fem_plan_create": [_int, _i64, _i64, _vp, _vp, _vp, _i64, _int, _vp, ctypes.POINTER(_vp)],
+    "fem_plan_destroy": [_vp],
+    "fem_plan_check_host": [_int, _i64, _i64, _vp, _vp, _vp, _i64, _int, ctypes.POINTER(PlanStats)],
+    "fem_plan_get_stats": [_vp, ctypes.POINTER(PlanStats)],
+    "fem_build_local_matrices": [_vp, _int, _vp, _vp, _vp, _vp],
+    "fem_combine_local": [_vp, _int, _vp, _vp, _dbl, _int, _vp, _vp],
+    "fem_element_residual": [_vp, _int, _vp, _vp, _dbl, _vp, _vp, _vp, _int, _vp],
+    "fem_element_residual_f32": [_vp, _vp, _vp, _vp, _vp, _int, _vp],
+    "fem_jacobi_diag": [_vp, _int, _vp, _vp, _dbl, _vp, _vp],
+    "fem_assemble_rhs": [_vp, _int, _vp, _vp, _vp, _vp],
+    "fem_pcg_solve": [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, _vp, _vp, ctypes.POINTER(SolveInfo), _vp],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.fem_last_error.restype = ctypes.c_char_p
+_lib.fem_last_error.argtypes = []
+_lib.fem_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
+_lib.fem_solve_opts_default.restype = None
+
+EXPORTED = sorted(list(_SIGS) + ["fem_last_error", "fem_solve_opts_default"])
+
+
+def library():
+    return _lib
+
+
+def _check(rc, allow=()):
+    if rc != FEM_OK and rc not in allow:
+        raise FemError(rc, _lib.fem_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, numel, what):
+    if t is None:
+        return
+    if t.dtype != dtype:
+        raise TypeError(f"{what}: expected {dtype}, got {t.dtype}")
+    if t.numel() != numel:
+        raise ValueError(f"{what}: expected {numel} elements, got {t.numel()}")
+
+
+def matrix_shape(dtype, nb, n_elems):
+    """Tensor shape and torch dtype of one local-matrix array in `dtype` storage."""
+    if dtype == F64:
+        return (nb * nb, n_elems), torch.float64
+    if dtype == F32:
+        return (nb * nb, n_elems), torch.float32
+    if dtype == F32X2:
+        return (2, nb * nb, n_elems), torch.float32
+    raise ValueError("unknown dtype")
+
+
+class Plan:
+    """Owns a fem_plan (chunked element -> node index of one mesh)."""
+
+    def __init__(self, dim, coords_soa, conn_soa, dirichlet=None, chunk_elems=0, stream=None):
+        n_nodes = coords_soa.shape[1]
+        n_elems = conn_soa.shape[1]
+        _need(coords_soa, torch.float64, dim * n_nodes, "coords")
+        _need(conn_soa, torch.int32, (dim + 1) * n_elems, "conn")
+        if dirichlet is not None and dirichlet.numel() == 0:
+            dirichlet = None
+        if dirichlet is not None:
+            _need(dirichlet, torch.int32, dirichlet.numel(), "dirichlet")
+        h = ctypes.c_void_p()
+        _check(_lib.fem_plan_create(dim, n_nodes, n_elems, _ptr(coords_soa), _ptr(conn_soa) if n_elems else None,
+                                    _ptr(dirichlet), 0 if dirichlet is None else dirichlet.numel(), chunk_elems,
+                                    _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.dim, self.nb, self.n_nodes, self.n_elems = dim, dim + 1, n_nodes, n_elems
+        self.device = coords_soa.device
+
+    @classmethod
+    def from_mesh(cls, mesh, dirichlet=None, chunk_elems=0, device="cuda"):
+        coords = torch.from_numpy(mesh.coords.T.copy()).to(device)
+        conn = torch.from_numpy(mesh.elems.T.copy()).to(device)
+        d = None if dirichlet is None else torch.as_tensor(dirichlet, dtype=torch.int32).to(device)
+        return cls(mesh.dim, coords.contiguous(), conn.contiguous(), d, chunk_elems)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("plan destroyed")
+        return self._h
+
+    def stats(self):
+        st = PlanStats()
+        _check(_lib.fem_plan_get_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            _lib.fem_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def empty_matrix(self, dtype):
+        shape, tdt = matrix_shape(dtype, self.nb, self.n_elems)
+        return torch.empty(shape, dtype=tdt, device=self.device)
+
+    def empty_vector(self, tdt=torch.float64):
+        return torch.empty(self.n_nodes, dtype=tdt, device=self.device)
+
+    def _mat(self, t, dtype, what):
+        if t is None:
+            return
+        shape, tdt = matrix_shape(dtype, self.nb, self.n_elems)
+        _need(t, tdt, int(torch.Size(shape).numel()), what)
+
+
+def plan_check_host(mesh, dirichlet=None, chunk_elems=0):
+    """Host-only validation and sizing of a plan (no GPU needed).  Returns the stats dict."""
+    import numpy as np
+
+    coords = np.ascontiguousarray(mesh.coords.T, dtype=np.float64)
+    conn = np.ascontiguousarray(mesh.elems.T, dtype=np.int32)
+    d = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.int32)
+    st = PlanStats()
+    _check(_lib.fem_plan_check_host(mesh.dim, coords.shape[1], conn.shape[1], coords.ctypes.data,
+                                    conn.ctypes.data if conn.size else None,
+                                    None if d is None or d.size == 0 else d.ctypes.data,
+                                    0 if d is None else d.size, chunk_elems, ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in st._fields_}
+
+
+def build_local_matrices(plan, dtype, K=None, M=None, vol=None, stream=None):
+    plan._mat(K, dtype, "K_e")
+    plan._mat(M, dtype, "M_e")
+    _need(vol, torch.float64, plan.n_elems, "vol")
+    _check(_lib.fem_build_local_matrices(plan.handle, dtype, _ptr(K), _ptr(M), _ptr(vol), _stream(stream)))
+
+
+def combine_local(plan, dtype_in, K, M, nu, dtype_out, A, stream=None):
+    plan._mat(K, dtype_in, "K_e")
+    plan._mat(M, dtype_in, "M_e")
+    plan._mat(A, dtype_out, "A_e")
+    _check(_lib.fem_combine_local(plan.handle, dtype_in, _ptr(K), _ptr(M), float(nu), dtype_out, _ptr(A),
+                                  _stream(stream)))
+
+
+def element_residual(plan, dtype, K, M, nu, b, x, r, mask=True, stream=None):
+    plan._mat(K, dtype, "K_e")
+    plan._mat(M, dtype, "M_e")
+    for t, w in ((b, "b"), (x, "x"), (r, "r")):
+        _need(t, torch.float64, plan.n_nodes, w)
+    _check(_lib.fem_element_residual(plan.handle, dtype, _ptr(K), _ptr(M), float(nu), _ptr(b), _ptr(x), _ptr(r),
+                                     1 if mask else 0, _stream(stream)))
+
+
+def element_residual_f32(plan, A, b, x, r, mask=True, stream=None):
+    plan._mat(A, F32, "A_e")
+    for t, w in ((b, "b"), (x, "x"), (r, "r")):
+        _need(t, torch.float32, plan.n_nodes, w)
+    _check(_lib.fem_element_residual_f32(plan.handle, _ptr(A), _ptr(b), _ptr(x), _ptr(r), 1 if mask else 0,
+                                         _stream(stream)))
+
+
+def jacobi_diag(plan, dtype, K, M, nu, d, stream=None):
+    plan._mat(K, dtype, "K_e")
+    plan._mat(M, dtype, "M_e")
+    _need(d, torch.float64, plan.n_nodes, "diag")
+    _check(_lib.fem_jacobi_diag(plan.handle, dtype, _ptr(K), _ptr(M), float(nu), _ptr(d), _stream(stream)))
+
+
+def assemble_rhs(plan, dtype, M, f, b, stream=None):
+    plan._mat(M, dtype, "M_e")
+    _need(f, torch.float64, plan.n_nodes, "f")
+    _need(b, torch.float64, plan.n_nodes, "b")
+    _check(_lib.fem_assemble_rhs(plan.handle, dtype, _ptr(M), _ptr(f), _ptr(b), _stream(stream)))
+
+
+def solve_opts(**kw):
+    o = SolveOpts()
+    _lib.fem_solve_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def pcg_solve(plan, opts, K, M, b, x, stream=None, allow=(FEM_ENOCONV,)):
+    """Runs fem_pcg_solve; returns the info dict (status included)."""
+    plan._mat(K, opts.dtype, "K_e")
+    plan._mat(M, opts.dtype, "M_e")
+    _need(b, torch.float64, plan.n_nodes, "b")
+    _need(x, torch.float64, plan.n_nodes, "x")
+    info = SolveInfo()
+    _check(_lib.fem_pcg_solve(plan.handle, ctypes.byref(opts), _ptr(K), _ptr(M), _ptr(b), _ptr(x),
+                              ctypes.byref(info), _stream(stream)), allow=allow)
+    return info.as_dict()
+
+
+def last_error():
+    return _lib.fem_last_error().decode()

@@ -1,0 +1,233 @@
+"""Parity of the HIP kernels with the FP64 oracle (element by element).
+
+FP64 results must match to 1e-12 relative; the FP32 residual must stay within
+the componentwise bound derived from its arithmetic.  Sizes span several
+chunks with a ragged last chunk; the chunk size is varied down to 64 elements
+so that many nodes are shared between chunks.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1911_03973_amd import inputs
+
+from problems import Problem, cuda, from_soa, max_rel, pair_value, to_soa
+
+pytestmark = pytest.mark.gpu
+
+fem = pytest.importorskip("paper_1911_03973_amd.fem")
+
+
+def _meshes():
+    return [
+        ("tri_fig1_2elem", inputs.square_mesh(1, order="rowmajor"), 0),
+        ("tri_17_jitter_E64", inputs.square_mesh(17, jitter=0.2, seed=3), 64),
+        ("tri_45_jitter_E320", inputs.square_mesh(45, jitter=0.2, seed=4), 320),
+        ("tri_64_default", inputs.square_mesh(64), 0),
+        ("tri_33_rowmajor_E2048", inputs.square_mesh(33, order="rowmajor", jitter=0.1, seed=5), 2048),
+        ("tet_5_jitter_E64", inputs.cube_mesh(5, jitter=0.15, seed=6), 64),
+        ("tet_9_jitter_default", inputs.cube_mesh(9, jitter=0.15, seed=7), 0),
+        ("tet_12_E1536", inputs.cube_mesh(12), 1536),
+    ]
+
+
+MESHES = _meshes()
+
+
+@pytest.fixture(params=MESHES, ids=[m[0] for m in MESHES])
+def case(request):
+    name, mesh, E = request.param
+    print(f"[case] {name} n_nodes={mesh.n_nodes} n_elems={mesh.n_elems} E={E}", flush=True)
+    prob = Problem(mesh, nu=0.75, dirichlet="all", f="sine", seed=11)
+    plan = fem.Plan.from_mesh(mesh, prob.nd, chunk_elems=E)
+    return prob, plan
+
+
+def test_local_matrices_f64(case):
+    prob, plan = case
+    K = plan.empty_matrix(fem.F64)
+    M = plan.empty_matrix(fem.F64)
+    vol = torch.empty(plan.n_elems, dtype=torch.float64, device="cuda")
+    fem.build_local_matrices(plan, fem.F64, K, M, vol)
+    torch.cuda.synchronize()
+    nb = plan.nb
+    Kg = from_soa(K.cpu().numpy(), nb)
+    Mg = from_soa(M.cpu().numpy(), nb)
+    assert max_rel(Kg, prob.K) <= 1e-12
+    assert max_rel(Mg, prob.M) <= 1e-12
+    assert max_rel(vol.cpu().numpy(), prob.vol) <= 1e-12
+
+
+def test_local_matrices_f32_and_pair(case):
+    prob, plan = case
+    nb = plan.nb
+    K32 = plan.empty_matrix(fem.F32)
+    fem.build_local_matrices(plan, fem.F32, K32, None, None)
+    Kp = plan.empty_matrix(fem.F32X2)
+    Mp = plan.empty_matrix(fem.F32X2)
+    fem.build_local_matrices(plan, fem.F32X2, Kp, Mp, None)
+    torch.cuda.synchronize()
+    Ko = prob.K
+    # FP32 storage is the FP64 value rounded once: within 2^-24 of it
+    k32 = from_soa(K32.double().cpu().numpy(), nb)
+    assert np.all(np.abs(k32 - Ko) <= 2.0 ** -24 * np.abs(Ko) + 1e-15 * np.abs(Ko).max())
+    # hi + lo reproduces FP64 to ~2^-48
+    assert max_rel(from_soa(pair_value(Kp), nb), Ko) <= 1e-12
+    assert max_rel(from_soa(pair_value(Mp), nb), prob.M) <= 1e-12
+    hi = Kp[0].double().cpu().numpy()
+    np.testing.assert_array_equal(hi, K32.double().cpu().numpy())
+
+
+def test_residual_f64_matches_oracle(case):
+    prob, plan = case
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(prob.n)
+    K = cuda(to_soa(prob.K))
+    M = cuda(to_soa(prob.M))
+    xg, bg = cuda(x), cuda(prob.b)
+    r = plan.empty_vector()
+    for mask in (True, False):
+        fem.element_residual(plan, fem.F64, K, M, prob.nu, bg, xg, r, mask=mask)
+        torch.cuda.synchronize()
+        ro = oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, x,
+                             prob.mask if mask else None)
+        s = oracle.residual_scale(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, x)
+        assert max_rel(r.cpu().numpy(), ro, scale=s.max()) <= 1e-12
+        assert max_rel(r.cpu().numpy(), ro) <= 1e-11
+    # b = NULL and M = NULL
+    fem.element_residual(plan, fem.F64, K, None, 0.0, None, xg, r, mask=False)
+    torch.cuda.synchronize()
+    ro = oracle.residual(prob.n, prob.mesh.elems, prob.K, None, 0.0, None, x)
+    s = oracle.residual_scale(prob.n, prob.mesh.elems, prob.K, None, 0.0, None, x)
+    assert max_rel(r.cpu().numpy(), ro, scale=s.max()) <= 1e-12
+
+
+def test_residual_from_gpu_pair_matrices(case):
+    """The whole GPU chain: K_e, M_e built on the GPU as hi/lo pairs, residual
+    in FP64 from them, against the oracle's FP64 chain."""
+    prob, plan = case
+    Kp = plan.empty_matrix(fem.F32X2)
+    Mp = plan.empty_matrix(fem.F32X2)
+    fem.build_local_matrices(plan, fem.F32X2, Kp, Mp, None)
+    x = np.random.default_rng(2).standard_normal(prob.n)
+    r = plan.empty_vector()
+    fem.element_residual(plan, fem.F32X2, Kp, Mp, prob.nu, cuda(prob.b), cuda(x), r, mask=True)
+    torch.cuda.synchronize()
+    ro = oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, x, prob.mask)
+    s = oracle.residual_scale(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, x)
+    assert max_rel(r.cpu().numpy(), ro, scale=s.max()) <= 1e-12
+
+
+def test_residual_f32_error_bound(case):
+    """|r32 - r64|_i <= c * gamma_k * s_i with s = |b| + sum_e C_e^T |A_e||x_e|.
+
+    k = n_b + deg + 2 covers the local dot product, the in-chunk and cross-chunk
+    sums and the subtraction from b; the inputs A, x and b are themselves
+    rounded to FP32 once, which adds one unit roundoff per term (c = 2)."""
+    prob, plan = case
+    A = prob.K + prob.nu * prob.M
+    A32 = cuda(to_soa(A).astype(np.float32))
+    x = np.random.default_rng(3).standard_normal(prob.n)
+    r = plan.empty_vector(torch.float32)
+    fem.element_residual_f32(plan, A32, cuda(prob.b.astype(np.float32)), cuda(x.astype(np.float32)), r, mask=True)
+    torch.cuda.synchronize()
+    ro = oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, x, prob.mask)
+    s = oracle.residual_scale(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, x)
+    deg = np.bincount(prob.mesh.elems.ravel(), minlength=prob.n).max()
+    k = plan.nb + deg + 2
+    u = 2.0 ** -24
+    gamma = k * u / (1 - k * u)
+    err = np.abs(r.double().cpu().numpy() - ro)
+    assert np.all(err <= 2 * gamma * s + 1e-30)
+
+
+def test_jacobi_diag_and_rhs(case):
+    prob, plan = case
+    K = cuda(to_soa(prob.K))
+    M = cuda(to_soa(prob.M))
+    d = plan.empty_vector()
+    fem.jacobi_diag(plan, fem.F64, K, M, prob.nu, d)
+    b = plan.empty_vector()
+    fem.assemble_rhs(plan, fem.F64, M, cuda(prob.f), b)
+    torch.cuda.synchronize()
+    do = oracle.jacobi_diag(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu)
+    assert max_rel(d.cpu().numpy(), do) <= 1e-12
+    assert max_rel(b.cpu().numpy(), prob.b) <= 1e-12
+
+
+def test_combine_local(case):
+    prob, plan = case
+    K = cuda(to_soa(prob.K))
+    M = cuda(to_soa(prob.M))
+    A = plan.empty_matrix(fem.F64)
+    fem.combine_local(plan, fem.F64, K, M, prob.nu, fem.F64, A)
+    Ap = plan.empty_matrix(fem.F32X2)
+    fem.combine_local(plan, fem.F64, K, M, prob.nu, fem.F32X2, Ap)
+    torch.cuda.synchronize()
+    Ao = to_soa(prob.K + prob.nu * prob.M)
+    assert max_rel(A.cpu().numpy(), Ao) <= 1e-15
+    assert max_rel(pair_value(Ap), Ao) <= 1e-14
+
+
+def test_bitwise_reproducible(case):
+    prob, plan = case
+    K = cuda(to_soa(prob.K))
+    M = cuda(to_soa(prob.M))
+    x = cuda(np.random.default_rng(4).standard_normal(prob.n))
+    outs = []
+    for _ in range(3):
+        r = plan.empty_vector()
+        fem.element_residual(plan, fem.F64, K, M, prob.nu, cuda(prob.b), x, r, mask=True)
+        outs.append(r.cpu().numpy())
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+
+
+# --------------------------------------------------------------------------
+# Edge cases
+# --------------------------------------------------------------------------
+
+def test_isolated_node_and_empty_mesh():
+    m = inputs.square_mesh(6, jitter=0.1, seed=2)
+    coords = np.vstack([m.coords, [[3.0, 3.0]]])
+    mesh = inputs.Mesh(coords, m.elems, m.n)
+    prob = Problem(mesh, nu=1.0, dirichlet=None)
+    plan = fem.Plan.from_mesh(mesh, None, chunk_elems=64)
+    x = np.random.default_rng(0).standard_normal(mesh.n_nodes)
+    b = np.random.default_rng(1).standard_normal(mesh.n_nodes)
+    r = plan.empty_vector()
+    fem.element_residual(plan, fem.F64, cuda(to_soa(prob.K)), cuda(to_soa(prob.M)), 1.0, cuda(b), cuda(x), r,
+                         mask=False)
+    torch.cuda.synchronize()
+    ro = oracle.residual(mesh.n_nodes, mesh.elems, prob.K, prob.M, 1.0, b, x)
+    assert max_rel(r.cpu().numpy(), ro) <= 1e-12
+    assert r[-1].item() == b[-1]
+    # an empty element list: r = b everywhere
+    empty = fem.Plan(2, cuda(m.coords.T), torch.zeros((3, 0), dtype=torch.int32, device="cuda"))
+    r = empty.empty_vector()
+    bb = cuda(b[: m.n_nodes])
+    fem.element_residual(empty, fem.F64, None, None, 0.0, bb, cuda(x[: m.n_nodes]), r, mask=False)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(r.cpu().numpy(), b[: m.n_nodes])
+
+
+def test_invalid_arguments_rejected():
+    m = inputs.square_mesh(4)
+    bad = m.elems.copy()
+    bad[2, 1] = m.n_nodes + 5
+    with pytest.raises(fem.FemError) as ei:
+        fem.Plan(2, cuda(m.coords.T), cuda(bad.T))
+    assert ei.value.code == fem.FEM_EINVAL
+    plan = fem.Plan.from_mesh(m, inputs.boundary_nodes(m))
+    K = plan.empty_matrix(fem.F64)
+    fem.build_local_matrices(plan, fem.F64, K, None, None)
+    x = plan.empty_vector().zero_()
+    with pytest.raises(fem.FemError):
+        fem.element_residual(plan, fem.F64, K, K, -1.0, None, x, plan.empty_vector())
+    with pytest.raises(fem.FemError):
+        fem.element_residual(plan, fem.F64, K, None, 0.0, None, x, x)  # r aliases x
+    with pytest.raises(fem.FemError) as ei:
+        free = fem.Plan.from_mesh(m, None)
+        fem.pcg_solve(free, fem.solve_opts(nu=0.0), K, None, x.clone(), plan.empty_vector().zero_())
+    assert ei.value.code == fem.FEM_ESINGULAR
