@@ -93,6 +93,43 @@ def cpu_baseline(mesh, w, seconds):
     }
 
 
+def residual_kernels(fem, plan, mesh, K, M, nu, dt, calls):
+    """Standalone element residuals r = b - A x on the same mesh (full n_b x n_b storage)."""
+    import torch
+
+    nb = mesh.nb
+    out = {}
+    A32 = plan.empty_matrix(fem.F32)
+    fem.combine_local(plan, dt, K, M, nu, fem.F32, A32)
+    Ap = plan.empty_matrix(fem.F32X2)
+    fem.combine_local(plan, dt, K, M, nu, fem.F32X2, Ap)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x32 = torch.rand(mesh.n_nodes, device="cuda", generator=g, dtype=torch.float32)
+    b32 = torch.rand(mesh.n_nodes, device="cuda", generator=g, dtype=torch.float32)
+    r32 = torch.empty_like(x32)
+    x64, b64, r64 = x32.double(), b32.double(), torch.empty(mesh.n_nodes, dtype=torch.float64, device="cuda")
+    cases = [
+        ("f32", lambda: fem.element_residual_f32(plan, A32, b32, x32, r32, mask=True),
+         mesh.n_elems * (nb * nb * 4 + 4 * nb) + mesh.n_nodes * 3 * 4),
+        ("f64_from_hi_lo", lambda: fem.element_residual(plan, fem.F32X2, Ap, None, 0.0, b64, x64, r64, mask=True),
+         mesh.n_elems * (nb * nb * 8 + 4 * nb) + mesh.n_nodes * 3 * 8),
+    ]
+    for name, fn, nbytes in cases:
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(calls):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / calls
+        out[name] = {"us": round(us, 2), "bytes": nbytes, "GB/s": round(nbytes / us / 1e3, 1),
+                     "frac": round(nbytes / us / 1e3 / HBM_PEAK_GBS, 4)}
+    del A32, Ap
+    return out
+
+
 def inputs_boundary(mesh, w):
     from paper_1911_03973_amd import inputs
 
@@ -108,6 +145,9 @@ def main():
     ap.add_argument("--profile", type=int, default=4, help="time every k-th matvec with HIP events")
     ap.add_argument("--check-every", type=int, default=64)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--vectors", type=int, default=0, help="mixed precision: 0 FP64, 1 FP32 iteration vectors")
+    ap.add_argument("--block", type=int, default=0, help="workgroup size of the element pass (0 = default)")
+    ap.add_argument("--residual-calls", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -137,7 +177,7 @@ def main():
     b = plan.empty_vector()
     x = plan.empty_vector()
     opts = fem.solve_opts(dtype=dt, nu=w["nu"], rtol=1e-8, check_every=args.check_every, profile=args.profile,
-                          max_iter=200000)
+                          max_iter=200000, vectors=args.vectors, block=args.block)
 
     def step():
         fem.build_local_matrices(plan, dt, K, M, None)
@@ -161,11 +201,16 @@ def main():
     mv_ms = sum(i["matvec_ms"] for i in infos)
     mv_n = sum(i["matvec_samples"] for i in infos)
     nb = mesh.nb
-    s_a, s_v = (4, 4) if dt != fem.F64 else (8, 8)
-    bytes_mv = mesh.n_elems * (nb * nb * s_a + 4 * nb) + mesh.n_nodes * 2 * s_v
+    n_pk = nb + nb * (nb - 1) // 2  # packed symmetric difference form: row sums + upper off-diagonals
+    s_a = 4 if dt != fem.F64 else 8
+    s_v = 4 if (dt != fem.F64 and args.vectors == 1) else 8
+    # one fused CG pass: matrix heads + the connectivity-equivalent index + 9 vector streams
+    # (read r, q, x, p, D^-1; write r, x, p, q)
+    bytes_mv = mesh.n_elems * (n_pk * s_a + 4 * nb) + mesh.n_nodes * 9 * s_v
     avg_mv_s = (mv_ms / mv_n) / 1e3 if mv_n else float("nan")
     gbs = bytes_mv / avg_mv_s / 1e9
     ok = all(i["status"] == 0 and i["relres"] <= 1e-8 for i in infos)
+    resid = residual_kernels(fem, plan, mesh, K, M, w["nu"], dt, args.residual_calls)
     out = {
         "metric": METRIC,
         "value": round(gbs, 2),
@@ -185,6 +230,7 @@ def main():
             "n_elems": mesh.n_elems,
             "chunk_elems": st["chunk_elems"],
             "storage": w["dtype"],
+            "block": args.block,
         },
         "roofline": {
             "bound": "hbm",
@@ -205,6 +251,9 @@ def main():
         "converged": ok,
         "plan_seconds": round(t_plan, 3),
         "learned_fcg": None,
+        "pass_kind": ("fused CG pass, packed difference form (%d values/elem, %s), %s vectors"
+                      % (n_pk, "FP32 heads" if dt != fem.F64 else "FP64", "FP32" if s_v == 4 else "FP64")),
+        "residual_kernels": resid,
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

@@ -78,8 +78,9 @@ typedef struct {
  *  d_conn         int32  [n_b][n_elems]   (read; not kept)
  *  d_dirichlet    int32  [n_dirichlet] node ids of the Dirichlet part nd
  *                 (duplicates allowed; may be NULL when n_dirichlet = 0)
- *  chunk_elems    elements per chunk, 0 = default; 64 <= chunk_elems <= 8192
- *                 and a multiple of 64
+ *  chunk_elems    elements per chunk, 0 = default (2048 for triangles, 1536
+ *                 for tetrahedra); one of 64, 128, 256, 512, 1024, 1536 and,
+ *                 for triangles only, 2048
  * The plan partitions the element list into chunks of consecutive elements;
  * element orders with spatial locality (e.g. a Morton order of the cells)
  * give compact chunks and the fewest shared nodes.  Errors: FEM_EINVAL for a
@@ -148,18 +149,26 @@ int fem_assemble_rhs(const fem_plan *plan, int dtype, const void *d_M_e, const d
                      double *d_b, void *stream);
 
 typedef struct {
-    int dtype;          /* FEM_F64: FP64 throughout.  FEM_F32X2 or FEM_F32:
-                           FP32 inner CG (FP32 matrices and vectors, FP64 dot
-                           products and alpha/beta) inside FP64 iterative
-                           refinement whose residual uses the full inputs. */
+    int dtype;          /* storage of d_K_e / d_M_e.  FEM_F64: FP64 solve.
+                           FEM_F32X2 or FEM_F32: mixed precision -- the CG
+                           iterations read FP32 local matrices, while dot
+                           products, alpha/beta and every refresh of the
+                           residual b - A x are FP64 (iterative refinement,
+                           the refresh using the full input precision). */
     double nu;          /* >= 0 */
     double rtol;        /* stop at ||b - A x||_2 <= rtol ||b - A x0||_2 */
     int max_iter;       /* cap on CG iterations (inner ones summed) */
     int precond;        /* fem_precond */
-    double inner_rtol;  /* mixed precision: inner relative tolerance */
-    int max_outer;      /* mixed precision: cap on refinement steps */
+    double inner_rtol;  /* mixed precision: the FP64 residual is refreshed
+                           whenever the iterated residual norm has fallen by
+                           this factor since the last refresh */
+    int max_outer;      /* mixed precision: cap on refreshes */
     int check_every;    /* host reads the convergence flag every k iterations */
     int profile;        /* record HIP events around every `profile`-th matvec */
+    int vectors;        /* mixed precision: 0 = FP64 iteration vectors,
+                           1 = FP32 iteration vectors */
+    int block;          /* workgroup size of the element pass: 256, 512,
+                           1024, or 0 for the default */
 } fem_solve_opts;
 
 typedef struct {

@@ -69,28 +69,24 @@ int alloc_work(fem_plan *plan, int slot, int dtype) {
     if (w.arena) return FEM_OK;
     const fem::DevPlan &P = plan->dev;
     const int64_t n = P.n_nodes;
-    const int64_t ent = (int64_t)P.nb * P.nb * P.n_elems;
-    const bool mixed = slot == 1;
-    const fem::Grids gr = fem::solver_grids(P, fem::chunk_lds_bytes<3, double>(P.E) / 3 * P.nb);
+    const int64_t npk = (int64_t)fem::packed_count(P.nb) * P.n_elems;
+    // the largest chunk grid (8 workgroups per CU) plus the fix-up grid
+    const int64_t npart = 8 * (int64_t)fem::device_cu_count() + fem::fixup_grid(P.n_shared) + 8;
     ArenaLayout L;
-    size_t oA = L.add(mixed ? (size_t)ent * 2 * sizeof(float) : (size_t)ent * sizeof(double));
+    // FP64 packed operator, or FP32 hi/lo pair of it: the same bytes
+    size_t oA = L.add((size_t)npk * sizeof(double));
     size_t od = L.add(n * sizeof(double));
-    size_t odi64 = L.add(mixed ? 0 : n * sizeof(double));
+    size_t odi = L.add(n * sizeof(double));
+    size_t or_ = L.add(n * sizeof(double));
+    size_t op_ = L.add(n * sizeof(double));
+    size_t oq = L.add(n * sizeof(double));
+    size_t oxc = L.add(n * sizeof(float));
     size_t or64 = L.add(n * sizeof(double));
-    size_t op64 = L.add(mixed ? 0 : n * sizeof(double));
-    size_t oq64 = L.add(n * sizeof(double));
-    size_t odi32 = L.add(mixed ? n * sizeof(float) : 0);
-    size_t or32 = L.add(mixed ? n * sizeof(float) : 0);
-    size_t op32 = L.add(mixed ? n * sizeof(float) : 0);
-    size_t oq32 = L.add(mixed ? n * sizeof(float) : 0);
-    size_t oxc = L.add(mixed ? n * sizeof(float) : 0);
     size_t opart64 = L.add(std::max<int64_t>(P.n_partials, 1) * sizeof(double));
-    size_t opart32 = L.add(mixed ? std::max<int64_t>(P.n_partials, 1) * sizeof(float) : 0);
+    size_t opartv = L.add(std::max<int64_t>(P.n_partials, 1) * sizeof(double));
+    size_t odots = L.add((size_t)8 * npart * sizeof(double));
     size_t oupd = L.add((size_t)3 * 1024 * sizeof(double));
-    // p.q partials: the main grid is at most 8 blocks per CU whatever the
-    // vector precision, plus the fix-up grid
-    size_t omv = L.add((size_t)(8 * fem::device_cu_count() + gr.gf + 8) * sizeof(double));
-    size_t ost = L.add(sizeof(fem::SolveState));
+    size_t ost = L.add(sizeof(fem::IterState));
     size_t obad = L.add(sizeof(int));
     void *arena = nullptr;
     if (hipMalloc(&arena, L.total) != hipSuccess) {
@@ -101,22 +97,19 @@ int alloc_work(fem_plan *plan, int slot, int dtype) {
     w.arena = arena;
     w.bytes = L.total;
     w.kind = dtype;
-    w.A = b + oA;
+    w.Apk = b + oA;
     w.d64 = reinterpret_cast<double *>(b + od);
-    w.dinv64 = reinterpret_cast<double *>(b + odi64);
+    w.dinv = b + odi;
+    w.r = b + or_;
+    w.p = b + op_;
+    w.q = b + oq;
+    w.xc = b + oxc;
     w.r64 = reinterpret_cast<double *>(b + or64);
-    w.p64 = reinterpret_cast<double *>(b + op64);
-    w.q64 = reinterpret_cast<double *>(b + oq64);
-    w.dinv32 = reinterpret_cast<float *>(b + odi32);
-    w.r32 = reinterpret_cast<float *>(b + or32);
-    w.p32 = reinterpret_cast<float *>(b + op32);
-    w.q32 = reinterpret_cast<float *>(b + oq32);
-    w.xc32 = reinterpret_cast<float *>(b + oxc);
     w.part64 = reinterpret_cast<double *>(b + opart64);
-    w.part32 = reinterpret_cast<float *>(b + opart32);
+    w.partv = b + opartv;
+    w.dots = reinterpret_cast<double *>(b + odots);
     w.upd = reinterpret_cast<double *>(b + oupd);
-    w.mv = reinterpret_cast<double *>(b + omv);
-    w.st = reinterpret_cast<fem::SolveState *>(b + ost);
+    w.st = reinterpret_cast<fem::IterState *>(b + ost);
     w.bad = reinterpret_cast<int *>(b + obad);
     return FEM_OK;
 }
@@ -139,6 +132,8 @@ void fem_solve_opts_default(fem_solve_opts *o) {
     o->max_outer = 200;
     o->check_every = 32;
     o->profile = 0;
+    o->vectors = 0;
+    o->block = 0;
 }
 
 int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_coords, const int32_t *d_conn,
@@ -155,9 +150,9 @@ int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_c
     if (n_dirichlet < 0 || (n_dirichlet > 0 && !d_dirichlet)) return set_error(FEM_EINVAL, "bad Dirichlet list");
     const int nb = dim + 1;
     if (chunk_elems == 0) chunk_elems = fem::default_chunk_elems(nb);
-    if (chunk_elems < 64 || chunk_elems % 64 != 0 || chunk_elems > fem::max_chunk_elems(nb))
-        return set_error(FEM_EINVAL, "chunk_elems must be a multiple of 64 in [64, " +
-                                         std::to_string(fem::max_chunk_elems(nb)) + "]");
+    if (!fem::valid_chunk_elems(nb, chunk_elems))
+        return set_error(FEM_EINVAL, nb == 3 ? "chunk_elems must be one of 64, 128, 256, 512, 1024, 1536, 2048"
+                                             : "chunk_elems must be one of 64, 128, 256, 512, 1024, 1536");
     hipStream_t s = S(stream);
     std::vector<double> coords((size_t)dim * n_nodes);
     std::vector<int32_t> conn((size_t)nb * n_elems);
@@ -275,9 +270,9 @@ int fem_plan_check_host(int dim, int64_t n_nodes, int64_t n_elems, const double 
     if (n_dirichlet < 0 || (n_dirichlet > 0 && !dirichlet)) return set_error(FEM_EINVAL, "bad Dirichlet list");
     const int nb = dim + 1;
     if (chunk_elems == 0) chunk_elems = fem::default_chunk_elems(nb);
-    if (chunk_elems < 64 || chunk_elems % 64 != 0 || chunk_elems > fem::max_chunk_elems(nb))
-        return set_error(FEM_EINVAL, "chunk_elems must be a multiple of 64 in [64, " +
-                                         std::to_string(fem::max_chunk_elems(nb)) + "]");
+    if (!fem::valid_chunk_elems(nb, chunk_elems))
+        return set_error(FEM_EINVAL, nb == 3 ? "chunk_elems must be one of 64, 128, 256, 512, 1024, 1536, 2048"
+                                             : "chunk_elems must be one of 64, 128, 256, 512, 1024, 1536");
     for (int64_t i = 0; i < (int64_t)dim * n_nodes; ++i)
         if (!std::isfinite(coords[i])) return set_error(FEM_EINVAL, "non-finite coordinate");
     fem::HostPlan H;
@@ -401,6 +396,9 @@ int fem_pcg_solve(const fem_plan *plan_c, const fem_solve_opts *o, const void *d
     if (o->dtype != FEM_F64 && (!(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0) || o->max_outer < 1))
         return set_error(FEM_EINVAL, "mixed precision needs inner_rtol in (0,1) and max_outer >= 1");
     if (o->profile < 0) return set_error(FEM_EINVAL, "profile must be >= 0");
+    if (o->vectors != 0 && o->vectors != 1) return set_error(FEM_EINVAL, "vectors must be 0 (FP64) or 1 (FP32)");
+    if (o->block != 0 && o->block != 256 && o->block != 512 && o->block != 1024)
+        return set_error(FEM_EINVAL, "block must be 0, 256, 512 or 1024");
     if ((!d_K_e && plan->dev.n_elems > 0) || !d_b || !d_x) return set_error(FEM_EINVAL, "NULL argument");
     if (o->nu != 0.0 && !d_M_e) return set_error(FEM_EINVAL, "nu > 0 needs M_e");
     if ((const void *)d_x == (const void *)d_b) return set_error(FEM_EINVAL, "x must not alias b");
@@ -411,7 +409,9 @@ int fem_pcg_solve(const fem_plan *plan_c, const fem_solve_opts *o, const void *d
     const int slot = o->dtype == FEM_F64 ? 0 : 1;
     if (int rc = alloc_work(plan, slot, o->dtype)) return rc;
     hipStream_t s = S(stream);
-    int rc = fem::solve_pcg(plan->dev, plan->work[slot], o->dtype, d_K_e, d_M_e, o->nu, d_b, d_x, o->rtol,
+    const int block = o->block ? o->block : fem::default_block(plan->dev.nb, plan->dev.E);
+    int rc = fem::solve_pcg(plan->dev, plan->work[slot], o->dtype, o->vectors == 0, block, d_K_e, d_M_e, o->nu, d_b,
+                            d_x, o->rtol,
                             o->max_iter, o->precond == FEM_PRECOND_JACOBI, o->inner_rtol, o->max_outer,
                             o->check_every, o->profile, info, s);
     if (hipStreamSynchronize(s) != hipSuccess && rc == FEM_OK) rc = set_error(FEM_EHIP, "stream synchronisation failed");

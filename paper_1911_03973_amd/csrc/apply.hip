@@ -22,18 +22,16 @@ struct OpAffine {
     const uint8_t *mask;
     T sign;
     int use_mask;
-    __device__ __forceinline__ bool begin(double *) { return true; }
-    __device__ __forceinline__ bool begin_fixup(double *) { return true; }
+    __device__ __forceinline__ bool begin() { return true; }
     __device__ __forceinline__ T gather(int g, bool) const { return x[g]; }
     __device__ __forceinline__ void gather_shared(int) {}
-    __device__ __forceinline__ double finish(int g, T acc) const {
+    __device__ __forceinline__ void finish(int g, T acc) const {
         T v = (b ? b[g] : (T)0) + sign * acc;
         if (use_mask && mask[g]) v = (T)0;
         out[g] = v;
-        return 0.0;
     }
-    __device__ __forceinline__ void end(double, double *) const {}
-    __device__ __forceinline__ void end_fixup(double, double *) const {}
+    template <int BS>
+    __device__ __forceinline__ void end(double *, int) const {}
 };
 
 int g_cu = 0;
@@ -41,14 +39,16 @@ int g_cu = 0;
 template <int NB, class T, class Ld, class Op, bool DIAG>
 int run_chunked(const DevPlan &P, const Ld &ld, const Op &op, T *scratch, hipStream_t s) {
     const size_t lds = chunk_lds_bytes<NB, T>(P.E);
-    const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / (lds + 1024))));
-    const int64_t cap = (int64_t)per_cu * device_cu_count();
-    const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(P.n_chunks, cap));
-    k_chunk_main<NB, T, Ld, Op, DIAG><<<gm, kBlock, lds, s>>>(P, ld, op, scratch);
+    const ChunkGrid cg = chunk_grid(P.n_chunks, lds);
+    int rc = dispatch_ept(P.E, [&](auto ept) {
+        k_chunk_main<NB, decltype(ept)::value, kBlock, T, Ld, Op, DIAG>
+            <<<cg.grid, kBlock, lds, s>>>(P, ld, op, scratch, cg.xcd);
+        return 0;
+    });
+    if (rc) return rc;
     FEM_HIP_CHECK(hipGetLastError());
     if (P.n_shared > 0) {
-        const int gf = (int)std::min<int64_t>((P.n_shared + kBlock - 1) / kBlock, 2048);
-        k_chunk_fixup<T, Op><<<gf, kBlock, 0, s>>>(P, op, scratch);
+        k_chunk_fixup<kBlock, T, Op><<<fixup_grid(P.n_shared), kBlock, 0, s>>>(P, op, scratch, 0);
         FEM_HIP_CHECK(hipGetLastError());
     }
     return 0;
@@ -70,7 +70,31 @@ int diag64_nb(const DevPlan &P, const void *K, const void *M, double nu, double 
     return run_chunked<NB, double, decltype(ld), decltype(op), true>(P, ld, op, scratch, s);
 }
 
+template <int NB, int KIND>
+int apply_pk64_nb(const DevPlan &P, const void *A, const double *x, const double *b, double *out, double sign,
+                  int use_mask, double *scratch, hipStream_t s) {
+    LdPk<NB, KIND> ld{A, P.n_elems};
+    OpAffine<double> op{x, b, out, P.mask, sign, use_mask};
+    return run_chunked<NB, double, decltype(ld), decltype(op), false>(P, ld, op, scratch, s);
+}
+
 }  // namespace
+
+ChunkGrid chunk_grid(int64_t n_chunks, size_t lds, int bs) {
+    const int per_cu = std::max(1, std::min(2048 / bs, (int)(160 * 1024 / (lds + 512))));
+    const int64_t cap = (int64_t)per_cu * device_cu_count();
+    ChunkGrid g;
+    if (n_chunks >= 8) {
+        int64_t gr = std::min<int64_t>(cap, n_chunks);
+        gr = std::max<int64_t>(8, gr / 8 * 8);
+        g.grid = (int)gr;
+        g.xcd = 1;
+    } else {
+        g.grid = (int)std::max<int64_t>(1, n_chunks);
+        g.xcd = 0;
+    }
+    return g;
+}
 
 int device_cu_count() {
     if (g_cu <= 0) {
@@ -83,13 +107,18 @@ int device_cu_count() {
     return g_cu;
 }
 
-int max_chunk_elems(int nb) {
-    // FP64 slot buffer + uint16 slot list within kMaxChunkLds, multiple of 64
-    int e = kMaxChunkLds / (nb * (8 + 2));
-    return (e / 64) * 64;
+bool valid_chunk_elems(int nb, int E) {
+    switch (E) {
+        case 64: case 128: case 256: case 512: case 1024: case 1536: case 2048: break;
+        default: return false;
+    }
+    // FP64 slot buffer + uint16 slot list within kMaxChunkLds
+    return (size_t)nb * E * (8 + 2) <= (size_t)kMaxChunkLds;
 }
 
 int default_chunk_elems(int nb) { return nb == 3 ? 2048 : 1536; }
+
+int default_block(int nb, int E) { return E >= 1024 ? 512 : 256; }
 
 int launch_apply64(const DevPlan &P, int kind, const void *K, const void *M, double nu, const double *x,
                    const double *b, double *out, double sign, int use_mask, double *scratch, hipStream_t s) {
@@ -103,6 +132,16 @@ int launch_apply64(const DevPlan &P, int kind, const void *K, const void *M, dou
     if (kind == MAT_F32) FEM_A64(4, MAT_F32);
     FEM_A64(4, MAT_F32X2);
 #undef FEM_A64
+}
+
+int launch_apply_pk64(const DevPlan &P, int kind, const void *A, const double *x, const double *b, double *out,
+                      double sign, int use_mask, double *scratch, hipStream_t s) {
+    if (P.nb == 3) {
+        if (kind == MAT_F64) return apply_pk64_nb<3, MAT_F64>(P, A, x, b, out, sign, use_mask, scratch, s);
+        return apply_pk64_nb<3, MAT_F32X2>(P, A, x, b, out, sign, use_mask, scratch, s);
+    }
+    if (kind == MAT_F64) return apply_pk64_nb<4, MAT_F64>(P, A, x, b, out, sign, use_mask, scratch, s);
+    return apply_pk64_nb<4, MAT_F32X2>(P, A, x, b, out, sign, use_mask, scratch, s);
 }
 
 int launch_apply32(const DevPlan &P, const float *A, const float *x, const float *b, float *out, float sign,

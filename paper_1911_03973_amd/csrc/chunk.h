@@ -3,63 +3,167 @@
 //
 // Algorithm 1 restricts x to every element (x_e = R_e x), applies the local
 // matrix and assembles r = sum_e C_e^T r_e.  Here one workgroup takes a chunk
-// of consecutive elements at a time (grid-stride over chunks):
+// of E consecutive elements at a time (grid-stride over chunks):
 //
+//   fetch   the E elements' matrix values are requested first, straight into
+//           registers (EPT = E/256 elements per thread), so their HBM latency
+//           overlaps the rest of the pass
 //   stage   the chunk's slot list (uint16, grouped by local node) -> LDS
-//   phase A node-driven: every local node loads its input value once (a
-//           coalesced-ish gather of the chunk's node footprint) and writes it
-//           into all its slots                         == restriction R_e x
-//   phase B element-driven, one thread per element: the n_b^2 entries of A_e
-//           stream in coalesced from the SoA arrays, y = A_e x_e, and y
-//           overwrites the element's slots              == local product
+//   phase A node-driven: every local node loads its input value once and
+//           writes it into all its slots                == restriction R_e x
+//   phase B element-driven: y = A_e x_e from registers; y overwrites the
+//           element's slots                              == local product
 //   phase C node-driven: every local node sums its slots in ascending slot
-//           order (fixed), complete nodes are finished in place, shared
-//           nodes leave a partial                       == assembly C_e^T
+//           order (fixed); nodes of this chunk only are finished in place,
+//           shared nodes leave a partial                 == assembly C_e^T
 //   fix-up  one thread per shared node adds its partials in ascending chunk
 //           order.
 //
-// Every sum therefore has one fixed order: the result is bitwise
-// reproducible and no floating-point atomics are used.  The operation-specific
-// parts (what is loaded in phase A, what is stored in phase C) are `Op`
-// policies; the element-matrix access is a `Ld` policy.
+// Every sum has one fixed order: results are bitwise reproducible and no
+// floating-point atomics are used.  Chunks are dealt to workgroups so that
+// each of the 8 XCDs (workgroup i runs on XCD i mod 8) walks a contiguous
+// range of chunks: neighbouring chunks share halo nodes, which then hit the
+// same L2.  What is loaded in phase A and stored in phase C is an `Op`
+// policy; the element matrix is an `Ld` policy.
 #pragma once
+
+#include <type_traits>
 
 #include "common.h"
 
 namespace fem {
 
-// Matrix access: A(i,j) of element e as type T.
+// ---------------------------------------------------------------------------
+// Element matrix policies.  fetch() issues the loads of element e into a
+// register record; apply() computes y = A_e x_e; diag() returns (A_e)_ii.
+// ---------------------------------------------------------------------------
+
+// Full n_b x n_b storage, A_e = K_e + nu M_e combined at fetch time.
 template <int NB, int KIND, class T>
 struct LdKM {
     const void *K;
     const void *M;  // nullable
     double nu;
     int64_t ne;
-    __device__ __forceinline__ void load(int64_t e, T (&a)[NB * NB]) const {
+    struct Regs {
+        T a[NB * NB];
+    };
+    __device__ __forceinline__ void fetch(int64_t e, Regs &R) const {
         const int64_t blk = (int64_t)NB * NB * ne;
 #pragma unroll
         for (int ij = 0; ij < NB * NB; ++ij) {
             double v = load_entry<KIND>(K, (int64_t)ij * ne + e, blk);
             if (M) v += nu * load_entry<KIND>(M, (int64_t)ij * ne + e, blk);
-            a[ij] = (T)v;
+            R.a[ij] = (T)v;
         }
+    }
+    __device__ __forceinline__ static void apply(const Regs &R, const T (&x)[NB], T (&y)[NB]) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            T s = R.a[i * NB] * x[0];
+#pragma unroll
+            for (int j = 1; j < NB; ++j) s += R.a[i * NB + j] * x[j];
+            y[i] = s;
+        }
+    }
+    __device__ __forceinline__ static void diag(const Regs &R, T (&y)[NB]) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) y[i] = R.a[i * NB + i];
     }
 };
 
-// FP32 combined matrix, loaded as float.
+// FP32 combined full storage, FP32 arithmetic.
 template <int NB>
 struct LdF32 {
     const float *A;
     int64_t ne;
-    __device__ __forceinline__ void load(int64_t e, float (&a)[NB * NB]) const {
+    struct Regs {
+        float a[NB * NB];
+    };
+    __device__ __forceinline__ void fetch(int64_t e, Regs &R) const {
 #pragma unroll
-        for (int ij = 0; ij < NB * NB; ++ij) a[ij] = __builtin_nontemporal_load(A + (int64_t)ij * ne + e);
+        for (int ij = 0; ij < NB * NB; ++ij) R.a[ij] = __builtin_nontemporal_load(A + (int64_t)ij * ne + e);
+    }
+    __device__ __forceinline__ static void apply(const Regs &R, const float (&x)[NB], float (&y)[NB]) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            float s = R.a[i * NB] * x[0];
+#pragma unroll
+            for (int j = 1; j < NB; ++j) s += R.a[i * NB + j] * x[j];
+            y[i] = s;
+        }
+    }
+    __device__ __forceinline__ static void diag(const Regs &R, float (&y)[NB]) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) y[i] = R.a[i * NB + i];
     }
 };
 
-struct ChunkShape {
-    int E;           // elements per chunk
-    size_t lds;      // dynamic LDS bytes
+// Packed symmetric difference form of A_e (see solver.h, packed_count):
+// values 0..NB-1 are the row sums rho_i = sum_j (A_e)_ij, then the upper
+// off-diagonal entries a_ij (i < j) row by row, and
+//   (A_e x)_i = rho_i x_i + sum_{j != i} a_ij (x_j - x_i),
+// evaluated in FP64.  For a matrix with zero row sums (a stiffness matrix)
+// the rounding error then scales with the differences x_j - x_i rather than
+// with x itself, which keeps an FP32-stored operator accurate on smooth
+// vectors.  KIND: MAT_F64 (double values), MAT_F32 (float; the head of a
+// hi/lo pair) or MAT_F32X2 (hi + lo).
+template <int NB, int KIND>
+struct LdPk {
+    static constexpr int NP = NB + NB * (NB - 1) / 2;
+    using V = typename std::conditional<KIND == MAT_F32, float, double>::type;
+    const void *A;
+    int64_t ne;
+    struct Regs {
+        V v[NP];
+    };
+    __device__ __forceinline__ void fetch(int64_t e, Regs &R) const {
+        const int64_t blk = (int64_t)NP * ne;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            if constexpr (KIND == MAT_F32)
+                R.v[k] = __builtin_nontemporal_load(static_cast<const float *>(A) + (int64_t)k * ne + e);
+            else
+                R.v[k] = load_entry<KIND>(A, (int64_t)k * ne + e, blk);
+        }
+    }
+    template <class T>
+    __device__ __forceinline__ static void apply(const Regs &R, const T (&xt)[NB], T (&yt)[NB]) {
+        double x[NB], y[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            x[i] = (double)xt[i];
+            y[i] = (double)R.v[i] * x[i];
+        }
+        int k = NB;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = i + 1; j < NB; ++j) {
+                const double t = (double)R.v[k++] * (x[j] - x[i]);
+                y[i] += t;
+                y[j] -= t;
+            }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) yt[i] = (T)y[i];
+    }
+    template <class T>
+    __device__ __forceinline__ static void diag(const Regs &R, T (&yt)[NB]) {
+        double y[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) y[i] = (double)R.v[i];
+        int k = NB;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = i + 1; j < NB; ++j) {
+                y[i] -= (double)R.v[k];
+                y[j] -= (double)R.v[k];
+                ++k;
+            }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) yt[i] = (T)y[i];
+    }
 };
 
 template <int NB, class T>
@@ -67,36 +171,72 @@ __host__ __device__ constexpr size_t chunk_lds_bytes(int E) {
     return (size_t)NB * E * sizeof(T) + (size_t)NB * E * sizeof(uint16_t);
 }
 
-// DIAG = true: phase A is skipped and phase B yields y_i = A_ii.
-template <int NB, class T, class Ld, class Op, bool DIAG>
-__global__ __launch_bounds__(kBlock) void k_chunk_main(const DevPlan P, const Ld ld, Op op,
-                                                       T *__restrict__ partial) {
+// Chunk visited by workgroup b at its it-th step, or -1 when done.  With
+// xcd != 0 (grid a multiple of 8) XCD b%8 walks chunks [x*cpx, (x+1)*cpx).
+__device__ __forceinline__ int64_t chunk_of(int64_t b, int64_t it, int64_t n_chunks, int64_t grid, int xcd) {
+    if (!xcd) {
+        const int64_t c = b + it * grid;
+        return c < n_chunks ? c : -1;
+    }
+    const int64_t cpx = (n_chunks + 7) / 8;
+    const int64_t bpx = grid / 8;
+    const int64_t j = (b >> 3) + it * bpx;
+    if (j >= cpx) return -1;
+    const int64_t c = (b & 7) * cpx + j;
+    return c < n_chunks ? c : -1;
+}
+
+// Stage the chunk's slot list (16-byte aligned, padded to n_b*E) into LDS.
+__device__ __forceinline__ void stage_slots(const uint16_t *__restrict__ src_u16, uint16_t *sl, int ns) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(src_u16);
+    uint4 *dst = reinterpret_cast<uint4 *>(sl);
+    const int nv = (ns + 7) >> 3;
+    for (int k = threadIdx.x; k < nv; k += kBlock) dst[k] = src[k];
+}
+
+// Shared scratch of the chunk kernels for block reductions (up to 8 sums).
+template <int BS>
+struct RedBuf {
+    double v[8 * (BS / kWave)];
+};
+
+// One workgroup of BS threads walks chunks of E = P.E elements; each thread
+// owns EPT = ceil(E / BS) element slots.  DIAG = true: phase A is skipped
+// and phase B yields y_i = A_ii.
+template <int NB, int EPT, int BS, class T, class Ld, class Op, bool DIAG>
+__global__ __launch_bounds__(BS) void k_chunk_main(const DevPlan P, const Ld ld, Op op, T *__restrict__ partial,
+                                                   int xcd) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int E = P.E;
     T *buf = reinterpret_cast<T *>(smem);
     uint16_t *sl = reinterpret_cast<uint16_t *>(smem + (size_t)NB * E * sizeof(T));
-    __shared__ double red[kBlock / kWave];
-    if (!op.begin(red)) return;
-    double dacc = 0.0;
-    for (int64_t c = blockIdx.x; c < P.n_chunks; c += gridDim.x) {
+    __shared__ RedBuf<BS> red;
+    if (!op.begin()) return;
+    for (int64_t it = 0;; ++it) {
+        const int64_t c = chunk_of(blockIdx.x, it, P.n_chunks, gridDim.x, xcd);
+        if (c < 0) break;
         const int64_t e0 = c * (int64_t)E;
         const int ne = (int)((P.n_elems - e0) < E ? (P.n_elems - e0) : E);
-        const int ns = ne * NB;
+        typename Ld::Regs R[EPT];
+#pragma unroll
+        for (int t = 0; t < EPT; ++t) {
+            const int le = t * BS + threadIdx.x;
+            if (le < ne) ld.fetch(e0 + le, R[t]);
+        }
         const int nb0 = P.chunk_node_off[c];
         const int nl = P.chunk_node_off[c + 1] - nb0;
         const int ncomp = P.chunk_info[2 * c];
         const int pbase = P.chunk_info[2 * c + 1];
         __syncthreads();  // the previous chunk's phase C is done with buf / sl
         {
-            // slot list -> LDS, 16-byte vectors (n_b*E*2 bytes is a multiple of 16)
             const uint4 *src = reinterpret_cast<const uint4 *>(P.slots + c * (int64_t)NB * E);
             uint4 *dst = reinterpret_cast<uint4 *>(sl);
-            const int nv = (ns + 7) >> 3;
-            for (int k = threadIdx.x; k < nv; k += kBlock) dst[k] = src[k];
+            const int nv = (ne * NB + 7) >> 3;
+            for (int k = threadIdx.x; k < nv; k += BS) dst[k] = src[k];
         }
         __syncthreads();
         if constexpr (!DIAG) {
-            for (int k = threadIdx.x; k < nl; k += kBlock) {
+            for (int k = threadIdx.x; k < nl; k += BS) {
                 const int g = P.loc_nodes[nb0 + k];
                 const int s0 = k ? P.loc_end[nb0 + k - 1] : 0;
                 const int s1 = P.loc_end[nb0 + k];
@@ -105,55 +245,110 @@ __global__ __launch_bounds__(kBlock) void k_chunk_main(const DevPlan P, const Ld
             }
             __syncthreads();
         }
-        for (int le = threadIdx.x; le < ne; le += kBlock) {
-            T a[NB * NB];
-            ld.load(e0 + le, a);
-            T y[NB];
-            if constexpr (DIAG) {
 #pragma unroll
-                for (int i = 0; i < NB; ++i) y[i] = a[i * NB + i];
-            } else {
-                T xe[NB];
+        for (int t = 0; t < EPT; ++t) {
+            const int le = t * BS + threadIdx.x;
+            if (le < ne) {
+                T y[NB];
+                if constexpr (DIAG) {
+                    Ld::diag(R[t], y);
+                } else {
+                    T xe[NB];
 #pragma unroll
-                for (int j = 0; j < NB; ++j) xe[j] = buf[le * NB + j];
-#pragma unroll
-                for (int i = 0; i < NB; ++i) {
-                    T s = a[i * NB] * xe[0];
-#pragma unroll
-                    for (int j = 1; j < NB; ++j) s += a[i * NB + j] * xe[j];
-                    y[i] = s;
+                    for (int j = 0; j < NB; ++j) xe[j] = buf[le * NB + j];
+                    Ld::apply(R[t], xe, y);
                 }
-            }
 #pragma unroll
-            for (int i = 0; i < NB; ++i) buf[le * NB + i] = y[i];
+                for (int i = 0; i < NB; ++i) buf[le * NB + i] = y[i];
+            }
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < nl; k += kBlock) {
+        for (int k = threadIdx.x; k < nl; k += BS) {
             const int s0 = k ? P.loc_end[nb0 + k - 1] : 0;
             const int s1 = P.loc_end[nb0 + k];
             T acc = (T)0;
             for (int s = s0; s < s1; ++s) acc += buf[sl[s]];
-            if (k < ncomp) dacc += op.finish(P.loc_nodes[nb0 + k], acc);
+            if (k < ncomp) op.finish(P.loc_nodes[nb0 + k], acc);
             else partial[pbase + (k - ncomp)] = acc;
         }
     }
-    op.end(dacc, red);
+    op.template end<BS>(red.v, blockIdx.x);
 }
 
-template <class T, class Op>
-__global__ __launch_bounds__(kBlock) void k_chunk_fixup(const DevPlan P, Op op, const T *__restrict__ partial) {
-    __shared__ double red[kBlock / kWave];
-    if (!op.begin_fixup(red)) return;
-    double dacc = 0.0;
-    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < P.n_shared; s += (int64_t)gridDim.x * kBlock) {
+// Shared nodes: one thread per node adds the node's partials in ascending
+// chunk order.  Dot-product partials of this kernel go to slot_base + block.
+template <int BS, class T, class Op>
+__global__ __launch_bounds__(BS) void k_chunk_fixup(const DevPlan P, Op op, const T *__restrict__ partial,
+                                                    int slot_base) {
+    __shared__ RedBuf<BS> red;
+    if (!op.begin()) return;
+    for (int64_t s = (int64_t)blockIdx.x * BS + threadIdx.x; s < P.n_shared; s += (int64_t)gridDim.x * BS) {
         const int g = P.fix_nodes[s];
         const int k0 = P.fix_off[s], k1 = P.fix_off[s + 1];
         T acc = (T)0;
         for (int k = k0; k < k1; ++k) acc += partial[P.fix_parts[k]];
         op.gather_shared(g);
-        dacc += op.finish(g, acc);
+        op.finish(g, acc);
     }
-    op.end_fixup(dacc, red);
+    op.template end<BS>(red.v, slot_base + blockIdx.x);
+}
+
+// Grid of the chunk kernels: enough workgroups to fill every CU at the
+// occupancy the LDS footprint allows (at most 2048 threads per CU), a
+// multiple of 8 when possible (XCD-aware chunk order), never more than
+// there are chunks.
+struct ChunkGrid {
+    int grid;
+    int xcd;
+};
+
+ChunkGrid chunk_grid(int64_t n_chunks, size_t lds, int bs = kBlock);
+
+inline int fixup_grid(int64_t n_shared) {
+    int64_t g = (n_shared + kBlock - 1) / kBlock;
+    return (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
+}
+
+// Calls f(std::integral_constant<int, EPT>) for the plan's chunk size and a
+// block of 256 threads.
+template <class F>
+int dispatch_ept(int E, F &&f) {
+    switch (E) {
+        case 64:
+        case 128:
+        case 256: return f(std::integral_constant<int, 1>());
+        case 512: return f(std::integral_constant<int, 2>());
+        case 1024: return f(std::integral_constant<int, 4>());
+        case 1536: return f(std::integral_constant<int, 6>());
+        case 2048: return f(std::integral_constant<int, 8>());
+        default: return set_error(-1, "unsupported chunk size");
+    }
+}
+
+// Calls f(integral_constant<BS>, integral_constant<EPT>) for a chunk size E
+// and a workgroup size BS in {256, 512, 1024} (EPT = ceil(E / BS)).
+template <class F>
+int dispatch_tile(int E, int BS, F &&f) {
+    using std::integral_constant;
+    if (BS == 256) return dispatch_ept(E, [&](auto ept) { return f(integral_constant<int, 256>(), ept); });
+    if (BS == 512) {
+        switch (E) {
+            case 64: case 128: case 256: case 512: return f(integral_constant<int, 512>(), integral_constant<int, 1>());
+            case 1024: return f(integral_constant<int, 512>(), integral_constant<int, 2>());
+            case 1536: return f(integral_constant<int, 512>(), integral_constant<int, 3>());
+            case 2048: return f(integral_constant<int, 512>(), integral_constant<int, 4>());
+            default: break;
+        }
+    }
+    if (BS == 1024) {
+        switch (E) {
+            case 64: case 128: case 256: case 512: case 1024:
+                return f(integral_constant<int, 1024>(), integral_constant<int, 1>());
+            case 1536: case 2048: return f(integral_constant<int, 1024>(), integral_constant<int, 2>());
+            default: break;
+        }
+    }
+    return set_error(-1, "unsupported chunk size / workgroup size");
 }
 
 }  // namespace fem

@@ -36,8 +36,9 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Deterministic block sum of one value per thread (blockDim == kBlock).
-// Every thread receives the same total.  `red` must hold kBlock/kWave doubles.
+// Deterministic block sum of one value per thread (blockDim == BS).
+// Every thread receives the same total.  `red` must hold BS/64 doubles.
+template <int BS = kBlock>
 __device__ __forceinline__ double block_sum(double v, double *red) {
     v = wave_sum(v);
     const int w = threadIdx.x / kWave;
@@ -46,15 +47,36 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     __syncthreads();
     double t = 0.0;
 #pragma unroll
-    for (int k = 0; k < kBlock / kWave; ++k) t += red[k];
+    for (int k = 0; k < BS / kWave; ++k) t += red[k];
     return t;
 }
 
+// N block sums at once (one LDS exchange).  `red` must hold N*BS/64 doubles.
+template <int BS, int N>
+__device__ __forceinline__ void block_sum_n(double (&v)[N], double *red) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = wave_sum(v[j]);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+        for (int j = 0; j < N; ++j) red[j * (BS / kWave) + w] = v[j];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < BS / kWave; ++k) t += red[j * (BS / kWave) + k];
+        v[j] = t;
+    }
+}
+
 // Sum n partials (fixed assignment and order; identical result in every block).
+template <int BS = kBlock>
 __device__ __forceinline__ double reduce_partials(const double *part, int n, double *red) {
     double v = 0.0;
-    for (int k = threadIdx.x; k < n; k += kBlock) v += part[k];
-    return block_sum(v, red);
+    for (int k = threadIdx.x; k < n; k += BS) v += part[k];
+    return block_sum<BS>(v, red);
 }
 
 std::string &last_error();

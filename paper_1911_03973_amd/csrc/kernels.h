@@ -11,8 +11,10 @@ namespace fem {
 // list of one chunk must fit in 64 KiB of LDS.
 constexpr int kMaxChunkLds = 65536;
 
-int max_chunk_elems(int nb);
+bool valid_chunk_elems(int nb, int E);
 int default_chunk_elems(int nb);
+// Default workgroup size of the solver's element pass for a chunk size.
+int default_block(int nb, int E);
 int device_cu_count();
 
 int launch_local_matrices(const DevPlan &P, int kind, void *K, void *M, double *vol, hipStream_t s);
@@ -26,6 +28,13 @@ int launch_apply64(const DevPlan &P, int kind, const void *K, const void *M, dou
 // the same with float matrices, vectors and accumulation; scratch: n_partials floats
 int launch_apply32(const DevPlan &P, const float *A, const float *x, const float *b, float *out, float sign,
                    int use_mask, float *scratch, hipStream_t s);
+// The same through the packed difference form (kind MAT_F64 or MAT_F32X2).
+int launch_apply_pk64(const DevPlan &P, int kind, const void *A, const double *x, const double *b, double *out,
+                      double sign, int use_mask, double *scratch, hipStream_t s);
+// Packed difference form of A_e = K_e + nu M_e (FP64 arithmetic), stored as
+// kout = MAT_F64 or MAT_F32X2.
+int launch_pack(const DevPlan &P, int kin, const void *K, const void *M, double nu, int kout, void *A,
+                hipStream_t s);
 // d = sum_e C_e^T diag(A_e)
 int launch_diag64(const DevPlan &P, int kind, const void *K, const void *M, double nu, double *d,
                   double *scratch, hipStream_t s);

@@ -121,6 +121,50 @@ __global__ __launch_bounds__(kBlock) void k_combine(const void *__restrict__ K, 
     }
 }
 
+// Packed symmetric difference form of A_e = K_e + nu M_e: row sums, then the
+// symmetrised upper off-diagonal entries a_ij = (A_ij + A_ji) / 2.
+template <int NB, int KIN, int KOUT>
+__global__ __launch_bounds__(kBlock) void k_pack(const void *__restrict__ K, const void *__restrict__ M, double nu,
+                                                 int64_t n_elems, void *__restrict__ A) {
+    constexpr int NP = NB + NB * (NB - 1) / 2;
+    const int64_t blk_in = (int64_t)NB * NB * n_elems;
+    const int64_t blk_out = (int64_t)NP * n_elems;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_elems;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double a[NB][NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int64_t idx = (int64_t)(i * NB + j) * n_elems + e;
+                double v = load_entry<KIN>(K, idx, blk_in);
+                if (M) v += nu * load_entry<KIN>(M, idx, blk_in);
+                a[i][j] = v;
+            }
+        double off[NB][NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = i + 1; j < NB; ++j) {
+                off[i][j] = 0.5 * (a[i][j] + a[j][i]);
+                off[j][i] = off[i][j];
+            }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            double rho = a[i][i];
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (j != i) rho += off[i][j];
+            store_entry<KOUT>(A, (int64_t)i * n_elems + e, blk_out, rho);
+        }
+        int k = NB;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = i + 1; j < NB; ++j) store_entry<KOUT>(A, (int64_t)(k++) * n_elems + e, blk_out, off[i][j]);
+    }
+}
+
 int grid_for(int64_t n, int64_t cap) {
     int64_t g = (n + kBlock - 1) / kBlock;
     if (g > cap) g = cap;
@@ -169,6 +213,30 @@ int launch_combine(const DevPlan &P, int kin, const void *K, const void *M, doub
 #undef FEM_CB_IN
 #undef FEM_CB_OUT
 #undef FEM_CB
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int launch_pack(const DevPlan &P, int kin, const void *K, const void *M, double nu, int kout, void *A,
+                hipStream_t s) {
+    const int g = grid_for(P.n_elems, 65536);
+#define FEM_PK(NB, KI, KO) k_pack<NB, KI, KO><<<g, kBlock, 0, s>>>(K, M, nu, P.n_elems, A)
+#define FEM_PK_OUT(NB, KI)                                  \
+    do {                                                    \
+        if (kout == MAT_F64) FEM_PK(NB, KI, MAT_F64);       \
+        else FEM_PK(NB, KI, MAT_F32X2);                     \
+    } while (0)
+#define FEM_PK_IN(NB)                                       \
+    do {                                                    \
+        if (kin == MAT_F64) FEM_PK_OUT(NB, MAT_F64);        \
+        else if (kin == MAT_F32) FEM_PK_OUT(NB, MAT_F32);   \
+        else FEM_PK_OUT(NB, MAT_F32X2);                     \
+    } while (0)
+    if (P.nb == 3) FEM_PK_IN(3);
+    else FEM_PK_IN(4);
+#undef FEM_PK_IN
+#undef FEM_PK_OUT
+#undef FEM_PK
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }

@@ -1,32 +1,46 @@
 // pcg.hip -- Jacobi-preconditioned conjugate gradients driven by the element
-// operator, in FP64 and in FP32 with FP64 reliable updates.
+// operator, in FP64 and with FP32-stored local matrices inside FP64
+// iterative refinement.
 //
-// One CG iteration is three kernels:
-//   main    reduces the previous update's partials (r.z, r.r) in a fixed order,
-//           decides convergence / reliable-update on the device, forms
-//           beta and p = z + beta p inside the restriction phase of the
-//           element operator, q = A p (masked), and per-block p.q partials;
-//   fixup   the same for the nodes shared between chunks;
-//   update  reduces p.q, alpha = r.z / p.q, x += alpha p, r -= alpha q, and
-//           per-block partials of r.z and r.r (z = D^{-1} r is never stored).
-// Every reduction has one fixed order (wave64 xor butterfly, then the block's
-// four waves, then the blocks in index order), so a solve is bitwise
-// reproducible.  The host only enqueues; it reads a small state record every
-// `check_every` iterations.  Once the device has raised its flag the remaining
-// enqueued kernels return at once.
+// One iteration is a single pass over the elements plus two small kernels:
+//   element pass  (k_chunk_main with OpIter, then k_chunk_fixup for the nodes
+//                  shared between chunks) completes the previous iteration's
+//                  update r -= alpha q, x += alpha p while gathering,
+//                  forms p = D^{-1} r + beta p in the restriction phase,
+//                  computes q = A p, and accumulates seven per-block dot
+//                  products: p.q, q.Dr, q.Dq, q.r, q.q and, directly, r.Dr
+//                  and r.r of the residual just formed;
+//   finalize      one workgroup adds the partials in a fixed order and
+//                  advances the scalars: alpha = r.z / p.q and, without a
+//                  second reduction, the next r'.z' = r.z - 2 alpha q.Dr +
+//                  alpha^2 q.Dq and r'.r' = r.r - 2 alpha q.r + alpha^2 q.q
+//                  (the single-reduction form of Chronopoulos & Gear), beta,
+//                  and the convergence / refresh decision.  The recurrence
+//                  always starts from the directly summed r.z and r.r of the
+//                  current residual, so its rounding error cannot accumulate
+//                  over iterations (it would, relative to the shrinking r.z,
+//                  after a few decades of convergence).
+// The element kernels read the scalars that the previous finalize wrote, so
+// each value has one writer and a kernel boundary between writer and reader.
+// The host only enqueues; it reads the state record every `check_every`
+// iterations.  Once the device has raised its flag, the kernels still queued
+// return at once.
 //
-// Mixed precision (FP32 inner, FP64 outer): r, p, q, the correction of x and
-// D^{-1} are FP32 and the operator is the FP32 head of the hi/lo pair of the
-// combined local matrices; dot products are accumulated in FP64 and alpha /
-// beta are FP64.  Whenever the FP32 residual has fallen by a factor `delta`
-// since the last refresh (or below the target), the correction is folded into
-// the FP64 x, the true residual b - A x is recomputed in FP64 from hi + lo,
-// and CG continues from it with the same search direction -- iterative
-// refinement in the "reliable update" form of Sleijpen & van der Vorst.
+// The operator is stored in the packed symmetric difference form (chunk.h,
+// LdPk): FP64 values for the FP64 solver, or FP32 hi/lo pairs for the mixed
+// solver, whose iterations read only the FP32 heads.  Every refresh (reliable
+// update of Sleijpen & van der Vorst: when r.r has fallen by delta^2 since the
+// last refresh, or below the target) applies the pending step, recomputes the
+// true residual b - A x in FP64 from hi + lo, and continues CG from it with
+// the same search direction.  Iteration vectors are FP64 by default; FP32
+// vectors (with an FP32 correction of x folded into the FP64 x at each
+// refresh) are the low-traffic variant.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
+#include <vector>
 
 #include "chunk.h"
 #include "kernels.h"
@@ -36,132 +50,179 @@ namespace fem {
 
 namespace {
 
-// ---------------------------------------------------------------- ops ----
-template <class T>
-struct OpPcg {
-    const T *r;
-    const T *dinv;
-    T *p;
-    T *q;
-    const uint8_t *mask;
-    SolveState *st;
-    const double *upd;  // [2][n_upd] r.z then r.r partials
-    int n_upd;
-    double *mv;         // p.q partials: [gm] main blocks then [gf] fixup blocks
-    int gm;
-    int first;
-    double thr2;        // trigger when r.r <= thr2
-    double rel2;        // or when r.r < rel2 (reliable update), 0 = off
-    T beta;
+constexpr int kDots = 7;
 
-    __device__ bool begin(double *red) {
-        if (st->flag) return false;
-        const double rz = reduce_partials(upd, n_upd, red);
-        const double rr = reduce_partials(upd + n_upd, n_upd, red);
-        if (!(rr > thr2) || (rel2 > 0.0 && rr < rel2) || !isfinite(rz) || !isfinite(rr)) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                st->flag = (isfinite(rz) && isfinite(rr)) ? 1 : 2;
-                st->rr_trigger = rr;
-            }
-            return false;
-        }
-        const double b = first ? 0.0 : rz / st->rz_prev;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            st->rz_cur = rz;
-            st->beta = b;
-        }
-        beta = (T)b;
-        return true;
+// r_new = r - alpha q, x_new = x + alpha p, p_new = D^{-1} r_new + beta p
+// rounded to the vector type VT.  Written with explicit fma so that the
+// element pass and the fix-up produce identical bits for a shared node.
+template <class VT>
+struct Step {
+    __device__ __forceinline__ static VT r_next(VT r, VT q, double alpha) {
+        return (VT)__builtin_fma(-alpha, (double)q, (double)r);
     }
-    __device__ bool begin_fixup(double *) {
-        if (st->flag) return false;
-        beta = first ? (T)0 : (T)st->beta;
-        return true;
+    __device__ __forceinline__ static VT x_next(VT x, VT p, double alpha) {
+        return (VT)__builtin_fma(alpha, (double)p, (double)x);
     }
-    __device__ __forceinline__ T pnew(int g) const {
-        const T z = dinv[g] * r[g];
-        return first ? z : z + beta * p[g];
-    }
-    __device__ __forceinline__ T gather(int g, bool complete) {
-        const T v = pnew(g);
-        if (complete) p[g] = v;
-        return v;
-    }
-    __device__ __forceinline__ void gather_shared(int g) { p[g] = pnew(g); }
-    __device__ __forceinline__ double finish(int g, T acc) const {
-        const T qv = mask[g] ? (T)0 : acc;
-        q[g] = qv;
-        return (double)p[g] * (double)qv;
-    }
-    __device__ void end(double d, double *red) const {
-        const double t = block_sum(d, red);
-        if (threadIdx.x == 0) mv[blockIdx.x] = t;
-    }
-    __device__ void end_fixup(double d, double *red) const {
-        const double t = block_sum(d, red);
-        if (threadIdx.x == 0) mv[gm + blockIdx.x] = t;
+    __device__ __forceinline__ static VT p_next(VT d, VT rn, VT p, double beta) {
+        return (VT)__builtin_fma(beta, (double)p, (double)d * (double)rn);
     }
 };
 
-// ------------------------------------------------------------- kernels ----
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_update(int64_t n, T *__restrict__ x, T *__restrict__ r,
-                                                   const T *__restrict__ p, const T *__restrict__ q,
-                                                   const T *__restrict__ dinv, SolveState *st,
-                                                   const double *__restrict__ mv, int n_mv,
-                                                   double *__restrict__ upd) {
-    __shared__ double red[kBlock / kWave];
+template <class VT>
+struct OpIter {
+    VT *x, *r, *p, *q;
+    const VT *dinv;
+    const uint8_t *mask;
+    const IterState *st;
+    double *dots;  // [kDots][npart]
+    int npart, gm;
+    // per-thread
+    int mode;
+    double alpha, beta;
+    double d[kDots];
+
+    __device__ __forceinline__ bool begin() {
+        if (st->flag) return false;
+        mode = st->mode;
+        alpha = st->alpha;
+        beta = st->beta;
+#pragma unroll
+        for (int j = 0; j < kDots; ++j) d[j] = 0.0;
+        return true;
+    }
+
+    // new r, x, p of node g from the old values
+    __device__ __forceinline__ void advance(int g, VT &rn, VT &xn, VT &pn, bool &wr_rx) const {
+        const VT dv = dinv[g];
+        if (mode == MODE_CONTINUE) {
+            rn = Step<VT>::r_next(r[g], q[g], alpha);
+            xn = Step<VT>::x_next(x[g], p[g], alpha);
+            pn = Step<VT>::p_next(dv, rn, p[g], beta);
+            wr_rx = true;
+        } else {
+            rn = r[g];
+            xn = (VT)0;
+            pn = (mode == MODE_FIRST) ? (VT)((double)dv * (double)rn) : Step<VT>::p_next(dv, rn, p[g], beta);
+            wr_rx = false;
+        }
+    }
+    __device__ __forceinline__ void own(int g, VT rn, VT xn, VT pn, bool wr) {
+        if (wr) {
+            r[g] = rn;
+            x[g] = xn;
+        }
+        p[g] = pn;
+        const double rd = (double)rn;
+        d[5] += rd * (double)dinv[g] * rd;
+        d[6] += rd * rd;
+    }
+    __device__ __forceinline__ VT gather(int g, bool complete) {
+        VT rn, xn, pn;
+        bool wr;
+        advance(g, rn, xn, pn, wr);
+        if (complete) own(g, rn, xn, pn, wr);
+        return pn;
+    }
+    __device__ __forceinline__ void gather_shared(int g) {
+        VT rn, xn, pn;
+        bool wr;
+        advance(g, rn, xn, pn, wr);
+        own(g, rn, xn, pn, wr);
+    }
+    __device__ __forceinline__ void finish(int g, VT acc) {
+        const VT qv = mask[g] ? (VT)0 : acc;
+        q[g] = qv;
+        const double qd = (double)qv, pd = (double)p[g], rd = (double)r[g], dd = (double)dinv[g];
+        d[0] += pd * qd;
+        d[1] += qd * dd * rd;
+        d[2] += qd * dd * qd;
+        d[3] += qd * rd;
+        d[4] += qd * qd;
+    }
+    template <int BS>
+    __device__ void end(double *red, int slot) {
+        block_sum_n<BS, kDots>(d, red);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int j = 0; j < kDots; ++j) dots[(int64_t)j * npart + slot] = d[j];
+    }
+};
+
+// One workgroup: totals of the dot partials, then the scalar recurrence.
+__global__ __launch_bounds__(kBlock) void k_finalize(IterState *st, const double *__restrict__ dots, int npart,
+                                                     double thr2, double rel2) {
+    __shared__ double red[kDots * (kBlock / kWave)];
     if (st->flag) return;
-    const double pq = reduce_partials(mv, n_mv, red);
-    const double rz = st->rz_cur;
-    if (!(pq > 0.0) || !isfinite(pq)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->flag = 2;
+    // every thread sums a fixed, strided subset of each partial list, four
+    // partials in flight per list, then one block reduction of all seven
+    double t[kDots];
+#pragma unroll
+    for (int j = 0; j < kDots; ++j) t[j] = 0.0;
+    int k = threadIdx.x;
+    for (; k + 3 * kBlock < npart; k += 4 * kBlock) {
+#pragma unroll
+        for (int j = 0; j < kDots; ++j) {
+            const double *dj = dots + (int64_t)j * npart;
+            t[j] += ((dj[k] + dj[k + kBlock]) + (dj[k + 2 * kBlock] + dj[k + 3 * kBlock]));
+        }
+    }
+    for (; k < npart; k += kBlock)
+#pragma unroll
+        for (int j = 0; j < kDots; ++j) t[j] += dots[(int64_t)j * npart + k];
+    block_sum_n<kBlock, kDots>(t, red);
+    if (threadIdx.x != 0) return;
+    const double pq = t[0], qDr = t[1], qDq = t[2], qr = t[3], qq = t[4];
+    const double rz = t[5], rr = t[6];  // r.Dr and r.r of the residual behind p
+    st->rz = rz;
+    st->rr = rr;
+    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
+        st->flag = 2;
+        st->pending = 0;
         return;
     }
-    const double ad = rz / pq;
-    const T a = (T)ad;
-    double srz = 0.0, srr = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        x[i] += a * p[i];
-        const T ri = r[i] - a * q[i];
-        r[i] = ri;
-        const double rd = (double)ri;
-        srz += rd * (double)(dinv[i] * ri);
-        srr += rd * rd;
+    const double alpha = rz / pq;
+    const double rzn = rz - alpha * (2.0 * qDr - alpha * qDq);
+    const double rrn = rr - alpha * (2.0 * qr - alpha * qq);
+    st->alpha = alpha;
+    st->pq = pq;
+    st->pending = 1;
+    st->n_updates += 1;
+    st->rz_next = rzn;
+    st->rr_next = rrn;
+    if (!(rrn > thr2) || (rel2 > 0.0 && rrn < rel2) || !(rzn > 0.0) || !isfinite(rrn)) {
+        st->flag = 1;  // the host refreshes; rz stays that of the residual behind p
+        return;
     }
-    srz = block_sum(srz, red);
-    srr = block_sum(srr, red);
-    if (threadIdx.x == 0) {
-        upd[blockIdx.x] = srz;
-        upd[gridDim.x + blockIdx.x] = srr;
-        if (blockIdx.x == 0) {
-            st->rz_prev = rz;
-            st->alpha = ad;
-            st->n_updates += 1;
-        }
+    st->beta = rzn / rz;
+    st->mode = MODE_CONTINUE;
+}
+
+// Applies the pending step to every node (after a trigger or at the end).
+template <class VT>
+__global__ __launch_bounds__(kBlock) void k_pending(int64_t n, VT *__restrict__ x, VT *__restrict__ r,
+                                                    const VT *__restrict__ p, const VT *__restrict__ q,
+                                                    const IterState *st) {
+    if (!st->pending || st->flag == 2) return;
+    const double alpha = st->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        r[i] = Step<VT>::r_next(r[i], q[i], alpha);
+        x[i] = Step<VT>::x_next(x[i], p[i], alpha);
     }
 }
 
-// Partials of r.z and r.r for a fresh residual (start / refresh).  For the
-// mixed-precision path r64 is given: r32 = fl32(r64) is written and the
-// r.r partials of r64 go to upd[2 n_upd ...].
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_init_dots(int64_t n, T *__restrict__ r, const T *__restrict__ dinv,
+// r (VT) = r64, per-block partials of r.D r, r.r (VT values) and r64.r64.
+template <class VT>
+__global__ __launch_bounds__(kBlock) void k_init_dots(int64_t n, VT *__restrict__ r, const VT *__restrict__ dinv,
                                                       const double *__restrict__ r64, double *__restrict__ upd) {
     __shared__ double red[kBlock / kWave];
     double srz = 0.0, srr = 0.0, s64 = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        T ri;
-        if (r64) {
-            const double v = r64[i];
-            s64 += v * v;
-            ri = (T)v;
-            r[i] = ri;
-        } else {
-            ri = r[i];
-        }
+        const double v = r64[i];
+        s64 += v * v;
+        const VT ri = (VT)v;
+        r[i] = ri;
         const double rd = (double)ri;
-        srz += rd * (double)(dinv[i] * ri);
+        srz += rd * (double)dinv[i] * rd;
         srr += rd * rd;
     }
     srz = block_sum(srz, red);
@@ -174,30 +235,43 @@ __global__ __launch_bounds__(kBlock) void k_init_dots(int64_t n, T *__restrict__
     }
 }
 
-// One block: totals of the init partials into the state record.
-__global__ __launch_bounds__(kBlock) void k_reduce_state(SolveState *st, const double *__restrict__ upd, int n_upd) {
+// One workgroup: a fresh residual's totals into the state; the next element
+// pass starts a new p (first) or continues the old one with
+// beta = r'.z' / r.z (fresh).
+__global__ __launch_bounds__(kBlock) void k_refresh_state(IterState *st, const double *__restrict__ upd, int n_upd,
+                                                          int first) {
     __shared__ double red[kBlock / kWave];
     const double rz = reduce_partials(upd, n_upd, red);
     const double rr = reduce_partials(upd + n_upd, n_upd, red);
     const double r64 = reduce_partials(upd + 2 * n_upd, n_upd, red);
     if (threadIdx.x == 0) {
-        st->rz_init = rz;
-        st->rr_init = rr;
-        st->rr64_init = r64;
+        if (first) {
+            st->n_updates = 0;
+            st->beta = 0.0;
+            st->mode = MODE_FIRST;
+        } else {
+            st->beta = (st->rz > 0.0) ? rz / st->rz : 0.0;
+            st->mode = MODE_FRESH;
+        }
+        st->rz = rz;
+        st->rr = rr;
+        st->rr64 = r64;
         st->flag = 0;
+        st->pending = 0;
+        st->alpha = 0.0;
     }
 }
 
-template <class T>
+template <class VT>
 __global__ __launch_bounds__(kBlock) void k_dinv(int64_t n, const double *__restrict__ d,
-                                                 const uint8_t *__restrict__ mask, T *__restrict__ dinv,
-                                                 int jacobi, int *__restrict__ bad) {
+                                                 const uint8_t *__restrict__ mask, VT *__restrict__ dinv, int jacobi,
+                                                 int *__restrict__ bad) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        T v;
-        if (mask[i]) v = (T)0;
+        VT v;
+        if (mask[i]) v = (VT)0;
         else {
-            if (!(d[i] > 0.0)) *bad = 1;  // benign race: any writer stores 1
-            v = jacobi ? (T)(1.0 / d[i]) : (T)1;
+            if (!(d[i] > 0.0)) *bad = 1;  // every writer stores the same value
+            v = jacobi ? (VT)(1.0 / d[i]) : (VT)1;
         }
         dinv[i] = v;
     }
@@ -216,41 +290,12 @@ __global__ __launch_bounds__(kBlock) void k_fill(int64_t n, T *__restrict__ v, T
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) v[i] = val;
 }
 
-__global__ void k_clear_state(SolveState *st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        SolveState z{};
-        *st = z;
-    }
+__global__ void k_zero_int(int *p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
-__global__ void k_clear_flag(SolveState *st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) st->flag = 0;
-}
-
-}  // namespace
-
-Grids solver_grids(const DevPlan &P, size_t elem_lds) {
-    Grids g;
-    g.lds = elem_lds;
-    const int per_cu = std::max(1, std::min(8, (int)(160 * 1024 / (elem_lds + 1024))));
-    g.gm = (int)std::max<int64_t>(1, std::min<int64_t>(P.n_chunks, (int64_t)per_cu * device_cu_count()));
-    g.gf = P.n_shared > 0 ? (int)std::min<int64_t>((P.n_shared + kBlock - 1) / kBlock, 1024) : 0;
-    g.gu = (int)std::max<int64_t>(1, std::min<int64_t>((P.n_nodes + 4 * kBlock - 1) / (4 * kBlock), 1024));
-    return g;
-}
-
-// ------------------------------------------------------------ the driver ----
-namespace {
-
-struct Timer {
-    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
-    double s() const {
-        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    }
-};
-
-int read_state(SolveState *d_st, SolveState &h, hipStream_t s) {
-    FEM_HIP_CHECK(hipMemcpyAsync(&h, d_st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+int read_state(IterState *d_st, IterState &h, hipStream_t s) {
+    FEM_HIP_CHECK(hipMemcpyAsync(&h, d_st, sizeof(IterState), hipMemcpyDeviceToHost, s));
     FEM_HIP_CHECK(hipStreamSynchronize(s));
     return 0;
 }
@@ -270,8 +315,7 @@ struct EventPool {
         }
         return 0;
     }
-    // stream already synchronised
-    void harvest() {
+    void harvest() {  // stream already synchronised
         for (int i = 0; i < used; ++i) {
             float t = 0.f;
             if (hipEventElapsedTime(&t, a[i], b[i]) == hipSuccess) {
@@ -287,197 +331,159 @@ struct EventPool {
     }
 };
 
-}  // namespace
+// The solve for one (NB, EPT, matrix head kind, vector type).
+template <int NB, int EPT, int BS, int MK, class VT>
+int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, const double *b, double *x64, double rtol, int max_iter,
+           double delta, int max_outer, int check_every, int profile, fem_solve_info *info, hipStream_t s) {
+    const bool fold = std::is_same<VT, float>::value;  // FP32 vectors: x is an FP32 correction
+    const int64_t n = P.n_nodes;
+    VT *xv = fold ? reinterpret_cast<VT *>(w.xc) : reinterpret_cast<VT *>(x64);
+    VT *r = reinterpret_cast<VT *>(w.r), *p = reinterpret_cast<VT *>(w.p), *q = reinterpret_cast<VT *>(w.q);
+    const VT *dinv = reinterpret_cast<const VT *>(w.dinv);
+    VT *partv = reinterpret_cast<VT *>(w.partv);
+    const size_t lds = chunk_lds_bytes<NB, VT>(P.E);
+    const ChunkGrid cg = chunk_grid(P.n_chunks, lds, BS);
+    const int gf = P.n_shared > 0 ? fixup_grid(P.n_shared) : 0;
+    const int npart = cg.grid + gf;
+    const int gu = (int)std::max<int64_t>(1, std::min<int64_t>((n + 4 * kBlock - 1) / (4 * kBlock), 1024));
+    const int gv = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 4096));
+    LdPk<NB, MK> ld{w.Apk, P.n_elems};
+    OpIter<VT> op{xv, r, p, q, dinv, P.mask, w.st, w.dots, npart, cg.grid, 0, 0.0, 0.0, {0, 0, 0, 0, 0, 0, 0}};
 
-template <int NB, class T, class Ld>
-static int cg_loop(const DevPlan &P, const Ld &ld, SolverWork &w, T *x, T *r, T *p, T *q, const T *dinv,
-                   T *scratch, const double *b64, double *x64, const void *A64, int kind64, double rtol, double r0,
-                   double delta, int max_iter, int max_outer, int check_every, int profile, fem_solve_info *info,
-                   hipStream_t s, const Grids &gr) {
-    // x, r, p, q: iteration vectors (T).  For T = float, x is the FP32
-    // correction and x64 / b64 / A64 drive the FP64 refresh.
-    const bool mixed = !std::is_same<T, double>::value;
-    SolveState h{};
-    EventPool ev;
-    if (profile > 0) {
-        int rc = ev.ensure(check_every);
+    // refresh: true FP64 residual of x64 into r64 -> r, totals into the state
+    auto refresh = [&](int first) -> int {
+        if (fold) k_fold<<<gv, kBlock, 0, s>>>(n, x64, reinterpret_cast<float *>(w.xc));
+        int rc = launch_apply_pk64(P, pk_kind, w.Apk, x64, b, w.r64, -1.0, 1, w.part64, s);
         if (rc) return rc;
+        k_init_dots<VT><<<gu, kBlock, 0, s>>>(n, r, dinv, w.r64, w.upd);
+        k_refresh_state<<<1, kBlock, 0, s>>>(w.st, w.upd, gu, first);
+        FEM_HIP_CHECK(hipGetLastError());
+        return 0;
+    };
+
+    IterState h{};
+    int rc = refresh(1);
+    if (rc) return rc;
+    rc = read_state(w.st, h, s);
+    if (rc) return rc;
+    const double r0 = std::sqrt(h.rr64);
+    info->r0 = r0;
+    if (r0 == 0.0) {
+        info->relres = 0.0;
+        return FEM_OK;
     }
     const double thr2 = (rtol * r0) * (rtol * r0);
-    double rmax2 = r0 * r0;
-    int launched = 0, first = 1, replacements = 0, outer = 0, status = FEM_OK;
+    const double dd = delta > 0.0 ? delta * delta : 0.0;
+    double rel2 = dd * h.rr;
+    EventPool ev;
+    if (profile > 0 && (rc = ev.ensure(check_every))) return rc;
+    int launched = 0, refreshes = 0, status = FEM_OK;
     int64_t calls = 0;
     while (true) {
         const int m = std::min(check_every, max_iter - launched);
         for (int j = 0; j < m; ++j) {
-            OpPcg<T> op{r, dinv, p, q, P.mask, w.st, w.upd, gr.gu, w.mv, gr.gm, first, thr2,
-                        mixed ? delta * delta * rmax2 : 0.0, (T)0};
             const bool timed = profile > 0 && ((launched + j) % profile == 0) && ev.used < (int)ev.a.size();
             if (timed) FEM_HIP_CHECK(hipEventRecord(ev.a[ev.used], s));
-            k_chunk_main<NB, T, Ld, OpPcg<T>, false><<<gr.gm, kBlock, gr.lds, s>>>(P, ld, op, scratch);
-            if (P.n_shared > 0) k_chunk_fixup<T, OpPcg<T>><<<gr.gf, kBlock, 0, s>>>(P, op, scratch);
+            k_chunk_main<NB, EPT, BS, VT, decltype(ld), OpIter<VT>, false>
+                <<<cg.grid, BS, lds, s>>>(P, ld, op, partv, cg.xcd);
+            if (gf) k_chunk_fixup<kBlock, VT, OpIter<VT>><<<gf, kBlock, 0, s>>>(P, op, partv, cg.grid);
             if (timed) {
                 FEM_HIP_CHECK(hipEventRecord(ev.b[ev.used], s));
                 ev.used++;
             }
-            k_update<T><<<gr.gu, kBlock, 0, s>>>(P.n_nodes, x, r, p, q, dinv, w.st, w.mv, gr.gm + gr.gf, w.upd);
+            k_finalize<<<1, kBlock, 0, s>>>(w.st, w.dots, npart, thr2, rel2);
             FEM_HIP_CHECK(hipGetLastError());
-            first = 0;
             ++calls;
         }
         launched += m;
-        int rc = read_state(w.st, h, s);
-        if (rc) return rc;
+        if ((rc = read_state(w.st, h, s))) return rc;
         if (profile > 0) ev.harvest();
         if (h.flag == 2) {
             status = FEM_EBREAKDOWN;
             break;
         }
         if (h.flag == 1) {
-            // refresh: true residual in FP64
-            if (mixed) {
-                k_fold<<<gr.gu, kBlock, 0, s>>>(P.n_nodes, x64, reinterpret_cast<float *>(x));
-                FEM_HIP_CHECK(hipGetLastError());
-            }
-            double *rt = mixed ? w.r64 : reinterpret_cast<double *>(r);
-            rc = launch_apply64(P, kind64, A64, nullptr, 0.0, mixed ? x64 : reinterpret_cast<double *>(x), b64, rt,
-                                -1.0, 1, w.part64, s);
-            if (rc) return rc;
+            k_pending<VT><<<gv, kBlock, 0, s>>>(n, xv, r, p, q, w.st);
+            if ((rc = refresh(0))) return rc;
             ++calls;
-            k_init_dots<T><<<gr.gu, kBlock, 0, s>>>(P.n_nodes, r, dinv, mixed ? w.r64 : nullptr, w.upd);
-            k_reduce_state<<<1, kBlock, 0, s>>>(w.st, w.upd, gr.gu);
-            FEM_HIP_CHECK(hipGetLastError());
-            rc = read_state(w.st, h, s);
-            if (rc) return rc;
-            const double rtrue = std::sqrt(mixed ? h.rr64_init : h.rr_init);
-            ++outer;
-            if (rtrue <= rtol * r0) break;
-            if (!mixed && ++replacements > 3) {
+            if ((rc = read_state(w.st, h, s))) return rc;
+            ++refreshes;
+            if (std::sqrt(h.rr64) <= rtol * r0) break;
+            if (refreshes >= max_outer) {
                 status = FEM_ENOCONV;
                 break;
             }
-            if (mixed && outer >= max_outer) {
-                status = FEM_ENOCONV;
-                break;
-            }
-            rmax2 = h.rr_init;  // FP32 (or FP64) r.r of the refreshed residual
+            rel2 = dd * h.rr;
         }
         if (launched >= max_iter) {
             status = FEM_ENOCONV;
+            k_pending<VT><<<gv, kBlock, 0, s>>>(n, xv, r, p, q, w.st);
+            if ((rc = refresh(0))) return rc;
+            if ((rc = read_state(w.st, h, s))) return rc;
             break;
         }
     }
     info->iters = h.n_updates;
-    info->outer = mixed ? outer : 0;
-    info->replacements = mixed ? 0 : replacements;
+    info->outer = refreshes;
+    info->replacements = refreshes;
     info->matvec_calls = (int)calls;
     info->matvec_ms = ev.ms;
     info->matvec_samples = ev.samples;
+    info->relres = std::sqrt(h.rr64) / r0;
     return status;
 }
 
-int solve_pcg(const DevPlan &P, SolverWork &w, int dtype, const void *K, const void *M, double nu,
-              const double *b, double *x, double rtol, int max_iter, int jacobi, double delta, int max_outer,
-              int check_every, int profile, fem_solve_info *info, hipStream_t s) {
+}  // namespace
+
+int solve_pcg(const DevPlan &P, SolverWork &w, int dtype, int vec64, int block, const void *K, const void *M,
+              double nu, const double *b, double *x, double rtol, int max_iter, int jacobi, double delta,
+              int max_outer, int check_every, int profile, fem_solve_info *info, hipStream_t s) {
     const bool mixed = dtype != MAT_F64;
     const int64_t n = P.n_nodes;
     const int gv = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 4096));
-    // combined operator: FP64 (dtype F64) or hi/lo pair (mixed)
-    const int kout = mixed ? MAT_F32X2 : MAT_F64;
-    int rc = launch_combine(P, dtype, K, (nu != 0.0) ? M : nullptr, nu, kout, w.A, s);
+    const int pk_kind = mixed ? MAT_F32X2 : MAT_F64;
+    const void *Mu = (nu != 0.0) ? M : nullptr;
+    int rc = launch_pack(P, dtype, K, Mu, nu, pk_kind, w.Apk, s);
     if (rc) return rc;
-    // Jacobi diagonal of the combined operator (FP64), then D^{-1} (0 on nd)
-    rc = launch_diag64(P, kout, w.A, nullptr, 0.0, w.d64, w.part64, s);
+    rc = launch_diag64(P, dtype, K, Mu, nu, w.d64, w.part64, s);
     if (rc) return rc;
-    FEM_HIP_CHECK(hipMemsetAsync(w.bad, 0, sizeof(int), s));
-    k_clear_state<<<1, 1, 0, s>>>(w.st);
-    // x0 residual in FP64 from the full operator
-    rc = launch_apply64(P, kout, w.A, nullptr, 0.0, x, b, w.r64, -1.0, 1, w.part64, s);
-    if (rc) return rc;
-    if (!mixed) {
-        double *dinv = w.dinv64;
-        k_dinv<double><<<gv, kBlock, 0, s>>>(n, w.d64, P.mask, dinv, jacobi, w.bad);
-        FEM_HIP_CHECK(hipGetLastError());
-        const Grids gr = solver_grids(P, chunk_lds_bytes<3, double>(P.E) / 3 * P.nb);
-        k_init_dots<double><<<gr.gu, kBlock, 0, s>>>(n, w.r64, dinv, nullptr, w.upd);
-        k_reduce_state<<<1, kBlock, 0, s>>>(w.st, w.upd, gr.gu);
-        FEM_HIP_CHECK(hipGetLastError());
-        SolveState h{};
-        rc = read_state(w.st, h, s);
-        if (rc) return rc;
-        int bad = 0;
-        FEM_HIP_CHECK(hipMemcpy(&bad, w.bad, sizeof(int), hipMemcpyDeviceToHost));
-        if (bad) return set_error(FEM_ESINGULAR, "a free node has a non-positive diagonal entry");
-        const double r0 = std::sqrt(h.rr_init);
-        info->r0 = r0;
-        if (r0 == 0.0) {
-            info->relres = 0.0;
-            return FEM_OK;
-        }
-        int st;
-        if (P.nb == 3) {
-            LdKM<3, MAT_F64, double> ld{w.A, nullptr, 0.0, P.n_elems};
-            st = cg_loop<3, double>(P, ld, w, x, w.r64, w.p64, w.q64, dinv, w.part64, b, x, w.A, MAT_F64, rtol, r0,
-                                    0.0, max_iter, 0, check_every, profile, info, s, gr);
-        } else {
-            LdKM<4, MAT_F64, double> ld{w.A, nullptr, 0.0, P.n_elems};
-            st = cg_loop<4, double>(P, ld, w, x, w.r64, w.p64, w.q64, dinv, w.part64, b, x, w.A, MAT_F64, rtol, r0,
-                                    0.0, max_iter, 0, check_every, profile, info, s, gr);
-        }
-        if (st < 0 && st != FEM_ENOCONV && st != FEM_EBREAKDOWN) return st;
-        // final true residual (x is the FP64 solution)
-        rc = launch_apply64(P, MAT_F64, w.A, nullptr, 0.0, x, b, w.q64, -1.0, 1, w.part64, s);
-        if (rc) return rc;
-        k_init_dots<double><<<gr.gu, kBlock, 0, s>>>(n, w.q64, dinv, nullptr, w.upd);
-        k_reduce_state<<<1, kBlock, 0, s>>>(w.st, w.upd, gr.gu);
-        rc = read_state(w.st, h, s);
-        if (rc) return rc;
-        info->relres = std::sqrt(h.rr_init) / r0;
-        return st;
-    }
-    // ---- mixed precision ----
-    float *dinv = w.dinv32;
-    k_dinv<float><<<gv, kBlock, 0, s>>>(n, w.d64, P.mask, dinv, jacobi, w.bad);
-    k_fill<float><<<gv, kBlock, 0, s>>>(n, w.xc32, 0.0f);
-    FEM_HIP_CHECK(hipGetLastError());
-    const Grids gr = solver_grids(P, chunk_lds_bytes<3, float>(P.E) / 3 * P.nb);
-    k_init_dots<float><<<gr.gu, kBlock, 0, s>>>(n, w.r32, dinv, w.r64, w.upd);
-    k_reduce_state<<<1, kBlock, 0, s>>>(w.st, w.upd, gr.gu);
-    FEM_HIP_CHECK(hipGetLastError());
-    SolveState h{};
-    rc = read_state(w.st, h, s);
-    if (rc) return rc;
-    int bad = 0;
-    FEM_HIP_CHECK(hipMemcpy(&bad, w.bad, sizeof(int), hipMemcpyDeviceToHost));
-    if (bad) return set_error(FEM_ESINGULAR, "a free node has a non-positive diagonal entry");
-    const double r0 = std::sqrt(h.rr64_init);
-    info->r0 = r0;
-    if (r0 == 0.0) {
-        info->relres = 0.0;
-        return FEM_OK;
-    }
-    const float *Ahi = reinterpret_cast<const float *>(w.A);
-    int st;
-    if (P.nb == 3) {
-        LdF32<3> ld{Ahi, P.n_elems};
-        st = cg_loop<3, float>(P, ld, w, w.xc32, w.r32, w.p32, w.q32, dinv, w.part32, b, x, w.A, MAT_F32X2, rtol, r0,
-                               delta, max_iter, max_outer, check_every, profile, info, s, gr);
+    k_zero_int<<<1, 1, 0, s>>>(w.bad);
+    const bool v32 = mixed && !vec64;
+    if (v32) {
+        k_dinv<float><<<gv, kBlock, 0, s>>>(n, w.d64, P.mask, reinterpret_cast<float *>(w.dinv), jacobi, w.bad);
+        k_fill<float><<<gv, kBlock, 0, s>>>(n, reinterpret_cast<float *>(w.xc), 0.0f);
     } else {
-        LdF32<4> ld{Ahi, P.n_elems};
-        st = cg_loop<4, float>(P, ld, w, w.xc32, w.r32, w.p32, w.q32, dinv, w.part32, b, x, w.A, MAT_F32X2, rtol, r0,
-                               delta, max_iter, max_outer, check_every, profile, info, s, gr);
+        k_dinv<double><<<gv, kBlock, 0, s>>>(n, w.d64, P.mask, reinterpret_cast<double *>(w.dinv), jacobi, w.bad);
     }
-    if (st < 0 && st != FEM_ENOCONV && st != FEM_EBREAKDOWN) return st;
-    // fold any pending correction and measure the true FP64 residual
-    k_fold<<<gr.gu, kBlock, 0, s>>>(n, x, w.xc32);
-    rc = launch_apply64(P, MAT_F32X2, w.A, nullptr, 0.0, x, b, w.r64, -1.0, 1, w.part64, s);
-    if (rc) return rc;
-    k_init_dots<float><<<gr.gu, kBlock, 0, s>>>(n, w.r32, dinv, w.r64, w.upd);
-    k_reduce_state<<<1, kBlock, 0, s>>>(w.st, w.upd, gr.gu);
-    rc = read_state(w.st, h, s);
-    if (rc) return rc;
-    info->relres = std::sqrt(h.rr64_init) / r0;
-    return st;
+    FEM_HIP_CHECK(hipGetLastError());
+    int bad = 0;
+    FEM_HIP_CHECK(hipMemcpyAsync(&bad, w.bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    FEM_HIP_CHECK(hipStreamSynchronize(s));
+    if (bad) return set_error(FEM_ESINGULAR, "a free node has a non-positive diagonal entry");
+    // delta = 0 disables refreshes before the target (FP64 solver)
+    const double dl = mixed ? delta : 0.0;
+    const int outer_cap = mixed ? max_outer : 4;
+    return dispatch_tile(P.E, block, [&](auto bs, auto ept) -> int {
+        constexpr int BS = decltype(bs)::value;
+        constexpr int EPT = decltype(ept)::value;
+        if (P.nb == 3) {
+            if (!mixed) return cg_run<3, EPT, BS, MAT_F64, double>(P, w, pk_kind, b, x, rtol, max_iter, dl, outer_cap,
+                                                                  check_every, profile, info, s);
+            if (v32) return cg_run<3, EPT, BS, MAT_F32, float>(P, w, pk_kind, b, x, rtol, max_iter, dl, outer_cap,
+                                                              check_every, profile, info, s);
+            return cg_run<3, EPT, BS, MAT_F32, double>(P, w, pk_kind, b, x, rtol, max_iter, dl, outer_cap,
+                                                       check_every, profile, info, s);
+        }
+        if constexpr (EPT * BS <= 1536 || (EPT <= 2 && BS == 1024)) {
+            if (!mixed) return cg_run<4, EPT, BS, MAT_F64, double>(P, w, pk_kind, b, x, rtol, max_iter, dl, outer_cap,
+                                                                  check_every, profile, info, s);
+            if (v32) return cg_run<4, EPT, BS, MAT_F32, float>(P, w, pk_kind, b, x, rtol, max_iter, dl, outer_cap,
+                                                              check_every, profile, info, s);
+            return cg_run<4, EPT, BS, MAT_F32, double>(P, w, pk_kind, b, x, rtol, max_iter, dl, outer_cap,
+                                                       check_every, profile, info, s);
+        }
+        return set_error(FEM_EINVAL, "chunk size too large for tetrahedra");
+    });
 }
 
 }  // namespace fem

@@ -10,16 +10,23 @@
 
 namespace fem {
 
-// Written only by thread 0 of block 0 of the kernel that owns each field,
-// read by later kernels on the same stream.
-struct SolveState {
-    int flag;          // 0 running, 1 trigger (converged / reliable update), 2 breakdown
-    int n_updates;     // CG updates executed
-    double rz_cur;     // r.z of the current iteration (written by main)
-    double rz_prev;    // r.z of the previous iteration (written by update)
-    double beta, alpha;
-    double rr_trigger;
-    double rz_init, rr_init, rr64_init;  // totals of a fresh residual
+enum IterMode { MODE_CONTINUE = 0, MODE_FRESH = 1, MODE_FIRST = 2 };
+
+// Scalars of the CG recurrence.  Each field has exactly one writer kernel
+// (the single-block finalize / refresh kernels); the element kernels only read
+// it, after a kernel boundary on the same stream.
+struct IterState {
+    int flag;       // 0 running, 1 trigger (target or reliable update), 2 breakdown
+    int mode;       // IterMode of the next element pass
+    int pending;    // 1: alpha * (p, q) not yet applied to (x, r)
+    int n_updates;  // CG iterations completed (alpha known)
+    double alpha;   // step of the last completed iteration
+    double beta;    // p = z + beta p for the next element pass
+    double rz;      // r.z of the residual behind the current p (summed directly)
+    double rr;      // r.r of the same residual
+    double rz_next, rr_next;
+    double rr64;    // r.r of the FP64 residual at the last refresh
+    double pq;      // last p.q
 };
 
 struct Grids {
@@ -32,20 +39,27 @@ struct SolverWork {
     int kind = -1;
     void *arena = nullptr;
     size_t bytes = 0;
-    void *A = nullptr;             // combined local matrices: FP64 or FP32 hi/lo pair
-    double *d64 = nullptr, *dinv64 = nullptr, *r64 = nullptr, *p64 = nullptr, *q64 = nullptr;
-    float *dinv32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *xc32 = nullptr;
-    double *part64 = nullptr;
-    float *part32 = nullptr;
-    double *upd = nullptr, *mv = nullptr;
-    SolveState *st = nullptr;
+    void *Apk = nullptr;          // packed difference form: FP64 [np][ne] or FP32 pair [2][np][ne]
+    double *d64 = nullptr;        // diagonal of the operator
+    void *dinv = nullptr;         // D^{-1} (0 on Dirichlet nodes), vector type
+    void *r = nullptr, *p = nullptr, *q = nullptr, *xc = nullptr;  // iteration vectors
+    double *r64 = nullptr;        // FP64 residual of a refresh
+    double *part64 = nullptr;     // shared-node partials of FP64 passes
+    void *partv = nullptr;        // shared-node partials of iteration passes
+    double *dots = nullptr;       // [5][npart] per-block dot partials
+    double *upd = nullptr;        // [3][gu] init partials
+    IterState *st = nullptr;
     int *bad = nullptr;
 };
 
 Grids solver_grids(const DevPlan &P, size_t elem_lds);
 
-int solve_pcg(const DevPlan &P, SolverWork &w, int dtype, const void *K, const void *M, double nu,
-              const double *b, double *x, double rtol, int max_iter, int jacobi, double delta, int max_outer,
-              int check_every, int profile, fem_solve_info *info, hipStream_t s);
+int solve_pcg(const DevPlan &P, SolverWork &w, int dtype, int vec64, int block, const void *K, const void *M,
+              double nu, const double *b, double *x, double rtol, int max_iter, int jacobi, double delta,
+              int max_outer, int check_every, int profile, fem_solve_info *info, hipStream_t s);
+
+// Number of values of the packed symmetric difference form of one element:
+// n_b row sums followed by the n_b (n_b - 1) / 2 upper off-diagonal entries.
+__host__ __device__ constexpr int packed_count(int nb) { return nb + nb * (nb - 1) / 2; }
 
 }  // namespace fem

@@ -54,7 +54,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [
         ("dtype", ctypes.c_int), ("nu", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int),
         ("precond", ctypes.c_int), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int),
-        ("check_every", ctypes.c_int), ("profile", ctypes.c_int),
+        ("check_every", ctypes.c_int), ("profile", ctypes.c_int), ("vectors", ctypes.c_int),
+        ("block", ctypes.c_int),
     ]
 
 

@@ -23,7 +23,7 @@ def _meshes():
     return [
         ("tri_fig1_2elem", inputs.square_mesh(1, order="rowmajor"), 0),
         ("tri_17_jitter_E64", inputs.square_mesh(17, jitter=0.2, seed=3), 64),
-        ("tri_45_jitter_E320", inputs.square_mesh(45, jitter=0.2, seed=4), 320),
+        ("tri_45_jitter_E512", inputs.square_mesh(45, jitter=0.2, seed=4), 512),
         ("tri_64_default", inputs.square_mesh(64), 0),
         ("tri_33_rowmajor_E2048", inputs.square_mesh(33, order="rowmajor", jitter=0.1, seed=5), 2048),
         ("tet_5_jitter_E64", inputs.cube_mesh(5, jitter=0.15, seed=6), 64),

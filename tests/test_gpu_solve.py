@@ -91,8 +91,8 @@ def test_fp64_solve_3d_and_dirichlet_values():
     assert abs(info["iters"] - io["iters"]) <= max(1, 0.02 * io["iters"])
 
 
-@pytest.mark.parametrize("dim,dtype", [(2, 2), (3, 2), (2, 1)])
-def test_mixed_precision_reaches_fp64_target(dim, dtype):
+@pytest.mark.parametrize("dim,dtype,vectors", [(2, 2, 0), (3, 2, 0), (2, 1, 0), (2, 2, 1), (3, 2, 1)])
+def test_mixed_precision_reaches_fp64_target(dim, dtype, vectors):
     """FP32 inner CG with FP64 reliable updates: the oracle's FP64 residual of
     the GPU solution meets 1e-8 (for FP32X2 storage; plain FP32 storage solves
     the FP32-rounded operator, whose own solution is only ~1e-5 accurate, so
@@ -106,14 +106,16 @@ def test_mixed_precision_reaches_fp64_target(dim, dtype):
     plan = fem.Plan.from_mesh(mesh, prob.nd)
     K, M = _setup(prob, plan, dtype)
     x = cuda(_x0(prob))
-    info = fem.pcg_solve(plan, fem.solve_opts(dtype=dtype, nu=prob.nu, rtol=1e-8), K, M, cuda(prob.b), x)
+    info = fem.pcg_solve(plan, fem.solve_opts(dtype=dtype, nu=prob.nu, rtol=1e-8, vectors=vectors), K, M,
+                         cuda(prob.b), x)
     print(info)
     assert info["status"] == fem.FEM_OK
     assert info["relres"] <= 1e-8
     if dtype == fem.F32X2:
         assert _true_relres(prob, x.cpu().numpy(), _x0(prob)) <= 1.05e-8
     _, io = oracle.pcg(prob.n, mesh.elems, prob.K, prob.M, prob.nu, prob.b, prob.mask, _x0(prob), rtol=1e-8)
-    assert info["iters"] <= 2.0 * io["iters"]
+    # FP64 vectors keep the FP64 iteration count; FP32 vectors lose some
+    assert info["iters"] <= (1.1 if vectors == 0 else 1.6) * io["iters"]
 
 
 def test_solver_reports_noconv_and_keeps_iterate():
