@@ -78,7 +78,7 @@ typedef struct {
  *  d_conn         int32  [n_b][n_elems]   (read; not kept)
  *  d_dirichlet    int32  [n_dirichlet] node ids of the Dirichlet part nd
  *                 (duplicates allowed; may be NULL when n_dirichlet = 0)
- *  chunk_elems    elements per chunk, 0 = default (2048 for triangles, 1536
+ *  chunk_elems    elements per chunk, 0 = default (1024 for triangles, 1536
  *                 for tetrahedra); one of 64, 128, 256, 512, 1024, 1536 and,
  *                 for triangles only, 2048
  * The plan partitions the element list into chunks of consecutive elements;

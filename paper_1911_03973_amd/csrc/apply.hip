@@ -23,8 +23,8 @@ struct OpAffine {
     T sign;
     int use_mask;
     __device__ __forceinline__ bool begin() { return true; }
-    __device__ __forceinline__ T gather(int g, bool) const { return x[g]; }
-    __device__ __forceinline__ void gather_shared(int) {}
+    __device__ __forceinline__ T gather(int g, int) const { return x[g]; }
+    __device__ __forceinline__ void fixup_node(int, int g, T acc) const { finish(g, acc); }
     __device__ __forceinline__ void finish(int g, T acc) const {
         T v = (b ? b[g] : (T)0) + sign * acc;
         if (use_mask && mask[g]) v = (T)0;
@@ -116,9 +116,9 @@ bool valid_chunk_elems(int nb, int E) {
     return (size_t)nb * E * (8 + 2) <= (size_t)kMaxChunkLds;
 }
 
-int default_chunk_elems(int nb) { return nb == 3 ? 2048 : 1536; }
+int default_chunk_elems(int nb) { return nb == 3 ? 1024 : 1536; }
 
-int default_block(int nb, int E) { return E >= 1024 ? 512 : 256; }
+int default_block(int nb, int E) { return E > 1024 ? 512 : 256; }
 
 int launch_apply64(const DevPlan &P, int kind, const void *K, const void *M, double nu, const double *x,
                    const double *b, double *out, double sign, int use_mask, double *scratch, hipStream_t s) {

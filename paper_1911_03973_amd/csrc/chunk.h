@@ -17,7 +17,8 @@
 //           order (fixed); nodes of this chunk only are finished in place,
 //           shared nodes leave a partial                 == assembly C_e^T
 //   fix-up  one thread per shared node adds its partials in ascending chunk
-//           order.
+//           order.  Ops may keep the values of shared nodes in compact
+//           arrays indexed by the shared-node number (phase A passes it).
 //
 // Every sum has one fixed order: results are bitwise reproducible and no
 // floating-point atomics are used.  Chunks are dealt to workgroups so that
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(BS) void k_chunk_main(const DevPlan P, const Ld ld,
                 const int g = P.loc_nodes[nb0 + k];
                 const int s0 = k ? P.loc_end[nb0 + k - 1] : 0;
                 const int s1 = P.loc_end[nb0 + k];
-                const T v = op.gather(g, k < ncomp);
+                const T v = op.gather(g, k < ncomp ? -1 : P.part_owner[pbase + (k - ncomp)]);
                 for (int s = s0; s < s1; ++s) buf[sl[s]] = v;
             }
             __syncthreads();
@@ -283,12 +284,10 @@ __global__ __launch_bounds__(BS) void k_chunk_fixup(const DevPlan P, Op op, cons
     __shared__ RedBuf<BS> red;
     if (!op.begin()) return;
     for (int64_t s = (int64_t)blockIdx.x * BS + threadIdx.x; s < P.n_shared; s += (int64_t)gridDim.x * BS) {
-        const int g = P.fix_nodes[s];
         const int k0 = P.fix_off[s], k1 = P.fix_off[s + 1];
         T acc = (T)0;
         for (int k = k0; k < k1; ++k) acc += partial[P.fix_parts[k]];
-        op.gather_shared(g);
-        op.finish(g, acc);
+        op.fixup_node((int)s, P.fix_nodes[s], acc);
     }
     op.template end<BS>(red.v, slot_base + blockIdx.x);
 }

@@ -68,14 +68,20 @@ struct Step {
     }
 };
 
+// The element pass of one CG iteration.  Complete nodes (in one chunk only)
+// live in the full vectors; shared nodes live, during the iterations, in
+// compact arrays indexed by the shared-node number, so the fix-up streams
+// them contiguously instead of gathering scattered cache lines.  A Dirichlet
+// node is recognised by D^{-1} = 0.
 template <class VT>
 struct OpIter {
     VT *x, *r, *p, *q;
     const VT *dinv;
-    const uint8_t *mask;
+    VT *sx, *sr, *sp, *sq;
+    const VT *sd;
     const IterState *st;
     double *dots;  // [kDots][npart]
-    int npart, gm;
+    int npart;
     // per-thread
     int mode;
     double alpha, beta;
@@ -90,54 +96,73 @@ struct OpIter {
         for (int j = 0; j < kDots; ++j) d[j] = 0.0;
         return true;
     }
-
-    // new r, x, p of node g from the old values
-    __device__ __forceinline__ void advance(int g, VT &rn, VT &xn, VT &pn, bool &wr_rx) const {
-        const VT dv = dinv[g];
+    // new r, x, p from the old values; wr: r and x changed
+    __device__ __forceinline__ void advance(VT r0, VT q0, VT x0, VT p0, VT dv, VT &rn, VT &xn, VT &pn,
+                                            bool &wr) const {
         if (mode == MODE_CONTINUE) {
-            rn = Step<VT>::r_next(r[g], q[g], alpha);
-            xn = Step<VT>::x_next(x[g], p[g], alpha);
-            pn = Step<VT>::p_next(dv, rn, p[g], beta);
-            wr_rx = true;
+            rn = Step<VT>::r_next(r0, q0, alpha);
+            xn = Step<VT>::x_next(x0, p0, alpha);
+            pn = Step<VT>::p_next(dv, rn, p0, beta);
+            wr = true;
         } else {
-            rn = r[g];
-            xn = (VT)0;
-            pn = (mode == MODE_FIRST) ? (VT)((double)dv * (double)rn) : Step<VT>::p_next(dv, rn, p[g], beta);
-            wr_rx = false;
+            rn = r0;
+            xn = x0;
+            pn = (mode == MODE_FIRST) ? (VT)((double)dv * (double)rn) : Step<VT>::p_next(dv, rn, p0, beta);
+            wr = false;
         }
     }
-    __device__ __forceinline__ void own(int g, VT rn, VT xn, VT pn, bool wr) {
-        if (wr) {
-            r[g] = rn;
-            x[g] = xn;
-        }
-        p[g] = pn;
+    __device__ __forceinline__ void direct_dots(VT rn, VT dv) {
         const double rd = (double)rn;
-        d[5] += rd * (double)dinv[g] * rd;
+        d[5] += rd * (double)dv * rd;
         d[6] += rd * rd;
     }
-    __device__ __forceinline__ VT gather(int g, bool complete) {
-        VT rn, xn, pn;
-        bool wr;
-        advance(g, rn, xn, pn, wr);
-        if (complete) own(g, rn, xn, pn, wr);
-        return pn;
-    }
-    __device__ __forceinline__ void gather_shared(int g) {
-        VT rn, xn, pn;
-        bool wr;
-        advance(g, rn, xn, pn, wr);
-        own(g, rn, xn, pn, wr);
-    }
-    __device__ __forceinline__ void finish(int g, VT acc) {
-        const VT qv = mask[g] ? (VT)0 : acc;
-        q[g] = qv;
-        const double qd = (double)qv, pd = (double)p[g], rd = (double)r[g], dd = (double)dinv[g];
+    __device__ __forceinline__ void pq_dots(VT pn, VT rn, VT dv, VT qv) {
+        const double qd = (double)qv, pd = (double)pn, rd = (double)rn, dd = (double)dv;
         d[0] += pd * qd;
         d[1] += qd * dd * rd;
         d[2] += qd * dd * qd;
         d[3] += qd * rd;
         d[4] += qd * qd;
+    }
+    __device__ __forceinline__ VT gather(int g, int sidx) {
+        VT rn, xn, pn;
+        bool wr;
+        if (sidx < 0) {
+            const VT dv = dinv[g];
+            const bool cont = mode == MODE_CONTINUE;
+            advance(r[g], cont ? q[g] : (VT)0, cont ? x[g] : (VT)0, mode == MODE_FIRST ? (VT)0 : p[g], dv, rn, xn,
+                    pn, wr);
+            if (wr) {
+                r[g] = rn;
+                x[g] = xn;
+            }
+            p[g] = pn;
+            direct_dots(rn, dv);
+        } else {
+            advance(sr[sidx], sq[sidx], sx[sidx], sp[sidx], sd[sidx], rn, xn, pn, wr);
+        }
+        return pn;
+    }
+    __device__ __forceinline__ void finish(int g, VT acc) {
+        const VT dv = dinv[g];
+        const VT qv = (dv == (VT)0) ? (VT)0 : acc;
+        q[g] = qv;
+        pq_dots(p[g], r[g], dv, qv);
+    }
+    __device__ __forceinline__ void fixup_node(int s, int, VT acc) {
+        const VT dv = sd[s];
+        VT rn, xn, pn;
+        bool wr;
+        advance(sr[s], sq[s], sx[s], sp[s], dv, rn, xn, pn, wr);
+        if (wr) {
+            sr[s] = rn;
+            sx[s] = xn;
+        }
+        sp[s] = pn;
+        direct_dots(rn, dv);
+        const VT qv = (dv == (VT)0) ? (VT)0 : acc;
+        sq[s] = qv;
+        pq_dots(pn, rn, dv, qv);
     }
     template <int BS>
     __device__ void end(double *red, int slot) {
@@ -147,6 +172,28 @@ struct OpIter {
             for (int j = 0; j < kDots; ++j) dots[(int64_t)j * npart + slot] = d[j];
     }
 };
+
+// Shared-node values between the full vectors and the compact arrays.
+template <class VT>
+__global__ __launch_bounds__(kBlock) void k_shared_copy(int64_t n_shared, const int32_t *__restrict__ nodes, VT *x,
+                                                        VT *r, VT *p, VT *q, const VT *dinv, VT *sx, VT *sr, VT *sp,
+                                                        VT *sq, VT *sd, int to_compact) {
+    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n_shared; s += (int64_t)gridDim.x * kBlock) {
+        const int g = nodes[s];
+        if (to_compact) {
+            sx[s] = x[g];
+            sr[s] = r[g];
+            sp[s] = p[g];
+            sq[s] = q[g];
+            sd[s] = dinv[g];
+        } else {
+            x[g] = sx[s];
+            r[g] = sr[s];
+            p[g] = sp[s];
+            q[g] = sq[s];
+        }
+    }
+}
 
 // One workgroup: totals of the dot partials, then the scalar recurrence.
 __global__ __launch_bounds__(kBlock) void k_finalize(IterState *st, const double *__restrict__ dots, int npart,
@@ -348,15 +395,30 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, const double *b, double
     const int gu = (int)std::max<int64_t>(1, std::min<int64_t>((n + 4 * kBlock - 1) / (4 * kBlock), 1024));
     const int gv = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 4096));
     LdPk<NB, MK> ld{w.Apk, P.n_elems};
-    OpIter<VT> op{xv, r, p, q, dinv, P.mask, w.st, w.dots, npart, cg.grid, 0, 0.0, 0.0, {0, 0, 0, 0, 0, 0, 0}};
+    VT *sv = reinterpret_cast<VT *>(w.shared);
+    const int64_t ns = std::max<int64_t>(P.n_shared, 1);
+    VT *sx = sv, *sr = sv + ns, *sp = sv + 2 * ns, *sq = sv + 3 * ns, *sd = sv + 4 * ns;
+    OpIter<VT> op{xv, r, p, q, dinv, sx, sr, sp, sq, sd, w.st, w.dots, npart, 0, 0.0, 0.0, {0, 0, 0, 0, 0, 0, 0}};
+    const int gs = (int)std::max<int64_t>(1, std::min<int64_t>((P.n_shared + kBlock - 1) / kBlock, 4096));
+    auto shared_copy = [&](int to_compact) {
+        if (P.n_shared > 0)
+            k_shared_copy<VT><<<gs, kBlock, 0, s>>>(P.n_shared, P.fix_nodes, xv, r, p, q, dinv, sx, sr, sp, sq, sd,
+                                                    to_compact);
+    };
 
-    // refresh: true FP64 residual of x64 into r64 -> r, totals into the state
+    // refresh: finish the pending step, true FP64 residual of x64 into r64 ->
+    // r, totals into the state, shared-node values back to the compact arrays
     auto refresh = [&](int first) -> int {
+        if (!first) {
+            shared_copy(0);
+            k_pending<VT><<<gv, kBlock, 0, s>>>(n, xv, r, p, q, w.st);
+        }
         if (fold) k_fold<<<gv, kBlock, 0, s>>>(n, x64, reinterpret_cast<float *>(w.xc));
         int rc = launch_apply_pk64(P, pk_kind, w.Apk, x64, b, w.r64, -1.0, 1, w.part64, s);
         if (rc) return rc;
         k_init_dots<VT><<<gu, kBlock, 0, s>>>(n, r, dinv, w.r64, w.upd);
         k_refresh_state<<<1, kBlock, 0, s>>>(w.st, w.upd, gu, first);
+        shared_copy(1);
         FEM_HIP_CHECK(hipGetLastError());
         return 0;
     };
@@ -400,10 +462,10 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, const double *b, double
         if (profile > 0) ev.harvest();
         if (h.flag == 2) {
             status = FEM_EBREAKDOWN;
+            shared_copy(0);
             break;
         }
         if (h.flag == 1) {
-            k_pending<VT><<<gv, kBlock, 0, s>>>(n, xv, r, p, q, w.st);
             if ((rc = refresh(0))) return rc;
             ++calls;
             if ((rc = read_state(w.st, h, s))) return rc;
@@ -417,7 +479,6 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, const double *b, double
         }
         if (launched >= max_iter) {
             status = FEM_ENOCONV;
-            k_pending<VT><<<gv, kBlock, 0, s>>>(n, xv, r, p, q, w.st);
             if ((rc = refresh(0))) return rc;
             if ((rc = read_state(w.st, h, s))) return rc;
             break;

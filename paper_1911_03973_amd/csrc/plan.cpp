@@ -213,6 +213,9 @@ int build_host_plan(int dim, int64_t n_nodes, int64_t n_elems, const double *coo
             P.fix_parts[P.fix_off[s] + fill[s]++] = P.chunk_info[2 * c + 1] + (t - ncomp);
         }
     }
+    P.part_owner.assign(np, 0);
+    for (int64_t s = 0; s < P.n_shared; ++s)
+        for (int32_t k = P.fix_off[s]; k < P.fix_off[s + 1]; ++k) P.part_owner[P.fix_parts[k]] = (int32_t)s;
     return 0;
 }
 

@@ -20,6 +20,7 @@ struct HostPlan {
     std::vector<int32_t> fix_nodes;       // [n_shared] nodes in != 1 chunk (incl. isolated)
     std::vector<int32_t> fix_off;         // [n_shared+1]
     std::vector<int32_t> fix_parts;       // [n_partials]
+    std::vector<int32_t> part_owner;      // [n_partials] shared-node index of each partial slot
     std::vector<uint8_t> mask;            // [n_nodes] Dirichlet flags
 };
 
@@ -37,6 +38,7 @@ struct DevPlan {
     const int32_t *fix_nodes;
     const int32_t *fix_off;
     const int32_t *fix_parts;
+    const int32_t *part_owner;
     const uint8_t *mask;
 };
 

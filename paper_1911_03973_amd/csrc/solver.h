@@ -46,7 +46,8 @@ struct SolverWork {
     double *r64 = nullptr;        // FP64 residual of a refresh
     double *part64 = nullptr;     // shared-node partials of FP64 passes
     void *partv = nullptr;        // shared-node partials of iteration passes
-    double *dots = nullptr;       // [5][npart] per-block dot partials
+    double *dots = nullptr;       // [8][npart] per-block dot partials
+    void *shared = nullptr;       // compact shared-node x, r, p, q, D^{-1}: [5][n_shared] vector type
     double *upd = nullptr;        // [3][gu] init partials
     IterState *st = nullptr;
     int *bad = nullptr;
