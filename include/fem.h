@@ -200,6 +200,68 @@ int fem_pcg_solve(const fem_plan *plan, const fem_solve_opts *opts, const void *
                   const void *d_M_e, const double *d_b, double *d_x, fem_solve_info *info,
                   void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Batches of independent problems solved in one persistent launch.           */
+/* ------------------------------------------------------------------------ */
+typedef struct fem_batch fem_batch; /* opaque */
+
+/* Plan for n_problems independent meshes given back to back:
+ *  node_off, elem_off, dir_off  host int64 [n_problems + 1] prefix offsets
+ *  d_coords     double [dim][node_off[P]] (union of all problems, SoA)
+ *  d_conn       int32  [n_b][elem_off[P]], node ids LOCAL to each problem
+ *  d_dirichlet  int32  [dir_off[P]], node ids local to each problem
+ * Every problem is validated and chunked as by fem_plan_create (no chunk
+ * holds elements of two problems).  The union of the problems is itself a
+ * mesh: the union-level calls below act on all problems at once. */
+int fem_batch_create(int dim, int n_problems, const int64_t *node_off, const int64_t *elem_off,
+                     const int64_t *dir_off, const double *d_coords, const int32_t *d_conn,
+                     const int32_t *d_dirichlet, int chunk_elems, void *stream, fem_batch **out);
+int fem_batch_destroy(fem_batch *batch);
+int fem_batch_get_stats(const fem_batch *batch, fem_plan_stats *out);
+
+/* Union-level operations, same layouts and semantics as the single-plan calls
+ * (element arrays over elem_off[P] elements, vectors over node_off[P] nodes). */
+int fem_batch_build_local_matrices(const fem_batch *batch, int dtype, void *d_K_e, void *d_M_e,
+                                   void *stream);
+int fem_batch_assemble_rhs(const fem_batch *batch, int dtype, const void *d_M_e, const double *d_f,
+                           double *d_b, void *stream);
+
+typedef struct {
+    int dtype;               /* storage of K_e / M_e (FEM_F64, FEM_F32, FEM_F32X2) */
+    double rtol;             /* per problem: ||b - A x|| <= rtol ||b - A x0|| */
+    int max_iter;            /* per-problem cap on CG iterations */
+    double refresh;          /* FP64 residual refresh when r.r fell by refresh^2 */
+    int max_refresh;         /* per-problem cap on refreshes */
+    int block;               /* workgroup size 256/512/1024, 0 = default */
+    int grid;                /* persistent workgroups, 0 = fill the GPU */
+    double watchdog_seconds; /* abort if the work queue stays empty this long */
+    int use_graph;           /* 1: capture the solve in a HIP graph and replay it */
+    int group;               /* chunks per work item, 0 = per-problem schedule */
+    int items_per_phase;     /* per-problem schedule: target work items per
+                                phase (a problem of n chunks takes
+                                ceil(n / items_per_phase) chunks per item) */
+} fem_batch_opts;
+
+typedef struct {
+    int status;              /* fem_status of this problem */
+    int iters, refreshes;
+    double relres;           /* true FP64 relative residual */
+    double r0;
+} fem_batch_result;
+
+void fem_batch_opts_default(fem_batch_opts *o);
+
+/* Solves every problem p: (K + nu[p] M) u = b with its Dirichlet rows masked,
+ * x holding x0 (Dirichlet values) on entry and the solutions on exit; all
+ * problems in one persistent kernel launch (work queue of (problem, chunk)
+ * items, per-problem phase counters), optionally replayed from a captured
+ * HIP graph.  h_nu: host double [P]; results: host [P]; *seconds: wall time.
+ * Returns FEM_OK when every problem converged, else the first failing
+ * problem's status (FEM_EHIP if the watchdog aborted the launch). */
+int fem_batch_solve(fem_batch *batch, const fem_batch_opts *opts, const void *d_K_e, const void *d_M_e,
+                    const double *h_nu, const double *d_b, double *d_x, fem_batch_result *results,
+                    double *seconds, void *stream);
+
 /* Thread-local message describing the last failure ("" if none). */
 const char *fem_last_error(void);
 

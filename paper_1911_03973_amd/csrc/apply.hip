@@ -144,6 +144,24 @@ int launch_apply_pk64(const DevPlan &P, int kind, const void *A, const double *x
     return apply_pk64_nb<4, MAT_F32X2>(P, A, x, b, out, sign, use_mask, scratch, s);
 }
 
+int launch_diag_pk64(const DevPlan &P, int kind, const void *A, double *d, double *scratch, hipStream_t s) {
+    OpAffine<double> op{nullptr, nullptr, d, P.mask, 1.0, 0};
+    if (P.nb == 3) {
+        if (kind == MAT_F64) {
+            LdPk<3, MAT_F64> ld{A, P.n_elems};
+            return run_chunked<3, double, decltype(ld), decltype(op), true>(P, ld, op, scratch, s);
+        }
+        LdPk<3, MAT_F32X2> ld{A, P.n_elems};
+        return run_chunked<3, double, decltype(ld), decltype(op), true>(P, ld, op, scratch, s);
+    }
+    if (kind == MAT_F64) {
+        LdPk<4, MAT_F64> ld{A, P.n_elems};
+        return run_chunked<4, double, decltype(ld), decltype(op), true>(P, ld, op, scratch, s);
+    }
+    LdPk<4, MAT_F32X2> ld{A, P.n_elems};
+    return run_chunked<4, double, decltype(ld), decltype(op), true>(P, ld, op, scratch, s);
+}
+
 int launch_apply32(const DevPlan &P, const float *A, const float *x, const float *b, float *out, float sign,
                    int use_mask, float *scratch, hipStream_t s) {
     OpAffine<float> op{x, b, out, P.mask, sign, use_mask};

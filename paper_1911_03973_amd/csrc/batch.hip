@@ -1,0 +1,598 @@
+// batch.hip -- many independent problems solved by one persistent kernel.
+//
+// Every problem keeps its own Jacobi-PCG (FP32 operator heads, FP64 vectors,
+// FP64 reliable refreshes; the scheme of pcg.hip).  All problems share one
+// launch: its workgroups take work items from a device queue,
+//   CHUNK(p, j)  the element pass of chunk j of problem p,
+//   FIX(p, j)    the shared-node fix-up of segment j of problem p,
+//   FIN(p)       the scalar step of problem p,
+// and each problem alternates between iteration rounds (element pass with
+// the CG updates) and refresh rounds (pending step + FP64 residual b - A x).
+// Per problem, an integer counter counts the finished items of the current
+// phase; the workgroup that finishes the last one enqueues the next phase.
+// Nothing ever waits for another workgroup: a workgroup only waits for the
+// queue to hold an item, so the launch needs no co-residency, and it ends
+// when every problem is finished.  A wall-clock watchdog bounds every wait,
+// so a logic error ends the launch with an abort flag instead of a hang.
+//
+// Memory ordering: producers release (agent-scope fence) before they count or
+// publish an item; the counter's last arriver and every consumer acquire
+// after reading it.  All floating-point sums keep a fixed order (per-chunk and
+// per-segment partials summed in index order by FIN), so the result does not
+// depend on which workgroup ran which item.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "chunk.h"
+#include "kernels.h"
+#include "solver.h"
+
+namespace fem {
+
+namespace {
+
+constexpr int kSeg = 1024;      // shared nodes per fix-up item
+constexpr int kBDots = 7;
+enum ItemType : unsigned long long { IT_CHUNK = 1, IT_FIX = 2, IT_FIN = 3 };
+
+__device__ __forceinline__ unsigned long long make_item(unsigned long long t, int p, int j) {
+    return (t << 56) | ((unsigned long long)(unsigned)p << 28) | (unsigned long long)(unsigned)j;
+}
+
+struct BatchArgs {
+    DevPlan P;
+    const void *A;  // packed pair [2][NP][n_elems]: heads for iterations, hi + lo for refreshes
+    double *x, *r, *p, *q;
+    const double *dinv, *b;
+    double *sx, *sr, *sp, *sq, *sd;  // compact shared-node values [n_shared]
+    double *part;                    // shared-node partials [n_partials]
+    const int32_t *pchunk0, *pshared0, *pseg0;  // [P+1]
+    const int32_t *pgroup;                      // [P] chunks per CHUNK item
+    int nprob;
+    BatchProblem *prob;
+    int *cnt;        // [P] finished items of the current phase
+    double *cdots;   // [n_chunks][kBDots]
+    double *sdots;   // [n_segments][kBDots]
+    unsigned long long *qitems, *qtags, *qhead, *qtail;
+    unsigned long long qmask;
+    int *ndone, *abort_flag;
+    double rtol, delta;
+    int max_iter, max_refresh;
+    long long spin_ticks;  // watchdog, in 100 MHz ticks
+};
+
+__device__ __forceinline__ long long now_ticks() { return (long long)__builtin_amdgcn_s_memrealtime(); }
+
+__device__ __forceinline__ unsigned long long ld_acq(unsigned long long *a) {
+    return __hip_atomic_load(a, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_acq_i(int *a) {
+    return __hip_atomic_load(a, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Whole workgroup: append items (type, p, 0..n-1) to the queue.  The items
+// are written by all threads; after a barrier one thread releases them and
+// publishes their tags.
+template <int BS>
+__device__ void enqueue(const BatchArgs &a, unsigned long long type, int p, int n, unsigned long long *s_base) {
+    if (threadIdx.x == 0) *s_base = atomicAdd(a.qtail, (unsigned long long)n);
+    __syncthreads();
+    const unsigned long long base = *s_base;
+    for (int i = threadIdx.x; i < n; i += BS)
+        __hip_atomic_store(&a.qitems[(base + i) & a.qmask], make_item(type, p, i), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        for (int i = 0; i < n; ++i)
+            __hip_atomic_store(&a.qtags[(base + i) & a.qmask], base + i + 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+}
+
+// Whole workgroup, after an item of problem p's current phase is done:
+// returns true in every thread of the workgroup that finished the phase.
+template <int BS>
+__device__ bool phase_done(const BatchArgs &a, int p, int n_items, int *s_last) {
+    __syncthreads();  // every store of the workgroup has completed
+    if (threadIdx.x == 0) {
+        __threadfence();  // release them at agent scope
+        const int old = atomicAdd(&a.cnt[p], 1);
+        int last = old == n_items - 1;
+        if (last) {
+            __threadfence();  // acquire the other workgroups' stores
+            __hip_atomic_store(&a.cnt[p], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        *s_last = last;
+    }
+    __syncthreads();
+    return *s_last != 0;
+}
+
+// ---- element-pass policies ------------------------------------------------
+struct BOpIter {  // iteration round (see OpIter in pcg.hip)
+    double *x, *r, *p, *q;
+    const double *dinv;
+    double *sx, *sr, *sp, *sq;
+    const double *sd;
+    int mode;
+    double alpha, beta;
+    double d[kBDots];
+    __device__ __forceinline__ void advance(double r0, double q0, double x0, double p0, double dv, double &rn,
+                                            double &xn, double &pn, bool &wr) const {
+        if (mode == MODE_CONTINUE) {
+            rn = __builtin_fma(-alpha, q0, r0);
+            xn = __builtin_fma(alpha, p0, x0);
+            pn = __builtin_fma(beta, p0, dv * rn);
+            wr = true;
+        } else {
+            rn = r0;
+            xn = x0;
+            pn = (mode == MODE_FIRST) ? dv * rn : __builtin_fma(beta, p0, dv * rn);
+            wr = false;
+        }
+    }
+    __device__ __forceinline__ void direct(double rn, double dv) {
+        d[5] += rn * dv * rn;
+        d[6] += rn * rn;
+    }
+    __device__ __forceinline__ void pqd(double pn, double rn, double dv, double qv) {
+        d[0] += pn * qv;
+        d[1] += qv * dv * rn;
+        d[2] += qv * dv * qv;
+        d[3] += qv * rn;
+        d[4] += qv * qv;
+    }
+    __device__ __forceinline__ double gather(int g, int sidx) {
+        double rn, xn, pn;
+        bool wr;
+        if (sidx < 0) {
+            const double dv = dinv[g];
+            const bool cont = mode == MODE_CONTINUE;
+            advance(r[g], cont ? q[g] : 0.0, cont ? x[g] : 0.0, mode == MODE_FIRST ? 0.0 : p[g], dv, rn, xn, pn, wr);
+            if (wr) {
+                r[g] = rn;
+                x[g] = xn;
+            }
+            p[g] = pn;
+            direct(rn, dv);
+        } else {
+            advance(sr[sidx], sq[sidx], sx[sidx], mode == MODE_FIRST ? 0.0 : sp[sidx], sd[sidx], rn, xn, pn, wr);
+        }
+        return pn;
+    }
+    __device__ __forceinline__ void finish(int g, double acc) {
+        const double dv = dinv[g];
+        const double qv = dv == 0.0 ? 0.0 : acc;
+        q[g] = qv;
+        pqd(p[g], r[g], dv, qv);
+    }
+    __device__ __forceinline__ void fixup_node(int s, int, double acc) {
+        const double dv = sd[s];
+        double rn, xn, pn;
+        bool wr;
+        advance(sr[s], sq[s], sx[s], mode == MODE_FIRST ? 0.0 : sp[s], dv, rn, xn, pn, wr);
+        if (wr) {
+            sr[s] = rn;
+            sx[s] = xn;
+        }
+        sp[s] = pn;
+        direct(rn, dv);
+        const double qv = dv == 0.0 ? 0.0 : acc;
+        sq[s] = qv;
+        pqd(pn, rn, dv, qv);
+    }
+};
+
+struct BOpRefresh {  // refresh round: pending step on x, then r = b - A x
+    double *x, *r;
+    const double *p, *dinv, *b;
+    double *sx, *sr;
+    const double *sp, *sd;
+    const int32_t *fix_nodes;
+    double alpha;  // 0 when nothing is pending
+    double d[kBDots];
+    __device__ __forceinline__ double gather(int g, int sidx) {
+        if (sidx < 0) {
+            const double xn = alpha != 0.0 ? __builtin_fma(alpha, p[g], x[g]) : x[g];
+            if (alpha != 0.0) x[g] = xn;
+            return xn;
+        }
+        return alpha != 0.0 ? __builtin_fma(alpha, sp[sidx], sx[sidx]) : sx[sidx];
+    }
+    __device__ __forceinline__ void finish(int g, double acc) {
+        const double dv = dinv[g];
+        const double rv = dv == 0.0 ? 0.0 : b[g] - acc;
+        r[g] = rv;
+        d[5] += rv * dv * rv;
+        d[6] += rv * rv;
+    }
+    __device__ __forceinline__ void fixup_node(int s, int g, double acc) {
+        const double dv = sd[s];
+        if (alpha != 0.0) sx[s] = __builtin_fma(alpha, sp[s], sx[s]);
+        const double rv = dv == 0.0 ? 0.0 : b[g] - acc;
+        sr[s] = rv;
+        d[5] += rv * dv * rv;
+        d[6] += rv * rv;
+    }
+};
+
+template <int BS>
+__device__ void store_dots(double (&d)[kBDots], double *red, double *dst) {
+    block_sum_n<BS, kBDots>(d, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < kBDots; ++j) dst[j] = d[j];
+}
+
+// ---- the persistent kernel -------------------------------------------------
+template <int NB, int EPT, int BS>
+__global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *buf = reinterpret_cast<double *>(smem);
+    uint16_t *sl = reinterpret_cast<uint16_t *>(smem + (size_t)NB * a.P.E * sizeof(double));
+    __shared__ RedBuf<BS> red;
+    __shared__ unsigned long long s_item, s_base;
+    __shared__ int s_exit, s_last;
+    __shared__ double s_sc[8];
+    const DevPlan &P = a.P;
+    while (true) {
+        if (threadIdx.x == 0) {
+            const unsigned long long idx = atomicAdd(a.qhead, 1ull);
+            const long long t0 = now_ticks();
+            int ex = 0;
+            unsigned long long item = 0;
+            // second bound, independent of the clock: about 2^28 sleeps of
+            // ~60 ns each
+            for (unsigned spins = 0;; ++spins) {
+                if (__hip_atomic_load(&a.qtags[idx & a.qmask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                    idx + 1) {
+                    __threadfence();  // acquire the item and everything released before it
+                    item = __hip_atomic_load(&a.qitems[idx & a.qmask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                if ((spins & 63) == 63 && (ld_acq_i(a.ndone) >= a.nprob || ld_acq_i(a.abort_flag))) {
+                    ex = 1;
+                    break;
+                }
+                if (now_ticks() - t0 > a.spin_ticks || spins > (1u << 28)) {
+                    __hip_atomic_store(a.abort_flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    ex = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            s_item = item;
+            s_exit = ex;
+        }
+        __syncthreads();
+        if (s_exit) break;
+        const unsigned long long item = s_item;
+        const int type = (int)(item >> 56);
+        const int p = (int)((item >> 28) & 0xFFFFFFFull);
+        const int j = (int)(item & 0xFFFFFFFull);
+        BatchProblem *pr = a.prob + p;
+        const int c0 = a.pchunk0[p], nch = a.pchunk0[p + 1] - c0;
+        const int grp = a.pgroup[p];  // chunks per CHUNK item of this problem
+        const int nci = (nch + grp - 1) / grp;
+        const int sh0 = a.pshared0[p], nsh = a.pshared0[p + 1] - sh0;
+        const int sg0 = a.pseg0[p], nseg = a.pseg0[p + 1] - sg0;
+        const int round = pr->round;
+        if (type == IT_CHUNK || type == IT_FIX) {
+            double d[kBDots];
+            if (round == 0) {
+                BOpIter op{a.x, a.r, a.p, a.q, a.dinv, a.sx, a.sr, a.sp, a.sq, a.sd, pr->mode, pr->alpha, pr->beta,
+                           {0, 0, 0, 0, 0, 0, 0}};
+                if (type == IT_CHUNK) {
+                    LdPk<NB, MAT_F32> ld{a.A, P.n_elems};
+                    const int cj1 = min(nch, (j + 1) * grp);
+                    for (int cj = j * grp; cj < cj1; ++cj) {
+#pragma unroll
+                        for (int t = 0; t < kBDots; ++t) op.d[t] = 0.0;
+                        __syncthreads();
+                        chunk_pass<NB, EPT, BS, double, LdPk<NB, MAT_F32>, BOpIter, false>(P, ld, op, a.part, c0 + cj,
+                                                                                          buf, sl);
+                        store_dots<BS>(op.d, red.v, a.cdots + (int64_t)(c0 + cj) * kBDots);
+                    }
+                } else {
+                    const int s1 = min(nsh, (j + 1) * kSeg);
+                    for (int s = j * kSeg + threadIdx.x; s < s1; s += BS) {
+                        const int sg = sh0 + s;
+                        double acc = 0.0;
+                        for (int k = P.fix_off[sg]; k < P.fix_off[sg + 1]; ++k) acc += a.part[P.fix_parts[k]];
+                        op.fixup_node(sg, P.fix_nodes[sg], acc);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < kBDots; ++t) d[t] = op.d[t];
+            } else {
+                BOpRefresh op{a.x, a.r, a.p, a.dinv, a.b, a.sx, a.sr, a.sp, a.sd, P.fix_nodes,
+                              pr->pending ? pr->alpha : 0.0, {0, 0, 0, 0, 0, 0, 0}};
+                if (type == IT_CHUNK) {
+                    LdPk<NB, MAT_F32X2> ld{a.A, P.n_elems};
+                    const int cj1 = min(nch, (j + 1) * grp);
+                    for (int cj = j * grp; cj < cj1; ++cj) {
+#pragma unroll
+                        for (int t = 0; t < kBDots; ++t) op.d[t] = 0.0;
+                        __syncthreads();
+                        chunk_pass<NB, EPT, BS, double, LdPk<NB, MAT_F32X2>, BOpRefresh, false>(P, ld, op, a.part,
+                                                                                               c0 + cj, buf, sl);
+                        store_dots<BS>(op.d, red.v, a.cdots + (int64_t)(c0 + cj) * kBDots);
+                    }
+                } else {
+                    const int s1 = min(nsh, (j + 1) * kSeg);
+                    for (int s = j * kSeg + threadIdx.x; s < s1; s += BS) {
+                        const int sg = sh0 + s;
+                        double acc = 0.0;
+                        for (int k = P.fix_off[sg]; k < P.fix_off[sg + 1]; ++k) acc += a.part[P.fix_parts[k]];
+                        op.fixup_node(sg, P.fix_nodes[sg], acc);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < kBDots; ++t) d[t] = op.d[t];
+            }
+            if (type == IT_FIX) store_dots<BS>(d, red.v, a.sdots + (int64_t)(sg0 + j) * kBDots);
+            const int n_items = type == IT_CHUNK ? nci : nseg;
+            if (phase_done<BS>(a, p, n_items, &s_last)) {
+                if (type == IT_CHUNK && nseg > 0) enqueue<BS>(a, IT_FIX, p, nseg, &s_base);
+                else enqueue<BS>(a, IT_FIN, p, 1, &s_base);
+            }
+        } else {
+            // FIN: sum the partials of p in a fixed order, advance its scalars
+            double t[kBDots];
+#pragma unroll
+            for (int k = 0; k < kBDots; ++k) t[k] = 0.0;
+            for (int c = threadIdx.x; c < nch; c += BS)
+#pragma unroll
+                for (int k = 0; k < kBDots; ++k) t[k] += a.cdots[(int64_t)(c0 + c) * kBDots + k];
+            for (int sgi = threadIdx.x; sgi < nseg; sgi += BS)
+#pragma unroll
+                for (int k = 0; k < kBDots; ++k) t[k] += a.sdots[(int64_t)(sg0 + sgi) * kBDots + k];
+            block_sum_n<BS, kBDots>(t, red.v);
+            if (threadIdx.x == 0) {
+                int next = 0;  // 0 done, 1 iterate, 2 refresh
+                const double rz = t[5], rr = t[6];
+                if (round == 1) {
+                    pr->refreshes += pr->first ? 0 : 1;
+                    if (pr->first) {
+                        pr->r0 = sqrt(rr);
+                        pr->thr2 = (a.rtol * pr->r0) * (a.rtol * pr->r0);
+                    }
+                    pr->rr_true = rr;
+                    if (pr->broken) {
+                        pr->status = FEM_EBREAKDOWN;
+                    } else if (!(pr->r0 > 0.0) || rr <= pr->thr2) {
+                        pr->status = 0;
+                    } else if (pr->iters >= a.max_iter || pr->refreshes > a.max_refresh || !isfinite(rr)) {
+                        pr->status = FEM_ENOCONV;
+                    } else {
+                        pr->beta = pr->first ? 0.0 : rz / pr->rz;
+                        pr->mode = pr->first ? MODE_FIRST : MODE_FRESH;
+                        pr->rel2 = a.delta * a.delta * rr;
+                        pr->first = 0;
+                        pr->pending = 0;
+                        pr->round = 0;
+                        next = 1;
+                    }
+                } else {
+                    const double pq = t[0], qDr = t[1], qDq = t[2], qr = t[3], qq = t[4];
+                    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rz)) {
+                        pr->broken = 1;
+                        pr->pending = 0;
+                        pr->round = 1;
+                        next = 2;  // one refresh round writes back a consistent x, then stops
+                    } else {
+                        const double alpha = rz / pq;
+                        const double rzn = rz - alpha * (2.0 * qDr - alpha * qDq);
+                        const double rrn = rr - alpha * (2.0 * qr - alpha * qq);
+                        pr->alpha = alpha;
+                        pr->rz = rz;
+                        pr->pending = 1;
+                        pr->iters += 1;
+                        if (!(rrn > pr->thr2) || rrn < pr->rel2 || !(rzn > 0.0) || pr->iters >= a.max_iter) {
+                            pr->round = 1;
+                            next = 2;
+                        } else {
+                            pr->beta = rzn / rz;
+                            pr->mode = MODE_CONTINUE;
+                            next = 1;
+                        }
+                    }
+                }
+                s_sc[0] = (double)next;
+            }
+            __syncthreads();
+            const int next = (int)s_sc[0];
+            if (next == 0) {
+                if (threadIdx.x == 0) {
+                    pr->flag = 1;
+                    __threadfence();
+                    atomicAdd(a.ndone, 1);
+                }
+            } else {
+                enqueue<BS>(a, IT_CHUNK, p, nci, &s_base);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---- setup kernels -----------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_batch_init(BatchArgs a, int64_t n_items) {
+    const int64_t tid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = tid; i <= a.qmask; i += stride) a.qtags[i] = 0;
+    for (int p = (int)tid; p < a.nprob; p += (int)stride) {
+        BatchProblem z{};
+        z.round = 1;
+        z.first = 1;
+        z.status = FEM_ENOCONV;
+        a.prob[p] = z;
+        a.cnt[p] = 0;
+    }
+    if (tid == 0) {
+        *a.qhead = 0;
+        *a.qtail = (unsigned long long)n_items;
+        *a.ndone = 0;
+        *a.abort_flag = 0;
+    }
+}
+
+// Initial items: the first (refresh) round of every problem, in problem
+// order; item k of the seed is group j of problem p with pitem0[p] + j = k.
+__global__ __launch_bounds__(kBlock) void k_batch_seed(BatchArgs a, const int32_t *__restrict__ pitem0,
+                                                       int64_t n_items) {
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < n_items; c += (int64_t)gridDim.x * kBlock) {
+        int lo = 0, hi = a.nprob;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) / 2;
+            if (pitem0[mid] <= c) lo = mid;
+            else hi = mid;
+        }
+        a.qitems[c & a.qmask] = make_item(IT_CHUNK, lo, (int)(c - pitem0[lo]));
+        a.qtags[c & a.qmask] = (unsigned long long)c + 1;
+    }
+}
+
+// A problem with no element at all finishes at once (no item would start it).
+__global__ void k_batch_empty(BatchArgs a) {
+    for (int p = threadIdx.x; p < a.nprob; p += blockDim.x)
+        if (a.pchunk0[p + 1] == a.pchunk0[p]) {
+            a.prob[p].flag = 1;
+            a.prob[p].status = 0;
+            atomicAdd(a.ndone, 1);
+        }
+}
+
+// Packed pair of A_e = K_e + nu_p M_e with the problem's own nu.
+template <int NB, int KIN>
+__global__ __launch_bounds__(kBlock) void k_pack_batch(const void *__restrict__ K, const void *__restrict__ M,
+                                                       const double *__restrict__ nu, const int64_t *__restrict__ elem0,
+                                                       int nprob, int64_t n_elems, float *__restrict__ A) {
+    constexpr int NP = NB + NB * (NB - 1) / 2;
+    const int64_t blk_in = (int64_t)NB * NB * n_elems;
+    const int64_t blk_out = (int64_t)NP * n_elems;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n_elems; e += (int64_t)gridDim.x * kBlock) {
+        int lo = 0, hi = nprob;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) / 2;
+            if (elem0[mid] <= e) lo = mid;
+            else hi = mid;
+        }
+        const double v = nu[lo];
+        double a[NB][NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) {
+                const int64_t idx = (int64_t)(i * NB + jj) * n_elems + e;
+                a[i][jj] = load_entry<KIN>(K, idx, blk_in) + v * load_entry<KIN>(M, idx, blk_in);
+            }
+        auto put = [&](int k, double val) {
+            const float hi32 = (float)val;
+            A[(int64_t)k * n_elems + e] = hi32;
+            A[blk_out + (int64_t)k * n_elems + e] = (float)(val - (double)hi32);
+        };
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            double rho = a[i][i];
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj)
+                if (jj != i) rho += 0.5 * (a[i][jj] + a[jj][i]);
+            put(i, rho);
+        }
+        int k = NB;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int jj = i + 1; jj < NB; ++jj) put(k++, 0.5 * (a[i][jj] + a[jj][i]));
+    }
+}
+
+}  // namespace
+
+int batch_pack(const DevPlan &P, int kin, const void *K, const void *M, const double *d_nu, const int64_t *d_elem0,
+               int nprob, float *A, hipStream_t s) {
+    const int g = (int)std::max<int64_t>(1, std::min<int64_t>((P.n_elems + kBlock - 1) / kBlock, 65536));
+#define FEM_PB(NB, KI) k_pack_batch<NB, KI><<<g, kBlock, 0, s>>>(K, M, d_nu, d_elem0, nprob, P.n_elems, A)
+    if (P.nb == 3) {
+        if (kin == MAT_F64) FEM_PB(3, MAT_F64);
+        else if (kin == MAT_F32) FEM_PB(3, MAT_F32);
+        else FEM_PB(3, MAT_F32X2);
+    } else {
+        if (kin == MAT_F64) FEM_PB(4, MAT_F64);
+        else if (kin == MAT_F32) FEM_PB(4, MAT_F32);
+        else FEM_PB(4, MAT_F32X2);
+    }
+#undef FEM_PB
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int batch_launch(const BatchLaunch &L, hipStream_t s) {
+    BatchArgs a{};
+    a.P = L.P;
+    a.A = L.A;
+    a.x = L.x;
+    a.r = L.r;
+    a.p = L.p;
+    a.q = L.q;
+    a.dinv = L.dinv;
+    a.b = L.b;
+    const int64_t ns = std::max<int64_t>(L.P.n_shared, 1);
+    a.sx = L.shared;
+    a.sr = L.shared + ns;
+    a.sp = L.shared + 2 * ns;
+    a.sq = L.shared + 3 * ns;
+    a.sd = L.shared + 4 * ns;
+    a.part = L.part;
+    a.pchunk0 = L.pchunk0;
+    a.pshared0 = L.pshared0;
+    a.pseg0 = L.pseg0;
+    a.pgroup = L.pgroup;
+    a.nprob = L.nprob;
+    a.prob = L.prob;
+    a.cnt = L.cnt;
+    a.cdots = L.cdots;
+    a.sdots = L.sdots;
+    a.qitems = L.qitems;
+    a.qtags = L.qtags;
+    a.qhead = L.qhead;
+    a.qtail = L.qtail;
+    a.qmask = L.qcap - 1;
+    a.ndone = L.ndone;
+    a.abort_flag = L.abort_flag;
+    a.rtol = L.rtol;
+    a.delta = L.delta;
+    a.max_iter = L.max_iter;
+    a.max_refresh = L.max_refresh;
+    a.spin_ticks = (long long)(L.watchdog_seconds * 1e8);
+    const int gi = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)(L.qcap / kBlock), 4096));
+    k_batch_init<<<gi, kBlock, 0, s>>>(a, L.n_seed);
+    k_batch_seed<<<gi, kBlock, 0, s>>>(a, L.pitem0, L.n_seed);
+    k_batch_empty<<<1, kBlock, 0, s>>>(a);
+    FEM_HIP_CHECK(hipGetLastError());
+    const size_t lds = chunk_lds_bytes<3, double>(L.P.E) / 3 * L.P.nb;
+    const int per_cu = std::max(1, std::min(2048 / L.block, (int)(160 * 1024 / (lds + 2048))));
+    const int grid = L.grid > 0 ? L.grid : per_cu * device_cu_count();
+    int rc = dispatch_tile(L.P.E, L.block, [&](auto bs, auto ept) -> int {
+        constexpr int BS = decltype(bs)::value;
+        constexpr int EPT = decltype(ept)::value;
+        if (L.P.nb == 3) {
+            k_batch<3, EPT, BS><<<grid, BS, lds, s>>>(a);
+        } else {
+            if constexpr (EPT * BS <= 1536 || (EPT <= 2 && BS == 1024)) k_batch<4, EPT, BS><<<grid, BS, lds, s>>>(a);
+            else return set_error(FEM_EINVAL, "chunk size too large for tetrahedra");
+        }
+        return 0;
+    });
+    if (rc) return rc;
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+}  // namespace fem

@@ -35,6 +35,8 @@ int launch_apply_pk64(const DevPlan &P, int kind, const void *A, const double *x
 // kout = MAT_F64 or MAT_F32X2.
 int launch_pack(const DevPlan &P, int kin, const void *K, const void *M, double nu, int kout, void *A,
                 hipStream_t s);
+// d = sum_e C_e^T diag(A_e) from the packed difference form
+int launch_diag_pk64(const DevPlan &P, int kind, const void *A, double *d, double *scratch, hipStream_t s);
 // d = sum_e C_e^T diag(A_e)
 int launch_diag64(const DevPlan &P, int kind, const void *K, const void *M, double nu, double *d,
                   double *scratch, hipStream_t s);

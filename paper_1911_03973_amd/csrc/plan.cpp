@@ -219,4 +219,101 @@ int build_host_plan(int dim, int64_t n_nodes, int64_t n_elems, const double *coo
     return 0;
 }
 
+int build_batch_plan(int dim, int n_problems, const int64_t *node_off, const int64_t *elem_off,
+                     const int64_t *dir_off, const double *coords, const int32_t *conn, const int32_t *dirichlet,
+                     int chunk_elems, BatchHost &B, std::string &err) {
+    const int nb = dim + 1;
+    const int64_t NN = node_off[n_problems], NE = elem_off[n_problems];
+    std::vector<HostPlan> parts(n_problems);
+    std::vector<std::string> errs(n_problems);
+    std::vector<int> rcs(n_problems, 0);
+    parallel_for(n_problems, [&](int64_t p) {
+        const int64_t nn = node_off[p + 1] - node_off[p], ne = elem_off[p + 1] - elem_off[p];
+        std::vector<double> lc((size_t)dim * nn);
+        for (int r = 0; r < dim; ++r)
+            for (int64_t i = 0; i < nn; ++i) lc[(size_t)r * nn + i] = coords[(size_t)r * NN + node_off[p] + i];
+        std::vector<int32_t> le((size_t)nb * ne);
+        for (int a = 0; a < nb; ++a)
+            for (int64_t e = 0; e < ne; ++e) le[(size_t)a * ne + e] = conn[(size_t)a * NE + elem_off[p] + e];
+        rcs[p] = build_host_plan(dim, nn, ne, lc.data(), le.data(), dirichlet + dir_off[p], dir_off[p + 1] - dir_off[p],
+                                 chunk_elems, parts[p], errs[p]);
+    });
+    for (int p = 0; p < n_problems; ++p)
+        if (rcs[p]) {
+            err = "problem " + std::to_string(p) + ": " + errs[p];
+            return -1;
+        }
+    HostPlan &U = B.U;
+    U = HostPlan();
+    U.dim = dim;
+    U.nb = nb;
+    U.E = chunk_elems;
+    U.n_nodes = NN;
+    U.n_elems = NE;
+    B.node0.assign(node_off, node_off + n_problems + 1);
+    B.elem0.assign(elem_off, elem_off + n_problems + 1);
+    B.chunk0.assign(n_problems + 1, 0);
+    B.shared0.assign(n_problems + 1, 0);
+    B.part0.assign(n_problems + 1, 0);
+    B.n_dir.assign(n_problems, 0);
+    B.isolated_free.assign(n_problems, 0);
+    for (int p = 0; p < n_problems; ++p) {
+        B.chunk0[p + 1] = B.chunk0[p] + (int32_t)parts[p].n_chunks;
+        B.shared0[p + 1] = B.shared0[p] + (int32_t)parts[p].n_shared;
+        B.part0[p + 1] = B.part0[p] + parts[p].n_partials;
+        B.n_dir[p] = parts[p].n_dirichlet;
+        B.isolated_free[p] = parts[p].n_isolated_free;
+    }
+    U.n_chunks = B.chunk0[n_problems];
+    U.n_shared = B.shared0[n_problems];
+    U.n_partials = B.part0[n_problems];
+    U.chunk_node_off.assign(U.n_chunks + 1, 0);
+    U.chunk_info.assign((size_t)U.n_chunks * 2, 0);
+    U.slots.assign((size_t)U.n_chunks * nb * chunk_elems, 0);
+    U.fix_off.assign(U.n_shared + 1, 0);
+    U.fix_nodes.resize(U.n_shared);
+    U.fix_parts.resize(U.n_partials);
+    U.part_owner.resize(U.n_partials);
+    U.mask.resize(NN);
+    B.chunk_elem0.assign(U.n_chunks + 1, 0);
+    int64_t nloc = 0;
+    std::vector<int64_t> loc0(n_problems + 1, 0);
+    for (int p = 0; p < n_problems; ++p) loc0[p + 1] = loc0[p] + parts[p].n_local;
+    U.n_local = loc0[n_problems];
+    U.loc_nodes.resize(U.n_local);
+    U.loc_end.resize(U.n_local);
+    parallel_for(n_problems, [&](int64_t p) {
+        const HostPlan &H = parts[p];
+        const int32_t c0 = B.chunk0[p];
+        for (int64_t c = 0; c < H.n_chunks; ++c) {
+            U.chunk_node_off[c0 + c] = (int32_t)(loc0[p] + H.chunk_node_off[c]);
+            U.chunk_info[2 * (c0 + c)] = H.chunk_info[2 * c];
+            U.chunk_info[2 * (c0 + c) + 1] = (int32_t)(B.part0[p] + H.chunk_info[2 * c + 1]);
+            B.chunk_elem0[c0 + c] = elem_off[p] + c * chunk_elems;
+        }
+        std::copy(H.slots.begin(), H.slots.end(), U.slots.begin() + (size_t)c0 * nb * chunk_elems);
+        for (int64_t k = 0; k < H.n_local; ++k) {
+            U.loc_nodes[loc0[p] + k] = (int32_t)(node_off[p] + H.loc_nodes[k]);
+            U.loc_end[loc0[p] + k] = H.loc_end[k];
+        }
+        const int32_t s0 = B.shared0[p];
+        for (int64_t k = 0; k < H.n_shared; ++k) {
+            U.fix_nodes[s0 + k] = (int32_t)(node_off[p] + H.fix_nodes[k]);
+            U.fix_off[s0 + k] = (int32_t)(B.part0[p] + H.fix_off[k]);
+        }
+        for (int64_t k = 0; k < H.n_partials; ++k) {
+            U.fix_parts[B.part0[p] + k] = (int32_t)(B.part0[p] + H.fix_parts[k]);
+            U.part_owner[B.part0[p] + k] = s0 + H.part_owner[k];
+        }
+        std::copy(H.mask.begin(), H.mask.end(), U.mask.begin() + node_off[p]);
+    });
+    U.chunk_node_off[U.n_chunks] = (int32_t)U.n_local;
+    U.fix_off[U.n_shared] = (int32_t)U.n_partials;
+    B.chunk_elem0[U.n_chunks] = NE;
+    (void)nloc;
+    U.n_dirichlet = 0;
+    for (int64_t i = 0; i < NN; ++i) U.n_dirichlet += U.mask[i];
+    return 0;
+}
+
 }  // namespace fem

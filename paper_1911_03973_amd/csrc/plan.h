@@ -28,6 +28,7 @@ struct HostPlan {
 struct DevPlan {
     int dim, nb, E;
     int64_t n_nodes, n_elems, n_chunks, n_local, n_shared, n_partials;
+    const int64_t *chunk_elem0;  // [n_chunks+1] first element of each chunk; NULL: chunk c starts at c*E
     const double *coords;        // [dim][n_nodes]
     const int32_t *conn;         // [nb][n_elems]
     const int32_t *chunk_node_off;
@@ -45,5 +46,24 @@ struct DevPlan {
 int build_host_plan(int dim, int64_t n_nodes, int64_t n_elems, const double *coords,
                     const int32_t *conn, const int32_t *dirichlet, int64_t n_dir, int chunk_elems,
                     HostPlan &P, std::string &err);
+
+// Many independent meshes as one: every problem is chunked on its own (no
+// chunk straddles two problems) and the index arrays are concatenated with
+// node, element, chunk, shared-node and partial offsets.
+struct BatchHost {
+    HostPlan U;                           // union arrays (global ids)
+    std::vector<int64_t> chunk_elem0;     // [n_chunks+1]
+    std::vector<int64_t> node0, elem0;    // [P+1]
+    std::vector<int32_t> chunk0, shared0; // [P+1]
+    std::vector<int64_t> part0;           // [P+1]
+    std::vector<int64_t> n_dir;           // [P] distinct Dirichlet nodes
+    std::vector<int64_t> isolated_free;   // [P]
+};
+
+// coords: union SoA [dim][total nodes]; conn: union SoA [nb][total elems] with
+// problem-local node ids; dirichlet: concatenated problem-local ids.
+int build_batch_plan(int dim, int n_problems, const int64_t *node_off, const int64_t *elem_off,
+                     const int64_t *dir_off, const double *coords, const int32_t *conn, const int32_t *dirichlet,
+                     int chunk_elems, BatchHost &B, std::string &err);
 
 }  // namespace fem

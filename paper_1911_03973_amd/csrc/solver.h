@@ -55,6 +55,48 @@ struct SolverWork {
 
 Grids solver_grids(const DevPlan &P, size_t elem_lds);
 
+// Per-problem record of the batched solver (written by that problem's FIN
+// item, read by its element items after a release/acquire hand-over).
+struct BatchProblem {
+    int flag;       // 1 once the problem is finished
+    int status;     // fem_status of the problem
+    int round;      // 0 iteration round, 1 refresh round
+    int mode;       // IterMode of the next iteration round
+    int pending;    // alpha * p not yet applied to x
+    int iters, refreshes, first, broken, pad;
+    double alpha, beta, rz;
+    double r0, thr2, rel2, rr_true;
+};
+
+// Everything one persistent batched launch needs (device pointers).
+struct BatchLaunch {
+    DevPlan P;  // union of all problems
+    const void *A;
+    double *x, *r, *p, *q;
+    const double *dinv, *b;
+    double *shared;  // [5][n_shared]
+    double *part;
+    const int32_t *pchunk0, *pshared0, *pseg0;
+    const int32_t *pgroup;  // [P] chunks per work item
+    const int32_t *pitem0;  // [P+1] prefix of the work items of a chunk round
+    int64_t n_seed;         // work items of one chunk round of all problems
+    int nprob;
+    BatchProblem *prob;
+    int *cnt;
+    double *cdots, *sdots;
+    unsigned long long *qitems, *qtags, *qhead, *qtail;
+    unsigned long long qcap;
+    int *ndone, *abort_flag;
+    double rtol, delta;
+    int max_iter, max_refresh;
+    double watchdog_seconds;
+    int block, grid;
+};
+
+int batch_pack(const DevPlan &P, int kin, const void *K, const void *M, const double *d_nu, const int64_t *d_elem0,
+               int nprob, float *A, hipStream_t s);
+int batch_launch(const BatchLaunch &L, hipStream_t s);
+
 int solve_pcg(const DevPlan &P, SolverWork &w, int dtype, int vec64, int block, const void *K, const void *M,
               double nu, const double *b, double *x, double rtol, int max_iter, int jacobi, double delta,
               int max_outer, int check_every, int profile, fem_solve_info *info, hipStream_t s);

@@ -70,6 +70,22 @@ class SolveInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class BatchOpts(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int), ("refresh", ctypes.c_double),
+        ("max_refresh", ctypes.c_int), ("block", ctypes.c_int), ("grid", ctypes.c_int),
+        ("watchdog_seconds", ctypes.c_double), ("use_graph", ctypes.c_int), ("group", ctypes.c_int),
+        ("items_per_phase", ctypes.c_int),
+    ]
+
+
+class BatchResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int), ("iters", ctypes.c_int), ("refreshes", ctypes.c_int), ("relres", ctypes.c_double),
+        ("r0", ctypes.c_double),
+    ]
+
+
 _vp, _i64, _int, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
 _SIGS = {
     "fem_plan_create": [_int, _i64, _i64, _vp, _vp, _vp, _i64, _int, _vp, ctypes.POINTER(_vp)],
@@ -83,6 +99,13 @@ _SIGS = {
     "fem_jacobi_diag": [_vp, _int, _vp, _vp, _dbl, _vp, _vp],
     "fem_assemble_rhs": [_vp, _int, _vp, _vp, _vp, _vp],
     "fem_pcg_solve": [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, _vp, _vp, ctypes.POINTER(SolveInfo), _vp],
+    "fem_batch_create": [_int, _int, _vp, _vp, _vp, _vp, _vp, _vp, _int, _vp, ctypes.POINTER(_vp)],
+    "fem_batch_destroy": [_vp],
+    "fem_batch_get_stats": [_vp, ctypes.POINTER(PlanStats)],
+    "fem_batch_build_local_matrices": [_vp, _int, _vp, _vp, _vp],
+    "fem_batch_assemble_rhs": [_vp, _int, _vp, _vp, _vp, _vp],
+    "fem_batch_solve": [_vp, ctypes.POINTER(BatchOpts), _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(BatchResult),
+                        ctypes.POINTER(ctypes.c_double), _vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -92,8 +115,10 @@ _lib.fem_last_error.restype = ctypes.c_char_p
 _lib.fem_last_error.argtypes = []
 _lib.fem_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
 _lib.fem_solve_opts_default.restype = None
+_lib.fem_batch_opts_default.argtypes = [ctypes.POINTER(BatchOpts)]
+_lib.fem_batch_opts_default.restype = None
 
-EXPORTED = sorted(list(_SIGS) + ["fem_last_error", "fem_solve_opts_default"])
+EXPORTED = sorted(list(_SIGS) + ["fem_last_error", "fem_solve_opts_default", "fem_batch_opts_default"])
 
 
 def library():
@@ -289,3 +314,98 @@ def pcg_solve(plan, opts, K, M, b, x, stream=None, allow=(FEM_ENOCONV,)):
 
 def last_error():
     return _lib.fem_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+# Batches of independent problems
+# ---------------------------------------------------------------------------
+
+def batch_opts(**kw):
+    o = BatchOpts()
+    _lib.fem_batch_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Batch:
+    """Owns a fem_batch: independent meshes solved together in one persistent launch."""
+
+    def __init__(self, meshes, dirichlets, chunk_elems=0, device="cuda", stream=None):
+        import numpy as np
+
+        dim = meshes[0].dim
+        P = len(meshes)
+        node_off = np.zeros(P + 1, np.int64)
+        elem_off = np.zeros(P + 1, np.int64)
+        dir_off = np.zeros(P + 1, np.int64)
+        for i, (m, d) in enumerate(zip(meshes, dirichlets)):
+            node_off[i + 1] = node_off[i] + m.n_nodes
+            elem_off[i + 1] = elem_off[i] + m.n_elems
+            dir_off[i + 1] = dir_off[i] + (0 if d is None else len(d))
+        coords = np.concatenate([m.coords for m in meshes]).T.copy()
+        conn = np.concatenate([m.elems for m in meshes]).T.copy()
+        dirs = np.concatenate([np.asarray(d if d is not None else [], np.int32) for d in dirichlets]).astype(np.int32)
+        self._coords = torch.from_numpy(coords).to(device)
+        self._conn = torch.from_numpy(conn).to(device)
+        self._dir = torch.from_numpy(dirs if dirs.size else np.zeros(1, np.int32)).to(device)
+        h = ctypes.c_void_p()
+        _check(_lib.fem_batch_create(dim, P, node_off.ctypes.data, elem_off.ctypes.data, dir_off.ctypes.data,
+                                     _ptr(self._coords), _ptr(self._conn), _ptr(self._dir), chunk_elems,
+                                     _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.dim, self.nb, self.n_problems = dim, dim + 1, P
+        self.node_off, self.elem_off = node_off, elem_off
+        self.n_nodes, self.n_elems = int(node_off[-1]), int(elem_off[-1])
+        self.device = self._coords.device
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("batch destroyed")
+        return self._h
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            _lib.fem_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def stats(self):
+        st = PlanStats()
+        _check(_lib.fem_batch_get_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def empty_matrix(self, dtype):
+        shape, tdt = matrix_shape(dtype, self.nb, self.n_elems)
+        return torch.empty(shape, dtype=tdt, device=self.device)
+
+    def build_local_matrices(self, dtype, K, M, stream=None):
+        _check(_lib.fem_batch_build_local_matrices(self.handle, dtype, _ptr(K), _ptr(M), _stream(stream)))
+
+    def assemble_rhs(self, dtype, M, f, b, stream=None):
+        _need(f, torch.float64, self.n_nodes, "f")
+        _need(b, torch.float64, self.n_nodes, "b")
+        _check(_lib.fem_batch_assemble_rhs(self.handle, dtype, _ptr(M), _ptr(f), _ptr(b), _stream(stream)))
+
+    def solve(self, opts, K, M, nus, b, x, stream=None, allow=(FEM_ENOCONV,)):
+        """Returns (status, [per-problem result dicts], seconds)."""
+        import numpy as np
+
+        nu = np.ascontiguousarray(nus, dtype=np.float64)
+        assert nu.shape == (self.n_problems,)
+        _need(b, torch.float64, self.n_nodes, "b")
+        _need(x, torch.float64, self.n_nodes, "x")
+        res = (BatchResult * self.n_problems)()
+        sec = ctypes.c_double(0.0)
+        rc = _check(_lib.fem_batch_solve(self.handle, ctypes.byref(opts), _ptr(K), _ptr(M), nu.ctypes.data, _ptr(b),
+                                         _ptr(x), res, ctypes.byref(sec), _stream(stream)), allow=allow)
+        out = [{k: getattr(r, k) for k, _ in r._fields_} for r in res]
+        return rc, out, sec.value
