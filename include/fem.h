@@ -262,6 +262,100 @@ int fem_batch_solve(fem_batch *batch, const fem_batch_opts *opts, const void *d_
                     const double *h_nu, const double *d_b, double *d_x, fem_batch_result *results,
                     double *seconds, void *stream);
 
+/* ------------------------------------------------------------------------ */
+/* Learned preconditioner: a U-Net on the structured nodal grid, used as     */
+/* z = N(r) in flexible CG.  Section 3 notes that the iteration counts grow  */
+/* with the condition number on finer meshes, so the solvers need a          */
+/* preconditioner, and the Outlooks name preconditioners as the next step;   */
+/* this one is trained on (residual, error) pairs from the Jacobi-PCG solver. */
+/* ------------------------------------------------------------------------ */
+typedef struct fem_unet fem_unet; /* opaque */
+
+/* Create a U-Net for images of H x W pixels (multiples of 8) and batches of
+ * up to max_batch images; channels = base width c (16 or 32).
+ *  Architecture, level l at (H >> l) x (W >> l), NHWC BF16 activations:
+ *    encoder  two 3x3 conv + ReLU per level (8->c, c->c | c->2c, 2c->2c |
+ *             2c->4c, 4c->4c | 4c->8c, 8c->8c), 2x2 average pooling between
+ *    decoder  2x2 stride-2 transposed conv (8c->4c, 4c->2c, 2c->c), concat
+ *             with the encoder output of that level (up-sampled first), two
+ *             3x3 conv + ReLU (2k->k, k->k)
+ *    output   1x1 conv c->1 in FP32
+ *  Input channels: 2 (the rest of the first layer's 8 are zero padding).
+ *  Parameters: one FP32 vector, layer by layer, weights then bias:
+ *    3x3 conv   W[ky*3+kx][ci][co] (input pixel (y+ky-1, x+kx-1), zero
+ *               outside the image), bias[co]
+ *    transposed W[ci][a*2+b][co]: output pixel (2y+a, 2x+b) gets
+ *               sum_ci in(y,x,ci) W[ci][a*2+b][co] + bias[co]
+ *    output     w[c], bias
+ *  Arithmetic: BF16 operands on MFMA with FP32 accumulation; FP32 master
+ *  weights, Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * Initial weights are He-normal from `seed` (biases 0).  Allocates its own
+ * device memory; synchronises `stream`. */
+int fem_unet_create(int H, int W, int max_batch, int channels, uint64_t seed, void *stream, fem_unet **out);
+int fem_unet_destroy(fem_unet *net);
+int fem_unet_param_count(const fem_unet *net, int64_t *count);
+/* FP32 parameter vector in the layout above (device memory, count floats).
+ * set_params also clears the Adam state. */
+int fem_unet_get_params(const fem_unet *net, float *d_params, void *stream);
+int fem_unet_set_params(fem_unet *net, const float *d_params, void *stream);
+/* d_in float [batch][H][W][2] (NHWC), d_out float [batch][H][W]. */
+int fem_unet_forward(fem_unet *net, int batch, const float *d_in, float *d_out, void *stream);
+/* Loss L = (1/batch) sum_b ||N(in_b) - t_b||^2 / ||t_b||^2 (d_loss: one
+ * device double) and its gradient with respect to every parameter (d_grad:
+ * device float [count], may be NULL).  d_target float [batch][H][W]. */
+int fem_unet_loss_grad(fem_unet *net, int batch, const float *d_in, const float *d_target, double *d_loss,
+                       float *d_grad, void *stream);
+/* One Adam step on L with learning rate lr (d_loss may be NULL). */
+int fem_unet_train_step(fem_unet *net, int batch, const float *d_in, const float *d_target, float lr,
+                        double *d_loss, void *stream);
+/* z = N(r) on the structured grid of (grid_n + 1)^2 nodes numbered
+ * i + j (grid_n + 1) (grid_n = H = W): the interior residual (1 <= i, j <=
+ * grid_n - 1), divided by its RMS, is pixel (i-1, j-1) of channel 0, with the
+ * last row and column zero; channel 1 is the constant cval.  The output is
+ * written to the interior nodes; boundary nodes and nodes with d_mask != 0
+ * (uint8 [n_nodes], may be NULL) get 0.  Allocates nothing. */
+int fem_unet_precondition(fem_unet *net, int grid_n, const double *d_r, double cval, const uint8_t *d_mask,
+                          double *d_z, void *stream);
+
+typedef struct {
+    int dtype;          /* storage of K_e / M_e */
+    double nu;
+    double rtol;        /* stop when the FP64 ||b - A x|| <= rtol ||b - A x0|| */
+    int max_iter;       /* FCG iterations, plus as many Jacobi-PCG ones after a handover */
+    int grid_n;         /* structured grid of (grid_n + 1)^2 nodes (see fem_unet_precondition) */
+    double cval;        /* constant second input channel of the network */
+    int stall_iters;    /* hand over to Jacobi-PCG when ||r|| has not halved in this many iterations */
+    int max_replace;    /* true-residual restarts allowed */
+} fem_fcg_opts;
+
+typedef struct {
+    int status;
+    int iters;          /* FCG iterations */
+    int pcg_iters;      /* Jacobi-PCG iterations after a handover */
+    int precond_calls;  /* network applications */
+    int fell_back;      /* FCG iteration at which Jacobi-PCG took over, -1 if never */
+    int fallback_reason;/* 0 none, 1 non-finite or zero network output,
+                           2 p.q <= 0, 3 stall */
+    int replacements;
+    double relres;      /* true FP64 ||b - A x|| / ||b - A x0|| */
+    double r0;
+    double seconds;
+} fem_fcg_info;
+
+void fem_fcg_opts_default(fem_fcg_opts *o);
+
+/* Flexible CG (FCG(1)) for (K + nu M) u = b with the Dirichlet rows masked,
+ * preconditioned by z = N(r) (net != NULL; the mesh must be the structured
+ * 2D grid described at fem_unet_precondition) or by Jacobi (net == NULL).
+ * With a network, a non-finite or zero output, p.q <= 0, or stall_iters
+ * iterations without halving ||r|| hand the current iterate over to the
+ * Jacobi-PCG solver (fem_pcg_solve with opts->dtype), which finishes the
+ * solve.  The true FP64 residual decides convergence.  x: x0 on entry
+ * (Dirichlet values included), the solution on exit.  Allocates a workspace
+ * for the call; synchronises `stream`. */
+int fem_fcg_solve(const fem_plan *plan, const fem_fcg_opts *opts, fem_unet *net, const void *d_K_e,
+                  const void *d_M_e, const double *d_b, double *d_x, fem_fcg_info *info, void *stream);
+
 /* Thread-local message describing the last failure ("" if none). */
 const char *fem_last_error(void);
 

@@ -20,7 +20,8 @@ OBJ_DIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["plan.cpp", "local.hip", "apply.hip", "pcg.hip", "batch.hip", "api.hip", "batch_api.hip"]
+SOURCES = ["plan.cpp", "local.hip", "apply.hip", "pcg.hip", "batch.hip", "api.hip", "batch_api.hip", "unet.hip",
+           "fcg.hip"]
 
 COMMON = [
     "-O3",

@@ -427,4 +427,70 @@ int fem_pcg_solve(const fem_plan *plan_c, const fem_solve_opts *o, const void *d
     return rc;
 }
 
+void fem_fcg_opts_default(fem_fcg_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->dtype = FEM_F64;
+    o->rtol = 1e-8;
+    o->max_iter = 100000;
+    o->stall_iters = 50;
+    o->max_replace = 8;
+}
+
+int fem_fcg_solve(const fem_plan *plan_c, const fem_fcg_opts *o, fem_unet *net, const void *d_K_e,
+                  const void *d_M_e, const double *d_b, double *d_x, fem_fcg_info *info, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (int rc = check_plan(plan_c)) return rc;
+    fem_plan *plan = const_cast<fem_plan *>(plan_c);
+    if (!o || !info) return set_error(FEM_EINVAL, "opts and info must not be NULL");
+    std::memset(info, 0, sizeof(*info));
+    info->fell_back = -1;
+    if (!valid_dtype(o->dtype)) return set_error(FEM_EINVAL, "unknown dtype");
+    if (!std::isfinite(o->nu) || o->nu < 0.0) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
+    if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) return set_error(FEM_EINVAL, "rtol must be in (0, 1)");
+    if (o->max_iter < 1) return set_error(FEM_EINVAL, "max_iter must be >= 1");
+    if (o->stall_iters < 1 || o->max_replace < 0) return set_error(FEM_EINVAL, "stall_iters >= 1, max_replace >= 0");
+    if ((!d_K_e && plan->dev.n_elems > 0) || !d_b || !d_x) return set_error(FEM_EINVAL, "NULL argument");
+    if (o->nu != 0.0 && !d_M_e) return set_error(FEM_EINVAL, "nu > 0 needs M_e");
+    if ((const void *)d_x == (const void *)d_b) return set_error(FEM_EINVAL, "x must not alias b");
+    if (o->nu == 0.0 && plan->stats.n_dirichlet == 0)
+        return set_error(FEM_ESINGULAR, "nu = 0 needs a Dirichlet part of positive measure");
+    if (plan->n_isolated_free > 0)
+        return set_error(FEM_ESINGULAR, "a node outside every element is not a Dirichlet node");
+    if (net) {
+        const int64_t g = o->grid_n;
+        if (plan->dev.dim != 2 || g < 8 || (g + 1) * (g + 1) != plan->dev.n_nodes)
+            return set_error(FEM_EINVAL, "the network needs a 2D structured grid of (grid_n + 1)^2 nodes");
+        if (!std::isfinite(o->cval)) return set_error(FEM_EINVAL, "cval must be finite");
+    }
+    hipStream_t s = S(stream);
+    fem::FcgResult res;
+    int rc = fem::solve_fcg(plan->dev, o->dtype, d_K_e, o->nu != 0.0 ? d_M_e : nullptr, o->nu, d_b, d_x, o->rtol,
+                            o->max_iter, net, o->grid_n, o->cval, o->stall_iters, o->max_replace, res, s);
+    info->iters = res.iters;
+    info->precond_calls = res.precond_calls;
+    info->fell_back = res.fell_back;
+    info->fallback_reason = res.fallback_reason;
+    info->replacements = res.replacements;
+    info->r0 = res.r0;
+    info->relres = res.relres;
+    if (rc == fem::kFcgHandover) {
+        // Jacobi-PCG from the current iterate to the same absolute target
+        fem_solve_opts po;
+        fem_solve_opts_default(&po);
+        po.dtype = o->dtype;
+        po.nu = o->nu;
+        po.max_iter = o->max_iter;
+        po.rtol = std::min(0.5, o->rtol * res.r0 / std::max(res.rnorm, 1e-300));
+        fem_solve_info pi;
+        rc = fem_pcg_solve(plan, &po, d_K_e, d_M_e, d_b, d_x, &pi, stream);
+        info->pcg_iters = pi.iters;
+        info->relres = res.r0 > 0.0 ? pi.relres * pi.r0 / res.r0 : 0.0;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && rc == FEM_OK) rc = set_error(FEM_EHIP, "stream synchronisation failed");
+    info->status = rc;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
 }  // extern "C"

@@ -105,4 +105,18 @@ int solve_pcg(const DevPlan &P, SolverWork &w, int dtype, int vec64, int block, 
 // n_b row sums followed by the n_b (n_b - 1) / 2 upper off-diagonal entries.
 __host__ __device__ constexpr int packed_count(int nb) { return nb + nb * (nb - 1) / 2; }
 
+// Flexible CG (fcg.hip).  With a network, a non-finite or zero network
+// output, p.q <= 0, or stall_iters iterations without halving ||r|| end the
+// FCG phase with kFcgHandover (x and res.rnorm hold the current iterate and
+// its residual norm) so that the caller continues with Jacobi-PCG; without a
+// network the preconditioner is Jacobi throughout.
+struct FcgResult {
+    int status, iters, precond_calls, fell_back, fallback_reason, replacements;
+    double relres, r0, rnorm;
+};
+constexpr int kFcgHandover = 1;
+int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double nu, const double *b, double *x,
+              double rtol, int max_iter, fem_unet *net, int grid_n, double cval, int stall_iters, int max_replace,
+              FcgResult &res, hipStream_t s);
+
 }  // namespace fem

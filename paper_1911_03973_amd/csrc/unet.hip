@@ -1,0 +1,1066 @@
+// unet.hip -- a small U-Net on the structured nodal grid, trained and applied
+// with hand-written BF16 MFMA kernels (FP32 accumulation).  It serves as the
+// preconditioner of flexible CG (fcg.hip).
+//
+// Network (base width c; NHWC BF16 activations; level l has (H>>l) x (W>>l)):
+//   L0  conv3x3(8 -> c) ReLU          L1  conv3x3(c -> c) ReLU       = e0
+//   pool; L2 conv(c -> 2c) ReLU;      L3  conv(2c -> 2c) ReLU        = e1
+//   pool; L4 conv(2c -> 4c) ReLU;     L5  conv(4c -> 4c) ReLU        = e2
+//   pool; L6 conv(4c -> 8c) ReLU;     L7  conv(8c -> 8c) ReLU        = m
+//   L8  upconv2x2(8c -> 4c);  L9  conv([u2, e2] -> 4c) ReLU;  L10 conv(4c -> 4c) ReLU = d2
+//   L11 upconv2x2(4c -> 2c);  L12 conv([u1, e1] -> 2c) ReLU;  L13 conv(2c -> 2c) ReLU = d1
+//   L14 upconv2x2(2c -> c);   L15 conv([u0, e0] -> c) ReLU;   L16 conv(c -> c) ReLU   = d0
+//   out conv1x1(c -> 1), FP32
+// pool = 2x2 average; the input has 2 channels (scaled residual, constant
+// channel) stored as 8 so that every MFMA fragment reads 8 channels.
+//
+// Every convolution is an implicit GEMM on v_mfma_f32_16x16x32_bf16: rows are
+// pixels (16 per wave, 64 per workgroup), columns output channels, and the
+// reduction runs over (tap, input channel) in blocks of 32.  Each lane loads 8
+// consecutive channels of one pixel (16 bytes) and 8 reduction rows of the
+// weight fragment, which is kept pre-packed in MFMA operand order.
+// Backward-data is the same GEMM on the ReLU-masked output gradient with the
+// transposed weights.  Weight gradients reduce over pixels in fixed slices
+// whose FP32 partials are added in slice order, so a training step is bitwise
+// reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "fem.h"
+#include "unet.h"
+
+namespace fem {
+
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPixTile = 64;   // pixels per GEMM workgroup (4 waves x 16)
+constexpr int kWSlice = 4096;  // pixels per weight-gradient slice
+
+__device__ __forceinline__ f4 mfma(bf8 a, bf8 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+
+__device__ __forceinline__ bf8 zero8() {
+    bf8 z;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) z[i] = (bf16)0.0f;
+    return z;
+}
+
+__device__ __forceinline__ bf8 ld8(const bf16 *p) { return *reinterpret_cast<const bf8 *>(p); }
+
+// ---------------------------------------------------------------------------
+// A-operand sources: 8 consecutive reduction entries (k0 .. k0+7) of row m.
+// ---------------------------------------------------------------------------
+
+// conv3x3 forward: row m = pixel (b, y, x); k = tap * Cin + ci, tap = ky*3+kx;
+// channels [0, C1) from src1, [C1, C1 + C2) from src2 (concatenation).
+struct SrcConv {
+    const bf16 *src1, *src2;
+    int C1, C2, H, W;
+    __device__ __forceinline__ bf8 load(int m, int k0) const {
+        const int Cin = C1 + C2;
+        const int tap = k0 / Cin, ci = k0 - tap * Cin;
+        if (tap >= 9) return zero8();
+        const int x = m % W, t = m / W, y = t % H;
+        const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+        if (yy < 0 || yy >= H || xx < 0 || xx >= W) return zero8();
+        const int64_t pix = (int64_t)m + (int64_t)(tap / 3 - 1) * W + (tap % 3 - 1);
+        if (ci < C1) return ld8(src1 + pix * C1 + ci);
+        return ld8(src2 + pix * C2 + (ci - C1));
+    }
+};
+
+// conv3x3 backward-data: row m = input pixel q; k = tap * Cout + co, entry
+// gz[q - d_tap][co] with gz = gy * (y > 0).
+struct SrcConvBwd {
+    const bf16 *gy, *y;
+    int Cout, H, W;
+    __device__ __forceinline__ bf8 load(int m, int k0) const {
+        const int tap = k0 / Cout, co = k0 - tap * Cout;
+        if (tap >= 9) return zero8();
+        const int x = m % W, t = m / W, yq = t % H;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const int yy = yq - dy, xx = x - dx;
+        if (yy < 0 || yy >= H || xx < 0 || xx >= W) return zero8();
+        const int64_t off = ((int64_t)m - (int64_t)dy * W - dx) * Cout + co;
+        bf8 g = ld8(gy + off);
+        const bf8 v = ld8(y + off);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) g[i] = ((float)v[i] > 0.0f) ? g[i] : (bf16)0.0f;
+        return g;
+    }
+};
+
+// rows of a [M][C] tensor (up-conv forward: m = low-resolution pixel)
+struct SrcRows {
+    const bf16 *src;
+    int C;
+    __device__ __forceinline__ bf8 load(int m, int k0) const {
+        if (k0 >= C) return zero8();
+        return ld8(src + (int64_t)m * C + k0);
+    }
+};
+
+__device__ __forceinline__ int64_t fine_pixel(int m, int q, int H, int W) {
+    // low pixel m = (b, y, x) of an H x W level -> fine pixel (b, 2y + q/2, 2x + q%2)
+    const int x = m % W, t = m / W, y = t % H, b = t / H;
+    return ((int64_t)b * 2 * H + 2 * y + (q >> 1)) * (2 * W) + 2 * x + (q & 1);
+}
+
+// up-conv backward-data: row m = low pixel; k = q * Cout + co, entry du[fine(m, q)][co]
+struct SrcUpBwd {
+    const bf16 *du;
+    int Cout, H, W;  // low resolution
+    __device__ __forceinline__ bf8 load(int m, int k0) const {
+        const int q = k0 / Cout, co = k0 - q * Cout;
+        if (q >= 4) return zero8();
+        return ld8(du + fine_pixel(m, q, H, W) * Cout + co);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Epilogues: value v of row m, column n.
+// ---------------------------------------------------------------------------
+struct EpiConv {  // bias + ReLU -> bf16 [M][N]
+    bf16 *out;
+    const float *bias;
+    int N;
+    __device__ __forceinline__ void put(int m, int n, float v) const {
+        v += bias[n];
+        out[(int64_t)m * N + n] = (bf16)(v > 0.0f ? v : 0.0f);
+    }
+};
+
+struct EpiGrad {  // gradient of a (possibly concatenated) input: columns [0,C1) -> g1, the rest -> g2
+    bf16 *g1, *g2;
+    int C1, C2;
+    __device__ __forceinline__ void put(int m, int n, float v) const {
+        if (n < C1)
+            g1[(int64_t)m * C1 + n] = (bf16)v;
+        else if (g2)
+            g2[(int64_t)m * C2 + (n - C1)] = (bf16)v;
+    }
+};
+
+struct EpiUp {  // up-conv forward: column n = q*Cout + co -> out[fine(m, q)][co] (+ bias)
+    bf16 *out;
+    const float *bias;
+    int Cout, H, W;  // low resolution
+    __device__ __forceinline__ void put(int m, int n, float v) const {
+        const int q = n / Cout, co = n - q * Cout;
+        out[fine_pixel(m, q, H, W) * Cout + co] = (bf16)(v + bias[co]);
+    }
+};
+
+// Row GEMM D[M][16 NT] = A[M][32 KB] B[32 KB][16 NT]; Bp holds B in fragment
+// order [KB][NT][64 lanes][8].  Each wave owns 16 rows and all columns.
+template <class Src, class Epi, int NT>
+__global__ __launch_bounds__(256) void k_gemm_rows(Src src, Epi epi, const bf16 *__restrict__ Bp, int M, int KB) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m0 = blockIdx.x * kPixTile + wave * 16;
+    if (m0 >= M) return;
+    f4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    const int mr = m0 + (lane & 15);
+    const bool row_ok = mr < M;
+    for (int kb = 0; kb < KB; ++kb) {
+        const bf8 a = row_ok ? src.load(mr, kb * 32 + 8 * (lane >> 4)) : zero8();
+        const bf16 *bk = Bp + ((int64_t)kb * NT * 64 + lane) * 8;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mfma(a, ld8(bk + (int64_t)t * 64 * 8), acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = m0 + 4 * (lane >> 4) + i;
+            if (m < M) epi.put(m, t * 16 + (lane & 15), acc[t][i]);
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradients: dW[r][n] = sum_pixels A[pixel][r] G[pixel][n]; the rows r
+// are those of the im2col operand plus a last bias row of ones.  Workgroup
+// (i, s) computes rows [64 i, 64 i + 64) over the pixel slice s into
+// partial[s][R1][N]; the slices are added in order afterwards.
+// ---------------------------------------------------------------------------
+struct WSrcConv {  // conv3x3: r = tap * Cin + ci; r == R is the bias row
+    const bf16 *src1, *src2;
+    int C1, C2, H, W, R;
+    __device__ __forceinline__ float a(int64_t pix, int r) const {
+        if (r == R) return 1.0f;
+        const int Cin = C1 + C2;
+        const int tap = r / Cin, ci = r - tap * Cin;
+        const int x = (int)(pix % W);
+        const int y = (int)((pix / W) % H);
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        if (y + dy < 0 || y + dy >= H || x + dx < 0 || x + dx >= W) return 0.0f;
+        const int64_t q = pix + (int64_t)dy * W + dx;
+        return ci < C1 ? (float)src1[q * C1 + ci] : (float)src2[q * C2 + (ci - C1)];
+    }
+};
+struct WGradConv {  // gy * (y > 0)
+    const bf16 *gy, *y;
+    int N;
+    __device__ __forceinline__ float g(int64_t pix, int n) const {
+        const int64_t o = pix * N + n;
+        return (float)y[o] > 0.0f ? (float)gy[o] : 0.0f;
+    }
+};
+struct WSrcUp {  // up-conv: r = ci; r == C is the bias row
+    const bf16 *src;
+    int C;
+    __device__ __forceinline__ float a(int64_t pix, int r) const { return r == C ? 1.0f : (float)src[pix * C + r]; }
+};
+struct WGradUp {  // column n = q * Cout + co: du at the fine position q of low pixel pix
+    const bf16 *du;
+    int Cout, H, W;
+    __device__ __forceinline__ float g(int64_t pix, int n) const {
+        const int q = n / Cout, co = n - q * Cout;
+        return (float)du[fine_pixel((int)pix, q, H, W) * Cout + co];
+    }
+};
+
+template <class WS, class WG, int NT>
+__global__ __launch_bounds__(256) void k_gemm_wgrad(WS ws, WG wg, int R1, int N, int64_t P,
+                                                    float *__restrict__ partial) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = blockIdx.x * 64 + wave * 16;
+    if (r0 >= R1) return;
+    const int s = blockIdx.y;
+    const int64_t p0 = (int64_t)s * kWSlice, p1 = std::min<int64_t>(P, p0 + kWSlice);
+    f4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    const int r = r0 + (lane & 15);
+    for (int64_t pb = p0; pb < p1; pb += 32) {
+        bf8 a;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int64_t pix = pb + 8 * (lane >> 4) + i;
+            a[i] = (bf16)((pix < p1 && r < R1) ? ws.a(pix, r) : 0.0f);
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            bf8 bv;
+            const int n = t * 16 + (lane & 15);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int64_t pix = pb + 8 * (lane >> 4) + i;
+                bv[i] = (bf16)((pix < p1 && n < N) ? wg.g(pix, n) : 0.0f);
+            }
+            acc[t] = mfma(a, bv, acc[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rr = r0 + 4 * (lane >> 4) + i, n = t * 16 + (lane & 15);
+            if (rr < R1 && n < N) partial[((int64_t)s * R1 + rr) * N + n] = acc[t][i];
+        }
+}
+
+// out[i] = sum_s partial[s][i], s in order
+__global__ void k_sum_splits(const float *__restrict__ partial, int splits, int64_t n, float *__restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float v = 0.f;
+        for (int s = 0; s < splits; ++s) v += partial[(int64_t)s * n + i];
+        out[i] = v;
+    }
+}
+
+// up-conv: rows [0, Cin) of partial[s][Cin+1][4 Cout] are the weights; the
+// bias row is summed over the 4 positions into out[Cin*4Cout + co]
+__global__ void k_sum_splits_up(const float *__restrict__ partial, int splits, int Cin, int Cout,
+                                float *__restrict__ out) {
+    const int64_t nw = (int64_t)Cin * 4 * Cout, n = nw + Cout, per = nw + 4 * Cout;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float v = 0.f;
+        if (i < nw) {
+            for (int s = 0; s < splits; ++s) v += partial[(int64_t)s * per + i];
+        } else {
+            const int co = (int)(i - nw);
+            for (int s = 0; s < splits; ++s)
+                for (int q = 0; q < 4; ++q) v += partial[(int64_t)s * per + nw + q * Cout + co];
+        }
+        out[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise and small kernels
+// ---------------------------------------------------------------------------
+__global__ void k_pool_fwd(const bf16 *__restrict__ in, bf16 *__restrict__ out, int B, int H, int W, int C) {
+    // in [B][H][W][C] -> out [B][H/2][W/2][C]
+    const int64_t n = (int64_t)B * (H / 2) * (W / 2) * C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        int64_t t = i / C;
+        const int x = (int)(t % (W / 2));
+        t /= (W / 2);
+        const int y = (int)(t % (H / 2));
+        const int64_t b = t / (H / 2);
+        const int64_t base = ((b * H + 2 * y) * W + 2 * x) * C + c;
+        const float s = ((float)in[base] + (float)in[base + C]) +
+                        ((float)in[base + (int64_t)W * C] + (float)in[base + (int64_t)W * C + C]);
+        out[i] = (bf16)(0.25f * s);
+    }
+}
+
+// gin (fine) += gout (coarse) / 4
+__global__ void k_pool_bwd(const bf16 *__restrict__ gout, bf16 *__restrict__ gin, int B, int H, int W, int C) {
+    const int64_t n = (int64_t)B * H * W * C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        int64_t t = i / C;
+        const int x = (int)(t % W);
+        t /= W;
+        const int y = (int)(t % H);
+        const int64_t b = t / H;
+        const float g = (float)gout[((b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
+        gin[i] = (bf16)((float)gin[i] + 0.25f * g);
+    }
+}
+
+// [P][2] fp32 -> [P][8] bf16 (channels 2..7 zero)
+__global__ void k_make_input(const float *__restrict__ in2, bf16 *__restrict__ x8, int64_t P) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        bf8 v = zero8();
+        v[0] = (bf16)in2[2 * p];
+        v[1] = (bf16)in2[2 * p + 1];
+        *reinterpret_cast<bf8 *>(x8 + p * 8) = v;
+    }
+}
+
+// out[p] = b + sum_c d0[p][c] w[c]
+__global__ void k_out_fwd(const bf16 *__restrict__ d0, const float *__restrict__ w, const float *__restrict__ bias,
+                          int C, int64_t P, float *__restrict__ out) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        float s = bias[0];
+        for (int c = 0; c < C; ++c) s += (float)d0[p * C + c] * w[c];
+        out[p] = s;
+    }
+}
+
+// per (slice, sample): sums of t^2 and (y - t)^2 -> part[b][slice][2]
+__global__ __launch_bounds__(256) void k_loss_part(const float *__restrict__ y, const float *__restrict__ t,
+                                                   int64_t HW, int slices, double *__restrict__ part) {
+    __shared__ double red[2 * 4];
+    const int b = blockIdx.y, s = blockIdx.x;
+    const int64_t per = (HW + slices - 1) / slices;
+    const int64_t i0 = s * per, i1 = std::min<int64_t>(HW, i0 + per);
+    double v[2] = {0.0, 0.0};
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        const double tv = t[b * HW + i], dv = (double)y[b * HW + i] - tv;
+        v[0] += tv * tv;
+        v[1] += dv * dv;
+    }
+    block_sum_n<256, 2>(v, red);
+    if (threadIdx.x == 0) {
+        part[((int64_t)b * slices + s) * 2] = v[0];
+        part[((int64_t)b * slices + s) * 2 + 1] = v[1];
+    }
+}
+
+// sums[b] = (sum t^2, sum (y-t)^2); loss = mean over b of the ratio (one thread)
+__global__ void k_loss_fin(const double *__restrict__ part, int B, int slices, double *__restrict__ sums,
+                           double *__restrict__ loss) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double L = 0.0;
+    for (int b = 0; b < B; ++b) {
+        double st = 0.0, se = 0.0;
+        for (int s = 0; s < slices; ++s) {
+            st += part[((int64_t)b * slices + s) * 2];
+            se += part[((int64_t)b * slices + s) * 2 + 1];
+        }
+        sums[2 * b] = st;
+        sums[2 * b + 1] = se;
+        L += se / fmax(st, 1e-300);
+    }
+    if (loss) *loss = L / B;
+}
+
+// gy = 2 (y - t) / (B sum t^2) (FP32), gd0[p][c] = gy w[c] (BF16)
+__global__ void k_out_bwd(const float *__restrict__ y, const float *__restrict__ t, const double *__restrict__ sums,
+                          const float *__restrict__ w, int C, int64_t HW, int B, float *__restrict__ gy,
+                          bf16 *__restrict__ gd0) {
+    const int64_t P = HW * B;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = p / HW;
+        const float g = (float)(2.0 * ((double)y[p] - t[p]) / ((double)B * fmax(sums[2 * b], 1e-300)));
+        gy[p] = g;
+        for (int c = 0; c < C; ++c) gd0[p * C + c] = (bf16)(g * w[c]);
+    }
+}
+
+// 1x1 output layer weight gradient over pixel slices:
+// part[s][c] = sum_p d0[p][c] gy[p] (c < C), part[s][C] = sum_p gy[p]
+__global__ __launch_bounds__(256) void k_out_wgrad(const bf16 *__restrict__ d0, const float *__restrict__ gy, int C,
+                                                   int64_t P, float *__restrict__ part) {
+    __shared__ double red[4];
+    const int s = blockIdx.x;
+    const int64_t p0 = (int64_t)s * kWSlice, p1 = std::min<int64_t>(P, p0 + kWSlice);
+    for (int c = 0; c <= C; ++c) {
+        double v = 0.0;
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += 256)
+            v += (double)gy[p] * (c < C ? (double)(float)d0[p * C + c] : 1.0);
+        v = block_sum<256>(v, red);
+        if (threadIdx.x == 0) part[(int64_t)s * (C + 1) + c] = (float)v;
+    }
+}
+
+// Adam on the FP32 master weights; c1, c2 are the bias corrections 1 - beta^t
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                       int64_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// B operands in fragment order from the FP32 weights.
+struct MapConvFwd {  // k = tap*Cin + ci, n = co: W[tap][ci][co]
+    const float *w;
+    int Cin, Cout;
+    __device__ float operator()(int k, int n) const { return k < 9 * Cin ? w[(int64_t)k * Cout + n] : 0.f; }
+};
+struct MapConvBwd {  // k = tap*Cout + co, n = ci: W[tap][ci][co]
+    const float *w;
+    int Cin, Cout;
+    __device__ float operator()(int k, int n) const {
+        const int tap = k / Cout, co = k - tap * Cout;
+        if (tap >= 9 || n >= Cin) return 0.f;
+        return w[((int64_t)tap * Cin + n) * Cout + co];
+    }
+};
+struct MapUpFwd {  // k = ci, n = q*Cout + co: W[ci][q][co]
+    const float *w;
+    int Cin, Cout;
+    __device__ float operator()(int k, int n) const { return k < Cin ? w[(int64_t)k * 4 * Cout + n] : 0.f; }
+};
+struct MapUpBwd {  // k = q*Cout + co, n = ci: W[ci][q][co]
+    const float *w;
+    int Cin, Cout;
+    __device__ float operator()(int k, int n) const {
+        return (k < 4 * Cout && n < Cin) ? w[(int64_t)n * 4 * Cout + k] : 0.f;
+    }
+};
+template <class Map>
+__global__ void k_pack_b(Map map, int KB, int NT, bf16 *__restrict__ Bp) {
+    const int64_t total = (int64_t)KB * NT * 64 * 8;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int e = (int)(i % 8);
+        int64_t t = i / 8;
+        const int lane = (int)(t % 64);
+        t /= 64;
+        const int nt = (int)(t % NT);
+        const int kb = (int)(t / NT);
+        Bp[i] = (bf16)map(kb * 32 + 8 * (lane >> 4) + e, nt * 16 + (lane & 15));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Grid glue of the preconditioner: nodal residual -> image, image -> nodal z.
+// Node (i, j) of the (N+1) x (N+1) grid is i + j (N+1); interior node (i, j),
+// 1 <= i, j <= N-1, is pixel (x, y) = (i-1, j-1) of an N x N image whose last
+// row and column are zero padding.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_interior_sumsq(const double *__restrict__ r, int N, double *__restrict__ part) {
+    __shared__ double red[4];
+    const int64_t n = (int64_t)(N - 1) * (N - 1);
+    double s = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const int64_t x = p % (N - 1), y = p / (N - 1);
+        const double v = r[(y + 1) * (N + 1) + x + 1];
+        s += v * v;
+    }
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+__global__ void k_grid_in(const double *__restrict__ r, const double *__restrict__ part, int nparts, int N, float cval,
+                          float *__restrict__ in2) {
+    __shared__ double inv_s;
+    if (threadIdx.x == 0) {
+        double ss = 0.0;
+        for (int k = 0; k < nparts; ++k) ss += part[k];
+        const double n_int = (double)(N - 1) * (N - 1);
+        inv_s = ss > 0.0 ? 1.0 / sqrt(ss / n_int) : 0.0;
+    }
+    __syncthreads();
+    const double inv = inv_s;
+    const int64_t P = (int64_t)N * N;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(p % N), y = (int)(p / N);
+        float v = 0.f;
+        if (x < N - 1 && y < N - 1) v = (float)(r[(int64_t)(y + 1) * (N + 1) + (x + 1)] * inv);
+        in2[2 * p] = v;
+        in2[2 * p + 1] = cval;
+    }
+}
+__global__ void k_grid_out(const float *__restrict__ out, int N, const uint8_t *__restrict__ mask, double *__restrict__ z) {
+    const int64_t n = (int64_t)(N + 1) * (N + 1);
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(g % (N + 1)), j = (int)(g / (N + 1));
+        double v = 0.0;
+        if (i >= 1 && i <= N - 1 && j >= 1 && j <= N - 1) v = out[(int64_t)(j - 1) * N + (i - 1)];
+        if (mask && mask[g]) v = 0.0;
+        z[g] = v;
+    }
+}
+
+inline int grid1(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384)); }
+
+enum LayerKind { CONV = 0, UP = 1 };
+
+struct Layer {
+    int kind;
+    int lvl;     // level of the GEMM rows (conv: its level; up-conv: the low level)
+    int C1, C2;  // input channels (conv: concatenation split; up-conv: C1 = Cin)
+    int Cout;
+    int64_t woff, boff;
+    bf16 *Bf = nullptr, *Bb = nullptr;
+    int KBf = 0, NTf = 0, KBb = 0, NTb = 0;
+    int Cin() const { return C1 + C2; }
+};
+
+struct Tensor {
+    bf16 *a = nullptr, *g = nullptr;
+    int lvl = 0, C = 0;
+};
+
+}  // namespace
+
+struct UNet {
+    int H = 0, W = 0, maxB = 0, c = 0;
+    std::vector<Layer> L;
+    int64_t nparam = 0, out_woff = 0, out_boff = 0;
+    int64_t step = 0;
+    void *arena = nullptr;
+    float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    Tensor x8, e0a, e0, p0, e1a, e1, p1, e2a, e2, p2, ma, mm, u2, d2a, d2, u1, d1a, d1, u0, d0a, d0;
+    float *out = nullptr, *gy = nullptr, *in2 = nullptr, *partial = nullptr;
+    double *sums = nullptr, *lpart = nullptr, *gpart = nullptr;
+    int64_t partial_cap = 0;
+    int loss_slices = 64;
+};
+
+namespace {
+
+int64_t pixels(const UNet &N, int lvl, int B) { return (int64_t)B * (N.H >> lvl) * (N.W >> lvl); }
+
+template <class Src, class Epi>
+int launch_rows(const Src &s, const Epi &e, const bf16 *Bp, int64_t M, int KB, int NT, hipStream_t st) {
+    const int g = (int)((M + kPixTile - 1) / kPixTile);
+    const int m = (int)M;
+    switch (NT) {
+        case 1: k_gemm_rows<Src, Epi, 1><<<g, 256, 0, st>>>(s, e, Bp, m, KB); break;
+        case 2: k_gemm_rows<Src, Epi, 2><<<g, 256, 0, st>>>(s, e, Bp, m, KB); break;
+        case 4: k_gemm_rows<Src, Epi, 4><<<g, 256, 0, st>>>(s, e, Bp, m, KB); break;
+        case 8: k_gemm_rows<Src, Epi, 8><<<g, 256, 0, st>>>(s, e, Bp, m, KB); break;
+        case 16: k_gemm_rows<Src, Epi, 16><<<g, 256, 0, st>>>(s, e, Bp, m, KB); break;
+        case 32: k_gemm_rows<Src, Epi, 32><<<g, 256, 0, st>>>(s, e, Bp, m, KB); break;
+        default: return set_error(FEM_EINVAL, "unsupported GEMM width");
+    }
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int64_t wgrad_splits(int64_t P) { return std::max<int64_t>(1, (P + kWSlice - 1) / kWSlice); }
+
+template <class WS, class WG>
+int launch_wgrad(UNet &N, const WS &ws, const WG &wg, int R1, int Nc, int64_t P, hipStream_t st) {
+    const int64_t splits = wgrad_splits(P);
+    if (splits * R1 * Nc > N.partial_cap || splits > 65535)
+        return set_error(FEM_EINVAL, "weight-gradient scratch too small");
+    const int NT = (Nc + 15) / 16;
+    dim3 grid((R1 + 63) / 64, (unsigned)splits);
+    switch (NT) {
+        case 1: k_gemm_wgrad<WS, WG, 1><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, N.partial); break;
+        case 2: k_gemm_wgrad<WS, WG, 2><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, N.partial); break;
+        case 4: k_gemm_wgrad<WS, WG, 4><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, N.partial); break;
+        case 8: k_gemm_wgrad<WS, WG, 8><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, N.partial); break;
+        case 16: k_gemm_wgrad<WS, WG, 16><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, N.partial); break;
+        case 32: k_gemm_wgrad<WS, WG, 32><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, N.partial); break;
+        default: return set_error(FEM_EINVAL, "unsupported GEMM width");
+    }
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int repack(UNet &N, hipStream_t st) {
+    for (auto &l : N.L) {
+        const float *w = N.w + l.woff;
+        const int64_t nf = (int64_t)l.KBf * l.NTf * 512, nb = (int64_t)l.KBb * l.NTb * 512;
+        if (l.kind == CONV) {
+            k_pack_b<<<grid1(nf), 256, 0, st>>>(MapConvFwd{w, l.Cin(), l.Cout}, l.KBf, l.NTf, l.Bf);
+            if (l.Bb) k_pack_b<<<grid1(nb), 256, 0, st>>>(MapConvBwd{w, l.Cin(), l.Cout}, l.KBb, l.NTb, l.Bb);
+        } else {
+            k_pack_b<<<grid1(nf), 256, 0, st>>>(MapUpFwd{w, l.C1, l.Cout}, l.KBf, l.NTf, l.Bf);
+            k_pack_b<<<grid1(nb), 256, 0, st>>>(MapUpBwd{w, l.C1, l.Cout}, l.KBb, l.NTb, l.Bb);
+        }
+    }
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int conv_fwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B, hipStream_t st) {
+    SrcConv src{s1.a, s2 ? s2->a : nullptr, l.C1, l.C2, N.H >> l.lvl, N.W >> l.lvl};
+    EpiConv epi{y.a, N.w + l.boff, l.Cout};
+    return launch_rows(src, epi, l.Bf, pixels(N, l.lvl, B), l.KBf, l.NTf, st);
+}
+
+// conv3x3 + ReLU backward: input gradients into s1.g (and s2->g), overwritten; weight gradients
+int conv_bwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, bool input_grad, int B,
+             hipStream_t st) {
+    const int H = N.H >> l.lvl, W = N.W >> l.lvl;
+    const int64_t M = pixels(N, l.lvl, B);
+    if (input_grad) {
+        SrcConvBwd src{y.g, y.a, l.Cout, H, W};
+        EpiGrad epi{s1.g, s2 ? s2->g : nullptr, l.C1, l.C2};
+        if (int rc = launch_rows(src, epi, l.Bb, M, l.KBb, l.NTb, st)) return rc;
+    }
+    const int R = 9 * l.Cin();
+    WSrcConv ws{s1.a, s2 ? s2->a : nullptr, l.C1, l.C2, H, W, R};
+    WGradConv wg{y.g, y.a, l.Cout};
+    if (int rc = launch_wgrad(N, ws, wg, R + 1, l.Cout, M, st)) return rc;
+    const int64_t n = (int64_t)(R + 1) * l.Cout;  // weights [tap][ci][co] then the bias: contiguous
+    k_sum_splits<<<grid1(n), 256, 0, st>>>(N.partial, (int)wgrad_splits(M), n, N.g + l.woff);
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int up_fwd(UNet &N, const Layer &l, const Tensor &in, const Tensor &y, int B, hipStream_t st) {
+    SrcRows src{in.a, l.C1};
+    EpiUp epi{y.a, N.w + l.boff, l.Cout, N.H >> l.lvl, N.W >> l.lvl};
+    return launch_rows(src, epi, l.Bf, pixels(N, l.lvl, B), l.KBf, l.NTf, st);
+}
+
+int up_bwd(UNet &N, const Layer &l, const Tensor &in, const Tensor &y, int B, hipStream_t st) {
+    const int H = N.H >> l.lvl, W = N.W >> l.lvl;
+    const int64_t M = pixels(N, l.lvl, B);
+    SrcUpBwd src{y.g, l.Cout, H, W};
+    EpiGrad epi{in.g, nullptr, l.C1, 0};
+    if (int rc = launch_rows(src, epi, l.Bb, M, l.KBb, l.NTb, st)) return rc;
+    WSrcUp ws{in.a, l.C1};
+    WGradUp wg{y.g, l.Cout, H, W};
+    if (int rc = launch_wgrad(N, ws, wg, l.C1 + 1, 4 * l.Cout, M, st)) return rc;
+    const int64_t n = (int64_t)l.C1 * 4 * l.Cout + l.Cout;
+    k_sum_splits_up<<<grid1(n), 256, 0, st>>>(N.partial, (int)wgrad_splits(M), l.C1, l.Cout, N.g + l.woff);
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int pool(const UNet &N, const Tensor &in, const Tensor &out, int B, hipStream_t st) {
+    const int H = N.H >> in.lvl, W = N.W >> in.lvl;
+    k_pool_fwd<<<grid1(pixels(N, out.lvl, B) * in.C), 256, 0, st>>>(in.a, out.a, B, H, W, in.C);
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int pool_bwd(const UNet &N, const Tensor &in, const Tensor &out, int B, hipStream_t st) {
+    const int H = N.H >> in.lvl, W = N.W >> in.lvl;
+    k_pool_bwd<<<grid1(pixels(N, in.lvl, B) * in.C), 256, 0, st>>>(out.g, in.g, B, H, W, in.C);
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+// forward of input [B][H][W][2] (FP32) into N.out [B][H][W]
+int forward(UNet &N, int B, const float *in, hipStream_t st) {
+    const int64_t P0 = pixels(N, 0, B);
+    k_make_input<<<grid1(P0), 256, 0, st>>>(in, N.x8.a, P0);
+    const auto &L = N.L;
+    int rc = 0;
+    auto ok = [&](int r) {
+        if (!rc) rc = r;
+    };
+    ok(conv_fwd(N, L[0], N.x8, nullptr, N.e0a, B, st));
+    ok(conv_fwd(N, L[1], N.e0a, nullptr, N.e0, B, st));
+    ok(pool(N, N.e0, N.p0, B, st));
+    ok(conv_fwd(N, L[2], N.p0, nullptr, N.e1a, B, st));
+    ok(conv_fwd(N, L[3], N.e1a, nullptr, N.e1, B, st));
+    ok(pool(N, N.e1, N.p1, B, st));
+    ok(conv_fwd(N, L[4], N.p1, nullptr, N.e2a, B, st));
+    ok(conv_fwd(N, L[5], N.e2a, nullptr, N.e2, B, st));
+    ok(pool(N, N.e2, N.p2, B, st));
+    ok(conv_fwd(N, L[6], N.p2, nullptr, N.ma, B, st));
+    ok(conv_fwd(N, L[7], N.ma, nullptr, N.mm, B, st));
+    ok(up_fwd(N, L[8], N.mm, N.u2, B, st));
+    ok(conv_fwd(N, L[9], N.u2, &N.e2, N.d2a, B, st));
+    ok(conv_fwd(N, L[10], N.d2a, nullptr, N.d2, B, st));
+    ok(up_fwd(N, L[11], N.d2, N.u1, B, st));
+    ok(conv_fwd(N, L[12], N.u1, &N.e1, N.d1a, B, st));
+    ok(conv_fwd(N, L[13], N.d1a, nullptr, N.d1, B, st));
+    ok(up_fwd(N, L[14], N.d1, N.u0, B, st));
+    ok(conv_fwd(N, L[15], N.u0, &N.e0, N.d0a, B, st));
+    ok(conv_fwd(N, L[16], N.d0a, nullptr, N.d0, B, st));
+    if (rc) return rc;
+    k_out_fwd<<<grid1(P0), 256, 0, st>>>(N.d0.a, N.w + N.out_woff, N.w + N.out_boff, N.c, P0, N.out);
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+// loss and every parameter gradient (into N.g) for the forward held in N.out
+int backward(UNet &N, int B, const float *target, double *loss, hipStream_t st) {
+    const int64_t HW = (int64_t)N.H * N.W, P0 = HW * B;
+    dim3 lg(N.loss_slices, B);
+    k_loss_part<<<lg, 256, 0, st>>>(N.out, target, HW, N.loss_slices, N.lpart);
+    k_loss_fin<<<1, 64, 0, st>>>(N.lpart, B, N.loss_slices, N.sums, loss);
+    k_out_bwd<<<grid1(P0), 256, 0, st>>>(N.out, target, N.sums, N.w + N.out_woff, N.c, HW, B, N.gy, N.d0.g);
+    const int64_t so = wgrad_splits(P0);
+    k_out_wgrad<<<(unsigned)so, 256, 0, st>>>(N.d0.a, N.gy, N.c, P0, N.partial);
+    k_sum_splits<<<1, 256, 0, st>>>(N.partial, (int)so, N.c + 1, N.g + N.out_woff);
+    FEM_HIP_CHECK(hipGetLastError());
+    const auto &L = N.L;
+    int rc = 0;
+    auto ok = [&](int r) {
+        if (!rc) rc = r;
+    };
+    ok(conv_bwd(N, L[16], N.d0a, nullptr, N.d0, true, B, st));
+    ok(conv_bwd(N, L[15], N.u0, &N.e0, N.d0a, true, B, st));
+    ok(up_bwd(N, L[14], N.d1, N.u0, B, st));
+    ok(conv_bwd(N, L[13], N.d1a, nullptr, N.d1, true, B, st));
+    ok(conv_bwd(N, L[12], N.u1, &N.e1, N.d1a, true, B, st));
+    ok(up_bwd(N, L[11], N.d2, N.u1, B, st));
+    ok(conv_bwd(N, L[10], N.d2a, nullptr, N.d2, true, B, st));
+    ok(conv_bwd(N, L[9], N.u2, &N.e2, N.d2a, true, B, st));
+    ok(up_bwd(N, L[8], N.mm, N.u2, B, st));
+    ok(conv_bwd(N, L[7], N.ma, nullptr, N.mm, true, B, st));
+    ok(conv_bwd(N, L[6], N.p2, nullptr, N.ma, true, B, st));
+    ok(pool_bwd(N, N.e2, N.p2, B, st));
+    ok(conv_bwd(N, L[5], N.e2a, nullptr, N.e2, true, B, st));
+    ok(conv_bwd(N, L[4], N.p1, nullptr, N.e2a, true, B, st));
+    ok(pool_bwd(N, N.e1, N.p1, B, st));
+    ok(conv_bwd(N, L[3], N.e1a, nullptr, N.e1, true, B, st));
+    ok(conv_bwd(N, L[2], N.p0, nullptr, N.e1a, true, B, st));
+    ok(pool_bwd(N, N.e0, N.p0, B, st));
+    ok(conv_bwd(N, L[1], N.e0a, nullptr, N.e0, true, B, st));
+    ok(conv_bwd(N, L[0], N.x8, nullptr, N.e0a, false, B, st));
+    return rc;
+}
+
+void add_layer(UNet &N, int kind, int lvl, int C1, int C2, int Cout) {
+    Layer l;
+    l.kind = kind;
+    l.lvl = lvl;
+    l.C1 = C1;
+    l.C2 = C2;
+    l.Cout = Cout;
+    l.woff = N.nparam;
+    if (kind == CONV) {
+        l.boff = l.woff + (int64_t)9 * l.Cin() * Cout;
+        l.KBf = (9 * l.Cin() + 31) / 32;
+        l.NTf = Cout / 16;
+        l.KBb = (9 * Cout + 31) / 32;
+        l.NTb = (l.Cin() + 15) / 16;
+    } else {
+        l.boff = l.woff + (int64_t)C1 * 4 * Cout;
+        l.KBf = (C1 + 31) / 32;
+        l.NTf = 4 * Cout / 16;
+        l.KBb = (4 * Cout + 31) / 32;
+        l.NTb = C1 / 16;
+    }
+    N.nparam = l.boff + Cout;
+    N.L.push_back(l);
+}
+
+// He-normal weights (std sqrt(2 / fan_in)), zero biases; the first layer's
+// padding input channels 2..7 get zero weights.
+void init_params(const UNet &N, uint64_t seed, std::vector<float> &w) {
+    std::mt19937_64 gen(seed);
+    w.assign((size_t)N.nparam, 0.0f);
+    for (size_t li = 0; li < N.L.size(); ++li) {
+        const Layer &l = N.L[li];
+        const int fan_in = l.kind == CONV ? 9 * (li == 0 ? 2 : l.Cin()) : l.C1;
+        std::normal_distribution<double> nd(0.0, std::sqrt(2.0 / fan_in));
+        const int64_t nw = l.boff - l.woff;
+        for (int64_t i = 0; i < nw; ++i) {
+            double v = nd(gen);
+            if (li == 0 && (i / l.Cout) % l.Cin() >= 2) v = 0.0;
+            w[(size_t)(l.woff + i)] = (float)v;
+        }
+    }
+    std::normal_distribution<double> nd(0.0, std::sqrt(1.0 / N.c));
+    for (int ci = 0; ci < N.c; ++ci) w[(size_t)(N.out_woff + ci)] = (float)nd(gen);
+}
+
+}  // namespace
+
+}  // namespace fem
+
+struct fem_unet {
+    fem::UNet net;
+};
+
+namespace {
+
+using fem::set_error;
+
+hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+int check_net(const fem_unet *n) { return n ? FEM_OK : set_error(FEM_EINVAL, "network is NULL"); }
+
+int check_batch(const fem_unet *n, int B) {
+    if (B < 1 || B > n->net.maxB) return set_error(FEM_EINVAL, "batch must be in [1, max_batch]");
+    return FEM_OK;
+}
+
+}  // namespace
+
+namespace fem {
+
+int unet_grid_precondition(fem_unet *net, int grid_n, const double *r, double cval, const uint8_t *mask, double *z,
+                           hipStream_t st) {
+    UNet &N = net->net;
+    if (grid_n != N.H || grid_n != N.W) return set_error(FEM_EINVAL, "grid size must equal the network image size");
+    const int64_t n_int = (int64_t)(grid_n - 1) * (grid_n - 1);
+    const int parts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n_int + 255) / 256));
+    k_interior_sumsq<<<parts, 256, 0, st>>>(r, grid_n, N.gpart);
+    k_grid_in<<<grid1((int64_t)grid_n * grid_n), 256, 0, st>>>(r, N.gpart, parts, grid_n, (float)cval, N.in2);
+    FEM_HIP_CHECK(hipGetLastError());
+    if (int rc = forward(N, 1, N.in2, st)) return rc;
+    k_grid_out<<<grid1((int64_t)(grid_n + 1) * (grid_n + 1)), 256, 0, st>>>(N.out, grid_n, mask, z);
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+}  // namespace fem
+
+extern "C" {
+
+int fem_unet_create(int H, int W, int max_batch, int channels, uint64_t seed, void *stream, fem_unet **out) {
+    fem::last_error().clear();
+    if (!out) return set_error(FEM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (H < 8 || W < 8 || H % 8 || W % 8 || H > 8192 || W > 8192)
+        return set_error(FEM_EINVAL, "H and W must be multiples of 8 in [8, 8192]");
+    if (channels != 16 && channels != 32) return set_error(FEM_EINVAL, "channels must be 16 or 32");
+    if (max_batch < 1 || (int64_t)max_batch * H * W > ((int64_t)1 << 27))
+        return set_error(FEM_EINVAL, "max_batch * H * W must be in [1, 2^27]");
+    fem_unet *net = new (std::nothrow) fem_unet();
+    if (!net) return set_error(FEM_ENOMEM, "host allocation failed");
+    fem::UNet &N = net->net;
+    N.H = H;
+    N.W = W;
+    N.maxB = max_batch;
+    N.c = channels;
+    const int c = channels;
+    using fem::CONV;
+    using fem::UP;
+    fem::add_layer(N, CONV, 0, 8, 0, c);
+    fem::add_layer(N, CONV, 0, c, 0, c);
+    fem::add_layer(N, CONV, 1, c, 0, 2 * c);
+    fem::add_layer(N, CONV, 1, 2 * c, 0, 2 * c);
+    fem::add_layer(N, CONV, 2, 2 * c, 0, 4 * c);
+    fem::add_layer(N, CONV, 2, 4 * c, 0, 4 * c);
+    fem::add_layer(N, CONV, 3, 4 * c, 0, 8 * c);
+    fem::add_layer(N, CONV, 3, 8 * c, 0, 8 * c);
+    fem::add_layer(N, UP, 3, 8 * c, 0, 4 * c);
+    fem::add_layer(N, CONV, 2, 4 * c, 4 * c, 4 * c);
+    fem::add_layer(N, CONV, 2, 4 * c, 0, 4 * c);
+    fem::add_layer(N, UP, 2, 4 * c, 0, 2 * c);
+    fem::add_layer(N, CONV, 1, 2 * c, 2 * c, 2 * c);
+    fem::add_layer(N, CONV, 1, 2 * c, 0, 2 * c);
+    fem::add_layer(N, UP, 1, 2 * c, 0, c);
+    fem::add_layer(N, CONV, 0, c, c, c);
+    fem::add_layer(N, CONV, 0, c, 0, c);
+    N.out_woff = N.nparam;
+    N.out_boff = N.out_woff + c;
+    N.nparam = N.out_boff + 1;
+
+    // one device arena: parameters, Adam state, packed operands, activations, scratch
+    struct Item {
+        void **ptr;
+        size_t bytes;
+    };
+    std::vector<Item> items;
+    auto add = [&](void **p, size_t bytes) { items.push_back({p, bytes}); };
+    const int64_t np = N.nparam;
+    add((void **)&N.w, np * 4);
+    add((void **)&N.g, np * 4);
+    add((void **)&N.m, np * 4);
+    add((void **)&N.v, np * 4);
+    for (size_t li = 0; li < N.L.size(); ++li) {
+        fem::Layer &l = N.L[li];
+        add((void **)&l.Bf, (size_t)l.KBf * l.NTf * 512 * 2);
+        if (li != 0) add((void **)&l.Bb, (size_t)l.KBb * l.NTb * 512 * 2);
+    }
+    const int B = max_batch;
+    auto tens = [&](fem::Tensor &t, int lvl, int C) {
+        t.lvl = lvl;
+        t.C = C;
+        const size_t bytes = (size_t)fem::pixels(N, lvl, B) * C * 2;
+        add((void **)&t.a, bytes);
+        add((void **)&t.g, bytes);
+    };
+    tens(N.x8, 0, 8);
+    tens(N.e0a, 0, c);
+    tens(N.e0, 0, c);
+    tens(N.p0, 1, c);
+    tens(N.e1a, 1, 2 * c);
+    tens(N.e1, 1, 2 * c);
+    tens(N.p1, 2, 2 * c);
+    tens(N.e2a, 2, 4 * c);
+    tens(N.e2, 2, 4 * c);
+    tens(N.p2, 3, 4 * c);
+    tens(N.ma, 3, 8 * c);
+    tens(N.mm, 3, 8 * c);
+    tens(N.u2, 2, 4 * c);
+    tens(N.d2a, 2, 4 * c);
+    tens(N.d2, 2, 4 * c);
+    tens(N.u1, 1, 2 * c);
+    tens(N.d1a, 1, 2 * c);
+    tens(N.d1, 1, 2 * c);
+    tens(N.u0, 0, c);
+    tens(N.d0a, 0, c);
+    tens(N.d0, 0, c);
+    const int64_t P0 = fem::pixels(N, 0, B);
+    add((void **)&N.out, P0 * 4);
+    add((void **)&N.gy, P0 * 4);
+    add((void **)&N.in2, (size_t)H * W * 2 * 4);
+    int64_t cap = fem::wgrad_splits(P0) * (c + 1);
+    for (const auto &l : N.L) {
+        const int64_t M = fem::pixels(N, l.lvl, B);
+        const int64_t need =
+            l.kind == CONV ? (int64_t)(9 * l.Cin() + 1) * l.Cout : (int64_t)(l.C1 + 1) * 4 * l.Cout;
+        cap = std::max(cap, fem::wgrad_splits(M) * need);
+    }
+    N.partial_cap = cap;
+    add((void **)&N.partial, cap * 4);
+    add((void **)&N.sums, (size_t)2 * B * 8);
+    add((void **)&N.lpart, (size_t)2 * B * N.loss_slices * 8);
+    add((void **)&N.gpart, 1024 * 8);
+    size_t total = 0;
+    std::vector<size_t> offs;
+    for (auto &it : items) {
+        offs.push_back(total);
+        total += (it.bytes + 255) / 256 * 256;
+    }
+    if (hipMalloc(&N.arena, total) != hipSuccess) {
+        (void)hipGetLastError();
+        delete net;
+        return set_error(FEM_ENOMEM, "device allocation of the network failed");
+    }
+    for (size_t i = 0; i < items.size(); ++i) *items[i].ptr = static_cast<char *>(N.arena) + offs[i];
+    hipStream_t st = S(stream);
+    std::vector<float> w0;
+    fem::init_params(N, seed, w0);
+    int rc = 0;
+    if (hipMemsetAsync(N.arena, 0, total, st) != hipSuccess ||
+        hipMemcpyAsync(N.w, w0.data(), np * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = set_error(FEM_EHIP, "upload of the initial parameters failed");
+    if (!rc) rc = fem::repack(N, st);
+    if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = set_error(FEM_EHIP, "stream synchronisation failed");
+    if (rc) {
+        (void)hipFree(N.arena);
+        delete net;
+        return rc;
+    }
+    *out = net;
+    return FEM_OK;
+}
+
+int fem_unet_destroy(fem_unet *net) {
+    if (!net) return FEM_OK;
+    int rc = FEM_OK;
+    if (net->net.arena && hipFree(net->net.arena) != hipSuccess) rc = set_error(FEM_EHIP, "hipFree failed");
+    delete net;
+    return rc;
+}
+
+int fem_unet_param_count(const fem_unet *net, int64_t *count) {
+    if (int rc = check_net(net)) return rc;
+    if (!count) return set_error(FEM_EINVAL, "count is NULL");
+    *count = net->net.nparam;
+    return FEM_OK;
+}
+
+int fem_unet_get_params(const fem_unet *net, float *d_params, void *stream) {
+    if (int rc = check_net(net)) return rc;
+    if (!d_params) return set_error(FEM_EINVAL, "params is NULL");
+    FEM_HIP_CHECK(hipMemcpyAsync(d_params, net->net.w, net->net.nparam * 4, hipMemcpyDeviceToDevice, S(stream)));
+    return FEM_OK;
+}
+
+int fem_unet_set_params(fem_unet *net, const float *d_params, void *stream) {
+    if (int rc = check_net(net)) return rc;
+    if (!d_params) return set_error(FEM_EINVAL, "params is NULL");
+    fem::UNet &N = net->net;
+    hipStream_t st = S(stream);
+    FEM_HIP_CHECK(hipMemcpyAsync(N.w, d_params, N.nparam * 4, hipMemcpyDeviceToDevice, st));
+    FEM_HIP_CHECK(hipMemsetAsync(N.m, 0, N.nparam * 4, st));
+    FEM_HIP_CHECK(hipMemsetAsync(N.v, 0, N.nparam * 4, st));
+    N.step = 0;
+    return fem::repack(N, st);
+}
+
+int fem_unet_forward(fem_unet *net, int batch, const float *d_in, float *d_out, void *stream) {
+    if (int rc = check_net(net)) return rc;
+    if (int rc = check_batch(net, batch)) return rc;
+    if (!d_in || !d_out) return set_error(FEM_EINVAL, "NULL argument");
+    fem::UNet &N = net->net;
+    hipStream_t st = S(stream);
+    if (int rc = fem::forward(N, batch, d_in, st)) return rc;
+    FEM_HIP_CHECK(hipMemcpyAsync(d_out, N.out, fem::pixels(N, 0, batch) * 4, hipMemcpyDeviceToDevice, st));
+    return FEM_OK;
+}
+
+int fem_unet_loss_grad(fem_unet *net, int batch, const float *d_in, const float *d_target, double *d_loss,
+                       float *d_grad, void *stream) {
+    if (int rc = check_net(net)) return rc;
+    if (int rc = check_batch(net, batch)) return rc;
+    if (!d_in || !d_target || !d_loss) return set_error(FEM_EINVAL, "NULL argument");
+    fem::UNet &N = net->net;
+    hipStream_t st = S(stream);
+    if (int rc = fem::forward(N, batch, d_in, st)) return rc;
+    if (int rc = fem::backward(N, batch, d_target, d_loss, st)) return rc;
+    if (d_grad) FEM_HIP_CHECK(hipMemcpyAsync(d_grad, N.g, N.nparam * 4, hipMemcpyDeviceToDevice, st));
+    return FEM_OK;
+}
+
+int fem_unet_train_step(fem_unet *net, int batch, const float *d_in, const float *d_target, float lr,
+                        double *d_loss, void *stream) {
+    if (int rc = check_net(net)) return rc;
+    if (int rc = check_batch(net, batch)) return rc;
+    if (!d_in || !d_target) return set_error(FEM_EINVAL, "NULL argument");
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return set_error(FEM_EINVAL, "lr must be finite and > 0");
+    fem::UNet &N = net->net;
+    hipStream_t st = S(stream);
+    if (int rc = fem::forward(N, batch, d_in, st)) return rc;
+    if (int rc = fem::backward(N, batch, d_target, d_loss, st)) return rc;
+    N.step += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 - std::pow(b1, (double)N.step)), c2 = (float)(1.0 - std::pow(b2, (double)N.step));
+    fem::k_adam<<<fem::grid1(N.nparam), 256, 0, st>>>(N.w, N.g, N.m, N.v, N.nparam, lr, (float)b1, (float)b2, 1e-8f,
+                                                      c1, c2);
+    FEM_HIP_CHECK(hipGetLastError());
+    return fem::repack(N, st);
+}
+
+int fem_unet_precondition(fem_unet *net, int grid_n, const double *d_r, double cval, const uint8_t *d_mask,
+                          double *d_z, void *stream) {
+    if (int rc = check_net(net)) return rc;
+    if (!d_r || !d_z) return set_error(FEM_EINVAL, "NULL argument");
+    if (d_r == d_z) return set_error(FEM_EINVAL, "z must not alias r");
+    if (!std::isfinite(cval)) return set_error(FEM_EINVAL, "cval must be finite");
+    return fem::unet_grid_precondition(net, grid_n, d_r, cval, d_mask, d_z, S(stream));
+}
+
+}  // extern "C"

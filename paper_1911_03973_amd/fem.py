@@ -86,6 +86,23 @@ class BatchResult(ctypes.Structure):
     ]
 
 
+class FcgOpts(ctypes.Structure):
+    _fields_ = [
+        ("dtype", ctypes.c_int), ("nu", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int),
+        ("grid_n", ctypes.c_int), ("cval", ctypes.c_double), ("stall_iters", ctypes.c_int),
+        ("max_replace", ctypes.c_int),
+    ]
+
+
+class FcgInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int), ("iters", ctypes.c_int), ("pcg_iters", ctypes.c_int),
+        ("precond_calls", ctypes.c_int), ("fell_back", ctypes.c_int), ("fallback_reason", ctypes.c_int),
+        ("replacements", ctypes.c_int), ("relres", ctypes.c_double), ("r0", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+    ]
+
+
 _vp, _i64, _int, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
 _SIGS = {
     "fem_plan_create": [_int, _i64, _i64, _vp, _vp, _vp, _i64, _int, _vp, ctypes.POINTER(_vp)],
@@ -106,6 +123,16 @@ _SIGS = {
     "fem_batch_assemble_rhs": [_vp, _int, _vp, _vp, _vp, _vp],
     "fem_batch_solve": [_vp, ctypes.POINTER(BatchOpts), _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(BatchResult),
                         ctypes.POINTER(ctypes.c_double), _vp],
+    "fem_unet_create": [_int, _int, _int, _int, ctypes.c_uint64, _vp, ctypes.POINTER(_vp)],
+    "fem_unet_destroy": [_vp],
+    "fem_unet_param_count": [_vp, ctypes.POINTER(_i64)],
+    "fem_unet_get_params": [_vp, _vp, _vp],
+    "fem_unet_set_params": [_vp, _vp, _vp],
+    "fem_unet_forward": [_vp, _int, _vp, _vp, _vp],
+    "fem_unet_loss_grad": [_vp, _int, _vp, _vp, _vp, _vp, _vp],
+    "fem_unet_train_step": [_vp, _int, _vp, _vp, ctypes.c_float, _vp, _vp],
+    "fem_unet_precondition": [_vp, _int, _vp, _dbl, _vp, _vp, _vp],
+    "fem_fcg_solve": [_vp, ctypes.POINTER(FcgOpts), _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(FcgInfo), _vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -117,8 +144,11 @@ _lib.fem_solve_opts_default.argtypes = [ctypes.POINTER(SolveOpts)]
 _lib.fem_solve_opts_default.restype = None
 _lib.fem_batch_opts_default.argtypes = [ctypes.POINTER(BatchOpts)]
 _lib.fem_batch_opts_default.restype = None
+_lib.fem_fcg_opts_default.argtypes = [ctypes.POINTER(FcgOpts)]
+_lib.fem_fcg_opts_default.restype = None
 
-EXPORTED = sorted(list(_SIGS) + ["fem_last_error", "fem_solve_opts_default", "fem_batch_opts_default"])
+EXPORTED = sorted(list(_SIGS) + ["fem_last_error", "fem_solve_opts_default", "fem_batch_opts_default",
+                                 "fem_fcg_opts_default"])
 
 
 def library():
@@ -409,3 +439,105 @@ class Batch:
                                          _ptr(x), res, ctypes.byref(sec), _stream(stream)), allow=allow)
         out = [{k: getattr(r, k) for k, _ in r._fields_} for r in res]
         return rc, out, sec.value
+
+
+# ---------------------------------------------------------------------------
+# Learned preconditioner and flexible CG
+# ---------------------------------------------------------------------------
+
+class UNet:
+    """Owns a fem_unet: a U-Net on H x W images trained and run by the library's MFMA kernels."""
+
+    def __init__(self, H, W, max_batch=1, channels=16, seed=0, stream=None):
+        h = _vp()
+        _check(_lib.fem_unet_create(int(H), int(W), int(max_batch), int(channels), int(seed), _stream(stream),
+                                    ctypes.byref(h)))
+        self._h = h
+        self.H, self.W, self.max_batch, self.channels = int(H), int(W), int(max_batch), int(channels)
+        cnt = _i64(0)
+        _check(_lib.fem_unet_param_count(self._h, ctypes.byref(cnt)))
+        self.n_params = cnt.value
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("network destroyed")
+        return self._h
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.fem_unet_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def get_params(self, stream=None):
+        w = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(_lib.fem_unet_get_params(self.handle, _ptr(w), _stream(stream)))
+        return w
+
+    def set_params(self, w, stream=None):
+        _need(w, torch.float32, self.n_params, "params")
+        _check(_lib.fem_unet_set_params(self.handle, _ptr(w), _stream(stream)))
+
+    def _io(self, inp, target=None):
+        B = inp.shape[0]
+        _need(inp, torch.float32, B * self.H * self.W * 2, "input")
+        if target is not None:
+            _need(target, torch.float32, B * self.H * self.W, "target")
+        return B
+
+    def forward(self, inp, stream=None):
+        """inp float32 [B, H, W, 2] -> float32 [B, H, W]."""
+        B = self._io(inp)
+        out = torch.empty((B, self.H, self.W), dtype=torch.float32, device="cuda")
+        _check(_lib.fem_unet_forward(self.handle, B, _ptr(inp), _ptr(out), _stream(stream)))
+        return out
+
+    def loss_grad(self, inp, target, stream=None):
+        """(loss tensor [1] float64, gradient float32 [n_params])."""
+        B = self._io(inp, target)
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(_lib.fem_unet_loss_grad(self.handle, B, _ptr(inp), _ptr(target), _ptr(loss), _ptr(g),
+                                       _stream(stream)))
+        return loss, g
+
+    def train_step(self, inp, target, lr, loss=None, stream=None):
+        B = self._io(inp, target)
+        _check(_lib.fem_unet_train_step(self.handle, B, _ptr(inp), _ptr(target), float(lr), _ptr(loss),
+                                        _stream(stream)))
+
+    def precondition(self, grid_n, r, cval, z, mask=None, stream=None):
+        n = (grid_n + 1) ** 2
+        _need(r, torch.float64, n, "r")
+        _need(z, torch.float64, n, "z")
+        _need(mask, torch.uint8, n, "mask")
+        _check(_lib.fem_unet_precondition(self.handle, int(grid_n), _ptr(r), float(cval), _ptr(mask), _ptr(z),
+                                          _stream(stream)))
+
+
+def fcg_opts(**kw):
+    o = FcgOpts()
+    _lib.fem_fcg_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def fcg_solve(plan, opts, net, K, M, b, x, stream=None, allow=(FEM_ENOCONV,)):
+    """Runs fem_fcg_solve (net None: Jacobi preconditioner); returns the info dict."""
+    plan._mat(K, opts.dtype, "K_e")
+    plan._mat(M, opts.dtype, "M_e")
+    _need(b, torch.float64, plan.n_nodes, "b")
+    _need(x, torch.float64, plan.n_nodes, "x")
+    info = FcgInfo()
+    _check(_lib.fem_fcg_solve(plan.handle, ctypes.byref(opts), net.handle if net is not None else None, _ptr(K),
+                              _ptr(M), _ptr(b), _ptr(x), ctypes.byref(info), _stream(stream)), allow=allow)
+    return {k: getattr(info, k) for k, _ in info._fields_}

@@ -1,0 +1,80 @@
+"""Flexible CG on the element residual: Jacobi-FCG against the oracle's
+Jacobi-PCG (FCG(1) with a fixed SPD preconditioner generates the PCG iterates
+in exact arithmetic), convergence with a network preconditioner judged by the
+oracle's own FP64 residual, and the hand-over to Jacobi-PCG."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1911_03973_amd import inputs
+
+from problems import Problem, cuda
+
+pytestmark = pytest.mark.gpu
+
+fem = pytest.importorskip("paper_1911_03973_amd.fem")
+learn = pytest.importorskip("paper_1911_03973_amd.learn")
+
+
+def _true_relres(prob, x):
+    r = oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, x, prob.mask)
+    r0 = oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, np.zeros(prob.n), prob.mask)
+    return np.linalg.norm(r) / np.linalg.norm(r0)
+
+
+def _gpu(prob, dtype=fem.F64):
+    plan = fem.Plan.from_mesh(prob.mesh, prob.nd)
+    K = plan.empty_matrix(dtype)
+    M = plan.empty_matrix(dtype)
+    fem.build_local_matrices(plan, dtype, K, M, None)
+    return plan, K, M, cuda(prob.b)
+
+
+@pytest.mark.parametrize("nu,dtype", [(0.0, fem.F64), (30.0, fem.F64), (30.0, fem.F32X2)])
+def test_jacobi_fcg_matches_oracle_pcg(nu, dtype):
+    prob = Problem(inputs.square_mesh(64), nu=nu, f="sine" if nu else None, seed=3)
+    plan, K, M, b = _gpu(prob, dtype)
+    x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+    info = fem.fcg_solve(plan, fem.fcg_opts(dtype=dtype, nu=nu, rtol=1e-8), None, K, M, b, x)
+    assert info["status"] == 0 and info["fell_back"] == -1 and info["precond_calls"] == 0
+    _, io = oracle.pcg(prob.n, prob.mesh.elems, prob.K, prob.M, nu, prob.b, prob.mask, np.zeros(prob.n), rtol=1e-8)
+    assert abs(info["iters"] - io["iters"]) <= max(2, 0.02 * io["iters"])
+    xs = x.cpu().numpy()
+    assert _true_relres(prob, xs) <= 1e-8
+    assert info["relres"] == pytest.approx(_true_relres(prob, xs), rel=1e-6)
+
+
+def test_fcg_with_network_converges_and_is_judged_by_true_residual():
+    N = 32
+    gp = learn.GridProblem.make(N, 12.5, 7)
+    net = fem.UNet(N, N, channels=16, seed=4)
+    x = torch.zeros(gp.n_nodes, dtype=torch.float64, device="cuda")
+    info = gp.fcg(net, x, rtol=1e-8, stall_iters=400)
+    assert info["status"] == 0
+    prob = Problem(inputs.square_mesh(N), nu=12.5, f="sine", seed=7)
+    assert _true_relres(prob, x.cpu().numpy()) <= 1e-8
+    assert info["precond_calls"] >= 1
+
+
+def test_fcg_hands_over_to_jacobi_pcg():
+    N = 32
+    gp = learn.GridProblem.make(N, 0.0, 9)
+    net = fem.UNet(N, N, channels=16, seed=4)
+    x = torch.zeros(gp.n_nodes, dtype=torch.float64, device="cuda")
+    info = gp.fcg(net, x, rtol=1e-8, stall_iters=1)
+    assert info["status"] == 0
+    assert info["fell_back"] >= 0 and info["fallback_reason"] in (1, 2, 3) and info["pcg_iters"] > 0
+    prob = Problem(inputs.square_mesh(N), nu=0.0, f="sine", seed=9)
+    rr = _true_relres(prob, x.cpu().numpy())
+    assert rr <= 1e-8
+    assert info["relres"] == pytest.approx(rr, rel=1e-3)
+
+
+def test_fcg_rejects_bad_grid():
+    prob = Problem(inputs.square_mesh(16), nu=1.0)
+    plan, K, M, b = _gpu(prob)
+    net = fem.UNet(32, 32)
+    x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(fem.FemError):
+        fem.fcg_solve(plan, fem.fcg_opts(nu=1.0, grid_n=32), net, K, M, b, x)
