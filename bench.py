@@ -231,6 +231,96 @@ def run_batched(args, w):
     print(json.dumps(out), flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per fused CG pass from the committed rocprofv3 counter summary, if it is current.
+
+    profiles/c2_hbm_counters.md carries a line `traffic: {json}` with the
+    element-pass source hash the counters were taken with and the calibrated
+    FETCH_SIZE + WRITE_SIZE bytes per pass (k_chunk_main + k_chunk_fixup of
+    the iteration); any change to those sources makes it stale (None).
+    """
+    from paper_1911_03973_amd.build import sources_hash
+
+    path = os.path.join(ROOT, "profiles", "c2_hbm_counters.md")
+    try:
+        with open(path) as f:
+            for line in f:
+                if line.startswith("traffic: "):
+                    rec = json.loads(line[len("traffic: "):])
+                    if rec.get("sources") == sources_hash():
+                        return rec
+    except (OSError, ValueError):
+        pass
+    return None
+
+
+def learned_fcg(args):
+    """Learned-preconditioner workload: 1024^2 squares, nu ~ U(0, 100), random-sine f, u = 0 on the boundary.
+
+    Training pairs come from the plain FP64 Jacobi-PCG solver (restarted segments
+    from x0 = 0, see paper_1911_03973_amd/learn.py); the network is trained with
+    the library's BF16 MFMA kernels; then every held-out problem is solved to a
+    true relative residual of 1e-8 by (a) Jacobi-PCG with FP32 element passes and
+    FP64 refinement (the optimized solver of the main workload) and (b) learned
+    FCG on the same FP32 hi/lo element matrices.  Training time is reported
+    separately from the solve times.
+    """
+    import numpy as np
+    import torch
+
+    from paper_1911_03973_amd import fem, learn
+
+    N = args.learned_n
+    segs = [int(v) for v in args.learned_segments.split(",")]
+    log(f"[bench] learned: pairs from {args.learned_problems} problems at {N}^2, segments {segs}")
+    t = time.perf_counter()
+    ins, tgs = learn.make_dataset(N, args.learned_problems, 100, segs)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t
+    net = fem.UNet(N, N, max_batch=args.learned_batch, channels=16, seed=0)
+    log(f"[bench] learned: {ins.shape[0]} pairs in {t_data:.1f} s; training {args.learned_steps} steps")
+    t = time.perf_counter()
+    hist = learn.train(net, ins, tgs, args.learned_steps, args.learned_batch, args.learned_lr,
+                       log_every=max(args.learned_steps // 5, 1))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t
+    n_pairs = int(ins.shape[0])
+    del ins, tgs
+    rows = []
+    for nu, seed in learn.problem_params(args.learned_eval, 5000):
+        gp = learn.GridProblem.make(N, nu, seed, dtype=fem.F32X2)
+        x = torch.zeros(gp.n_nodes, dtype=torch.float64, device="cuda")
+        gp.pcg(x)  # warm-up: workspace allocation
+        x.zero_()
+        a = gp.pcg(x)
+        x.zero_()
+        gp.fcg(net, x, max_iter=2)  # warm-up
+        x.zero_()
+        b = gp.fcg(net, x)
+        rows.append({"nu": round(nu, 3), "pcg_iters": a["iters"], "pcg_s": round(a["seconds"], 4),
+                     "pcg_relres": a["relres"], "fcg_iters": b["iters"], "fcg_pcg_iters": b["pcg_iters"],
+                     "fcg_fell_back": b["fell_back"], "fcg_s": round(b["seconds"], 4), "fcg_relres": b["relres"]})
+        log(f"[bench] learned: nu {nu:.2f} Jacobi-PCG {a['iters']} it {a['seconds']:.3f} s | "
+            f"learned FCG {b['iters']}+{b['pcg_iters']} it {b['seconds']:.3f} s")
+        del gp
+    t_pcg = float(np.median([r["pcg_s"] for r in rows]))
+    t_fcg = float(np.median([r["fcg_s"] for r in rows]))
+    return {
+        "workload": f"2D P1 {N}x{N} squares ({(N + 1) ** 2} nodes, {2 * N * N} triangles), nu~U(0,100), "
+                    "random-sine f, u=0 on the boundary; held-out problems",
+        "network": "U-Net 4 levels, 16-128 channels, BF16 MFMA / FP32 accumulation, 482753 parameters",
+        "preconditioner": "FCG(1), two-level cycle: 2 damped-Jacobi steps, network correction, 2 Jacobi steps",
+        "pairs": n_pairs,
+        "train_steps": args.learned_steps, "train_batch": args.learned_batch,
+        "train_loss_first": round(float(hist[:10].mean()), 4), "train_loss_last": round(float(hist[-20:].mean()), 4),
+        "data_s": round(t_data, 2), "train_s": round(t_train, 2),
+        "time_to_1e8_jacobi_pcg_s": round(t_pcg, 4), "time_to_1e8_learned_fcg_s": round(t_fcg, 4),
+        "speedup_vs_jacobi_pcg": round(t_pcg / t_fcg, 3),
+        "iters_jacobi_pcg": [r["pcg_iters"] for r in rows], "iters_learned_fcg": [r["fcg_iters"] for r in rows],
+        "problems": rows,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +342,14 @@ def main():
     ap.add_argument("--group", type=int, default=0, help="batched: chunks per work item (0 = per-problem schedule)")
     ap.add_argument("--items", type=int, default=32, help="batched: target work items per problem phase")
     ap.add_argument("--autotune", action="store_true", help="batched: pick the schedule with the autotuner first")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-FCG vs Jacobi-PCG comparison")
+    ap.add_argument("--learned-n", type=int, default=1024)
+    ap.add_argument("--learned-problems", type=int, default=16)
+    ap.add_argument("--learned-segments", default="10,10,20,20,40,40,80,80,160,160")
+    ap.add_argument("--learned-steps", type=int, default=600)
+    ap.add_argument("--learned-batch", type=int, default=4)
+    ap.add_argument("--learned-lr", type=float, default=2e-3)
+    ap.add_argument("--learned-eval", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs its hot path on a single MI355X "
@@ -324,6 +422,8 @@ def main():
     if args.max_iter < 200000:
         log("[bench] capped iterations: a profiling run, not a time-to-1e-8 measurement")
     resid = residual_kernels(fem, plan, mesh, K, M, w["nu"], dt, args.residual_calls)
+    rec = measured_traffic() if args.workload == "c2" and args.vectors == 0 and args.block == 0 else None
+    traffic = rec["bytes_per_pass"] if rec and rec.get("chunk_elems") == st["chunk_elems"] else None
     out = {
         "metric": METRIC,
         "value": round(gbs, 2),
@@ -351,7 +451,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
         },
         "elements_per_s": round(mesh.n_elems / avg_mv_s, 1),
         "matvec_us": round(avg_mv_s * 1e6, 2),
@@ -363,7 +463,7 @@ def main():
         "relres": [i["relres"] for i in infos],
         "converged": ok,
         "plan_seconds": round(t_plan, 3),
-        "learned_fcg": None,
+        "learned_fcg": None if args.no_learned else learned_fcg(args),
         "pass_kind": ("fused CG pass, packed difference form (%d values/elem, %s), %s vectors"
                       % (n_pk, "FP32 heads" if dt != fem.F64 else "FP64", "FP32" if s_v == 4 else "FP64")),
         "residual_kernels": resid,

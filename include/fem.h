@@ -263,6 +263,48 @@ int fem_batch_solve(fem_batch *batch, const fem_batch_opts *opts, const void *d_
                     double *seconds, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* The paper's iterations on the element residual (Section 2)                 */
+/* ------------------------------------------------------------------------ */
+typedef enum {
+    FEM_RICHARDSON = 0,         /* x += omega r, omega = 2 / (lam1 + lam2) (eq. (richardson)) */
+    FEM_CHEBYSHEV2 = 1,         /* x += r / alpha_{k mod N}, roots of the scaled Chebyshev
+                                   polynomial of degree N in the listing's order
+                                   (eq. (Czebyshev2lev)) */
+    FEM_CHEBYSHEV3 = 2,         /* three-level recurrence with C_{k+1} = 2 sigma C_k - C_{k-1}
+                                   (eqs. (recrCk), (Czebyshev3lev)); first step r0 / d */
+    FEM_CHEBYSHEV3_LISTING = 3  /* the alpha/beta form of the 3-level listing (its first
+                                   beta is (c alpha / 2)^2) */
+} fem_iteration;
+
+typedef struct {
+    int method;      /* fem_iteration */
+    int dtype;       /* storage of K_e / M_e */
+    double nu;
+    double lam1, lam2; /* spectral bounds 0 < lam1 < lam2 of the masked operator */
+    int cycle;       /* N of the 2-level method */
+    int iters;       /* number of iterations (no stopping test, as in Section 3) */
+} fem_iter_opts;
+
+typedef struct {
+    int status;
+    int iters;
+    double relres;   /* ||b - A x|| / ||b - A x0|| (masked, FP64) after the last step */
+    double r0;
+    double seconds;
+} fem_iter_info;
+
+void fem_iter_opts_default(fem_iter_opts *o);
+
+/* Runs opts->iters steps of the chosen iteration on (K + nu M) u = b with the
+ * Dirichlet rows masked (x holds the Dirichlet values, which stay fixed).
+ * Each step is one element residual (eq. (4), Algorithm 1, through the FP64
+ * packed difference form of A_e) and one vector update; the step sizes are
+ * formed on the host in FP64 from (lam1, lam2, N, k).  Allocates a workspace
+ * for the call; synchronises `stream`. */
+int fem_iterate(const fem_plan *plan, const fem_iter_opts *opts, const void *d_K_e, const void *d_M_e,
+                const double *d_b, double *d_x, fem_iter_info *info, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Learned preconditioner: a U-Net on the structured nodal grid, used as     */
 /* z = N(r) in flexible CG.  Section 3 notes that the iteration counts grow  */
 /* with the condition number on finer meshes, so the solvers need a          */
@@ -326,6 +368,12 @@ typedef struct {
     double cval;        /* constant second input channel of the network */
     int stall_iters;    /* hand over to Jacobi-PCG when ||r|| has not halved in this many iterations */
     int max_replace;    /* true-residual restarts allowed */
+    int smooth;         /* 0: z = N(r); k > 0: two-level cycle with the network as
+                           coarse correction: k damped-Jacobi steps
+                           z += omega D^-1 (r - A z) from z = 0, then
+                           z += s N(r - A z) with s = (n.rz)/(n.A n), then k
+                           more Jacobi steps (default 2) */
+    double omega;       /* Jacobi damping of the cycle, (0, 2) (default 2/3) */
 } fem_fcg_opts;
 
 typedef struct {
@@ -345,8 +393,9 @@ typedef struct {
 void fem_fcg_opts_default(fem_fcg_opts *o);
 
 /* Flexible CG (FCG(1)) for (K + nu M) u = b with the Dirichlet rows masked,
- * preconditioned by z = N(r) (net != NULL; the mesh must be the structured
- * 2D grid described at fem_unet_precondition) or by Jacobi (net == NULL).
+ * preconditioned by the network (net != NULL; the mesh must be the structured
+ * 2D grid described at fem_unet_precondition), alone or inside the two-level
+ * cycle of opts->smooth, or by Jacobi (net == NULL).
  * With a network, a non-finite or zero output, p.q <= 0, or stall_iters
  * iterations without halving ||r|| hand the current iterate over to the
  * Jacobi-PCG solver (fem_pcg_solve with opts->dtype), which finishes the

@@ -21,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["plan.cpp", "local.hip", "apply.hip", "pcg.hip", "batch.hip", "api.hip", "batch_api.hip", "unet.hip",
-           "fcg.hip"]
+           "fcg.hip", "iterate.hip"]
 
 COMMON = [
     "-O3",
@@ -38,6 +38,23 @@ HIP_FLAGS = [
     "-ffp-contract=fast",
     "-munsafe-fp-atomics",
 ]
+
+
+# Sources of the solver's element pass: a profile of that pass is current only
+# while these files are unchanged.
+ELEMENT_PASS_SOURCES = ("plan.h", "plan.cpp", "common.h", "chunk.h", "kernels.h", "solver.h", "pcg.hip")
+
+
+def sources_hash(names=ELEMENT_PASS_SOURCES) -> str:
+    """Short SHA-256 over the named csrc files (name and content, in the given order)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for n in names:
+        h.update(n.encode())
+        with open(os.path.join(CSRC, n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _compile(src: str, verbose: bool) -> str:

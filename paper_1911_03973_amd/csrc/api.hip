@@ -427,6 +427,45 @@ int fem_pcg_solve(const fem_plan *plan_c, const fem_solve_opts *o, const void *d
     return rc;
 }
 
+void fem_iter_opts_default(fem_iter_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->method = FEM_CHEBYSHEV3;
+    o->dtype = FEM_F64;
+    o->cycle = 1;
+}
+
+int fem_iterate(const fem_plan *plan_c, const fem_iter_opts *o, const void *d_K_e, const void *d_M_e,
+                const double *d_b, double *d_x, fem_iter_info *info, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (int rc = check_plan(plan_c)) return rc;
+    if (!o || !info) return set_error(FEM_EINVAL, "opts and info must not be NULL");
+    std::memset(info, 0, sizeof(*info));
+    if (o->method < FEM_RICHARDSON || o->method > FEM_CHEBYSHEV3_LISTING)
+        return set_error(FEM_EINVAL, "unknown iteration");
+    if (!valid_dtype(o->dtype)) return set_error(FEM_EINVAL, "unknown dtype");
+    if (!std::isfinite(o->nu) || o->nu < 0.0) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
+    if (!std::isfinite(o->lam1) || !std::isfinite(o->lam2) || !(o->lam1 > 0.0) || !(o->lam2 > o->lam1))
+        return set_error(FEM_EINVAL, "need finite bounds 0 < lam1 < lam2");
+    if (o->iters < 0) return set_error(FEM_EINVAL, "iters must be >= 0");
+    if (o->method == FEM_CHEBYSHEV2 && o->cycle < 1) return set_error(FEM_EINVAL, "cycle must be >= 1");
+    if ((!d_K_e && plan_c->dev.n_elems > 0) || !d_b || !d_x) return set_error(FEM_EINVAL, "NULL argument");
+    if (o->nu != 0.0 && !d_M_e) return set_error(FEM_EINVAL, "nu > 0 needs M_e");
+    if ((const void *)d_x == (const void *)d_b) return set_error(FEM_EINVAL, "x must not alias b");
+    hipStream_t s = S(stream);
+    fem::IterResult res;
+    int rc = fem::run_iteration(plan_c->dev, o->dtype, d_K_e, o->nu != 0.0 ? d_M_e : nullptr, o->nu, d_b, d_x,
+                                o->method, o->lam1, o->lam2, o->method == FEM_CHEBYSHEV2 ? o->cycle : 1, o->iters,
+                                res, s);
+    if (hipStreamSynchronize(s) != hipSuccess && rc == FEM_OK) rc = set_error(FEM_EHIP, "stream synchronisation failed");
+    info->status = rc;
+    info->iters = res.iters;
+    info->relres = res.relres;
+    info->r0 = res.r0;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
 void fem_fcg_opts_default(fem_fcg_opts *o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
@@ -435,6 +474,8 @@ void fem_fcg_opts_default(fem_fcg_opts *o) {
     o->max_iter = 100000;
     o->stall_iters = 50;
     o->max_replace = 8;
+    o->smooth = 2;
+    o->omega = 2.0 / 3.0;
 }
 
 int fem_fcg_solve(const fem_plan *plan_c, const fem_fcg_opts *o, fem_unet *net, const void *d_K_e,
@@ -450,6 +491,8 @@ int fem_fcg_solve(const fem_plan *plan_c, const fem_fcg_opts *o, fem_unet *net, 
     if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) return set_error(FEM_EINVAL, "rtol must be in (0, 1)");
     if (o->max_iter < 1) return set_error(FEM_EINVAL, "max_iter must be >= 1");
     if (o->stall_iters < 1 || o->max_replace < 0) return set_error(FEM_EINVAL, "stall_iters >= 1, max_replace >= 0");
+    if (o->smooth < 0 || o->smooth > 8 || !(o->omega > 0.0) || !(o->omega < 2.0))
+        return set_error(FEM_EINVAL, "smooth must be in [0, 8] and omega in (0, 2)");
     if ((!d_K_e && plan->dev.n_elems > 0) || !d_b || !d_x) return set_error(FEM_EINVAL, "NULL argument");
     if (o->nu != 0.0 && !d_M_e) return set_error(FEM_EINVAL, "nu > 0 needs M_e");
     if ((const void *)d_x == (const void *)d_b) return set_error(FEM_EINVAL, "x must not alias b");
@@ -466,7 +509,8 @@ int fem_fcg_solve(const fem_plan *plan_c, const fem_fcg_opts *o, fem_unet *net, 
     hipStream_t s = S(stream);
     fem::FcgResult res;
     int rc = fem::solve_fcg(plan->dev, o->dtype, d_K_e, o->nu != 0.0 ? d_M_e : nullptr, o->nu, d_b, d_x, o->rtol,
-                            o->max_iter, net, o->grid_n, o->cval, o->stall_iters, o->max_replace, res, s);
+                            o->max_iter, net, o->grid_n, o->cval, o->smooth, o->omega, o->stall_iters,
+                            o->max_replace, res, s);
     info->iters = res.iters;
     info->precond_calls = res.precond_calls;
     info->fell_back = res.fell_back;

@@ -10,6 +10,13 @@
 // The true residual judges convergence: when the recursive residual meets the
 // tolerance, r = b - A x is recomputed in FP64 and the iteration restarts
 // from it if the tolerance is not met.
+//
+// With a network and smooth > 0 the preconditioner is a two-level cycle in
+// which the network plays the coarse correction: `smooth` damped-Jacobi steps
+// z += omega D^-1 (r - A z) from z = 0, the network correction
+// z += s N(r - A z) with the energy-optimal s = (n . rz) / (n . A n), and
+// `smooth` more Jacobi steps.  The network is trained on smooth solver
+// residuals; the smoothing steps remove the rough components it has not seen.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,44 +28,11 @@
 #include "kernels.h"
 #include "solver.h"
 #include "unet.h"
+#include "vec.h"
 
 namespace fem {
 
 namespace {
-
-constexpr int kDotBlocks = 512;
-
-// partial[b][j] = sum over this block's rows of a_j[i] * b_j[i], j < NV
-template <int NV>
-__global__ __launch_bounds__(kBlock) void k_dots(int64_t n, const double *const *__restrict__ av,
-                                                 const double *const *__restrict__ bv, double *__restrict__ part) {
-    __shared__ double red[NV * kBlock / kWave];
-    double v[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] = 0.0;
-    const double *a[NV], *b[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        a[j] = av[j];
-        b[j] = bv[j];
-    }
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-#pragma unroll
-        for (int j = 0; j < NV; ++j) v[j] += a[j][i] * b[j][i];
-    block_sum_n<kBlock, NV>(v, red);
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int j = 0; j < NV; ++j) part[(int64_t)blockIdx.x * NV + j] = v[j];
-}
-
-// out[j] = sum_b part[b][j] in block order (one thread per j)
-__global__ void k_dots_fin(const double *__restrict__ part, int blocks, int nv, double *__restrict__ out) {
-    const int j = threadIdx.x;
-    if (j >= nv) return;
-    double s = 0.0;
-    for (int b = 0; b < blocks; ++b) s += part[(int64_t)b * nv + j];
-    out[j] = s;
-}
 
 __global__ void k_jacobi(int64_t n, const double *__restrict__ dinv, const double *__restrict__ r,
                          double *__restrict__ z) {
@@ -100,12 +74,43 @@ __global__ __launch_bounds__(kBlock) void k_step(int64_t n, double alpha, const 
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, kDotBlocks)); }
+// z = omega D^-1 r (first smoothing step from z = 0), or z += omega D^-1 rz
+__global__ void k_smooth(int64_t n, double omega, const double *__restrict__ dinv, const double *__restrict__ rz,
+                         double *__restrict__ z, int first) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const double v = omega * dinv[i] * rz[i];
+        z[i] = first ? v : z[i] + v;
+    }
+}
+
+// s = (n . rz) / (n . A n), 0 when the network output is zero or the ratio is not finite
+__global__ void k_coarse_scale(const double *__restrict__ part, int blocks, double *__restrict__ sc) {
+    if (threadIdx.x != 0) return;
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < blocks; ++k) {
+        a += part[2 * k];
+        b += part[2 * k + 1];
+    }
+    const double v = a / b;
+    sc[0] = (b > 0.0 && isfinite(v)) ? v : 0.0;
+}
+
+// z += s nz, rz -= s An
+__global__ void k_coarse_update(int64_t n, const double *__restrict__ sc, const double *__restrict__ nz,
+                                const double *__restrict__ An, double *__restrict__ z, double *__restrict__ rz) {
+    const double c = sc[0];
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        z[i] += c * nz[i];
+        rz[i] -= c * An[i];
+    }
+}
+
 
 struct FcgWork {
     void *arena = nullptr;
     double *A = nullptr, *d = nullptr, *dinv = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
-    double *scratch = nullptr, *part = nullptr, *sums = nullptr;
+    double *rz = nullptr, *nz = nullptr, *An = nullptr;  // two-level preconditioner vectors
+    double *scratch = nullptr, *part = nullptr, *sums = nullptr, *sc = nullptr;
     const double **ptrs = nullptr;  // device pointer tables of k_dots
     int *bad = nullptr;
     ~FcgWork() {
@@ -116,8 +121,8 @@ struct FcgWork {
 }  // namespace
 
 int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double nu, const double *b, double *x,
-              double rtol, int max_iter, fem_unet *net, int grid_n, double cval, int stall_iters, int max_replace,
-              FcgResult &res, hipStream_t s) {
+              double rtol, int max_iter, fem_unet *net, int grid_n, double cval, int smooth, double omega,
+              int stall_iters, int max_replace, FcgResult &res, hipStream_t s) {
     std::memset(&res, 0, sizeof(res));
     res.fell_back = -1;
     const int64_t n = P.n_nodes;
@@ -132,7 +137,7 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
     const size_t oA = take(npk * 8), od = take(n * 8), odi = take(n * 8), or_ = take(n * 8), oz = take(n * 8),
                  op = take(n * 8), oq = take(n * 8), osc = take(std::max<int64_t>(P.n_partials, 1) * 8),
                  opart = take((size_t)kDotBlocks * 4 * 8), osum = take(8 * 8), optr = take(16 * sizeof(void *)),
-                 obad = take(sizeof(int));
+                 obad = take(sizeof(int)), orz = take(n * 8), onz = take(n * 8), oAn = take(n * 8), osc2 = take(8);
     if (hipMalloc(&w.arena, off) != hipSuccess) {
         (void)hipGetLastError();
         return set_error(FEM_ENOMEM, "device allocation of the FCG workspace failed");
@@ -150,9 +155,14 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
     w.sums = reinterpret_cast<double *>(base + osum);
     w.ptrs = reinterpret_cast<const double **>(base + optr);
     w.bad = reinterpret_cast<int *>(base + obad);
+    w.rz = reinterpret_cast<double *>(base + orz);
+    w.nz = reinterpret_cast<double *>(base + onz);
+    w.An = reinterpret_cast<double *>(base + oAn);
+    w.sc = reinterpret_cast<double *>(base + osc2);
 
     // pointer tables: [0..2] (z, z, z) x (r, z, q); [3..4] (p, p) x (q, r)
-    const double *tab[16] = {w.z, w.z, w.z, w.r, w.z, w.q, w.p, w.p, w.q, w.r};
+    // [10..11] (nz, nz) x (rz, An)
+    const double *tab[16] = {w.z, w.z, w.z, w.r, w.z, w.q, w.p, w.p, w.q, w.r, w.nz, w.nz, w.rz, w.An};
     FEM_HIP_CHECK(hipMemcpyAsync(w.ptrs, tab, sizeof(tab), hipMemcpyHostToDevice, s));
     FEM_HIP_CHECK(hipMemsetAsync(w.bad, 0, sizeof(int), s));
     if (int rc = launch_pack(P, dtype, K, M, nu, MAT_F64, w.A, s)) return rc;
@@ -198,9 +208,33 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
     for (int it = 0; it < max_iter; ++it) {
         // z = N(r) or D^-1 r; then (z.r, z.z, z.q_prev)
         bool net_ok = use_net;
-        if (use_net) {
+        if (use_net && smooth == 0) {
             if (int rc = unet_grid_precondition(net, grid_n, w.r, cval, P.mask, w.z, s)) return rc;
             res.precond_calls += 1;
+        } else if (use_net) {
+            // pre-smoothing: z = omega D^-1 r, then (smooth - 1) steps on rz = r - A z
+            k_smooth<<<gv, kBlock, 0, s>>>(n, omega, w.dinv, w.r, w.z, 1);
+            for (int k = 1; k < smooth; ++k) {
+                if (int rc = launch_apply_pk64(P, MAT_F64, w.A, w.z, w.r, w.rz, -1.0, 1, w.scratch, s)) return rc;
+                k_smooth<<<gv, kBlock, 0, s>>>(n, omega, w.dinv, w.rz, w.z, 0);
+            }
+            if (int rc = launch_apply_pk64(P, MAT_F64, w.A, w.z, w.r, w.rz, -1.0, 1, w.scratch, s)) return rc;
+            // coarse correction by the network
+            if (int rc = unet_grid_precondition(net, grid_n, w.rz, cval, P.mask, w.nz, s)) return rc;
+            res.precond_calls += 1;
+            if (int rc = launch_apply_pk64(P, MAT_F64, w.A, w.nz, nullptr, w.An, 1.0, 1, w.scratch, s)) return rc;
+            k_dots<2><<<gv, kBlock, 0, s>>>(n, w.ptrs + 10, w.ptrs + 12, w.part);
+            k_coarse_scale<<<1, 64, 0, s>>>(w.part, gv, w.sc);
+            k_coarse_update<<<gv, kBlock, 0, s>>>(n, w.sc, w.nz, w.An, w.z, w.rz);
+            // post-smoothing
+            for (int k = 0; k < smooth; ++k) {
+                if (k > 0) {
+                    if (int rc = launch_apply_pk64(P, MAT_F64, w.A, w.z, w.r, w.rz, -1.0, 1, w.scratch, s))
+                        return rc;
+                }
+                k_smooth<<<gv, kBlock, 0, s>>>(n, omega, w.dinv, w.rz, w.z, 0);
+            }
+            FEM_HIP_CHECK(hipGetLastError());
         } else {
             k_jacobi<<<gv, kBlock, 0, s>>>(n, w.dinv, w.r, w.z);
         }

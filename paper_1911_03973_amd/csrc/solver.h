@@ -115,8 +115,17 @@ struct FcgResult {
     double relres, r0, rnorm;
 };
 constexpr int kFcgHandover = 1;
+
+// The paper's iterations (iterate.hip); numbering as fem_iteration in fem.h.
+enum IterMethod { ITER_RICHARDSON = 0, ITER_CHEB2 = 1, ITER_CHEB3 = 2, ITER_CHEB3_LISTING = 3 };
+struct IterResult {
+    int iters;
+    double r0, relres;
+};
+int run_iteration(const DevPlan &P, int dtype, const void *K, const void *M, double nu, const double *b, double *x,
+                  int method, double lam1, double lam2, int cycle, int iters, IterResult &res, hipStream_t s);
 int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double nu, const double *b, double *x,
-              double rtol, int max_iter, fem_unet *net, int grid_n, double cval, int stall_iters, int max_replace,
-              FcgResult &res, hipStream_t s);
+              double rtol, int max_iter, fem_unet *net, int grid_n, double cval, int smooth, double omega,
+              int stall_iters, int max_replace, FcgResult &res, hipStream_t s);
 
 }  // namespace fem

@@ -90,7 +90,7 @@ class FcgOpts(ctypes.Structure):
     _fields_ = [
         ("dtype", ctypes.c_int), ("nu", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int),
         ("grid_n", ctypes.c_int), ("cval", ctypes.c_double), ("stall_iters", ctypes.c_int),
-        ("max_replace", ctypes.c_int),
+        ("max_replace", ctypes.c_int), ("smooth", ctypes.c_int), ("omega", ctypes.c_double),
     ]
 
 
@@ -102,6 +102,22 @@ class FcgInfo(ctypes.Structure):
         ("seconds", ctypes.c_double),
     ]
 
+
+class IterOpts(ctypes.Structure):
+    _fields_ = [
+        ("method", ctypes.c_int), ("dtype", ctypes.c_int), ("nu", ctypes.c_double), ("lam1", ctypes.c_double),
+        ("lam2", ctypes.c_double), ("cycle", ctypes.c_int), ("iters", ctypes.c_int),
+    ]
+
+
+class IterInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int), ("iters", ctypes.c_int), ("relres", ctypes.c_double), ("r0", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+    ]
+
+
+RICHARDSON, CHEBYSHEV2, CHEBYSHEV3, CHEBYSHEV3_LISTING = 0, 1, 2, 3
 
 _vp, _i64, _int, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
 _SIGS = {
@@ -133,6 +149,7 @@ _SIGS = {
     "fem_unet_train_step": [_vp, _int, _vp, _vp, ctypes.c_float, _vp, _vp],
     "fem_unet_precondition": [_vp, _int, _vp, _dbl, _vp, _vp, _vp],
     "fem_fcg_solve": [_vp, ctypes.POINTER(FcgOpts), _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(FcgInfo), _vp],
+    "fem_iterate": [_vp, ctypes.POINTER(IterOpts), _vp, _vp, _vp, _vp, ctypes.POINTER(IterInfo), _vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -146,9 +163,11 @@ _lib.fem_batch_opts_default.argtypes = [ctypes.POINTER(BatchOpts)]
 _lib.fem_batch_opts_default.restype = None
 _lib.fem_fcg_opts_default.argtypes = [ctypes.POINTER(FcgOpts)]
 _lib.fem_fcg_opts_default.restype = None
+_lib.fem_iter_opts_default.argtypes = [ctypes.POINTER(IterOpts)]
+_lib.fem_iter_opts_default.restype = None
 
 EXPORTED = sorted(list(_SIGS) + ["fem_last_error", "fem_solve_opts_default", "fem_batch_opts_default",
-                                 "fem_fcg_opts_default"])
+                                 "fem_fcg_opts_default", "fem_iter_opts_default"])
 
 
 def library():
@@ -540,4 +559,30 @@ def fcg_solve(plan, opts, net, K, M, b, x, stream=None, allow=(FEM_ENOCONV,)):
     info = FcgInfo()
     _check(_lib.fem_fcg_solve(plan.handle, ctypes.byref(opts), net.handle if net is not None else None, _ptr(K),
                               _ptr(M), _ptr(b), _ptr(x), ctypes.byref(info), _stream(stream)), allow=allow)
+    return {k: getattr(info, k) for k, _ in info._fields_}
+
+
+# ---------------------------------------------------------------------------
+# The paper's iterations (Richardson, 2- and 3-level Chebyshev)
+# ---------------------------------------------------------------------------
+
+def iter_opts(**kw):
+    o = IterOpts()
+    _lib.fem_iter_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def iterate(plan, opts, K, M, b, x, stream=None):
+    """Runs fem_iterate (opts.iters steps, x updated in place); returns the info dict."""
+    plan._mat(K, opts.dtype, "K_e")
+    plan._mat(M, opts.dtype, "M_e")
+    _need(b, torch.float64, plan.n_nodes, "b")
+    _need(x, torch.float64, plan.n_nodes, "x")
+    info = IterInfo()
+    _check(_lib.fem_iterate(plan.handle, ctypes.byref(opts), _ptr(K), _ptr(M), _ptr(b), _ptr(x), ctypes.byref(info),
+                            _stream(stream)))
     return {k: getattr(info, k) for k, _ in info._fields_}

@@ -12,6 +12,13 @@ target is e_k scaled to unit RMS.  Flexible CG only uses the direction of
 z = N(r) (its step length is re-optimised every iteration), so the scale of
 the error is not learned.
 
+Inside the two-level cycle of fem_fcg_solve (opts.smooth = k > 0) the network
+sees the residual left after k damped-Jacobi steps.  snapshot_pairs(smooth=k)
+can pass the pairs through the same steps first (z = the k-step Jacobi
+approximation of A^-1 r_k, input r_k - A z, target e_k - z); measured on 64^2
+and 128^2 grids this does not beat training on the raw pairs, which stay the
+default.
+
 All solver and network arithmetic runs in libfem's kernels; torch only moves
 the nodal vectors into the image layout of the training batches.
 """
@@ -61,6 +68,24 @@ class GridProblem:
     def n_nodes(self):
         return (self.N + 1) ** 2
 
+    def dinv(self):
+        if getattr(self, "_dinv", None) is None:
+            d = self.plan.empty_vector()
+            fem.jacobi_diag(self.plan, self.dtype, self.K, self.M, self.nu, d)
+            self._dinv = torch.where(self.mask.bool(), torch.zeros_like(d), 1.0 / d)
+        return self._dinv
+
+    def presmooth(self, r, steps, omega):
+        """(z, r - A z) after `steps` damped-Jacobi steps z += omega D^-1 (r - A z) from z = 0."""
+        dinv = self.dinv()
+        z = omega * dinv * r
+        rz = self.plan.empty_vector()
+        fem.element_residual(self.plan, self.dtype, self.K, self.M, self.nu, r, z, rz, mask=True)
+        for _ in range(steps - 1):
+            z = z + omega * dinv * rz
+            fem.element_residual(self.plan, self.dtype, self.K, self.M, self.nu, r, z, rz, mask=True)
+        return z, rz
+
     def residual(self, x, r=None):
         r = self.plan.empty_vector() if r is None else r
         fem.element_residual(self.plan, self.dtype, self.K, self.M, self.nu, self.b, x, r, mask=True)
@@ -86,8 +111,9 @@ def interior_image(v, N):
     return img
 
 
-def snapshot_pairs(prob, segments, u_star=None):
-    """(inputs [S, N, N, 2], targets [S, N, N]) from restarted Jacobi-PCG segments of the given lengths."""
+def snapshot_pairs(prob, segments, u_star=None, smooth=0, omega=2.0 / 3.0):
+    """(inputs [S, N, N, 2], targets [S, N, N]) from restarted Jacobi-PCG segments of the given lengths,
+    pre-smoothed by `smooth` damped-Jacobi steps (0: the raw pairs)."""
     N = prob.N
     if u_star is None:
         u_star = torch.zeros(prob.n_nodes, dtype=torch.float64, device="cuda")
@@ -99,7 +125,10 @@ def snapshot_pairs(prob, segments, u_star=None):
         prob.pcg(x, max_iter=int(k), rtol=1e-12)
         prob.residual(x, r)
         e = u_star - x
-        if float(torch.linalg.vector_norm(e)) == 0.0:
+        if smooth:
+            z, r = prob.presmooth(r, smooth, omega)
+            e = e - z
+        if float(torch.linalg.vector_norm(e)) == 0.0 or float(torch.linalg.vector_norm(r)) == 0.0:
             break
         img = torch.empty((N, N, 2), dtype=torch.float32, device="cuda")
         img[..., 0] = interior_image(r, N)
@@ -115,11 +144,11 @@ def problem_params(count, base_seed, nu_max=100.0):
     return [(float(rng.uniform(0.0, nu_max)), base_seed + 1 + i) for i in range(count)]
 
 
-def make_dataset(N, count, base_seed, segments, dtype=fem.F64):
+def make_dataset(N, count, base_seed, segments, dtype=fem.F64, smooth=0, omega=2.0 / 3.0):
     ins, tgs = [], []
     for nu, seed in problem_params(count, base_seed):
         prob = GridProblem.make(N, nu, seed, dtype)
-        a, t = snapshot_pairs(prob, segments)
+        a, t = snapshot_pairs(prob, segments, smooth=smooth, omega=omega)
         ins.append(a)
         tgs.append(t)
         del prob
