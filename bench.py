@@ -294,14 +294,19 @@ def learned_fcg(args):
         x.zero_()
         a = gp.pcg(x)
         x.zero_()
-        gp.fcg(net, x, max_iter=2)  # warm-up
+        gp.fcg(net, x, max_iter=2, smooth=args.learned_smooth)  # warm-up
         x.zero_()
-        b = gp.fcg(net, x)
+        b = gp.fcg(net, x, smooth=args.learned_smooth)
+        x.zero_()
+        c = gp.fcg(net, x, smooth=args.learned_smooth, stall_iters=1 << 30, max_iter=args.learned_max_iter)
         rows.append({"nu": round(nu, 3), "pcg_iters": a["iters"], "pcg_s": round(a["seconds"], 4),
                      "pcg_relres": a["relres"], "fcg_iters": b["iters"], "fcg_pcg_iters": b["pcg_iters"],
-                     "fcg_fell_back": b["fell_back"], "fcg_s": round(b["seconds"], 4), "fcg_relres": b["relres"]})
+                     "fcg_fell_back": b["fell_back"], "fcg_s": round(b["seconds"], 4), "fcg_relres": b["relres"],
+                     "fcg_no_handover_iters": c["iters"], "fcg_no_handover_s": round(c["seconds"], 4),
+                     "fcg_no_handover_status": c["status"], "fcg_no_handover_relres": c["relres"]})
         log(f"[bench] learned: nu {nu:.2f} Jacobi-PCG {a['iters']} it {a['seconds']:.3f} s | "
-            f"learned FCG {b['iters']}+{b['pcg_iters']} it {b['seconds']:.3f} s")
+            f"learned FCG {b['iters']}+{b['pcg_iters']} it {b['seconds']:.3f} s | "
+            f"without hand-over {c['iters']} it {c['seconds']:.3f} s")
         del gp
     t_pcg = float(np.median([r["pcg_s"] for r in rows]))
     t_fcg = float(np.median([r["fcg_s"] for r in rows]))
@@ -309,14 +314,19 @@ def learned_fcg(args):
         "workload": f"2D P1 {N}x{N} squares ({(N + 1) ** 2} nodes, {2 * N * N} triangles), nu~U(0,100), "
                     "random-sine f, u=0 on the boundary; held-out problems",
         "network": "U-Net 4 levels, 16-128 channels, BF16 MFMA / FP32 accumulation, 482753 parameters",
-        "preconditioner": "FCG(1), two-level cycle: 2 damped-Jacobi steps, network correction, 2 Jacobi steps",
+        "preconditioner": f"FCG(1), two-level cycle: {args.learned_smooth} damped-Jacobi steps (omega 2/3), network "
+                          f"correction, {args.learned_smooth} Jacobi steps; hand-over to Jacobi-PCG after 50 "
+                          "iterations without halving ||r||",
         "pairs": n_pairs,
         "train_steps": args.learned_steps, "train_batch": args.learned_batch,
         "train_loss_first": round(float(hist[:10].mean()), 4), "train_loss_last": round(float(hist[-20:].mean()), 4),
         "data_s": round(t_data, 2), "train_s": round(t_train, 2),
         "time_to_1e8_jacobi_pcg_s": round(t_pcg, 4), "time_to_1e8_learned_fcg_s": round(t_fcg, 4),
         "speedup_vs_jacobi_pcg": round(t_pcg / t_fcg, 3),
-        "iters_jacobi_pcg": [r["pcg_iters"] for r in rows], "iters_learned_fcg": [r["fcg_iters"] for r in rows],
+        "iters_jacobi_pcg": [r["pcg_iters"] for r in rows],
+        "iters_learned_fcg": [r["fcg_iters"] + r["fcg_pcg_iters"] for r in rows],
+        "iters_learned_fcg_no_handover": [r["fcg_no_handover_iters"] for r in rows],
+        "time_to_1e8_learned_fcg_no_handover_s": round(float(np.median([r["fcg_no_handover_s"] for r in rows])), 4),
         "problems": rows,
     }
 
@@ -344,9 +354,11 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="batched: pick the schedule with the autotuner first")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-FCG vs Jacobi-PCG comparison")
     ap.add_argument("--learned-n", type=int, default=1024)
-    ap.add_argument("--learned-problems", type=int, default=16)
+    ap.add_argument("--learned-problems", type=int, default=24)
     ap.add_argument("--learned-segments", default="10,10,20,20,40,40,80,80,160,160")
-    ap.add_argument("--learned-steps", type=int, default=600)
+    ap.add_argument("--learned-steps", type=int, default=1000)
+    ap.add_argument("--learned-smooth", type=int, default=4)
+    ap.add_argument("--learned-max-iter", type=int, default=4000)
     ap.add_argument("--learned-batch", type=int, default=4)
     ap.add_argument("--learned-lr", type=float, default=2e-3)
     ap.add_argument("--learned-eval", type=int, default=3)

@@ -372,7 +372,7 @@ typedef struct {
                            coarse correction: k damped-Jacobi steps
                            z += omega D^-1 (r - A z) from z = 0, then
                            z += s N(r - A z) with s = (n.rz)/(n.A n), then k
-                           more Jacobi steps (default 2) */
+                           more Jacobi steps (default 4) */
     double omega;       /* Jacobi damping of the cycle, (0, 2) (default 2/3) */
 } fem_fcg_opts;
 

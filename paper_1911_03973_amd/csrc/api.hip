@@ -474,7 +474,7 @@ void fem_fcg_opts_default(fem_fcg_opts *o) {
     o->max_iter = 100000;
     o->stall_iters = 50;
     o->max_replace = 8;
-    o->smooth = 2;
+    o->smooth = 4;
     o->omega = 2.0 / 3.0;
 }
 
