@@ -85,7 +85,8 @@ int alloc_work(fem_plan *plan, int slot, int dtype) {
     size_t opart64 = L.add(std::max<int64_t>(P.n_partials, 1) * sizeof(double));
     size_t opartv = L.add(std::max<int64_t>(P.n_partials, 1) * sizeof(double));
     size_t odots = L.add((size_t)8 * npart * sizeof(double));
-    size_t oshared = L.add((size_t)5 * std::max<int64_t>(P.n_shared, 1) * sizeof(double));
+    size_t oxl = L.add(n * sizeof(double));
+    size_t operm = L.add(n * sizeof(int32_t));
     size_t oupd = L.add((size_t)3 * 1024 * sizeof(double));
     size_t ost = L.add(sizeof(fem::IterState));
     size_t obad = L.add(sizeof(int));
@@ -109,7 +110,8 @@ int alloc_work(fem_plan *plan, int slot, int dtype) {
     w.part64 = reinterpret_cast<double *>(b + opart64);
     w.partv = b + opartv;
     w.dots = reinterpret_cast<double *>(b + odots);
-    w.shared = b + oshared;
+    w.xl = b + oxl;
+    w.perm = reinterpret_cast<int32_t *>(b + operm);
     w.upd = reinterpret_cast<double *>(b + oupd);
     w.st = reinterpret_cast<fem::IterState *>(b + ost);
     w.bad = reinterpret_cast<int *>(b + obad);
@@ -189,6 +191,7 @@ int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_c
     const size_t o_fo = L.add(H.fix_off.size() * sizeof(int32_t));
     const size_t o_fp = L.add(H.fix_parts.size() * sizeof(int32_t));
     const size_t o_po = L.add(H.part_owner.size() * sizeof(int32_t));
+    const size_t o_co = L.add(H.comp_off.size() * sizeof(int32_t));
     const size_t o_mask = L.add(H.mask.size());
     const size_t o_s64 = L.add(std::max<int64_t>(H.n_partials, 1) * sizeof(double));
     const size_t o_s32 = L.add(std::max<int64_t>(H.n_partials, 1) * sizeof(float));
@@ -216,6 +219,7 @@ int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_c
     bad |= up(o_fo, H.fix_off.data(), H.fix_off.size() * sizeof(int32_t));
     bad |= up(o_fp, H.fix_parts.data(), H.fix_parts.size() * sizeof(int32_t));
     bad |= up(o_po, H.part_owner.data(), H.part_owner.size() * sizeof(int32_t));
+    bad |= up(o_co, H.comp_off.data(), H.comp_off.size() * sizeof(int32_t));
     bad |= up(o_mask, H.mask.data(), H.mask.size());
     if (bad || hipStreamSynchronize(s) != hipSuccess) {
         (void)hipGetLastError();
@@ -244,6 +248,7 @@ int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_c
     D.fix_off = reinterpret_cast<const int32_t *>(b + o_fo);
     D.fix_parts = reinterpret_cast<const int32_t *>(b + o_fp);
     D.part_owner = reinterpret_cast<const int32_t *>(b + o_po);
+    D.comp_off = reinterpret_cast<const int32_t *>(b + o_co);
     D.mask = reinterpret_cast<const uint8_t *>(b + o_mask);
     plan->scratch64 = reinterpret_cast<double *>(b + o_s64);
     plan->scratch32 = reinterpret_cast<float *>(b + o_s32);
@@ -301,7 +306,8 @@ int fem_plan_check_host(int dim, int64_t n_nodes, int64_t n_elems, const double 
     out->n_partials = H.n_partials;
     out->index_bytes = (int64_t)(H.chunk_node_off.size() * 4 + H.chunk_info.size() * 4 + H.loc_nodes.size() * 4 +
                                  H.loc_end.size() * 2 + H.slots.size() * 2 + H.fix_nodes.size() * 4 +
-                                 H.fix_off.size() * 4 + H.fix_parts.size() * 8 + H.mask.size());
+                                 H.fix_off.size() * 4 + H.fix_parts.size() * 8 + H.comp_off.size() * 4 +
+                                 H.mask.size());
     return FEM_OK;
 }
 

@@ -16,6 +16,7 @@ namespace {
 // out = (b ? b : 0) + sign * acc, zeroed on Dirichlet nodes if use_mask.
 template <class T>
 struct OpAffine {
+    static constexpr bool kLocal = false;
     const T *x;
     const T *b;
     T *out;

@@ -115,6 +115,7 @@ __device__ bool phase_done(const BatchArgs &a, int p, int n_items, int *s_last) 
 
 // ---- element-pass policies ------------------------------------------------
 struct BOpIter {  // iteration round (see OpIter in pcg.hip)
+    static constexpr bool kLocal = false;
     double *x, *r, *p, *q;
     const double *dinv;
     double *sx, *sr, *sp, *sq;
@@ -189,6 +190,7 @@ struct BOpIter {  // iteration round (see OpIter in pcg.hip)
 };
 
 struct BOpRefresh {  // refresh round: pending step on x, then r = b - A x
+    static constexpr bool kLocal = false;
     double *x, *r;
     const double *p, *dinv, *b;
     double *sx, *sr;

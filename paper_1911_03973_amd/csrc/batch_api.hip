@@ -310,6 +310,7 @@ int fem_batch_create(int dim, int n_problems, const int64_t *node_off, const int
     D.fix_off = reinterpret_cast<const int32_t *>(b + o_fo);
     D.fix_parts = reinterpret_cast<const int32_t *>(b + o_fp);
     D.part_owner = reinterpret_cast<const int32_t *>(b + o_po);
+    D.comp_off = nullptr;
     D.mask = reinterpret_cast<const uint8_t *>(b + o_mask);
     B->pchunk0 = reinterpret_cast<int32_t *>(b + o_pc);
     B->pshared0 = reinterpret_cast<int32_t *>(b + o_ps);

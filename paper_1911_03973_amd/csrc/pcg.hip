@@ -26,6 +26,16 @@
 // iterations.  Once the device has raised its flag, the kernels still queued
 // return at once.
 //
+// The iteration vectors live in a solver-local node order: the complete
+// nodes of chunk 0, 1, ... (each chunk's block contiguous, in the order of
+// its node list), then the shared nodes in shared-node order (DevPlan::
+// comp_off).  The element pass then reads and writes each chunk's nodes as
+// one contiguous run instead of scattered row segments of the mesh
+// numbering, and the shared nodes form the compact tail that the fix-up
+// streams.  The caller's x and the FP64 residual refreshes stay in mesh order;
+// x is gathered into the local order at the start and scattered back at
+// every refresh and at the end.
+//
 // The operator is stored in the packed symmetric difference form (chunk.h,
 // LdPk): FP64 values for the FP64 solver, or FP32 hi/lo pairs for the mixed
 // solver, whose iterations read only the FP32 heads.  Every refresh (reliable
@@ -68,13 +78,13 @@ struct Step {
     }
 };
 
-// The element pass of one CG iteration.  Complete nodes (in one chunk only)
-// live in the full vectors; shared nodes live, during the iterations, in
-// compact arrays indexed by the shared-node number, so the fix-up streams
-// them contiguously instead of gathering scattered cache lines.  A Dirichlet
-// node is recognised by D^{-1} = 0.
+// The element pass of one CG iteration on solver-local vectors: complete
+// nodes by their local index, shared nodes through the tail pointers
+// (sx = x + n_complete, ...) by their shared-node number.  A Dirichlet node is
+// recognised by D^{-1} = 0.
 template <class VT>
 struct OpIter {
+    static constexpr bool kLocal = true;
     VT *x, *r, *p, *q;
     const VT *dinv;
     VT *sx, *sr, *sp, *sq;
@@ -173,24 +183,39 @@ struct OpIter {
     }
 };
 
-// Shared-node values between the full vectors and the compact arrays.
+// perm[local] = mesh node id: complete nodes chunk by chunk, then shared nodes
+__global__ __launch_bounds__(kBlock) void k_perm_complete(const DevPlan P, int32_t *__restrict__ perm) {
+    for (int64_t c = blockIdx.x; c < P.n_chunks; c += gridDim.x) {
+        const int nb0 = P.chunk_node_off[c], ncomp = P.chunk_info[2 * c], off = P.comp_off[c];
+        for (int k = threadIdx.x; k < ncomp; k += kBlock) perm[off + k] = P.loc_nodes[nb0 + k];
+    }
+}
+__global__ __launch_bounds__(kBlock) void k_perm_shared(const DevPlan P, int32_t *__restrict__ perm) {
+    const int64_t nc = P.comp_off[P.n_chunks];
+    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < P.n_shared; s += (int64_t)gridDim.x * kBlock)
+        perm[nc + s] = P.fix_nodes[s];
+}
+
+// dst[i] = src[perm[i]] (mesh order -> local order)
 template <class VT>
-__global__ __launch_bounds__(kBlock) void k_shared_copy(int64_t n_shared, const int32_t *__restrict__ nodes, VT *x,
-                                                        VT *r, VT *p, VT *q, const VT *dinv, VT *sx, VT *sr, VT *sp,
-                                                        VT *sq, VT *sd, int to_compact) {
-    for (int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x; s < n_shared; s += (int64_t)gridDim.x * kBlock) {
-        const int g = nodes[s];
-        if (to_compact) {
-            sx[s] = x[g];
-            sr[s] = r[g];
-            sp[s] = p[g];
-            sq[s] = q[g];
-            sd[s] = dinv[g];
+__global__ __launch_bounds__(kBlock) void k_gather_perm(int64_t n, const int32_t *__restrict__ perm,
+                                                        const double *__restrict__ src, VT *__restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        dst[i] = (VT)src[perm[i]];
+}
+
+// Local x back to the caller's x64: copy (FP64 vectors) or add and clear the
+// FP32 correction (FP32 vectors).
+template <class VT>
+__global__ __launch_bounds__(kBlock) void k_scatter_x(int64_t n, const int32_t *__restrict__ perm,
+                                                      VT *__restrict__ xl, double *__restrict__ x64, int fold) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const int g = perm[i];
+        if (fold) {
+            x64[g] += (double)xl[i];
+            xl[i] = (VT)0;
         } else {
-            x[g] = sx[s];
-            r[g] = sr[s];
-            p[g] = sp[s];
-            q[g] = sq[s];
+            x64[g] = (double)xl[i];
         }
     }
 }
@@ -257,14 +282,16 @@ __global__ __launch_bounds__(kBlock) void k_pending(int64_t n, VT *__restrict__ 
     }
 }
 
-// r (VT) = r64, per-block partials of r.D r, r.r (VT values) and r64.r64.
+// r (VT, local order) = r64 (mesh order), per-block partials of r.D r, r.r
+// (VT values) and r64.r64.
 template <class VT>
 __global__ __launch_bounds__(kBlock) void k_init_dots(int64_t n, VT *__restrict__ r, const VT *__restrict__ dinv,
-                                                      const double *__restrict__ r64, double *__restrict__ upd) {
+                                                      const double *__restrict__ r64, const int32_t *__restrict__ perm,
+                                                      double *__restrict__ upd) {
     __shared__ double red[kBlock / kWave];
     double srz = 0.0, srr = 0.0, s64 = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        const double v = r64[i];
+        const double v = r64[perm[i]];
         s64 += v * v;
         const VT ri = (VT)v;
         r[i] = ri;
@@ -309,26 +336,20 @@ __global__ __launch_bounds__(kBlock) void k_refresh_state(IterState *st, const d
     }
 }
 
+// D^{-1} in local order (0 on Dirichlet nodes)
 template <class VT>
 __global__ __launch_bounds__(kBlock) void k_dinv(int64_t n, const double *__restrict__ d,
-                                                 const uint8_t *__restrict__ mask, VT *__restrict__ dinv, int jacobi,
-                                                 int *__restrict__ bad) {
+                                                 const uint8_t *__restrict__ mask, const int32_t *__restrict__ perm,
+                                                 VT *__restrict__ dinv, int jacobi, int *__restrict__ bad) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const int g = perm[i];
         VT v;
-        if (mask[i]) v = (VT)0;
+        if (mask[g]) v = (VT)0;
         else {
-            if (!(d[i] > 0.0)) *bad = 1;  // every writer stores the same value
-            v = jacobi ? (VT)(1.0 / d[i]) : (VT)1;
+            if (!(d[g] > 0.0)) *bad = 1;  // every writer stores the same value
+            v = jacobi ? (VT)(1.0 / d[g]) : (VT)1;
         }
         dinv[i] = v;
-    }
-}
-
-// x64 += xc, xc = 0
-__global__ __launch_bounds__(kBlock) void k_fold(int64_t n, double *__restrict__ x, float *__restrict__ xc) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        x[i] += (double)xc[i];
-        xc[i] = 0.0f;
     }
 }
 
@@ -384,7 +405,8 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, const double *b, double
            double delta, int max_outer, int check_every, int profile, fem_solve_info *info, hipStream_t s) {
     const bool fold = std::is_same<VT, float>::value;  // FP32 vectors: x is an FP32 correction
     const int64_t n = P.n_nodes;
-    VT *xv = fold ? reinterpret_cast<VT *>(w.xc) : reinterpret_cast<VT *>(x64);
+    const int64_t nc = n - P.n_shared;  // complete nodes; the shared ones are the tail
+    VT *xv = fold ? reinterpret_cast<VT *>(w.xc) : reinterpret_cast<VT *>(w.xl);
     VT *r = reinterpret_cast<VT *>(w.r), *p = reinterpret_cast<VT *>(w.p), *q = reinterpret_cast<VT *>(w.q);
     const VT *dinv = reinterpret_cast<const VT *>(w.dinv);
     VT *partv = reinterpret_cast<VT *>(w.partv);
@@ -395,34 +417,25 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, const double *b, double
     const int gu = (int)std::max<int64_t>(1, std::min<int64_t>((n + 4 * kBlock - 1) / (4 * kBlock), 1024));
     const int gv = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 4096));
     LdPk<NB, MK> ld{w.Apk, P.n_elems};
-    VT *sv = reinterpret_cast<VT *>(w.shared);
-    const int64_t ns = std::max<int64_t>(P.n_shared, 1);
-    VT *sx = sv, *sr = sv + ns, *sp = sv + 2 * ns, *sq = sv + 3 * ns, *sd = sv + 4 * ns;
+    VT *sx = xv + nc, *sr = r + nc, *sp = p + nc, *sq = q + nc;
+    const VT *sd = dinv + nc;
     OpIter<VT> op{xv, r, p, q, dinv, sx, sr, sp, sq, sd, w.st, w.dots, npart, 0, 0.0, 0.0, {0, 0, 0, 0, 0, 0, 0}};
-    const int gs = (int)std::max<int64_t>(1, std::min<int64_t>((P.n_shared + kBlock - 1) / kBlock, 4096));
-    auto shared_copy = [&](int to_compact) {
-        if (P.n_shared > 0)
-            k_shared_copy<VT><<<gs, kBlock, 0, s>>>(P.n_shared, P.fix_nodes, xv, r, p, q, dinv, sx, sr, sp, sq, sd,
-                                                    to_compact);
-    };
+    auto scatter_x = [&]() { k_scatter_x<VT><<<gv, kBlock, 0, s>>>(n, w.perm, xv, x64, fold ? 1 : 0); };
 
-    // refresh: finish the pending step, true FP64 residual of x64 into r64 ->
-    // r, totals into the state, shared-node values back to the compact arrays
+    // refresh: finish the pending step, x back to mesh order, true FP64
+    // residual of x64 into r64 -> local r, totals into the state
     auto refresh = [&](int first) -> int {
-        if (!first) {
-            shared_copy(0);
-            k_pending<VT><<<gv, kBlock, 0, s>>>(n, xv, r, p, q, w.st);
-        }
-        if (fold) k_fold<<<gv, kBlock, 0, s>>>(n, x64, reinterpret_cast<float *>(w.xc));
+        if (!first) k_pending<VT><<<gv, kBlock, 0, s>>>(n, xv, r, p, q, w.st);
+        scatter_x();
         int rc = launch_apply_pk64(P, pk_kind, w.Apk, x64, b, w.r64, -1.0, 1, w.part64, s);
         if (rc) return rc;
-        k_init_dots<VT><<<gu, kBlock, 0, s>>>(n, r, dinv, w.r64, w.upd);
+        k_init_dots<VT><<<gu, kBlock, 0, s>>>(n, r, dinv, w.r64, w.perm, w.upd);
         k_refresh_state<<<1, kBlock, 0, s>>>(w.st, w.upd, gu, first);
-        shared_copy(1);
         FEM_HIP_CHECK(hipGetLastError());
         return 0;
     };
 
+    if (!fold) k_gather_perm<VT><<<gv, kBlock, 0, s>>>(n, w.perm, x64, xv);
     IterState h{};
     int rc = refresh(1);
     if (rc) return rc;
@@ -462,7 +475,7 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, const double *b, double
         if (profile > 0) ev.harvest();
         if (h.flag == 2) {
             status = FEM_EBREAKDOWN;
-            shared_copy(0);
+            scatter_x();
             break;
         }
         if (h.flag == 1) {
@@ -509,12 +522,19 @@ int solve_pcg(const DevPlan &P, SolverWork &w, int dtype, int vec64, int block, 
     rc = launch_diag64(P, dtype, K, Mu, nu, w.d64, w.part64, s);
     if (rc) return rc;
     k_zero_int<<<1, 1, 0, s>>>(w.bad);
+    if (P.n_chunks > 0)
+        k_perm_complete<<<(int)std::min<int64_t>(P.n_chunks, 4096), kBlock, 0, s>>>(P, w.perm);
+    if (P.n_shared > 0)
+        k_perm_shared<<<(int)std::max<int64_t>(1, std::min<int64_t>((P.n_shared + kBlock - 1) / kBlock, 4096)),
+                        kBlock, 0, s>>>(P, w.perm);
     const bool v32 = mixed && !vec64;
     if (v32) {
-        k_dinv<float><<<gv, kBlock, 0, s>>>(n, w.d64, P.mask, reinterpret_cast<float *>(w.dinv), jacobi, w.bad);
+        k_dinv<float><<<gv, kBlock, 0, s>>>(n, w.d64, P.mask, w.perm, reinterpret_cast<float *>(w.dinv), jacobi,
+                                            w.bad);
         k_fill<float><<<gv, kBlock, 0, s>>>(n, reinterpret_cast<float *>(w.xc), 0.0f);
     } else {
-        k_dinv<double><<<gv, kBlock, 0, s>>>(n, w.d64, P.mask, reinterpret_cast<double *>(w.dinv), jacobi, w.bad);
+        k_dinv<double><<<gv, kBlock, 0, s>>>(n, w.d64, P.mask, w.perm, reinterpret_cast<double *>(w.dinv), jacobi,
+                                             w.bad);
     }
     FEM_HIP_CHECK(hipGetLastError());
     int bad = 0;

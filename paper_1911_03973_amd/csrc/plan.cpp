@@ -216,6 +216,12 @@ int build_host_plan(int dim, int64_t n_nodes, int64_t n_elems, const double *coo
     P.part_owner.assign(np, 0);
     for (int64_t s = 0; s < P.n_shared; ++s)
         for (int32_t k = P.fix_off[s]; k < P.fix_off[s + 1]; ++k) P.part_owner[P.fix_parts[k]] = (int32_t)s;
+    P.comp_off.assign(P.n_chunks + 1, 0);
+    for (int64_t c = 0; c < P.n_chunks; ++c) P.comp_off[c + 1] = P.comp_off[c] + P.chunk_info[2 * c];
+    if ((int64_t)P.comp_off[P.n_chunks] + P.n_shared != n_nodes) {
+        err = "internal error: complete and shared nodes do not partition the nodes";
+        return -1;
+    }
     return 0;
 }
 

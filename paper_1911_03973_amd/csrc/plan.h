@@ -21,6 +21,7 @@ struct HostPlan {
     std::vector<int32_t> fix_off;         // [n_shared+1]
     std::vector<int32_t> fix_parts;       // [n_partials]
     std::vector<int32_t> part_owner;      // [n_partials] shared-node index of each partial slot
+    std::vector<int32_t> comp_off;        // [n_chunks+1] prefix of the complete-node counts
     std::vector<uint8_t> mask;            // [n_nodes] Dirichlet flags
 };
 
@@ -40,6 +41,10 @@ struct DevPlan {
     const int32_t *fix_off;
     const int32_t *fix_parts;
     const int32_t *part_owner;
+    // [n_chunks+1] prefix of the complete-node counts: complete node k of chunk
+    // c has solver-local index comp_off[c] + k, shared node s has
+    // comp_off[n_chunks] + s (a permutation of all nodes).  NULL for batches.
+    const int32_t *comp_off;
     const uint8_t *mask;
 };
 

@@ -47,7 +47,8 @@ struct SolverWork {
     double *part64 = nullptr;     // shared-node partials of FP64 passes
     void *partv = nullptr;        // shared-node partials of iteration passes
     double *dots = nullptr;       // [8][npart] per-block dot partials
-    void *shared = nullptr;       // compact shared-node x, r, p, q, D^{-1}: [5][n_shared] vector type
+    void *xl = nullptr;           // FP64 iterate in the solver-local node order
+    int32_t *perm = nullptr;      // local index -> mesh node id
     double *upd = nullptr;        // [3][gu] init partials
     IterState *st = nullptr;
     int *bad = nullptr;
