@@ -182,7 +182,7 @@ def run_batched(args, w):
     b = torch.empty(B.n_nodes, dtype=torch.float64, device="cuda")
     x = torch.empty(B.n_nodes, dtype=torch.float64, device="cuda")
     opts = fem.batch_opts(rtol=1e-8, block=args.block, use_graph=1, watchdog_seconds=60.0, group=args.group,
-                          items_per_phase=args.items,
+                          items_per_phase=args.items, inline_segments=args.inline_segs,
                           max_iter=min(args.max_iter, 100000))
 
     def step():
@@ -351,6 +351,8 @@ def main():
     ap.add_argument("--n-problems", type=int, default=256, help="batched workload: number of problems")
     ap.add_argument("--group", type=int, default=0, help="batched: chunks per work item (0 = per-problem schedule)")
     ap.add_argument("--items", type=int, default=32, help="batched: target work items per problem phase")
+    ap.add_argument("--inline-segs", type=int, default=64,
+                    help="batched: fix-up segments the last chunk item of a phase runs itself")
     ap.add_argument("--autotune", action="store_true", help="batched: pick the schedule with the autotuner first")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-FCG vs Jacobi-PCG comparison")
     ap.add_argument("--learned-n", type=int, default=1024)

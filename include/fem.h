@@ -240,6 +240,11 @@ typedef struct {
     int items_per_phase;     /* per-problem schedule: target work items per
                                 phase (a problem of n chunks takes
                                 ceil(n / items_per_phase) chunks per item) */
+    int inline_segments;     /* a problem with at most this many shared-node
+                                segments (1024 nodes each) has its fix-up and
+                                scalar step run by the workgroup finishing its
+                                last chunk item, one queue trip per iteration
+                                (default 64; 0: always separate items) */
 } fem_batch_opts;
 
 typedef struct {

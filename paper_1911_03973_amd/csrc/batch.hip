@@ -10,6 +10,10 @@
 // the CG updates) and refresh rounds (pending step + FP64 residual b - A x).
 // Per problem, an integer counter counts the finished items of the current
 // phase; the workgroup that finishes the last one enqueues the next phase.
+// The workgroup finishing a problem's last CHUNK item also runs its fix-up
+// (when it has at most inline_segs segments) and its scalar step, and the one
+// finishing the last FIX item runs the scalar step, so one iteration of a
+// problem costs one or two trips through the queue instead of three.
 // Nothing ever waits for another workgroup: a workgroup only waits for the
 // queue to hold an item, so the launch needs no co-residency, and it ends
 // when every problem is finished.  A wall-clock watchdog bounds every wait,
@@ -61,6 +65,7 @@ struct BatchArgs {
     int *ndone, *abort_flag;
     double rtol, delta;
     int max_iter, max_refresh;
+    int inline_segs;       // the last CHUNK item runs up to this many fix-up segments itself
     long long spin_ticks;  // watchdog, in 100 MHz ticks
 };
 
@@ -284,67 +289,37 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
         const int sh0 = a.pshared0[p], nsh = a.pshared0[p + 1] - sh0;
         const int sg0 = a.pseg0[p], nseg = a.pseg0[p + 1] - sg0;
         const int round = pr->round;
-        if (type == IT_CHUNK || type == IT_FIX) {
+        // fix-up of shared-node segment jj of p; its dot partials into sdots
+        auto fix_loop = [&](auto &op, int jj) {
+            const int s1 = min(nsh, (jj + 1) * kSeg);
+            for (int sl_ = jj * kSeg + threadIdx.x; sl_ < s1; sl_ += BS) {
+                const int sg = sh0 + sl_;
+                double acc = 0.0;
+                for (int k = P.fix_off[sg]; k < P.fix_off[sg + 1]; ++k) acc += a.part[P.fix_parts[k]];
+                op.fixup_node(sg, P.fix_nodes[sg], acc);
+            }
+        };
+        auto fix_segment = [&](int jj) {
             double d[kBDots];
             if (round == 0) {
                 BOpIter op{a.x, a.r, a.p, a.q, a.dinv, a.sx, a.sr, a.sp, a.sq, a.sd, pr->mode, pr->alpha, pr->beta,
                            {0, 0, 0, 0, 0, 0, 0}};
-                if (type == IT_CHUNK) {
-                    LdPk<NB, MAT_F32> ld{a.A, P.n_elems};
-                    const int cj1 = min(nch, (j + 1) * grp);
-                    for (int cj = j * grp; cj < cj1; ++cj) {
-#pragma unroll
-                        for (int t = 0; t < kBDots; ++t) op.d[t] = 0.0;
-                        __syncthreads();
-                        chunk_pass<NB, EPT, BS, double, LdPk<NB, MAT_F32>, BOpIter, false>(P, ld, op, a.part, c0 + cj,
-                                                                                          buf, sl);
-                        store_dots<BS>(op.d, red.v, a.cdots + (int64_t)(c0 + cj) * kBDots);
-                    }
-                } else {
-                    const int s1 = min(nsh, (j + 1) * kSeg);
-                    for (int s = j * kSeg + threadIdx.x; s < s1; s += BS) {
-                        const int sg = sh0 + s;
-                        double acc = 0.0;
-                        for (int k = P.fix_off[sg]; k < P.fix_off[sg + 1]; ++k) acc += a.part[P.fix_parts[k]];
-                        op.fixup_node(sg, P.fix_nodes[sg], acc);
-                    }
-                }
+                fix_loop(op, jj);
 #pragma unroll
                 for (int t = 0; t < kBDots; ++t) d[t] = op.d[t];
             } else {
                 BOpRefresh op{a.x, a.r, a.p, a.dinv, a.b, a.sx, a.sr, a.sp, a.sd, P.fix_nodes,
                               pr->pending ? pr->alpha : 0.0, {0, 0, 0, 0, 0, 0, 0}};
-                if (type == IT_CHUNK) {
-                    LdPk<NB, MAT_F32X2> ld{a.A, P.n_elems};
-                    const int cj1 = min(nch, (j + 1) * grp);
-                    for (int cj = j * grp; cj < cj1; ++cj) {
-#pragma unroll
-                        for (int t = 0; t < kBDots; ++t) op.d[t] = 0.0;
-                        __syncthreads();
-                        chunk_pass<NB, EPT, BS, double, LdPk<NB, MAT_F32X2>, BOpRefresh, false>(P, ld, op, a.part,
-                                                                                               c0 + cj, buf, sl);
-                        store_dots<BS>(op.d, red.v, a.cdots + (int64_t)(c0 + cj) * kBDots);
-                    }
-                } else {
-                    const int s1 = min(nsh, (j + 1) * kSeg);
-                    for (int s = j * kSeg + threadIdx.x; s < s1; s += BS) {
-                        const int sg = sh0 + s;
-                        double acc = 0.0;
-                        for (int k = P.fix_off[sg]; k < P.fix_off[sg + 1]; ++k) acc += a.part[P.fix_parts[k]];
-                        op.fixup_node(sg, P.fix_nodes[sg], acc);
-                    }
-                }
+                fix_loop(op, jj);
 #pragma unroll
                 for (int t = 0; t < kBDots; ++t) d[t] = op.d[t];
             }
-            if (type == IT_FIX) store_dots<BS>(d, red.v, a.sdots + (int64_t)(sg0 + j) * kBDots);
-            const int n_items = type == IT_CHUNK ? nci : nseg;
-            if (phase_done<BS>(a, p, n_items, &s_last)) {
-                if (type == IT_CHUNK && nseg > 0) enqueue<BS>(a, IT_FIX, p, nseg, &s_base);
-                else enqueue<BS>(a, IT_FIN, p, 1, &s_base);
-            }
-        } else {
-            // FIN: sum the partials of p in a fixed order, advance its scalars
+            store_dots<BS>(d, red.v, a.sdots + (int64_t)(sg0 + jj) * kBDots);
+        };
+        // the scalar step of p (every partial of the phase is visible to this
+        // workgroup), then the next phase or the end of p
+        auto finish_phase = [&]() {
+            __syncthreads();  // sdots written by this workgroup
             double t[kBDots];
 #pragma unroll
             for (int k = 0; k < kBDots; ++k) t[k] = 0.0;
@@ -418,6 +393,50 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
             } else {
                 enqueue<BS>(a, IT_CHUNK, p, nci, &s_base);
             }
+        };
+        if (type == IT_CHUNK) {
+            if (round == 0) {
+                BOpIter op{a.x, a.r, a.p, a.q, a.dinv, a.sx, a.sr, a.sp, a.sq, a.sd, pr->mode, pr->alpha, pr->beta,
+                           {0, 0, 0, 0, 0, 0, 0}};
+                LdPk<NB, MAT_F32> ld{a.A, P.n_elems};
+                const int cj1 = min(nch, (j + 1) * grp);
+                for (int cj = j * grp; cj < cj1; ++cj) {
+#pragma unroll
+                    for (int t = 0; t < kBDots; ++t) op.d[t] = 0.0;
+                    __syncthreads();
+                    chunk_pass<NB, EPT, BS, double, LdPk<NB, MAT_F32>, BOpIter, false>(P, ld, op, a.part, c0 + cj,
+                                                                                      buf, sl);
+                    store_dots<BS>(op.d, red.v, a.cdots + (int64_t)(c0 + cj) * kBDots);
+                }
+            } else {
+                BOpRefresh op{a.x, a.r, a.p, a.dinv, a.b, a.sx, a.sr, a.sp, a.sd, P.fix_nodes,
+                              pr->pending ? pr->alpha : 0.0, {0, 0, 0, 0, 0, 0, 0}};
+                LdPk<NB, MAT_F32X2> ld{a.A, P.n_elems};
+                const int cj1 = min(nch, (j + 1) * grp);
+                for (int cj = j * grp; cj < cj1; ++cj) {
+#pragma unroll
+                    for (int t = 0; t < kBDots; ++t) op.d[t] = 0.0;
+                    __syncthreads();
+                    chunk_pass<NB, EPT, BS, double, LdPk<NB, MAT_F32X2>, BOpRefresh, false>(P, ld, op, a.part,
+                                                                                           c0 + cj, buf, sl);
+                    store_dots<BS>(op.d, red.v, a.cdots + (int64_t)(c0 + cj) * kBDots);
+                }
+            }
+            if (phase_done<BS>(a, p, nci, &s_last)) {
+                // the last CHUNK item of the phase: a few fix-up segments and the
+                // scalar step run here, so the phase costs one queue trip
+                if (nseg > a.inline_segs) {
+                    enqueue<BS>(a, IT_FIX, p, nseg, &s_base);
+                } else {
+                    for (int jj = 0; jj < nseg; ++jj) fix_segment(jj);
+                    finish_phase();
+                }
+            }
+        } else if (type == IT_FIX) {
+            fix_segment(j);
+            if (phase_done<BS>(a, p, nseg, &s_last)) finish_phase();
+        } else {
+            finish_phase();
         }
         __syncthreads();
     }
@@ -556,6 +575,7 @@ int batch_launch(const BatchLaunch &L, hipStream_t s) {
     a.pshared0 = L.pshared0;
     a.pseg0 = L.pseg0;
     a.pgroup = L.pgroup;
+    a.inline_segs = L.inline_segs;
     a.nprob = L.nprob;
     a.prob = L.prob;
     a.cnt = L.cnt;

@@ -192,6 +192,7 @@ void fem_batch_opts_default(fem_batch_opts *o) {
     o->use_graph = 1;
     o->group = 0;
     o->items_per_phase = 32;
+    o->inline_segments = 64;
 }
 
 int fem_batch_create(int dim, int n_problems, const int64_t *node_off, const int64_t *elem_off,
@@ -393,7 +394,8 @@ int fem_batch_solve(fem_batch *B, const fem_batch_opts *o, const void *d_K_e, co
         if (B->isolated_free[p] > 0)
             return set_error(FEM_ESINGULAR, "problem " + std::to_string(p) + ": node outside every element");
     }
-    if (o->group < 0 || o->items_per_phase < 1) return set_error(FEM_EINVAL, "bad work-item schedule");
+    if (o->group < 0 || o->items_per_phase < 1 || o->inline_segments < 0)
+        return set_error(FEM_EINVAL, "bad work-item schedule");
     if (int rc = alloc_batch_work(B)) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     // work-item schedule: chunks per item for every problem, and the prefix
@@ -405,6 +407,7 @@ int fem_batch_solve(fem_batch *B, const fem_batch_opts *o, const void *d_K_e, co
         it0[p + 1] = it0[p] + (nch + grp[p] - 1) / grp[p];
     }
     B->L.n_seed = it0[B->nprob];
+    B->L.inline_segs = o->inline_segments;
     FEM_HIP_CHECK(hipMemcpyAsync(B->pgroup, grp.data(), B->nprob * sizeof(int32_t), hipMemcpyHostToDevice, s));
     FEM_HIP_CHECK(hipMemcpyAsync(B->pitem0, it0.data(), (B->nprob + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
     FEM_HIP_CHECK(hipMemcpyAsync(B->nu, h_nu, B->nprob * sizeof(double), hipMemcpyHostToDevice, s));

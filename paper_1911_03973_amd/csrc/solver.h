@@ -79,6 +79,7 @@ struct BatchLaunch {
     double *part;
     const int32_t *pchunk0, *pshared0, *pseg0;
     const int32_t *pgroup;  // [P] chunks per work item
+    int inline_segs;        // fix-up segments run inline by the last chunk item
     const int32_t *pitem0;  // [P+1] prefix of the work items of a chunk round
     int64_t n_seed;         // work items of one chunk round of all problems
     int nprob;
