@@ -172,7 +172,7 @@ def run_batched(args, w):
         log(f"[bench] autotuned: {dict((k, v) for k, v in tuned.items() if k != 'table')}")
         args.chunk, args.block, args.items = tuned["chunk_elems"], tuned["block"], tuned["items_per_phase"]
     t = time.perf_counter()
-    B = fem.Batch(meshes, dirs, chunk_elems=args.chunk)
+    B = fem.Batch(meshes, dirs, chunk_elems=args.chunk or args.batch_chunk)
     t_plan = time.perf_counter() - t
     st = B.stats()
     log(f"[bench] batch plan {t_plan:.2f} s: {st}")
@@ -227,6 +227,70 @@ def run_batched(args, w):
         "note": "value = algorithmic bytes of all element passes of the solve / solve wall time (whole job)",
         "schedule": {"chunk_elems": st["chunk_elems"], "block": args.block, "items_per_phase": args.items},
         "autotune": tuned,
+    }
+    print(json.dumps(out), flush=True)
+
+
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def unet_flops(H, W, c=16, real_in=2):
+    """Multiply-add flops (2 per MAC) of one U-Net forward on an H x W image."""
+    px = lambda lvl: (H >> lvl) * (W >> lvl)  # noqa: E731
+    conv = lambda lvl, cin, cout: 2 * 9 * cin * cout * px(lvl)  # noqa: E731
+    up = lambda lvl_low, cin, cout: 2 * cin * 4 * cout * px(lvl_low)  # noqa: E731
+    f = conv(0, real_in, c) + conv(0, c, c) + conv(1, c, 2 * c) + conv(1, 2 * c, 2 * c)
+    f += conv(2, 2 * c, 4 * c) + conv(2, 4 * c, 4 * c) + conv(3, 4 * c, 8 * c) + conv(3, 8 * c, 8 * c)
+    f += up(3, 8 * c, 4 * c) + conv(2, 8 * c, 4 * c) + conv(2, 4 * c, 4 * c)
+    f += up(2, 4 * c, 2 * c) + conv(1, 4 * c, 2 * c) + conv(1, 2 * c, 2 * c)
+    f += up(1, 2 * c, c) + conv(0, 2 * c, c) + conv(0, c, c) + 2 * c * px(0)
+    return f
+
+
+def run_unet(args):
+    """U-Net kernels alone: forward (batch 1) and training step (batch 4) at 1024^2, HIP-event timed."""
+    import torch
+
+    from paper_1911_03973_amd import fem
+
+    N = args.learned_n
+    fwd_flops = unet_flops(N, N)
+    net = fem.UNet(N, N, max_batch=4, channels=16, seed=0)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    inp = torch.randn((4, N, N, 2), generator=g, device="cuda")
+    tgt = torch.randn((4, N, N), generator=g, device="cuda")
+    x1 = inp[:1].contiguous()
+    for _ in range(args.warmup + 1):
+        net.forward(x1)
+        net.train_step(inp, tgt, 1e-4)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(args.steps, 1) * 10
+    s.record()
+    for _ in range(reps):
+        net.forward(x1)
+    e.record()
+    torch.cuda.synchronize()
+    fwd_ms = s.elapsed_time(e) / reps
+    s.record()
+    for _ in range(reps):
+        net.train_step(inp, tgt, 1e-4)
+    e.record()
+    torch.cuda.synchronize()
+    train_ms = s.elapsed_time(e) / reps
+    tf = fwd_flops / (fwd_ms * 1e-3) / 1e12
+    train_tf = 3 * 4 * fwd_flops / (train_ms * 1e-3) / 1e12
+    out = {
+        "metric": "U-Net forward TFLOP/s (BF16 MFMA, FP32 accumulation)", "value": round(tf, 2),
+        "unit": "TFLOP/s", "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+        "ms_per_step": round(fwd_ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"U-Net 4 levels 16-128 channels, {N}x{N} image, forward batch 1, "
+                               f"training step batch 4 (forward + backward + Adam)"},
+        "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None},
+        "forward_gflop": round(fwd_flops / 1e9, 2), "train_step_ms": round(train_ms, 3),
+        "train_tflops_3x_forward": round(train_tf, 2),
     }
     print(json.dumps(out), flush=True)
 
@@ -336,7 +400,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["unet"], default="c2")
     ap.add_argument("--profile", type=int, default=4, help="time every k-th matvec with HIP events")
     ap.add_argument("--check-every", type=int, default=64)
     ap.add_argument("--chunk", type=int, default=0)
@@ -350,7 +414,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-problems", type=int, default=256, help="batched workload: number of problems")
     ap.add_argument("--group", type=int, default=0, help="batched: chunks per work item (0 = per-problem schedule)")
-    ap.add_argument("--items", type=int, default=32, help="batched: target work items per problem phase")
+    ap.add_argument("--items", type=int, default=16, help="batched: target work items per problem phase")
+    ap.add_argument("--batch-chunk", type=int, default=2048, help="batched: elements per chunk")
     ap.add_argument("--inline-segs", type=int, default=64,
                     help="batched: fix-up segments the last chunk item of a phase runs itself")
     ap.add_argument("--autotune", action="store_true", help="batched: pick the schedule with the autotuner first")
@@ -375,6 +440,8 @@ def main():
 
     from paper_1911_03973_amd import fem
 
+    if args.workload == "unet":
+        return run_unet(args)
     w = WORKLOADS[args.workload]
     if args.workload == "c4":
         return run_batched(args, w)
