@@ -379,6 +379,8 @@ typedef struct {
                            z += s N(r - A z) with s = (n.rz)/(n.A n), then k
                            more Jacobi steps (default 4) */
     double omega;       /* Jacobi damping of the cycle, (0, 2) (default 2/3) */
+    int graph;          /* 1: the network's launches are captured once per solve into a
+                           HIP graph and replayed (default); 0: launched one by one */
 } fem_fcg_opts;
 
 typedef struct {

@@ -482,6 +482,7 @@ void fem_fcg_opts_default(fem_fcg_opts *o) {
     o->max_replace = 8;
     o->smooth = 4;
     o->omega = 2.0 / 3.0;
+    o->graph = 1;
 }
 
 int fem_fcg_solve(const fem_plan *plan_c, const fem_fcg_opts *o, fem_unet *net, const void *d_K_e,
@@ -497,6 +498,7 @@ int fem_fcg_solve(const fem_plan *plan_c, const fem_fcg_opts *o, fem_unet *net, 
     if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) return set_error(FEM_EINVAL, "rtol must be in (0, 1)");
     if (o->max_iter < 1) return set_error(FEM_EINVAL, "max_iter must be >= 1");
     if (o->stall_iters < 1 || o->max_replace < 0) return set_error(FEM_EINVAL, "stall_iters >= 1, max_replace >= 0");
+    if (o->graph != 0 && o->graph != 1) return set_error(FEM_EINVAL, "graph must be 0 or 1");
     if (o->smooth < 0 || o->smooth > 8 || !(o->omega > 0.0) || !(o->omega < 2.0))
         return set_error(FEM_EINVAL, "smooth must be in [0, 8] and omega in (0, 2)");
     if ((!d_K_e && plan->dev.n_elems > 0) || !d_b || !d_x) return set_error(FEM_EINVAL, "NULL argument");
@@ -516,7 +518,7 @@ int fem_fcg_solve(const fem_plan *plan_c, const fem_fcg_opts *o, fem_unet *net, 
     fem::FcgResult res;
     int rc = fem::solve_fcg(plan->dev, o->dtype, d_K_e, o->nu != 0.0 ? d_M_e : nullptr, o->nu, d_b, d_x, o->rtol,
                             o->max_iter, net, o->grid_n, o->cval, o->smooth, o->omega, o->stall_iters,
-                            o->max_replace, res, s);
+                            o->max_replace, o->graph, res, s);
     info->iters = res.iters;
     info->precond_calls = res.precond_calls;
     info->fell_back = res.fell_back;

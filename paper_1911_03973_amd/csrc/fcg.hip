@@ -106,6 +106,45 @@ __global__ void k_coarse_update(int64_t n, const double *__restrict__ sc, const 
 }
 
 
+// The preconditioner's launches captured once per solve into a HIP graph (on
+// an internal stream of default priority) and replayed on the solver's
+// stream; the inputs and outputs are the solve's fixed workspace vectors.
+struct PrecondGraph {
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const double *r = nullptr;
+    double *z = nullptr;
+    ~PrecondGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+    int run(fem_unet *net, int grid_n, const double *rr, double cval, const uint8_t *mask, double *zz, hipStream_t s) {
+        if (!exec || rr != r || zz != z) {
+            if (exec) {
+                FEM_HIP_CHECK(hipGraphExecDestroy(exec));
+                exec = nullptr;
+            }
+            if (!cap) FEM_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            hipGraph_t g;
+            FEM_HIP_CHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+            const int rc = unet_grid_precondition(net, grid_n, rr, cval, mask, zz, cap);
+            const hipError_t e = hipStreamEndCapture(cap, &g);
+            if (rc) return rc;
+            if (e != hipSuccess) return set_error(FEM_EHIP, "capture of the preconditioner failed");
+            const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (ei != hipSuccess) {
+                exec = nullptr;
+                return set_error(FEM_EHIP, "instantiation of the preconditioner graph failed");
+            }
+            r = rr;
+            z = zz;
+        }
+        FEM_HIP_CHECK(hipGraphLaunch(exec, s));
+        return 0;
+    }
+};
+
 struct FcgWork {
     void *arena = nullptr;
     double *A = nullptr, *d = nullptr, *dinv = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
@@ -122,8 +161,13 @@ struct FcgWork {
 
 int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double nu, const double *b, double *x,
               double rtol, int max_iter, fem_unet *net, int grid_n, double cval, int smooth, double omega,
-              int stall_iters, int max_replace, FcgResult &res, hipStream_t s) {
+              int stall_iters, int max_replace, int graph, FcgResult &res, hipStream_t s) {
     std::memset(&res, 0, sizeof(res));
+    PrecondGraph pg;
+    auto precondition = [&](const double *rr, double *zz) -> int {
+        if (graph) return pg.run(net, grid_n, rr, cval, P.mask, zz, s);
+        return unet_grid_precondition(net, grid_n, rr, cval, P.mask, zz, s);
+    };
     res.fell_back = -1;
     const int64_t n = P.n_nodes;
     const int64_t npk = (int64_t)packed_count(P.nb) * P.n_elems;
@@ -209,7 +253,7 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
         // z = N(r) or D^-1 r; then (z.r, z.z, z.q_prev)
         bool net_ok = use_net;
         if (use_net && smooth == 0) {
-            if (int rc = unet_grid_precondition(net, grid_n, w.r, cval, P.mask, w.z, s)) return rc;
+            if (int rc = precondition(w.r, w.z)) return rc;
             res.precond_calls += 1;
         } else if (use_net) {
             // pre-smoothing: z = omega D^-1 r, then (smooth - 1) steps on rz = r - A z
@@ -220,7 +264,7 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
             }
             if (int rc = launch_apply_pk64(P, MAT_F64, w.A, w.z, w.r, w.rz, -1.0, 1, w.scratch, s)) return rc;
             // coarse correction by the network
-            if (int rc = unet_grid_precondition(net, grid_n, w.rz, cval, P.mask, w.nz, s)) return rc;
+            if (int rc = precondition(w.rz, w.nz)) return rc;
             res.precond_calls += 1;
             if (int rc = launch_apply_pk64(P, MAT_F64, w.A, w.nz, nullptr, w.An, 1.0, 1, w.scratch, s)) return rc;
             k_dots<2><<<gv, kBlock, 0, s>>>(n, w.ptrs + 10, w.ptrs + 12, w.part);

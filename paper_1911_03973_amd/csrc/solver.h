@@ -128,6 +128,6 @@ int run_iteration(const DevPlan &P, int dtype, const void *K, const void *M, dou
                   int method, double lam1, double lam2, int cycle, int iters, IterResult &res, hipStream_t s);
 int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double nu, const double *b, double *x,
               double rtol, int max_iter, fem_unet *net, int grid_n, double cval, int smooth, double omega,
-              int stall_iters, int max_replace, FcgResult &res, hipStream_t s);
+              int stall_iters, int max_replace, int graph, FcgResult &res, hipStream_t s);
 
 }  // namespace fem

@@ -351,7 +351,11 @@ __global__ void k_out_fwd(const bf16 *__restrict__ d0, const float *__restrict__
                           int C, int64_t P, float *__restrict__ out) {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
         float s = bias[0];
-        for (int c = 0; c < C; ++c) s += (float)d0[p * C + c] * w[c];
+        for (int c = 0; c < C; c += 8) {  // C is a multiple of 8: 16-byte loads
+            const bf8 v = ld8(d0 + p * C + c);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) s += (float)v[i] * w[c + i];
+        }
         out[p] = s;
     }
 }
@@ -403,7 +407,12 @@ __global__ void k_out_bwd(const float *__restrict__ y, const float *__restrict__
         const int64_t b = p / HW;
         const float g = (float)(2.0 * ((double)y[p] - t[p]) / ((double)B * fmax(sums[2 * b], 1e-300)));
         gy[p] = g;
-        for (int c = 0; c < C; ++c) gd0[p * C + c] = (bf16)(g * w[c]);
+        for (int c = 0; c < C; c += 8) {
+            bf8 v;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = (bf16)(g * w[c + i]);
+            *reinterpret_cast<bf8 *>(gd0 + p * C + c) = v;
+        }
     }
 }
 

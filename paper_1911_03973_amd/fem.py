@@ -91,6 +91,7 @@ class FcgOpts(ctypes.Structure):
         ("dtype", ctypes.c_int), ("nu", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int),
         ("grid_n", ctypes.c_int), ("cval", ctypes.c_double), ("stall_iters", ctypes.c_int),
         ("max_replace", ctypes.c_int), ("smooth", ctypes.c_int), ("omega", ctypes.c_double),
+        ("graph", ctypes.c_int),
     ]
 
 

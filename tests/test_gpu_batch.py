@@ -38,15 +38,17 @@ def _check_solutions(probs, B, x, res, tol=1.05e-8):
         assert res[i]["iters"] <= 1.1 * io["iters"] + 2, (i, res[i]["iters"], io["iters"])
 
 
-@pytest.mark.parametrize("chunk", [0, 256])
-def test_batch_2d_uneven_sizes(chunk):
+@pytest.mark.parametrize("chunk,inline", [(0, 64), (256, 64), (256, 0), (64, 1)])
+def test_batch_2d_uneven_sizes(chunk, inline):
+    """inline = 0 runs every shared-node fix-up as separate queue items; 1 mixes both paths."""
     ns = [8, 17, 30, 12, 41, 3]
     nus = [1e-3, 0.5, 10.0, 1e3, 1.0, 0.0]
     meshes = [inputs.square_mesh(n, jitter=0.15, seed=i) for i, n in enumerate(ns)]
     probs, B, K, M, b = _batch(meshes, nus, list(range(100, 106)), chunk=chunk)
     print(B.stats())
     x = torch.zeros(B.n_nodes, dtype=torch.float64, device="cuda")
-    rc, res, sec = B.solve(fem.batch_opts(use_graph=0, watchdog_seconds=20.0), K, M, nus, b, x)
+    rc, res, sec = B.solve(fem.batch_opts(use_graph=0, watchdog_seconds=20.0, inline_segments=inline), K, M, nus,
+                           b, x)
     print(rc, res, sec)
     assert rc == 0
     _check_solutions(probs, B, x, res)

@@ -103,3 +103,19 @@ def test_trained_network_beats_jacobi_pcg_in_iterations():
         it_pcg.append(a["iters"])
         it_fcg.append(b["iters"])
     assert np.mean(it_fcg) <= 0.5 * np.mean(it_pcg), (it_fcg, it_pcg)
+
+
+def test_graph_replayed_preconditioner_matches_eager_launches():
+    """The network captured into a HIP graph and replayed every iteration (with
+    the solver's eager kernels and host synchronisations between replays) gives
+    the same iterates, bit for bit, as launching its kernels one by one."""
+    N = 32
+    gp = learn.GridProblem.make(N, 40.0, 3)
+    net = fem.UNet(N, N, channels=16, seed=6)
+    xs = []
+    for graph in (0, 1, 1):
+        x = torch.zeros(gp.n_nodes, dtype=torch.float64, device="cuda")
+        info = gp.fcg(net, x, rtol=1e-12, max_iter=25, stall_iters=1000, graph=graph)
+        xs.append((x.cpu(), info["iters"]))
+    assert xs[0][1] == xs[1][1] == xs[2][1] == 25
+    assert torch.equal(xs[0][0], xs[1][0]) and torch.equal(xs[1][0], xs[2][0])
