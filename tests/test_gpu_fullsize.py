@@ -1,0 +1,156 @@
+"""Parity at the benchmark workloads' full sizes, in the launch configuration
+the benchmark times (default chunk and workgroup sizes, FP32 hi/lo storage).
+
+  * local matrices on 4096 sampled elements against the oracle's formula;
+  * the right-hand side and the FP64 residual on 4096 sampled nodes: the
+    oracle evaluates them on the sub-mesh of all elements touching the sampled
+    nodes, which gives the exact nodal values there;
+  * the solve: the oracle's own FP64 residual of the GPU solution over the
+    whole mesh meets the 1e-8 target.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1911_03973_amd import inputs
+
+from problems import cuda, pair_value, to_soa
+
+pytestmark = pytest.mark.gpu
+
+fem = pytest.importorskip("paper_1911_03973_amd.fem")
+
+SAMPLES = 4096
+
+
+def _workload(name):
+    if name == "c2":
+        mesh = inputs.square_mesh(2048, jitter=0.2, seed=0)
+        return mesh, inputs.boundary_nodes(mesh, "x2=0"), 1.0, inputs.random_sine(mesh.coords, 1)
+    if name == "c3":
+        mesh = inputs.cube_mesh(160)
+        return mesh, inputs.boundary_nodes(mesh, "all"), 10.0, np.ones(mesh.n_nodes)
+    mesh = inputs.square_mesh(1024)  # the learned workload's grid
+    return mesh, inputs.boundary_nodes(mesh, "all"), 37.5, inputs.random_sine(mesh.coords, 11)
+
+
+def _sub_elements(mesh, nodes):
+    """Indices of every element with a vertex in `nodes`."""
+    hit = np.zeros(mesh.n_nodes, dtype=bool)
+    hit[nodes] = True
+    return np.nonzero(hit[mesh.elems].any(axis=1))[0]
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c5grid"])
+def test_full_size_kernels_on_sampled_outputs(name):
+    mesh, nd, nu, f = _workload(name)
+    rng = np.random.default_rng(42)
+    plan = fem.Plan.from_mesh(mesh, nd)
+    K = plan.empty_matrix(fem.F32X2)
+    M = plan.empty_matrix(fem.F32X2)
+    fem.build_local_matrices(plan, fem.F32X2, K, M, None)
+    b = plan.empty_vector()
+    fem.assemble_rhs(plan, fem.F32X2, M, cuda(f), b)
+    x = rng.standard_normal(mesh.n_nodes)
+    r = plan.empty_vector()
+    fem.element_residual(plan, fem.F32X2, K, M, nu, b, cuda(x), r, mask=True)
+    torch.cuda.synchronize()
+    nb = mesh.nb
+    # local matrices on sampled elements
+    es = rng.choice(mesh.n_elems, size=SAMPLES, replace=False)
+    Ko, Mo, _ = oracle.local_matrices(mesh.coords, mesh.elems[es])
+    Kg = pair_value(K)[:, es]
+    Mg = pair_value(M)[:, es]
+    assert np.abs(Kg - to_soa(Ko)).max() <= 1e-12 * np.abs(Ko).max()
+    assert np.abs(Mg - to_soa(Mo)).max() <= 1e-12 * np.abs(Mo).max()
+    # b and r on sampled nodes, from the sub-mesh around them
+    ns = rng.choice(mesh.n_nodes, size=SAMPLES, replace=False)
+    sub = mesh.elems[_sub_elements(mesh, ns)]
+    Ks, Ms, _ = oracle.local_matrices(mesh.coords, sub)
+    bs = oracle.rhs(mesh.n_nodes, sub, Ms, f)
+    mask = oracle.mask_from_nodes(mesh.n_nodes, nd)
+    rs = oracle.residual(mesh.n_nodes, sub, Ks, Ms, nu, bs, x, mask)
+    scale = oracle.residual_scale(mesh.n_nodes, sub, Ks, Ms, nu, bs, x)
+    bg, rg = b.cpu().numpy(), r.cpu().numpy()
+    assert np.abs(bg[ns] - bs[ns]).max() <= 1e-12 * np.abs(bs[ns]).max()
+    assert np.all(np.abs(rg[ns] - rs[ns]) <= 1e-12 * scale[ns] + 1e-300)
+    del nb
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_full_size_solve_meets_target_in_oracle_residual(name):
+    mesh, nd, nu, f = _workload(name)
+    plan = fem.Plan.from_mesh(mesh, nd)
+    K = plan.empty_matrix(fem.F32X2)
+    M = plan.empty_matrix(fem.F32X2)
+    fem.build_local_matrices(plan, fem.F32X2, K, M, None)
+    b = plan.empty_vector()
+    fem.assemble_rhs(plan, fem.F32X2, M, cuda(f), b)
+    x = torch.zeros(mesh.n_nodes, dtype=torch.float64, device="cuda")
+    info = fem.pcg_solve(plan, fem.solve_opts(dtype=fem.F32X2, nu=nu, rtol=1e-8, check_every=64), K, M, b, x)
+    assert info["status"] == 0 and info["relres"] <= 1e-8
+    Ko, Mo, _ = oracle.local_matrices(mesh.coords, mesh.elems)
+    bo = oracle.rhs(mesh.n_nodes, mesh.elems, Mo, f)
+    mask = oracle.mask_from_nodes(mesh.n_nodes, nd)
+    r = oracle.residual(mesh.n_nodes, mesh.elems, Ko, Mo, nu, bo, x.cpu().numpy(), mask)
+    r0 = oracle.residual(mesh.n_nodes, mesh.elems, Ko, Mo, nu, bo, np.zeros(mesh.n_nodes), mask)
+    rel = np.linalg.norm(r) / np.linalg.norm(r0)
+    assert rel <= 1.05e-8, rel
+    assert info["relres"] == pytest.approx(rel, rel=1e-4)
+
+
+def test_full_size_jacobi_fcg_on_learned_workload_grid():
+    mesh, nd, nu, f = _workload("c5grid")
+    plan = fem.Plan.from_mesh(mesh, nd)
+    K = plan.empty_matrix(fem.F32X2)
+    M = plan.empty_matrix(fem.F32X2)
+    fem.build_local_matrices(plan, fem.F32X2, K, M, None)
+    b = plan.empty_vector()
+    fem.assemble_rhs(plan, fem.F32X2, M, cuda(f), b)
+    x = torch.zeros(mesh.n_nodes, dtype=torch.float64, device="cuda")
+    info = fem.fcg_solve(plan, fem.fcg_opts(dtype=fem.F32X2, nu=nu, rtol=1e-8), None, K, M, b, x)
+    assert info["status"] == 0
+    Ko, Mo, _ = oracle.local_matrices(mesh.coords, mesh.elems)
+    bo = oracle.rhs(mesh.n_nodes, mesh.elems, Mo, f)
+    mask = oracle.mask_from_nodes(mesh.n_nodes, nd)
+    r = oracle.residual(mesh.n_nodes, mesh.elems, Ko, Mo, nu, bo, x.cpu().numpy(), mask)
+    r0 = oracle.residual(mesh.n_nodes, mesh.elems, Ko, Mo, nu, bo, np.zeros(mesh.n_nodes), mask)
+    assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8
+
+
+def test_full_size_batch_of_256_problems():
+    """The batched workload (256 problems, N ~ U{32..512}) in the benchmark's schedule;
+    the 16 largest problems and 16 others checked by the oracle's residual."""
+    params = inputs.batched_params(256)
+    meshes, dirs, fs, nus = [], [], [], []
+    for n, nu, seed in params:
+        m = inputs.square_mesh(n)
+        meshes.append(m)
+        dirs.append(inputs.boundary_nodes(m))
+        fs.append(inputs.random_sine(m.coords, seed))
+        nus.append(nu)
+    B = fem.Batch(meshes, dirs, chunk_elems=2048)
+    K = B.empty_matrix(fem.F32X2)
+    M = B.empty_matrix(fem.F32X2)
+    B.build_local_matrices(fem.F32X2, K, M)
+    b = torch.empty(B.n_nodes, dtype=torch.float64, device="cuda")
+    B.assemble_rhs(fem.F32X2, M, torch.from_numpy(np.concatenate(fs)).cuda(), b)
+    x = torch.zeros(B.n_nodes, dtype=torch.float64, device="cuda")
+    rc, res, sec = B.solve(fem.batch_opts(rtol=1e-8, use_graph=1, watchdog_seconds=60.0, items_per_phase=16), K, M,
+                           nus, b, x)
+    assert rc == 0
+    sizes = np.array([m.n_elems for m in meshes])
+    rng = np.random.default_rng(3)
+    check = list(np.argsort(sizes)[-16:]) + list(rng.choice(256, size=16, replace=False))
+    xs = x.cpu().numpy()
+    for i in check:
+        m, nu = meshes[i], nus[i]
+        Ko, Mo, _ = oracle.local_matrices(m.coords, m.elems)
+        bo = oracle.rhs(m.n_nodes, m.elems, Mo, fs[i])
+        mask = oracle.mask_from_nodes(m.n_nodes, dirs[i])
+        xi = xs[B.node_off[i]:B.node_off[i + 1]]
+        r = oracle.residual(m.n_nodes, m.elems, Ko, Mo, nu, bo, xi, mask)
+        r0 = oracle.residual(m.n_nodes, m.elems, Ko, Mo, nu, bo, np.zeros(m.n_nodes), mask)
+        assert res[i]["status"] == 0
+        assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8, (i, res[i])
