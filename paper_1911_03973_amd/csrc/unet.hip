@@ -191,6 +191,90 @@ __global__ __launch_bounds__(256) void k_gemm_rows(Src src, Epi epi, const bf16 
         }
 }
 
+// LDS-tiled 3x3 convolution forward (+ bias, ReLU).  A workgroup of 4 waves
+// owns a TY x TX pixel tile of one image: the tile's input with a one-pixel
+// halo ([C1 channels of src1 | C2 of src2]) is staged in LDS once, so every
+// input value is read once per tile instead of once per tap; the packed weight
+// fragments stream through LDS in blocks of kbc reduction blocks, shared by the
+// 4 waves.  Wave w computes tile pixels [64 MT/4 * w ...) as MT row tiles of
+// 16 pixels against all NT column tiles.  Pixels outside the image are
+// computed on zero input and not stored.
+template <int TY, int TX, int NT>
+__global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ src1, const bf16 *__restrict__ src2,
+                                                    int C1, int C2, int H, int W, int tiles_x, int tiles_y,
+                                                    const bf16 *__restrict__ Bp, int KB, int kbc,
+                                                    const float *__restrict__ bias, bf16 *__restrict__ out) {
+    constexpr int MT = TY * TX / 64;
+    constexpr int HX = TX + 2, HY = TY + 2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int Cin = C1 + C2, cu8 = Cin / 8;
+    bf16 *tin = reinterpret_cast<bf16 *>(smem);  // [HY][HX][Cin]
+    bf16 *tb = reinterpret_cast<bf16 *>(smem + (((size_t)HY * HX * Cin * 2 + 15) & ~(size_t)15));
+    const int tile = blockIdx.x;
+    const int tx = tile % tiles_x, t2 = tile / tiles_x, ty = t2 % tiles_y, b = t2 / tiles_y;
+    const int y0 = ty * TY, x0 = tx * TX;
+    for (int u = threadIdx.x; u < HY * HX * cu8; u += 256) {
+        const int cu = u % cu8, pp = u / cu8;
+        const int yy = y0 + pp / HX - 1, xx = x0 + pp % HX - 1;
+        bf8 v = zero8();
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+            const int64_t pix = ((int64_t)b * H + yy) * W + xx;
+            const int ci = cu * 8;
+            v = ci < C1 ? ld8(src1 + pix * C1 + ci) : ld8(src2 + pix * C2 + (ci - C1));
+        }
+        *reinterpret_cast<bf8 *>(tin + (size_t)pp * Cin + cu * 8) = v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    f4 acc[MT][NT];
+    int hoff[MT];  // halo-tile pixel of this lane's row in each row tile
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int p = (wave * MT + mt) * 16 + (lane & 15);
+        hoff[mt] = (p / TX) * HX + p % TX;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[mt][t] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int kc = 0; kc < KB; kc += kbc) {
+        const int nkb = min(kbc, KB - kc);
+        __syncthreads();  // the input tile is staged / the previous weight block is consumed
+        const bf8 *srcB = reinterpret_cast<const bf8 *>(Bp) + (size_t)kc * NT * 64;
+        for (int u = threadIdx.x; u < nkb * NT * 64; u += 256) reinterpret_cast<bf8 *>(tb)[u] = srcB[u];
+        __syncthreads();
+        for (int kl = 0; kl < nkb; ++kl) {
+            const int k0 = (kc + kl) * 32 + 8 * (lane >> 4);
+            const int tap = k0 / Cin, ci = k0 - tap * Cin;
+            const int toff = (tap / 3) * HX + tap % 3;
+            bf8 a[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                a[mt] = tap < 9 ? *reinterpret_cast<const bf8 *>(tin + (size_t)(hoff[mt] + toff) * Cin + ci) : zero8();
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const bf8 bv = *reinterpret_cast<const bf8 *>(tb + ((size_t)(kl * NT + t) * 64 + lane) * 8);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) acc[mt][t] = mfma(a[mt], bv, acc[mt][t]);
+            }
+        }
+    }
+    constexpr int N = NT * 16;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int p = (wave * MT + mt) * 16 + 4 * (lane >> 4) + i;
+            const int y = y0 + p / TX, x = x0 + p % TX;
+            if (y < H && x < W) {
+                const int64_t m = ((int64_t)b * H + y) * W + x;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const int n = t * 16 + (lane & 15);
+                    const float v = acc[mt][t][i] + bias[n];
+                    out[m * N + n] = (bf16)(v > 0.0f ? v : 0.0f);
+                }
+            }
+        }
+}
+
 // ---------------------------------------------------------------------------
 // Weight gradients: dW[r][n] = sum_pixels A[pixel][r] G[pixel][n]; the rows r
 // are those of the im2col operand plus a last bias row of ones.  Workgroup
@@ -630,7 +714,48 @@ int repack(UNet &N, hipStream_t st) {
     return 0;
 }
 
+size_t conv_tile_lds(int TY, int TX, int Cin) { return ((size_t)(TY + 2) * (TX + 2) * Cin * 2 + 15) & ~(size_t)15; }
+
+// tile fits next to at least one 1 KiB weight block per column tile in 64 KiB of LDS
+bool conv_tile_fits(int TY, int TX, const Layer &l) { return conv_tile_lds(TY, TX, l.Cin()) + (size_t)l.NTf * 1024 <= 65536; }
+
+template <int TY, int TX, int NT>
+int launch_conv_tiled_nt(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B,
+                         hipStream_t st) {
+    const int H = N.H >> l.lvl, W = N.W >> l.lvl;
+    const int tiles_x = (W + TX - 1) / TX, tiles_y = (H + TY - 1) / TY;
+    const size_t tin = conv_tile_lds(TY, TX, l.Cin());
+    const int kbc = (int)std::max<int64_t>(1, std::min<int64_t>(l.KBf, (65536 - (int64_t)tin) / (NT * 1024)));
+    const size_t lds = tin + (size_t)kbc * NT * 1024;
+    k_conv_tiled<TY, TX, NT><<<B * tiles_x * tiles_y, 256, lds, st>>>(s1.a, s2 ? s2->a : nullptr, l.C1, l.C2, H, W,
+                                                                        tiles_x, tiles_y, l.Bf, l.KBf, kbc,
+                                                                        N.w + l.boff, y.a);
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+// forward conv3x3 + ReLU: 8 x 32 pixel tiles (4 row tiles per wave) on the two
+// fine levels, 4 x 16 on the coarse ones, each where its input tile fits the
+// LDS budget; otherwise the row GEMM reading the input directly
 int conv_fwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B, hipStream_t st) {
+    if (l.lvl <= 1 && conv_tile_fits(8, 32, l)) {
+        switch (l.NTf) {
+            case 1: return launch_conv_tiled_nt<8, 32, 1>(N, l, s1, s2, y, B, st);
+            case 2: return launch_conv_tiled_nt<8, 32, 2>(N, l, s1, s2, y, B, st);
+            case 4: return launch_conv_tiled_nt<8, 32, 4>(N, l, s1, s2, y, B, st);
+            default: break;
+        }
+    }
+    if (conv_tile_fits(4, 16, l)) {
+        switch (l.NTf) {
+            case 1: return launch_conv_tiled_nt<4, 16, 1>(N, l, s1, s2, y, B, st);
+            case 2: return launch_conv_tiled_nt<4, 16, 2>(N, l, s1, s2, y, B, st);
+            case 4: return launch_conv_tiled_nt<4, 16, 4>(N, l, s1, s2, y, B, st);
+            case 8: return launch_conv_tiled_nt<4, 16, 8>(N, l, s1, s2, y, B, st);
+            case 16: return launch_conv_tiled_nt<4, 16, 16>(N, l, s1, s2, y, B, st);
+            default: break;
+        }
+    }
     SrcConv src{s1.a, s2 ? s2->a : nullptr, l.C1, l.C2, N.H >> l.lvl, N.W >> l.lvl};
     EpiConv epi{y.a, N.w + l.boff, l.Cout};
     return launch_rows(src, epi, l.Bf, pixels(N, l.lvl, B), l.KBf, l.NTf, st);
