@@ -38,7 +38,7 @@ namespace fem {
 
 namespace {
 
-constexpr int kSeg = 1024;      // shared nodes per fix-up item
+constexpr int kSeg = kBatchSeg;  // shared nodes per fix-up item
 constexpr int kBDots = 7;
 enum ItemType : unsigned long long { IT_CHUNK = 1, IT_FIX = 2, IT_FIN = 3 };
 
@@ -51,7 +51,8 @@ struct BatchArgs {
     const void *A;  // packed pair [2][NP][n_elems]: heads for iterations, hi + lo for refreshes
     double *x, *r, *p, *q;
     const double *dinv, *b;
-    double *sx, *sr, *sp, *sq, *sd;  // compact shared-node values [n_shared]
+    double *sx, *sr, *sp, *sq, *sd;  // shared-node tails of the local vectors [n_shared]
+    const double *sb;
     double *part;                    // shared-node partials [n_partials]
     const int32_t *pchunk0, *pshared0, *pseg0;  // [P+1]
     const int32_t *pgroup;                      // [P] chunks per CHUNK item
@@ -119,8 +120,8 @@ __device__ bool phase_done(const BatchArgs &a, int p, int n_items, int *s_last) 
 }
 
 // ---- element-pass policies ------------------------------------------------
-struct BOpIter {  // iteration round (see OpIter in pcg.hip)
-    static constexpr bool kLocal = false;
+struct BOpIter {  // iteration round (see OpIter in pcg.hip), solver-local vectors
+    static constexpr bool kLocal = true;
     double *x, *r, *p, *q;
     const double *dinv;
     double *sx, *sr, *sp, *sq;
@@ -194,13 +195,12 @@ struct BOpIter {  // iteration round (see OpIter in pcg.hip)
     }
 };
 
-struct BOpRefresh {  // refresh round: pending step on x, then r = b - A x
-    static constexpr bool kLocal = false;
+struct BOpRefresh {  // refresh round: pending step on x, then r = b - A x (solver-local vectors)
+    static constexpr bool kLocal = true;
     double *x, *r;
     const double *p, *dinv, *b;
     double *sx, *sr;
-    const double *sp, *sd;
-    const int32_t *fix_nodes;
+    const double *sp, *sd, *sb;
     double alpha;  // 0 when nothing is pending
     double d[kBDots];
     __device__ __forceinline__ double gather(int g, int sidx) {
@@ -218,10 +218,10 @@ struct BOpRefresh {  // refresh round: pending step on x, then r = b - A x
         d[5] += rv * dv * rv;
         d[6] += rv * rv;
     }
-    __device__ __forceinline__ void fixup_node(int s, int g, double acc) {
+    __device__ __forceinline__ void fixup_node(int s, int, double acc) {
         const double dv = sd[s];
         if (alpha != 0.0) sx[s] = __builtin_fma(alpha, sp[s], sx[s]);
-        const double rv = dv == 0.0 ? 0.0 : b[g] - acc;
+        const double rv = dv == 0.0 ? 0.0 : sb[s] - acc;
         sr[s] = rv;
         d[5] += rv * dv * rv;
         d[6] += rv * rv;
@@ -308,7 +308,7 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
 #pragma unroll
                 for (int t = 0; t < kBDots; ++t) d[t] = op.d[t];
             } else {
-                BOpRefresh op{a.x, a.r, a.p, a.dinv, a.b, a.sx, a.sr, a.sp, a.sd, P.fix_nodes,
+                BOpRefresh op{a.x, a.r, a.p, a.dinv, a.b, a.sx, a.sr, a.sp, a.sd, a.sb,
                               pr->pending ? pr->alpha : 0.0, {0, 0, 0, 0, 0, 0, 0}};
                 fix_loop(op, jj);
 #pragma unroll
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
                     store_dots<BS>(op.d, red.v, a.cdots + (int64_t)(c0 + cj) * kBDots);
                 }
             } else {
-                BOpRefresh op{a.x, a.r, a.p, a.dinv, a.b, a.sx, a.sr, a.sp, a.sd, P.fix_nodes,
+                BOpRefresh op{a.x, a.r, a.p, a.dinv, a.b, a.sx, a.sr, a.sp, a.sd, a.sb,
                               pr->pending ? pr->alpha : 0.0, {0, 0, 0, 0, 0, 0, 0}};
                 LdPk<NB, MAT_F32X2> ld{a.A, P.n_elems};
                 const int cj1 = min(nch, (j + 1) * grp);
@@ -564,12 +564,13 @@ int batch_launch(const BatchLaunch &L, hipStream_t s) {
     a.q = L.q;
     a.dinv = L.dinv;
     a.b = L.b;
-    const int64_t ns = std::max<int64_t>(L.P.n_shared, 1);
-    a.sx = L.shared;
-    a.sr = L.shared + ns;
-    a.sp = L.shared + 2 * ns;
-    a.sq = L.shared + 3 * ns;
-    a.sd = L.shared + 4 * ns;
+    const int64_t nc = L.P.n_nodes - L.P.n_shared;  // complete nodes; the shared ones are the tail
+    a.sx = L.x + nc;
+    a.sr = L.r + nc;
+    a.sp = L.p + nc;
+    a.sq = L.q + nc;
+    a.sd = const_cast<double *>(L.dinv) + nc;
+    a.sb = L.b + nc;
     a.part = L.part;
     a.pchunk0 = L.pchunk0;
     a.pshared0 = L.pshared0;

@@ -30,6 +30,8 @@ struct fem_batch {
     fem::BatchLaunch L{};
     float *Apk = nullptr;
     double *d64 = nullptr, *nu = nullptr;
+    double *xl = nullptr, *bl = nullptr;  // x and b in the solver-local node order
+    int32_t *perm = nullptr;              // local index -> union node id
     std::vector<fem::BatchProblem> host_prob;
     // captured graph and the arguments it was captured with
     hipGraphExec_t graph = nullptr;
@@ -55,22 +57,38 @@ struct Layout {
     }
 };
 
-__global__ void k_batch_dinv(int64_t n, const double *__restrict__ d, const uint8_t *__restrict__ mask,
-                             double *__restrict__ dinv) {
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        dinv[i] = (mask[i] || !(d[i] > 0.0)) ? 0.0 : 1.0 / d[i];
+// perm[local] = union node id: the complete nodes chunk by chunk, then the shared nodes
+__global__ void k_batch_perm(const fem::DevPlan P, int32_t *__restrict__ perm) {
+    for (int64_t c = blockIdx.x; c < P.n_chunks; c += gridDim.x) {
+        const int nb0 = P.chunk_node_off[c], ncomp = P.chunk_info[2 * c], off = P.comp_off[c];
+        for (int k = threadIdx.x; k < ncomp; k += blockDim.x) perm[off + k] = P.loc_nodes[nb0 + k];
+    }
+    const int64_t nc = P.comp_off[P.n_chunks];
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < P.n_shared;
+         s += (int64_t)gridDim.x * blockDim.x)
+        perm[nc + s] = P.fix_nodes[s];
 }
 
-__global__ void k_batch_shared(int64_t ns, const int32_t *__restrict__ nodes, double *x, const double *dinv,
-                               double *sx, double *sd, int to_compact) {
-    for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < ns; s += (int64_t)gridDim.x * 256) {
-        const int g = nodes[s];
-        if (to_compact) {
-            sx[s] = x[g];
-            sd[s] = dinv[g];
-        } else {
-            x[g] = sx[s];
-        }
+// dst[i] = src[perm[i]] (union order -> local order)
+__global__ void k_batch_gather(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ src,
+                               double *__restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        dst[i] = src[perm[i]];
+}
+
+// dst[perm[i]] = src[i] (local order -> union order)
+__global__ void k_batch_scatter(int64_t n, const int32_t *__restrict__ perm, const double *__restrict__ src,
+                                double *__restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        dst[perm[i]] = src[i];
+}
+
+// D^{-1} in local order, 0 on Dirichlet nodes
+__global__ void k_batch_dinv(int64_t n, const double *__restrict__ d, const uint8_t *__restrict__ mask,
+                             const int32_t *__restrict__ perm, double *__restrict__ dinv) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int g = perm[i];
+        dinv[i] = (mask[g] || !(d[g] > 0.0)) ? 0.0 : 1.0 / d[g];
     }
 }
 
@@ -79,7 +97,6 @@ int alloc_batch_work(fem_batch *B) {
     const fem::DevPlan &P = B->dev;
     const int64_t n = P.n_nodes, ne = P.n_elems;
     const int64_t npk = (int64_t)fem::packed_count(P.nb) * ne;
-    const int64_t ns = std::max<int64_t>(P.n_shared, 1);
     unsigned long long cap = 1;
     while (cap < (unsigned long long)(2 * (P.n_chunks + B->nprob) + 4096)) cap <<= 1;
     Layout L;
@@ -89,7 +106,9 @@ int alloc_batch_work(fem_batch *B) {
     size_t orr = L.add(n * sizeof(double));
     size_t opp = L.add(n * sizeof(double));
     size_t oqq = L.add(n * sizeof(double));
-    size_t osh = L.add((size_t)5 * ns * sizeof(double));
+    size_t oxl = L.add(n * sizeof(double));
+    size_t obl = L.add(n * sizeof(double));
+    size_t operm = L.add(n * sizeof(int32_t));
     size_t opart = L.add(std::max<int64_t>(P.n_partials, 1) * sizeof(double));
     size_t oprob = L.add((size_t)B->nprob * sizeof(fem::BatchProblem));
     size_t ocnt = L.add((size_t)B->nprob * sizeof(int));
@@ -115,7 +134,9 @@ int alloc_batch_work(fem_batch *B) {
     W.r = reinterpret_cast<double *>(b + orr);
     W.p = reinterpret_cast<double *>(b + opp);
     W.q = reinterpret_cast<double *>(b + oqq);
-    W.shared = reinterpret_cast<double *>(b + osh);
+    B->xl = reinterpret_cast<double *>(b + oxl);
+    B->bl = reinterpret_cast<double *>(b + obl);
+    B->perm = reinterpret_cast<int32_t *>(b + operm);
     W.part = reinterpret_cast<double *>(b + opart);
     W.prob = reinterpret_cast<fem::BatchProblem *>(b + oprob);
     W.cnt = reinterpret_cast<int *>(b + ocnt);
@@ -148,15 +169,15 @@ int enqueue_solve(fem_batch *B, const fem_batch_opts *o, const void *K, const vo
     if (rc) return rc;
     rc = fem::launch_diag_pk64(P, fem::MAT_F32X2, B->Apk, B->d64, B->scratch64, s);
     if (rc) return rc;
-    const int gv = (int)std::max<int64_t>(1, std::min<int64_t>((P.n_nodes + 255) / 256, 4096));
-    k_batch_dinv<<<gv, 256, 0, s>>>(P.n_nodes, B->d64, P.mask, const_cast<double *>(W.dinv));
-    const int64_t ns = std::max<int64_t>(P.n_shared, 1);
-    const int gs = (int)std::max<int64_t>(1, std::min<int64_t>((P.n_shared + 255) / 256, 4096));
-    if (P.n_shared > 0)
-        k_batch_shared<<<gs, 256, 0, s>>>(P.n_shared, P.fix_nodes, x, W.dinv, W.shared, W.shared + 4 * ns, 1);
+    const int64_t n = P.n_nodes;
+    const int gv = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+    k_batch_perm<<<gv, 256, 0, s>>>(P, B->perm);
+    k_batch_dinv<<<gv, 256, 0, s>>>(n, B->d64, P.mask, B->perm, const_cast<double *>(W.dinv));
+    k_batch_gather<<<gv, 256, 0, s>>>(n, B->perm, x, B->xl);
+    k_batch_gather<<<gv, 256, 0, s>>>(n, B->perm, b, B->bl);
     FEM_HIP_CHECK(hipGetLastError());
-    W.x = x;
-    W.b = b;
+    W.x = B->xl;
+    W.b = B->bl;
     W.rtol = o->rtol;
     W.delta = o->refresh;
     W.max_iter = o->max_iter;
@@ -166,8 +187,7 @@ int enqueue_solve(fem_batch *B, const fem_batch_opts *o, const void *K, const vo
     W.grid = o->grid;
     rc = fem::batch_launch(W, s);
     if (rc) return rc;
-    if (P.n_shared > 0)
-        k_batch_shared<<<gs, 256, 0, s>>>(P.n_shared, P.fix_nodes, x, W.dinv, W.shared, W.shared + 4 * ns, 0);
+    k_batch_scatter<<<gv, 256, 0, s>>>(n, B->perm, B->xl, x);
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
@@ -239,7 +259,7 @@ int fem_batch_create(int dim, int n_problems, const int64_t *node_off, const int
     std::vector<int32_t> pseg(n_problems + 1, 0);
     for (int p = 0; p < n_problems; ++p) {
         const int ns = H.shared0[p + 1] - H.shared0[p];
-        pseg[p + 1] = pseg[p] + (ns + 255) / 256;
+        pseg[p + 1] = pseg[p] + (ns + fem::kBatchSeg - 1) / fem::kBatchSeg;
     }
     const fem::HostPlan &U = H.U;
     Layout L;
@@ -249,6 +269,7 @@ int fem_batch_create(int dim, int n_problems, const int64_t *node_off, const int
     const size_t o_sl = L.add(U.slots.size() * 2), o_fn = L.add(U.fix_nodes.size() * 4);
     const size_t o_fo = L.add(U.fix_off.size() * 4), o_fp = L.add(U.fix_parts.size() * 4);
     const size_t o_po = L.add(U.part_owner.size() * 4), o_mask = L.add(U.mask.size());
+    const size_t o_co = L.add(U.comp_off.size() * 4);
     const size_t o_ce = L.add(H.chunk_elem0.size() * 8);
     const size_t o_pc = L.add((n_problems + 1) * 4), o_ps = L.add((n_problems + 1) * 4);
     const size_t o_pg = L.add((n_problems + 1) * 4), o_pe = L.add((n_problems + 1) * 8);
@@ -277,6 +298,7 @@ int fem_batch_create(int dim, int n_problems, const int64_t *node_off, const int
     up(o_fo, U.fix_off.data(), U.fix_off.size() * 4);
     up(o_fp, U.fix_parts.data(), U.fix_parts.size() * 4);
     up(o_po, U.part_owner.data(), U.part_owner.size() * 4);
+    up(o_co, U.comp_off.data(), U.comp_off.size() * 4);
     up(o_mask, U.mask.data(), U.mask.size());
     up(o_ce, H.chunk_elem0.data(), H.chunk_elem0.size() * 8);
     up(o_pc, H.chunk0.data(), (n_problems + 1) * 4);
@@ -311,7 +333,7 @@ int fem_batch_create(int dim, int n_problems, const int64_t *node_off, const int
     D.fix_off = reinterpret_cast<const int32_t *>(b + o_fo);
     D.fix_parts = reinterpret_cast<const int32_t *>(b + o_fp);
     D.part_owner = reinterpret_cast<const int32_t *>(b + o_po);
-    D.comp_off = nullptr;
+    D.comp_off = reinterpret_cast<const int32_t *>(b + o_co);
     D.mask = reinterpret_cast<const uint8_t *>(b + o_mask);
     B->pchunk0 = reinterpret_cast<int32_t *>(b + o_pc);
     B->pshared0 = reinterpret_cast<int32_t *>(b + o_ps);

@@ -219,7 +219,6 @@ __device__ __forceinline__ void chunk_range(const DevPlan &P, int64_t c, int64_t
 template <int NB, int EPT, int BS, class T, class Ld, class Op, bool DIAG>
 __device__ __forceinline__ void chunk_pass(const DevPlan &P, const Ld &ld, Op &op, T *__restrict__ partial,
                                            int64_t c, T *buf, uint16_t *sl) {
-    static_assert(!Op::kLocal, "chunk_pass addresses nodes by global id");
     int64_t e0;
     int ne;
     chunk_range(P, c, e0, ne);
@@ -234,6 +233,7 @@ __device__ __forceinline__ void chunk_pass(const DevPlan &P, const Ld &ld, Op &o
     const int nl = P.chunk_node_off[c + 1] - nb0;
     const int ncomp = P.chunk_info[2 * c];
     const int pbase = P.chunk_info[2 * c + 1];
+    const int coff = Op::kLocal ? P.comp_off[c] : 0;
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(P.slots + c * (int64_t)NB * P.E);
         uint4 *dst = reinterpret_cast<uint4 *>(sl);
@@ -243,7 +243,7 @@ __device__ __forceinline__ void chunk_pass(const DevPlan &P, const Ld &ld, Op &o
     __syncthreads();
     if constexpr (!DIAG) {
         for (int k = threadIdx.x; k < nl; k += BS) {
-            const int g = P.loc_nodes[nb0 + k];
+            const int g = Op::kLocal ? (k < ncomp ? coff + k : -1) : P.loc_nodes[nb0 + k];
             const int s0 = k ? P.loc_end[nb0 + k - 1] : 0;
             const int s1 = P.loc_end[nb0 + k];
             const T v = op.gather(g, k < ncomp ? -1 : P.part_owner[pbase + (k - ncomp)]);
@@ -274,7 +274,7 @@ __device__ __forceinline__ void chunk_pass(const DevPlan &P, const Ld &ld, Op &o
         const int s1 = P.loc_end[nb0 + k];
         T acc = (T)0;
         for (int s = s0; s < s1; ++s) acc += buf[sl[s]];
-        if (k < ncomp) op.finish(P.loc_nodes[nb0 + k], acc);
+        if (k < ncomp) op.finish(Op::kLocal ? coff + k : P.loc_nodes[nb0 + k], acc);
         else partial[pbase + (k - ncomp)] = acc;
     }
 }

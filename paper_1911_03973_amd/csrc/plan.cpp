@@ -315,6 +315,12 @@ int build_batch_plan(int dim, int n_problems, const int64_t *node_off, const int
     });
     U.chunk_node_off[U.n_chunks] = (int32_t)U.n_local;
     U.fix_off[U.n_shared] = (int32_t)U.n_partials;
+    U.comp_off.assign(U.n_chunks + 1, 0);
+    for (int64_t c = 0; c < U.n_chunks; ++c) U.comp_off[c + 1] = U.comp_off[c] + U.chunk_info[2 * c];
+    if ((int64_t)U.comp_off[U.n_chunks] + U.n_shared != NN) {
+        err = "internal error: complete and shared nodes do not partition the nodes";
+        return -1;
+    }
     B.chunk_elem0[U.n_chunks] = NE;
     (void)nloc;
     U.n_dirichlet = 0;

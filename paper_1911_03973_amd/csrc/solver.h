@@ -70,12 +70,13 @@ struct BatchProblem {
 };
 
 // Everything one persistent batched launch needs (device pointers).
+constexpr int kBatchSeg = 1024;  // shared nodes per fix-up segment of the batched solver
+
 struct BatchLaunch {
     DevPlan P;  // union of all problems
     const void *A;
-    double *x, *r, *p, *q;
+    double *x, *r, *p, *q;  // solver-local order (DevPlan::comp_off); shared nodes are the tail
     const double *dinv, *b;
-    double *shared;  // [5][n_shared]
     double *part;
     const int32_t *pchunk0, *pshared0, *pseg0;
     const int32_t *pgroup;  // [P] chunks per work item
