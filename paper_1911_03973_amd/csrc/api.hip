@@ -71,7 +71,7 @@ int alloc_work(fem_plan *plan, int slot, int dtype) {
     const int64_t n = P.n_nodes;
     const int64_t npk = (int64_t)fem::packed_count(P.nb) * P.n_elems;
     // the largest chunk grid (8 workgroups per CU) plus the fix-up grid
-    const int64_t npart = 8 * (int64_t)fem::device_cu_count() + fem::fixup_grid(P.n_shared) + 8;
+    const int64_t npart = 8 * (int64_t)fem::device_cu_count() + fem::fixup_grid(P.n_shared, fem::kFixDotsCap) + 8;
     ArenaLayout L;
     // FP64 packed operator, or FP32 hi/lo pair of it: the same bytes
     size_t oA = L.add((size_t)npk * sizeof(double));
@@ -191,6 +191,7 @@ int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_c
     const size_t o_fo = L.add(H.fix_off.size() * sizeof(int32_t));
     const size_t o_fp = L.add(H.fix_parts.size() * sizeof(int32_t));
     const size_t o_po = L.add(H.part_owner.size() * sizeof(int32_t));
+    const size_t o_fr = L.add(H.fix_rec.size() * sizeof(int32_t));
     const size_t o_co = L.add(H.comp_off.size() * sizeof(int32_t));
     const size_t o_mask = L.add(H.mask.size());
     const size_t o_s64 = L.add(std::max<int64_t>(H.n_partials, 1) * sizeof(double));
@@ -219,6 +220,7 @@ int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_c
     bad |= up(o_fo, H.fix_off.data(), H.fix_off.size() * sizeof(int32_t));
     bad |= up(o_fp, H.fix_parts.data(), H.fix_parts.size() * sizeof(int32_t));
     bad |= up(o_po, H.part_owner.data(), H.part_owner.size() * sizeof(int32_t));
+    bad |= up(o_fr, H.fix_rec.data(), H.fix_rec.size() * sizeof(int32_t));
     bad |= up(o_co, H.comp_off.data(), H.comp_off.size() * sizeof(int32_t));
     bad |= up(o_mask, H.mask.data(), H.mask.size());
     if (bad || hipStreamSynchronize(s) != hipSuccess) {
@@ -248,6 +250,7 @@ int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_c
     D.fix_off = reinterpret_cast<const int32_t *>(b + o_fo);
     D.fix_parts = reinterpret_cast<const int32_t *>(b + o_fp);
     D.part_owner = reinterpret_cast<const int32_t *>(b + o_po);
+    D.fix_rec = H.fix_rec.empty() ? nullptr : reinterpret_cast<const int32_t *>(b + o_fr);
     D.comp_off = reinterpret_cast<const int32_t *>(b + o_co);
     D.mask = reinterpret_cast<const uint8_t *>(b + o_mask);
     plan->scratch64 = reinterpret_cast<double *>(b + o_s64);
@@ -307,6 +310,7 @@ int fem_plan_check_host(int dim, int64_t n_nodes, int64_t n_elems, const double 
     out->index_bytes = (int64_t)(H.chunk_node_off.size() * 4 + H.chunk_info.size() * 4 + H.loc_nodes.size() * 4 +
                                  H.loc_end.size() * 2 + H.slots.size() * 2 + H.fix_nodes.size() * 4 +
                                  H.fix_off.size() * 4 + H.fix_parts.size() * 8 + H.comp_off.size() * 4 +
+                                 H.fix_rec.size() * 4 +
                                  H.mask.size());
     return FEM_OK;
 }

@@ -25,7 +25,17 @@ struct OpAffine {
     int use_mask;
     __device__ __forceinline__ bool begin() { return true; }
     __device__ __forceinline__ T gather(int g, int) const { return x[g]; }
-    __device__ __forceinline__ void fixup_node(int, int g, T acc) const { finish(g, acc); }
+    struct Pre {
+        T bv;
+        bool zero;
+    };
+    __device__ __forceinline__ Pre fixup_load(int, int g) const {
+        return {b ? b[g] : (T)0, use_mask && mask[g]};
+    }
+    __device__ __forceinline__ void fixup_store(int, int g, const Pre &pr, T acc) const {
+        const T v = pr.bv + sign * acc;
+        out[g] = pr.zero ? (T)0 : v;
+    }
     __device__ __forceinline__ void finish(int g, T acc) const {
         T v = (b ? b[g] : (T)0) + sign * acc;
         if (use_mask && mask[g]) v = (T)0;
@@ -49,7 +59,7 @@ int run_chunked(const DevPlan &P, const Ld &ld, const Op &op, T *scratch, hipStr
     if (rc) return rc;
     FEM_HIP_CHECK(hipGetLastError());
     if (P.n_shared > 0) {
-        k_chunk_fixup<kBlock, T, Op><<<fixup_grid(P.n_shared), kBlock, 0, s>>>(P, op, scratch, 0);
+        k_chunk_fixup<kFixBlock, T, Op><<<fixup_grid(P.n_shared), kFixBlock, 0, s>>>(P, op, scratch, 0);
         FEM_HIP_CHECK(hipGetLastError());
     }
     return 0;

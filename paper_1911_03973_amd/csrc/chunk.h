@@ -359,17 +359,35 @@ __global__ __launch_bounds__(BS) void k_chunk_main(const DevPlan P, const Ld ld,
 }
 
 // Shared nodes: one thread per node adds the node's partials in ascending
-// chunk order.  Dot-product partials of this kernel go to slot_base + block.
+// chunk order.  The op's own loads for the node (fixup_load) are issued
+// before the partials are summed, and the partial slots come from one
+// 16-byte record (DevPlan::fix_rec), so a node costs two dependent memory
+// round trips.  Dot-product partials of this kernel go to slot_base + block.
 template <int BS, class T, class Op>
 __global__ __launch_bounds__(BS) void k_chunk_fixup(const DevPlan P, Op op, const T *__restrict__ partial,
                                                     int slot_base) {
     __shared__ RedBuf<BS> red;
     if (!op.begin()) return;
     for (int64_t s = (int64_t)blockIdx.x * BS + threadIdx.x; s < P.n_shared; s += (int64_t)gridDim.x * BS) {
-        const int k0 = P.fix_off[s], k1 = P.fix_off[s + 1];
+        const int g = Op::kLocal ? -1 : P.fix_nodes[s];
+        const typename Op::Pre pre = op.fixup_load((int)s, g);
         T acc = (T)0;
-        for (int k = k0; k < k1; ++k) acc += partial[P.fix_parts[k]];
-        op.fixup_node((int)s, P.fix_nodes[s], acc);
+        if (P.fix_rec) {
+            const int4 rc = reinterpret_cast<const int4 *>(P.fix_rec)[s];
+            if (rc.x >= 0) acc += partial[rc.x];
+            if (rc.y >= 0) acc += partial[rc.y];
+            if (rc.z >= 0) acc += partial[rc.z];
+            if (rc.w >= 0) {
+                acc += partial[rc.w];
+            } else if (rc.w < -1) {
+                const int k1 = P.fix_off[s + 1];
+                for (int k = -2 - rc.w; k < k1; ++k) acc += partial[P.fix_parts[k]];
+            }
+        } else {
+            const int k0 = P.fix_off[s], k1 = P.fix_off[s + 1];
+            for (int k = k0; k < k1; ++k) acc += partial[P.fix_parts[k]];
+        }
+        op.fixup_store((int)s, g, pre, acc);
     }
     op.template end<BS>(red.v, slot_base + blockIdx.x);
 }
@@ -385,9 +403,15 @@ struct ChunkGrid {
 
 ChunkGrid chunk_grid(int64_t n_chunks, size_t lds, int bs = kBlock);
 
-inline int fixup_grid(int64_t n_shared) {
-    int64_t g = (n_shared + kBlock - 1) / kBlock;
-    return (int)(g < 1 ? 1 : (g > 1024 ? 1024 : g));
+// Fix-up launches: kFixBlock threads, one shared node each, grid-stride
+// beyond `cap` workgroups.  Passes that leave one dot-product partial per
+// workgroup cap the grid at kFixDotsCap, so that the single-workgroup
+// finalize has few partials to add.
+constexpr int kFixBlock = 256;
+constexpr int kFixDotsCap = 1024;
+inline int fixup_grid(int64_t n_shared, int cap = 16384) {
+    int64_t g = (n_shared + kFixBlock - 1) / kFixBlock;
+    return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
 // Calls f(std::integral_constant<int, EPT>) for the plan's chunk size and a

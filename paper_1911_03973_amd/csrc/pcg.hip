@@ -159,11 +159,15 @@ struct OpIter {
         q[g] = qv;
         pq_dots(p[g], r[g], dv, qv);
     }
-    __device__ __forceinline__ void fixup_node(int s, int, VT acc) {
-        const VT dv = sd[s];
+    struct Pre {
+        VT dv, r0, q0, x0, p0;
+    };
+    __device__ __forceinline__ Pre fixup_load(int s, int) const { return {sd[s], sr[s], sq[s], sx[s], sp[s]}; }
+    __device__ __forceinline__ void fixup_store(int s, int, const Pre &pr, VT acc) {
+        const VT dv = pr.dv;
         VT rn, xn, pn;
         bool wr;
-        advance(sr[s], sq[s], sx[s], sp[s], dv, rn, xn, pn, wr);
+        advance(pr.r0, pr.q0, pr.x0, pr.p0, dv, rn, xn, pn, wr);
         if (wr) {
             sr[s] = rn;
             sx[s] = xn;
@@ -412,7 +416,7 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, const double *b, double
     VT *partv = reinterpret_cast<VT *>(w.partv);
     const size_t lds = chunk_lds_bytes<NB, VT>(P.E);
     const ChunkGrid cg = chunk_grid(P.n_chunks, lds, BS);
-    const int gf = P.n_shared > 0 ? fixup_grid(P.n_shared) : 0;
+    const int gf = P.n_shared > 0 ? fixup_grid(P.n_shared, kFixDotsCap) : 0;
     const int npart = cg.grid + gf;
     const int gu = (int)std::max<int64_t>(1, std::min<int64_t>((n + 4 * kBlock - 1) / (4 * kBlock), 1024));
     const int gv = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 4096));
@@ -461,7 +465,7 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, const double *b, double
             if (timed) FEM_HIP_CHECK(hipEventRecord(ev.a[ev.used], s));
             k_chunk_main<NB, EPT, BS, VT, decltype(ld), OpIter<VT>, false>
                 <<<cg.grid, BS, lds, s>>>(P, ld, op, partv, cg.xcd);
-            if (gf) k_chunk_fixup<kBlock, VT, OpIter<VT>><<<gf, kBlock, 0, s>>>(P, op, partv, cg.grid);
+            if (gf) k_chunk_fixup<kFixBlock, VT, OpIter<VT>><<<gf, kFixBlock, 0, s>>>(P, op, partv, cg.grid);
             if (timed) {
                 FEM_HIP_CHECK(hipEventRecord(ev.b[ev.used], s));
                 ev.used++;

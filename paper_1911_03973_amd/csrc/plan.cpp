@@ -213,6 +213,12 @@ int build_host_plan(int dim, int64_t n_nodes, int64_t n_elems, const double *coo
             P.fix_parts[P.fix_off[s] + fill[s]++] = P.chunk_info[2 * c + 1] + (t - ncomp);
         }
     }
+    P.fix_rec.assign((size_t)4 * P.n_shared, -1);
+    for (int64_t s = 0; s < P.n_shared; ++s) {
+        const int32_t k0 = P.fix_off[s], cnt = P.fix_off[s + 1] - k0;
+        for (int i = 0; i < std::min(cnt, 4); ++i) P.fix_rec[4 * s + i] = P.fix_parts[k0 + i];
+        if (cnt > 4) P.fix_rec[4 * s + 3] = -2 - (k0 + 3);
+    }
     P.part_owner.assign(np, 0);
     for (int64_t s = 0; s < P.n_shared; ++s)
         for (int32_t k = P.fix_off[s]; k < P.fix_off[s + 1]; ++k) P.part_owner[P.fix_parts[k]] = (int32_t)s;

@@ -21,6 +21,10 @@ struct HostPlan {
     std::vector<int32_t> fix_off;         // [n_shared+1]
     std::vector<int32_t> fix_parts;       // [n_partials]
     std::vector<int32_t> part_owner;      // [n_partials] shared-node index of each partial slot
+    // [n_shared][4] the first partial slots of each shared node (ascending
+    // chunk order), -1 where it has fewer; with more than four, entry 3 is
+    // -2 - k and the slots from the fourth on are fix_parts[k .. fix_off[s+1])
+    std::vector<int32_t> fix_rec;
     std::vector<int32_t> comp_off;        // [n_chunks+1] prefix of the complete-node counts
     std::vector<uint8_t> mask;            // [n_nodes] Dirichlet flags
 };
@@ -41,6 +45,7 @@ struct DevPlan {
     const int32_t *fix_off;
     const int32_t *fix_parts;
     const int32_t *part_owner;
+    const int32_t *fix_rec;  // HostPlan::fix_rec; NULL: sum through fix_off / fix_parts
     // [n_chunks+1] prefix of the complete-node counts: complete node k of chunk
     // c has solver-local index comp_off[c] + k, shared node s has
     // comp_off[n_chunks] + s (a permutation of all nodes).  NULL for batches.
