@@ -5,6 +5,7 @@
 //   rhs       b = sum_e C_e^T M_e f_e                      (eq. (2)-(3))
 //   diagonal  d = sum_e C_e^T diag(K_e + nu M_e)
 #include <algorithm>
+#include <type_traits>
 
 #include "chunk.h"
 #include "kernels.h"
@@ -47,13 +48,31 @@ struct OpAffine {
 
 int g_cu = 0;
 
+// local nodes per thread held in registers by k_chunk_affine (a 1024-triangle
+// chunk of a structured mesh has about 560).  Used for the FP32 pass only:
+// with FP64 element matrices in registers the extra registers cost more
+// occupancy than the shorter load chains gain.
+constexpr int kAffineNodes = 3;
+
+// Element pass plus fix-up.  FP32 passes use k_chunk_affine with the
+// solver's workgroup size for the chunk size (default_block); FP64 passes,
+// whose element matrices take most of the registers, use k_chunk_main with
+// 256 threads (more elements in flight per thread: measured faster than
+// 512 threads for 1536-tetrahedron chunks).
 template <int NB, class T, class Ld, class Op, bool DIAG>
 int run_chunked(const DevPlan &P, const Ld &ld, const Op &op, T *scratch, hipStream_t s) {
     const size_t lds = chunk_lds_bytes<NB, T>(P.E);
-    const ChunkGrid cg = chunk_grid(P.n_chunks, lds);
-    int rc = dispatch_ept(P.E, [&](auto ept) {
-        k_chunk_main<NB, decltype(ept)::value, kBlock, T, Ld, Op, DIAG>
-            <<<cg.grid, kBlock, lds, s>>>(P, ld, op, scratch, cg.xcd);
+    constexpr bool kAffine = !DIAG && std::is_same<T, float>::value;
+    const int block = kAffine ? default_block(NB, P.E) : kBlock;
+    const ChunkGrid cg = chunk_grid(P.n_chunks, lds, block);
+    int rc = dispatch_tile(P.E, block, [&](auto bs, auto ept) {
+        constexpr int BS = decltype(bs)::value, EPT = decltype(ept)::value;
+        if constexpr (kAffine)
+            k_chunk_affine<NB, EPT, BS, kAffineNodes, T, Ld, Op><<<cg.grid, BS, lds, s>>>(P, ld, op, scratch, cg.xcd);
+        else if constexpr (BS == kBlock)
+            k_chunk_main<NB, EPT, BS, T, Ld, Op, DIAG><<<cg.grid, BS, lds, s>>>(P, ld, op, scratch, cg.xcd);
+        else
+            return set_error(-1, "internal error: unexpected workgroup size");
         return 0;
     });
     if (rc) return rc;

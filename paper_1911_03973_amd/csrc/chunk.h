@@ -358,6 +358,112 @@ __global__ __launch_bounds__(BS) void k_chunk_main(const DevPlan P, const Ld ld,
     op.template end<BS>(red.v, blockIdx.x);
 }
 
+// Chunk pass of ops that gather and finish by mesh node id (Op::kLocal
+// false; DIAG false): each thread keeps the node id, slot run and input
+// value of its first KN local nodes in registers, loaded right after the
+// element-matrix fetch and before the workgroup barrier, and requests the
+// op's finishing operands (fixup_load) before the barrier ahead of phase C,
+// so neither phase waits on a chain of dependent global loads.  Nodes beyond
+// KN * BS take the plain path.
+template <int NB, int EPT, int BS, int KN, class T, class Ld, class Op>
+__global__ __launch_bounds__(BS) void k_chunk_affine(const DevPlan P, const Ld ld, Op op, T *__restrict__ partial,
+                                                     int xcd) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *buf = reinterpret_cast<T *>(smem);
+    uint16_t *sl = reinterpret_cast<uint16_t *>(smem + (size_t)NB * P.E * sizeof(T));
+    for (int64_t it = 0;; ++it) {
+        const int64_t c = chunk_of(blockIdx.x, it, P.n_chunks, gridDim.x, xcd);
+        if (c < 0) break;
+        int64_t e0;
+        int ne;
+        chunk_range(P, c, e0, ne);
+        typename Ld::Regs R[EPT];
+#pragma unroll
+        for (int t = 0; t < EPT; ++t) {
+            const int le = t * BS + threadIdx.x;
+            if (le < ne) ld.fetch(e0 + le, R[t]);
+        }
+        const int nb0 = P.chunk_node_off[c];
+        const int nl = P.chunk_node_off[c + 1] - nb0;
+        const int ncomp = P.chunk_info[2 * c];
+        const int pbase = P.chunk_info[2 * c + 1];
+        int gk[KN];
+        unsigned run[KN];  // slot run [low 16 bits, high 16 bits)
+#pragma unroll
+        for (int j = 0; j < KN; ++j) {
+            const int k = threadIdx.x + j * BS;
+            gk[j] = 0;
+            run[j] = 0;
+            if (k < nl) {
+                gk[j] = P.loc_nodes[nb0 + k];
+                run[j] = (k ? (unsigned)P.loc_end[nb0 + k - 1] : 0u) | ((unsigned)P.loc_end[nb0 + k] << 16);
+            }
+        }
+        T xk[KN];
+#pragma unroll
+        for (int j = 0; j < KN; ++j) {
+            const int k = threadIdx.x + j * BS;
+            if (k < nl) xk[j] = op.gather(gk[j], -1);
+        }
+        __syncthreads();  // the previous chunk's phase C is done with buf / sl
+        {
+            const uint4 *src = reinterpret_cast<const uint4 *>(P.slots + c * (int64_t)NB * P.E);
+            uint4 *dst = reinterpret_cast<uint4 *>(sl);
+            const int nv = (ne * NB + 7) >> 3;
+            for (int k = threadIdx.x; k < nv; k += BS) dst[k] = src[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < KN; ++j) {
+            const int k = threadIdx.x + j * BS;
+            if (k < nl)
+                for (int s = (int)(run[j] & 0xFFFFu); s < (int)(run[j] >> 16); ++s) buf[sl[s]] = xk[j];
+        }
+        for (int k = threadIdx.x + KN * BS; k < nl; k += BS) {
+            const int s0 = P.loc_end[nb0 + k - 1], s1 = P.loc_end[nb0 + k];
+            const T v = op.gather(P.loc_nodes[nb0 + k], -1);
+            for (int s = s0; s < s1; ++s) buf[sl[s]] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < EPT; ++t) {
+            const int le = t * BS + threadIdx.x;
+            if (le < ne) {
+                T xe[NB], y[NB];
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) xe[jj] = buf[le * NB + jj];
+                Ld::apply(R[t], xe, y);
+#pragma unroll
+                for (int i = 0; i < NB; ++i) buf[le * NB + i] = y[i];
+            }
+        }
+        typename Op::Pre pk[KN];  // requested before the barrier: its latency overlaps the wait
+#pragma unroll
+        for (int j = 0; j < KN; ++j) {
+            const int k = threadIdx.x + j * BS;
+            if (k < ncomp) pk[j] = op.fixup_load(-1, gk[j]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < KN; ++j) {
+            const int k = threadIdx.x + j * BS;
+            if (k < nl) {
+                T acc = (T)0;
+                for (int s = (int)(run[j] & 0xFFFFu); s < (int)(run[j] >> 16); ++s) acc += buf[sl[s]];
+                if (k < ncomp) op.fixup_store(-1, gk[j], pk[j], acc);
+                else partial[pbase + (k - ncomp)] = acc;
+            }
+        }
+        for (int k = threadIdx.x + KN * BS; k < nl; k += BS) {
+            const int s0 = P.loc_end[nb0 + k - 1], s1 = P.loc_end[nb0 + k];
+            T acc = (T)0;
+            for (int s = s0; s < s1; ++s) acc += buf[sl[s]];
+            if (k < ncomp) op.finish(P.loc_nodes[nb0 + k], acc);
+            else partial[pbase + (k - ncomp)] = acc;
+        }
+    }
+}
+
 // Shared nodes: one thread per node adds the node's partials in ascending
 // chunk order.  The op's own loads for the node (fixup_load) are issued
 // before the partials are summed, and the partial slots come from one
