@@ -182,7 +182,7 @@ def run_batched(args, w):
     b = torch.empty(B.n_nodes, dtype=torch.float64, device="cuda")
     x = torch.empty(B.n_nodes, dtype=torch.float64, device="cuda")
     opts = fem.batch_opts(rtol=1e-8, block=args.block, use_graph=1, watchdog_seconds=60.0, group=args.group,
-                          items_per_phase=args.items, inline_segments=args.inline_segs,
+                          items_per_phase=args.items, inline_segments=args.inline_segs, adaptive=args.adaptive,
                           max_iter=min(args.max_iter, 100000))
 
     def step():
@@ -225,7 +225,8 @@ def run_batched(args, w):
         "iters_total": int(iters.sum()), "iters_max": int(iters.max()), "iters_min": int(iters.min()),
         "plan_seconds": round(t_plan, 3),
         "note": "value = algorithmic bytes of all element passes of the solve / solve wall time (whole job)",
-        "schedule": {"chunk_elems": st["chunk_elems"], "block": args.block, "items_per_phase": args.items},
+        "schedule": {"chunk_elems": st["chunk_elems"], "block": args.block, "items_per_phase": args.items,
+                     "adaptive": args.adaptive},
         "autotune": tuned,
     }
     print(json.dumps(out), flush=True)
@@ -418,6 +419,8 @@ def main():
     ap.add_argument("--batch-chunk", type=int, default=2048, help="batched: elements per chunk")
     ap.add_argument("--inline-segs", type=int, default=64,
                     help="batched: fix-up segments the last chunk item of a phase runs itself")
+    ap.add_argument("--adaptive", type=int, default=1,
+                    help="batched: regroup work items as problems finish (1) or keep the fixed schedule (0)")
     ap.add_argument("--autotune", action="store_true", help="batched: pick the schedule with the autotuner first")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-FCG vs Jacobi-PCG comparison")
     ap.add_argument("--learned-n", type=int, default=1024)

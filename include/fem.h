@@ -245,6 +245,12 @@ typedef struct {
                                 scalar step run by the workgroup finishing its
                                 last chunk item, one queue trip per iteration
                                 (default 64; 0: always separate items) */
+    int adaptive;            /* 1 (default; ignored when group > 0): once fewer
+                                problems are left than the workgroups can keep
+                                busy, a problem's phases are cut into more work
+                                items (down to one chunk each) and its fix-up
+                                runs as separate items.  Results are identical
+                                either way (partials are per chunk/segment). */
 } fem_batch_opts;
 
 typedef struct {

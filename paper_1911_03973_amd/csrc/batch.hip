@@ -13,7 +13,12 @@
 // The workgroup finishing a problem's last CHUNK item also runs its fix-up
 // (when it has at most inline_segs segments) and its scalar step, and the one
 // finishing the last FIX item runs the scalar step, so one iteration of a
-// problem costs one or two trips through the queue instead of three.
+// problem costs one or two trips through the queue instead of three.  With
+// `adaptive`, once fewer problems are left than the grid can keep busy, a
+// problem's next phase is cut into more CHUNK items (down to one chunk each,
+// aiming at two items per workgroup over the live problems) and its fix-up
+// goes to FIX items instead of running inline; partials are per chunk and
+// per segment, so the grouping never changes a result.
 // Nothing ever waits for another workgroup: a workgroup only waits for the
 // queue to hold an item, so the launch needs no co-residency, and it ends
 // when every problem is finished.  A wall-clock watchdog bounds every wait,
@@ -67,6 +72,7 @@ struct BatchArgs {
     double rtol, delta;
     int max_iter, max_refresh;
     int inline_segs;       // the last CHUNK item runs up to this many fix-up segments itself
+    int adaptive;          // regroup items by the number of live problems
     long long spin_ticks;  // watchdog, in 100 MHz ticks
 };
 
@@ -244,7 +250,7 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
     uint16_t *sl = reinterpret_cast<uint16_t *>(smem + (size_t)NB * a.P.E * sizeof(double));
     __shared__ RedBuf<BS> red;
     __shared__ unsigned long long s_item, s_base;
-    __shared__ int s_exit, s_last;
+    __shared__ int s_exit, s_last, s_few;
     __shared__ double s_sc[8];
     const DevPlan &P = a.P;
     while (true) {
@@ -284,7 +290,7 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
         const int j = (int)(item & 0xFFFFFFFull);
         BatchProblem *pr = a.prob + p;
         const int c0 = a.pchunk0[p], nch = a.pchunk0[p + 1] - c0;
-        const int grp = a.pgroup[p];  // chunks per CHUNK item of this problem
+        const int grp = pr->grp;  // chunks per CHUNK item of this phase
         const int nci = (nch + grp - 1) / grp;
         const int sh0 = a.pshared0[p], nsh = a.pshared0[p + 1] - sh0;
         const int sg0 = a.pseg0[p], nseg = a.pseg0[p + 1] - sg0;
@@ -380,7 +386,19 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
                         }
                     }
                 }
+                int items = (nch + pr->grp - 1) / pr->grp;
+                if (next != 0 && a.adaptive) {
+                    // aim at two items per workgroup over the problems still live
+                    const int live = max(1, a.nprob - __hip_atomic_load(a.ndone, __ATOMIC_RELAXED,
+                                                                         __HIP_MEMORY_SCOPE_AGENT));
+                    const int want = (int)((2 * gridDim.x + live - 1) / live);
+                    const int base = (nch + a.pgroup[p] - 1) / a.pgroup[p];
+                    items = min(nch, max(base, want));
+                    pr->grp = (nch + items - 1) / items;
+                    items = (nch + pr->grp - 1) / pr->grp;
+                }
                 s_sc[0] = (double)next;
+                s_sc[1] = (double)items;
             }
             __syncthreads();
             const int next = (int)s_sc[0];
@@ -391,7 +409,7 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
                     atomicAdd(a.ndone, 1);
                 }
             } else {
-                enqueue<BS>(a, IT_CHUNK, p, nci, &s_base);
+                enqueue<BS>(a, IT_CHUNK, p, (int)s_sc[1], &s_base);
             }
         };
         if (type == IT_CHUNK) {
@@ -424,8 +442,14 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
             }
             if (phase_done<BS>(a, p, nci, &s_last)) {
                 // the last CHUNK item of the phase: a few fix-up segments and the
-                // scalar step run here, so the phase costs one queue trip
-                if (nseg > a.inline_segs) {
+                // scalar step run here, so the phase costs one queue trip --
+                // unless few problems are left, when parallel FIX items are faster
+                if (threadIdx.x == 0)
+                    s_few = a.adaptive && nseg > 1 &&
+                            4 * (a.nprob - __hip_atomic_load(a.ndone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) <
+                                (int)gridDim.x;
+                __syncthreads();
+                if (nseg > a.inline_segs || s_few) {
                     enqueue<BS>(a, IT_FIX, p, nseg, &s_base);
                 } else {
                     for (int jj = 0; jj < nseg; ++jj) fix_segment(jj);
@@ -452,6 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_init(BatchArgs a, int64_t n_it
         z.round = 1;
         z.first = 1;
         z.status = FEM_ENOCONV;
+        z.grp = a.pgroup[p];
         a.prob[p] = z;
         a.cnt[p] = 0;
     }
@@ -577,6 +602,7 @@ int batch_launch(const BatchLaunch &L, hipStream_t s) {
     a.pseg0 = L.pseg0;
     a.pgroup = L.pgroup;
     a.inline_segs = L.inline_segs;
+    a.adaptive = L.adaptive;
     a.nprob = L.nprob;
     a.prob = L.prob;
     a.cnt = L.cnt;

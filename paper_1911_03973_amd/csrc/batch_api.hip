@@ -98,7 +98,9 @@ int alloc_batch_work(fem_batch *B) {
     const int64_t n = P.n_nodes, ne = P.n_elems;
     const int64_t npk = (int64_t)fem::packed_count(P.nb) * ne;
     unsigned long long cap = 1;
-    while (cap < (unsigned long long)(2 * (P.n_chunks + B->nprob) + 4096)) cap <<= 1;
+    // outstanding items: at most one phase per problem, i.e. its CHUNK items
+    // (<= its chunks) or its FIX items (its segments) plus one
+    while (cap < (unsigned long long)(2 * (P.n_chunks + B->n_seg + B->nprob) + 4096)) cap <<= 1;
     Layout L;
     size_t oA = L.add((size_t)npk * 2 * sizeof(float));
     size_t od = L.add(n * sizeof(double));
@@ -213,6 +215,7 @@ void fem_batch_opts_default(fem_batch_opts *o) {
     o->group = 0;
     o->items_per_phase = 32;
     o->inline_segments = 64;
+    o->adaptive = 1;
 }
 
 int fem_batch_create(int dim, int n_problems, const int64_t *node_off, const int64_t *elem_off,
@@ -416,7 +419,7 @@ int fem_batch_solve(fem_batch *B, const fem_batch_opts *o, const void *d_K_e, co
         if (B->isolated_free[p] > 0)
             return set_error(FEM_ESINGULAR, "problem " + std::to_string(p) + ": node outside every element");
     }
-    if (o->group < 0 || o->items_per_phase < 1 || o->inline_segments < 0)
+    if (o->group < 0 || o->items_per_phase < 1 || o->inline_segments < 0 || (o->adaptive != 0 && o->adaptive != 1))
         return set_error(FEM_EINVAL, "bad work-item schedule");
     if (int rc = alloc_batch_work(B)) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -430,6 +433,7 @@ int fem_batch_solve(fem_batch *B, const fem_batch_opts *o, const void *d_K_e, co
     }
     B->L.n_seed = it0[B->nprob];
     B->L.inline_segs = o->inline_segments;
+    B->L.adaptive = o->group > 0 ? 0 : o->adaptive;
     FEM_HIP_CHECK(hipMemcpyAsync(B->pgroup, grp.data(), B->nprob * sizeof(int32_t), hipMemcpyHostToDevice, s));
     FEM_HIP_CHECK(hipMemcpyAsync(B->pitem0, it0.data(), (B->nprob + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
     FEM_HIP_CHECK(hipMemcpyAsync(B->nu, h_nu, B->nprob * sizeof(double), hipMemcpyHostToDevice, s));

@@ -64,7 +64,8 @@ struct BatchProblem {
     int round;      // 0 iteration round, 1 refresh round
     int mode;       // IterMode of the next iteration round
     int pending;    // alpha * p not yet applied to x
-    int iters, refreshes, first, broken, pad;
+    int iters, refreshes, first, broken;
+    int grp;        // chunks per CHUNK item of the current phase
     double alpha, beta, rz;
     double r0, thr2, rel2, rr_true;
 };
@@ -81,6 +82,7 @@ struct BatchLaunch {
     const int32_t *pchunk0, *pshared0, *pseg0;
     const int32_t *pgroup;  // [P] chunks per work item
     int inline_segs;        // fix-up segments run inline by the last chunk item
+    int adaptive;           // regroup a problem's items by the number of problems left
     const int32_t *pitem0;  // [P+1] prefix of the work items of a chunk round
     int64_t n_seed;         // work items of one chunk round of all problems
     int nprob;

@@ -75,7 +75,7 @@ class BatchOpts(ctypes.Structure):
         ("dtype", ctypes.c_int), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int), ("refresh", ctypes.c_double),
         ("max_refresh", ctypes.c_int), ("block", ctypes.c_int), ("grid", ctypes.c_int),
         ("watchdog_seconds", ctypes.c_double), ("use_graph", ctypes.c_int), ("group", ctypes.c_int),
-        ("items_per_phase", ctypes.c_int), ("inline_segments", ctypes.c_int),
+        ("items_per_phase", ctypes.c_int), ("inline_segments", ctypes.c_int), ("adaptive", ctypes.c_int),
     ]
 
 

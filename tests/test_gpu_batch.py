@@ -109,3 +109,24 @@ def test_autotuners_return_valid_schedules():
 
     rb = autotune.autotune_batch(meshes, dirs, [1.0, 0.1], b_fn, chunks=(256,), blocks=(256,), items=(1, 4), iters=10)
     assert rb["items_per_phase"] in (1, 4) and len(rb["table"]) == 2
+
+
+def test_adaptive_grouping_gives_identical_bits():
+    """Regrouping a problem's chunks into more work items, and moving its
+    fix-up to separate items, once few problems are left (adaptive, the
+    default) leaves every sum in the same order: the solutions agree bit for
+    bit with the fixed schedule."""
+    ns = [40, 9, 25, 33, 14]
+    nus = [1.0, 1e-2, 30.0, 0.2, 5.0]
+    meshes = [inputs.square_mesh(n, jitter=0.2, seed=i + 20) for i, n in enumerate(ns)]
+    probs, B, K, M, b = _batch(meshes, nus, list(range(30, 35)), chunk=128)
+    outs = []
+    for adaptive in (1, 0):
+        x = torch.zeros(B.n_nodes, dtype=torch.float64, device="cuda")
+        rc, res, _ = B.solve(fem.batch_opts(use_graph=0, watchdog_seconds=20.0, items_per_phase=2,
+                                            adaptive=adaptive), K, M, nus, b, x)
+        assert rc == 0
+        outs.append((x.cpu().numpy(), [r["iters"] for r in res]))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1]
+    _check_solutions(probs, B, x, res)
