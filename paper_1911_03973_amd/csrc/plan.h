@@ -48,7 +48,8 @@ struct DevPlan {
     const int32_t *fix_rec;  // HostPlan::fix_rec; NULL: sum through fix_off / fix_parts
     // [n_chunks+1] prefix of the complete-node counts: complete node k of chunk
     // c has solver-local index comp_off[c] + k, shared node s has
-    // comp_off[n_chunks] + s (a permutation of all nodes).  NULL for batches.
+    // comp_off[n_chunks] + s (a permutation of all nodes; for a batch, of the
+    // union of its problems).
     const int32_t *comp_off;
     const uint8_t *mask;
 };
