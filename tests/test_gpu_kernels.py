@@ -19,6 +19,13 @@ pytestmark = pytest.mark.gpu
 fem = pytest.importorskip("paper_1911_03973_amd.fem")
 
 
+def _shuffled(mesh, seed):
+    """The same mesh with its elements in a seeded random order: every chunk
+    then touches most nodes, and every node lies in many chunks."""
+    order = np.random.default_rng(seed).permutation(mesh.n_elems)
+    return inputs.Mesh(coords=mesh.coords, elems=np.ascontiguousarray(mesh.elems[order]), n=mesh.n)
+
+
 def _meshes():
     return [
         ("tri_fig1_2elem", inputs.square_mesh(1, order="rowmajor"), 0),
@@ -29,6 +36,11 @@ def _meshes():
         ("tet_5_jitter_E64", inputs.cube_mesh(5, jitter=0.15, seed=6), 64),
         ("tet_9_jitter_default", inputs.cube_mesh(9, jitter=0.15, seed=7), 0),
         ("tet_12_E1536", inputs.cube_mesh(12), 1536),
+        # more local nodes per chunk than the FP32 pass holds in registers, and
+        # shared nodes with more partials than one fix-up record holds
+        ("tri_40_shuffled_E1024", _shuffled(inputs.square_mesh(40, jitter=0.2, seed=8), 9), 1024),
+        ("tri_24_shuffled_E128", _shuffled(inputs.square_mesh(24, jitter=0.2, seed=10), 11), 128),
+        ("tet_8_shuffled_E512", _shuffled(inputs.cube_mesh(8, jitter=0.1, seed=12), 13), 512),
     ]
 
 
