@@ -281,6 +281,10 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ src
 // (i, s) computes rows [64 i, 64 i + 64) over the pixel slice s into
 // partial[s][R1][N]; the slices are added in order afterwards.
 // ---------------------------------------------------------------------------
+// a8 / g8 return the operand for the 8 consecutive pixels p .. p + 7 of one
+// lane (0 from p1 on).  When the 8 pixels lie in one image row (W a multiple
+// of 8; p is then a multiple of 8) the pixel's row and column are computed
+// once, not per entry; otherwise entry by entry.  Same values either way.
 struct WSrcConv {  // conv3x3: r = tap * Cin + ci; r == R is the bias row
     const bf16 *src1, *src2;
     int C1, C2, H, W, R;
@@ -295,6 +299,30 @@ struct WSrcConv {  // conv3x3: r = tap * Cin + ci; r == R is the bias row
         const int64_t q = pix + (int64_t)dy * W + dx;
         return ci < C1 ? (float)src1[q * C1 + ci] : (float)src2[q * C2 + (ci - C1)];
     }
+    __device__ __forceinline__ bf8 a8(int64_t p, int r, int64_t p1) const {
+        bf8 v;
+        if (r == R || p + 8 > p1 || (W & 7)) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = (bf16)(p + i < p1 ? a(p + i, r) : 0.0f);
+            return v;
+        }
+        const int Cin = C1 + C2;
+        const int tap = r / Cin, ci = r - tap * Cin;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const int64_t row = p / W;
+        const int x0 = (int)(p - row * W);
+        const int y = (int)(row % H);
+        if (y + dy < 0 || y + dy >= H) return zero8();
+        const bool first = ci < C1;
+        const int C = first ? C1 : C2;
+        const bf16 *base = (first ? src1 + ci : src2 + (ci - C1)) + (p + (int64_t)dy * W + dx) * C;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int xx = x0 + i + dx;
+            v[i] = (xx >= 0 && xx < W) ? base[(int64_t)i * C] : (bf16)0.0f;
+        }
+        return v;
+    }
 };
 struct WGradConv {  // gy * (y > 0)
     const bf16 *gy, *y;
@@ -303,11 +331,23 @@ struct WGradConv {  // gy * (y > 0)
         const int64_t o = pix * N + n;
         return (float)y[o] > 0.0f ? (float)gy[o] : 0.0f;
     }
+    __device__ __forceinline__ bf8 g8(int64_t p, int n, int64_t p1) const {
+        bf8 v;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (bf16)(p + i < p1 ? g(p + i, n) : 0.0f);
+        return v;
+    }
 };
 struct WSrcUp {  // up-conv: r = ci; r == C is the bias row
     const bf16 *src;
     int C;
     __device__ __forceinline__ float a(int64_t pix, int r) const { return r == C ? 1.0f : (float)src[pix * C + r]; }
+    __device__ __forceinline__ bf8 a8(int64_t p, int r, int64_t p1) const {
+        bf8 v;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (bf16)(p + i < p1 ? a(p + i, r) : 0.0f);
+        return v;
+    }
 };
 struct WGradUp {  // column n = q * Cout + co: du at the fine position q of low pixel pix
     const bf16 *du;
@@ -315,6 +355,20 @@ struct WGradUp {  // column n = q * Cout + co: du at the fine position q of low 
     __device__ __forceinline__ float g(int64_t pix, int n) const {
         const int q = n / Cout, co = n - q * Cout;
         return (float)du[fine_pixel((int)pix, q, H, W) * Cout + co];
+    }
+    __device__ __forceinline__ bf8 g8(int64_t p, int n, int64_t p1) const {
+        bf8 v;
+        if (p + 8 > p1 || (W & 7)) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = (bf16)(p + i < p1 ? g(p + i, n) : 0.0f);
+            return v;
+        }
+        // low pixels p .. p+7 share a row: their fine pixels are 2 apart
+        const int q = n / Cout, co = n - q * Cout;
+        const bf16 *base = du + fine_pixel((int)p, q, H, W) * Cout + co;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = base[(int64_t)2 * i * Cout];
+        return v;
     }
 };
 
@@ -331,21 +385,12 @@ __global__ __launch_bounds__(256) void k_gemm_wgrad(WS ws, WG wg, int R1, int N,
     for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
     const int r = r0 + (lane & 15);
     for (int64_t pb = p0; pb < p1; pb += 32) {
-        bf8 a;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int64_t pix = pb + 8 * (lane >> 4) + i;
-            a[i] = (bf16)((pix < p1 && r < R1) ? ws.a(pix, r) : 0.0f);
-        }
+        const int64_t pl = pb + 8 * (lane >> 4);  // this lane's 8 pixels
+        const bf8 a = r < R1 ? ws.a8(pl, r, p1) : zero8();
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            bf8 bv;
             const int n = t * 16 + (lane & 15);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int64_t pix = pb + 8 * (lane >> 4) + i;
-                bv[i] = (bf16)((pix < p1 && n < N) ? wg.g(pix, n) : 0.0f);
-            }
+            const bf8 bv = n < N ? wg.g8(pl, n, p1) : zero8();
             acc[t] = mfma(a, bv, acc[t]);
         }
     }
