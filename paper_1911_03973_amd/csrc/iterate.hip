@@ -18,15 +18,19 @@
 //                        alpha = 1 / (d - beta / alpha) (the alpha/beta form
 //                        of the Section 2 listing)
 // The scalars depend only on (lam1, lam2, N, k) and are formed on the host in
-// FP64; each iteration is one element residual pass plus one vector update.
-// The ratio C_{k+1}/C_k is carried instead of C_k, which overflows after a
-// few thousand steps when lam1 << lam2.
+// FP64.  Each iteration is one element pass (OpStep): it forms the residual
+// of the current iterate node by node and applies the method's update to
+// that node at once, writing the new iterate to another buffer, so the
+// residual is never stored (the buffers rotate between steps).  The ratio
+// C_{k+1}/C_k is carried instead of C_k, which overflows after a few
+// thousand steps when lam1 << lam2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 
+#include "chunk.h"
 #include "common.h"
 #include "kernels.h"
 #include "solver.h"
@@ -36,30 +40,78 @@ namespace fem {
 
 namespace {
 
-// x += w r
-__global__ void k_axpy(int64_t n, double w, const double *__restrict__ r, double *__restrict__ x) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        x[i] += w * r[i];
-}
-
-// three-term step: x_new = x + a (x - x_prev) + w r; x_prev = x; x = x_new
-__global__ void k_three_term(int64_t n, double a, double w, const double *__restrict__ r, double *__restrict__ x,
-                             double *__restrict__ xp) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        const double xi = x[i];
-        x[i] = xi + a * (xi - xp[i]) + w * r[i];
-        xp[i] = xi;
+// One step of an iteration inside the element pass: r = b - A x on the node
+// (0 on Dirichlet nodes, as the masked residual), then
+//   STEP_AXPY   x_new = x + w r                      (Richardson, 2-level)
+//   STEP_THREE  x_new = x + a (x - x_prev) + w r     (3-level Chebyshev)
+//   STEP_DIR    p = r (first) or r + beta p, x_new = x + alpha p   (listing)
+// x is only read (the gather of every chunk needs it); x_new goes to its own
+// buffer.  The expressions are those of the stand-alone update kernels.
+enum StepKind { STEP_AXPY = 0, STEP_THREE = 1, STEP_DIR = 2 };
+struct OpStep {
+    static constexpr bool kLocal = false;
+    const double *x, *b, *xp;
+    double *xn, *p;
+    const uint8_t *mask;
+    int kind, first;
+    double w, a, beta;
+    __device__ __forceinline__ bool begin() const { return true; }
+    __device__ __forceinline__ double gather(int g, int) const { return x[g]; }
+    struct Pre {
+        double bv, xv, xpv, pv;
+        bool zero;
+    };
+    __device__ __forceinline__ Pre fixup_load(int, int g) const {
+        Pre pr;
+        pr.bv = b[g];
+        pr.xv = x[g];
+        pr.xpv = kind == STEP_THREE ? xp[g] : 0.0;
+        pr.pv = (kind == STEP_DIR && !first) ? p[g] : 0.0;
+        pr.zero = mask[g] != 0;
+        return pr;
     }
-}
-
-// p = r + beta p (beta ignored when first), x += alpha p
-__global__ void k_dir_step(int64_t n, double beta, double alpha, int first, const double *__restrict__ r,
-                           double *__restrict__ p, double *__restrict__ x) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        const double pi = first ? r[i] : r[i] + beta * p[i];
-        p[i] = pi;
-        x[i] += alpha * pi;
+    __device__ __forceinline__ void fixup_store(int, int g, const Pre &pr, double acc) const {
+        double r = pr.bv + (-1.0) * acc;
+        if (pr.zero) r = 0.0;
+        if (kind == STEP_AXPY) {
+            xn[g] = pr.xv + w * r;
+        } else if (kind == STEP_THREE) {
+            xn[g] = pr.xv + a * (pr.xv - pr.xpv) + w * r;
+        } else {
+            const double pi = first ? r : r + beta * pr.pv;
+            p[g] = pi;
+            xn[g] = pr.xv + a * pi;
+        }
     }
+    __device__ __forceinline__ void finish(int g, double acc) const { fixup_store(0, g, fixup_load(0, g), acc); }
+    template <int BS>
+    __device__ __forceinline__ void end(double *, int) const {}
+};
+
+// The fused step over the FP64 packed operator A (chunk pass + fix-up).
+int launch_step(const DevPlan &P, const double *A, const OpStep &op, double *scratch, hipStream_t s) {
+    const size_t lds = chunk_lds_bytes<3, double>(P.E) / 3 * P.nb;
+    const ChunkGrid cg = chunk_grid(P.n_chunks, lds);
+    int rc = dispatch_ept(P.E, [&](auto ept) -> int {
+        constexpr int EPT = decltype(ept)::value;
+        if (P.nb == 3) {
+            LdPk<3, MAT_F64> ld{A, P.n_elems};
+            k_chunk_main<3, EPT, kBlock, double, decltype(ld), OpStep, false>
+                <<<cg.grid, kBlock, lds, s>>>(P, ld, op, scratch, cg.xcd);
+        } else {
+            LdPk<4, MAT_F64> ld{A, P.n_elems};
+            k_chunk_main<4, EPT, kBlock, double, decltype(ld), OpStep, false>
+                <<<cg.grid, kBlock, lds, s>>>(P, ld, op, scratch, cg.xcd);
+        }
+        return 0;
+    });
+    if (rc) return rc;
+    FEM_HIP_CHECK(hipGetLastError());
+    if (P.n_shared > 0) {
+        k_chunk_fixup<kFixBlock, double, OpStep><<<fixup_grid(P.n_shared), kFixBlock, 0, s>>>(P, op, scratch, 0);
+        FEM_HIP_CHECK(hipGetLastError());
+    }
+    return 0;
 }
 
 struct IterWork {
@@ -83,7 +135,7 @@ int run_iteration(const DevPlan &P, int dtype, const void *K, const void *M, dou
         off += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
         return o;
     };
-    const size_t oA = take(npk * 8), or_ = take(n * 8), ov = take(n * 8),
+    const size_t oA = take(npk * 8), or_ = take(n * 8), ov = take(n * 8), ou = take(n * 8),
                  osc = take(std::max<int64_t>(P.n_partials, 1) * 8), opart = take((size_t)kDotBlocks * 8),
                  osum = take(64), optr = take(2 * sizeof(void *));
     if (hipMalloc(&w.arena, off) != hipSuccess) {
@@ -92,7 +144,8 @@ int run_iteration(const DevPlan &P, int dtype, const void *K, const void *M, dou
     }
     char *base = static_cast<char *>(w.arena);
     double *A = reinterpret_cast<double *>(base + oA), *r = reinterpret_cast<double *>(base + or_),
-           *v = reinterpret_cast<double *>(base + ov), *scratch = reinterpret_cast<double *>(base + osc),
+           *v = reinterpret_cast<double *>(base + ov), *u = reinterpret_cast<double *>(base + ou),
+           *scratch = reinterpret_cast<double *>(base + osc),
            *part = reinterpret_cast<double *>(base + opart), *sums = reinterpret_cast<double *>(base + osum);
     const double **ptrs = reinterpret_cast<const double **>(base + optr);
     const double *tab[2] = {r, r};
@@ -115,32 +168,53 @@ int run_iteration(const DevPlan &P, int dtype, const void *K, const void *M, dou
 
     const double d = 0.5 * (lam1 + lam2), c = 0.5 * (lam2 - lam1);
     const double pi = 3.14159265358979323846;
+    // iterate buffers: the caller's x and two workspace vectors rotate
+    double *xc = x, *xo = v, *xt = u;  // current, next, third (previous iterate of the 3-level method)
+    OpStep op{nullptr, b, nullptr, nullptr, nullptr, P.mask, STEP_AXPY, 0, 0.0, 0.0, 0.0};
+    auto step = [&](int kind, const double *xprev, double w_, double a_, double beta_, int first) -> int {
+        op.x = xc;
+        op.xp = xprev;
+        op.xn = xo;
+        op.p = u;
+        op.kind = kind;
+        op.first = first;
+        op.w = w_;
+        op.a = a_;
+        op.beta = beta_;
+        return launch_step(P, A, op, scratch, s);
+    };
     if (method == ITER_RICHARDSON || method == ITER_CHEB2) {
         for (int k = 0; k < iters; ++k) {
-            if (k > 0)
-                if (int rc = residual()) return rc;
             const double wk =
                 method == ITER_RICHARDSON ? 1.0 / d : 1.0 / (d + c * std::cos(pi * ((k % cycle) + 0.5) / cycle));
-            k_axpy<<<gv, kBlock, 0, s>>>(n, wk, r, x);
+            if (int rc = step(STEP_AXPY, nullptr, wk, 0.0, 0.0, 0)) return rc;
+            std::swap(xc, xo);
         }
     } else if (method == ITER_CHEB3) {
         const double sigma = d / c;
         double t_prev = 0.0, t = sigma;  // t = C_{k+1} / C_k at step k (C_1 / C_0 = sigma)
+        const double *xprev = nullptr;
         for (int k = 0; k < iters; ++k) {
-            if (k > 0)
-                if (int rc = residual()) return rc;
             if (k == 0) {
-                // x_prev = x0, x1 = x0 + r0 / d
-                FEM_HIP_CHECK(hipMemcpyAsync(v, x, n * 8, hipMemcpyDeviceToDevice, s));
-                k_axpy<<<gv, kBlock, 0, s>>>(n, 1.0 / d, r, x);
+                // x1 = x0 + r0 / d; x0 stays in its buffer as the previous iterate
+                if (int rc = step(STEP_AXPY, nullptr, 1.0 / d, 0.0, 0.0, 0)) return rc;
+                xprev = xc;
+                xc = xo;
+                xo = xt;
                 continue;
             }
             t_prev = t;
             t = 2.0 * sigma - 1.0 / t_prev;  // C_{k+1}/C_k from C_k/C_{k-1}
             // C_{k-1}/C_{k+1} = 1 / (t_prev t), C_k/C_{k+1} = 1 / t
-            k_three_term<<<gv, kBlock, 0, s>>>(n, 1.0 / (t_prev * t), 2.0 / (c * t), r, x, v);
+            if (int rc = step(STEP_THREE, xprev, 2.0 / (c * t), 1.0 / (t_prev * t), 0.0, 0)) return rc;
+            double *old_prev = const_cast<double *>(xprev);
+            xprev = xc;
+            xc = xo;
+            xo = old_prev;
         }
     } else {
+        // direction form: p in u, the iterate alternates between x and v
+        xo = v;
         double alpha = 1.0 / d;
         for (int k = 0; k < iters; ++k) {
             double beta = 0.0;
@@ -148,13 +222,13 @@ int run_iteration(const DevPlan &P, int dtype, const void *K, const void *M, dou
                 beta = 0.25 * (c * alpha) * (c * alpha);
                 alpha = 1.0 / (d - beta / alpha);
             }
-            k_dir_step<<<gv, kBlock, 0, s>>>(n, beta, alpha, k == 0, r, v, x);
-            if (int rc = residual()) return rc;
+            if (int rc = step(STEP_DIR, nullptr, 0.0, alpha, beta, k == 0)) return rc;
+            std::swap(xc, xo);
         }
     }
+    if (xc != x) FEM_HIP_CHECK(hipMemcpyAsync(x, xc, n * 8, hipMemcpyDeviceToDevice, s));
     FEM_HIP_CHECK(hipGetLastError());
-    if (method != ITER_CHEB3_LISTING || iters == 0)
-        if (int rc = residual()) return rc;
+    if (int rc = residual()) return rc;
     double rn = 0.0;
     if (int rc = norm(rn)) return rc;
     res.iters = iters;
