@@ -403,6 +403,93 @@ __global__ __launch_bounds__(256) void k_gemm_wgrad(WS ws, WG wg, int R1, int N,
         }
 }
 
+// Conv3x3 weight gradients with both operands staged through LDS.  For each
+// chunk of kWChunk pixels of its slice, workgroup (i, s) loads the 64 im2col
+// rows [64 i, 64 i + 64) and the masked output gradient gy * (y > 0) with
+// 16-byte loads (8 consecutive channels of one pixel: a row group shares its
+// tap when the channel counts are multiples of 8) and stores them transposed,
+// [row][pixel], so that each lane reads its 8 consecutive pixels of a row with
+// one 16-byte LDS read.  The MFMA operands, their order and the partials are
+// exactly those of k_gemm_wgrad<WSrcConv, WGradConv>.
+constexpr int kWChunk = 128;
+constexpr int kWPitch = kWChunk + 8;  // LDS row pitch in bf16 (272 bytes: 16-byte aligned rows)
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_wgrad_conv(WSrcConv ws, WGradConv wg, int R1, int N, int64_t P,
+                                                    float *__restrict__ partial) {
+    __shared__ __align__(16) bf16 sa[64 * kWPitch];
+    __shared__ __align__(16) bf16 sg[NT * 16 * kWPitch];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rb = blockIdx.x * 64;
+    const int r0 = rb + wave * 16;
+    const int s = blockIdx.y;
+    const int64_t p0 = (int64_t)s * kWSlice, p1 = std::min<int64_t>(P, p0 + kWSlice);
+    const int Cin = ws.C1 + ws.C2, H = ws.H, W = ws.W;
+    f4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t cb = p0; cb < p1; cb += kWChunk) {
+        __syncthreads();  // the previous chunk's operands are consumed
+        // A: items (pixel, group of 8 rows)
+        for (int it = threadIdx.x; it < kWChunk * 8; it += 256) {
+            const int pl = it % kWChunk, rg = it / kWChunk;
+            const int64_t p = cb + pl;
+            const int r = rb + 8 * rg;
+            bf8 v = zero8();
+            if (p < p1) {
+                if (r == ws.R) {
+                    v[0] = (bf16)1.0f;  // bias row; rows R+1.. are beyond R1
+                } else if (r < ws.R) {
+                    const int tap = r / Cin, ci = r - tap * Cin;
+                    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+                    const int64_t row = p / W;
+                    const int x = (int)(p - row * W), y = (int)(row % H);
+                    if (y + dy >= 0 && y + dy < H && x + dx >= 0 && x + dx < W) {
+                        const int64_t q = p + (int64_t)dy * W + dx;
+                        v = ci < ws.C1 ? ld8(ws.src1 + q * ws.C1 + ci) : ld8(ws.src2 + q * ws.C2 + (ci - ws.C1));
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sa[(8 * rg + j) * kWPitch + pl] = v[j];
+        }
+        // G: items (pixel, group of 8 output channels)
+        for (int it = threadIdx.x; it < kWChunk * 2 * NT; it += 256) {
+            const int pl = it % kWChunk, ng = it / kWChunk;
+            const int64_t p = cb + pl;
+            bf8 v = zero8();
+            if (p < p1) {
+                const bf8 g = ld8(wg.gy + p * N + 8 * ng), yv = ld8(wg.y + p * N + 8 * ng);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = (float)yv[j] > 0.0f ? g[j] : (bf16)0.0f;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sg[(8 * ng + j) * kWPitch + pl] = v[j];
+        }
+        __syncthreads();
+        if (r0 < R1) {
+            const int nks = (int)((std::min<int64_t>(p1 - cb, kWChunk) + 31) / 32);  // steps that start before p1
+            for (int ks = 0; ks < nks; ++ks) {
+                const int col = ks * 32 + 8 * (lane >> 4);
+                const bf8 a = *reinterpret_cast<const bf8 *>(sa + (wave * 16 + (lane & 15)) * kWPitch + col);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const bf8 bv = *reinterpret_cast<const bf8 *>(sg + (t * 16 + (lane & 15)) * kWPitch + col);
+                    acc[t] = mfma(a, bv, acc[t]);
+                }
+            }
+        }
+    }
+    if (r0 >= R1) return;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rr = r0 + 4 * (lane >> 4) + i, n = t * 16 + (lane & 15);
+            if (rr < R1 && n < N) partial[((int64_t)s * R1 + rr) * N + n] = acc[t][i];
+        }
+}
+
 // out[i] = sum_s partial[s][i], s in order
 __global__ void k_sum_splits(const float *__restrict__ partial, int splits, int64_t n, float *__restrict__ out) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -819,7 +906,22 @@ int conv_bwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const 
     const int R = 9 * l.Cin();
     WSrcConv ws{s1.a, s2 ? s2->a : nullptr, l.C1, l.C2, H, W, R};
     WGradConv wg{y.g, y.a, l.Cout};
-    if (int rc = launch_wgrad(N, ws, wg, R + 1, l.Cout, M, st)) return rc;
+    const int NTw = l.Cout / 16;
+    if (l.C1 % 8 == 0 && l.C2 % 8 == 0 && l.Cout % 16 == 0 && (NTw == 1 || NTw == 2 || NTw == 4 || NTw == 8)) {
+        const int64_t splits = wgrad_splits(M);
+        if (splits * (R + 1) * l.Cout > N.partial_cap || splits > 65535)
+            return set_error(FEM_EINVAL, "weight-gradient scratch too small");
+        dim3 grid((R + 1 + 63) / 64, (unsigned)splits);
+        switch (NTw) {
+            case 1: k_wgrad_conv<1><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, N.partial); break;
+            case 2: k_wgrad_conv<2><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, N.partial); break;
+            case 4: k_wgrad_conv<4><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, N.partial); break;
+            default: k_wgrad_conv<8><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, N.partial); break;
+        }
+        FEM_HIP_CHECK(hipGetLastError());
+    } else if (int rc = launch_wgrad(N, ws, wg, R + 1, l.Cout, M, st)) {
+        return rc;
+    }
     const int64_t n = (int64_t)(R + 1) * l.Cout;  // weights [tap][ci][co] then the bias: contiguous
     k_sum_splits<<<grid1(n), 256, 0, st>>>(N.partial, (int)wgrad_splits(M), n, N.g + l.woff);
     FEM_HIP_CHECK(hipGetLastError());
