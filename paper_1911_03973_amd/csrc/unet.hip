@@ -490,13 +490,27 @@ __global__ __launch_bounds__(256) void k_wgrad_conv(WSrcConv ws, WGradConv wg, i
         }
 }
 
+// sum_s x[s * stride], s = 0 .. splits-1 in order; kSumAhead loads are issued
+// before they are added, so the ordered sum is not a chain of round trips
+constexpr int kSumAhead = 32;
+__device__ __forceinline__ float ordered_sum(const float *__restrict__ x, int splits, int64_t stride) {
+    float v = 0.f;
+    int s = 0;
+    for (; s + kSumAhead <= splits; s += kSumAhead) {
+        float t[kSumAhead];
+#pragma unroll
+        for (int j = 0; j < kSumAhead; ++j) t[j] = x[(int64_t)(s + j) * stride];
+#pragma unroll
+        for (int j = 0; j < kSumAhead; ++j) v += t[j];
+    }
+    for (; s < splits; ++s) v += x[(int64_t)s * stride];
+    return v;
+}
+
 // out[i] = sum_s partial[s][i], s in order
 __global__ void k_sum_splits(const float *__restrict__ partial, int splits, int64_t n, float *__restrict__ out) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        float v = 0.f;
-        for (int s = 0; s < splits; ++s) v += partial[(int64_t)s * n + i];
-        out[i] = v;
-    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = ordered_sum(partial + i, splits, n);
 }
 
 // up-conv: rows [0, Cin) of partial[s][Cin+1][4 Cout] are the weights; the
@@ -507,7 +521,7 @@ __global__ void k_sum_splits_up(const float *__restrict__ partial, int splits, i
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         float v = 0.f;
         if (i < nw) {
-            for (int s = 0; s < splits; ++s) v += partial[(int64_t)s * per + i];
+            v = ordered_sum(partial + i, splits, per);
         } else {
             const int co = (int)(i - nw);
             for (int s = 0; s < splits; ++s)
