@@ -418,6 +418,57 @@ void fem_fcg_opts_default(fem_fcg_opts *o);
 int fem_fcg_solve(const fem_plan *plan, const fem_fcg_opts *opts, fem_unet *net, const void *d_K_e,
                   const void *d_M_e, const double *d_b, double *d_x, fem_fcg_info *info, void *stream);
 
+/* ---- Geometric multigrid on nested square meshes --------------------------
+ * The P1 operator's condition number grows like h^-2 (the reason the Section 3
+ * iterations need spectral bounds, and the preconditioning the paper calls for
+ * on fine meshes).  For the structured 2D meshes -- n x n squares cut along the
+ * (0,0)-(1,1) diagonal, node (i, j) numbered j (n + 1) + i -- the mesh of n/2
+ * squares is nested in that of n squares (red refinement), and a V-cycle over
+ * the hierarchy preconditions flexible CG:
+ *   prolongation  exact P1 interpolation (fine (2I,2J) <- coarse (I,J); an odd
+ *                 fine node <- the average of the two coarse ends of its edge,
+ *                 the diagonal edge included);
+ *   restriction   its transpose;
+ *   smoothing     `smooth` damped-Jacobi steps before and after (omega);
+ *   coarsest      exact solve through a dense inverse formed at setup.
+ * Every operator application is the element residual (eq. (4), Algorithm 1)
+ * through the FP64 packed difference form of the level's own K_e, M_e. */
+typedef struct fem_mg fem_mg;
+
+typedef struct {
+    double rtol;      /* stop at ||b - A x|| <= rtol ||b - A x0|| (true FP64 residual) */
+    int max_iter;     /* FCG iterations */
+    int smooth;       /* Jacobi steps before and after the coarse correction (>= 1) */
+    double omega;     /* Jacobi damping, in (0, 2); default 2/3 */
+    int max_replace;  /* restarts from the true residual when the recursive one met rtol */
+} fem_mg_opts;
+
+void fem_mg_opts_default(fem_mg_opts *o);
+
+/* levels >= 2 plans, finest first: plans[l] a plan of the grid_n[l] x grid_n[l]
+ * square mesh with grid_n[l] = 2 grid_n[l+1], its own Dirichlet set; d_K_e[l],
+ * d_M_e[l] its local matrices in `dtype` layout (d_M_e may be NULL when
+ * nu == 0).  The coarsest mesh may have at most 33 x 33 nodes.  The plans must
+ * outlive the hierarchy; the matrices are read during the call only (packed
+ * copies are kept).  FEM_EINVAL for a hierarchy that is not nested as
+ * described, FEM_ESINGULAR for a non-positive diagonal or a singular coarsest
+ * operator.  Synchronises `stream`. */
+int fem_mg_create(int levels, const fem_plan *const *plans, const int *grid_n, int dtype,
+                  const void *const *d_K_e, const void *const *d_M_e, double nu, void *stream, fem_mg **out);
+int fem_mg_destroy(fem_mg *mg);
+
+/* FCG(1) preconditioned by one V-cycle per iteration on the finest level's
+ * problem (K + nu M) u = b, Dirichlet rows masked; x: x0 on entry (Dirichlet
+ * values included), the solution on exit; info as fem_fcg_solve (pcg_iters,
+ * fell_back unused).  Synchronises `stream`. */
+int fem_mg_solve(fem_mg *mg, const fem_mg_opts *opts, const double *d_b, double *d_x, fem_fcg_info *info,
+                 void *stream);
+
+/* out = P^T A_level P zc for a vector zc of level level+1 (the Galerkin
+ * product; on nested meshes without jitter it equals A_{level+1} zc on free
+ * nodes).  For checking the transfer operators. */
+int fem_mg_galerkin_apply(fem_mg *mg, int level, const double *d_zc, double *d_out, void *stream);
+
 /* Thread-local message describing the last failure ("" if none). */
 const char *fem_last_error(void);
 

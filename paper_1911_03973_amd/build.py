@@ -21,7 +21,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["plan.cpp", "local.hip", "apply.hip", "pcg.hip", "batch.hip", "api.hip", "batch_api.hip", "unet.hip",
-           "fcg.hip", "iterate.hip"]
+           "fcg.hip", "iterate.hip", "mg.hip"]
 
 COMMON = [
     "-O3",

@@ -38,6 +38,8 @@ struct fem_plan {
     fem::SolverWork work[2];  // [0] FP64 solver, [1] mixed precision
 };
 
+fem::DevPlan fem::plan_device(const fem_plan *p) { return p->dev; }
+
 namespace {
 
 using fem::set_error;

@@ -40,49 +40,6 @@ __global__ void k_jacobi(int64_t n, const double *__restrict__ dinv, const doubl
         z[i] = dinv[i] * r[i];
 }
 
-__global__ void k_dinv_fcg(int64_t n, const double *__restrict__ d, const uint8_t *__restrict__ mask,
-                           double *__restrict__ dinv, int *__restrict__ bad) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        double v = 0.0;
-        if (!mask[i]) {
-            if (!(d[i] > 0.0)) *bad = 1;
-            v = 1.0 / d[i];
-        }
-        dinv[i] = v;
-    }
-}
-
-// p = z - beta p
-__global__ void k_dir(int64_t n, const double *__restrict__ z, double beta, double *__restrict__ p) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        p[i] = z[i] - beta * p[i];
-}
-
-// x += alpha p, r -= alpha q; partial r.r per block
-__global__ __launch_bounds__(kBlock) void k_step(int64_t n, double alpha, const double *__restrict__ p,
-                                                 const double *__restrict__ q, double *__restrict__ x,
-                                                 double *__restrict__ r, double *__restrict__ part) {
-    __shared__ double red[kBlock / kWave];
-    double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        x[i] += alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        s += ri * ri;
-    }
-    s = block_sum<kBlock>(s, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-// z = omega D^-1 r (first smoothing step from z = 0), or z += omega D^-1 rz
-__global__ void k_smooth(int64_t n, double omega, const double *__restrict__ dinv, const double *__restrict__ rz,
-                         double *__restrict__ z, int first) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        const double v = omega * dinv[i] * rz[i];
-        z[i] = first ? v : z[i] + v;
-    }
-}
-
 // s = (n . rz) / (n . A n), 0 when the network output is zero or the ratio is not finite
 __global__ void k_coarse_scale(const double *__restrict__ part, int blocks, double *__restrict__ sc) {
     if (threadIdx.x != 0) return;

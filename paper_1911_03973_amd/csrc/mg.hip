@@ -1,0 +1,474 @@
+// mg.hip -- geometric multigrid preconditioner on nested diagonal-cut grids.
+//
+// The condition number of the P1 operator grows like h^-2, which is why the
+// experiment of Section 3 needs its spectral bounds and why the paper points
+// to better preconditioning for fine meshes.  On the structured meshes of the
+// workloads (n x n squares cut along the (0,0)-(1,1) diagonal, node (i, j)
+// numbered j (n + 1) + i) the mesh of n/2 squares is nested in the mesh of n
+// squares: its triangles split into four (red refinement).  The P1 space of
+// the coarse mesh is then a subspace of the fine one, and the prolongation is
+// exact P1 interpolation:
+//   fine (2I, 2J)         <- coarse (I, J)
+//   fine (2I+1, 2J)       <- average of coarse (I, J), (I+1, J)
+//   fine (2I, 2J+1)       <- average of coarse (I, J), (I, J+1)
+//   fine (2I+1, 2J+1)     <- average of coarse (I, J), (I+1, J+1)  (diagonal edge)
+// The restriction is its transpose: a coarse node collects its fine node with
+// weight 1 and the six fine edge neighbours of that node, (+-1, 0), (0, +-1),
+// (1, 1) and (-1, -1), with weight 1/2.  With these, P^T A_h P equals the
+// operator assembled on the coarse mesh (Galerkin), which the tests check.
+//
+// One V-cycle from level l with residual r: `smooth` damped-Jacobi steps
+// z += omega D^-1 (r - A z) from z = 0, restriction of r - A z, the cycle on
+// the next level, z += P z_coarse, `smooth` more Jacobi steps; on the
+// coarsest level z = A^-1 r with a dense inverse formed once at setup.  Every
+// operator application is the element residual through the FP64 packed form;
+// Dirichlet rows stay zero in every correction.  The cycle preconditions
+// flexible CG (FCG(1), as in fcg.hip), judged by the true residual.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "fem.h"
+#include "kernels.h"
+#include "solver.h"
+#include "vec.h"
+
+namespace fem {
+
+namespace {
+
+// rc = P^T rf on the coarse grid of nc squares per side, 0 on coarse Dirichlet nodes
+__global__ void k_restrict(int nc, const double *__restrict__ rf, const uint8_t *__restrict__ mask_c,
+                           double *__restrict__ rc) {
+    const int mc = nc + 1, mf = 2 * nc + 1;
+    const int64_t total = (int64_t)mc * mc;
+    for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < total; id += (int64_t)gridDim.x * kBlock) {
+        const int I = (int)(id % mc), J = (int)(id / mc);
+        double v = 0.0;
+        if (!mask_c[id]) {
+            const int i = 2 * I, j = 2 * J;
+            auto f = [&](int a, int b) -> double {
+                return (a >= 0 && a < mf && b >= 0 && b < mf) ? rf[(int64_t)b * mf + a] : 0.0;
+            };
+            v = f(i, j) + 0.5 * (((f(i - 1, j) + f(i + 1, j)) + (f(i, j - 1) + f(i, j + 1))) +
+                                 (f(i + 1, j + 1) + f(i - 1, j - 1)));
+        }
+        rc[id] = v;
+    }
+}
+
+// zf += P zc, 0 on fine Dirichlet nodes (nc coarse squares per side)
+__global__ void k_prolong_add(int nc, const double *__restrict__ zc, const uint8_t *__restrict__ mask_f,
+                              double *__restrict__ zf) {
+    const int mc = nc + 1, mf = 2 * nc + 1;
+    const int64_t total = (int64_t)mf * mf;
+    for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < total; id += (int64_t)gridDim.x * kBlock) {
+        if (mask_f[id]) continue;
+        const int i = (int)(id % mf), j = (int)(id / mf);
+        const int I = i >> 1, J = j >> 1;
+        const double c00 = zc[(int64_t)J * mc + I];
+        double v;
+        if (!(i & 1) && !(j & 1)) v = c00;
+        else if ((i & 1) && !(j & 1)) v = 0.5 * (c00 + zc[(int64_t)J * mc + I + 1]);
+        else if (!(i & 1)) v = 0.5 * (c00 + zc[(int64_t)(J + 1) * mc + I]);
+        else v = 0.5 * (c00 + zc[(int64_t)(J + 1) * mc + I + 1]);
+        zf[id] += v;
+    }
+}
+
+// z = Ainv r (dense, row-major n x n)
+__global__ void k_dense_mv(int n, const double *__restrict__ Ainv, const double *__restrict__ r,
+                           double *__restrict__ z) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += Ainv[(int64_t)i * n + j] * r[j];
+        z[i] = s;
+    }
+}
+
+// e = unit vector j (length n)
+__global__ void k_unit(int64_t n, int64_t j, double *__restrict__ e) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        e[i] = i == j ? 1.0 : 0.0;
+}
+
+// Gauss-Jordan inversion with partial pivoting of a row-major n x n matrix
+bool invert(int n, std::vector<double> &a, std::vector<double> &inv) {
+    inv.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(a[(size_t)r * n + c]) > std::fabs(a[(size_t)piv * n + c])) piv = r;
+        const double pv = a[(size_t)piv * n + c];
+        if (!(std::fabs(pv) > 0.0) || !std::isfinite(pv)) return false;
+        if (piv != c)
+            for (int k = 0; k < n; ++k) {
+                std::swap(a[(size_t)piv * n + k], a[(size_t)c * n + k]);
+                std::swap(inv[(size_t)piv * n + k], inv[(size_t)c * n + k]);
+            }
+        const double s = 1.0 / pv;
+        for (int k = 0; k < n; ++k) {
+            a[(size_t)c * n + k] *= s;
+            inv[(size_t)c * n + k] *= s;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double f = a[(size_t)r * n + c];
+            if (f == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+                a[(size_t)r * n + k] -= f * a[(size_t)c * n + k];
+                inv[(size_t)r * n + k] -= f * inv[(size_t)c * n + k];
+            }
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+struct MgLevel {
+    DevPlan P{};
+    int n = 0;  // squares per side
+    double *A = nullptr, *dinv = nullptr, *r = nullptr, *z = nullptr, *t = nullptr, *scratch = nullptr;
+};
+
+}  // namespace fem
+
+struct fem_mg {
+    std::vector<fem::MgLevel> lv;
+    void *arena = nullptr;
+    double *Ainv = nullptr;  // coarsest level, dense inverse (Dirichlet rows / columns: identity)
+    int nc = 0;              // coarsest node count
+    // FCG vectors on the finest level
+    double *p = nullptr, *q = nullptr, *part = nullptr, *sums = nullptr;
+    const double **ptrs = nullptr;
+    int *bad = nullptr;
+    ~fem_mg() {
+        if (arena) (void)hipFree(arena);
+    }
+};
+
+namespace fem {
+
+// apply P^T A P on level l+1 vectors: used by tests through the C ABI
+int mg_galerkin_apply(fem_mg *mg, int l, const double *zc, double *out, hipStream_t s);
+
+namespace {
+
+int vcycle(fem_mg *mg, size_t l, const double *r, double *z, int smooth, double omega, hipStream_t s) {
+    MgLevel &L = mg->lv[l];
+    const int64_t n = (int64_t)(L.n + 1) * (L.n + 1);
+    const int gv = grid_for(n);
+    if (l + 1 == mg->lv.size()) {
+        k_dense_mv<<<(mg->nc + kBlock - 1) / kBlock, kBlock, 0, s>>>(mg->nc, mg->Ainv, r, z);
+        FEM_HIP_CHECK(hipGetLastError());
+        return 0;
+    }
+    k_smooth<<<gv, kBlock, 0, s>>>(n, omega, L.dinv, r, z, 1);
+    for (int k = 1; k < smooth; ++k) {
+        if (int rc = launch_apply_pk64(L.P, MAT_F64, L.A, z, r, L.t, -1.0, 1, L.scratch, s)) return rc;
+        k_smooth<<<gv, kBlock, 0, s>>>(n, omega, L.dinv, L.t, z, 0);
+    }
+    if (int rc = launch_apply_pk64(L.P, MAT_F64, L.A, z, r, L.t, -1.0, 1, L.scratch, s)) return rc;
+    MgLevel &C = mg->lv[l + 1];
+    const int64_t ncn = (int64_t)(C.n + 1) * (C.n + 1);
+    k_restrict<<<grid_for(ncn), kBlock, 0, s>>>(C.n, L.t, C.P.mask, C.r);
+    FEM_HIP_CHECK(hipGetLastError());
+    if (int rc = vcycle(mg, l + 1, C.r, C.z, smooth, omega, s)) return rc;
+    k_prolong_add<<<gv, kBlock, 0, s>>>(C.n, C.z, L.P.mask, z);
+    for (int k = 0; k < smooth; ++k) {
+        if (int rc = launch_apply_pk64(L.P, MAT_F64, L.A, z, r, L.t, -1.0, 1, L.scratch, s)) return rc;
+        k_smooth<<<gv, kBlock, 0, s>>>(n, omega, L.dinv, L.t, z, 0);
+    }
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+}  // namespace
+
+int mg_galerkin_apply(fem_mg *mg, int l, const double *zc, double *out, hipStream_t s) {
+    MgLevel &F = mg->lv[l], &C = mg->lv[l + 1];
+    const int64_t nf = (int64_t)(F.n + 1) * (F.n + 1);
+    const int gv = grid_for(nf);
+    k_unit<<<gv, kBlock, 0, s>>>(nf, -1, F.z);  // zero
+    k_prolong_add<<<gv, kBlock, 0, s>>>(C.n, zc, F.P.mask, F.z);
+    if (int rc = launch_apply_pk64(F.P, MAT_F64, F.A, F.z, nullptr, F.t, 1.0, 1, F.scratch, s)) return rc;
+    k_restrict<<<grid_for((int64_t)(C.n + 1) * (C.n + 1)), kBlock, 0, s>>>(C.n, F.t, C.P.mask, out);
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+}  // namespace fem
+
+namespace {
+fem_plan_stats plan_stats(const fem_plan *p) {
+    fem_plan_stats st{};
+    (void)fem_plan_get_stats(p, &st);
+    return st;
+}
+}  // namespace
+
+extern "C" {
+
+void fem_mg_opts_default(fem_mg_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->rtol = 1e-8;
+    o->max_iter = 500;
+    o->smooth = 2;
+    o->omega = 2.0 / 3.0;
+    o->max_replace = 4;
+}
+
+int fem_mg_create(int levels, const fem_plan *const *plans, const int *grid_n, int dtype, const void *const *K,
+                  const void *const *M, double nu, void *stream, fem_mg **out) {
+    using fem::set_error;
+    fem::last_error().clear();
+    if (!out) return set_error(FEM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (levels < 2 || levels > 16 || !plans || !grid_n || !K) return set_error(FEM_EINVAL, "bad level list");
+    if (dtype != FEM_F64 && dtype != FEM_F32 && dtype != FEM_F32X2) return set_error(FEM_EINVAL, "unknown dtype");
+    if (!std::isfinite(nu) || nu < 0.0) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
+    for (int l = 0; l < levels; ++l) {
+        if (!plans[l] || !K[l] || (nu != 0.0 && (!M || !M[l]))) return set_error(FEM_EINVAL, "NULL plan or matrix");
+        const fem_plan_stats st = plan_stats(plans[l]);
+        if (st.dim != 2 || grid_n[l] < 1 || st.n_nodes != (int64_t)(grid_n[l] + 1) * (grid_n[l] + 1) ||
+            st.n_elems != 2 * (int64_t)grid_n[l] * grid_n[l])
+            return set_error(FEM_EINVAL, "level " + std::to_string(l) + " is not an n x n diagonal-cut square mesh");
+        if (l > 0 && grid_n[l - 1] != 2 * grid_n[l])
+            return set_error(FEM_EINVAL, "each level must halve the squares per side");
+    }
+    const int nc = (grid_n[levels - 1] + 1) * (grid_n[levels - 1] + 1);
+    if (nc > 1089) return set_error(FEM_EINVAL, "the coarsest level may have at most 33 x 33 nodes");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    fem_mg *mg = new (std::nothrow) fem_mg();
+    if (!mg) return set_error(FEM_ENOMEM, "host allocation failed");
+    mg->lv.resize(levels);
+    mg->nc = nc;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+        return o;
+    };
+    std::vector<size_t> oA(levels), od(levels), odi(levels), or_(levels), oz(levels), ot(levels), osc(levels);
+    for (int l = 0; l < levels; ++l) {
+        mg->lv[l].P = fem::plan_device(plans[l]);
+        mg->lv[l].n = grid_n[l];
+        const fem::DevPlan &P = mg->lv[l].P;
+        const int64_t n = P.n_nodes;
+        oA[l] = take((size_t)fem::packed_count(P.nb) * P.n_elems * 8);
+        od[l] = take(n * 8);
+        odi[l] = take(n * 8);
+        or_[l] = take(n * 8);
+        oz[l] = take(n * 8);
+        ot[l] = take(n * 8);
+        osc[l] = take(std::max<int64_t>(P.n_partials, 1) * 8);
+    }
+    const int64_t n0 = mg->lv[0].P.n_nodes;
+    const size_t oinv = take((size_t)nc * nc * 8), ocol = take((size_t)nc * nc * 8), op = take(n0 * 8),
+                 oq = take(n0 * 8), opart = take((size_t)fem::kDotBlocks * 4 * 8), osum = take(8 * 8),
+                 optr = take(16 * sizeof(void *)), obad = take(sizeof(int));
+    if (hipMalloc(&mg->arena, off) != hipSuccess) {
+        (void)hipGetLastError();
+        delete mg;
+        return set_error(FEM_ENOMEM, "device allocation of the multigrid workspace failed");
+    }
+    char *b = static_cast<char *>(mg->arena);
+    for (int l = 0; l < levels; ++l) {
+        fem::MgLevel &L = mg->lv[l];
+        L.A = reinterpret_cast<double *>(b + oA[l]);
+        L.dinv = reinterpret_cast<double *>(b + odi[l]);
+        L.r = reinterpret_cast<double *>(b + or_[l]);
+        L.z = reinterpret_cast<double *>(b + oz[l]);
+        L.t = reinterpret_cast<double *>(b + ot[l]);
+        L.scratch = reinterpret_cast<double *>(b + osc[l]);
+    }
+    mg->Ainv = reinterpret_cast<double *>(b + oinv);
+    double *cols = reinterpret_cast<double *>(b + ocol);
+    mg->p = reinterpret_cast<double *>(b + op);
+    mg->q = reinterpret_cast<double *>(b + oq);
+    mg->part = reinterpret_cast<double *>(b + opart);
+    mg->sums = reinterpret_cast<double *>(b + osum);
+    mg->ptrs = reinterpret_cast<const double **>(b + optr);
+    mg->bad = reinterpret_cast<int *>(b + obad);
+    auto fail = [&](int rc) {
+        delete mg;
+        return rc;
+    };
+    int rc = 0;
+    if (hipMemsetAsync(mg->bad, 0, sizeof(int), s) != hipSuccess) rc = set_error(FEM_EHIP, "memset failed");
+    for (int l = 0; l < levels && !rc; ++l) {
+        fem::MgLevel &L = mg->lv[l];
+        const void *Ml = nu != 0.0 ? M[l] : nullptr;
+        rc = fem::launch_pack(L.P, dtype, K[l], Ml, nu, fem::MAT_F64, L.A, s);
+        if (!rc) rc = fem::launch_diag_pk64(L.P, fem::MAT_F64, L.A, reinterpret_cast<double *>(b + od[l]), L.scratch, s);
+        if (!rc) {
+            fem::k_dinv_fcg<<<fem::grid_for(L.P.n_nodes), fem::kBlock, 0, s>>>(
+                L.P.n_nodes, reinterpret_cast<double *>(b + od[l]), L.P.mask, L.dinv, mg->bad);
+            if (hipGetLastError() != hipSuccess) rc = set_error(FEM_EHIP, "kernel launch failed");
+        }
+    }
+    if (rc) return fail(rc);
+    int bad = 0;
+    if (hipMemcpyAsync(&bad, mg->bad, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(set_error(FEM_EHIP, "setup of the multigrid levels failed"));
+    }
+    if (bad) return fail(set_error(FEM_ESINGULAR, "a free node has a non-positive diagonal entry"));
+    // coarsest level: columns of the masked operator, Dirichlet rows / columns identity
+    fem::MgLevel &C = mg->lv[levels - 1];
+    for (int j = 0; j < nc && !rc; ++j) {
+        fem::k_unit<<<fem::grid_for(nc), fem::kBlock, 0, s>>>(nc, j, C.z);
+        rc = fem::launch_apply_pk64(C.P, fem::MAT_F64, C.A, C.z, nullptr, cols + (size_t)j * nc, 1.0, 1, C.scratch, s);
+    }
+    if (rc) return fail(rc);
+    std::vector<double> colh((size_t)nc * nc);
+    std::vector<uint8_t> mk(nc);
+    if (hipMemcpyAsync(colh.data(), cols, colh.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(mk.data(), C.P.mask, nc, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(set_error(FEM_EHIP, "download of the coarse operator failed"));
+    }
+    std::vector<double> a((size_t)nc * nc), inv;
+    for (int i = 0; i < nc; ++i)
+        for (int j = 0; j < nc; ++j) {
+            double v = colh[(size_t)j * nc + i];  // column j, row i
+            if (mk[i] || mk[j]) v = (i == j) ? 1.0 : 0.0;
+            a[(size_t)i * nc + j] = v;
+        }
+    if (!fem::invert(nc, a, inv)) return fail(set_error(FEM_ESINGULAR, "the coarsest operator is singular"));
+    if (hipMemcpyAsync(mg->Ainv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(set_error(FEM_EHIP, "upload of the coarse inverse failed"));
+    }
+    *out = mg;
+    return FEM_OK;
+}
+
+int fem_mg_destroy(fem_mg *mg) {
+    delete mg;
+    return FEM_OK;
+}
+
+int fem_mg_galerkin_apply(fem_mg *mg, int level, const double *d_zc, double *d_out, void *stream) {
+    using fem::set_error;
+    if (!mg || !d_zc || !d_out) return set_error(FEM_EINVAL, "NULL argument");
+    if (level < 0 || level + 1 >= (int)mg->lv.size()) return set_error(FEM_EINVAL, "bad level");
+    return fem::mg_galerkin_apply(mg, level, d_zc, d_out, reinterpret_cast<hipStream_t>(stream));
+}
+
+int fem_mg_solve(fem_mg *mg, const fem_mg_opts *o, const double *d_b, double *d_x, fem_fcg_info *info, void *stream) {
+    using namespace fem;
+    auto t0 = std::chrono::steady_clock::now();
+    last_error().clear();
+    if (!mg || !o || !info || !d_b || !d_x) return set_error(FEM_EINVAL, "NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    info->fell_back = -1;
+    if (!(o->rtol > 0.0 && o->rtol < 1.0) || o->max_iter < 1 || o->smooth < 1 || o->smooth > 64 ||
+        !(o->omega > 0.0 && o->omega < 2.0) || o->max_replace < 0)
+        return set_error(FEM_EINVAL, "bad multigrid options");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    MgLevel &F = mg->lv[0];
+    const DevPlan &P = F.P;
+    const int64_t n = P.n_nodes;
+    const int gv = grid_for(n);
+    double *r = F.r, *z = F.z, *p = mg->p, *q = mg->q;
+    // the finest level's r / z are the FCG residual and preconditioned residual;
+    // the V-cycle from level 0 reads r and writes z, using level-0 t as scratch.
+    // Dot tables: [0..2] x [3..5] = (z.r, z.p, z.q); [6..7] x [8..9] = (p.q, p.r); [3] x [3] = r.r
+    const double *tab[16] = {z, z, z, r, p, q, p, p, q, r};
+    FEM_HIP_CHECK(hipMemcpyAsync(mg->ptrs, tab, sizeof(tab), hipMemcpyHostToDevice, s));
+    double h[8];
+    auto fetch = [&](int cnt) -> int {
+        FEM_HIP_CHECK(hipMemcpyAsync(h, mg->sums, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+        FEM_HIP_CHECK(hipStreamSynchronize(s));
+        return 0;
+    };
+    auto true_residual = [&](double &rn) -> int {
+        if (int rc = launch_apply_pk64(P, MAT_F64, F.A, d_x, d_b, r, -1.0, 1, F.scratch, s)) return rc;
+        k_dots<1><<<gv, kBlock, 0, s>>>(n, mg->ptrs + 3, mg->ptrs + 3, mg->part);
+        k_dots_fin<<<1, 64, 0, s>>>(mg->part, gv, 1, mg->sums);
+        FEM_HIP_CHECK(hipGetLastError());
+        if (int rc = fetch(1)) return rc;
+        rn = std::sqrt(h[0]);
+        return 0;
+    };
+    int status = FEM_OK;
+    double rn = 0.0;
+    auto finish = [&](int st) {
+        info->status = st;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return st;
+    };
+    if (int rc = true_residual(rn)) return finish(rc);
+    info->r0 = rn;
+    if (!std::isfinite(rn)) return finish(set_error(FEM_EBREAKDOWN, "non-finite initial residual"));
+    if (rn == 0.0) return finish(FEM_OK);
+    const double target = o->rtol * rn;
+    bool restart = true;
+    double pq_prev = 1.0;
+    for (int it = 0; it < o->max_iter; ++it) {
+        if (int rc = vcycle(mg, 0, r, z, o->smooth, o->omega, s)) return finish(rc);
+        info->precond_calls += 1;
+        k_dots<3><<<gv, kBlock, 0, s>>>(n, mg->ptrs, mg->ptrs + 3, mg->part);  // z.r, z.p, z.q
+        k_dots_fin<<<1, 64, 0, s>>>(mg->part, gv, 3, mg->sums);
+        FEM_HIP_CHECK(hipGetLastError());
+        if (int rc = fetch(3)) return finish(rc);
+        const double zr = h[0], zq = h[2];
+        if (!(std::isfinite(zr) && zr > 0.0)) return finish(set_error(FEM_EBREAKDOWN, "r.z <= 0 in MG-FCG"));
+        if (restart) {
+            FEM_HIP_CHECK(hipMemcpyAsync(p, z, n * 8, hipMemcpyDeviceToDevice, s));
+        } else {
+            k_dir<<<gv, kBlock, 0, s>>>(n, z, zq / pq_prev, p);
+        }
+        restart = false;
+        if (int rc = launch_apply_pk64(P, MAT_F64, F.A, p, nullptr, q, 1.0, 1, F.scratch, s)) return finish(rc);
+        k_dots<2><<<gv, kBlock, 0, s>>>(n, mg->ptrs + 6, mg->ptrs + 8, mg->part);
+        k_dots_fin<<<1, 64, 0, s>>>(mg->part, gv, 2, mg->sums);
+        FEM_HIP_CHECK(hipGetLastError());
+        if (int rc = fetch(2)) return finish(rc);
+        const double pq = h[0], pr = h[1];
+        if (!(std::isfinite(pq) && pq > 0.0 && std::isfinite(pr)))
+            return finish(set_error(FEM_EBREAKDOWN, "p.q <= 0 in MG-FCG"));
+        const double alpha = pr / pq;
+        pq_prev = pq;
+        k_step<<<gv, kBlock, 0, s>>>(n, alpha, p, q, d_x, r, mg->part);
+        k_dots_fin<<<1, 64, 0, s>>>(mg->part, gv, 1, mg->sums);
+        FEM_HIP_CHECK(hipGetLastError());
+        if (int rc = fetch(1)) return finish(rc);
+        rn = std::sqrt(h[0]);
+        info->iters = it + 1;
+        if (!std::isfinite(rn)) return finish(set_error(FEM_EBREAKDOWN, "non-finite residual in MG-FCG"));
+        if (rn <= target) {
+            double rt = 0.0;
+            if (int rc = true_residual(rt)) return finish(rc);
+            rn = rt;
+            if (rt <= target) {
+                info->relres = rt / info->r0;
+                return finish(FEM_OK);
+            }
+            if (info->replacements >= o->max_replace) break;
+            info->replacements += 1;
+            restart = true;
+        }
+    }
+    double rt = 0.0;
+    if (int rc = true_residual(rt)) return finish(rc);
+    info->relres = rt / info->r0;
+    status = rt <= target ? FEM_OK : FEM_ENOCONV;
+    if (status == FEM_ENOCONV) set_error(FEM_ENOCONV, "MG-FCG reached the iteration limit");
+    return finish(status);
+}
+
+}  // extern "C"

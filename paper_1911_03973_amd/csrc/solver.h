@@ -10,6 +10,9 @@
 
 namespace fem {
 
+// The device index of a plan created by fem_plan_create (api.hip).
+DevPlan plan_device(const fem_plan *p);
+
 enum IterMode { MODE_CONTINUE = 0, MODE_FRESH = 1, MODE_FIRST = 2 };
 
 // Scalars of the CG recurrence.  Each field has exactly one writer kernel

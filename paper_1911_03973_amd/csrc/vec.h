@@ -1,5 +1,6 @@
-// vec.h -- deterministic nodal-vector reductions shared by the host-driven
-// solvers (fcg.hip, iterate.hip).  Each translation unit gets its own copy.
+// vec.h -- deterministic nodal-vector reductions and updates shared by the
+// host-driven solvers (fcg.hip, iterate.hip, mg.hip).  Each translation unit
+// gets its own copy.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -44,6 +45,50 @@ __global__ void k_dots_fin(const double *__restrict__ part, int blocks, int nv, 
     double s = 0.0;
     for (int b = 0; b < blocks; ++b) s += part[(int64_t)b * nv + j];
     out[j] = s;
+}
+
+// D^-1, 0 on Dirichlet nodes; *bad = 1 if a free node has d <= 0
+__global__ void k_dinv_fcg(int64_t n, const double *__restrict__ d, const uint8_t *__restrict__ mask,
+                           double *__restrict__ dinv, int *__restrict__ bad) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        double v = 0.0;
+        if (!mask[i]) {
+            if (!(d[i] > 0.0)) *bad = 1;
+            v = 1.0 / d[i];
+        }
+        dinv[i] = v;
+    }
+}
+
+// p = z - beta p
+__global__ void k_dir(int64_t n, const double *__restrict__ z, double beta, double *__restrict__ p) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        p[i] = z[i] - beta * p[i];
+}
+
+// x += alpha p, r -= alpha q; partial r.r per block
+__global__ __launch_bounds__(kBlock) void k_step(int64_t n, double alpha, const double *__restrict__ p,
+                                                 const double *__restrict__ q, double *__restrict__ x,
+                                                 double *__restrict__ r, double *__restrict__ part) {
+    __shared__ double red[kBlock / kWave];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        s += ri * ri;
+    }
+    s = block_sum<kBlock>(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// z = omega D^-1 r (first smoothing step from z = 0), or z += omega D^-1 rz
+__global__ void k_smooth(int64_t n, double omega, const double *__restrict__ dinv, const double *__restrict__ rz,
+                         double *__restrict__ z, int first) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const double v = omega * dinv[i] * rz[i];
+        z[i] = first ? v : z[i] + v;
+    }
 }
 
 int grid_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, kDotBlocks)); }

@@ -120,6 +120,14 @@ class IterInfo(ctypes.Structure):
 
 RICHARDSON, CHEBYSHEV2, CHEBYSHEV3, CHEBYSHEV3_LISTING = 0, 1, 2, 3
 
+
+class MgOpts(ctypes.Structure):
+    _fields_ = [
+        ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int), ("smooth", ctypes.c_int), ("omega", ctypes.c_double),
+        ("max_replace", ctypes.c_int),
+    ]
+
+
 _vp, _i64, _int, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
 _SIGS = {
     "fem_plan_create": [_int, _i64, _i64, _vp, _vp, _vp, _i64, _int, _vp, ctypes.POINTER(_vp)],
@@ -151,6 +159,10 @@ _SIGS = {
     "fem_unet_precondition": [_vp, _int, _vp, _dbl, _vp, _vp, _vp],
     "fem_fcg_solve": [_vp, ctypes.POINTER(FcgOpts), _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(FcgInfo), _vp],
     "fem_iterate": [_vp, ctypes.POINTER(IterOpts), _vp, _vp, _vp, _vp, ctypes.POINTER(IterInfo), _vp],
+    "fem_mg_create": [_int, _vp, _vp, _int, _vp, _vp, _dbl, _vp, ctypes.POINTER(_vp)],
+    "fem_mg_destroy": [_vp],
+    "fem_mg_solve": [_vp, ctypes.POINTER(MgOpts), _vp, _vp, ctypes.POINTER(FcgInfo), _vp],
+    "fem_mg_galerkin_apply": [_vp, _int, _vp, _vp, _vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -166,9 +178,11 @@ _lib.fem_fcg_opts_default.argtypes = [ctypes.POINTER(FcgOpts)]
 _lib.fem_fcg_opts_default.restype = None
 _lib.fem_iter_opts_default.argtypes = [ctypes.POINTER(IterOpts)]
 _lib.fem_iter_opts_default.restype = None
+_lib.fem_mg_opts_default.argtypes = [ctypes.POINTER(MgOpts)]
+_lib.fem_mg_opts_default.restype = None
 
 EXPORTED = sorted(list(_SIGS) + ["fem_last_error", "fem_solve_opts_default", "fem_batch_opts_default",
-                                 "fem_fcg_opts_default", "fem_iter_opts_default"])
+                                 "fem_fcg_opts_default", "fem_iter_opts_default", "fem_mg_opts_default"])
 
 
 def library():
@@ -587,3 +601,86 @@ def iterate(plan, opts, K, M, b, x, stream=None):
     _check(_lib.fem_iterate(plan.handle, ctypes.byref(opts), _ptr(K), _ptr(M), _ptr(b), _ptr(x), ctypes.byref(info),
                             _stream(stream)))
     return {k: getattr(info, k) for k, _ in info._fields_}
+
+
+# ---------------------------------------------------------------------------
+# Geometric multigrid on nested square meshes
+# ---------------------------------------------------------------------------
+
+def mg_opts(**kw):
+    o = MgOpts()
+    _lib.fem_mg_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class MG:
+    """Owns a fem_mg over plans of nested square meshes (finest first).  Keeps
+    references to the plans (which must outlive the hierarchy)."""
+
+    def __init__(self, plans, grid_n, dtype, K, M, nu, stream=None):
+        L = len(plans)
+        for l in range(L):
+            plans[l]._mat(K[l], dtype, "K_e")
+            if M is not None and M[l] is not None:
+                plans[l]._mat(M[l], dtype, "M_e")
+        ph = (_vp * L)(*[p.handle for p in plans])
+        gn = (ctypes.c_int * L)(*[int(g) for g in grid_n])
+        kh = (_vp * L)(*[_ptr(k) for k in K])
+        mh = (_vp * L)(*[(_ptr(m) if m is not None else None) for m in (M if M is not None else [None] * L)])
+        h = _vp()
+        _check(_lib.fem_mg_create(L, ph, gn, int(dtype), kh, mh, float(nu), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.plans = list(plans)
+        self.grid_n = [int(g) for g in grid_n]
+
+    @classmethod
+    def from_meshes(cls, meshes, dirichlets, nu, dtype=F64):
+        """Plans and local matrices for every level, then the hierarchy."""
+        plans, K, M = [], [], []
+        for mesh, nd in zip(meshes, dirichlets):
+            p = Plan.from_mesh(mesh, nd)
+            k = p.empty_matrix(dtype)
+            m = p.empty_matrix(dtype)
+            build_local_matrices(p, dtype, k, m, None)
+            plans.append(p)
+            K.append(k)
+            M.append(m)
+        mg = cls(plans, [m.n for m in meshes], dtype, K, M if nu != 0.0 else None, nu)
+        mg.K, mg.M = K, M
+        return mg
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("hierarchy destroyed")
+        return self._h
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.fem_mg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def solve(self, opts, b, x, stream=None, allow=(FEM_ENOCONV,)):
+        n = self.plans[0].n_nodes
+        _need(b, torch.float64, n, "b")
+        _need(x, torch.float64, n, "x")
+        info = FcgInfo()
+        _check(_lib.fem_mg_solve(self.handle, ctypes.byref(opts), _ptr(b), _ptr(x), ctypes.byref(info),
+                                 _stream(stream)), allow=allow)
+        return {k: getattr(info, k) for k, _ in info._fields_}
+
+    def galerkin_apply(self, level, zc, stream=None):
+        _need(zc, torch.float64, self.plans[level + 1].n_nodes, "zc")
+        out = torch.empty(self.plans[level + 1].n_nodes, dtype=torch.float64, device="cuda")
+        _check(_lib.fem_mg_galerkin_apply(self.handle, int(level), _ptr(zc), _ptr(out), _stream(stream)))
+        return out

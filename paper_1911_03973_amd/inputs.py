@@ -141,6 +141,28 @@ def square_mesh(n: int, order: str = "morton", jitter: float = 0.0, seed: int = 
     return Mesh(coords=coords, elems=elems, n=n)
 
 
+def square_hierarchy(mesh: Mesh, coarsest: int = 16, order: str = "morton") -> list:
+    """The meshes of n, n/2, ..., coarsest squares per side nested in `mesh`
+    (a square_mesh of n squares, n / coarsest a power of two): coarse node
+    (I, J) of level l takes the coordinates of fine node (2^l I, 2^l J), so a
+    jittered mesh keeps its jitter on every level.  Finest first."""
+    n = mesh.n
+    if n <= 0 or coarsest < 1 or n % coarsest or (n // coarsest) & (n // coarsest - 1):
+        raise ValueError("n / coarsest must be a power of two")
+    out = [mesh]
+    m = n + 1
+    level = 1
+    while n >> level >= coarsest:
+        nl = n >> level
+        c = square_mesh(nl, order=order)
+        ml = nl + 1
+        jj, ii = np.meshgrid(np.arange(ml), np.arange(ml), indexing="ij")
+        fine = (jj.ravel() << level) * m + (ii.ravel() << level)
+        out.append(Mesh(coords=np.ascontiguousarray(mesh.coords[fine]), elems=c.elems, n=nl))
+        level += 1
+    return out
+
+
 def cube_mesh(n: int, order: str = "morton", jitter: float = 0.0, seed: int = 0) -> Mesh:
     """Kuhn triangulation of (0,1)^3: n^3 cubes, 6 tetrahedra each."""
     if n < 1:

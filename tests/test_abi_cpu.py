@@ -109,3 +109,22 @@ def test_host_plan_isolated_nodes_and_empty_mesh():
 def test_solve_opts_defaults():
     o = fem.solve_opts()
     assert o.rtol == 1e-8 and o.precond == fem.PRECOND_JACOBI and o.check_every >= 1
+
+
+def test_square_hierarchy_is_nested():
+    """Every coarse node sits on the fine node (2^l I, 2^l J) and every level is
+    the generator's own mesh of n / 2^l squares (same triangles)."""
+    import numpy as np
+
+    from paper_1911_03973_amd import inputs
+
+    fine = inputs.square_mesh(32, jitter=0.2, seed=4)
+    levels = inputs.square_hierarchy(fine, coarsest=4)
+    assert [m.n for m in levels] == [32, 16, 8, 4]
+    for l, m in enumerate(levels):
+        ref = inputs.square_mesh(m.n)
+        np.testing.assert_array_equal(m.elems, ref.elems)
+        k = 1 << l
+        for J in range(m.n + 1):
+            for I in range(m.n + 1):
+                assert np.array_equal(m.coords[J * (m.n + 1) + I], fine.coords[(k * J) * 33 + k * I])

@@ -1,0 +1,81 @@
+"""Geometric multigrid on nested square meshes: the transfer operators against
+the Galerkin identity of nested P1 spaces, and MG-preconditioned FCG judged by
+the oracle's residual."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1911_03973_amd import inputs
+
+from problems import Problem, cuda
+
+pytestmark = pytest.mark.gpu
+
+fem = pytest.importorskip("paper_1911_03973_amd.fem")
+
+
+def _hierarchy(n, jitter, which, nu, coarsest=16, seed=0):
+    fine = inputs.square_mesh(n, jitter=jitter, seed=seed)
+    meshes = inputs.square_hierarchy(fine, coarsest=coarsest)
+    nds = [inputs.boundary_nodes(m, which) for m in meshes]
+    return meshes, nds, fem.MG.from_meshes(meshes, nds, nu)
+
+
+@pytest.mark.parametrize("n,which,nu", [(32, "all", 0.0), (64, "all", 0.5), (64, "x2=0", 2.0)])
+def test_galerkin_identity_on_nested_meshes(n, which, nu):
+    """Without jitter the coarse P1 space is a subspace of the fine one, so
+    P^T A_h P z = A_2h z on every free coarse node, for the stiffness and the
+    mass part alike: pins the prolongation weights and that the restriction is
+    their transpose."""
+    meshes, nds, mg = _hierarchy(n, 0.0, which, nu)
+    rng = np.random.default_rng(5)
+    for level in range(len(meshes) - 1):
+        mc = meshes[level + 1]
+        zc = rng.standard_normal(mc.n_nodes)
+        zc[nds[level + 1]] = 0.0
+        got = mg.galerkin_apply(level, cuda(zc)).cpu().numpy()
+        Kc, Mc, _ = oracle.local_matrices(mc.coords, mc.elems)
+        mask = oracle.mask_from_nodes(mc.n_nodes, nds[level + 1])
+        want = -oracle.residual(mc.n_nodes, mc.elems, Kc, Mc, nu, np.zeros(mc.n_nodes), zc, mask)
+        scale = np.abs(want).max()
+        assert np.abs(got - want).max() <= 1e-12 * scale, (level, np.abs(got - want).max() / scale)
+
+
+@pytest.mark.parametrize("jitter", [0.0, 0.2])
+def test_mg_fcg_converges_independently_of_the_mesh_size(jitter):
+    iters = []
+    for n in (64, 128, 256):
+        meshes, nds, mg = _hierarchy(n, jitter, "x2=0", 1.0, seed=n)
+        prob = Problem(meshes[0], nu=1.0, dirichlet="x2=0", f="sine", seed=n + 1)
+        x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+        info = mg.solve(fem.mg_opts(rtol=1e-8), cuda(prob.b), x)
+        print(n, info, flush=True)
+        assert info["status"] == fem.FEM_OK
+        xs = x.cpu().numpy()
+        r = oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, xs, prob.mask)
+        r0 = oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, np.zeros(prob.n), prob.mask)
+        assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8
+        iters.append(info["iters"])
+    # Jacobi-PCG needs ~2x the iterations per halving of h; the V-cycle keeps them flat
+    assert max(iters) <= 30 and max(iters) <= 1.5 * min(iters) + 2, iters
+
+
+def test_mg_solution_matches_single_level_solver():
+    meshes, nds, mg = _hierarchy(64, 0.2, "all", 0.3, seed=3)
+    prob = Problem(meshes[0], nu=0.3, dirichlet="all", f="sine", seed=9)
+    x0 = np.zeros(prob.n)
+    x = cuda(x0)
+    mg.solve(fem.mg_opts(rtol=1e-10), cuda(prob.b), x)
+    xo, _ = oracle.pcg(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, prob.mask, x0, rtol=1e-12)
+    assert np.abs(x.cpu().numpy() - xo).max() <= 1e-8 * np.abs(xo).max()
+
+
+def test_mg_rejects_a_hierarchy_that_is_not_nested():
+    meshes = [inputs.square_mesh(32), inputs.square_mesh(8)]
+    nds = [inputs.boundary_nodes(m) for m in meshes]
+    with pytest.raises(fem.FemError):
+        fem.MG.from_meshes(meshes, nds, 0.0)
+    with pytest.raises(fem.FemError):  # coarsest grid too large for the dense solve
+        big = inputs.square_hierarchy(inputs.square_mesh(128), coarsest=64)
+        fem.MG.from_meshes(big, [inputs.boundary_nodes(m) for m in big], 0.0)
