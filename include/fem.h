@@ -464,6 +464,14 @@ int fem_mg_destroy(fem_mg *mg);
 int fem_mg_solve(fem_mg *mg, const fem_mg_opts *opts, const double *d_b, double *d_x, fem_fcg_info *info,
                  void *stream);
 
+/* z = B r: one V-cycle on the finest level, as the solver applies it (smooth
+ * damped-Jacobi steps before and after, omega in (0, 2)).  r (n_nodes of the
+ * finest level, mesh order) is read on free nodes only; z is written on every
+ * node, 0 on Dirichlet nodes.  r and z must not alias.  Uses the hierarchy's
+ * own level vectors, so calls on one hierarchy must not overlap (launches on
+ * one stream are fine).  Asynchronous on `stream`. */
+int fem_mg_vcycle(fem_mg *mg, int smooth, double omega, const double *d_r, double *d_z, void *stream);
+
 /* out = P^T A_level P zc for a vector zc of level level+1 (the Galerkin
  * product; on nested meshes without jitter it equals A_{level+1} zc on free
  * nodes).  For checking the transfer operators. */

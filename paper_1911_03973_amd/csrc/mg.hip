@@ -82,14 +82,18 @@ __global__ void k_prolong_add(int nc, const double *__restrict__ zc, const uint8
     }
 }
 
-// z = Ainv r (dense, row-major n x n)
-__global__ void k_dense_mv(int n, const double *__restrict__ Ainv, const double *__restrict__ r,
-                           double *__restrict__ z) {
-    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        double s = 0.0;
-        for (int j = 0; j < n; ++j) s += Ainv[(int64_t)i * n + j] * r[j];
-        z[i] = s;
-    }
+// z = Ainv r (dense, row-major n x n): one wave per row, the lanes stride
+// the row (coalesced) and a butterfly adds their sums in a fixed order
+__global__ __launch_bounds__(kBlock) void k_dense_mv(int n, const double *__restrict__ Ainv,
+                                                     const double *__restrict__ r, double *__restrict__ z) {
+    const int lane = threadIdx.x % kWave;
+    const int row = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (row >= n) return;  // uniform across the wave
+    const double *a = Ainv + (int64_t)row * n;
+    double s = 0.0;
+    for (int j = lane; j < n; j += kWave) s += a[j] * r[j];
+    for (int off = kWave / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
+    if (lane == 0) z[row] = s;
 }
 
 // e = unit vector j (length n)
@@ -167,7 +171,7 @@ int vcycle(fem_mg *mg, size_t l, const double *r, double *z, int smooth, double 
     const int64_t n = (int64_t)(L.n + 1) * (L.n + 1);
     const int gv = grid_for(n);
     if (l + 1 == mg->lv.size()) {
-        k_dense_mv<<<(mg->nc + kBlock - 1) / kBlock, kBlock, 0, s>>>(mg->nc, mg->Ainv, r, z);
+        k_dense_mv<<<(mg->nc + kBlock / kWave - 1) / (kBlock / kWave), kBlock, 0, s>>>(mg->nc, mg->Ainv, r, z);
         FEM_HIP_CHECK(hipGetLastError());
         return 0;
     }
@@ -366,6 +370,16 @@ int fem_mg_galerkin_apply(fem_mg *mg, int level, const double *d_zc, double *d_o
     if (!mg || !d_zc || !d_out) return set_error(FEM_EINVAL, "NULL argument");
     if (level < 0 || level + 1 >= (int)mg->lv.size()) return set_error(FEM_EINVAL, "bad level");
     return fem::mg_galerkin_apply(mg, level, d_zc, d_out, reinterpret_cast<hipStream_t>(stream));
+}
+
+int fem_mg_vcycle(fem_mg *mg, int smooth, double omega, const double *d_r, double *d_z, void *stream) {
+    using fem::set_error;
+    fem::last_error().clear();
+    if (!mg || !d_r || !d_z) return set_error(FEM_EINVAL, "NULL argument");
+    if (d_r == d_z) return set_error(FEM_EINVAL, "r and z must not alias");
+    if (smooth < 1 || smooth > 64 || !(omega > 0.0 && omega < 2.0))
+        return set_error(FEM_EINVAL, "bad smoothing parameters");
+    return fem::vcycle(mg, 0, d_r, d_z, smooth, omega, reinterpret_cast<hipStream_t>(stream));
 }
 
 int fem_mg_solve(fem_mg *mg, const fem_mg_opts *o, const double *d_b, double *d_x, fem_fcg_info *info, void *stream) {

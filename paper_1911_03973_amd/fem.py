@@ -163,6 +163,7 @@ _SIGS = {
     "fem_mg_destroy": [_vp],
     "fem_mg_solve": [_vp, ctypes.POINTER(MgOpts), _vp, _vp, ctypes.POINTER(FcgInfo), _vp],
     "fem_mg_galerkin_apply": [_vp, _int, _vp, _vp, _vp],
+    "fem_mg_vcycle": [_vp, _int, _dbl, _vp, _vp, _vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -678,6 +679,16 @@ class MG:
         _check(_lib.fem_mg_solve(self.handle, ctypes.byref(opts), _ptr(b), _ptr(x), ctypes.byref(info),
                                  _stream(stream)), allow=allow)
         return {k: getattr(info, k) for k, _ in info._fields_}
+
+    def vcycle(self, r, smooth=2, omega=2.0 / 3.0, z=None, stream=None):
+        """z = B r, one V-cycle on the finest level."""
+        n = self.plans[0].n_nodes
+        _need(r, torch.float64, n, "r")
+        if z is None:
+            z = torch.empty(n, dtype=torch.float64, device="cuda")
+        _need(z, torch.float64, n, "z")
+        _check(_lib.fem_mg_vcycle(self.handle, int(smooth), float(omega), _ptr(r), _ptr(z), _stream(stream)))
+        return z
 
     def galerkin_apply(self, level, zc, stream=None):
         _need(zc, torch.float64, self.plans[level + 1].n_nodes, "zc")

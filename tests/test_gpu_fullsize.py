@@ -154,3 +154,36 @@ def test_full_size_batch_of_256_problems():
         r0 = oracle.residual(m.n_nodes, m.elems, Ko, Mo, nu, bo, np.zeros(m.n_nodes), mask)
         assert res[i]["status"] == 0
         assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8, (i, res[i])
+
+
+def test_full_size_multigrid_vcycle_and_solve():
+    """C2 through the multigrid hierarchy the benchmark uses (2048^2 -> 16^2):
+    the V-cycle operator is symmetric and positive on the full mesh (a
+    property at any size), and the oracle's FP64 residual of the MG-FCG
+    solution meets the 1e-8 target."""
+    mesh, nd, nu, f = _workload("c2")
+    meshes = inputs.square_hierarchy(mesh, coarsest=16)
+    nds = [inputs.boundary_nodes(m, "x2=0") for m in meshes]
+    mg = fem.MG.from_meshes(meshes, nds, nu)
+    rng = np.random.default_rng(8)
+    r1, r2 = rng.standard_normal(mesh.n_nodes), rng.standard_normal(mesh.n_nodes)
+    r1[nd] = 0.0
+    r2[nd] = 0.0
+    z1 = mg.vcycle(cuda(r1)).cpu().numpy()
+    z2 = mg.vcycle(cuda(r2)).cpu().numpy()
+    assert abs(r1 @ z2 - r2 @ z1) <= 1e-12 * np.linalg.norm(r1) * np.linalg.norm(z2)
+    assert r1 @ z1 > 0 and r2 @ z2 > 0
+    plan = mg.plans[0]
+    b = plan.empty_vector()
+    fem.assemble_rhs(plan, fem.F64, mg.M[0], cuda(f), b)
+    x = plan.empty_vector()
+    x.zero_()
+    info = mg.solve(fem.mg_opts(rtol=1e-8), b, x)
+    print("mg c2", info, flush=True)
+    assert info["status"] == fem.FEM_OK and info["iters"] <= 30
+    K, M, _ = oracle.local_matrices(mesh.coords, mesh.elems)
+    mask = oracle.mask_from_nodes(mesh.n_nodes, nd)
+    bo = oracle.rhs(mesh.n_nodes, mesh.elems, M, f)
+    r = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, bo, x.cpu().numpy(), mask)
+    r0 = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, bo, np.zeros(mesh.n_nodes), mask)
+    assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 import oracle
+import oracle.mg as omg
 from paper_1911_03973_amd import inputs
 
 from problems import Problem, cuda
@@ -79,3 +80,40 @@ def test_mg_rejects_a_hierarchy_that_is_not_nested():
     with pytest.raises(fem.FemError):  # coarsest grid too large for the dense solve
         big = inputs.square_hierarchy(inputs.square_mesh(128), coarsest=64)
         fem.MG.from_meshes(big, [inputs.boundary_nodes(m) for m in big], 0.0)
+
+
+@pytest.mark.parametrize("n,coarsest,jitter,which,nu,smooth", [
+    (16, 8, 0.0, "all", 0.0, 1),       # two levels
+    (32, 8, 0.0, "all", 0.0, 2),
+    (64, 16, 0.2, "x2=0", 0.5, 1),
+    (64, 8, 0.1, "all", 3.0, 3),       # four levels
+    (200, 25, 0.2, "x2=0", 1.0, 2),    # odd coarsest grid, many chunks and a ragged tail
+])
+def test_vcycle_matches_oracle(n, coarsest, jitter, which, nu, smooth):
+    """One V-cycle z = B r element by element against the oracle's cycle
+    (its own local matrices, sparse P from barycentric evaluation, dense LU on
+    the coarsest level).  r is nonzero on Dirichlet nodes too: both sides must
+    ignore it there.  Tolerance: every step is a linear map of norm O(1) in
+    FP64 except the coarsest solve, whose relative error is bounded by its
+    condition number (< 10^3 for at most 33^2 nodes) times 1e-16."""
+    seed = n + smooth
+    print(f"vcycle n={n} coarsest={coarsest} jitter={jitter} {which} nu={nu} smooth={smooth}", flush=True)
+    meshes, nds, mg = _hierarchy(n, jitter, which, nu, coarsest=coarsest, seed=seed)
+    levels, Ps = omg.hierarchy(meshes, nds, nu)
+    r = np.random.default_rng(seed).standard_normal(meshes[0].n_nodes)
+    for omega in (2.0 / 3.0, 0.9):
+        got = mg.vcycle(cuda(r), smooth, omega).cpu().numpy()
+        want = omg.vcycle(levels, Ps, r, smooth, omega)
+        scale = np.abs(want).max()
+        assert np.abs(got - want).max() <= 1e-12 * scale, (omega, np.abs(got - want).max() / scale)
+        assert np.all(got[nds[0]] == 0.0)
+
+
+def test_vcycle_rejects_bad_arguments():
+    meshes, nds, mg = _hierarchy(32, 0.0, "all", 0.0)
+    r = cuda(np.ones(meshes[0].n_nodes))
+    for smooth, omega in [(0, 0.5), (65, 0.5), (2, 0.0), (2, 2.0)]:
+        with pytest.raises(fem.FemError):
+            mg.vcycle(r, smooth, omega)
+    with pytest.raises(fem.FemError):
+        mg.vcycle(r, 2, 0.5, z=r)
