@@ -103,23 +103,33 @@ def residual_kernels(fem, plan, mesh, K, M, nu, dt, calls):
 
     nb = mesh.nb
     out = {}
-    A32 = plan.empty_matrix(fem.F32)
-    fem.combine_local(plan, dt, K, M, nu, fem.F32, A32)
-    Ap = plan.empty_matrix(fem.F32X2)
-    fem.combine_local(plan, dt, K, M, nu, fem.F32X2, Ap)
     g = torch.Generator(device="cuda").manual_seed(0)
     x32 = torch.rand(mesh.n_nodes, device="cuda", generator=g, dtype=torch.float32)
     b32 = torch.rand(mesh.n_nodes, device="cuda", generator=g, dtype=torch.float32)
     r32 = torch.empty_like(x32)
     x64, b64, r64 = x32.double(), b32.double(), torch.empty(mesh.n_nodes, dtype=torch.float64, device="cuda")
-    cases = [
-        ("f32", lambda: fem.element_residual_f32(plan, A32, b32, x32, r32, mask=True),
-         mesh.n_elems * (nb * nb * 4 + 4 * nb) + mesh.n_nodes * 3 * 4),
-        ("f64_from_hi_lo", lambda: fem.element_residual(plan, fem.F32X2, Ap, None, 0.0, b64, x64, r64, mask=True),
-         mesh.n_elems * (nb * nb * 8 + 4 * nb) + mesh.n_nodes * 3 * 8),
-    ]
+    A32 = Ap = None
+    cases = []
+    if dt != fem.MFREE:
+        A32 = plan.empty_matrix(fem.F32)
+        fem.combine_local(plan, dt, K, M, nu, fem.F32, A32)
+        Ap = plan.empty_matrix(fem.F32X2)
+        fem.combine_local(plan, dt, K, M, nu, fem.F32X2, Ap)
+        cases += [
+            ("f32", lambda: fem.element_residual_f32(plan, A32, b32, x32, r32, mask=True),
+             mesh.n_elems * (nb * nb * 4 + 4 * nb) + mesh.n_nodes * 3 * 4),
+            ("f64_from_hi_lo", lambda: fem.element_residual(plan, fem.F32X2, Ap, None, 0.0, b64, x64, r64, mask=True),
+             mesh.n_elems * (nb * nb * 8 + 4 * nb) + mesh.n_nodes * 3 * 8),
+        ]
+    # matrix-free FP64: connectivity-equivalent index, coordinates, x and b read, r written
+    cases.append(("f64_mfree", lambda: fem.element_residual(plan, fem.MFREE, None, None, nu, b64, x64, r64, mask=True),
+                  mesh.n_elems * 4 * nb + mesh.n_nodes * (mesh.dim + 3) * 8))
     for name, fn, nbytes in cases:
-        fn()
+        try:
+            fn()
+        except fem.FemError as e:  # chunk LDS above the workgroup limit
+            out[name] = {"refused": str(e)}
+            continue
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -533,6 +543,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--vectors", type=int, default=0, help="mixed precision: 0 FP64, 1 FP32 iteration vectors")
     ap.add_argument("--block", type=int, default=0, help="workgroup size of the element pass (0 = default)")
+    ap.add_argument("--operator", choices=["stored", "mfree"], default="stored",
+                    help="c1-c3: stored local matrices (the workload's storage) or the matrix-free operator")
     ap.add_argument("--residual-calls", type=int, default=20)
     ap.add_argument("--max-iter", type=int, default=200000, help="cap on CG iterations (profiling runs)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -578,17 +590,21 @@ def main():
     w = WORKLOADS[args.workload]
     if args.workload == "c4":
         return run_batched(args, w)
-    dt = {"f64": fem.F64, "f32x2": fem.F32X2}[w["dtype"]]
+    mfree = args.operator == "mfree"
+    dt = fem.MFREE if mfree else {"f64": fem.F64, "f32x2": fem.F32X2}[w["dtype"]]
     log(f"[bench] workload {args.workload}: building inputs")
     mesh, nd, f = make_problem(w)
     log(f"[bench] mesh {mesh.n_nodes} nodes {mesh.n_elems} elements; plan")
     torch.cuda.set_device(0)
     t = time.perf_counter()
-    plan = fem.Plan.from_mesh(mesh, nd, chunk_elems=args.chunk)
+    # matrix-free in 3D: 512-tet chunks (the coordinate table and slot index
+    # of 1536-tet chunks leave one workgroup per CU)
+    chunk = args.chunk or (512 if mfree and mesh.dim == 3 else 0)
+    plan = fem.Plan.from_mesh(mesh, nd, chunk_elems=chunk)
     t_plan = time.perf_counter() - t
     st = plan.stats()
-    K = plan.empty_matrix(dt)
-    M = plan.empty_matrix(dt)
+    K = None if mfree else plan.empty_matrix(dt)
+    M = None if mfree else plan.empty_matrix(dt)
     fg = torch.from_numpy(f).cuda()
     b = plan.empty_vector()
     x = plan.empty_vector()
@@ -596,7 +612,8 @@ def main():
                           max_iter=args.max_iter, vectors=args.vectors, block=args.block)
 
     def step():
-        fem.build_local_matrices(plan, dt, K, M, None)
+        if not mfree:
+            fem.build_local_matrices(plan, dt, K, M, None)
         fem.assemble_rhs(plan, dt, M, fg, b)
         x.zero_()  # Dirichlet data u = 0
         return fem.pcg_solve(plan, opts, K, M, b, x)
@@ -625,18 +642,20 @@ def main():
     mv_n = sum(i["matvec_samples"] for i in infos)
     nb = mesh.nb
     n_pk = nb + nb * (nb - 1) // 2  # packed symmetric difference form: row sums + upper off-diagonals
-    s_a = 4 if dt != fem.F64 else 8
-    s_v = 4 if (dt != fem.F64 and args.vectors == 1) else 8
-    # one fused CG pass: matrix heads + the connectivity-equivalent index + 9 vector streams
-    # (read r, q, x, p, D^-1; write r, x, p, q)
-    bytes_mv = mesh.n_elems * (n_pk * s_a + 4 * nb) + mesh.n_nodes * 9 * s_v
+    s_a = 0 if mfree else 4 if dt != fem.F64 else 8
+    s_v = 4 if (dt not in (fem.F64, fem.MFREE) and args.vectors == 1) else 8
+    # one fused CG pass: matrix heads (none when matrix-free) + the connectivity-equivalent
+    # index + 9 vector streams (read r, q, x, p, D^-1; write r, x, p, q) + the coordinates
+    # when matrix-free
+    bytes_mv = mesh.n_elems * (n_pk * s_a + 4 * nb) + mesh.n_nodes * (9 * s_v + (8 * mesh.dim if mfree else 0))
     avg_mv_s = (mv_ms / mv_n) / 1e3 if mv_n else float("nan")
     gbs = bytes_mv / avg_mv_s / 1e9
     ok = all(i["status"] == 0 and i["relres"] <= 1e-8 for i in infos)
     if args.max_iter < 200000:
         log("[bench] capped iterations: a profiling run, not a time-to-1e-8 measurement")
     resid = residual_kernels(fem, plan, mesh, K, M, w["nu"], dt, args.residual_calls)
-    rec = measured_traffic() if args.workload == "c2" and args.vectors == 0 and args.block == 0 else None
+    rec = (measured_traffic() if args.workload == "c2" and args.vectors == 0 and args.block == 0 and not mfree
+           else None)
     traffic = rec["bytes_per_pass"] if rec and rec.get("chunk_elems") == st["chunk_elems"] else None
     out = {
         "metric": METRIC,
@@ -649,14 +668,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if dt != fem.F64 else "f64",
+        "dtype": "f32" if dt not in (fem.F64, fem.MFREE) else "f64",
         "data": "synthetic",
         "config": {
             "workload": w["name"],
             "n_nodes": mesh.n_nodes,
             "n_elems": mesh.n_elems,
             "chunk_elems": st["chunk_elems"],
-            "storage": w["dtype"],
+            "storage": "matrix-free (K_e, M_e rebuilt per pass, FP64)" if mfree else w["dtype"],
             "block": args.block,
         },
         "roofline": {
@@ -678,7 +697,8 @@ def main():
         "converged": ok,
         "plan_seconds": round(t_plan, 3),
         "learned_fcg": None if args.no_learned else learned_fcg(args),
-        "pass_kind": ("fused CG pass, packed difference form (%d values/elem, %s), %s vectors"
+        "pass_kind": ("fused CG pass, matrix-free (packed form rebuilt from coordinates), FP64 vectors" if mfree
+                      else "fused CG pass, packed difference form (%d values/elem, %s), %s vectors"
                       % (n_pk, "FP32 heads" if dt != fem.F64 else "FP64", "FP32" if s_v == 4 else "FP64")),
         "residual_kernels": resid,
     }

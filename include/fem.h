@@ -53,7 +53,14 @@ typedef enum {
     FEM_ENOMEM = -6       /* device or host allocation failed */
 } fem_status;
 
-typedef enum { FEM_F64 = 0, FEM_F32 = 1, FEM_F32X2 = 2 } fem_dtype;
+/* FEM_MFREE: matrix-free.  No element array is read: K_e and M_e are rebuilt
+ * in FP64 from the plan's coordinates inside every element pass (the formulas
+ * of Section 1, eq. (2)).  Accepted by fem_element_residual, fem_jacobi_diag,
+ * fem_assemble_rhs and fem_pcg_solve, whose d_K_e / d_M_e are then ignored
+ * (NULL allowed); the pass's LDS also holds the chunk's node coordinates, so
+ * large chunks may exceed the workgroup limit (FEM_EINVAL: build the plan
+ * with smaller chunk_elems). */
+typedef enum { FEM_F64 = 0, FEM_F32 = 1, FEM_F32X2 = 2, FEM_MFREE = 3 } fem_dtype;
 
 typedef enum { FEM_PRECOND_NONE = 0, FEM_PRECOND_JACOBI = 1 } fem_precond;
 
@@ -154,7 +161,9 @@ typedef struct {
                            iterations read FP32 local matrices, while dot
                            products, alpha/beta and every refresh of the
                            residual b - A x are FP64 (iterative refinement,
-                           the refresh using the full input precision). */
+                           the refresh using the full input precision).
+                           FEM_MFREE: FP64 solve with the matrix-free
+                           operator (d_K_e, d_M_e ignored; vectors = 0). */
     double nu;          /* >= 0 */
     double rtol;        /* stop at ||b - A x||_2 <= rtol ||b - A x0||_2 */
     int max_iter;       /* cap on CG iterations (inner ones summed) */

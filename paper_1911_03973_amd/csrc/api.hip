@@ -35,7 +35,7 @@ struct fem_plan {
     double *scratch64 = nullptr;
     float *scratch32 = nullptr;
     int64_t n_isolated_free = 0;
-    fem::SolverWork work[2];  // [0] FP64 solver, [1] mixed precision
+    fem::SolverWork work[3];  // [0] FP64 solver, [1] mixed precision, [2] matrix-free
 };
 
 fem::DevPlan fem::plan_device(const fem_plan *p) { return p->dev; }
@@ -59,6 +59,7 @@ struct ArenaLayout {
 
 bool valid_dtype(int t) { return t == FEM_F64 || t == FEM_F32 || t == FEM_F32X2; }
 
+
 int check_plan(const fem_plan *p) {
     if (!p) return set_error(FEM_EINVAL, "plan is NULL");
     return FEM_OK;
@@ -75,8 +76,9 @@ int alloc_work(fem_plan *plan, int slot, int dtype) {
     // the largest chunk grid (8 workgroups per CU) plus the fix-up grid
     const int64_t npart = 8 * (int64_t)fem::device_cu_count() + fem::fixup_grid(P.n_shared, fem::kFixDotsCap) + 8;
     ArenaLayout L;
-    // FP64 packed operator, or FP32 hi/lo pair of it: the same bytes
-    size_t oA = L.add((size_t)npk * sizeof(double));
+    // FP64 packed operator, or FP32 hi/lo pair of it: the same bytes; the
+    // matrix-free solver keeps the coordinates in the solver-local order there
+    size_t oA = L.add(dtype == FEM_MFREE ? (size_t)P.dim * n * sizeof(double) : (size_t)npk * sizeof(double));
     size_t od = L.add(n * sizeof(double));
     size_t odi = L.add(n * sizeof(double));
     size_t or_ = L.add(n * sizeof(double));
@@ -241,6 +243,9 @@ int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_c
     D.n_local = H.n_local;
     D.n_shared = H.n_shared;
     D.n_partials = H.n_partials;
+    D.max_local = 0;
+    for (size_t c = 0; c + 1 < H.chunk_node_off.size(); ++c)
+        D.max_local = std::max(D.max_local, H.chunk_node_off[c + 1] - H.chunk_node_off[c]);
     D.coords = reinterpret_cast<const double *>(b + o_coords);
     D.conn = reinterpret_cast<const int32_t *>(b + o_conn);
     D.chunk_node_off = reinterpret_cast<const int32_t *>(b + o_cno);
@@ -358,6 +363,13 @@ int fem_combine_local(const fem_plan *plan, int dtype_in, const void *d_K_e, con
 int fem_element_residual(const fem_plan *plan, int dtype, const void *d_K_e, const void *d_M_e, double nu,
                          const double *d_b, const double *d_x, double *d_r, int mask_dirichlet, void *stream) {
     if (int rc = check_plan(plan)) return rc;
+    if (dtype == FEM_MFREE) {
+        if (!d_x || !d_r) return set_error(FEM_EINVAL, "NULL argument");
+        if (!std::isfinite(nu) || nu < 0.0) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
+        if (d_r == d_x || (d_b && d_r == d_b)) return set_error(FEM_EINVAL, "r must not alias x or b");
+        return fem::launch_apply_mf(plan->dev, 1.0, nu, d_x, d_b, d_r, -1.0, mask_dirichlet ? 1 : 0, plan->scratch64,
+                                    S(stream));
+    }
     if (!valid_dtype(dtype)) return set_error(FEM_EINVAL, "unknown dtype");
     if ((!d_K_e && plan->dev.n_elems > 0) || !d_x || !d_r) return set_error(FEM_EINVAL, "NULL argument");
     if (d_M_e && (!std::isfinite(nu) || nu < 0.0)) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
@@ -379,6 +391,11 @@ int fem_element_residual_f32(const fem_plan *plan, const float *d_A_e, const flo
 int fem_jacobi_diag(const fem_plan *plan, int dtype, const void *d_K_e, const void *d_M_e, double nu,
                     double *d_diag, void *stream) {
     if (int rc = check_plan(plan)) return rc;
+    if (dtype == FEM_MFREE) {
+        if (!d_diag) return set_error(FEM_EINVAL, "NULL argument");
+        if (!std::isfinite(nu) || nu < 0.0) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
+        return fem::launch_diag_mf(plan->dev, nu, d_diag, plan->scratch64, S(stream));
+    }
     if (!valid_dtype(dtype)) return set_error(FEM_EINVAL, "unknown dtype");
     if ((!d_K_e && plan->dev.n_elems > 0) || !d_diag) return set_error(FEM_EINVAL, "NULL argument");
     if (d_M_e && (!std::isfinite(nu) || nu < 0.0)) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
@@ -389,6 +406,11 @@ int fem_jacobi_diag(const fem_plan *plan, int dtype, const void *d_K_e, const vo
 int fem_assemble_rhs(const fem_plan *plan, int dtype, const void *d_M_e, const double *d_f, double *d_b,
                      void *stream) {
     if (int rc = check_plan(plan)) return rc;
+    if (dtype == FEM_MFREE) {
+        if (!d_f || !d_b) return set_error(FEM_EINVAL, "NULL argument");
+        if ((const void *)d_b == (const void *)d_f) return set_error(FEM_EINVAL, "b must not alias f");
+        return fem::launch_apply_mf(plan->dev, 0.0, 1.0, d_f, nullptr, d_b, 1.0, 0, plan->scratch64, S(stream));
+    }
     if (!valid_dtype(dtype)) return set_error(FEM_EINVAL, "unknown dtype");
     if ((!d_M_e && plan->dev.n_elems > 0) || !d_f || !d_b) return set_error(FEM_EINVAL, "NULL argument");
     if ((const void *)d_b == (const void *)d_f) return set_error(FEM_EINVAL, "b must not alias f");
@@ -403,30 +425,37 @@ int fem_pcg_solve(const fem_plan *plan_c, const fem_solve_opts *o, const void *d
     fem_plan *plan = const_cast<fem_plan *>(plan_c);
     if (!o || !info) return set_error(FEM_EINVAL, "opts and info must not be NULL");
     std::memset(info, 0, sizeof(*info));
-    if (!valid_dtype(o->dtype)) return set_error(FEM_EINVAL, "unknown dtype");
+    const bool mf = o->dtype == FEM_MFREE;
+    if (!valid_dtype(o->dtype) && !mf) return set_error(FEM_EINVAL, "unknown dtype");
     if (!std::isfinite(o->nu) || o->nu < 0.0) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
     if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) return set_error(FEM_EINVAL, "rtol must be in (0, 1)");
     if (o->max_iter < 1) return set_error(FEM_EINVAL, "max_iter must be >= 1");
     if (o->check_every < 1 || o->check_every > 4096) return set_error(FEM_EINVAL, "check_every must be in [1, 4096]");
     if (o->precond != FEM_PRECOND_NONE && o->precond != FEM_PRECOND_JACOBI)
         return set_error(FEM_EINVAL, "unknown preconditioner");
-    if (o->dtype != FEM_F64 && (!(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0) || o->max_outer < 1))
+    if (o->dtype != FEM_F64 && !mf && (!(o->inner_rtol > 0.0) || !(o->inner_rtol < 1.0) || o->max_outer < 1))
         return set_error(FEM_EINVAL, "mixed precision needs inner_rtol in (0,1) and max_outer >= 1");
     if (o->profile < 0) return set_error(FEM_EINVAL, "profile must be >= 0");
     if (o->vectors != 0 && o->vectors != 1) return set_error(FEM_EINVAL, "vectors must be 0 (FP64) or 1 (FP32)");
     if (o->block != 0 && o->block != 256 && o->block != 512 && o->block != 1024)
         return set_error(FEM_EINVAL, "block must be 0, 256, 512 or 1024");
-    if ((!d_K_e && plan->dev.n_elems > 0) || !d_b || !d_x) return set_error(FEM_EINVAL, "NULL argument");
-    if (o->nu != 0.0 && !d_M_e) return set_error(FEM_EINVAL, "nu > 0 needs M_e");
+    if ((!d_K_e && plan->dev.n_elems > 0 && !mf) || !d_b || !d_x) return set_error(FEM_EINVAL, "NULL argument");
+    if (o->nu != 0.0 && !d_M_e && !mf) return set_error(FEM_EINVAL, "nu > 0 needs M_e");
+    if (mf && o->vectors != 0) return set_error(FEM_EINVAL, "the matrix-free solver keeps FP64 vectors");
     if ((const void *)d_x == (const void *)d_b) return set_error(FEM_EINVAL, "x must not alias b");
     if (o->nu == 0.0 && plan->stats.n_dirichlet == 0)
         return set_error(FEM_ESINGULAR, "nu = 0 needs a Dirichlet part of positive measure");
     if (plan->n_isolated_free > 0)
         return set_error(FEM_ESINGULAR, "a node outside every element is not a Dirichlet node");
-    const int slot = o->dtype == FEM_F64 ? 0 : 1;
+    const int slot = mf ? 2 : o->dtype == FEM_F64 ? 0 : 1;
     if (int rc = alloc_work(plan, slot, o->dtype)) return rc;
     hipStream_t s = S(stream);
-    const int block = o->block ? o->block : fem::default_block(plan->dev.nb, plan->dev.E);
+    // matrix-free: two elements per thread by default (one thread per element
+    // leaves too little work to cover the rebuild's LDS and ALU latency)
+    const int E = plan->dev.E;
+    const int block = o->block ? o->block
+                      : mf     ? (E >= 2048 ? 1024 : E >= 1024 ? 512 : 256)
+                               : fem::default_block(plan->dev.nb, E);
     int rc = fem::solve_pcg(plan->dev, plan->work[slot], o->dtype, o->vectors == 0, block, d_K_e, d_M_e, o->nu, d_b,
                             d_x, o->rtol,
                             o->max_iter, o->precond == FEM_PRECOND_JACOBI, o->inner_rtol, o->max_outer,

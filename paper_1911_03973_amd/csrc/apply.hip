@@ -5,6 +5,7 @@
 //   rhs       b = sum_e C_e^T M_e f_e                      (eq. (2)-(3))
 //   diagonal  d = sum_e C_e^T diag(K_e + nu M_e)
 #include <algorithm>
+#include <string>
 #include <type_traits>
 
 #include "chunk.h"
@@ -61,7 +62,10 @@ constexpr int kAffineNodes = 3;
 // 512 threads for 1536-tetrahedron chunks).
 template <int NB, class T, class Ld, class Op, bool DIAG>
 int run_chunked(const DevPlan &P, const Ld &ld, const Op &op, T *scratch, hipStream_t s) {
-    const size_t lds = chunk_lds_bytes<NB, T>(P.E);
+    const size_t lds = chunk_lds_for<NB, T, Ld>(P);
+    if (lds > device_lds_limit())
+        return set_error(-1, "the chunk's LDS (" + std::to_string(lds) + " bytes) exceeds the workgroup limit; "
+                             "build the plan with smaller chunk_elems");
     constexpr bool kAffine = !DIAG && std::is_same<T, float>::value;
     const int block = kAffine ? default_block(NB, P.E) : kBlock;
     const ChunkGrid cg = chunk_grid(P.n_chunks, lds, block);
@@ -108,7 +112,46 @@ int apply_pk64_nb(const DevPlan &P, const void *A, const double *x, const double
     return run_chunked<NB, double, decltype(ld), decltype(op), false>(P, ld, op, scratch, s);
 }
 
+template <int NB>
+int apply_mf_nb(const DevPlan &P, double kk, double nu, const double *x, const double *b, double *out,
+                double sign, int use_mask, double *scratch, hipStream_t s) {
+    LdMf<NB> ld{P.coords, P.n_nodes, kk, nu};
+    OpAffine<double> op{x, b, out, P.mask, sign, use_mask};
+    return run_chunked<NB, double, decltype(ld), decltype(op), false>(P, ld, op, scratch, s);
+}
+
+template <int NB>
+int diag_mf_nb(const DevPlan &P, double nu, double *d, double *scratch, hipStream_t s) {
+    LdMf<NB> ld{P.coords, P.n_nodes, 1.0, nu};
+    OpAffine<double> op{nullptr, nullptr, d, P.mask, 1.0, 0};
+    return run_chunked<NB, double, decltype(ld), decltype(op), true>(P, ld, op, scratch, s);
+}
+
+int g_lds = 0;
+
 }  // namespace
+
+size_t device_lds_limit() {
+    if (g_lds <= 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+            g_lds = v;
+        if (g_lds <= 0) g_lds = kMaxChunkLds;
+    }
+    return (size_t)g_lds;
+}
+
+int launch_apply_mf(const DevPlan &P, double kk, double nu, const double *x, const double *b, double *out,
+                    double sign, int use_mask, double *scratch, hipStream_t s) {
+    if (P.nb == 3) return apply_mf_nb<3>(P, kk, nu, x, b, out, sign, use_mask, scratch, s);
+    return apply_mf_nb<4>(P, kk, nu, x, b, out, sign, use_mask, scratch, s);
+}
+
+int launch_diag_mf(const DevPlan &P, double nu, double *d, double *scratch, hipStream_t s) {
+    if (P.nb == 3) return diag_mf_nb<3>(P, nu, d, scratch, s);
+    return diag_mf_nb<4>(P, nu, d, scratch, s);
+}
 
 ChunkGrid chunk_grid(int64_t n_chunks, size_t lds, int bs) {
     const int per_cu = std::max(1, std::min(2048 / bs, (int)(160 * 1024 / (lds + 512))));

@@ -324,6 +324,9 @@ int fem_batch_create(int dim, int n_problems, const int64_t *node_off, const int
     D.n_local = U.n_local;
     D.n_shared = U.n_shared;
     D.n_partials = U.n_partials;
+    D.max_local = 0;
+    for (size_t c = 0; c + 1 < U.chunk_node_off.size(); ++c)
+        D.max_local = std::max(D.max_local, U.chunk_node_off[c + 1] - U.chunk_node_off[c]);
     D.chunk_elem0 = reinterpret_cast<const int64_t *>(b + o_ce);
     D.coords = reinterpret_cast<const double *>(b + o_coords);
     D.conn = reinterpret_cast<const int32_t *>(b + o_conn);

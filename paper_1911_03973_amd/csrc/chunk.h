@@ -172,6 +172,112 @@ __host__ __device__ constexpr size_t chunk_lds_bytes(int E) {
     return (size_t)NB * E * sizeof(T) + (size_t)NB * E * sizeof(uint16_t);
 }
 
+// Matrix-free operator: the vectorized assembly of Section 1 (eq. (2) per
+// element) moved into the element pass.  The packed difference form of
+// A_e = kk K_e + nu M_e is rebuilt in registers from the element's vertex
+// coordinates on every pass, so no element array is read; the arithmetic is
+// FP64.  With the edge vectors e_k = p_k - p_0 and det = det[e_1 .. e_d], the
+// scaled barycentric gradients c_k = det grad(lambda_k) are the rows of the
+// adjugate (2D: c_1 = (e2y, -e2x), c_2 = (-e1y, e1x); 3D: c_1 = e2 x e3,
+// c_2 = e3 x e1, c_3 = e1 x e2) and c_0 = -(c_1 + ... + c_d).  Then
+// K_ij = (c_i . c_j) / (d! |det|) (vol = |det| / d!), the row sums of K_e are
+// 0, M_e has vol / ((d+1)(d+2)) off the diagonal and row sums vol / (d+1).
+// Vertex coordinates reach the pass through LDS: phase A stores each local
+// node's coordinates once (a per-chunk table of max_local entries) and the
+// node's index into each of its slots; phase B reads an element's vertices
+// there through its slots.  Measured alternatives, all slower or no faster:
+// the coordinates written into every slot beside x (1.2x slower in 2D, 2x in
+// 3D: phase A's scattered LDS writes tripled), and a precomputed slot -> node
+// index read from HBM into registers or staged into LDS.
+template <int NB>
+struct LdMf {
+    static constexpr bool kCoords = true;
+    static constexpr int DIM = NB - 1;
+    using Base = LdPk<NB, MAT_F64>;
+    using Regs = typename Base::Regs;
+    const double *xyz;  // [DIM][n] coordinates, indexed like the op's nodes
+    int64_t n;
+    double kk, nu;
+    __device__ __forceinline__ void fetch(int64_t, Regs &) const {}
+    __device__ __forceinline__ double coord(int64_t i, int d) const { return xyz[(int64_t)d * n + i]; }
+    __device__ __forceinline__ void build(const double (&p)[NB][DIM], Regs &R) const {
+        double c[NB][DIM];
+        double det;
+        if constexpr (DIM == 2) {
+            const double e1x = p[1][0] - p[0][0], e1y = p[1][1] - p[0][1];
+            const double e2x = p[2][0] - p[0][0], e2y = p[2][1] - p[0][1];
+            det = e1x * e2y - e1y * e2x;
+            c[1][0] = e2y;
+            c[1][1] = -e2x;
+            c[2][0] = -e1y;
+            c[2][1] = e1x;
+        } else {
+            double e[3][3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) e[k][d] = p[k + 1][d] - p[0][d];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double *a = e[(k + 1) % 3], *b = e[(k + 2) % 3];
+                c[k + 1][0] = a[1] * b[2] - a[2] * b[1];
+                c[k + 1][1] = a[2] * b[0] - a[0] * b[2];
+                c[k + 1][2] = a[0] * b[1] - a[1] * b[0];
+            }
+            det = e[0][0] * c[1][0] + e[0][1] * c[1][1] + e[0][2] * c[1][2];
+        }
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 1; k < NB; ++k) t += c[k][d];
+            c[0][d] = -t;
+        }
+        const double fact = DIM == 2 ? 2.0 : 6.0;
+        const double ad = fabs(det);
+        const double vol = ad / fact;
+        const double ks = kk / (fact * ad);
+        const double moff = nu * vol / (double)((DIM + 1) * (DIM + 2));
+        const double mrow = nu * vol / (double)(DIM + 1);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) R.v[i] = mrow;
+        int k = NB;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = i + 1; j < NB; ++j) {
+                double g = 0.0;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) g += c[i][d] * c[j][d];
+                R.v[k++] = ks * g + moff;
+            }
+    }
+    template <class T>
+    __device__ __forceinline__ static void apply(const Regs &R, const T (&xt)[NB], T (&yt)[NB]) {
+        Base::apply(R, xt, yt);
+    }
+    template <class T>
+    __device__ __forceinline__ static void diag(const Regs &R, T (&yt)[NB]) {
+        Base::diag(R, yt);
+    }
+};
+
+// Loaders without kCoords read their element arrays from HBM.
+template <class L, class = void>
+struct HasCoords : std::false_type {};
+template <class L>
+struct HasCoords<L, std::void_t<decltype(L::kCoords)>> : std::integral_constant<bool, L::kCoords> {};
+
+// LDS of one chunk pass: slot buffer and slot list, plus (matrix-free) the
+// slot -> local node index and the coordinates of up to max_local nodes.
+template <int NB, class T, class Ld>
+size_t chunk_lds_for(const DevPlan &P) {
+    size_t b = chunk_lds_bytes<NB, T>(P.E);
+    if constexpr (HasCoords<Ld>::value)
+        b += (size_t)NB * P.E * sizeof(uint16_t) + (size_t)(NB - 1) * sizeof(double) * (size_t)P.max_local;
+    return b;
+}
+
 // Chunk visited by workgroup b at its it-th step, or -1 when done.  With
 // xcd != 0 (grid a multiple of 8) XCD b%8 walks chunks [x*cpx, (x+1)*cpx).
 __device__ __forceinline__ int64_t chunk_of(int64_t b, int64_t it, int64_t n_chunks, int64_t grid, int xcd) {
@@ -290,6 +396,11 @@ __global__ __launch_bounds__(BS) void k_chunk_main(const DevPlan P, const Ld ld,
     extern __shared__ __align__(16) unsigned char smem[];
     T *buf = reinterpret_cast<T *>(smem);
     uint16_t *sl = reinterpret_cast<uint16_t *>(smem + (size_t)NB * P.E * sizeof(T));
+    constexpr bool kMf = HasCoords<Ld>::value;
+    // matrix-free only: the local node of every slot, then the coordinates
+    // of the chunk's local nodes, [local node][dim]
+    uint16_t *lnode = sl + (size_t)NB * P.E;
+    double *crd = reinterpret_cast<double *>(lnode + (size_t)NB * P.E);
     __shared__ RedBuf<BS> red;
     if (!op.begin()) return;
     for (int64_t it = 0;; ++it) {
@@ -317,7 +428,25 @@ __global__ __launch_bounds__(BS) void k_chunk_main(const DevPlan P, const Ld ld,
             for (int k = threadIdx.x; k < nv; k += BS) dst[k] = src[k];
         }
         __syncthreads();
-        if constexpr (!DIAG) {
+        if constexpr (kMf) {
+            for (int k = threadIdx.x; k < nl; k += BS) {
+                const int g = Op::kLocal ? (k < ncomp ? coff + k : -1) : P.loc_nodes[nb0 + k];
+                const int s0 = k ? P.loc_end[nb0 + k - 1] : 0;
+                const int s1 = P.loc_end[nb0 + k];
+                const int own = k < ncomp ? -1 : P.part_owner[pbase + (k - ncomp)];
+                if constexpr (!DIAG) {
+                    const T v = op.gather(g, own);
+                    for (int s = s0; s < s1; ++s) buf[sl[s]] = v;
+                }
+                // the coordinates in the op's node order: shared nodes of a
+                // solver-local op follow the complete ones by shared index
+                const int64_t ci = (Op::kLocal && own >= 0) ? (P.n_nodes - P.n_shared) + own : (int64_t)g;
+#pragma unroll
+                for (int d = 0; d < NB - 1; ++d) crd[k * (NB - 1) + d] = ld.coord(ci, d);
+                for (int s = s0; s < s1; ++s) lnode[sl[s]] = (uint16_t)k;
+            }
+            __syncthreads();
+        } else if constexpr (!DIAG) {
             for (int k = threadIdx.x; k < nl; k += BS) {
                 // Op::kLocal: complete nodes by solver-local index, shared ones by their shared index only
                 const int g = Op::kLocal ? (k < ncomp ? coff + k : -1) : P.loc_nodes[nb0 + k];
@@ -327,6 +456,22 @@ __global__ __launch_bounds__(BS) void k_chunk_main(const DevPlan P, const Ld ld,
                 for (int s = s0; s < s1; ++s) buf[sl[s]] = v;
             }
             __syncthreads();
+        }
+        if constexpr (kMf) {
+            // all of the thread's elements first: these LDS reads do not wait
+            // behind the slot-buffer writes of the loop below
+#pragma unroll
+            for (int t = 0; t < EPT; ++t) {
+                const int le = t * BS + threadIdx.x;
+                if (le < ne) {
+                    double pv[NB][NB - 1];
+#pragma unroll
+                    for (int j = 0; j < NB; ++j)
+#pragma unroll
+                        for (int d = 0; d < NB - 1; ++d) pv[j][d] = crd[(int)lnode[le * NB + j] * (NB - 1) + d];
+                    ld.build(pv, R[t]);
+                }
+            }
         }
 #pragma unroll
         for (int t = 0; t < EPT; ++t) {

@@ -13,7 +13,9 @@ namespace fem {
 constexpr int kBlock = 256;  // 4 wave64 per workgroup
 constexpr int kWave = 64;
 
-enum MatKind { MAT_F64 = 0, MAT_F32 = 1, MAT_F32X2 = 2 };
+// MAT_MF: no stored element matrices, K_e and M_e rebuilt from the
+// coordinates inside every element pass (matrix-free).
+enum MatKind { MAT_F64 = 0, MAT_F32 = 1, MAT_F32X2 = 2, MAT_MF = 3 };
 
 // Element-matrix entry (i*nb+j) of element e, promoted to double.
 // `blk` is the size of one [nb*nb][n_elems] block (for the lo half of a pair).

@@ -37,6 +37,14 @@ int launch_pack(const DevPlan &P, int kin, const void *K, const void *M, double 
                 hipStream_t s);
 // d = sum_e C_e^T diag(A_e) from the packed difference form
 int launch_diag_pk64(const DevPlan &P, int kind, const void *A, double *d, double *scratch, hipStream_t s);
+// Matrix-free (K_e, M_e rebuilt from the plan's coordinates in every pass):
+// out = (b ? b : 0) + sign * sum_e C_e^T (kk K_e + nu M_e) C_e x, and the
+// diagonal of K + nu M.  FEM_EINVAL when the chunk's LDS exceeds the limit.
+int launch_apply_mf(const DevPlan &P, double kk, double nu, const double *x, const double *b, double *out,
+                    double sign, int use_mask, double *scratch, hipStream_t s);
+int launch_diag_mf(const DevPlan &P, double nu, double *d, double *scratch, hipStream_t s);
+// Dynamic LDS one workgroup may use on the current device.
+size_t device_lds_limit();
 // d = sum_e C_e^T diag(A_e)
 int launch_diag64(const DevPlan &P, int kind, const void *K, const void *M, double nu, double *d,
                   double *scratch, hipStream_t s);

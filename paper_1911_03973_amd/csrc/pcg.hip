@@ -404,9 +404,12 @@ struct EventPool {
 };
 
 // The solve for one (NB, EPT, matrix head kind, vector type).
+// MK == MAT_MF: matrix-free passes over the coordinates, which w.Apk holds
+// in the solver-local order (nu enters the rebuilt A_e).
 template <int NB, int EPT, int BS, int MK, class VT>
-int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, const double *b, double *x64, double rtol, int max_iter,
-           double delta, int max_outer, int check_every, int profile, fem_solve_info *info, hipStream_t s) {
+int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, double nu, const double *b, double *x64, double rtol,
+           int max_iter, double delta, int max_outer, int check_every, int profile, fem_solve_info *info,
+           hipStream_t s) {
     const bool fold = std::is_same<VT, float>::value;  // FP32 vectors: x is an FP32 correction
     const int64_t n = P.n_nodes;
     const int64_t nc = n - P.n_shared;  // complete nodes; the shared ones are the tail
@@ -414,13 +417,22 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, const double *b, double
     VT *r = reinterpret_cast<VT *>(w.r), *p = reinterpret_cast<VT *>(w.p), *q = reinterpret_cast<VT *>(w.q);
     const VT *dinv = reinterpret_cast<const VT *>(w.dinv);
     VT *partv = reinterpret_cast<VT *>(w.partv);
-    const size_t lds = chunk_lds_bytes<NB, VT>(P.E);
+    using LdT = typename std::conditional<MK == MAT_MF, LdMf<NB>, LdPk<NB, MK == MAT_MF ? MAT_F64 : MK>>::type;
+    const size_t lds = chunk_lds_for<NB, VT, LdT>(P);
+    if (lds > device_lds_limit())
+        return set_error(FEM_EINVAL, "the chunk's LDS exceeds the workgroup limit; use smaller chunk_elems");
     const ChunkGrid cg = chunk_grid(P.n_chunks, lds, BS);
     const int gf = P.n_shared > 0 ? fixup_grid(P.n_shared, kFixDotsCap) : 0;
     const int npart = cg.grid + gf;
     const int gu = (int)std::max<int64_t>(1, std::min<int64_t>((n + 4 * kBlock - 1) / (4 * kBlock), 1024));
     const int gv = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 4096));
-    LdPk<NB, MK> ld{w.Apk, P.n_elems};
+    auto make_ld = [&]() -> LdT {
+        if constexpr (MK == MAT_MF)
+            return LdT{static_cast<const double *>(w.Apk), n, 1.0, nu};
+        else
+            return LdT{w.Apk, P.n_elems};
+    };
+    const LdT ld = make_ld();
     VT *sx = xv + nc, *sr = r + nc, *sp = p + nc, *sq = q + nc;
     const VT *sd = dinv + nc;
     OpIter<VT> op{xv, r, p, q, dinv, sx, sr, sp, sq, sd, w.st, w.dots, npart, 0, 0.0, 0.0, {0, 0, 0, 0, 0, 0, 0}};
@@ -431,7 +443,8 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, const double *b, double
     auto refresh = [&](int first) -> int {
         if (!first) k_pending<VT><<<gv, kBlock, 0, s>>>(n, xv, r, p, q, w.st);
         scatter_x();
-        int rc = launch_apply_pk64(P, pk_kind, w.Apk, x64, b, w.r64, -1.0, 1, w.part64, s);
+        int rc = MK == MAT_MF ? launch_apply_mf(P, 1.0, nu, x64, b, w.r64, -1.0, 1, w.part64, s)
+                              : launch_apply_pk64(P, pk_kind, w.Apk, x64, b, w.r64, -1.0, 1, w.part64, s);
         if (rc) return rc;
         k_init_dots<VT><<<gu, kBlock, 0, s>>>(n, r, dinv, w.r64, w.perm, w.upd);
         k_refresh_state<<<1, kBlock, 0, s>>>(w.st, w.upd, gu, first);
@@ -463,7 +476,7 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, const double *b, double
         for (int j = 0; j < m; ++j) {
             const bool timed = profile > 0 && ((launched + j) % profile == 0) && ev.used < (int)ev.a.size();
             if (timed) FEM_HIP_CHECK(hipEventRecord(ev.a[ev.used], s));
-            k_chunk_main<NB, EPT, BS, VT, decltype(ld), OpIter<VT>, false>
+            k_chunk_main<NB, EPT, BS, VT, LdT, OpIter<VT>, false>
                 <<<cg.grid, BS, lds, s>>>(P, ld, op, partv, cg.xcd);
             if (gf) k_chunk_fixup<kFixBlock, VT, OpIter<VT>><<<gf, kFixBlock, 0, s>>>(P, op, partv, cg.grid);
             if (timed) {
@@ -516,14 +529,19 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, const double *b, double
 int solve_pcg(const DevPlan &P, SolverWork &w, int dtype, int vec64, int block, const void *K, const void *M,
               double nu, const double *b, double *x, double rtol, int max_iter, int jacobi, double delta,
               int max_outer, int check_every, int profile, fem_solve_info *info, hipStream_t s) {
-    const bool mixed = dtype != MAT_F64;
+    const bool mf = dtype == MAT_MF;
+    const bool mixed = dtype != MAT_F64 && !mf;
     const int64_t n = P.n_nodes;
     const int gv = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 4096));
     const int pk_kind = mixed ? MAT_F32X2 : MAT_F64;
     const void *Mu = (nu != 0.0) ? M : nullptr;
-    int rc = launch_pack(P, dtype, K, Mu, nu, pk_kind, w.Apk, s);
-    if (rc) return rc;
-    rc = launch_diag64(P, dtype, K, Mu, nu, w.d64, w.part64, s);
+    int rc = 0;
+    if (mf) {
+        rc = launch_diag_mf(P, nu, w.d64, w.part64, s);
+    } else {
+        rc = launch_pack(P, dtype, K, Mu, nu, pk_kind, w.Apk, s);
+        if (!rc) rc = launch_diag64(P, dtype, K, Mu, nu, w.d64, w.part64, s);
+    }
     if (rc) return rc;
     k_zero_int<<<1, 1, 0, s>>>(w.bad);
     if (P.n_chunks > 0)
@@ -531,6 +549,10 @@ int solve_pcg(const DevPlan &P, SolverWork &w, int dtype, int vec64, int block, 
     if (P.n_shared > 0)
         k_perm_shared<<<(int)std::max<int64_t>(1, std::min<int64_t>((P.n_shared + kBlock - 1) / kBlock, 4096)),
                         kBlock, 0, s>>>(P, w.perm);
+    if (mf)  // coordinates into the solver-local order
+        for (int d = 0; d < P.dim; ++d)
+            k_gather_perm<double><<<gv, kBlock, 0, s>>>(n, w.perm, P.coords + (int64_t)d * n,
+                                                        static_cast<double *>(w.Apk) + (int64_t)d * n);
     const bool v32 = mixed && !vec64;
     if (v32) {
         k_dinv<float><<<gv, kBlock, 0, s>>>(n, w.d64, P.mask, w.perm, reinterpret_cast<float *>(w.dinv), jacobi,
@@ -552,19 +574,23 @@ int solve_pcg(const DevPlan &P, SolverWork &w, int dtype, int vec64, int block, 
         constexpr int BS = decltype(bs)::value;
         constexpr int EPT = decltype(ept)::value;
         if (P.nb == 3) {
-            if (!mixed) return cg_run<3, EPT, BS, MAT_F64, double>(P, w, pk_kind, b, x, rtol, max_iter, dl, outer_cap,
+            if (mf) return cg_run<3, EPT, BS, MAT_MF, double>(P, w, pk_kind, nu, b, x, rtol, max_iter, dl, outer_cap,
+                                                             check_every, profile, info, s);
+            if (!mixed) return cg_run<3, EPT, BS, MAT_F64, double>(P, w, pk_kind, nu, b, x, rtol, max_iter, dl, outer_cap,
                                                                   check_every, profile, info, s);
-            if (v32) return cg_run<3, EPT, BS, MAT_F32, float>(P, w, pk_kind, b, x, rtol, max_iter, dl, outer_cap,
+            if (v32) return cg_run<3, EPT, BS, MAT_F32, float>(P, w, pk_kind, nu, b, x, rtol, max_iter, dl, outer_cap,
                                                               check_every, profile, info, s);
-            return cg_run<3, EPT, BS, MAT_F32, double>(P, w, pk_kind, b, x, rtol, max_iter, dl, outer_cap,
+            return cg_run<3, EPT, BS, MAT_F32, double>(P, w, pk_kind, nu, b, x, rtol, max_iter, dl, outer_cap,
                                                        check_every, profile, info, s);
         }
         if constexpr (EPT * BS <= 1536 || (EPT <= 2 && BS == 1024)) {
-            if (!mixed) return cg_run<4, EPT, BS, MAT_F64, double>(P, w, pk_kind, b, x, rtol, max_iter, dl, outer_cap,
+            if (mf) return cg_run<4, EPT, BS, MAT_MF, double>(P, w, pk_kind, nu, b, x, rtol, max_iter, dl, outer_cap,
+                                                             check_every, profile, info, s);
+            if (!mixed) return cg_run<4, EPT, BS, MAT_F64, double>(P, w, pk_kind, nu, b, x, rtol, max_iter, dl, outer_cap,
                                                                   check_every, profile, info, s);
-            if (v32) return cg_run<4, EPT, BS, MAT_F32, float>(P, w, pk_kind, b, x, rtol, max_iter, dl, outer_cap,
+            if (v32) return cg_run<4, EPT, BS, MAT_F32, float>(P, w, pk_kind, nu, b, x, rtol, max_iter, dl, outer_cap,
                                                               check_every, profile, info, s);
-            return cg_run<4, EPT, BS, MAT_F32, double>(P, w, pk_kind, b, x, rtol, max_iter, dl, outer_cap,
+            return cg_run<4, EPT, BS, MAT_F32, double>(P, w, pk_kind, nu, b, x, rtol, max_iter, dl, outer_cap,
                                                        check_every, profile, info, s);
         }
         return set_error(FEM_EINVAL, "chunk size too large for tetrahedra");

@@ -32,6 +32,7 @@ struct HostPlan {
 // Device-resident index (raw pointers into plan-owned allocations).
 struct DevPlan {
     int dim, nb, E;
+    int max_local;  // most distinct nodes of one chunk
     int64_t n_nodes, n_elems, n_chunks, n_local, n_shared, n_partials;
     const int64_t *chunk_elem0;  // [n_chunks+1] first element of each chunk; NULL: chunk c starts at c*E
     const double *coords;        // [dim][n_nodes]

@@ -23,6 +23,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 FEM_OK, FEM_EINVAL, FEM_EHIP, FEM_ENOCONV, FEM_ESINGULAR, FEM_EBREAKDOWN, FEM_ENOMEM = 0, -1, -2, -3, -4, -5, -6
 F64, F32, F32X2 = 0, 1, 2
+MFREE = 3  # matrix-free: K_e, M_e rebuilt from the coordinates in every pass
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 
 _STATUS = {
@@ -288,7 +289,7 @@ class Plan:
         return torch.empty(self.n_nodes, dtype=tdt, device=self.device)
 
     def _mat(self, t, dtype, what):
-        if t is None:
+        if t is None or dtype == MFREE:
             return
         shape, tdt = matrix_shape(dtype, self.nb, self.n_elems)
         _need(t, tdt, int(torch.Size(shape).numel()), what)

@@ -187,3 +187,39 @@ def test_full_size_multigrid_vcycle_and_solve():
     r = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, bo, x.cpu().numpy(), mask)
     r0 = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, bo, np.zeros(mesh.n_nodes), mask)
     assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8
+
+
+@pytest.mark.parametrize("name,E,block", [("c2", 0, 512), ("c3", 512, 0)])
+def test_full_size_mfree_on_sampled_nodes_and_solve(name, E, block):
+    """The matrix-free operator at full size, in the launch configuration the
+    benchmark times: the residual on 4096 sampled nodes (oracle on the
+    sub-mesh around them) and the oracle's residual of the solution."""
+    mesh, nd, nu, f = _workload(name)
+    rng = np.random.default_rng(43)
+    plan = fem.Plan.from_mesh(mesh, nd, chunk_elems=E)
+    b = plan.empty_vector()
+    fem.assemble_rhs(plan, fem.MFREE, None, cuda(f), b)
+    x = rng.standard_normal(mesh.n_nodes)
+    r = plan.empty_vector()
+    fem.element_residual(plan, fem.MFREE, None, None, nu, b, cuda(x), r, mask=True)
+    torch.cuda.synchronize()
+    ns = rng.choice(mesh.n_nodes, size=SAMPLES, replace=False)
+    sub = mesh.elems[_sub_elements(mesh, ns)]
+    Ks, Ms, _ = oracle.local_matrices(mesh.coords, sub)
+    bs = oracle.rhs(mesh.n_nodes, sub, Ms, f)
+    mask = oracle.mask_from_nodes(mesh.n_nodes, nd)
+    rs = oracle.residual(mesh.n_nodes, sub, Ks, Ms, nu, bs, x, mask)
+    scale = oracle.residual_scale(mesh.n_nodes, sub, Ks, Ms, nu, bs, x)
+    bg, rg = b.cpu().numpy(), r.cpu().numpy()
+    assert np.abs(bg[ns] - bs[ns]).max() <= 1e-12 * np.abs(bs[ns]).max()
+    assert np.all(np.abs(rg[ns] - rs[ns]) <= 1e-12 * scale[ns] + 1e-300)
+    xs = torch.zeros(mesh.n_nodes, dtype=torch.float64, device="cuda")
+    info = fem.pcg_solve(plan, fem.solve_opts(dtype=fem.MFREE, nu=nu, rtol=1e-8, check_every=64, block=block),
+                         None, None, b, xs)
+    print(name, "mfree", info, flush=True)
+    assert info["status"] == 0 and info["relres"] <= 1e-8
+    Ko, Mo, _ = oracle.local_matrices(mesh.coords, mesh.elems)
+    bo = oracle.rhs(mesh.n_nodes, mesh.elems, Mo, f)
+    ro = oracle.residual(mesh.n_nodes, mesh.elems, Ko, Mo, nu, bo, xs.cpu().numpy(), mask)
+    r0 = oracle.residual(mesh.n_nodes, mesh.elems, Ko, Mo, nu, bo, np.zeros(mesh.n_nodes), mask)
+    assert np.linalg.norm(ro) / np.linalg.norm(r0) <= 1.05e-8

@@ -1,0 +1,167 @@
+"""Matrix-free operator (FEM_MFREE): K_e and M_e rebuilt from the coordinates
+inside every element pass, against the FP64 oracle's stored local matrices.
+
+The residual, the Jacobi diagonal and the right-hand side must match to
+1e-12 relative (the same bar as the stored FP64 path: the rebuilt entries
+differ from the oracle's by rounding only); the solver is judged like the
+stored FP64 solver (first iterates to 1e-10, iteration counts within 2 %,
+the oracle's residual of the solution).  Chunks whose LDS (slot buffer plus
+node coordinates) exceeds the device's workgroup limit must be refused with
+FEM_EINVAL, never launched.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1911_03973_amd import inputs
+
+from problems import Problem, cuda, max_rel
+
+pytestmark = pytest.mark.gpu
+
+fem = pytest.importorskip("paper_1911_03973_amd.fem")
+
+
+def _shuffled(mesh, seed):
+    order = np.random.default_rng(seed).permutation(mesh.n_elems)
+    return inputs.Mesh(coords=mesh.coords, elems=np.ascontiguousarray(mesh.elems[order]), n=mesh.n)
+
+
+MESHES = [
+    ("tri_fig1_2elem", inputs.square_mesh(1, order="rowmajor"), 0),
+    ("tri_17_jitter_E64", inputs.square_mesh(17, jitter=0.2, seed=3), 64),
+    ("tri_45_jitter_E512", inputs.square_mesh(45, jitter=0.2, seed=4), 512),
+    ("tri_64_default", inputs.square_mesh(64, jitter=0.2, seed=14), 0),
+    ("tri_33_rowmajor_E2048", inputs.square_mesh(33, order="rowmajor", jitter=0.1, seed=5), 2048),
+    ("tri_24_shuffled_E128", _shuffled(inputs.square_mesh(24, jitter=0.2, seed=10), 11), 128),
+    ("tri_40_shuffled_E1024", _shuffled(inputs.square_mesh(40, jitter=0.2, seed=8), 9), 1024),
+    ("tet_5_jitter_E64", inputs.cube_mesh(5, jitter=0.15, seed=6), 64),
+    ("tet_9_jitter_E512", inputs.cube_mesh(9, jitter=0.15, seed=7), 512),
+    ("tet_12_E1536", inputs.cube_mesh(12, jitter=0.1, seed=15), 1536),
+    ("tet_8_shuffled_E256", _shuffled(inputs.cube_mesh(8, jitter=0.1, seed=12), 13), 256),
+]
+
+
+@pytest.fixture(params=MESHES, ids=[m[0] for m in MESHES])
+def case(request):
+    name, mesh, E = request.param
+    print(f"[case] {name} n_nodes={mesh.n_nodes} n_elems={mesh.n_elems} E={E}", flush=True)
+    prob = Problem(mesh, nu=0.75, dirichlet="all", f="sine", seed=11)
+    plan = fem.Plan.from_mesh(mesh, prob.nd, chunk_elems=E)
+    return prob, plan
+
+
+def _run_or_refused(fn):
+    """Run fn; a refusal must name the LDS limit.  Returns False if refused."""
+    try:
+        fn()
+    except fem.FemError as e:
+        assert e.code == fem.FEM_EINVAL and "LDS" in str(e), e
+        return False
+    return True
+
+
+def test_mfree_residual_matches_oracle(case):
+    prob, plan = case
+    x = np.random.default_rng(1).standard_normal(prob.n)
+    xg, bg = cuda(x), cuda(prob.b)
+    r = plan.empty_vector()
+    for nu in (prob.nu, 0.0, 37.5):
+        for mask in (True, False):
+            if not _run_or_refused(lambda: fem.element_residual(plan, fem.MFREE, None, None, nu, bg, xg, r,
+                                                                mask=mask)):
+                pytest.skip("chunk LDS above this device's workgroup limit (refused with FEM_EINVAL)")
+            torch.cuda.synchronize()
+            ro = oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, nu, prob.b, x,
+                                 prob.mask if mask else None)
+            s = oracle.residual_scale(prob.n, prob.mesh.elems, prob.K, prob.M, nu, prob.b, x)
+            assert max_rel(r.cpu().numpy(), ro, scale=s.max()) <= 1e-12, (nu, mask)
+    fem.element_residual(plan, fem.MFREE, None, None, 0.0, None, xg, r, mask=False)
+    torch.cuda.synchronize()
+    ro = oracle.residual(prob.n, prob.mesh.elems, prob.K, None, 0.0, None, x)
+    s = oracle.residual_scale(prob.n, prob.mesh.elems, prob.K, None, 0.0, None, x)
+    assert max_rel(r.cpu().numpy(), ro, scale=s.max()) <= 1e-12
+
+
+def test_mfree_diagonal_and_rhs_match_oracle(case):
+    prob, plan = case
+    d = plan.empty_vector()
+    if not _run_or_refused(lambda: fem.jacobi_diag(plan, fem.MFREE, None, None, prob.nu, d)):
+        pytest.skip("chunk LDS above this device's workgroup limit (refused with FEM_EINVAL)")
+    b = plan.empty_vector()
+    fem.assemble_rhs(plan, fem.MFREE, None, cuda(prob.f), b)
+    torch.cuda.synchronize()
+    do = oracle.jacobi_diag(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu)
+    assert max_rel(d.cpu().numpy(), do) <= 1e-12
+    assert max_rel(b.cpu().numpy(), prob.b) <= 1e-12
+
+
+def test_mfree_equals_stored_fp64_operator_to_rounding(case):
+    """The rebuilt operator and the GPU's stored FP64 one agree to rounding."""
+    prob, plan = case
+    K = plan.empty_matrix(fem.F64)
+    M = plan.empty_matrix(fem.F64)
+    fem.build_local_matrices(plan, fem.F64, K, M, None)
+    x = cuda(np.random.default_rng(4).standard_normal(prob.n))
+    r1, r2 = plan.empty_vector(), plan.empty_vector()
+    if not _run_or_refused(lambda: fem.element_residual(plan, fem.MFREE, None, None, prob.nu, None, x, r1)):
+        pytest.skip("chunk LDS above this device's workgroup limit (refused with FEM_EINVAL)")
+    fem.element_residual(plan, fem.F64, K, M, prob.nu, None, x, r2)
+    torch.cuda.synchronize()
+    assert max_rel(r1.cpu().numpy(), r2.cpu().numpy()) <= 1e-11
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_mfree_first_iterates_match_oracle(dim):
+    mesh = inputs.square_mesh(24, jitter=0.2, seed=9) if dim == 2 else inputs.cube_mesh(8, jitter=0.1, seed=9)
+    prob = Problem(mesh, nu=2.5, dirichlet="all", f="sine", seed=3)
+    plan = fem.Plan.from_mesh(mesh, prob.nd, chunk_elems=256)
+    u = 1.0 + mesh.coords[:, 0]
+    x0 = np.zeros(prob.n)
+    x0[prob.nd] = u[prob.nd]
+    for k in (1, 2, 5, 10):
+        x = cuda(x0)
+        info = fem.pcg_solve(plan, fem.solve_opts(dtype=fem.MFREE, nu=prob.nu, max_iter=k, check_every=4), None,
+                             None, cuda(prob.b), x)
+        xo, io = oracle.pcg(prob.n, mesh.elems, prob.K, prob.M, prob.nu, prob.b, prob.mask, x0.copy(),
+                            max_iter=k, raise_on_noconv=False)
+        assert info["iters"] == io["iters"] == k
+        assert max_rel(x.cpu().numpy(), xo) <= 1e-10, k
+
+
+@pytest.mark.parametrize("dim,E,block", [(2, 0, 0), (2, 1024, 512), (3, 512, 0), (3, 256, 256)])
+def test_mfree_solve_meets_target_in_oracle_residual(dim, E, block):
+    if dim == 2:
+        mesh = inputs.square_mesh(96, jitter=0.2, seed=21)
+        prob = Problem(mesh, nu=1.0, dirichlet="x2=0", f="sine", seed=22)
+    else:
+        mesh = inputs.cube_mesh(14, jitter=0.1, seed=23)
+        prob = Problem(mesh, nu=10.0, dirichlet="all", f="sine", seed=24)
+    plan = fem.Plan.from_mesh(mesh, prob.nd, chunk_elems=E)
+    x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+    info = fem.pcg_solve(plan, fem.solve_opts(dtype=fem.MFREE, nu=prob.nu, rtol=1e-8, block=block), None, None,
+                         cuda(prob.b), x)
+    assert info["status"] == fem.FEM_OK
+    r = oracle.residual(prob.n, mesh.elems, prob.K, prob.M, prob.nu, prob.b, x.cpu().numpy(), prob.mask)
+    r0 = oracle.residual(prob.n, mesh.elems, prob.K, prob.M, prob.nu, prob.b, np.zeros(prob.n), prob.mask)
+    assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8
+    _, io = oracle.pcg(prob.n, mesh.elems, prob.K, prob.M, prob.nu, prob.b, prob.mask, np.zeros(prob.n), rtol=1e-8)
+    assert abs(info["iters"] - io["iters"]) <= max(2, 0.02 * io["iters"]), (info["iters"], io["iters"])
+    # bitwise reproducible
+    x2 = torch.zeros_like(x)
+    fem.pcg_solve(plan, fem.solve_opts(dtype=fem.MFREE, nu=prob.nu, rtol=1e-8, block=block), None, None,
+                  cuda(prob.b), x2)
+    assert torch.equal(x, x2)
+
+
+def test_mfree_rejects_fp32_vectors_and_unsupported_entry_points():
+    mesh = inputs.square_mesh(8)
+    plan = fem.Plan.from_mesh(mesh, inputs.boundary_nodes(mesh))
+    b = plan.empty_vector()
+    b.zero_()
+    x = plan.empty_vector()
+    with pytest.raises(fem.FemError):
+        fem.pcg_solve(plan, fem.solve_opts(dtype=fem.MFREE, vectors=1), None, None, b, x)
+    with pytest.raises(fem.FemError):  # nothing to build: matrix-free has no stored arrays
+        fem.build_local_matrices(plan, fem.MFREE, plan.empty_matrix(fem.F64), None, None)
