@@ -1,0 +1,92 @@
+"""FP64 reference of the quadratic (P2) triangle matrices (test infrastructure only).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of the
+benchmark may import this module.  It shares no code with the GPU library.
+
+The paper's outlook names higher-order elements as the next step; it gives no
+formulas for them.  This module takes the textbook definition: on a straight
+triangle with barycentric coordinates lambda_0..2 (vertex k <-> lambda_k), the
+six Lagrange basis functions
+    phi_k = lambda_k (2 lambda_k - 1)        k = 0, 1, 2  (vertices)
+    phi_3 = 4 lambda_0 lambda_1, phi_4 = 4 lambda_1 lambda_2,
+    phi_5 = 4 lambda_2 lambda_0                           (edge midpoints)
+and the local matrices K_ij = int grad phi_i . grad phi_j, M_ij = int phi_i
+phi_j, as in eq. (2) for P1.  The integrals are evaluated by a collapsed
+(Duffy) tensor Gauss-Legendre rule on the reference triangle, exact for the
+degree-4 integrands of M, with the affine map of the element; the GPU library
+integrates barycentric monomials in closed form instead.
+
+Pins (tests/test_oracle_p2.py): K annihilates constants, the vertex rows of M
+integrate to zero and the midpoint rows to area/3, the discrete solution of a
+problem whose exact solution is quadratic is that quadratic at every node, and
+the nodal error of a smooth solution falls faster than the P1 rate.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+NB = 6
+
+
+def _rule(k=4):
+    """Points (xi, eta) and weights of the collapsed Gauss rule on the reference
+    triangle {xi, eta >= 0, xi + eta <= 1} (weights sum to 1/2)."""
+    g, w = np.polynomial.legendre.leggauss(k)
+    g = 0.5 * (g + 1.0)
+    w = 0.5 * w
+    xi, eta, wt = [], [], []
+    for a in range(k):
+        for b in range(k):
+            u, v = g[a], g[b]
+            xi.append(u)
+            eta.append(v * (1.0 - u))
+            wt.append(w[a] * w[b] * (1.0 - u))
+    return np.array(xi), np.array(eta), np.array(wt)
+
+
+def _basis(l0, l1, l2):
+    """Values of the six basis functions at barycentric points (arrays)."""
+    return np.stack([l0 * (2 * l0 - 1), l1 * (2 * l1 - 1), l2 * (2 * l2 - 1),
+                     4 * l0 * l1, 4 * l1 * l2, 4 * l2 * l0])
+
+
+def _basis_grad_bary(l0, l1, l2):
+    """d phi_k / d lambda_a, shape (6, 3, n_points)."""
+    z = np.zeros_like(l0)
+    return np.stack([
+        np.stack([4 * l0 - 1, z, z]),
+        np.stack([z, 4 * l1 - 1, z]),
+        np.stack([z, z, 4 * l2 - 1]),
+        np.stack([4 * l1, 4 * l0, z]),
+        np.stack([z, 4 * l2, 4 * l1]),
+        np.stack([4 * l2, z, 4 * l0]),
+    ])
+
+
+def local_matrices_p2(coords, elems):
+    """K_e, M_e (n_elems, 6, 6) and area (n_elems,) of straight P2 triangles.
+
+    coords (n_nodes, 2); elems (n_elems, 6): vertices, then the midpoints of
+    edges (0,1), (1,2), (2,0).  Only the vertices enter the (affine) map."""
+    coords = np.asarray(coords, dtype=np.float64)
+    elems = np.asarray(elems, dtype=np.int64)
+    xi, eta, wt = _rule(4)
+    l0, l1, l2 = 1.0 - xi - eta, xi, eta
+    phi = _basis(l0, l1, l2)                 # (6, q)
+    dphi = _basis_grad_bary(l0, l1, l2)      # (6, 3, q)
+    ne = elems.shape[0]
+    K = np.empty((ne, NB, NB))
+    M = np.empty((ne, NB, NB))
+    area = np.empty(ne)
+    for e in range(ne):
+        p = coords[elems[e, :3]]
+        B = np.stack([p[1] - p[0], p[2] - p[0]], axis=1)   # columns: edge vectors
+        det = np.linalg.det(B)
+        Binv = np.linalg.inv(B)
+        gl = np.vstack([-(Binv[0] + Binv[1]), Binv[0], Binv[1]])  # grad lambda_a, (3, 2)
+        G = np.einsum("kaq,ad->kqd", dphi, gl)                   # grad phi_k at the points
+        jac = abs(det)
+        K[e] = np.einsum("iqd,jqd,q->ij", G, G, wt) * jac
+        M[e] = np.einsum("iq,jq,q->ij", phi, phi, wt) * jac
+        area[e] = 0.5 * jac
+    return K, M, area

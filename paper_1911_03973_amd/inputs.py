@@ -35,6 +35,7 @@ import numpy as np
 __all__ = [
     "Mesh",
     "square_mesh",
+    "square_mesh_p2",
     "cube_mesh",
     "boundary_nodes",
     "dirichlet_nodes",
@@ -139,6 +140,40 @@ def square_mesh(n: int, order: str = "morton", jitter: float = 0.0, seed: int = 
     t2 = np.stack([a, c, d], axis=1)
     elems = np.stack([t1, t2], axis=1).reshape(-1, 3).astype(np.int32)
     return Mesh(coords=coords, elems=elems, n=n)
+
+
+def square_mesh_p2(n: int, order: str = "morton", jitter: float = 0.0, seed: int = 0) -> Mesh:
+    """Quadratic (P2) triangles on the diagonal-cut mesh of n x n squares.
+
+    The nodes are the points of the (2n+1) x (2n+1) lattice of half-steps:
+    lattice point (I, J) -> J*(2n+1) + I; even-even points are the triangle
+    vertices, the others the midpoints of the horizontal, vertical and
+    diagonal edges (the diagonal midpoint is the square's centre).  Each
+    element lists its vertices [a, b, c] as in :func:`square_mesh`, then the
+    midpoints of its edges (a, b), (b, c), (c, a).  Jitter moves the interior
+    vertices as in :func:`square_mesh` (same seed, same draws); midpoints stay
+    at the middle of their (straight) edges.  ``Mesh.n`` is 2n, the lattice
+    size, so :func:`boundary_nodes` finds the boundary by lattice index.
+    """
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    base = square_mesh(n, order=order, jitter=jitter, seed=seed)
+    m, M = n + 1, 2 * n + 1
+    vi, vj = np.arange(base.n_nodes) % m, np.arange(base.n_nodes) // m
+    lat = (2 * vj) * M + 2 * vi  # lattice id of every vertex
+    coords = np.zeros((M * M, 2))
+    coords[lat] = base.coords
+    e = base.elems.astype(np.int64)
+    la, lb, lc = lat[e[:, 0]], lat[e[:, 1]], lat[e[:, 2]]
+
+    def mid(p, q):  # lattice midpoint of two lattice points (both even-even)
+        return ((p // M + q // M) // 2) * M + (p % M + q % M) // 2
+
+    mab, mbc, mca = mid(la, lb), mid(lb, lc), mid(lc, la)
+    for mm, p, q in ((mab, la, lb), (mbc, lb, lc), (mca, lc, la)):
+        coords[mm] = 0.5 * (coords[p] + coords[q])
+    elems = np.stack([la, lb, lc, mab, mbc, mca], axis=1).astype(np.int32)
+    return Mesh(coords=coords, elems=elems, n=2 * n)
 
 
 def square_hierarchy(mesh: Mesh, coarsest: int = 16, order: str = "morton") -> list:
