@@ -38,6 +38,11 @@ WORKLOADS = {
                name="batched: 256 independent 2D P1 problems, N~U{32..512} squares per side, nu log-uniform "
                     "[1e-3,1e3], random-sine f (per-problem seeds), full Dirichlet; one persistent launch, "
                     "FP32 element matvec + FP64 refinement to 1e-8 per problem"),
+    "p2": dict(dim=2, n=1024, jitter=0.2, jseed=0, nu=1.0, f="sine", fseed=1, dirichlet="x2=0", dtype="f32x2",
+               order=2,
+               name="2D quadratic (P2) triangles on 1024x1024 squares (4198401 nodes, 2097152 triangles), "
+                    "jitter 0.2h, nu=1, random-sine f, Dirichlet x2=0; FP32 element matvec + FP64 refinement "
+                    "to 1e-8"),
     "c3": dict(dim=3, n=160, jitter=0.0, jseed=0, nu=10.0, f="one", fseed=0, dirichlet="all", dtype="f32x2",
                name="3D P1 160^3 cubes x 6 tets (4173281 nodes, 24576000 tets), nu=10, f=1, full Dirichlet; "
                     "FP32 element matvec + FP64 refinement to 1e-8"),
@@ -53,7 +58,9 @@ def make_problem(w):
 
     from paper_1911_03973_amd import inputs
 
-    if w["dim"] == 2:
+    if w.get("order") == 2:
+        mesh = inputs.square_mesh_p2(w["n"], jitter=w["jitter"], seed=w["jseed"])
+    elif w["dim"] == 2:
         mesh = inputs.square_mesh(w["n"], jitter=w["jitter"], seed=w["jseed"])
     else:
         mesh = inputs.cube_mesh(w["n"], jitter=w["jitter"], seed=w["jseed"])
@@ -69,7 +76,12 @@ def cpu_baseline(mesh, w, seconds):
     import oracle
 
     t = time.perf_counter()
-    K, M, _ = oracle.local_matrices(mesh.coords, mesh.elems)
+    if mesh.nb == 6:
+        import oracle.p2
+
+        K, M, _ = oracle.p2.local_matrices_p2(mesh.coords, mesh.elems)
+    else:
+        K, M, _ = oracle.local_matrices(mesh.coords, mesh.elems)
     t_local = time.perf_counter() - t
     rng = np.random.default_rng(0)
     x = rng.standard_normal(mesh.n_nodes)

@@ -78,15 +78,17 @@ def local_matrices_p2(coords, elems):
     K = np.empty((ne, NB, NB))
     M = np.empty((ne, NB, NB))
     area = np.empty(ne)
-    for e in range(ne):
-        p = coords[elems[e, :3]]
-        B = np.stack([p[1] - p[0], p[2] - p[0]], axis=1)   # columns: edge vectors
+    Mref = np.einsum("iq,jq,q->ij", phi, phi, wt)  # int over the reference triangle
+    step = 32768
+    for e0 in range(0, ne, step):  # blocks of elements, each by the same formulas
+        p = coords[elems[e0:e0 + step, :3]]                       # (b, 3, 2)
+        B = np.stack([p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]], axis=2)  # columns: edge vectors
         det = np.linalg.det(B)
-        Binv = np.linalg.inv(B)
-        gl = np.vstack([-(Binv[0] + Binv[1]), Binv[0], Binv[1]])  # grad lambda_a, (3, 2)
-        G = np.einsum("kaq,ad->kqd", dphi, gl)                   # grad phi_k at the points
-        jac = abs(det)
-        K[e] = np.einsum("iqd,jqd,q->ij", G, G, wt) * jac
-        M[e] = np.einsum("iq,jq,q->ij", phi, phi, wt) * jac
-        area[e] = 0.5 * jac
+        Binv = np.linalg.inv(B)                                   # rows: grad lambda_1, grad lambda_2
+        gl = np.concatenate([-(Binv[:, 0:1] + Binv[:, 1:2]), Binv], axis=1)  # (b, 3, 2)
+        G = np.einsum("kaq,ead->ekqd", dphi, gl)                   # grad phi_k at the points
+        jac = np.abs(det)
+        K[e0:e0 + step] = np.einsum("eiqd,ejqd,q->eij", G, G, wt) * jac[:, None, None]
+        M[e0:e0 + step] = Mref[None] * jac[:, None, None]
+        area[e0:e0 + step] = 0.5 * jac
     return K, M, area

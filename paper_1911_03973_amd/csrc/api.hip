@@ -144,9 +144,10 @@ void fem_solve_opts_default(fem_solve_opts *o) {
     o->block = 0;
 }
 
-int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_coords, const int32_t *d_conn,
-                    const int32_t *d_dirichlet, int64_t n_dirichlet, int chunk_elems, void *stream,
-                    fem_plan **out) {
+namespace {
+
+int plan_create(int dim, int nb, int64_t n_nodes, int64_t n_elems, const double *d_coords, const int32_t *d_conn,
+                const int32_t *d_dirichlet, int64_t n_dirichlet, int chunk_elems, void *stream, fem_plan **out) {
     fem::last_error().clear();
     if (!out) return set_error(FEM_EINVAL, "out is NULL");
     *out = nullptr;
@@ -156,11 +157,11 @@ int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_c
     if (!d_coords) return set_error(FEM_EINVAL, "coords is NULL");
     if (n_elems > 0 && !d_conn) return set_error(FEM_EINVAL, "conn is NULL");
     if (n_dirichlet < 0 || (n_dirichlet > 0 && !d_dirichlet)) return set_error(FEM_EINVAL, "bad Dirichlet list");
-    const int nb = dim + 1;
     if (chunk_elems == 0) chunk_elems = fem::default_chunk_elems(nb);
     if (!fem::valid_chunk_elems(nb, chunk_elems))
-        return set_error(FEM_EINVAL, nb == 3 ? "chunk_elems must be one of 64, 128, 256, 512, 1024, 1536, 2048"
-                                             : "chunk_elems must be one of 64, 128, 256, 512, 1024, 1536");
+        return set_error(FEM_EINVAL, nb == 3   ? "chunk_elems must be one of 64, 128, 256, 512, 1024, 1536, 2048"
+                                     : nb == 4 ? "chunk_elems must be one of 64, 128, 256, 512, 1024, 1536"
+                                               : "chunk_elems must be one of 64, 128, 256, 512, 1024");
     hipStream_t s = S(stream);
     std::vector<double> coords((size_t)dim * n_nodes);
     std::vector<int32_t> conn((size_t)nb * n_elems);
@@ -177,7 +178,7 @@ int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_c
     fem::HostPlan H;
     std::string err;
     try {
-        if (fem::build_host_plan(dim, n_nodes, n_elems, coords.data(), conn.data(), dir.data(), n_dirichlet,
+        if (fem::build_host_plan(dim, nb, n_nodes, n_elems, coords.data(), conn.data(), dir.data(), n_dirichlet,
                                  chunk_elems, H, err) != 0)
             return set_error(FEM_EINVAL, err);
     } catch (const std::bad_alloc &) {
@@ -279,6 +280,22 @@ int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_c
     return FEM_OK;
 }
 
+}  // namespace
+
+int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_coords, const int32_t *d_conn,
+                    const int32_t *d_dirichlet, int64_t n_dirichlet, int chunk_elems, void *stream,
+                    fem_plan **out) {
+    return plan_create(dim, dim + 1, n_nodes, n_elems, d_coords, d_conn, d_dirichlet, n_dirichlet, chunk_elems,
+                       stream, out);
+}
+
+int fem_plan_create_p2(int64_t n_nodes, int64_t n_elems, const double *d_coords, const int32_t *d_conn,
+                       const int32_t *d_dirichlet, int64_t n_dirichlet, int chunk_elems, void *stream,
+                       fem_plan **out) {
+    return plan_create(2, 6, n_nodes, n_elems, d_coords, d_conn, d_dirichlet, n_dirichlet, chunk_elems, stream,
+                       out);
+}
+
 int fem_plan_check_host(int dim, int64_t n_nodes, int64_t n_elems, const double *coords, const int32_t *conn,
                         const int32_t *dirichlet, int64_t n_dirichlet, int chunk_elems, fem_plan_stats *out) {
     fem::last_error().clear();
@@ -298,7 +315,7 @@ int fem_plan_check_host(int dim, int64_t n_nodes, int64_t n_elems, const double 
     fem::HostPlan H;
     std::string err;
     try {
-        if (fem::build_host_plan(dim, n_nodes, n_elems, coords, conn, dirichlet, n_dirichlet, chunk_elems, H, err))
+        if (fem::build_host_plan(dim, dim + 1, n_nodes, n_elems, coords, conn, dirichlet, n_dirichlet, chunk_elems, H, err))
             return set_error(FEM_EINVAL, err);
     } catch (const std::bad_alloc &) {
         return set_error(FEM_ENOMEM, "host allocation failed while building the plan");
@@ -442,6 +459,8 @@ int fem_pcg_solve(const fem_plan *plan_c, const fem_solve_opts *o, const void *d
     if ((!d_K_e && plan->dev.n_elems > 0 && !mf) || !d_b || !d_x) return set_error(FEM_EINVAL, "NULL argument");
     if (o->nu != 0.0 && !d_M_e && !mf) return set_error(FEM_EINVAL, "nu > 0 needs M_e");
     if (mf && o->vectors != 0) return set_error(FEM_EINVAL, "the matrix-free solver keeps FP64 vectors");
+    if (plan->dev.nb == 6 && (mf || o->vectors != 0))
+        return set_error(FEM_EINVAL, "quadratic elements need stored matrices and FP64 vectors");
     if ((const void *)d_x == (const void *)d_b) return set_error(FEM_EINVAL, "x must not alias b");
     if (o->nu == 0.0 && plan->stats.n_dirichlet == 0)
         return set_error(FEM_ESINGULAR, "nu = 0 needs a Dirichlet part of positive measure");
@@ -484,6 +503,7 @@ int fem_iterate(const fem_plan *plan_c, const fem_iter_opts *o, const void *d_K_
     std::memset(info, 0, sizeof(*info));
     if (o->method < FEM_RICHARDSON || o->method > FEM_CHEBYSHEV3_LISTING)
         return set_error(FEM_EINVAL, "unknown iteration");
+    if (plan_c->dev.nb == 6) return set_error(FEM_EINVAL, "the iterations run on linear elements");
     if (!valid_dtype(o->dtype)) return set_error(FEM_EINVAL, "unknown dtype");
     if (!std::isfinite(o->nu) || o->nu < 0.0) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
     if (!std::isfinite(o->lam1) || !std::isfinite(o->lam2) || !(o->lam1 > 0.0) || !(o->lam2 > o->lam1))
@@ -528,6 +548,7 @@ int fem_fcg_solve(const fem_plan *plan_c, const fem_fcg_opts *o, fem_unet *net, 
     if (!o || !info) return set_error(FEM_EINVAL, "opts and info must not be NULL");
     std::memset(info, 0, sizeof(*info));
     info->fell_back = -1;
+    if (plan->dev.nb != 3) return set_error(FEM_EINVAL, "flexible CG with the network runs on linear triangles");
     if (!valid_dtype(o->dtype)) return set_error(FEM_EINVAL, "unknown dtype");
     if (!std::isfinite(o->nu) || o->nu < 0.0) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
     if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) return set_error(FEM_EINVAL, "rtol must be in (0, 1)");

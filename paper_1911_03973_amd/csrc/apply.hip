@@ -145,12 +145,14 @@ size_t device_lds_limit() {
 int launch_apply_mf(const DevPlan &P, double kk, double nu, const double *x, const double *b, double *out,
                     double sign, int use_mask, double *scratch, hipStream_t s) {
     if (P.nb == 3) return apply_mf_nb<3>(P, kk, nu, x, b, out, sign, use_mask, scratch, s);
-    return apply_mf_nb<4>(P, kk, nu, x, b, out, sign, use_mask, scratch, s);
+    if (P.nb == 4) return apply_mf_nb<4>(P, kk, nu, x, b, out, sign, use_mask, scratch, s);
+    return set_error(-1, "the matrix-free operator covers linear (P1) elements only");
 }
 
 int launch_diag_mf(const DevPlan &P, double nu, double *d, double *scratch, hipStream_t s) {
     if (P.nb == 3) return diag_mf_nb<3>(P, nu, d, scratch, s);
-    return diag_mf_nb<4>(P, nu, d, scratch, s);
+    if (P.nb == 4) return diag_mf_nb<4>(P, nu, d, scratch, s);
+    return set_error(-1, "the matrix-free operator covers linear (P1) elements only");
 }
 
 ChunkGrid chunk_grid(int64_t n_chunks, size_t lds, int bs) {
@@ -189,75 +191,60 @@ bool valid_chunk_elems(int nb, int E) {
     return (size_t)nb * E * (8 + 2) <= (size_t)kMaxChunkLds;
 }
 
-int default_chunk_elems(int nb) { return nb == 3 ? 1024 : 1536; }
+int default_chunk_elems(int nb) { return nb == 3 ? 1024 : nb == 4 ? 1536 : 512; }
 
 int default_block(int nb, int E) { return E > 1024 ? 512 : 256; }
 
 int launch_apply64(const DevPlan &P, int kind, const void *K, const void *M, double nu, const double *x,
                    const double *b, double *out, double sign, int use_mask, double *scratch, hipStream_t s) {
-#define FEM_A64(NB, KND) return apply64_nb<NB, KND>(P, K, M, nu, x, b, out, sign, use_mask, scratch, s)
-    if (P.nb == 3) {
-        if (kind == MAT_F64) FEM_A64(3, MAT_F64);
-        if (kind == MAT_F32) FEM_A64(3, MAT_F32);
-        FEM_A64(3, MAT_F32X2);
-    }
-    if (kind == MAT_F64) FEM_A64(4, MAT_F64);
-    if (kind == MAT_F32) FEM_A64(4, MAT_F32);
-    FEM_A64(4, MAT_F32X2);
-#undef FEM_A64
+    return dispatch_nb(P.nb, [&](auto nbc) -> int {
+        constexpr int NB = decltype(nbc)::value;
+        if (kind == MAT_F64) return apply64_nb<NB, MAT_F64>(P, K, M, nu, x, b, out, sign, use_mask, scratch, s);
+        if (kind == MAT_F32) return apply64_nb<NB, MAT_F32>(P, K, M, nu, x, b, out, sign, use_mask, scratch, s);
+        return apply64_nb<NB, MAT_F32X2>(P, K, M, nu, x, b, out, sign, use_mask, scratch, s);
+    });
 }
 
 int launch_apply_pk64(const DevPlan &P, int kind, const void *A, const double *x, const double *b, double *out,
                       double sign, int use_mask, double *scratch, hipStream_t s) {
-    if (P.nb == 3) {
-        if (kind == MAT_F64) return apply_pk64_nb<3, MAT_F64>(P, A, x, b, out, sign, use_mask, scratch, s);
-        return apply_pk64_nb<3, MAT_F32X2>(P, A, x, b, out, sign, use_mask, scratch, s);
-    }
-    if (kind == MAT_F64) return apply_pk64_nb<4, MAT_F64>(P, A, x, b, out, sign, use_mask, scratch, s);
-    return apply_pk64_nb<4, MAT_F32X2>(P, A, x, b, out, sign, use_mask, scratch, s);
+    return dispatch_nb(P.nb, [&](auto nbc) -> int {
+        constexpr int NB = decltype(nbc)::value;
+        if (kind == MAT_F64) return apply_pk64_nb<NB, MAT_F64>(P, A, x, b, out, sign, use_mask, scratch, s);
+        return apply_pk64_nb<NB, MAT_F32X2>(P, A, x, b, out, sign, use_mask, scratch, s);
+    });
 }
 
 int launch_diag_pk64(const DevPlan &P, int kind, const void *A, double *d, double *scratch, hipStream_t s) {
     OpAffine<double> op{nullptr, nullptr, d, P.mask, 1.0, 0};
-    if (P.nb == 3) {
+    return dispatch_nb(P.nb, [&](auto nbc) -> int {
+        constexpr int NB = decltype(nbc)::value;
         if (kind == MAT_F64) {
-            LdPk<3, MAT_F64> ld{A, P.n_elems};
-            return run_chunked<3, double, decltype(ld), decltype(op), true>(P, ld, op, scratch, s);
+            LdPk<NB, MAT_F64> ld{A, P.n_elems};
+            return run_chunked<NB, double, decltype(ld), decltype(op), true>(P, ld, op, scratch, s);
         }
-        LdPk<3, MAT_F32X2> ld{A, P.n_elems};
-        return run_chunked<3, double, decltype(ld), decltype(op), true>(P, ld, op, scratch, s);
-    }
-    if (kind == MAT_F64) {
-        LdPk<4, MAT_F64> ld{A, P.n_elems};
-        return run_chunked<4, double, decltype(ld), decltype(op), true>(P, ld, op, scratch, s);
-    }
-    LdPk<4, MAT_F32X2> ld{A, P.n_elems};
-    return run_chunked<4, double, decltype(ld), decltype(op), true>(P, ld, op, scratch, s);
+        LdPk<NB, MAT_F32X2> ld{A, P.n_elems};
+        return run_chunked<NB, double, decltype(ld), decltype(op), true>(P, ld, op, scratch, s);
+    });
 }
 
 int launch_apply32(const DevPlan &P, const float *A, const float *x, const float *b, float *out, float sign,
                    int use_mask, float *scratch, hipStream_t s) {
     OpAffine<float> op{x, b, out, P.mask, sign, use_mask};
-    if (P.nb == 3) {
-        LdF32<3> ld{A, P.n_elems};
-        return run_chunked<3, float, decltype(ld), decltype(op), false>(P, ld, op, scratch, s);
-    }
-    LdF32<4> ld{A, P.n_elems};
-    return run_chunked<4, float, decltype(ld), decltype(op), false>(P, ld, op, scratch, s);
+    return dispatch_nb(P.nb, [&](auto nbc) -> int {
+        constexpr int NB = decltype(nbc)::value;
+        LdF32<NB> ld{A, P.n_elems};
+        return run_chunked<NB, float, decltype(ld), decltype(op), false>(P, ld, op, scratch, s);
+    });
 }
 
 int launch_diag64(const DevPlan &P, int kind, const void *K, const void *M, double nu, double *d,
                   double *scratch, hipStream_t s) {
-#define FEM_D64(NB, KND) return diag64_nb<NB, KND>(P, K, M, nu, d, scratch, s)
-    if (P.nb == 3) {
-        if (kind == MAT_F64) FEM_D64(3, MAT_F64);
-        if (kind == MAT_F32) FEM_D64(3, MAT_F32);
-        FEM_D64(3, MAT_F32X2);
-    }
-    if (kind == MAT_F64) FEM_D64(4, MAT_F64);
-    if (kind == MAT_F32) FEM_D64(4, MAT_F32);
-    FEM_D64(4, MAT_F32X2);
-#undef FEM_D64
+    return dispatch_nb(P.nb, [&](auto nbc) -> int {
+        constexpr int NB = decltype(nbc)::value;
+        if (kind == MAT_F64) return diag64_nb<NB, MAT_F64>(P, K, M, nu, d, scratch, s);
+        if (kind == MAT_F32) return diag64_nb<NB, MAT_F32>(P, K, M, nu, d, scratch, s);
+        return diag64_nb<NB, MAT_F32X2>(P, K, M, nu, d, scratch, s);
+    });
 }
 
 }  // namespace fem

@@ -681,6 +681,18 @@ int dispatch_ept(int E, F &&f) {
     }
 }
 
+// Calls f(integral_constant<NB>) for the element sizes the library runs:
+// linear triangles (3), linear tetrahedra (4) and quadratic triangles (6).
+template <class F>
+int dispatch_nb(int nb, F &&f) {
+    switch (nb) {
+        case 3: return f(std::integral_constant<int, 3>());
+        case 4: return f(std::integral_constant<int, 4>());
+        case 6: return f(std::integral_constant<int, 6>());
+        default: return set_error(-1, "unsupported element size");
+    }
+}
+
 // Calls f(integral_constant<BS>, integral_constant<EPT>) for a chunk size E
 // and a workgroup size BS in {256, 512, 1024} (EPT = ceil(E / BS)).
 template <class F>

@@ -109,6 +109,154 @@ __global__ __launch_bounds__(kBlock) void k_local_matrices(const double *__restr
     }
 }
 
+// Quadratic (P2) triangles.  With barycentric coordinates lambda_0..2 the six
+// Lagrange functions are phi_k = lambda_k (2 lambda_k - 1) (vertices) and
+// phi_{3+e} = 4 lambda_u lambda_v for the edges e = (0,1), (1,2), (2,0).  Their
+// gradients are sum_a c_ka grad(lambda_a) with factors c_ka linear in lambda,
+// so K_ij = area * sum_ab (grad lambda_a . grad lambda_b) S[i][a][j][b] with
+// S[i][a][j][b] = (1/area) int c_ia c_jb, and M_ij = area * Mref[i][j] with
+// Mref[i][j] = (1/area) int phi_i phi_j.  Both tables are integrals of
+// barycentric monomials, (1/area) int lambda^alpha = 2 alpha! / (|alpha| + 2)!,
+// evaluated at compile time.
+struct P2Tables {
+    double S[6][3][6][3];
+    double M[6][6];
+};
+
+constexpr double p2_fact(int n) { return n <= 1 ? 1.0 : n * p2_fact(n - 1); }
+
+// (1/area) int over the triangle of lambda_0^a0 lambda_1^a1 lambda_2^a2
+constexpr double p2_mono(int a0, int a1, int a2) {
+    return 2.0 * p2_fact(a0) * p2_fact(a1) * p2_fact(a2) / p2_fact(a0 + a1 + a2 + 2);
+}
+
+constexpr P2Tables p2_tables() {
+    P2Tables t{};
+    // c_ka = sum_p A[k][a][p] lambda_p + B[k][a]
+    double A[6][3][3] = {};
+    double B[6][3] = {};
+    const int eu[3] = {0, 1, 2}, ev[3] = {1, 2, 0};
+    for (int k = 0; k < 3; ++k) {
+        A[k][k][k] = 4.0;
+        B[k][k] = -1.0;
+    }
+    for (int e = 0; e < 3; ++e) {
+        A[3 + e][eu[e]][ev[e]] = 4.0;
+        A[3 + e][ev[e]][eu[e]] = 4.0;
+    }
+    for (int i = 0; i < 6; ++i)
+        for (int a = 0; a < 3; ++a)
+            for (int j = 0; j < 6; ++j)
+                for (int b = 0; b < 3; ++b) {
+                    double v = B[i][a] * B[j][b];
+                    for (int p = 0; p < 3; ++p) {
+                        int ep[3] = {0, 0, 0};
+                        ep[p] = 1;
+                        v += (A[i][a][p] * B[j][b] + B[i][a] * A[j][b][p]) * p2_mono(ep[0], ep[1], ep[2]);
+                        for (int q = 0; q < 3; ++q) {
+                            int eq[3] = {ep[0], ep[1], ep[2]};
+                            eq[q] += 1;
+                            v += A[i][a][p] * A[j][b][q] * p2_mono(eq[0], eq[1], eq[2]);
+                        }
+                    }
+                    t.S[i][a][j][b] = v;
+                }
+    // phi_k as a quadratic form in lambda: phi_k = sum_pq C[k][p][q] lambda_p lambda_q
+    // (lambda_k (2 lambda_k - 1) = lambda_k^2 - sum_{m != k} lambda_k lambda_m, since sum lambda = 1)
+    double C[6][3][3] = {};
+    for (int k = 0; k < 3; ++k)
+        for (int m = 0; m < 3; ++m) {
+            if (m == k) C[k][k][k] = 1.0;
+            else {
+                C[k][k][m] = -0.5;
+                C[k][m][k] = -0.5;
+            }
+        }
+    for (int e = 0; e < 3; ++e) {
+        C[3 + e][eu[e]][ev[e]] = 2.0;
+        C[3 + e][ev[e]][eu[e]] = 2.0;
+    }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            double v = 0.0;
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q)
+                    for (int r = 0; r < 3; ++r)
+                        for (int u = 0; u < 3; ++u) {
+                            const double c = C[i][p][q] * C[j][r][u];
+                            if (c == 0.0) continue;
+                            int ex[3] = {0, 0, 0};
+                            ex[p] += 1;
+                            ex[q] += 1;
+                            ex[r] += 1;
+                            ex[u] += 1;
+                            v += c * p2_mono(ex[0], ex[1], ex[2]);
+                        }
+            t.M[i][j] = v;
+        }
+    return t;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_local_matrices_p2(const double *__restrict__ coords,
+                                                              const int32_t *__restrict__ conn,
+                                                              int64_t n_nodes, int64_t n_elems,
+                                                              void *__restrict__ K, void *__restrict__ M,
+                                                              double *__restrict__ vol) {
+    constexpr int NB = 6;
+    constexpr P2Tables T = p2_tables();
+    const int64_t blk = (int64_t)NB * NB * n_elems;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_elems;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double p[3][2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int32_t v = conn[(int64_t)a * n_elems + e];
+            p[a][0] = coords[v];
+            p[a][1] = coords[n_nodes + v];
+        }
+        const double b00 = p[1][0] - p[0][0], b01 = p[2][0] - p[0][0];
+        const double b10 = p[1][1] - p[0][1], b11 = p[2][1] - p[0][1];
+        const double det = b00 * b11 - b01 * b10;
+        // grad lambda_1, grad lambda_2 are the rows of B^{-1}; grad lambda_0 = -(their sum)
+        double G[3][2];
+        G[1][0] = b11 / det;
+        G[1][1] = -b01 / det;
+        G[2][0] = -b10 / det;
+        G[2][1] = b00 / det;
+        G[0][0] = -(G[1][0] + G[2][0]);
+        G[0][1] = -(G[1][1] + G[2][1]);
+        const double area = 0.5 * fabs(det);
+        if (K) {
+            double g[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) g[a][b] = G[a][0] * G[b][0] + G[a][1] * G[b][1];
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b)
+                            if (T.S[i][a][j][b] != 0.0) v += T.S[i][a][j][b] * g[a][b];
+                    store_entry<KIND>(K, (int64_t)(i * NB + j) * n_elems + e, blk, area * v);
+                }
+        }
+        if (M) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+                    store_entry<KIND>(M, (int64_t)(i * NB + j) * n_elems + e, blk, area * T.M[i][j]);
+        }
+        if (vol) vol[e] = area;
+    }
+}
+
 template <int NB, int KIN, int KOUT>
 __global__ __launch_bounds__(kBlock) void k_combine(const void *__restrict__ K, const void *__restrict__ M,
                                                     double nu, int64_t n_elems, void *__restrict__ A) {
@@ -178,7 +326,13 @@ int launch_local_matrices(const DevPlan &P, int kind, void *K, void *M, double *
     const int g = grid_for(P.n_elems, 65536);
 #define FEM_LM(D, KND) \
     k_local_matrices<D, KND><<<g, kBlock, 0, s>>>(P.coords, P.conn, P.n_nodes, P.n_elems, K, M, vol)
-    if (P.dim == 2) {
+#define FEM_LM2(KND) \
+    k_local_matrices_p2<KND><<<g, kBlock, 0, s>>>(P.coords, P.conn, P.n_nodes, P.n_elems, K, M, vol)
+    if (P.nb == 6) {
+        if (kind == MAT_F64) FEM_LM2(MAT_F64);
+        else if (kind == MAT_F32) FEM_LM2(MAT_F32);
+        else FEM_LM2(MAT_F32X2);
+    } else if (P.dim == 2) {
         if (kind == MAT_F64) FEM_LM(2, MAT_F64);
         else if (kind == MAT_F32) FEM_LM(2, MAT_F32);
         else FEM_LM(2, MAT_F32X2);
@@ -188,6 +342,7 @@ int launch_local_matrices(const DevPlan &P, int kind, void *K, void *M, double *
         else FEM_LM(3, MAT_F32X2);
     }
 #undef FEM_LM
+#undef FEM_LM2
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
@@ -209,7 +364,8 @@ int launch_combine(const DevPlan &P, int kin, const void *K, const void *M, doub
         else FEM_CB_OUT(NB, MAT_F32X2);            \
     } while (0)
     if (P.nb == 3) FEM_CB_IN(3);
-    else FEM_CB_IN(4);
+    else if (P.nb == 4) FEM_CB_IN(4);
+    else FEM_CB_IN(6);
 #undef FEM_CB_IN
 #undef FEM_CB_OUT
 #undef FEM_CB
@@ -233,7 +389,8 @@ int launch_pack(const DevPlan &P, int kin, const void *K, const void *M, double 
         else FEM_PK_OUT(NB, MAT_F32X2);                     \
     } while (0)
     if (P.nb == 3) FEM_PK_IN(3);
-    else FEM_PK_IN(4);
+    else if (P.nb == 4) FEM_PK_IN(4);
+    else FEM_PK_IN(6);
 #undef FEM_PK_IN
 #undef FEM_PK_OUT
 #undef FEM_PK

@@ -243,7 +243,7 @@ int fem_mg_create(int levels, const fem_plan *const *plans, const int *grid_n, i
     for (int l = 0; l < levels; ++l) {
         if (!plans[l] || !K[l] || (nu != 0.0 && (!M || !M[l]))) return set_error(FEM_EINVAL, "NULL plan or matrix");
         const fem_plan_stats st = plan_stats(plans[l]);
-        if (st.dim != 2 || grid_n[l] < 1 || st.n_nodes != (int64_t)(grid_n[l] + 1) * (grid_n[l] + 1) ||
+        if (st.dim != 2 || st.n_b != 3 || grid_n[l] < 1 || st.n_nodes != (int64_t)(grid_n[l] + 1) * (grid_n[l] + 1) ||
             st.n_elems != 2 * (int64_t)grid_n[l] * grid_n[l])
             return set_error(FEM_EINVAL, "level " + std::to_string(l) + " is not an n x n diagonal-cut square mesh");
         if (l > 0 && grid_n[l - 1] != 2 * grid_n[l])

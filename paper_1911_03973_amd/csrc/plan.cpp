@@ -50,10 +50,13 @@ void parallel_for(int64_t n, F &&f) {
 
 }  // namespace
 
-int build_host_plan(int dim, int64_t n_nodes, int64_t n_elems, const double *coords,
+int build_host_plan(int dim, int nb, int64_t n_nodes, int64_t n_elems, const double *coords,
                     const int32_t *conn, const int32_t *dirichlet, int64_t n_dir, int chunk_elems,
                     HostPlan &P, std::string &err) {
-    const int nb = dim + 1;
+    if (nb != dim + 1 && !(dim == 2 && nb == 6)) {
+        err = "elements must be linear simplices or quadratic triangles";
+        return -1;
+    }
     P = HostPlan();
     P.dim = dim;
     P.nb = nb;
@@ -67,7 +70,7 @@ int build_host_plan(int dim, int64_t n_nodes, int64_t n_elems, const double *coo
     parallel_for(P.n_chunks, [&](int64_t c) {
         int64_t e0 = c * chunk_elems, e1 = std::min<int64_t>(n_elems, e0 + chunk_elems);
         for (int64_t e = e0; e < e1 && !bad[c]; ++e) {
-            int32_t v[4];
+            int32_t v[6];
             for (int a = 0; a < nb; ++a) {
                 v[a] = conn[(int64_t)a * n_elems + e];
                 if (v[a] < 0 || v[a] >= n_nodes) { bad[c] = 1; break; }
@@ -247,7 +250,7 @@ int build_batch_plan(int dim, int n_problems, const int64_t *node_off, const int
         std::vector<int32_t> le((size_t)nb * ne);
         for (int a = 0; a < nb; ++a)
             for (int64_t e = 0; e < ne; ++e) le[(size_t)a * ne + e] = conn[(size_t)a * NE + elem_off[p] + e];
-        rcs[p] = build_host_plan(dim, nn, ne, lc.data(), le.data(), dirichlet + dir_off[p], dir_off[p + 1] - dir_off[p],
+        rcs[p] = build_host_plan(dim, dim + 1, nn, ne, lc.data(), le.data(), dirichlet + dir_off[p], dir_off[p + 1] - dir_off[p],
                                  chunk_elems, parts[p], errs[p]);
     });
     for (int p = 0; p < n_problems; ++p)

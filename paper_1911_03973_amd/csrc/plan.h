@@ -55,7 +55,10 @@ struct DevPlan {
     const uint8_t *mask;
 };
 
-int build_host_plan(int dim, int64_t n_nodes, int64_t n_elems, const double *coords,
+// nb = dim + 1 (linear simplices) or, in 2D, 6 (quadratic triangles: the
+// three vertices, then the midpoints of edges (0,1), (1,2), (2,0); the volume
+// check uses the vertices).
+int build_host_plan(int dim, int nb, int64_t n_nodes, int64_t n_elems, const double *coords,
                     const int32_t *conn, const int32_t *dirichlet, int64_t n_dir, int chunk_elems,
                     HostPlan &P, std::string &err);
 

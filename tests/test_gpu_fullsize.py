@@ -223,3 +223,50 @@ def test_full_size_mfree_on_sampled_nodes_and_solve(name, E, block):
     ro = oracle.residual(mesh.n_nodes, mesh.elems, Ko, Mo, nu, bo, xs.cpu().numpy(), mask)
     r0 = oracle.residual(mesh.n_nodes, mesh.elems, Ko, Mo, nu, bo, np.zeros(mesh.n_nodes), mask)
     assert np.linalg.norm(ro) / np.linalg.norm(r0) <= 1.05e-8
+
+
+def test_full_size_p2_on_sampled_nodes_and_solve():
+    """The P2 benchmark workload (1024^2 squares, 4.2 M nodes, 2.1 M quadratic
+    triangles, FP32 hi/lo storage, the bench's launch configuration): local
+    matrices on sampled elements, b and the residual on sampled nodes, and the
+    oracle's residual of the solution."""
+    import oracle.p2 as op2
+
+    mesh = inputs.square_mesh_p2(1024, jitter=0.2, seed=0)
+    nd = inputs.boundary_nodes(mesh, "x2=0")
+    nu = 1.0
+    f = inputs.random_sine(mesh.coords, 1)
+    rng = np.random.default_rng(44)
+    plan = fem.Plan.from_mesh(mesh, nd)
+    K = plan.empty_matrix(fem.F32X2)
+    M = plan.empty_matrix(fem.F32X2)
+    fem.build_local_matrices(plan, fem.F32X2, K, M, None)
+    b = plan.empty_vector()
+    fem.assemble_rhs(plan, fem.F32X2, M, cuda(f), b)
+    x = rng.standard_normal(mesh.n_nodes)
+    r = plan.empty_vector()
+    fem.element_residual(plan, fem.F32X2, K, M, nu, b, cuda(x), r, mask=True)
+    torch.cuda.synchronize()
+    es = rng.choice(mesh.n_elems, size=SAMPLES, replace=False)
+    Ko, Mo, _ = op2.local_matrices_p2(mesh.coords, mesh.elems[es])
+    assert np.abs(pair_value(K)[:, es] - to_soa(Ko)).max() <= 1e-12 * np.abs(Ko).max()
+    assert np.abs(pair_value(M)[:, es] - to_soa(Mo)).max() <= 1e-12 * np.abs(Mo).max()
+    ns = rng.choice(mesh.n_nodes, size=SAMPLES, replace=False)
+    sub = mesh.elems[_sub_elements(mesh, ns)]
+    Ks, Ms, _ = op2.local_matrices_p2(mesh.coords, sub)
+    bs = oracle.rhs(mesh.n_nodes, sub, Ms, f)
+    mask = oracle.mask_from_nodes(mesh.n_nodes, nd)
+    rs = oracle.residual(mesh.n_nodes, sub, Ks, Ms, nu, bs, x, mask)
+    scale = oracle.residual_scale(mesh.n_nodes, sub, Ks, Ms, nu, bs, x)
+    bg, rg = b.cpu().numpy(), r.cpu().numpy()
+    assert np.abs(bg[ns] - bs[ns]).max() <= 1e-12 * np.abs(bs[ns]).max()
+    assert np.all(np.abs(rg[ns] - rs[ns]) <= 1e-12 * scale[ns] + 1e-300)
+    xs = torch.zeros(mesh.n_nodes, dtype=torch.float64, device="cuda")
+    info = fem.pcg_solve(plan, fem.solve_opts(dtype=fem.F32X2, nu=nu, rtol=1e-8, check_every=64), K, M, b, xs)
+    print("p2", info, flush=True)
+    assert info["status"] == 0 and info["relres"] <= 1e-8
+    Kf, Mf, _ = op2.local_matrices_p2(mesh.coords, mesh.elems)
+    bo = oracle.rhs(mesh.n_nodes, mesh.elems, Mf, f)
+    ro = oracle.residual(mesh.n_nodes, mesh.elems, Kf, Mf, nu, bo, xs.cpu().numpy(), mask)
+    r0 = oracle.residual(mesh.n_nodes, mesh.elems, Kf, Mf, nu, bo, np.zeros(mesh.n_nodes), mask)
+    assert np.linalg.norm(ro) / np.linalg.norm(r0) <= 1.05e-8
