@@ -105,7 +105,7 @@ int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_c
  * exactly.  The residual, diagonal, right-hand side and fem_pcg_solve (stored
  * FEM_F64 / FEM_F32X2 / FEM_F32 matrices, FP64 vectors) accept such a plan;
  * the matrix-free operator, the iterations, flexible CG, multigrid and the
- * batched solver return FEM_EINVAL.  chunk_elems: 64 ... 1024 (default 512). */
+ * batched solver return FEM_EINVAL.  chunk_elems: 64 ... 1024 (default 1024). */
 int fem_plan_create_p2(int64_t n_nodes, int64_t n_elems, const double *d_coords, const int32_t *d_conn,
                        const int32_t *d_dirichlet, int64_t n_dirichlet, int chunk_elems, void *stream,
                        fem_plan **out);
