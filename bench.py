@@ -547,7 +547,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["unet", "cheb", "mg"], default="c2")
     ap.add_argument("--mg-coarsest", type=int, default=16, help="mg workload: squares per side of the coarsest grid")
-    ap.add_argument("--mg-smooth", type=int, default=2, help="mg workload: Jacobi steps before and after")
+    ap.add_argument("--mg-smooth", type=int, default=1, help="mg workload: Jacobi steps before and after")
     ap.add_argument("--iter-n", type=int, default=2048, help="cheb workload: squares per side")
     ap.add_argument("--iter-steps", type=int, default=200, help="cheb workload: iterations of the shorter run")
     ap.add_argument("--profile", type=int, default=4, help="time every k-th matvec with HIP events")

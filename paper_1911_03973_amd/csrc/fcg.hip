@@ -182,7 +182,7 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
     auto true_residual = [&](double &rn) -> int {
         if (int rc = launch_apply_pk64(P, MAT_F64, w.A, x, b, w.r, -1.0, 1, w.scratch, s)) return rc;
         k_dots<1><<<gv, kBlock, 0, s>>>(n, w.ptrs + 3, w.ptrs + 3, w.part);
-        k_dots_fin<<<1, 64, 0, s>>>(w.part, gv, 1, w.sums);
+        k_dots_fin<<<1, kBlock, 0, s>>>(w.part, gv, 1, w.sums);
         FEM_HIP_CHECK(hipGetLastError());
         if (int rc = fetch(1)) return rc;
         rn = std::sqrt(h[0]);
@@ -240,7 +240,7 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
             k_jacobi<<<gv, kBlock, 0, s>>>(n, w.dinv, w.r, w.z);
         }
         k_dots<3><<<gv, kBlock, 0, s>>>(n, w.ptrs, w.ptrs + 3, w.part);
-        k_dots_fin<<<1, 64, 0, s>>>(w.part, gv, 3, w.sums);
+        k_dots_fin<<<1, kBlock, 0, s>>>(w.part, gv, 3, w.sums);
         FEM_HIP_CHECK(hipGetLastError());
         if (int rc = fetch(3)) return rc;
         double zr = h[0], zz = h[1], zq = h[2];
@@ -264,7 +264,7 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
         restart = false;
         if (int rc = launch_apply_pk64(P, MAT_F64, w.A, w.p, nullptr, w.q, 1.0, 1, w.scratch, s)) return rc;
         k_dots<2><<<gv, kBlock, 0, s>>>(n, w.ptrs + 6, w.ptrs + 8, w.part);
-        k_dots_fin<<<1, 64, 0, s>>>(w.part, gv, 2, w.sums);
+        k_dots_fin<<<1, kBlock, 0, s>>>(w.part, gv, 2, w.sums);
         FEM_HIP_CHECK(hipGetLastError());
         if (int rc = fetch(2)) return rc;
         const double pq = h[0], pr = h[1];
@@ -281,7 +281,7 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
         const double alpha = pr / pq;
         pq_prev = pq;
         k_step<<<gv, kBlock, 0, s>>>(n, alpha, w.p, w.q, x, w.r, w.part);
-        k_dots_fin<<<1, 64, 0, s>>>(w.part, gv, 1, w.sums);
+        k_dots_fin<<<1, kBlock, 0, s>>>(w.part, gv, 1, w.sums);
         FEM_HIP_CHECK(hipGetLastError());
         if (int rc = fetch(1)) return rc;
         rn = std::sqrt(h[0]);

@@ -155,7 +155,7 @@ int run_iteration(const DevPlan &P, int dtype, const void *K, const void *M, dou
     auto residual = [&]() { return launch_apply_pk64(P, MAT_F64, A, x, b, r, -1.0, 1, scratch, s); };
     auto norm = [&](double &out) -> int {
         k_dots<1><<<gv, kBlock, 0, s>>>(n, ptrs, ptrs + 1, part);
-        k_dots_fin<<<1, 64, 0, s>>>(part, gv, 1, sums);
+        k_dots_fin<<<1, kBlock, 0, s>>>(part, gv, 1, sums);
         FEM_HIP_CHECK(hipGetLastError());
         double h = 0.0;
         FEM_HIP_CHECK(hipMemcpyAsync(&h, sums, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -33,6 +33,7 @@
 #include <new>
 #include <vector>
 
+#include "chunk.h"
 #include "common.h"
 #include "fem.h"
 #include "kernels.h"
@@ -95,6 +96,32 @@ __global__ __launch_bounds__(kBlock) void k_dense_mv(int n, const double *__rest
     for (int off = kWave / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
     if (lane == 0) z[row] = s;
 }
+
+// One damped-Jacobi step fused into the element pass: zn = z + omega D^-1
+// (r - A z), 0 on Dirichlet nodes, without storing r - A z.  zn must not
+// alias z (other workgroups still gather z).
+struct OpSmooth {
+    static constexpr bool kLocal = false;
+    const double *z, *r, *dinv;
+    double *zn;
+    const uint8_t *mask;
+    double omega;
+    __device__ __forceinline__ bool begin() const { return true; }
+    __device__ __forceinline__ double gather(int g, int) const { return z[g]; }
+    struct Pre {
+        double rv, zv, dv;
+        bool zero;
+    };
+    __device__ __forceinline__ Pre fixup_load(int, int g) const { return {r[g], z[g], dinv[g], mask[g] != 0}; }
+    __device__ __forceinline__ void fixup_store(int, int g, const Pre &pr, double acc) const {
+        double t = pr.rv + (-1.0) * acc;
+        if (pr.zero) t = 0.0;
+        zn[g] = pr.zv + omega * pr.dv * t;
+    }
+    __device__ __forceinline__ void finish(int g, double acc) const { fixup_store(0, g, fixup_load(0, g), acc); }
+    template <int BS>
+    __device__ __forceinline__ void end(double *, int) const {}
+};
 
 // e = unit vector j (length n)
 __global__ void k_unit(int64_t n, int64_t j, double *__restrict__ e) {
@@ -166,6 +193,31 @@ int mg_galerkin_apply(fem_mg *mg, int l, const double *zc, double *out, hipStrea
 
 namespace {
 
+// zn = z + omega D^-1 (r - A z) on level L (element pass + fix-up)
+int smooth_step(const MgLevel &L, const double *r, const double *z, double *zn, double omega, hipStream_t s) {
+    const DevPlan &P = L.P;
+    const OpSmooth op{z, r, L.dinv, zn, P.mask, omega};
+    const size_t lds = chunk_lds_bytes<3, double>(P.E);
+    const ChunkGrid cg = chunk_grid(P.n_chunks, lds);
+    int rc = dispatch_ept(P.E, [&](auto ept) -> int {
+        constexpr int EPT = decltype(ept)::value;
+        LdPk<3, MAT_F64> ld{L.A, P.n_elems};
+        k_chunk_main<3, EPT, kBlock, double, decltype(ld), OpSmooth, false>
+            <<<cg.grid, kBlock, lds, s>>>(P, ld, op, L.scratch, cg.xcd);
+        return 0;
+    });
+    if (rc) return rc;
+    FEM_HIP_CHECK(hipGetLastError());
+    if (P.n_shared > 0) {
+        k_chunk_fixup<kFixBlock, double, OpSmooth><<<fixup_grid(P.n_shared), kFixBlock, 0, s>>>(P, op, L.scratch, 0);
+        FEM_HIP_CHECK(hipGetLastError());
+    }
+    return 0;
+}
+
+// The smoothing steps alternate between z and the level's t, starting in t
+// so that the 2 smooth - 1 fused steps end in z; the restricted residual
+// r - A z goes to whichever of the two does not hold the iterate.
 int vcycle(fem_mg *mg, size_t l, const double *r, double *z, int smooth, double omega, hipStream_t s) {
     MgLevel &L = mg->lv[l];
     const int64_t n = (int64_t)(L.n + 1) * (L.n + 1);
@@ -175,22 +227,24 @@ int vcycle(fem_mg *mg, size_t l, const double *r, double *z, int smooth, double 
         FEM_HIP_CHECK(hipGetLastError());
         return 0;
     }
-    k_smooth<<<gv, kBlock, 0, s>>>(n, omega, L.dinv, r, z, 1);
+    double *cur = L.t, *oth = z;
+    k_smooth<<<gv, kBlock, 0, s>>>(n, omega, L.dinv, r, cur, 1);
     for (int k = 1; k < smooth; ++k) {
-        if (int rc = launch_apply_pk64(L.P, MAT_F64, L.A, z, r, L.t, -1.0, 1, L.scratch, s)) return rc;
-        k_smooth<<<gv, kBlock, 0, s>>>(n, omega, L.dinv, L.t, z, 0);
+        if (int rc = smooth_step(L, r, cur, oth, omega, s)) return rc;
+        std::swap(cur, oth);
     }
-    if (int rc = launch_apply_pk64(L.P, MAT_F64, L.A, z, r, L.t, -1.0, 1, L.scratch, s)) return rc;
+    if (int rc = launch_apply_pk64(L.P, MAT_F64, L.A, cur, r, oth, -1.0, 1, L.scratch, s)) return rc;
     MgLevel &C = mg->lv[l + 1];
     const int64_t ncn = (int64_t)(C.n + 1) * (C.n + 1);
-    k_restrict<<<grid_for(ncn), kBlock, 0, s>>>(C.n, L.t, C.P.mask, C.r);
+    k_restrict<<<grid_for(ncn), kBlock, 0, s>>>(C.n, oth, C.P.mask, C.r);
     FEM_HIP_CHECK(hipGetLastError());
     if (int rc = vcycle(mg, l + 1, C.r, C.z, smooth, omega, s)) return rc;
-    k_prolong_add<<<gv, kBlock, 0, s>>>(C.n, C.z, L.P.mask, z);
+    k_prolong_add<<<gv, kBlock, 0, s>>>(C.n, C.z, L.P.mask, cur);
     for (int k = 0; k < smooth; ++k) {
-        if (int rc = launch_apply_pk64(L.P, MAT_F64, L.A, z, r, L.t, -1.0, 1, L.scratch, s)) return rc;
-        k_smooth<<<gv, kBlock, 0, s>>>(n, omega, L.dinv, L.t, z, 0);
+        if (int rc = smooth_step(L, r, cur, oth, omega, s)) return rc;
+        std::swap(cur, oth);
     }
+    if (cur != z) return set_error(FEM_EINVAL, "internal error: smoothing ended outside z");
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
@@ -412,7 +466,7 @@ int fem_mg_solve(fem_mg *mg, const fem_mg_opts *o, const double *d_b, double *d_
     auto true_residual = [&](double &rn) -> int {
         if (int rc = launch_apply_pk64(P, MAT_F64, F.A, d_x, d_b, r, -1.0, 1, F.scratch, s)) return rc;
         k_dots<1><<<gv, kBlock, 0, s>>>(n, mg->ptrs + 3, mg->ptrs + 3, mg->part);
-        k_dots_fin<<<1, 64, 0, s>>>(mg->part, gv, 1, mg->sums);
+        k_dots_fin<<<1, kBlock, 0, s>>>(mg->part, gv, 1, mg->sums);
         FEM_HIP_CHECK(hipGetLastError());
         if (int rc = fetch(1)) return rc;
         rn = std::sqrt(h[0]);
@@ -436,7 +490,7 @@ int fem_mg_solve(fem_mg *mg, const fem_mg_opts *o, const double *d_b, double *d_
         if (int rc = vcycle(mg, 0, r, z, o->smooth, o->omega, s)) return finish(rc);
         info->precond_calls += 1;
         k_dots<3><<<gv, kBlock, 0, s>>>(n, mg->ptrs, mg->ptrs + 3, mg->part);  // z.r, z.p, z.q
-        k_dots_fin<<<1, 64, 0, s>>>(mg->part, gv, 3, mg->sums);
+        k_dots_fin<<<1, kBlock, 0, s>>>(mg->part, gv, 3, mg->sums);
         FEM_HIP_CHECK(hipGetLastError());
         if (int rc = fetch(3)) return finish(rc);
         const double zr = h[0], zq = h[2];
@@ -449,7 +503,7 @@ int fem_mg_solve(fem_mg *mg, const fem_mg_opts *o, const double *d_b, double *d_
         restart = false;
         if (int rc = launch_apply_pk64(P, MAT_F64, F.A, p, nullptr, q, 1.0, 1, F.scratch, s)) return finish(rc);
         k_dots<2><<<gv, kBlock, 0, s>>>(n, mg->ptrs + 6, mg->ptrs + 8, mg->part);
-        k_dots_fin<<<1, 64, 0, s>>>(mg->part, gv, 2, mg->sums);
+        k_dots_fin<<<1, kBlock, 0, s>>>(mg->part, gv, 2, mg->sums);
         FEM_HIP_CHECK(hipGetLastError());
         if (int rc = fetch(2)) return finish(rc);
         const double pq = h[0], pr = h[1];
@@ -458,7 +512,7 @@ int fem_mg_solve(fem_mg *mg, const fem_mg_opts *o, const double *d_b, double *d_
         const double alpha = pr / pq;
         pq_prev = pq;
         k_step<<<gv, kBlock, 0, s>>>(n, alpha, p, q, d_x, r, mg->part);
-        k_dots_fin<<<1, 64, 0, s>>>(mg->part, gv, 1, mg->sums);
+        k_dots_fin<<<1, kBlock, 0, s>>>(mg->part, gv, 1, mg->sums);
         FEM_HIP_CHECK(hipGetLastError());
         if (int rc = fetch(1)) return finish(rc);
         rn = std::sqrt(h[0]);
