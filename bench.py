@@ -401,7 +401,7 @@ def run_multigrid(args):
     b = plan.empty_vector()
     fem.assemble_rhs(plan, fem.F64, mg.M[0], torch.from_numpy(f).cuda(), b)
     x = plan.empty_vector()
-    opts = fem.mg_opts(rtol=1e-8, smooth=args.mg_smooth)
+    opts = fem.mg_opts(rtol=1e-8, smooth=args.mg_smooth, cycle_dtype=fem.F32 if args.mg_cycle == "f32" else fem.F64)
 
     def mg_solve():
         x.zero_()
@@ -429,7 +429,7 @@ def run_multigrid(args):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": w["name"].replace("FP32 element matvec + FP64 refinement to 1e-8",
                                                  "FCG with a geometric multigrid V-cycle, FP64 operators, to 1e-8"),
-                   "levels": [m.n for m in meshes], "smooth": args.mg_smooth},
+                   "levels": [m.n for m in meshes], "smooth": args.mg_smooth, "cycle": args.mg_cycle},
         "roofline": None,
         "time_to_1e8_s": round(sec, 4), "iters": info["iters"], "relres": info["relres"],
         "vcycles": info["precond_calls"], "setup_s": round(t_setup, 3),
@@ -548,6 +548,8 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["unet", "cheb", "mg"], default="c2")
     ap.add_argument("--mg-coarsest", type=int, default=16, help="mg workload: squares per side of the coarsest grid")
     ap.add_argument("--mg-smooth", type=int, default=1, help="mg workload: Jacobi steps before and after")
+    ap.add_argument("--mg-cycle", choices=["f64", "f32"], default="f32",
+                    help="mg workload: precision of the V-cycle's operator products")
     ap.add_argument("--iter-n", type=int, default=2048, help="cheb workload: squares per side")
     ap.add_argument("--iter-steps", type=int, default=200, help="cheb workload: iterations of the shorter run")
     ap.add_argument("--profile", type=int, default=4, help="time every k-th matvec with HIP events")

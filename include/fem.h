@@ -463,6 +463,9 @@ typedef struct {
     int smooth;       /* Jacobi steps before and after the coarse correction (>= 1) */
     double omega;     /* Jacobi damping, in (0, 2); default 2/3 */
     int max_replace;  /* restarts from the true residual when the recursive one met rtol */
+    int cycle_dtype;  /* FEM_F64 (default): the V-cycle's operator products in FP64; FEM_F32:
+                         they read the FP32 heads of the packed operator (half the bytes;
+                         FCG's own products and the true residual stay FP64) */
 } fem_mg_opts;
 
 void fem_mg_opts_default(fem_mg_opts *o);
@@ -487,12 +490,14 @@ int fem_mg_solve(fem_mg *mg, const fem_mg_opts *opts, const double *d_b, double 
                  void *stream);
 
 /* z = B r: one V-cycle on the finest level, as the solver applies it (smooth
- * damped-Jacobi steps before and after, omega in (0, 2)).  r (n_nodes of the
+ * damped-Jacobi steps before and after, omega in (0, 2), cycle_dtype as in
+ * fem_mg_opts).  r (n_nodes of the
  * finest level, mesh order) is read on free nodes only; z is written on every
  * node, 0 on Dirichlet nodes.  r and z must not alias.  Uses the hierarchy's
  * own level vectors, so calls on one hierarchy must not overlap (launches on
  * one stream are fine).  Asynchronous on `stream`. */
-int fem_mg_vcycle(fem_mg *mg, int smooth, double omega, const double *d_r, double *d_z, void *stream);
+int fem_mg_vcycle(fem_mg *mg, int smooth, double omega, int cycle_dtype, const double *d_r, double *d_z,
+                  void *stream);
 
 /* out = P^T A_level P zc for a vector zc of level level+1 (the Galerkin
  * product; on nested meshes without jitter it equals A_{level+1} zc on free

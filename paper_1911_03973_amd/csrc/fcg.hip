@@ -166,6 +166,10 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
     const double *tab[16] = {w.z, w.z, w.z, w.r, w.z, w.q, w.p, w.p, w.q, w.r, w.nz, w.nz, w.rz, w.An};
     FEM_HIP_CHECK(hipMemcpyAsync(w.ptrs, tab, sizeof(tab), hipMemcpyHostToDevice, s));
     FEM_HIP_CHECK(hipMemsetAsync(w.bad, 0, sizeof(int), s));
+    // q and p hold the previous direction's products; the first iteration's
+    // z.q_prev must read defined values (the memory is recycled)
+    FEM_HIP_CHECK(hipMemsetAsync(w.q, 0, n * 8, s));
+    FEM_HIP_CHECK(hipMemsetAsync(w.p, 0, n * 8, s));
     if (int rc = launch_pack(P, dtype, K, M, nu, MAT_F64, w.A, s)) return rc;
     if (int rc = launch_diag_pk64(P, MAT_F64, w.A, w.d, w.scratch, s)) return rc;
     const int gv = grid_for(n);
@@ -245,7 +249,8 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
         if (int rc = fetch(3)) return rc;
         double zr = h[0], zz = h[1], zq = h[2];
         // a network output that is non-finite or zero cannot give a direction
-        if (use_net && !(std::isfinite(zz) && std::isfinite(zr) && std::isfinite(zq) && zz > 0.0)) {
+        // (z.q_prev enters only after a first step)
+        if (use_net && !(std::isfinite(zz) && std::isfinite(zr) && (restart || std::isfinite(zq)) && zz > 0.0)) {
             res.fallback_reason = 1;
             net_ok = false;
         }

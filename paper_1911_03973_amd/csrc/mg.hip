@@ -123,6 +123,28 @@ struct OpSmooth {
     __device__ __forceinline__ void end(double *, int) const {}
 };
 
+// t = r - A z, 0 on Dirichlet nodes (the residual restricted to the next level)
+struct OpResid {
+    static constexpr bool kLocal = false;
+    const double *z, *r;
+    double *t;
+    const uint8_t *mask;
+    __device__ __forceinline__ bool begin() const { return true; }
+    __device__ __forceinline__ double gather(int g, int) const { return z[g]; }
+    struct Pre {
+        double rv;
+        bool zero;
+    };
+    __device__ __forceinline__ Pre fixup_load(int, int g) const { return {r[g], mask[g] != 0}; }
+    __device__ __forceinline__ void fixup_store(int, int g, const Pre &pr, double acc) const {
+        const double v = pr.rv + (-1.0) * acc;
+        t[g] = pr.zero ? 0.0 : v;
+    }
+    __device__ __forceinline__ void finish(int g, double acc) const { fixup_store(0, g, fixup_load(0, g), acc); }
+    template <int BS>
+    __device__ __forceinline__ void end(double *, int) const {}
+};
+
 // e = unit vector j (length n)
 __global__ void k_unit(int64_t n, int64_t j, double *__restrict__ e) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
@@ -168,6 +190,7 @@ struct MgLevel {
     DevPlan P{};
     int n = 0;  // squares per side
     double *A = nullptr, *dinv = nullptr, *r = nullptr, *z = nullptr, *t = nullptr, *scratch = nullptr;
+    void *A32 = nullptr;  // the packed operator as FP32 hi/lo pair; the cycle may read its heads
 };
 
 }  // namespace fem
@@ -193,32 +216,45 @@ int mg_galerkin_apply(fem_mg *mg, int l, const double *zc, double *out, hipStrea
 
 namespace {
 
-// zn = z + omega D^-1 (r - A z) on level L (element pass + fix-up)
-int smooth_step(const MgLevel &L, const double *r, const double *z, double *zn, double omega, hipStream_t s) {
+// One element pass (+ fix-up) of op over level L's packed operator: FP64
+// values, or the FP32 heads of the hi/lo pair (f32).
+template <class Op>
+int level_pass(const MgLevel &L, const Op &op, bool f32, hipStream_t s) {
     const DevPlan &P = L.P;
-    const OpSmooth op{z, r, L.dinv, zn, P.mask, omega};
     const size_t lds = chunk_lds_bytes<3, double>(P.E);
     const ChunkGrid cg = chunk_grid(P.n_chunks, lds);
     int rc = dispatch_ept(P.E, [&](auto ept) -> int {
         constexpr int EPT = decltype(ept)::value;
-        LdPk<3, MAT_F64> ld{L.A, P.n_elems};
-        k_chunk_main<3, EPT, kBlock, double, decltype(ld), OpSmooth, false>
-            <<<cg.grid, kBlock, lds, s>>>(P, ld, op, L.scratch, cg.xcd);
+        if (f32) {
+            LdPk<3, MAT_F32> ld{L.A32, P.n_elems};
+            k_chunk_main<3, EPT, kBlock, double, decltype(ld), Op, false>
+                <<<cg.grid, kBlock, lds, s>>>(P, ld, op, L.scratch, cg.xcd);
+        } else {
+            LdPk<3, MAT_F64> ld{L.A, P.n_elems};
+            k_chunk_main<3, EPT, kBlock, double, decltype(ld), Op, false>
+                <<<cg.grid, kBlock, lds, s>>>(P, ld, op, L.scratch, cg.xcd);
+        }
         return 0;
     });
     if (rc) return rc;
     FEM_HIP_CHECK(hipGetLastError());
     if (P.n_shared > 0) {
-        k_chunk_fixup<kFixBlock, double, OpSmooth><<<fixup_grid(P.n_shared), kFixBlock, 0, s>>>(P, op, L.scratch, 0);
+        k_chunk_fixup<kFixBlock, double, Op><<<fixup_grid(P.n_shared), kFixBlock, 0, s>>>(P, op, L.scratch, 0);
         FEM_HIP_CHECK(hipGetLastError());
     }
     return 0;
 }
 
+// zn = z + omega D^-1 (r - A z) on level L
+int smooth_step(const MgLevel &L, const double *r, const double *z, double *zn, double omega, bool f32,
+                hipStream_t s) {
+    return level_pass(L, OpSmooth{z, r, L.dinv, zn, L.P.mask, omega}, f32, s);
+}
+
 // The smoothing steps alternate between z and the level's t, starting in t
 // so that the 2 smooth - 1 fused steps end in z; the restricted residual
 // r - A z goes to whichever of the two does not hold the iterate.
-int vcycle(fem_mg *mg, size_t l, const double *r, double *z, int smooth, double omega, hipStream_t s) {
+int vcycle(fem_mg *mg, size_t l, const double *r, double *z, int smooth, double omega, bool f32, hipStream_t s) {
     MgLevel &L = mg->lv[l];
     const int64_t n = (int64_t)(L.n + 1) * (L.n + 1);
     const int gv = grid_for(n);
@@ -230,18 +266,18 @@ int vcycle(fem_mg *mg, size_t l, const double *r, double *z, int smooth, double 
     double *cur = L.t, *oth = z;
     k_smooth<<<gv, kBlock, 0, s>>>(n, omega, L.dinv, r, cur, 1);
     for (int k = 1; k < smooth; ++k) {
-        if (int rc = smooth_step(L, r, cur, oth, omega, s)) return rc;
+        if (int rc = smooth_step(L, r, cur, oth, omega, f32, s)) return rc;
         std::swap(cur, oth);
     }
-    if (int rc = launch_apply_pk64(L.P, MAT_F64, L.A, cur, r, oth, -1.0, 1, L.scratch, s)) return rc;
+    if (int rc = level_pass(L, OpResid{cur, r, oth, L.P.mask}, f32, s)) return rc;
     MgLevel &C = mg->lv[l + 1];
     const int64_t ncn = (int64_t)(C.n + 1) * (C.n + 1);
     k_restrict<<<grid_for(ncn), kBlock, 0, s>>>(C.n, oth, C.P.mask, C.r);
     FEM_HIP_CHECK(hipGetLastError());
-    if (int rc = vcycle(mg, l + 1, C.r, C.z, smooth, omega, s)) return rc;
+    if (int rc = vcycle(mg, l + 1, C.r, C.z, smooth, omega, f32, s)) return rc;
     k_prolong_add<<<gv, kBlock, 0, s>>>(C.n, C.z, L.P.mask, cur);
     for (int k = 0; k < smooth; ++k) {
-        if (int rc = smooth_step(L, r, cur, oth, omega, s)) return rc;
+        if (int rc = smooth_step(L, r, cur, oth, omega, f32, s)) return rc;
         std::swap(cur, oth);
     }
     if (cur != z) return set_error(FEM_EINVAL, "internal error: smoothing ended outside z");
@@ -283,6 +319,7 @@ void fem_mg_opts_default(fem_mg_opts *o) {
     o->smooth = 2;
     o->omega = 2.0 / 3.0;
     o->max_replace = 4;
+    o->cycle_dtype = FEM_F64;
 }
 
 int fem_mg_create(int levels, const fem_plan *const *plans, const int *grid_n, int dtype, const void *const *K,
@@ -316,13 +353,15 @@ int fem_mg_create(int levels, const fem_plan *const *plans, const int *grid_n, i
         off += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
         return o;
     };
-    std::vector<size_t> oA(levels), od(levels), odi(levels), or_(levels), oz(levels), ot(levels), osc(levels);
+    std::vector<size_t> oA(levels), oA32(levels), od(levels), odi(levels), or_(levels), oz(levels), ot(levels),
+        osc(levels);
     for (int l = 0; l < levels; ++l) {
         mg->lv[l].P = fem::plan_device(plans[l]);
         mg->lv[l].n = grid_n[l];
         const fem::DevPlan &P = mg->lv[l].P;
         const int64_t n = P.n_nodes;
         oA[l] = take((size_t)fem::packed_count(P.nb) * P.n_elems * 8);
+        oA32[l] = take((size_t)fem::packed_count(P.nb) * P.n_elems * 8);  // float [2][np][ne]
         od[l] = take(n * 8);
         odi[l] = take(n * 8);
         or_[l] = take(n * 8);
@@ -343,6 +382,7 @@ int fem_mg_create(int levels, const fem_plan *const *plans, const int *grid_n, i
     for (int l = 0; l < levels; ++l) {
         fem::MgLevel &L = mg->lv[l];
         L.A = reinterpret_cast<double *>(b + oA[l]);
+        L.A32 = b + oA32[l];
         L.dinv = reinterpret_cast<double *>(b + odi[l]);
         L.r = reinterpret_cast<double *>(b + or_[l]);
         L.z = reinterpret_cast<double *>(b + oz[l]);
@@ -367,6 +407,7 @@ int fem_mg_create(int levels, const fem_plan *const *plans, const int *grid_n, i
         fem::MgLevel &L = mg->lv[l];
         const void *Ml = nu != 0.0 ? M[l] : nullptr;
         rc = fem::launch_pack(L.P, dtype, K[l], Ml, nu, fem::MAT_F64, L.A, s);
+        if (!rc) rc = fem::launch_pack(L.P, dtype, K[l], Ml, nu, fem::MAT_F32X2, L.A32, s);
         if (!rc) rc = fem::launch_diag_pk64(L.P, fem::MAT_F64, L.A, reinterpret_cast<double *>(b + od[l]), L.scratch, s);
         if (!rc) {
             fem::k_dinv_fcg<<<fem::grid_for(L.P.n_nodes), fem::kBlock, 0, s>>>(
@@ -426,14 +467,16 @@ int fem_mg_galerkin_apply(fem_mg *mg, int level, const double *d_zc, double *d_o
     return fem::mg_galerkin_apply(mg, level, d_zc, d_out, reinterpret_cast<hipStream_t>(stream));
 }
 
-int fem_mg_vcycle(fem_mg *mg, int smooth, double omega, const double *d_r, double *d_z, void *stream) {
+int fem_mg_vcycle(fem_mg *mg, int smooth, double omega, int cycle_dtype, const double *d_r, double *d_z,
+                  void *stream) {
     using fem::set_error;
     fem::last_error().clear();
     if (!mg || !d_r || !d_z) return set_error(FEM_EINVAL, "NULL argument");
     if (d_r == d_z) return set_error(FEM_EINVAL, "r and z must not alias");
     if (smooth < 1 || smooth > 64 || !(omega > 0.0 && omega < 2.0))
         return set_error(FEM_EINVAL, "bad smoothing parameters");
-    return fem::vcycle(mg, 0, d_r, d_z, smooth, omega, reinterpret_cast<hipStream_t>(stream));
+    if (cycle_dtype != FEM_F64 && cycle_dtype != FEM_F32) return set_error(FEM_EINVAL, "cycle_dtype: FEM_F64 or FEM_F32");
+    return fem::vcycle(mg, 0, d_r, d_z, smooth, omega, cycle_dtype == FEM_F32, reinterpret_cast<hipStream_t>(stream));
 }
 
 int fem_mg_solve(fem_mg *mg, const fem_mg_opts *o, const double *d_b, double *d_x, fem_fcg_info *info, void *stream) {
@@ -444,7 +487,8 @@ int fem_mg_solve(fem_mg *mg, const fem_mg_opts *o, const double *d_b, double *d_
     std::memset(info, 0, sizeof(*info));
     info->fell_back = -1;
     if (!(o->rtol > 0.0 && o->rtol < 1.0) || o->max_iter < 1 || o->smooth < 1 || o->smooth > 64 ||
-        !(o->omega > 0.0 && o->omega < 2.0) || o->max_replace < 0)
+        !(o->omega > 0.0 && o->omega < 2.0) || o->max_replace < 0 ||
+        (o->cycle_dtype != FEM_F64 && o->cycle_dtype != FEM_F32))
         return set_error(FEM_EINVAL, "bad multigrid options");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     MgLevel &F = mg->lv[0];
@@ -457,6 +501,9 @@ int fem_mg_solve(fem_mg *mg, const fem_mg_opts *o, const double *d_b, double *d_
     // Dot tables: [0..2] x [3..5] = (z.r, z.p, z.q); [6..7] x [8..9] = (p.q, p.r); [3] x [3] = r.r
     const double *tab[16] = {z, z, z, r, p, q, p, p, q, r};
     FEM_HIP_CHECK(hipMemcpyAsync(mg->ptrs, tab, sizeof(tab), hipMemcpyHostToDevice, s));
+    // the first iteration's z.p and z.q read the previous direction: defined zeros
+    FEM_HIP_CHECK(hipMemsetAsync(p, 0, n * 8, s));
+    FEM_HIP_CHECK(hipMemsetAsync(q, 0, n * 8, s));
     double h[8];
     auto fetch = [&](int cnt) -> int {
         FEM_HIP_CHECK(hipMemcpyAsync(h, mg->sums, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -487,7 +534,7 @@ int fem_mg_solve(fem_mg *mg, const fem_mg_opts *o, const double *d_b, double *d_
     bool restart = true;
     double pq_prev = 1.0;
     for (int it = 0; it < o->max_iter; ++it) {
-        if (int rc = vcycle(mg, 0, r, z, o->smooth, o->omega, s)) return finish(rc);
+        if (int rc = vcycle(mg, 0, r, z, o->smooth, o->omega, o->cycle_dtype == FEM_F32, s)) return finish(rc);
         info->precond_calls += 1;
         k_dots<3><<<gv, kBlock, 0, s>>>(n, mg->ptrs, mg->ptrs + 3, mg->part);  // z.r, z.p, z.q
         k_dots_fin<<<1, kBlock, 0, s>>>(mg->part, gv, 3, mg->sums);

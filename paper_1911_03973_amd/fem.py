@@ -125,7 +125,7 @@ RICHARDSON, CHEBYSHEV2, CHEBYSHEV3, CHEBYSHEV3_LISTING = 0, 1, 2, 3
 class MgOpts(ctypes.Structure):
     _fields_ = [
         ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int), ("smooth", ctypes.c_int), ("omega", ctypes.c_double),
-        ("max_replace", ctypes.c_int),
+        ("max_replace", ctypes.c_int), ("cycle_dtype", ctypes.c_int),
     ]
 
 
@@ -165,7 +165,7 @@ _SIGS = {
     "fem_mg_destroy": [_vp],
     "fem_mg_solve": [_vp, ctypes.POINTER(MgOpts), _vp, _vp, ctypes.POINTER(FcgInfo), _vp],
     "fem_mg_galerkin_apply": [_vp, _int, _vp, _vp, _vp],
-    "fem_mg_vcycle": [_vp, _int, _dbl, _vp, _vp, _vp],
+    "fem_mg_vcycle": [_vp, _int, _dbl, _int, _vp, _vp, _vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -691,14 +691,15 @@ class MG:
                                  _stream(stream)), allow=allow)
         return {k: getattr(info, k) for k, _ in info._fields_}
 
-    def vcycle(self, r, smooth=2, omega=2.0 / 3.0, z=None, stream=None):
+    def vcycle(self, r, smooth=2, omega=2.0 / 3.0, z=None, cycle_dtype=F64, stream=None):
         """z = B r, one V-cycle on the finest level."""
         n = self.plans[0].n_nodes
         _need(r, torch.float64, n, "r")
         if z is None:
             z = torch.empty(n, dtype=torch.float64, device="cuda")
         _need(z, torch.float64, n, "z")
-        _check(_lib.fem_mg_vcycle(self.handle, int(smooth), float(omega), _ptr(r), _ptr(z), _stream(stream)))
+        _check(_lib.fem_mg_vcycle(self.handle, int(smooth), float(omega), int(cycle_dtype), _ptr(r), _ptr(z),
+                                  _stream(stream)))
         return z
 
     def galerkin_apply(self, level, zc, stream=None):

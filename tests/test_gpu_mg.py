@@ -117,3 +117,37 @@ def test_vcycle_rejects_bad_arguments():
             mg.vcycle(r, smooth, omega)
     with pytest.raises(fem.FemError):
         mg.vcycle(r, 2, 0.5, z=r)
+
+
+@pytest.mark.parametrize("n,coarsest,smooth", [(64, 16, 1), (128, 16, 2)])
+def test_vcycle_with_fp32_heads_stays_close_to_oracle(n, coarsest, smooth):
+    """The cycle reading the FP32 heads of the packed operator: every product
+    carries entrywise relative errors of at most 2^-24 (one rounding of each
+    packed value), and the cycle is a contraction-like linear map, so over its
+    2 smooth + 2 products per level the result stays within about
+    (levels * (2 smooth + 2)) * 2^-24 of the FP64 cycle; asserted with a 10x
+    margin as 1e-5 of max|z|."""
+    meshes, nds, mg = _hierarchy(n, 0.2, "x2=0", 1.0, coarsest=coarsest, seed=n)
+    levels, Ps = omg.hierarchy(meshes, nds, 1.0)
+    r = np.random.default_rng(n).standard_normal(meshes[0].n_nodes)
+    want = omg.vcycle(levels, Ps, r, smooth, 2.0 / 3.0)
+    got = mg.vcycle(cuda(r), smooth, 2.0 / 3.0, cycle_dtype=fem.F32).cpu().numpy()
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print("fp32-head cycle rel err", err, flush=True)
+    assert err <= 1e-5
+    assert err > 0.0  # it really read the FP32 heads
+
+
+def test_mg_fcg_with_fp32_cycle_meets_target():
+    meshes, nds, mg = _hierarchy(256, 0.2, "x2=0", 1.0, seed=7)
+    prob = Problem(meshes[0], nu=1.0, dirichlet="x2=0", f="sine", seed=8)
+    its = {}
+    for cd in (fem.F64, fem.F32):
+        x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+        info = mg.solve(fem.mg_opts(rtol=1e-8, cycle_dtype=cd), cuda(prob.b), x)
+        assert info["status"] == fem.FEM_OK
+        r = oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, x.cpu().numpy(), prob.mask)
+        r0 = oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, np.zeros(prob.n), prob.mask)
+        assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8
+        its[cd] = info["iters"]
+    assert its[fem.F32] <= its[fem.F64] + 2, its
