@@ -165,3 +165,28 @@ def test_mfree_rejects_fp32_vectors_and_unsupported_entry_points():
         fem.pcg_solve(plan, fem.solve_opts(dtype=fem.MFREE, vectors=1), None, None, b, x)
     with pytest.raises(fem.FemError):  # nothing to build: matrix-free has no stored arrays
         fem.build_local_matrices(plan, fem.MFREE, plan.empty_matrix(fem.F64), None, None)
+
+
+def test_mfree_isolated_node_and_empty_mesh():
+    m = inputs.square_mesh(6, jitter=0.1, seed=2)
+    coords = np.vstack([m.coords, [[3.0, 3.0]]])
+    mesh = inputs.Mesh(coords, m.elems, m.n)
+    prob = Problem(mesh, nu=1.0, dirichlet=None)
+    plan = fem.Plan.from_mesh(mesh, None, chunk_elems=64)
+    x = np.random.default_rng(0).standard_normal(mesh.n_nodes)
+    b = np.random.default_rng(1).standard_normal(mesh.n_nodes)
+    r = plan.empty_vector()
+    fem.element_residual(plan, fem.MFREE, None, None, 1.0, cuda(b), cuda(x), r, mask=False)
+    torch.cuda.synchronize()
+    ro = oracle.residual(mesh.n_nodes, mesh.elems, prob.K, prob.M, 1.0, b, x)
+    assert max_rel(r.cpu().numpy(), ro) <= 1e-12
+    assert r[-1].item() == b[-1]
+    empty = fem.Plan(2, cuda(m.coords.T), torch.zeros((3, 0), dtype=torch.int32, device="cuda"))
+    r = empty.empty_vector()
+    fem.element_residual(empty, fem.MFREE, None, None, 0.5, cuda(b[: m.n_nodes]), cuda(x[: m.n_nodes]), r,
+                         mask=False)
+    d = empty.empty_vector()
+    fem.jacobi_diag(empty, fem.MFREE, None, None, 0.5, d)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(r.cpu().numpy(), b[: m.n_nodes])
+    np.testing.assert_array_equal(d.cpu().numpy(), np.zeros(m.n_nodes))

@@ -187,3 +187,23 @@ def test_p2_rejects_unsupported_paths():
         fem.element_residual(plan, fem.MFREE, None, None, 1.0, None, b, x)
     with pytest.raises(fem.FemError):
         fem.Plan.from_mesh(mesh, nd, chunk_elems=1536)
+
+
+def test_p2_isolated_node_and_empty_mesh():
+    m = inputs.square_mesh_p2(4, jitter=0.1, seed=2)
+    mesh = inputs.Mesh(np.vstack([m.coords, [[3.0, 3.0]]]), m.elems, m.n)
+    K, M, _ = op2.local_matrices_p2(mesh.coords, mesh.elems)
+    plan = fem.Plan.from_mesh(mesh, None, chunk_elems=64)
+    x = np.random.default_rng(0).standard_normal(mesh.n_nodes)
+    b = np.random.default_rng(1).standard_normal(mesh.n_nodes)
+    r = plan.empty_vector()
+    fem.element_residual(plan, fem.F64, cuda(to_soa(K)), cuda(to_soa(M)), 1.0, cuda(b), cuda(x), r, mask=False)
+    torch.cuda.synchronize()
+    ro = oracle.residual(mesh.n_nodes, mesh.elems, K, M, 1.0, b, x)
+    assert max_rel(r.cpu().numpy(), ro) <= 1e-12
+    assert r[-1].item() == b[-1]
+    empty = fem.Plan(2, cuda(m.coords.T), torch.zeros((6, 0), dtype=torch.int32, device="cuda"))
+    r = empty.empty_vector()
+    fem.element_residual(empty, fem.F64, None, None, 0.0, cuda(b[: m.n_nodes]), cuda(x[: m.n_nodes]), r, mask=False)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(r.cpu().numpy(), b[: m.n_nodes])
