@@ -176,17 +176,19 @@ def test_full_size_multigrid_vcycle_and_solve():
     plan = mg.plans[0]
     b = plan.empty_vector()
     fem.assemble_rhs(plan, fem.F64, mg.M[0], cuda(f), b)
-    x = plan.empty_vector()
-    x.zero_()
-    info = mg.solve(fem.mg_opts(rtol=1e-8), b, x)
-    print("mg c2", info, flush=True)
-    assert info["status"] == fem.FEM_OK and info["iters"] <= 30
     K, M, _ = oracle.local_matrices(mesh.coords, mesh.elems)
     mask = oracle.mask_from_nodes(mesh.n_nodes, nd)
     bo = oracle.rhs(mesh.n_nodes, mesh.elems, M, f)
-    r = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, bo, x.cpu().numpy(), mask)
     r0 = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, bo, np.zeros(mesh.n_nodes), mask)
-    assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8
+    # the library default (FP64 cycle, 2 + 2 steps) and the benchmark's (FP32 heads, 1 + 1)
+    for opts in (fem.mg_opts(rtol=1e-8), fem.mg_opts(rtol=1e-8, smooth=1, cycle_dtype=fem.F32)):
+        x = plan.empty_vector()
+        x.zero_()
+        info = mg.solve(opts, b, x)
+        print("mg c2", opts.smooth, opts.cycle_dtype, info, flush=True)
+        assert info["status"] == fem.FEM_OK and info["iters"] <= 30
+        r = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, bo, x.cpu().numpy(), mask)
+        assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8
 
 
 @pytest.mark.parametrize("name,E,block", [("c2", 0, 512), ("c3", 512, 0)])
