@@ -184,8 +184,8 @@ __host__ __device__ constexpr size_t chunk_lds_bytes(int E) {
 // 0, M_e has vol / ((d+1)(d+2)) off the diagonal and row sums vol / (d+1).
 // Vertex coordinates reach the pass through LDS: phase A stores each local
 // node's coordinates once (a per-chunk table of max_local entries) and the
-// node's index into each of its slots; phase B reads an element's vertices
-// there through its slots.  Measured alternatives, all slower or no faster:
+// node's index into a 4-entry record per element; phase B reads the record
+// with one 8-byte load and the vertices through it.  Measured alternatives, all slower or no faster:
 // the coordinates written into every slot beside x (1.2x slower in 2D, 2x in
 // 3D: phase A's scattered LDS writes tripled), and a precomputed slot -> node
 // index read from HBM into registers or staged into LDS.
@@ -274,7 +274,7 @@ template <int NB, class T, class Ld>
 size_t chunk_lds_for(const DevPlan &P) {
     size_t b = chunk_lds_bytes<NB, T>(P.E);
     if constexpr (HasCoords<Ld>::value)
-        b += (size_t)NB * P.E * sizeof(uint16_t) + (size_t)(NB - 1) * sizeof(double) * (size_t)P.max_local;
+        b += (size_t)4 * P.E * sizeof(uint16_t) + (size_t)(NB - 1) * sizeof(double) * (size_t)P.max_local;
     return b;
 }
 
@@ -397,10 +397,12 @@ __global__ __launch_bounds__(BS) void k_chunk_main(const DevPlan P, const Ld ld,
     T *buf = reinterpret_cast<T *>(smem);
     uint16_t *sl = reinterpret_cast<uint16_t *>(smem + (size_t)NB * P.E * sizeof(T));
     constexpr bool kMf = HasCoords<Ld>::value;
-    // matrix-free only: the local node of every slot, then the coordinates
-    // of the chunk's local nodes, [local node][dim]
+    // matrix-free only: element le's local nodes at lnode[4 le + j] (one 8-byte
+    // LDS read per element), then the coordinates of the chunk's local nodes,
+    // [local node][dim]
+    static_assert(!kMf || NB <= 4, "the matrix-free record holds four vertices");
     uint16_t *lnode = sl + (size_t)NB * P.E;
-    double *crd = reinterpret_cast<double *>(lnode + (size_t)NB * P.E);
+    double *crd = reinterpret_cast<double *>(lnode + (size_t)4 * P.E);
     __shared__ RedBuf<BS> red;
     if (!op.begin()) return;
     for (int64_t it = 0;; ++it) {
@@ -443,7 +445,10 @@ __global__ __launch_bounds__(BS) void k_chunk_main(const DevPlan P, const Ld ld,
                 const int64_t ci = (Op::kLocal && own >= 0) ? (P.n_nodes - P.n_shared) + own : (int64_t)g;
 #pragma unroll
                 for (int d = 0; d < NB - 1; ++d) crd[k * (NB - 1) + d] = ld.coord(ci, d);
-                for (int s = s0; s < s1; ++s) lnode[sl[s]] = (uint16_t)k;
+                for (int s = s0; s < s1; ++s) {
+                    const int q = sl[s];  // slot = le * NB + j
+                    lnode[(q / NB) * 4 + q % NB] = (uint16_t)k;
+                }
             }
             __syncthreads();
         } else if constexpr (!DIAG) {
@@ -464,11 +469,14 @@ __global__ __launch_bounds__(BS) void k_chunk_main(const DevPlan P, const Ld ld,
             for (int t = 0; t < EPT; ++t) {
                 const int le = t * BS + threadIdx.x;
                 if (le < ne) {
+                    const uint2 ln4 = *reinterpret_cast<const uint2 *>(lnode + 4 * le);
+                    const int kn[4] = {(int)(ln4.x & 0xFFFFu), (int)(ln4.x >> 16), (int)(ln4.y & 0xFFFFu),
+                                       (int)(ln4.y >> 16)};
                     double pv[NB][NB - 1];
 #pragma unroll
                     for (int j = 0; j < NB; ++j)
 #pragma unroll
-                        for (int d = 0; d < NB - 1; ++d) pv[j][d] = crd[(int)lnode[le * NB + j] * (NB - 1) + d];
+                        for (int d = 0; d < NB - 1; ++d) pv[j][d] = crd[kn[j] * (NB - 1) + d];
                     ld.build(pv, R[t]);
                 }
             }
