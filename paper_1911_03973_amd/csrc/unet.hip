@@ -199,22 +199,25 @@ __global__ __launch_bounds__(256) void k_gemm_rows(Src src, Epi epi, const bf16 
 // 4 waves.  Wave w computes tile pixels [64 MT/4 * w ...) as MT row tiles of
 // 16 pixels against all NT column tiles.  Pixels outside the image are
 // computed on zero input and not stored.
+// Cin = C1 + C2 is a power of two (2^lcin): the (tap, channel) split of a
+// reduction index and the staging loop's (pixel, channel group) split are
+// shifts and masks (runtime divisions made this kernel VALU-bound).
 template <int TY, int TX, int NT>
 __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ src1, const bf16 *__restrict__ src2,
-                                                    int C1, int C2, int H, int W, int tiles_x, int tiles_y,
+                                                    int C1, int C2, int lcin, int H, int W, int tiles_x, int tiles_y,
                                                     const bf16 *__restrict__ Bp, int KB, int kbc,
                                                     const float *__restrict__ bias, bf16 *__restrict__ out) {
     constexpr int MT = TY * TX / 64;
     constexpr int HX = TX + 2, HY = TY + 2;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int Cin = C1 + C2, cu8 = Cin / 8;
+    const int Cin = C1 + C2, cu8 = Cin / 8, lcu = lcin - 3;
     bf16 *tin = reinterpret_cast<bf16 *>(smem);  // [HY][HX][Cin]
     bf16 *tb = reinterpret_cast<bf16 *>(smem + (((size_t)HY * HX * Cin * 2 + 15) & ~(size_t)15));
     const int tile = blockIdx.x;
     const int tx = tile % tiles_x, t2 = tile / tiles_x, ty = t2 % tiles_y, b = t2 / tiles_y;
     const int y0 = ty * TY, x0 = tx * TX;
     for (int u = threadIdx.x; u < HY * HX * cu8; u += 256) {
-        const int cu = u % cu8, pp = u / cu8;
+        const int cu = u & (cu8 - 1), pp = u >> lcu;
         const int yy = y0 + pp / HX - 1, xx = x0 + pp % HX - 1;
         bf8 v = zero8();
         if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
@@ -242,7 +245,7 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ src
         __syncthreads();
         for (int kl = 0; kl < nkb; ++kl) {
             const int k0 = (kc + kl) * 32 + 8 * (lane >> 4);
-            const int tap = k0 / Cin, ci = k0 - tap * Cin;
+            const int tap = k0 >> lcin, ci = k0 & (Cin - 1);
             const int toff = (tap / 3) * HX + tap % 3;
             bf8 a[MT];
 #pragma unroll
@@ -257,19 +260,23 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ src
         }
     }
     constexpr int N = NT * 16;
+    float bv[NT];  // this lane's output channels' biases, loaded once
+#pragma unroll
+    for (int t = 0; t < NT; ++t) bv[t] = bias[t * 16 + (lane & 15)];
+    const bool full = y0 + TY <= H && x0 + TX <= W;  // no pixel of the tile outside the image
+    bf16 *ob = out + (((int64_t)b * H + y0) * W + x0) * N + (lane & 15);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int p = (wave * MT + mt) * 16 + 4 * (lane >> 4) + i;
-            const int y = y0 + p / TX, x = x0 + p % TX;
-            if (y < H && x < W) {
-                const int64_t m = ((int64_t)b * H + y) * W + x;
+            const int py = p / TX, px = p % TX;
+            if (full || (y0 + py < H && x0 + px < W)) {
+                bf16 *o = ob + ((int64_t)py * W + px) * N;
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
-                    const int n = t * 16 + (lane & 15);
-                    const float v = acc[mt][t][i] + bias[n];
-                    out[m * N + n] = (bf16)(v > 0.0f ? v : 0.0f);
+                    const float v = acc[mt][t][i] + bv[t];
+                    o[t * 16] = (bf16)(v > 0.0f ? v : 0.0f);
                 }
             }
         }
@@ -863,7 +870,12 @@ int repack(UNet &N, hipStream_t st) {
 size_t conv_tile_lds(int TY, int TX, int Cin) { return ((size_t)(TY + 2) * (TX + 2) * Cin * 2 + 15) & ~(size_t)15; }
 
 // tile fits next to at least one 1 KiB weight block per column tile in 64 KiB of LDS
-bool conv_tile_fits(int TY, int TX, const Layer &l) { return conv_tile_lds(TY, TX, l.Cin()) + (size_t)l.NTf * 1024 <= 65536; }
+// (and its channel count is a power of two, which the tiled kernel's index
+// arithmetic needs)
+bool conv_tile_fits(int TY, int TX, const Layer &l) {
+    const int c = l.Cin();
+    return c >= 8 && (c & (c - 1)) == 0 && conv_tile_lds(TY, TX, c) + (size_t)l.NTf * 1024 <= 65536;
+}
 
 template <int TY, int TX, int NT>
 int launch_conv_tiled_nt(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B,
@@ -873,7 +885,8 @@ int launch_conv_tiled_nt(UNet &N, const Layer &l, const Tensor &s1, const Tensor
     const size_t tin = conv_tile_lds(TY, TX, l.Cin());
     const int kbc = (int)std::max<int64_t>(1, std::min<int64_t>(l.KBf, (65536 - (int64_t)tin) / (NT * 1024)));
     const size_t lds = tin + (size_t)kbc * NT * 1024;
-    k_conv_tiled<TY, TX, NT><<<B * tiles_x * tiles_y, 256, lds, st>>>(s1.a, s2 ? s2->a : nullptr, l.C1, l.C2, H, W,
+    const int lcin = __builtin_ctz((unsigned)l.Cin());
+    k_conv_tiled<TY, TX, NT><<<B * tiles_x * tiles_y, 256, lds, st>>>(s1.a, s2 ? s2->a : nullptr, l.C1, l.C2, lcin, H, W,
                                                                         tiles_x, tiles_y, l.Bf, l.KBf, kbc,
                                                                         N.w + l.boff, y.a);
     FEM_HIP_CHECK(hipGetLastError());
