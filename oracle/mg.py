@@ -8,7 +8,8 @@ the growth of the iteration count with the mesh size in its experiment
 (Section 3) come from the h^-2 conditioning of the P1 operator; the paper
 names better preconditioning as the remedy for fine meshes.  This module holds
 the textbook two-grid / V-cycle construction on the nested diagonal-cut
-square meshes of the workloads, written from its definitions:
+square meshes and Kuhn cube meshes of the workloads, written from its
+definitions:
 
   prolongation   P maps a coarse P1 function to the same function on the fine
                  mesh: each fine node's row holds the coarse hat functions
@@ -16,7 +17,8 @@ square meshes of the workloads, written from its definitions:
                  lattice coordinates of the coarse mesh (node (I, J) at the
                  point (I, J); square [I, I+1] x [J, J+1] cut along its
                  (0,0)-(1,1) diagonal), by barycentric coordinates of the
-                 coarse triangle that holds the fine point;
+                 coarse triangle that holds the fine point (in 3D: of the
+                 coarse Kuhn tetrahedron, `prolongation3`);
   restriction    P^T;
   smoother       damped Jacobi z <- z + omega D^-1 (r - A z), starting from
                  z = 0, `smooth` steps before and after the coarse correction;
@@ -39,6 +41,39 @@ import numpy as np
 import scipy.sparse
 
 from . import jacobi_diag, local_matrices, mask_from_nodes, residual
+
+
+def prolongation3(n_coarse: int):
+    """P ((2n+1)^3 x (n+1)^3, scipy CSR) for a Kuhn cube mesh of n^3 cubes,
+    node (i, j, k) of a mesh with m nodes per side numbered (k m + j) m + i.
+    In lattice units a point with local cube coordinates sorted as
+    x_(1) >= x_(2) >= x_(3) lies in the Kuhn tetrahedron that walks from the
+    cube's corner along the axes in that order; its barycentric coordinates
+    are 1 - x_(1), x_(1) - x_(2), x_(2) - x_(3) and x_(3)."""
+    nc = n_coarse
+    mc, mf = nc + 1, 2 * nc + 1
+    rows, cols, vals = [], [], []
+    step = (1, mc, mc * mc)
+    for k in range(mf):
+        for j in range(mf):
+            for i in range(mf):
+                x = (i / 2.0, j / 2.0, k / 2.0)
+                c0 = [min(int(np.floor(v)), nc - 1) for v in x]
+                loc = [x[a] - c0[a] for a in range(3)]
+                order = sorted(range(3), key=lambda a: -loc[a])
+                srt = [loc[a] for a in order]
+                node = (c0[2] * mc + c0[1]) * mc + c0[0]
+                lam = [(node, 1.0 - srt[0])]
+                for q in range(3):
+                    node += step[order[q]]
+                    lam.append((node, srt[q] - (srt[q + 1] if q < 2 else 0.0)))
+                row = (k * mf + j) * mf + i
+                for nd, w in lam:
+                    if w != 0.0:
+                        rows.append(row)
+                        cols.append(nd)
+                        vals.append(w)
+    return scipy.sparse.coo_matrix((vals, (rows, cols)), shape=(mf ** 3, mc ** 3)).tocsr()
 
 
 def prolongation(n_coarse: int):
@@ -87,6 +122,7 @@ class Level:
 
     def __init__(self, mesh, dirichlet, nu):
         self.n = int(mesh.n)
+        self.dim = int(mesh.dim)
         self.n_nodes = int(mesh.n_nodes)
         self.elems = np.ascontiguousarray(mesh.elems, dtype=np.int32)
         self.K, self.M, _ = local_matrices(mesh.coords, mesh.elems)
@@ -112,7 +148,7 @@ def hierarchy(meshes, dirichlets, nu):
     for a, b in zip(levels[:-1], levels[1:]):
         if a.n != 2 * b.n:
             raise ValueError("each level must halve the squares per side")
-    Ps = [prolongation(lv.n) for lv in levels[1:]]
+    Ps = [(prolongation3(lv.n) if lv.dim == 3 else prolongation(lv.n)) for lv in levels[1:]]
     return levels, Ps
 
 

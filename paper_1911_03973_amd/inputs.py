@@ -37,6 +37,7 @@ __all__ = [
     "square_mesh",
     "square_mesh_p2",
     "cube_mesh",
+    "cube_hierarchy",
     "boundary_nodes",
     "dirichlet_nodes",
     "random_sine",
@@ -193,6 +194,29 @@ def square_hierarchy(mesh: Mesh, coarsest: int = 16, order: str = "morton") -> l
         ml = nl + 1
         jj, ii = np.meshgrid(np.arange(ml), np.arange(ml), indexing="ij")
         fine = (jj.ravel() << level) * m + (ii.ravel() << level)
+        out.append(Mesh(coords=np.ascontiguousarray(mesh.coords[fine]), elems=c.elems, n=nl))
+        level += 1
+    return out
+
+
+def cube_hierarchy(mesh: Mesh, coarsest: int = 5, order: str = "morton") -> list:
+    """The meshes of n, n/2, ..., coarsest cubes per side nested in `mesh` (a
+    cube_mesh of n cubes, n / coarsest a power of two): coarse node (I, J, K)
+    of level l takes the coordinates of fine node (2^l I, 2^l J, 2^l K).  The
+    Kuhn split of every level uses the same (0,0,0)-(1,1,1) diagonal, so each
+    coarse tetrahedron is a union of fine ones.  Finest first."""
+    n = mesh.n
+    if n <= 0 or coarsest < 1 or n % coarsest or (n // coarsest) & (n // coarsest - 1):
+        raise ValueError("n / coarsest must be a power of two")
+    out = [mesh]
+    m = n + 1
+    level = 1
+    while n >> level >= coarsest:
+        nl = n >> level
+        c = cube_mesh(nl, order=order)
+        ml = nl + 1
+        kk, jj, ii = np.meshgrid(np.arange(ml), np.arange(ml), np.arange(ml), indexing="ij")
+        fine = ((kk.ravel() << level) * m + (jj.ravel() << level)) * m + (ii.ravel() << level)
         out.append(Mesh(coords=np.ascontiguousarray(mesh.coords[fine]), elems=c.elems, n=nl))
         level += 1
     return out

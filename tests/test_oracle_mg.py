@@ -135,3 +135,70 @@ def test_vcycle_contraction_is_mesh_independent(smooth, bound):
         rates.append(rate)
     assert max(rates) < bound, rates
     assert rates[-1] - rates[-2] < 0.03, rates
+
+
+# ---- Kuhn cube meshes (3D) ----
+
+def test_prolongation3_reproduces_linear_functions_and_partitions_unity():
+    for nc in (1, 2, 3):
+        P = omg.prolongation3(nc)
+        mc, mf = nc + 1, 2 * nc + 1
+        K, rem = np.divmod(np.arange(mc ** 3), mc * mc)
+        J, I = np.divmod(rem, mc)
+        k, rem = np.divmod(np.arange(mf ** 3), mf * mf)
+        j, i = np.divmod(rem, mf)
+        for a, b, c, d in [(1.0, 0.0, 0.0, 0.0), (0.3, -1.25, 2.5, 0.75)]:
+            got = P @ (a + b * I + c * J + d * K)
+            want = a + b * i / 2.0 + c * j / 2.0 + d * k / 2.0
+            assert np.abs(got - want).max() <= 1e-14
+        assert np.allclose(P.sum(axis=1), 1.0, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("n,nu", [(2, 0.0), (4, 0.0), (4, 1.3)])
+def test_galerkin_identity_of_nested_kuhn_meshes(n, nu):
+    """Uniform refinement of the Kuhn split of the cube lattice is again a
+    Kuhn split with the same diagonal, so the coarse P1 space is a subspace of
+    the fine one and P^T A_h P = A_2h."""
+    fine = inputs.cube_mesh(n)
+    coarse = inputs.cube_hierarchy(fine, coarsest=n // 2)[1]
+    assert _galerkin_gap(omg.prolongation3(n // 2), fine, coarse, nu) <= 1e-13
+
+
+def test_galerkin_identity_3d_detects_the_wrong_cube_diagonal():
+    """Planted mistake: cube centres averaged over the (1,0,0)-(0,1,1)
+    diagonal, which is not an edge of the Kuhn split."""
+    n = 4
+    fine = inputs.cube_mesh(n)
+    coarse = inputs.cube_hierarchy(fine, coarsest=n // 2)[1]
+    nc = n // 2
+    mc, mf = nc + 1, 2 * nc + 1
+    P = omg.prolongation3(nc).toarray()
+    for K in range(nc):
+        for J in range(nc):
+            for I in range(nc):
+                row = ((2 * K + 1) * mf + 2 * J + 1) * mf + 2 * I + 1
+                P[row] = 0.0
+                P[row, (K * mc + J) * mc + I + 1] = 0.5
+                P[row, ((K + 1) * mc + J + 1) * mc + I] = 0.5
+    assert _galerkin_gap(P, fine, coarse, 0.0) > 1e-4
+
+
+def test_vcycle_3d_is_symmetric_and_contracts():
+    fine = inputs.cube_mesh(8, jitter=0.1, seed=2)
+    meshes = inputs.cube_hierarchy(fine, coarsest=2)
+    nds = [inputs.boundary_nodes(m, "all") for m in meshes]
+    levels, Ps = omg.hierarchy(meshes, nds, 0.5)
+    L = levels[0]
+    rng = np.random.default_rng(3)
+    r1, r2 = rng.standard_normal(L.n_nodes) * L.free, rng.standard_normal(L.n_nodes) * L.free
+    z1 = omg.vcycle(levels, Ps, r1, 2, 2.0 / 3.0)
+    z2 = omg.vcycle(levels, Ps, r2, 2, 2.0 / 3.0)
+    assert abs(r1 @ z2 - r2 @ z1) <= 1e-13 * np.linalg.norm(r1) * np.linalg.norm(z2)
+    zero = np.zeros(L.n_nodes)
+    e = rng.standard_normal(L.n_nodes) * L.free
+    for _ in range(15):
+        ae = -L.residual(zero, e)
+        e_new = e - omg.vcycle(levels, Ps, ae, 2, 2.0 / 3.0)
+        rate = np.sqrt(e_new @ -L.residual(zero, e_new)) / np.sqrt(e @ ae)
+        e = e_new
+    assert rate < 0.5, rate
