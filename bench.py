@@ -382,18 +382,22 @@ def run_iterations(args):
 
 
 def run_multigrid(args):
-    """The C2 problem solved by FCG with the geometric multigrid V-cycle (the
-    hierarchy 2048^2 -> 16^2 of nested meshes that keep the jitter), against
-    the single-level Jacobi-PCG solve of the same problem on the same GPU."""
+    """The C2 (or C3) problem solved by FCG with the geometric multigrid
+    V-cycle (the hierarchy 2048^2 -> 16^2 of nested square meshes that keep the
+    jitter, or 160^3 -> 5^3 of Kuhn cube meshes), against the single-level
+    Jacobi-PCG solve of the same problem on the same GPU."""
     import numpy as np
     import torch
 
     from paper_1911_03973_amd import fem, inputs
 
-    w = WORKLOADS["c2"]
+    w = WORKLOADS[args.mg_base]
     mesh, nd, f = make_problem(w)
     t = time.perf_counter()
-    meshes = inputs.square_hierarchy(mesh, coarsest=args.mg_coarsest)
+    if w["dim"] == 3:
+        meshes = inputs.cube_hierarchy(mesh, coarsest=args.mg_coarsest or 5)
+    else:
+        meshes = inputs.square_hierarchy(mesh, coarsest=args.mg_coarsest or 16)
     nds = [inputs.boundary_nodes(m, w["dirichlet"]) for m in meshes]
     mg = fem.MG.from_meshes(meshes, nds, w["nu"])
     t_setup = time.perf_counter() - t
@@ -546,7 +550,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["unet", "cheb", "mg"], default="c2")
-    ap.add_argument("--mg-coarsest", type=int, default=16, help="mg workload: squares per side of the coarsest grid")
+    ap.add_argument("--mg-base", choices=["c2", "c3"], default="c2", help="mg workload: the problem (2D or 3D)")
+    ap.add_argument("--mg-coarsest", type=int, default=0,
+                    help="mg workload: cells per side of the coarsest grid (0: 16 in 2D, 5 in 3D)")
     ap.add_argument("--mg-smooth", type=int, default=1, help="mg workload: Jacobi steps before and after")
     ap.add_argument("--mg-cycle", choices=["f64", "f32"], default="f32",
                     help="mg workload: precision of the V-cycle's operator products")

@@ -440,13 +440,16 @@ void fem_fcg_opts_default(fem_fcg_opts *o);
 int fem_fcg_solve(const fem_plan *plan, const fem_fcg_opts *opts, fem_unet *net, const void *d_K_e,
                   const void *d_M_e, const double *d_b, double *d_x, fem_fcg_info *info, void *stream);
 
-/* ---- Geometric multigrid on nested square meshes --------------------------
+/* ---- Geometric multigrid on nested square and cube meshes -----------------
  * The P1 operator's condition number grows like h^-2 (the reason the Section 3
  * iterations need spectral bounds, and the preconditioning the paper calls for
  * on fine meshes).  For the structured 2D meshes -- n x n squares cut along the
  * (0,0)-(1,1) diagonal, node (i, j) numbered j (n + 1) + i -- the mesh of n/2
- * squares is nested in that of n squares (red refinement), and a V-cycle over
- * the hierarchy preconditions flexible CG:
+ * squares is nested in that of n squares (red refinement); so is the 3D Kuhn
+ * mesh of (n/2)^3 cubes in that of n^3 cubes (6 tetrahedra per cube around its
+ * (0,0,0)-(1,1,1) diagonal, node (i, j, k) numbered (k (n+1) + j)(n+1) + i,
+ * every vertex joined to its 14 neighbours +-e, e in {0,1}^3 \ {0}).  A V-cycle
+ * over the hierarchy preconditions flexible CG:
  *   prolongation  exact P1 interpolation (fine (2I,2J) <- coarse (I,J); an odd
  *                 fine node <- the average of the two coarse ends of its edge,
  *                 the diagonal edge included);
@@ -471,9 +474,10 @@ typedef struct {
 void fem_mg_opts_default(fem_mg_opts *o);
 
 /* levels >= 2 plans, finest first: plans[l] a plan of the grid_n[l] x grid_n[l]
- * square mesh with grid_n[l] = 2 grid_n[l+1], its own Dirichlet set; d_K_e[l],
- * d_M_e[l] its local matrices in `dtype` layout (d_M_e may be NULL when
- * nu == 0).  The coarsest mesh may have at most 33 x 33 nodes.  The plans must
+ * square mesh (or of the grid_n[l]^3 cube mesh; all levels of one dimension)
+ * with grid_n[l] = 2 grid_n[l+1], its own Dirichlet set; d_K_e[l], d_M_e[l]
+ * its local matrices in `dtype` layout (d_M_e may be NULL when nu == 0).  The
+ * coarsest mesh may have at most 1089 nodes (33 x 33, 10^3).  The plans must
  * outlive the hierarchy; the matrices are read during the call only (packed
  * copies are kept).  FEM_EINVAL for a hierarchy that is not nested as
  * described, FEM_ESINGULAR for a non-positive diagonal or a singular coarsest

@@ -1,4 +1,5 @@
-// mg.hip -- geometric multigrid preconditioner on nested diagonal-cut grids.
+// mg.hip -- geometric multigrid preconditioner on nested diagonal-cut square
+// grids and Kuhn cube grids.
 //
 // The condition number of the P1 operator grows like h^-2, which is why the
 // experiment of Section 3 needs its spectral bounds and why the paper points
@@ -12,6 +13,10 @@
 //   fine (2I+1, 2J)       <- average of coarse (I, J), (I+1, J)
 //   fine (2I, 2J+1)       <- average of coarse (I, J), (I, J+1)
 //   fine (2I+1, 2J+1)     <- average of coarse (I, J), (I+1, J+1)  (diagonal edge)
+// The Kuhn split of the cube lattice (6 tetrahedra around each cube's
+// (0,0,0)-(1,1,1) diagonal) refines the same way: a fine node with parity
+// pattern e != 0 is the midpoint of the coarse edge from (i, j, k) >> 1 along
+// e, and the restriction gathers the 14 lattice neighbours +-e.
 // The restriction is its transpose: a coarse node collects its fine node with
 // weight 1 and the six fine edge neighbours of that node, (+-1, 0), (0, +-1),
 // (1, 1) and (-1, -1), with weight 1/2.  With these, P^T A_h P equals the
@@ -79,6 +84,53 @@ __global__ void k_prolong_add(int nc, const double *__restrict__ zc, const uint8
         else if ((i & 1) && !(j & 1)) v = 0.5 * (c00 + zc[(int64_t)J * mc + I + 1]);
         else if (!(i & 1)) v = 0.5 * (c00 + zc[(int64_t)(J + 1) * mc + I]);
         else v = 0.5 * (c00 + zc[(int64_t)(J + 1) * mc + I + 1]);
+        zf[id] += v;
+    }
+}
+
+// Kuhn cube meshes (node (i, j, k) numbered (k m + j) m + i): every lattice
+// vertex is joined to its 14 neighbours +-e, e in {0,1}^3 \ {0}, so a fine
+// node with an odd index is the midpoint of the coarse edge from
+// (i, j, k) >> 1 along its parity pattern.
+// rc = P^T rf: fine (2I, 2J, 2K) with weight 1, the 14 neighbours with 1/2
+__global__ void k_restrict3(int nc, const double *__restrict__ rf, const uint8_t *__restrict__ mask_c,
+                            double *__restrict__ rc) {
+    const int mc = nc + 1, mf = 2 * nc + 1;
+    const int64_t total = (int64_t)mc * mc * mc;
+    for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < total; id += (int64_t)gridDim.x * kBlock) {
+        const int I = (int)(id % mc), J = (int)((id / mc) % mc), K = (int)(id / ((int64_t)mc * mc));
+        double v = 0.0;
+        if (!mask_c[id]) {
+            const int i = 2 * I, j = 2 * J, k = 2 * K;
+            auto f = [&](int a, int b, int c) -> double {
+                return (a >= 0 && a < mf && b >= 0 && b < mf && c >= 0 && c < mf)
+                           ? rf[((int64_t)c * mf + b) * mf + a]
+                           : 0.0;
+            };
+            double h = 0.0;
+#pragma unroll
+            for (int e = 1; e < 8; ++e) {
+                const int a = e & 1, b = (e >> 1) & 1, c = e >> 2;
+                h += f(i + a, j + b, k + c) + f(i - a, j - b, k - c);
+            }
+            v = f(i, j, k) + 0.5 * h;
+        }
+        rc[id] = v;
+    }
+}
+
+// zf += P zc, 0 on fine Dirichlet nodes (nc coarse cubes per side)
+__global__ void k_prolong_add3(int nc, const double *__restrict__ zc, const uint8_t *__restrict__ mask_f,
+                               double *__restrict__ zf) {
+    const int mc = nc + 1, mf = 2 * nc + 1;
+    const int64_t total = (int64_t)mf * mf * mf;
+    for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < total; id += (int64_t)gridDim.x * kBlock) {
+        if (mask_f[id]) continue;
+        const int i = (int)(id % mf), j = (int)((id / mf) % mf), k = (int)(id / ((int64_t)mf * mf));
+        const int a = i & 1, b = j & 1, c = k & 1;
+        const int64_t lo = ((int64_t)(k >> 1) * mc + (j >> 1)) * mc + (i >> 1);
+        double v = zc[lo];
+        if (a | b | c) v = 0.5 * (v + zc[lo + ((int64_t)c * mc + b) * mc + a]);
         zf[id] += v;
     }
 }
@@ -188,7 +240,8 @@ bool invert(int n, std::vector<double> &a, std::vector<double> &inv) {
 
 struct MgLevel {
     DevPlan P{};
-    int n = 0;  // squares per side
+    int n = 0;    // squares (cubes) per side
+    int dim = 2;
     double *A = nullptr, *dinv = nullptr, *r = nullptr, *z = nullptr, *t = nullptr, *scratch = nullptr;
     void *A32 = nullptr;  // the packed operator as FP32 hi/lo pair; the cycle may read its heads
 };
@@ -216,22 +269,41 @@ int mg_galerkin_apply(fem_mg *mg, int l, const double *zc, double *out, hipStrea
 
 namespace {
 
-// One element pass (+ fix-up) of op over level L's packed operator: FP64
-// values, or the FP32 heads of the hi/lo pair (f32).
-template <class Op>
-int level_pass(const MgLevel &L, const Op &op, bool f32, hipStream_t s) {
+int64_t level_nodes(const MgLevel &L) {
+    const int64_t m = L.n + 1;
+    return L.dim == 3 ? m * m * m : m * m;
+}
+
+// rc = P^T rf and zf += P zc between level F and the next coarser level C
+int restrict_to(const MgLevel &C, const double *rf, double *rc, hipStream_t s) {
+    const int g = grid_for(level_nodes(C));
+    if (C.dim == 3) k_restrict3<<<g, kBlock, 0, s>>>(C.n, rf, C.P.mask, rc);
+    else k_restrict<<<g, kBlock, 0, s>>>(C.n, rf, C.P.mask, rc);
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+int prolong_add(const MgLevel &F, const MgLevel &C, const double *zc, double *zf, hipStream_t s) {
+    const int g = grid_for(level_nodes(F));
+    if (C.dim == 3) k_prolong_add3<<<g, kBlock, 0, s>>>(C.n, zc, F.P.mask, zf);
+    else k_prolong_add<<<g, kBlock, 0, s>>>(C.n, zc, F.P.mask, zf);
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+template <int NB, class Op>
+int level_pass_nb(const MgLevel &L, const Op &op, bool f32, hipStream_t s) {
     const DevPlan &P = L.P;
-    const size_t lds = chunk_lds_bytes<3, double>(P.E);
+    const size_t lds = chunk_lds_bytes<NB, double>(P.E);
     const ChunkGrid cg = chunk_grid(P.n_chunks, lds);
     int rc = dispatch_ept(P.E, [&](auto ept) -> int {
         constexpr int EPT = decltype(ept)::value;
         if (f32) {
-            LdPk<3, MAT_F32> ld{L.A32, P.n_elems};
-            k_chunk_main<3, EPT, kBlock, double, decltype(ld), Op, false>
+            LdPk<NB, MAT_F32> ld{L.A32, P.n_elems};
+            k_chunk_main<NB, EPT, kBlock, double, decltype(ld), Op, false>
                 <<<cg.grid, kBlock, lds, s>>>(P, ld, op, L.scratch, cg.xcd);
         } else {
-            LdPk<3, MAT_F64> ld{L.A, P.n_elems};
-            k_chunk_main<3, EPT, kBlock, double, decltype(ld), Op, false>
+            LdPk<NB, MAT_F64> ld{L.A, P.n_elems};
+            k_chunk_main<NB, EPT, kBlock, double, decltype(ld), Op, false>
                 <<<cg.grid, kBlock, lds, s>>>(P, ld, op, L.scratch, cg.xcd);
         }
         return 0;
@@ -245,6 +317,14 @@ int level_pass(const MgLevel &L, const Op &op, bool f32, hipStream_t s) {
     return 0;
 }
 
+// One element pass (+ fix-up) of op over level L's packed operator: FP64
+// values, or the FP32 heads of the hi/lo pair (f32); triangles or tetrahedra.
+template <class Op>
+int level_pass(const MgLevel &L, const Op &op, bool f32, hipStream_t s) {
+    if (L.P.nb == 4) return level_pass_nb<4>(L, op, f32, s);
+    return level_pass_nb<3>(L, op, f32, s);
+}
+
 // zn = z + omega D^-1 (r - A z) on level L
 int smooth_step(const MgLevel &L, const double *r, const double *z, double *zn, double omega, bool f32,
                 hipStream_t s) {
@@ -256,7 +336,7 @@ int smooth_step(const MgLevel &L, const double *r, const double *z, double *zn, 
 // r - A z goes to whichever of the two does not hold the iterate.
 int vcycle(fem_mg *mg, size_t l, const double *r, double *z, int smooth, double omega, bool f32, hipStream_t s) {
     MgLevel &L = mg->lv[l];
-    const int64_t n = (int64_t)(L.n + 1) * (L.n + 1);
+    const int64_t n = level_nodes(L);
     const int gv = grid_for(n);
     if (l + 1 == mg->lv.size()) {
         k_dense_mv<<<(mg->nc + kBlock / kWave - 1) / (kBlock / kWave), kBlock, 0, s>>>(mg->nc, mg->Ainv, r, z);
@@ -271,11 +351,9 @@ int vcycle(fem_mg *mg, size_t l, const double *r, double *z, int smooth, double 
     }
     if (int rc = level_pass(L, OpResid{cur, r, oth, L.P.mask}, f32, s)) return rc;
     MgLevel &C = mg->lv[l + 1];
-    const int64_t ncn = (int64_t)(C.n + 1) * (C.n + 1);
-    k_restrict<<<grid_for(ncn), kBlock, 0, s>>>(C.n, oth, C.P.mask, C.r);
-    FEM_HIP_CHECK(hipGetLastError());
+    if (int rc = restrict_to(C, oth, C.r, s)) return rc;
     if (int rc = vcycle(mg, l + 1, C.r, C.z, smooth, omega, f32, s)) return rc;
-    k_prolong_add<<<gv, kBlock, 0, s>>>(C.n, C.z, L.P.mask, cur);
+    if (int rc = prolong_add(L, C, C.z, cur, s)) return rc;
     for (int k = 0; k < smooth; ++k) {
         if (int rc = smooth_step(L, r, cur, oth, omega, f32, s)) return rc;
         std::swap(cur, oth);
@@ -289,14 +367,12 @@ int vcycle(fem_mg *mg, size_t l, const double *r, double *z, int smooth, double 
 
 int mg_galerkin_apply(fem_mg *mg, int l, const double *zc, double *out, hipStream_t s) {
     MgLevel &F = mg->lv[l], &C = mg->lv[l + 1];
-    const int64_t nf = (int64_t)(F.n + 1) * (F.n + 1);
+    const int64_t nf = level_nodes(F);
     const int gv = grid_for(nf);
     k_unit<<<gv, kBlock, 0, s>>>(nf, -1, F.z);  // zero
-    k_prolong_add<<<gv, kBlock, 0, s>>>(C.n, zc, F.P.mask, F.z);
+    if (int rc = prolong_add(F, C, zc, F.z, s)) return rc;
     if (int rc = launch_apply_pk64(F.P, MAT_F64, F.A, F.z, nullptr, F.t, 1.0, 1, F.scratch, s)) return rc;
-    k_restrict<<<grid_for((int64_t)(C.n + 1) * (C.n + 1)), kBlock, 0, s>>>(C.n, F.t, C.P.mask, out);
-    FEM_HIP_CHECK(hipGetLastError());
-    return 0;
+    return restrict_to(C, F.t, out, s);
 }
 
 }  // namespace fem
@@ -331,17 +407,24 @@ int fem_mg_create(int levels, const fem_plan *const *plans, const int *grid_n, i
     if (levels < 2 || levels > 16 || !plans || !grid_n || !K) return set_error(FEM_EINVAL, "bad level list");
     if (dtype != FEM_F64 && dtype != FEM_F32 && dtype != FEM_F32X2) return set_error(FEM_EINVAL, "unknown dtype");
     if (!std::isfinite(nu) || nu < 0.0) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
+    int dim0 = 0;
     for (int l = 0; l < levels; ++l) {
         if (!plans[l] || !K[l] || (nu != 0.0 && (!M || !M[l]))) return set_error(FEM_EINVAL, "NULL plan or matrix");
         const fem_plan_stats st = plan_stats(plans[l]);
-        if (st.dim != 2 || st.n_b != 3 || grid_n[l] < 1 || st.n_nodes != (int64_t)(grid_n[l] + 1) * (grid_n[l] + 1) ||
-            st.n_elems != 2 * (int64_t)grid_n[l] * grid_n[l])
-            return set_error(FEM_EINVAL, "level " + std::to_string(l) + " is not an n x n diagonal-cut square mesh");
+        const int64_t g = grid_n[l], m = g + 1;
+        const bool sq = st.dim == 2 && st.n_b == 3 && st.n_nodes == m * m && st.n_elems == 2 * g * g;
+        const bool cu = st.dim == 3 && st.n_b == 4 && st.n_nodes == m * m * m && st.n_elems == 6 * g * g * g;
+        if (g < 1 || !(sq || cu))
+            return set_error(FEM_EINVAL, "level " + std::to_string(l) +
+                                             " is not an n x n diagonal-cut square mesh or an n^3 Kuhn cube mesh");
+        if (l > 0 && st.dim != dim0) return set_error(FEM_EINVAL, "all levels must have the same dimension");
+        if (l == 0) dim0 = st.dim;
         if (l > 0 && grid_n[l - 1] != 2 * grid_n[l])
-            return set_error(FEM_EINVAL, "each level must halve the squares per side");
+            return set_error(FEM_EINVAL, "each level must halve the squares (cubes) per side");
     }
-    const int nc = (grid_n[levels - 1] + 1) * (grid_n[levels - 1] + 1);
-    if (nc > 1089) return set_error(FEM_EINVAL, "the coarsest level may have at most 33 x 33 nodes");
+    const int mcs = grid_n[levels - 1] + 1;
+    const int nc = dim0 == 3 ? mcs * mcs * mcs : mcs * mcs;
+    if (nc > 1089) return set_error(FEM_EINVAL, "the coarsest level may have at most 1089 nodes (33^2, 10^3)");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     fem_mg *mg = new (std::nothrow) fem_mg();
     if (!mg) return set_error(FEM_ENOMEM, "host allocation failed");
@@ -358,6 +441,7 @@ int fem_mg_create(int levels, const fem_plan *const *plans, const int *grid_n, i
     for (int l = 0; l < levels; ++l) {
         mg->lv[l].P = fem::plan_device(plans[l]);
         mg->lv[l].n = grid_n[l];
+        mg->lv[l].dim = dim0;
         const fem::DevPlan &P = mg->lv[l].P;
         const int64_t n = P.n_nodes;
         oA[l] = take((size_t)fem::packed_count(P.nb) * P.n_elems * 8);

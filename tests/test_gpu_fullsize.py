@@ -272,3 +272,27 @@ def test_full_size_p2_on_sampled_nodes_and_solve():
     ro = oracle.residual(mesh.n_nodes, mesh.elems, Kf, Mf, nu, bo, xs.cpu().numpy(), mask)
     r0 = oracle.residual(mesh.n_nodes, mesh.elems, Kf, Mf, nu, bo, np.zeros(mesh.n_nodes), mask)
     assert np.linalg.norm(ro) / np.linalg.norm(r0) <= 1.05e-8
+
+
+def test_full_size_multigrid_on_c3():
+    """C3 (160^3 cubes, 24.6 M tetrahedra) through the Kuhn hierarchy
+    160 -> 80 -> 40 -> 20 -> 10 -> 5 in the benchmark's configuration: the
+    oracle's FP64 residual of the MG-FCG solution meets 1e-8."""
+    mesh, nd, nu, f = _workload("c3")
+    meshes = inputs.cube_hierarchy(mesh, coarsest=5)
+    nds = [inputs.boundary_nodes(m, "all") for m in meshes]
+    mg = fem.MG.from_meshes(meshes, nds, nu)
+    plan = mg.plans[0]
+    b = plan.empty_vector()
+    fem.assemble_rhs(plan, fem.F64, mg.M[0], cuda(f), b)
+    x = plan.empty_vector()
+    x.zero_()
+    info = mg.solve(fem.mg_opts(rtol=1e-8, smooth=1, cycle_dtype=fem.F32), b, x)
+    print("mg c3", info, flush=True)
+    assert info["status"] == fem.FEM_OK and info["iters"] <= 40
+    K, M, _ = oracle.local_matrices(mesh.coords, mesh.elems)
+    mask = oracle.mask_from_nodes(mesh.n_nodes, nd)
+    bo = oracle.rhs(mesh.n_nodes, mesh.elems, M, f)
+    r = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, bo, x.cpu().numpy(), mask)
+    r0 = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, bo, np.zeros(mesh.n_nodes), mask)
+    assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8

@@ -151,3 +151,65 @@ def test_mg_fcg_with_fp32_cycle_meets_target():
         assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8
         its[cd] = info["iters"]
     assert its[fem.F32] <= its[fem.F64] + 2, its
+
+
+# ---- Kuhn cube meshes (3D) ----
+
+def _hierarchy3(n, jitter, which, nu, coarsest, seed=0):
+    fine = inputs.cube_mesh(n, jitter=jitter, seed=seed)
+    meshes = inputs.cube_hierarchy(fine, coarsest=coarsest)
+    nds = [inputs.boundary_nodes(m, which) for m in meshes]
+    return meshes, nds, fem.MG.from_meshes(meshes, nds, nu)
+
+
+@pytest.mark.parametrize("n,nu", [(8, 0.0), (16, 0.7)])
+def test_galerkin_identity_on_nested_kuhn_meshes(n, nu):
+    meshes, nds, mg = _hierarchy3(n, 0.0, "all", nu, coarsest=2)
+    rng = np.random.default_rng(6)
+    for level in range(len(meshes) - 1):
+        mc = meshes[level + 1]
+        zc = rng.standard_normal(mc.n_nodes)
+        zc[nds[level + 1]] = 0.0
+        got = mg.galerkin_apply(level, cuda(zc)).cpu().numpy()
+        Kc, Mc, _ = oracle.local_matrices(mc.coords, mc.elems)
+        mask = oracle.mask_from_nodes(mc.n_nodes, nds[level + 1])
+        want = -oracle.residual(mc.n_nodes, mc.elems, Kc, Mc, nu, np.zeros(mc.n_nodes), zc, mask)
+        scale = np.abs(want).max()
+        assert np.abs(got - want).max() <= 1e-12 * scale, (level, np.abs(got - want).max() / scale)
+
+
+@pytest.mark.parametrize("n,coarsest,jitter,nu,smooth", [(8, 2, 0.0, 0.0, 1), (16, 4, 0.1, 1.0, 2),
+                                                          (20, 5, 0.1, 10.0, 1)])
+def test_vcycle_3d_matches_oracle(n, coarsest, jitter, nu, smooth):
+    print(f"vcycle3 n={n} coarsest={coarsest} jitter={jitter} nu={nu} smooth={smooth}", flush=True)
+    meshes, nds, mg = _hierarchy3(n, jitter, "all", nu, coarsest, seed=n)
+    levels, Ps = omg.hierarchy(meshes, nds, nu)
+    r = np.random.default_rng(n + 1).standard_normal(meshes[0].n_nodes)
+    got = mg.vcycle(cuda(r), smooth, 2.0 / 3.0).cpu().numpy()
+    want = omg.vcycle(levels, Ps, r, smooth, 2.0 / 3.0)
+    scale = np.abs(want).max()
+    assert np.abs(got - want).max() <= 1e-12 * scale, np.abs(got - want).max() / scale
+    assert np.all(got[nds[0]] == 0.0)
+
+
+def test_mg_fcg_3d_converges_independently_of_the_mesh_size():
+    iters = []
+    for n in (16, 32, 64):
+        meshes, nds, mg = _hierarchy3(n, 0.1, "all", 10.0, coarsest=4, seed=n)
+        prob = Problem(meshes[0], nu=10.0, dirichlet="all", f="sine", seed=n + 1)
+        x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+        info = mg.solve(fem.mg_opts(rtol=1e-8), cuda(prob.b), x)
+        print(n, info, flush=True)
+        assert info["status"] == fem.FEM_OK
+        r = oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, x.cpu().numpy(), prob.mask)
+        r0 = oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, np.zeros(prob.n), prob.mask)
+        assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8
+        iters.append(info["iters"])
+    assert max(iters) <= 30 and max(iters) <= 1.5 * min(iters) + 2, iters
+
+
+def test_mg_rejects_mixed_dimensions():
+    m2 = inputs.square_mesh(8)
+    m3 = inputs.cube_mesh(4)
+    with pytest.raises(fem.FemError):
+        fem.MG.from_meshes([m2, m3], [inputs.boundary_nodes(m2), inputs.boundary_nodes(m3)], 0.0)
