@@ -245,12 +245,13 @@ __global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ src
         __syncthreads();
         for (int kl = 0; kl < nkb; ++kl) {
             const int k0 = (kc + kl) * 32 + 8 * (lane >> 4);
-            const int tap = k0 >> lcin, ci = k0 & (Cin - 1);
+            // past the 9 taps (the last block's padding) the packed weights are
+            // zero: read the last tap's (finite) inputs instead of selecting zeros
+            const int tap = min(k0 >> lcin, 8), ci = k0 & (Cin - 1);
             const int toff = (tap / 3) * HX + tap % 3;
             bf8 a[MT];
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                a[mt] = tap < 9 ? *reinterpret_cast<const bf8 *>(tin + (size_t)(hoff[mt] + toff) * Cin + ci) : zero8();
+            for (int mt = 0; mt < MT; ++mt) a[mt] = *reinterpret_cast<const bf8 *>(tin + (size_t)(hoff[mt] + toff) * Cin + ci);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const bf8 bv = *reinterpret_cast<const bf8 *>(tb + ((size_t)(kl * NT + t) * 64 + lane) * 8);
