@@ -128,3 +128,38 @@ def test_square_hierarchy_is_nested():
         for J in range(m.n + 1):
             for I in range(m.n + 1):
                 assert np.array_equal(m.coords[J * (m.n + 1) + I], fine.coords[(k * J) * 33 + k * I])
+
+
+def test_cube_hierarchy_is_nested():
+    """Every coarse node sits on the fine node (2^l I, 2^l J, 2^l K) and every
+    level is the generator's own Kuhn mesh of n / 2^l cubes."""
+    import numpy as np
+
+    from paper_1911_03973_amd import inputs
+
+    fine = inputs.cube_mesh(20, jitter=0.1, seed=5)
+    levels = inputs.cube_hierarchy(fine, coarsest=5)
+    assert [m.n for m in levels] == [20, 10, 5]
+    for l, m in enumerate(levels):
+        np.testing.assert_array_equal(m.elems, inputs.cube_mesh(m.n).elems)
+        k, mf, mc = 1 << l, 21, m.n + 1
+        K, rem = np.divmod(np.arange(mc ** 3), mc * mc)
+        J, I = np.divmod(rem, mc)
+        np.testing.assert_array_equal(m.coords, fine.coords[((k * K) * mf + k * J) * mf + k * I])
+
+
+def test_p2_mesh_lattice_and_midpoints():
+    """P2 nodes are the (2n+1)^2 lattice; each element lists its vertices,
+    then the midpoints of edges (0,1), (1,2), (2,0), at the middle of the
+    (jittered, straight) edges."""
+    import numpy as np
+
+    from paper_1911_03973_amd import inputs
+
+    m = inputs.square_mesh_p2(6, jitter=0.2, seed=3)
+    assert m.n_nodes == 13 * 13 and m.n_elems == 72 and m.nb == 6
+    c = m.coords
+    e = m.elems
+    for a, b, mid in ((0, 1, 3), (1, 2, 4), (2, 0, 5)):
+        np.testing.assert_allclose(c[e[:, mid]], 0.5 * (c[e[:, a]] + c[e[:, b]]), rtol=0, atol=1e-15)
+    assert len(np.unique(e)) == m.n_nodes
