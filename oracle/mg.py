@@ -22,6 +22,11 @@ definitions:
   restriction    P^T;
   smoother       damped Jacobi z <- z + omega D^-1 (r - A z), starting from
                  z = 0, `smooth` steps before and after the coarse correction;
+                 or the paper's three-level Chebyshev iteration (Section 2,
+                 eq. (9) with the scaling factors of eq. (8)) applied to the
+                 Jacobi-scaled level system D^-1 A z = D^-1 r on the interval
+                 [lower * g, g], where g is the Gershgorin bound of D^-1 A
+                 built from the element matrices (`Level.gersh`);
   coarsest       exact solve of the free-node system (dense LU of numpy).
 
 Dirichlet nodes carry zero corrections on every level: residuals there are
@@ -29,13 +34,19 @@ ignored and corrections stay zero, so every level works with the free-node
 block of its operator.  Operator applications go through the oracle's element
 residual (Algorithm 1, eq. (4)) with the level's own K_e, M_e.
 
-Pins (tests/test_oracle_mg.py): P reproduces linear functions exactly; the
+Pins (tests/test_oracle_mg.py): g is 2 on the uniform square mesh and bounds
+the largest eigenvalue of the free-node pencil (A, D) from above; m Chebyshev
+smoothing steps multiply the error along each eigenvector of that pencil by
+the scaled Chebyshev polynomial T_m((theta - lambda) / delta) / T_m(theta /
+delta) (numpy's Chebyshev series, not the recurrence); P reproduces linear functions exactly; the
 Galerkin identity P^T A_h P = A_2h of nested P1 spaces on dense matrices
 assembled here by the definition; the V-cycle operator is symmetric; a
 one-level cycle solves the coarse system; the V-cycle contracts the error by
 a mesh-independent factor well below one.
 """
 from __future__ import annotations
+
+import functools
 
 import numpy as np
 import scipy.sparse
@@ -132,6 +143,17 @@ class Level:
         self.free = self.mask == 0
         self.dinv = np.where(self.free, 1.0 / np.where(self.free, d, 1.0), 0.0)
 
+    @functools.cached_property
+    def gersh(self):
+        """g = max over free nodes i of D_ii^-1 sum_e sum_j |(A_e)_ij| (the
+        element matrices' absolute row sums gathered to the nodes, every
+        column counted).  Since sum_e |(A_e)_ij| >= |a_ij|, Gershgorin's
+        theorem for D^-1 A bounds its eigenvalues by g."""
+        Ae = np.asarray(self.K, dtype=np.float64) + self.nu * np.asarray(self.M, dtype=np.float64)
+        absrow = np.zeros(self.n_nodes)
+        np.add.at(absrow, self.elems.astype(np.int64).ravel(), np.abs(Ae).sum(axis=2).ravel())
+        return float((self.dinv * absrow)[self.free].max()) if self.free.any() else 0.0
+
     def residual(self, r, z):
         """r - A z on free nodes, 0 on Dirichlet nodes."""
         return residual(self.n_nodes, self.elems, self.K, self.M, self.nu, r, z, self.mask)
@@ -152,8 +174,35 @@ def hierarchy(meshes, dirichlets, nu):
     return levels, Ps
 
 
-def vcycle(levels, Ps, r, smooth, omega, l=0):
-    """z = B r: one V-cycle from level l (the coarsest level solves exactly)."""
+def chebyshev_smooth(L, r, z, steps, lower, lam_hi=None):
+    """`steps` iterations of the paper's three-level Chebyshev method (eq. (9),
+    scaling factors of eq. (8)) for D^-1 A z = D^-1 r on [lam1, lam2] =
+    [lower g, g], from z (None: z = 0, whose first step needs no product):
+      z^1 = z^0 + 2 / (lam1 + lam2) D^-1 r_0,
+      z^{k+1} = z^k + C_{k-1} / C_{k+1} (z^k - z^{k-1}) + 4 / (lam2 - lam1) C_k / C_{k+1} D^-1 r_k,
+    r_k = r - A z^k, C_0 = 1, C_1 = sigma = (lam1 + lam2) / (lam2 - lam1),
+    C_{k+1} = 2 sigma C_k - C_{k-1}; the ratio rho_k = C_{k-1} / C_k follows
+    rho_1 = 1 / sigma, rho_{k+1} = 1 / (2 sigma - rho_k)."""
+    lam2 = L.gersh if lam_hi is None else lam_hi
+    lam1 = lower * lam2
+    sigma = (lam1 + lam2) / (lam2 - lam1)
+    res = r if z is None else L.residual(r, z)
+    z_old = np.zeros(L.n_nodes) if z is None else z
+    z = z_old + (2.0 / (lam1 + lam2)) * L.dinv * res
+    rho = 1.0 / sigma
+    for _ in range(steps - 1):
+        ck = 1.0 / (2.0 * sigma - rho)  # C_k / C_{k+1}
+        z_new = z + (rho * ck) * (z - z_old) + (4.0 / (lam2 - lam1) * ck) * L.dinv * L.residual(r, z)
+        z_old, z = z, z_new
+        rho = ck
+    return z
+
+
+def vcycle(levels, Ps, r, smooth, omega, l=0, smoother="jacobi", lower=0.3):
+    """z = B r: one V-cycle from level l (the coarsest level solves exactly).
+    smoother "jacobi": `smooth` damped-Jacobi steps (factor omega) before and
+    after the coarse correction; "chebyshev": `smooth` Chebyshev steps on
+    [lower g, g] instead (omega unused)."""
     L = levels[l]
     r = np.where(L.free, np.asarray(r, dtype=np.float64), 0.0)
     if l == len(levels) - 1:
@@ -162,12 +211,20 @@ def vcycle(levels, Ps, r, smooth, omega, l=0):
         if f.size:
             z[f] = np.linalg.solve(A, r[f])
         return z
-    z = omega * L.dinv * r
-    for _ in range(smooth - 1):
-        z = z + omega * L.dinv * L.residual(r, z)
+    if smoother == "chebyshev":
+        z = chebyshev_smooth(L, r, None, smooth, lower)
+    elif smoother == "jacobi":
+        z = omega * L.dinv * r
+        for _ in range(smooth - 1):
+            z = z + omega * L.dinv * L.residual(r, z)
+    else:
+        raise ValueError("smoother: 'jacobi' or 'chebyshev'")
     rc = Ps[l].T @ L.residual(r, z)
-    zc = vcycle(levels, Ps, rc, smooth, omega, l + 1)
+    zc = vcycle(levels, Ps, rc, smooth, omega, l + 1, smoother, lower)
     z = z + np.where(L.free, Ps[l] @ zc, 0.0)
-    for _ in range(smooth):
-        z = z + omega * L.dinv * L.residual(r, z)
+    if smoother == "chebyshev":
+        z = chebyshev_smooth(L, r, z, smooth, lower)
+    else:
+        for _ in range(smooth):
+            z = z + omega * L.dinv * L.residual(r, z)
     return z

@@ -202,3 +202,101 @@ def test_vcycle_3d_is_symmetric_and_contracts():
         rate = np.sqrt(e_new @ -L.residual(zero, e_new)) / np.sqrt(e @ ae)
         e = e_new
     assert rate < 0.5, rate
+
+
+# ---- Chebyshev smoothing (the paper's three-level iteration on D^-1 A) ----
+
+
+def _pencil(L):
+    """Eigenpairs of the free-node pencil (A, D): A v = lambda D v, V^T D V = I."""
+    import scipy.linalg
+
+    A, f = L.dense_free()
+    lam, V = scipy.linalg.eigh(A, np.diag(np.diag(A)))
+    return A, f, lam, V
+
+
+def test_gershgorin_bound_is_two_on_the_uniform_square_mesh():
+    """Right isosceles triangles couple their two acute vertices by 0 and all
+    other pairs negatively, so at every free node the element absolute row
+    sums add up to 2 x the diagonal (the 5-point stencil 4, -1, -1, -1, -1)."""
+    m = inputs.square_mesh(8)
+    L = omg.Level(m, inputs.boundary_nodes(m), 0.0)
+    assert abs(L.gersh - 2.0) <= 1e-14
+
+
+@pytest.mark.parametrize("dim,nu", [(2, 0.0), (2, 3.0), (3, 0.0), (3, 1.0)])
+def test_gershgorin_bound_covers_the_spectrum(dim, nu):
+    """lambda_max(D^-1 A) <= g (Gershgorin's theorem), and g is tight enough to
+    place the smoother's interval (within 25 %).  Row sums without absolute
+    values (a plausible slip) give a 'bound' far below lambda_max."""
+    mesh = inputs.square_mesh(10, jitter=0.2, seed=6) if dim == 2 else inputs.cube_mesh(5, jitter=0.1, seed=6)
+    L = omg.Level(mesh, inputs.boundary_nodes(mesh), nu)
+    _, _, lam, _ = _pencil(L)
+    assert lam.max() <= L.gersh * (1.0 + 1e-12)
+    assert L.gersh <= 1.25 * lam.max(), (L.gersh, lam.max())
+    Ae = L.K + nu * L.M
+    signed = np.zeros(L.n_nodes)
+    np.add.at(signed, L.elems.astype(np.int64).ravel(), Ae.sum(axis=2).ravel())
+    assert (L.dinv * signed)[L.free].max() < 0.9 * lam.max()
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3, 5])
+@pytest.mark.parametrize("start", ["zero", "random"])
+def test_chebyshev_smoother_applies_the_scaled_chebyshev_polynomial(steps, start):
+    """For A u = r, m steps from z^0 leave the error u - z^m = P_m(D^-1 A)(u - z^0)
+    with P_m(x) = T_m((theta - x) / delta) / T_m(theta / delta), theta and delta
+    the centre and half-width of [lower g, g]; checked along the pencil's
+    eigenvectors with numpy's Chebyshev basis (the recurrence is not used)."""
+    mesh = inputs.square_mesh(8, jitter=0.2, seed=3)
+    L = omg.Level(mesh, inputs.boundary_nodes(mesh, "x2=0"), 0.5)
+    A, f, lam, V = _pencil(L)
+    lower = 0.3
+    lam1, lam2 = lower * L.gersh, L.gersh
+    theta, delta = 0.5 * (lam1 + lam2), 0.5 * (lam2 - lam1)
+    T = np.polynomial.chebyshev.Chebyshev.basis(steps)
+    P = T((theta - lam) / delta) / T(theta / delta)
+    rng = np.random.default_rng(steps)
+    u = np.zeros(L.n_nodes)
+    u[f] = rng.standard_normal(f.size)
+    r = np.zeros(L.n_nodes)
+    r[f] = A @ u[f]
+    z0 = None
+    e0 = u[f].copy()
+    if start == "random":
+        z0 = np.zeros(L.n_nodes)
+        z0[f] = rng.standard_normal(f.size)
+        e0 = u[f] - z0[f]
+    z = omg.chebyshev_smooth(L, r, z0, steps, lower)
+    c = V.T @ (np.diag(A) * e0)  # coefficients in the D-orthonormal eigenbasis
+    want = V @ (P * c)
+    assert np.abs((u[f] - z[f]) - want).max() <= 1e-11 * np.abs(e0).max()
+    assert np.all(z[L.mask == 1] == 0.0)
+
+
+def test_chebyshev_vcycle_is_symmetric_and_contracts():
+    """The same polynomial before and after the correction keeps B symmetric
+    and positive definite; its contraction stays mesh-independent and below
+    that of two damped-Jacobi steps on the same meshes."""
+    rates = {}
+    for n in (16, 32, 64):
+        _, _, levels, Ps = _hierarchy(n, 4, 0.2, "x2=0", 0.5, seed=n)
+        L = levels[0]
+        rng = np.random.default_rng(n)
+        r1, r2 = rng.standard_normal(L.n_nodes) * L.free, rng.standard_normal(L.n_nodes) * L.free
+        z1 = omg.vcycle(levels, Ps, r1, 2, 0.0, smoother="chebyshev")
+        z2 = omg.vcycle(levels, Ps, r2, 2, 0.0, smoother="chebyshev")
+        assert abs(r1 @ z2 - r2 @ z1) <= 1e-13 * np.linalg.norm(r1) * np.linalg.norm(z2)
+        assert r1 @ z1 > 0 and r2 @ z2 > 0
+        zero = np.zeros(L.n_nodes)
+        for sm in ("chebyshev", "jacobi"):
+            e = rng.standard_normal(L.n_nodes) * L.free
+            for _ in range(15):
+                ae = -L.residual(zero, e)
+                e_new = e - omg.vcycle(levels, Ps, ae, 2, 2.0 / 3.0, smoother=sm)
+                rate = np.sqrt(e_new @ -L.residual(zero, e_new)) / np.sqrt(e @ ae)
+                e = e_new
+            rates[(n, sm)] = rate
+    assert max(rates[(n, "chebyshev")] for n in (16, 32, 64)) < 0.3, rates
+    for n in (16, 32, 64):
+        assert rates[(n, "chebyshev")] < rates[(n, "jacobi")], rates
