@@ -405,7 +405,9 @@ def run_multigrid(args):
     b = plan.empty_vector()
     fem.assemble_rhs(plan, fem.F64, mg.M[0], torch.from_numpy(f).cuda(), b)
     x = plan.empty_vector()
-    opts = fem.mg_opts(rtol=1e-8, smooth=args.mg_smooth, cycle_dtype=fem.F32 if args.mg_cycle == "f32" else fem.F64)
+    smoother = fem.SMOOTH_CHEBYSHEV if args.mg_smoother == "chebyshev" else fem.SMOOTH_JACOBI
+    opts = fem.mg_opts(rtol=1e-8, smooth=args.mg_smooth, cycle_dtype=fem.F32 if args.mg_cycle == "f32" else fem.F64,
+                       smoother=smoother)
 
     def mg_solve():
         x.zero_()
@@ -433,7 +435,8 @@ def run_multigrid(args):
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": w["name"].replace("FP32 element matvec + FP64 refinement to 1e-8",
                                                  "FCG with a geometric multigrid V-cycle, FP64 operators, to 1e-8"),
-                   "levels": [m.n for m in meshes], "smooth": args.mg_smooth, "cycle": args.mg_cycle},
+                   "levels": [m.n for m in meshes], "smooth": args.mg_smooth, "smoother": args.mg_smoother,
+                   "cycle": args.mg_cycle},
         "roofline": None,
         "time_to_1e8_s": round(sec, 4), "iters": info["iters"], "relres": info["relres"],
         "vcycles": info["precond_calls"], "setup_s": round(t_setup, 3),
@@ -553,7 +556,9 @@ def main():
     ap.add_argument("--mg-base", choices=["c2", "c3"], default="c2", help="mg workload: the problem (2D or 3D)")
     ap.add_argument("--mg-coarsest", type=int, default=0,
                     help="mg workload: cells per side of the coarsest grid (0: 16 in 2D, 5 in 3D)")
-    ap.add_argument("--mg-smooth", type=int, default=1, help="mg workload: Jacobi steps before and after")
+    ap.add_argument("--mg-smooth", type=int, default=1, help="mg workload: smoothing steps before and after")
+    ap.add_argument("--mg-smoother", choices=["jacobi", "chebyshev"], default="jacobi",
+                    help="mg workload: damped Jacobi or Chebyshev smoothing")
     ap.add_argument("--mg-cycle", choices=["f64", "f32"], default="f32",
                     help="mg workload: precision of the V-cycle's operator products")
     ap.add_argument("--iter-n", type=int, default=2048, help="cheb workload: squares per side")

@@ -454,21 +454,34 @@ int fem_fcg_solve(const fem_plan *plan, const fem_fcg_opts *opts, fem_unet *net,
  *                 fine node <- the average of the two coarse ends of its edge,
  *                 the diagonal edge included);
  *   restriction   its transpose;
- *   smoothing     `smooth` damped-Jacobi steps before and after (omega);
+ *   smoothing     `smooth` damped-Jacobi steps before and after (omega), or
+ *                 as many Chebyshev steps (fem_smoother);
  *   coarsest      exact solve through a dense inverse formed at setup.
  * Every operator application is the element residual (eq. (4), Algorithm 1)
  * through the FP64 packed difference form of the level's own K_e, M_e. */
 typedef struct fem_mg fem_mg;
 
+/* Smoothers of the V-cycle.  FEM_SMOOTH_CHEBYSHEV: `smooth` steps of the
+ * three-level Chebyshev iteration (Section 2, eq. (9) with the scaling factors
+ * of eq. (8)) for D^-1 A z = D^-1 r on [cheb_lower g, g], g the level's
+ * Gershgorin bound of D^-1 A from the element matrices
+ * (max over free i of D_ii^-1 sum_e sum_j |(A_e)_ij|, fem_mg_level_bound);
+ * the same polynomial before and after the correction keeps the V-cycle
+ * symmetric. */
+typedef enum { FEM_SMOOTH_JACOBI = 0, FEM_SMOOTH_CHEBYSHEV = 1 } fem_smoother;
+
 typedef struct {
     double rtol;      /* stop at ||b - A x|| <= rtol ||b - A x0|| (true FP64 residual) */
     int max_iter;     /* FCG iterations */
-    int smooth;       /* Jacobi steps before and after the coarse correction (>= 1) */
-    double omega;     /* Jacobi damping, in (0, 2); default 2/3 */
+    int smooth;       /* smoothing steps before and after the coarse correction, in [1, 64] */
+    double omega;     /* Jacobi damping, in (0, 2); default 2/3 (FEM_SMOOTH_JACOBI only) */
     int max_replace;  /* restarts from the true residual when the recursive one met rtol */
     int cycle_dtype;  /* FEM_F64 (default): the V-cycle's operator products in FP64; FEM_F32:
                          they read the FP32 heads of the packed operator (half the bytes;
                          FCG's own products and the true residual stay FP64) */
+    int smoother;       /* fem_smoother; default FEM_SMOOTH_JACOBI */
+    double cheb_lower;  /* FEM_SMOOTH_CHEBYSHEV: lower end of the interval as a fraction of g,
+                           in (0, 1); default 0.3 */
 } fem_mg_opts;
 
 void fem_mg_opts_default(fem_mg_opts *o);
@@ -493,15 +506,19 @@ int fem_mg_destroy(fem_mg *mg);
 int fem_mg_solve(fem_mg *mg, const fem_mg_opts *opts, const double *d_b, double *d_x, fem_fcg_info *info,
                  void *stream);
 
-/* z = B r: one V-cycle on the finest level, as the solver applies it (smooth
- * damped-Jacobi steps before and after, omega in (0, 2), cycle_dtype as in
- * fem_mg_opts).  r (n_nodes of the
- * finest level, mesh order) is read on free nodes only; z is written on every
- * node, 0 on Dirichlet nodes.  r and z must not alias.  Uses the hierarchy's
- * own level vectors, so calls on one hierarchy must not overlap (launches on
- * one stream are fine).  Asynchronous on `stream`. */
-int fem_mg_vcycle(fem_mg *mg, int smooth, double omega, int cycle_dtype, const double *d_r, double *d_z,
-                  void *stream);
+/* z = B r: one V-cycle on the finest level, as the solver applies it, with
+ * the smoothing fields of opts (smooth, omega, smoother, cheb_lower,
+ * cycle_dtype; the others are ignored).  r (n_nodes of the finest level, mesh
+ * order) is read on free nodes only; z is written on every node, 0 on
+ * Dirichlet nodes.  r and z must not alias.  Uses the hierarchy's own level
+ * vectors, so calls on one hierarchy must not overlap (launches on one stream
+ * are fine).  FEM_EINVAL for options out of range.  Asynchronous on `stream`. */
+int fem_mg_vcycle(fem_mg *mg, const fem_mg_opts *opts, const double *d_r, double *d_z, void *stream);
+
+/* *g = the Gershgorin bound of D^-1 A on `level` (0 = finest) that places the
+ * Chebyshev smoother's interval, computed at fem_mg_create (1 on a level
+ * without free nodes).  g is a host pointer. */
+int fem_mg_level_bound(const fem_mg *mg, int level, double *g);
 
 /* out = P^T A_level P zc for a vector zc of level level+1 (the Galerkin
  * product; on nested meshes without jitter it equals A_{level+1} zc on free

@@ -25,7 +25,17 @@
 // One V-cycle from level l with residual r: `smooth` damped-Jacobi steps
 // z += omega D^-1 (r - A z) from z = 0, restriction of r - A z, the cycle on
 // the next level, z += P z_coarse, `smooth` more Jacobi steps; on the
-// coarsest level z = A^-1 r with a dense inverse formed once at setup.  Every
+// coarsest level z = A^-1 r with a dense inverse formed once at setup.
+// The Chebyshev smoother replaces the Jacobi steps by `smooth` steps of the
+// three-level Chebyshev iteration of Section 2 (eq. (9), scaling factors of
+// eq. (8)) on the Jacobi-scaled level system D^-1 A z = D^-1 r over
+// [lower g, g], g = max over free nodes of D_ii^-1 sum_e sum_j |(A_e)_ij|
+// (Gershgorin's bound of D^-1 A from the element matrices, one element pass
+// at setup).  A step keeps the increment d = z^{k+1} - z^k:
+//   d <- rho_k / (2 sigma - rho_k) d + 4 / (lam2 - lam1) / (2 sigma - rho_k) D^-1 (r - A z),
+//   z <- z + d,
+// rho_1 = 1 / sigma, rho_{k+1} = 1 / (2 sigma - rho_k), sigma = (lam1 + lam2) / (lam2 - lam1);
+// the first step of either side is d = 2 / (lam1 + lam2) D^-1 (r - A z).  Every
 // operator application is the element residual through the FP64 packed form;
 // Dirichlet rows stay zero in every correction.  The cycle preconditions
 // flexible CG (FCG(1), as in fcg.hip), judged by the true residual.
@@ -175,6 +185,117 @@ struct OpSmooth {
     __device__ __forceinline__ void end(double *, int) const {}
 };
 
+// One Chebyshev step: t = r - A z (0 on Dirichlet nodes), d <- c1 d +
+// c2 D^-1 t, zn = z + d.  c1 == 0 restarts the recurrence and does not read d
+// (whose old contents may be anything).
+struct OpCheb {
+    static constexpr bool kLocal = false;
+    const double *z, *r, *dinv;
+    double *zn, *d;
+    const uint8_t *mask;
+    double c1, c2;
+    __device__ __forceinline__ bool begin() const { return true; }
+    __device__ __forceinline__ double gather(int g, int) const { return z[g]; }
+    struct Pre {
+        double rv, zv, dv, cv;
+        bool zero;
+    };
+    __device__ __forceinline__ Pre fixup_load(int, int g) const {
+        return {r[g], z[g], dinv[g], c1 != 0.0 ? d[g] : 0.0, mask[g] != 0};
+    }
+    __device__ __forceinline__ void fixup_store(int, int g, const Pre &pr, double acc) const {
+        double t = pr.rv + (-1.0) * acc;
+        if (pr.zero) t = 0.0;
+        const double dn = c1 * pr.cv + c2 * pr.dv * t;
+        d[g] = dn;
+        zn[g] = pr.zv + dn;
+    }
+    __device__ __forceinline__ void finish(int g, double acc) const { fixup_store(0, g, fixup_load(0, g), acc); }
+    template <int BS>
+    __device__ __forceinline__ void end(double *, int) const {}
+};
+
+// |A_e| x: the element matrix with every entry in absolute value, read from
+// the FP64 packed difference form (A_ij = v_ij off the diagonal, A_ii = the
+// row sum v_i minus the row's off-diagonal entries).
+template <int NB>
+struct LdAbs {
+    using Base = LdPk<NB, MAT_F64>;
+    using Regs = typename Base::Regs;
+    Base base;
+    __device__ __forceinline__ void fetch(int64_t e, Regs &R) const { base.fetch(e, R); }
+    template <class T>
+    __device__ __forceinline__ static void apply(const Regs &R, const T (&xt)[NB], T (&yt)[NB]) {
+        double dg[NB], y[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) dg[i] = R.v[i];
+        int k = NB;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = i + 1; j < NB; ++j) {
+                dg[i] -= R.v[k];
+                dg[j] -= R.v[k];
+                ++k;
+            }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) y[i] = fabs(dg[i]) * (double)xt[i];
+        k = NB;
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = i + 1; j < NB; ++j) {
+                const double a = fabs(R.v[k++]);
+                y[i] += a * (double)xt[j];
+                y[j] += a * (double)xt[i];
+            }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) yt[i] = (T)y[i];
+    }
+};
+
+// out = sum_e C_e^T |A_e| 1 (the element absolute row sums at the nodes)
+struct OpAbsRow {
+    static constexpr bool kLocal = false;
+    double *out;
+    __device__ __forceinline__ bool begin() const { return true; }
+    __device__ __forceinline__ double gather(int, int) const { return 1.0; }
+    struct Pre {};
+    __device__ __forceinline__ Pre fixup_load(int, int) const { return {}; }
+    __device__ __forceinline__ void fixup_store(int, int g, const Pre &, double acc) const { out[g] = acc; }
+    __device__ __forceinline__ void finish(int g, double acc) const { out[g] = acc; }
+    template <int BS>
+    __device__ __forceinline__ void end(double *, int) const {}
+};
+
+// part[block] = max over the block's free nodes of dinv[i] * absrow[i]
+__global__ __launch_bounds__(kBlock) void k_gersh(int64_t n, const double *__restrict__ absrow,
+                                                  const double *__restrict__ dinv, const uint8_t *__restrict__ mask,
+                                                  double *__restrict__ part) {
+    __shared__ double red[kBlock];
+    double m = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        if (!mask[i]) m = fmax(m, dinv[i] * absrow[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// z = d = w D^-1 r: the first Chebyshev step from z = 0 (no product needed)
+__global__ __launch_bounds__(kBlock) void k_cheb_first(int64_t n, double w, const double *__restrict__ dinv,
+                                                       const double *__restrict__ r, double *__restrict__ z,
+                                                       double *__restrict__ d) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const double v = w * dinv[i] * r[i];
+        z[i] = v;
+        d[i] = v;
+    }
+}
+
 // t = r - A z, 0 on Dirichlet nodes (the residual restricted to the next level)
 struct OpResid {
     static constexpr bool kLocal = false;
@@ -243,7 +364,18 @@ struct MgLevel {
     int n = 0;    // squares (cubes) per side
     int dim = 2;
     double *A = nullptr, *dinv = nullptr, *r = nullptr, *z = nullptr, *t = nullptr, *scratch = nullptr;
+    double *c = nullptr;  // the Chebyshev smoother's increment
     void *A32 = nullptr;  // the packed operator as FP32 hi/lo pair; the cycle may read its heads
+    double gersh = 1.0;   // Gershgorin bound of D^-1 A (element absolute row sums)
+};
+
+// What one V-cycle does on every level above the coarsest.
+struct Cycle {
+    int smooth;
+    double omega;  // damped Jacobi
+    bool f32;      // products read the FP32 heads
+    int smoother;  // FEM_SMOOTH_JACOBI or FEM_SMOOTH_CHEBYSHEV
+    double lower;  // Chebyshev interval [lower g, g]
 };
 
 }  // namespace fem
@@ -331,10 +463,36 @@ int smooth_step(const MgLevel &L, const double *r, const double *z, double *zn, 
     return level_pass(L, OpSmooth{z, r, L.dinv, zn, L.P.mask, omega}, f32, s);
 }
 
+// `steps` Chebyshev steps on level L that continue from cur (first: cur is
+// z = 0 and the first step needs no product); cur / oth swap after every
+// fused pass.
+int cheb_steps(const MgLevel &L, const Cycle &c, const double *r, double *&cur, double *&oth, bool from_zero,
+               hipStream_t s) {
+    const double lam2 = L.gersh, lam1 = c.lower * lam2;
+    const double sigma = (lam1 + lam2) / (lam2 - lam1), w0 = 2.0 / (lam1 + lam2), w = 4.0 / (lam2 - lam1);
+    if (from_zero) {
+        const int64_t n = level_nodes(L);
+        k_cheb_first<<<grid_for(n), kBlock, 0, s>>>(n, w0, L.dinv, r, cur, L.c);
+        FEM_HIP_CHECK(hipGetLastError());
+    } else {
+        if (int rc = level_pass(L, OpCheb{cur, r, L.dinv, oth, L.c, L.P.mask, 0.0, w0}, c.f32, s)) return rc;
+        std::swap(cur, oth);
+    }
+    double rho = 1.0 / sigma;
+    for (int k = 1; k < c.smooth; ++k) {
+        const double ck = 1.0 / (2.0 * sigma - rho);  // C_k / C_{k+1}
+        if (int rc = level_pass(L, OpCheb{cur, r, L.dinv, oth, L.c, L.P.mask, rho * ck, w * ck}, c.f32, s))
+            return rc;
+        std::swap(cur, oth);
+        rho = ck;
+    }
+    return 0;
+}
+
 // The smoothing steps alternate between z and the level's t, starting in t
 // so that the 2 smooth - 1 fused steps end in z; the restricted residual
 // r - A z goes to whichever of the two does not hold the iterate.
-int vcycle(fem_mg *mg, size_t l, const double *r, double *z, int smooth, double omega, bool f32, hipStream_t s) {
+int vcycle(fem_mg *mg, size_t l, const double *r, double *z, const Cycle &c, hipStream_t s) {
     MgLevel &L = mg->lv[l];
     const int64_t n = level_nodes(L);
     const int gv = grid_for(n);
@@ -343,23 +501,87 @@ int vcycle(fem_mg *mg, size_t l, const double *r, double *z, int smooth, double 
         FEM_HIP_CHECK(hipGetLastError());
         return 0;
     }
+    const bool cheb = c.smoother == FEM_SMOOTH_CHEBYSHEV;
     double *cur = L.t, *oth = z;
-    k_smooth<<<gv, kBlock, 0, s>>>(n, omega, L.dinv, r, cur, 1);
-    for (int k = 1; k < smooth; ++k) {
-        if (int rc = smooth_step(L, r, cur, oth, omega, f32, s)) return rc;
-        std::swap(cur, oth);
+    if (cheb) {
+        if (int rc = cheb_steps(L, c, r, cur, oth, true, s)) return rc;
+    } else {
+        k_smooth<<<gv, kBlock, 0, s>>>(n, c.omega, L.dinv, r, cur, 1);
+        for (int k = 1; k < c.smooth; ++k) {
+            if (int rc = smooth_step(L, r, cur, oth, c.omega, c.f32, s)) return rc;
+            std::swap(cur, oth);
+        }
     }
-    if (int rc = level_pass(L, OpResid{cur, r, oth, L.P.mask}, f32, s)) return rc;
+    if (int rc = level_pass(L, OpResid{cur, r, oth, L.P.mask}, c.f32, s)) return rc;
     MgLevel &C = mg->lv[l + 1];
     if (int rc = restrict_to(C, oth, C.r, s)) return rc;
-    if (int rc = vcycle(mg, l + 1, C.r, C.z, smooth, omega, f32, s)) return rc;
+    if (int rc = vcycle(mg, l + 1, C.r, C.z, c, s)) return rc;
     if (int rc = prolong_add(L, C, C.z, cur, s)) return rc;
-    for (int k = 0; k < smooth; ++k) {
-        if (int rc = smooth_step(L, r, cur, oth, omega, f32, s)) return rc;
-        std::swap(cur, oth);
+    if (cheb) {
+        if (int rc = cheb_steps(L, c, r, cur, oth, false, s)) return rc;
+    } else {
+        for (int k = 0; k < c.smooth; ++k) {
+            if (int rc = smooth_step(L, r, cur, oth, c.omega, c.f32, s)) return rc;
+            std::swap(cur, oth);
+        }
     }
     if (cur != z) return set_error(FEM_EINVAL, "internal error: smoothing ended outside z");
     FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+// Options -> the cycle; FEM_EINVAL for parameters outside their ranges.
+int cycle_from(const fem_mg_opts *o, Cycle &c) {
+    if (o->smooth < 1 || o->smooth > 64) return set_error(FEM_EINVAL, "smooth must be in [1, 64]");
+    if (o->cycle_dtype != FEM_F64 && o->cycle_dtype != FEM_F32)
+        return set_error(FEM_EINVAL, "cycle_dtype: FEM_F64 or FEM_F32");
+    if (o->smoother == FEM_SMOOTH_JACOBI) {
+        if (!(o->omega > 0.0 && o->omega < 2.0)) return set_error(FEM_EINVAL, "omega must be in (0, 2)");
+    } else if (o->smoother == FEM_SMOOTH_CHEBYSHEV) {
+        if (!(o->cheb_lower > 0.0 && o->cheb_lower < 1.0)) return set_error(FEM_EINVAL, "cheb_lower must be in (0, 1)");
+    } else {
+        return set_error(FEM_EINVAL, "smoother: FEM_SMOOTH_JACOBI or FEM_SMOOTH_CHEBYSHEV");
+    }
+    c = Cycle{o->smooth, o->omega, o->cycle_dtype == FEM_F32, o->smoother, o->cheb_lower};
+    return 0;
+}
+
+// g of level L: one element pass of |A_e| over the all-ones vector into the
+// level's t, then the maximum of D^-1 times it over free nodes (a level
+// without free nodes keeps g = 1: its smoothing is zero either way).
+int level_gersh(MgLevel &L, double *part, hipStream_t s) {
+    const int64_t n = level_nodes(L);
+    const DevPlan &P = L.P;
+    const size_t lds = P.nb == 4 ? chunk_lds_bytes<4, double>(P.E) : chunk_lds_bytes<3, double>(P.E);
+    const ChunkGrid cg = chunk_grid(P.n_chunks, lds);
+    const OpAbsRow op{L.t};
+    int rc = dispatch_ept(P.E, [&](auto ept) -> int {
+        constexpr int EPT = decltype(ept)::value;
+        if (P.nb == 4) {
+            LdAbs<4> ld{{L.A, P.n_elems}};
+            k_chunk_main<4, EPT, kBlock, double, LdAbs<4>, OpAbsRow, false>
+                <<<cg.grid, kBlock, lds, s>>>(P, ld, op, L.scratch, cg.xcd);
+        } else {
+            LdAbs<3> ld{{L.A, P.n_elems}};
+            k_chunk_main<3, EPT, kBlock, double, LdAbs<3>, OpAbsRow, false>
+                <<<cg.grid, kBlock, lds, s>>>(P, ld, op, L.scratch, cg.xcd);
+        }
+        return 0;
+    });
+    if (rc) return rc;
+    FEM_HIP_CHECK(hipGetLastError());
+    if (P.n_shared > 0) {
+        k_chunk_fixup<kFixBlock, double, OpAbsRow><<<fixup_grid(P.n_shared), kFixBlock, 0, s>>>(P, op, L.scratch, 0);
+        FEM_HIP_CHECK(hipGetLastError());
+    }
+    const int g = grid_for(n);
+    k_gersh<<<g, kBlock, 0, s>>>(n, L.t, L.dinv, L.P.mask, part);
+    FEM_HIP_CHECK(hipGetLastError());
+    std::vector<double> h(g);
+    FEM_HIP_CHECK(hipMemcpyAsync(h.data(), part, g * sizeof(double), hipMemcpyDeviceToHost, s));
+    FEM_HIP_CHECK(hipStreamSynchronize(s));
+    const double m = *std::max_element(h.begin(), h.end());
+    L.gersh = m > 0.0 ? m : 1.0;
     return 0;
 }
 
@@ -396,6 +618,8 @@ void fem_mg_opts_default(fem_mg_opts *o) {
     o->omega = 2.0 / 3.0;
     o->max_replace = 4;
     o->cycle_dtype = FEM_F64;
+    o->smoother = FEM_SMOOTH_JACOBI;
+    o->cheb_lower = 0.3;
 }
 
 int fem_mg_create(int levels, const fem_plan *const *plans, const int *grid_n, int dtype, const void *const *K,
@@ -437,7 +661,7 @@ int fem_mg_create(int levels, const fem_plan *const *plans, const int *grid_n, i
         return o;
     };
     std::vector<size_t> oA(levels), oA32(levels), od(levels), odi(levels), or_(levels), oz(levels), ot(levels),
-        osc(levels);
+        oc(levels), osc(levels);
     for (int l = 0; l < levels; ++l) {
         mg->lv[l].P = fem::plan_device(plans[l]);
         mg->lv[l].n = grid_n[l];
@@ -451,6 +675,7 @@ int fem_mg_create(int levels, const fem_plan *const *plans, const int *grid_n, i
         or_[l] = take(n * 8);
         oz[l] = take(n * 8);
         ot[l] = take(n * 8);
+        oc[l] = take(n * 8);
         osc[l] = take(std::max<int64_t>(P.n_partials, 1) * 8);
     }
     const int64_t n0 = mg->lv[0].P.n_nodes;
@@ -471,6 +696,7 @@ int fem_mg_create(int levels, const fem_plan *const *plans, const int *grid_n, i
         L.r = reinterpret_cast<double *>(b + or_[l]);
         L.z = reinterpret_cast<double *>(b + oz[l]);
         L.t = reinterpret_cast<double *>(b + ot[l]);
+        L.c = reinterpret_cast<double *>(b + oc[l]);
         L.scratch = reinterpret_cast<double *>(b + osc[l]);
     }
     mg->Ainv = reinterpret_cast<double *>(b + oinv);
@@ -507,6 +733,8 @@ int fem_mg_create(int levels, const fem_plan *const *plans, const int *grid_n, i
         return fail(set_error(FEM_EHIP, "setup of the multigrid levels failed"));
     }
     if (bad) return fail(set_error(FEM_ESINGULAR, "a free node has a non-positive diagonal entry"));
+    for (int l = 0; l < levels && !rc; ++l) rc = fem::level_gersh(mg->lv[l], mg->part, s);
+    if (rc) return fail(rc);
     // coarsest level: columns of the masked operator, Dirichlet rows / columns identity
     fem::MgLevel &C = mg->lv[levels - 1];
     for (int j = 0; j < nc && !rc; ++j) {
@@ -551,16 +779,23 @@ int fem_mg_galerkin_apply(fem_mg *mg, int level, const double *d_zc, double *d_o
     return fem::mg_galerkin_apply(mg, level, d_zc, d_out, reinterpret_cast<hipStream_t>(stream));
 }
 
-int fem_mg_vcycle(fem_mg *mg, int smooth, double omega, int cycle_dtype, const double *d_r, double *d_z,
-                  void *stream) {
+int fem_mg_vcycle(fem_mg *mg, const fem_mg_opts *opts, const double *d_r, double *d_z, void *stream) {
     using fem::set_error;
     fem::last_error().clear();
-    if (!mg || !d_r || !d_z) return set_error(FEM_EINVAL, "NULL argument");
+    if (!mg || !opts || !d_r || !d_z) return set_error(FEM_EINVAL, "NULL argument");
     if (d_r == d_z) return set_error(FEM_EINVAL, "r and z must not alias");
-    if (smooth < 1 || smooth > 64 || !(omega > 0.0 && omega < 2.0))
-        return set_error(FEM_EINVAL, "bad smoothing parameters");
-    if (cycle_dtype != FEM_F64 && cycle_dtype != FEM_F32) return set_error(FEM_EINVAL, "cycle_dtype: FEM_F64 or FEM_F32");
-    return fem::vcycle(mg, 0, d_r, d_z, smooth, omega, cycle_dtype == FEM_F32, reinterpret_cast<hipStream_t>(stream));
+    fem::Cycle c{};
+    if (int rc = fem::cycle_from(opts, c)) return rc;
+    return fem::vcycle(mg, 0, d_r, d_z, c, reinterpret_cast<hipStream_t>(stream));
+}
+
+int fem_mg_level_bound(const fem_mg *mg, int level, double *g) {
+    using fem::set_error;
+    fem::last_error().clear();
+    if (!mg || !g) return set_error(FEM_EINVAL, "NULL argument");
+    if (level < 0 || level >= (int)mg->lv.size()) return set_error(FEM_EINVAL, "bad level");
+    *g = mg->lv[level].gersh;
+    return FEM_OK;
 }
 
 int fem_mg_solve(fem_mg *mg, const fem_mg_opts *o, const double *d_b, double *d_x, fem_fcg_info *info, void *stream) {
@@ -570,10 +805,10 @@ int fem_mg_solve(fem_mg *mg, const fem_mg_opts *o, const double *d_b, double *d_
     if (!mg || !o || !info || !d_b || !d_x) return set_error(FEM_EINVAL, "NULL argument");
     std::memset(info, 0, sizeof(*info));
     info->fell_back = -1;
-    if (!(o->rtol > 0.0 && o->rtol < 1.0) || o->max_iter < 1 || o->smooth < 1 || o->smooth > 64 ||
-        !(o->omega > 0.0 && o->omega < 2.0) || o->max_replace < 0 ||
-        (o->cycle_dtype != FEM_F64 && o->cycle_dtype != FEM_F32))
+    if (!(o->rtol > 0.0 && o->rtol < 1.0) || o->max_iter < 1 || o->max_replace < 0)
         return set_error(FEM_EINVAL, "bad multigrid options");
+    Cycle cyc{};
+    if (int rc = cycle_from(o, cyc)) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     MgLevel &F = mg->lv[0];
     const DevPlan &P = F.P;
@@ -618,7 +853,7 @@ int fem_mg_solve(fem_mg *mg, const fem_mg_opts *o, const double *d_b, double *d_
     bool restart = true;
     double pq_prev = 1.0;
     for (int it = 0; it < o->max_iter; ++it) {
-        if (int rc = vcycle(mg, 0, r, z, o->smooth, o->omega, o->cycle_dtype == FEM_F32, s)) return finish(rc);
+        if (int rc = vcycle(mg, 0, r, z, cyc, s)) return finish(rc);
         info->precond_calls += 1;
         k_dots<3><<<gv, kBlock, 0, s>>>(n, mg->ptrs, mg->ptrs + 3, mg->part);  // z.r, z.p, z.q
         k_dots_fin<<<1, kBlock, 0, s>>>(mg->part, gv, 3, mg->sums);

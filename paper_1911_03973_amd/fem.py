@@ -25,6 +25,7 @@ FEM_OK, FEM_EINVAL, FEM_EHIP, FEM_ENOCONV, FEM_ESINGULAR, FEM_EBREAKDOWN, FEM_EN
 F64, F32, F32X2 = 0, 1, 2
 MFREE = 3  # matrix-free: K_e, M_e rebuilt from the coordinates in every pass
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
+SMOOTH_JACOBI, SMOOTH_CHEBYSHEV = 0, 1  # multigrid smoothers
 
 _STATUS = {
     FEM_EINVAL: "FEM_EINVAL",
@@ -125,7 +126,8 @@ RICHARDSON, CHEBYSHEV2, CHEBYSHEV3, CHEBYSHEV3_LISTING = 0, 1, 2, 3
 class MgOpts(ctypes.Structure):
     _fields_ = [
         ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int), ("smooth", ctypes.c_int), ("omega", ctypes.c_double),
-        ("max_replace", ctypes.c_int), ("cycle_dtype", ctypes.c_int),
+        ("max_replace", ctypes.c_int), ("cycle_dtype", ctypes.c_int), ("smoother", ctypes.c_int),
+        ("cheb_lower", ctypes.c_double),
     ]
 
 
@@ -165,7 +167,8 @@ _SIGS = {
     "fem_mg_destroy": [_vp],
     "fem_mg_solve": [_vp, ctypes.POINTER(MgOpts), _vp, _vp, ctypes.POINTER(FcgInfo), _vp],
     "fem_mg_galerkin_apply": [_vp, _int, _vp, _vp, _vp],
-    "fem_mg_vcycle": [_vp, _int, _dbl, _int, _vp, _vp, _vp],
+    "fem_mg_vcycle": [_vp, ctypes.POINTER(MgOpts), _vp, _vp, _vp],
+    "fem_mg_level_bound": [_vp, _int, ctypes.POINTER(_dbl)],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -691,16 +694,24 @@ class MG:
                                  _stream(stream)), allow=allow)
         return {k: getattr(info, k) for k, _ in info._fields_}
 
-    def vcycle(self, r, smooth=2, omega=2.0 / 3.0, z=None, cycle_dtype=F64, stream=None):
+    def vcycle(self, r, smooth=2, omega=2.0 / 3.0, z=None, cycle_dtype=F64, stream=None, smoother=SMOOTH_JACOBI,
+               cheb_lower=0.3):
         """z = B r, one V-cycle on the finest level."""
         n = self.plans[0].n_nodes
         _need(r, torch.float64, n, "r")
         if z is None:
             z = torch.empty(n, dtype=torch.float64, device="cuda")
         _need(z, torch.float64, n, "z")
-        _check(_lib.fem_mg_vcycle(self.handle, int(smooth), float(omega), int(cycle_dtype), _ptr(r), _ptr(z),
-                                  _stream(stream)))
+        o = mg_opts(smooth=int(smooth), omega=float(omega), cycle_dtype=int(cycle_dtype), smoother=int(smoother),
+                    cheb_lower=float(cheb_lower))
+        _check(_lib.fem_mg_vcycle(self.handle, ctypes.byref(o), _ptr(r), _ptr(z), _stream(stream)))
         return z
+
+    def level_bound(self, level):
+        """Gershgorin bound of D^-1 A on a level (the Chebyshev interval's top)."""
+        g = ctypes.c_double()
+        _check(_lib.fem_mg_level_bound(self.handle, int(level), ctypes.byref(g)))
+        return g.value
 
     def galerkin_apply(self, level, zc, stream=None):
         _need(zc, torch.float64, self.plans[level + 1].n_nodes, "zc")

@@ -213,3 +213,102 @@ def test_mg_rejects_mixed_dimensions():
     m3 = inputs.cube_mesh(4)
     with pytest.raises(fem.FemError):
         fem.MG.from_meshes([m2, m3], [inputs.boundary_nodes(m2), inputs.boundary_nodes(m3)], 0.0)
+
+
+# ---- Chebyshev smoothing ----
+
+def test_level_bounds_match_oracle():
+    """g of every level (one |A_e| element pass at setup) against the oracle's
+    element absolute row sums; on the uniform square mesh at nu = 0 it is
+    exactly the 5-point stencil's 2."""
+    meshes, nds, mg = _hierarchy(64, 0.2, "x2=0", 0.5, coarsest=8, seed=2)
+    levels, _ = omg.hierarchy(meshes, nds, 0.5)
+    for l, L in enumerate(levels):
+        assert abs(mg.level_bound(l) - L.gersh) <= 1e-12 * L.gersh, (l, mg.level_bound(l), L.gersh)
+    meshes3, nds3, mg3 = _hierarchy3(16, 0.1, "all", 1.0, coarsest=4, seed=3)
+    levels3, _ = omg.hierarchy(meshes3, nds3, 1.0)
+    for l, L in enumerate(levels3):
+        assert abs(mg3.level_bound(l) - L.gersh) <= 1e-12 * L.gersh, (l, mg3.level_bound(l), L.gersh)
+    _, _, mgu = _hierarchy(32, 0.0, "all", 0.0, coarsest=8)
+    assert all(abs(mgu.level_bound(l) - 2.0) <= 1e-13 for l in range(3))
+    with pytest.raises(fem.FemError):
+        mgu.level_bound(3)
+
+
+@pytest.mark.parametrize("dim,n,coarsest,jitter,which,nu,smooth,lower", [
+    (2, 16, 8, 0.0, "all", 0.0, 1, 0.3),      # two levels; one step = Jacobi with 1/theta
+    (2, 32, 8, 0.0, "all", 0.0, 2, 0.3),
+    (2, 64, 16, 0.2, "x2=0", 0.5, 3, 0.2),
+    (2, 64, 8, 0.1, "all", 3.0, 2, 0.3),      # four levels
+    (2, 200, 25, 0.2, "x2=0", 1.0, 2, 0.3),   # odd coarsest grid, ragged tail
+    (3, 8, 2, 0.0, "all", 0.0, 2, 0.3),
+    (3, 16, 4, 0.1, "all", 1.0, 3, 0.25),
+])
+def test_chebyshev_vcycle_matches_oracle(dim, n, coarsest, jitter, which, nu, smooth, lower):
+    """One V-cycle with Chebyshev smoothing against the oracle's (its own g,
+    recurrence in the paper's three-term form, sparse P, dense coarsest
+    solve); tolerance as for the Jacobi cycle: the steps are linear maps of
+    norm O(1) and the two g agree to rounding."""
+    print(f"cheb vcycle dim={dim} n={n} coarsest={coarsest} nu={nu} smooth={smooth} lower={lower}", flush=True)
+    if dim == 2:
+        meshes, nds, mg = _hierarchy(n, jitter, which, nu, coarsest=coarsest, seed=n)
+    else:
+        meshes, nds, mg = _hierarchy3(n, jitter, which, nu, coarsest, seed=n)
+    levels, Ps = omg.hierarchy(meshes, nds, nu)
+    r = np.random.default_rng(n + 3).standard_normal(meshes[0].n_nodes)
+    got = mg.vcycle(cuda(r), smooth, 0.0, smoother=fem.SMOOTH_CHEBYSHEV, cheb_lower=lower).cpu().numpy()
+    want = omg.vcycle(levels, Ps, r, smooth, 0.0, smoother="chebyshev", lower=lower)
+    scale = np.abs(want).max()
+    assert np.abs(got - want).max() <= 1e-12 * scale, np.abs(got - want).max() / scale
+    assert np.all(got[nds[0]] == 0.0)
+    # a second call reuses the level increments: same result bit for bit
+    again = mg.vcycle(cuda(r), smooth, 0.0, smoother=fem.SMOOTH_CHEBYSHEV, cheb_lower=lower).cpu().numpy()
+    assert np.array_equal(again, got)
+
+
+def test_chebyshev_vcycle_with_fp32_heads_stays_close_to_oracle():
+    meshes, nds, mg = _hierarchy(128, 0.2, "x2=0", 1.0, coarsest=16, seed=5)
+    levels, Ps = omg.hierarchy(meshes, nds, 1.0)
+    r = np.random.default_rng(5).standard_normal(meshes[0].n_nodes)
+    want = omg.vcycle(levels, Ps, r, 2, 0.0, smoother="chebyshev")
+    got = mg.vcycle(cuda(r), 2, 0.0, cycle_dtype=fem.F32, smoother=fem.SMOOTH_CHEBYSHEV).cpu().numpy()
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print("fp32-head chebyshev cycle rel err", err, flush=True)
+    assert 0.0 < err <= 1e-5
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_mg_fcg_with_chebyshev_smoothing(dim):
+    """MG-FCG with Chebyshev smoothing meets the target by the oracle's
+    residual, in no more iterations than with as many damped-Jacobi steps."""
+    if dim == 2:
+        meshes, nds, mg = _hierarchy(256, 0.2, "x2=0", 1.0, seed=11)
+        prob = Problem(meshes[0], nu=1.0, dirichlet="x2=0", f="sine", seed=12)
+    else:
+        meshes, nds, mg = _hierarchy3(32, 0.1, "all", 10.0, coarsest=4, seed=11)
+        prob = Problem(meshes[0], nu=10.0, dirichlet="all", f="sine", seed=12)
+    its = {}
+    for sm in (fem.SMOOTH_JACOBI, fem.SMOOTH_CHEBYSHEV):
+        x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+        info = mg.solve(fem.mg_opts(rtol=1e-8, smooth=2, smoother=sm), cuda(prob.b), x)
+        assert info["status"] == fem.FEM_OK
+        r = oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, x.cpu().numpy(), prob.mask)
+        r0 = oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, np.zeros(prob.n), prob.mask)
+        assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8
+        its[sm] = info["iters"]
+    print(dim, its, flush=True)
+    assert its[fem.SMOOTH_CHEBYSHEV] <= its[fem.SMOOTH_JACOBI], its
+
+
+def test_chebyshev_options_are_checked():
+    meshes, nds, mg = _hierarchy(32, 0.0, "all", 0.0)
+    r = cuda(np.ones(meshes[0].n_nodes))
+    for smoother, lower in [(2, 0.3), (-1, 0.3), (fem.SMOOTH_CHEBYSHEV, 0.0), (fem.SMOOTH_CHEBYSHEV, 1.0),
+                            (fem.SMOOTH_CHEBYSHEV, float("nan"))]:
+        with pytest.raises(fem.FemError):
+            mg.vcycle(r, 2, 0.5, smoother=smoother, cheb_lower=lower)
+    x = torch.zeros(meshes[0].n_nodes, dtype=torch.float64, device="cuda")
+    with pytest.raises(fem.FemError):
+        mg.solve(fem.mg_opts(smoother=fem.SMOOTH_CHEBYSHEV, cheb_lower=1.5), r, x)
+    # omega is not used by the Chebyshev smoother
+    mg.vcycle(r, 2, 0.0, smoother=fem.SMOOTH_CHEBYSHEV)
