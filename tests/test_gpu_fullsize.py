@@ -13,6 +13,7 @@ import pytest
 import torch
 
 import oracle
+import oracle.mg as omg
 from paper_1911_03973_amd import inputs
 
 from problems import cuda, pair_value, to_soa
@@ -169,10 +170,14 @@ def test_full_size_multigrid_vcycle_and_solve():
     r1, r2 = rng.standard_normal(mesh.n_nodes), rng.standard_normal(mesh.n_nodes)
     r1[nd] = 0.0
     r2[nd] = 0.0
-    z1 = mg.vcycle(cuda(r1)).cpu().numpy()
-    z2 = mg.vcycle(cuda(r2)).cpu().numpy()
-    assert abs(r1 @ z2 - r2 @ z1) <= 1e-12 * np.linalg.norm(r1) * np.linalg.norm(z2)
-    assert r1 @ z1 > 0 and r2 @ z2 > 0
+    for sm in (fem.SMOOTH_JACOBI, fem.SMOOTH_CHEBYSHEV):
+        z1 = mg.vcycle(cuda(r1), smoother=sm).cpu().numpy()
+        z2 = mg.vcycle(cuda(r2), smoother=sm).cpu().numpy()
+        assert abs(r1 @ z2 - r2 @ z1) <= 1e-12 * np.linalg.norm(r1) * np.linalg.norm(z2)
+        assert r1 @ z1 > 0 and r2 @ z2 > 0
+    # the finest level's Gershgorin bound against the oracle's
+    g = omg.Level(mesh, nd, nu).gersh
+    assert abs(mg.level_bound(0) - g) <= 1e-12 * g
     plan = mg.plans[0]
     b = plan.empty_vector()
     fem.assemble_rhs(plan, fem.F64, mg.M[0], cuda(f), b)
@@ -180,8 +185,10 @@ def test_full_size_multigrid_vcycle_and_solve():
     mask = oracle.mask_from_nodes(mesh.n_nodes, nd)
     bo = oracle.rhs(mesh.n_nodes, mesh.elems, M, f)
     r0 = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, bo, np.zeros(mesh.n_nodes), mask)
-    # the library default (FP64 cycle, 2 + 2 steps) and the benchmark's (FP32 heads, 1 + 1)
-    for opts in (fem.mg_opts(rtol=1e-8), fem.mg_opts(rtol=1e-8, smooth=1, cycle_dtype=fem.F32)):
+    # the library default (FP64 cycle, 2 + 2 steps), the benchmark's (FP32 heads, 1 + 1),
+    # and Chebyshev smoothing (FP32 heads, 2 + 2)
+    for opts in (fem.mg_opts(rtol=1e-8), fem.mg_opts(rtol=1e-8, smooth=1, cycle_dtype=fem.F32),
+                 fem.mg_opts(rtol=1e-8, smooth=2, cycle_dtype=fem.F32, smoother=fem.SMOOTH_CHEBYSHEV)):
         x = plan.empty_vector()
         x.zero_()
         info = mg.solve(opts, b, x)
@@ -285,14 +292,15 @@ def test_full_size_multigrid_on_c3():
     plan = mg.plans[0]
     b = plan.empty_vector()
     fem.assemble_rhs(plan, fem.F64, mg.M[0], cuda(f), b)
-    x = plan.empty_vector()
-    x.zero_()
-    info = mg.solve(fem.mg_opts(rtol=1e-8, smooth=1, cycle_dtype=fem.F32), b, x)
-    print("mg c3", info, flush=True)
-    assert info["status"] == fem.FEM_OK and info["iters"] <= 40
     K, M, _ = oracle.local_matrices(mesh.coords, mesh.elems)
     mask = oracle.mask_from_nodes(mesh.n_nodes, nd)
     bo = oracle.rhs(mesh.n_nodes, mesh.elems, M, f)
-    r = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, bo, x.cpu().numpy(), mask)
     r0 = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, bo, np.zeros(mesh.n_nodes), mask)
-    assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8
+    for sm in (fem.SMOOTH_JACOBI, fem.SMOOTH_CHEBYSHEV):
+        x = plan.empty_vector()
+        x.zero_()
+        info = mg.solve(fem.mg_opts(rtol=1e-8, smooth=1, cycle_dtype=fem.F32, smoother=sm), b, x)
+        print("mg c3", sm, info, flush=True)
+        assert info["status"] == fem.FEM_OK and info["iters"] <= 40
+        r = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, bo, x.cpu().numpy(), mask)
+        assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8
