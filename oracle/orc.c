@@ -167,11 +167,11 @@ int orc_residual_alg1(int nb, int64_t n_nodes, int64_t n_elems, const int32_t *e
                       const double *K, const double *M, double nu, const double *be,
                       const double *x, double *r)
 {
-    if (check_elems(nb, n_nodes, n_elems, elems)) return ORC_EINVAL;
+    if (nb > 16 || check_elems(nb, n_nodes, n_elems, elems)) return ORC_EINVAL;
     for (int64_t i = 0; i < n_nodes; ++i) r[i] = 0.0;
     for (int64_t e = 0; e < n_elems; ++e) {
         const int32_t *v = elems + e * nb;
-        double xe[4], re[4];
+        double xe[16], re[16];
         for (int j = 0; j < nb; ++j) xe[j] = x[v[j]];                /* restriction */
         for (int i = 0; i < nb; ++i) {                                /* local residual */
             double s = 0.0;

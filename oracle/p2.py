@@ -16,6 +16,12 @@ phi_j, as in eq. (2) for P1.  The integrals are evaluated by a collapsed
 degree-4 integrands of M, with the affine map of the element; the GPU library
 integrates barycentric monomials in closed form instead.
 
+For tetrahedra (`local_matrices_p2_tet`) the ten functions are
+    phi_k = lambda_k (2 lambda_k - 1)        k = 0..3     (vertices)
+    phi_{4+e} = 4 lambda_u lambda_v          e = (0,1), (0,2), (0,3), (1,2), (1,3), (2,3)
+integrated by the collapsed (Stroud conical product) Gauss rule on the
+reference tetrahedron, exact for the degree-4 mass integrands.
+
 Pins (tests/test_oracle_p2.py): K annihilates constants, the vertex rows of M
 integrate to zero and the midpoint rows to area/3, the discrete solution of a
 problem whose exact solution is quadratic is that quadratic at every node, and
@@ -92,3 +98,64 @@ def local_matrices_p2(coords, elems):
         M[e0:e0 + step] = Mref[None] * jac[:, None, None]
         area[e0:e0 + step] = 0.5 * jac
     return K, M, area
+
+
+TET_EDGES = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
+
+
+def _rule_tet(k=4):
+    """Points (x, y, z) and weights of the collapsed Gauss rule on the reference
+    tetrahedron {x, y, z >= 0, x + y + z <= 1} (weights sum to 1/6): the cube
+    point (u, v, w) maps to (u, v (1 - u), w (1 - u)(1 - v)) with Jacobian
+    (1 - u)^2 (1 - v)."""
+    g, w = np.polynomial.legendre.leggauss(k)
+    g = 0.5 * (g + 1.0)
+    w = 0.5 * w
+    pts, wt = [], []
+    for a in range(k):
+        for b in range(k):
+            for c in range(k):
+                u, v, t = g[a], g[b], g[c]
+                pts.append((u, v * (1.0 - u), t * (1.0 - u) * (1.0 - v)))
+                wt.append(w[a] * w[b] * w[c] * (1.0 - u) ** 2 * (1.0 - v))
+    p = np.array(pts)
+    return p[:, 0], p[:, 1], p[:, 2], np.array(wt)
+
+
+def local_matrices_p2_tet(coords, elems):
+    """K_e, M_e (n_elems, 10, 10) and volume (n_elems,) of straight P2
+    tetrahedra.  coords (n_nodes, 3); elems (n_elems, 10): vertices, then the
+    midpoints of the edges in TET_EDGES order.  Only the vertices enter the
+    (affine) map."""
+    coords = np.asarray(coords, dtype=np.float64)
+    elems = np.asarray(elems, dtype=np.int64)
+    x, y, z, wt = _rule_tet(4)
+    lam = np.stack([1.0 - x - y - z, x, y, z])  # (4, q)
+    nq = wt.size
+    phi = np.empty((10, nq))
+    dphi = np.zeros((10, 4, nq))  # d phi_k / d lambda_a
+    for k in range(4):
+        phi[k] = lam[k] * (2.0 * lam[k] - 1.0)
+        dphi[k, k] = 4.0 * lam[k] - 1.0
+    for e, (u, v) in enumerate(TET_EDGES):
+        phi[4 + e] = 4.0 * lam[u] * lam[v]
+        dphi[4 + e, u] = 4.0 * lam[v]
+        dphi[4 + e, v] = 4.0 * lam[u]
+    ne = elems.shape[0]
+    K = np.empty((ne, 10, 10))
+    M = np.empty((ne, 10, 10))
+    vol = np.empty(ne)
+    Mref = np.einsum("iq,jq,q->ij", phi, phi, wt)  # int over the reference tetrahedron
+    step = 16384
+    for e0 in range(0, ne, step):
+        p = coords[elems[e0:e0 + step, :4]]                                   # (b, 4, 3)
+        B = np.stack([p[:, 1] - p[:, 0], p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]], axis=2)  # columns: edges
+        det = np.linalg.det(B)
+        Binv = np.linalg.inv(B)                                               # rows: grad lambda_1..3
+        gl = np.concatenate([-Binv.sum(axis=1, keepdims=True), Binv], axis=1)  # (b, 4, 3)
+        G = np.einsum("kaq,ead->ekqd", dphi, gl)
+        jac = np.abs(det)
+        K[e0:e0 + step] = np.einsum("eiqd,ejqd,q->eij", G, G, wt) * jac[:, None, None]
+        M[e0:e0 + step] = Mref[None] * jac[:, None, None]
+        vol[e0:e0 + step] = jac / 6.0
+    return K, M, vol

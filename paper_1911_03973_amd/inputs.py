@@ -177,6 +177,44 @@ def square_mesh_p2(n: int, order: str = "morton", jitter: float = 0.0, seed: int
     return Mesh(coords=coords, elems=elems, n=2 * n)
 
 
+def cube_mesh_p2(n: int, order: str = "morton", jitter: float = 0.0, seed: int = 0) -> Mesh:
+    """Quadratic (P2) tetrahedra on the Kuhn mesh of n^3 cubes.
+
+    The nodes are the points of the (2n+1)^3 lattice of half-steps: lattice
+    point (I, J, K) -> (K*(2n+1) + J)*(2n+1) + I; even points are the
+    tetrahedron vertices, the others the midpoints of the lattice edges and of
+    the face and cube diagonals of the split.  Each element lists its vertices
+    [v0, v1, v2, v3] as in :func:`cube_mesh`, then the midpoints of its edges
+    (0,1), (0,2), (0,3), (1,2), (1,3), (2,3).  Jitter moves the interior
+    vertices as in :func:`cube_mesh` (same seed, same draws); midpoints stay at
+    the middle of their (straight) edges.  ``Mesh.n`` is 2n, the lattice size.
+    """
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    base = cube_mesh(n, order=order, jitter=jitter, seed=seed)
+    m, M = n + 1, 2 * n + 1
+    ids = np.arange(base.n_nodes)
+    vi, vj, vk = ids % m, (ids // m) % m, ids // (m * m)
+    lat = ((2 * vk) * M + 2 * vj) * M + 2 * vi  # lattice id of every vertex
+    coords = np.zeros((M ** 3, 3))
+    coords[lat] = base.coords
+    e = base.elems.astype(np.int64)
+    lv = [lat[e[:, a]] for a in range(4)]
+
+    def mid(p, q):  # lattice midpoint of two even lattice points
+        pi, pj, pk = p % M, (p // M) % M, p // (M * M)
+        qi, qj, qk = q % M, (q // M) % M, q // (M * M)
+        return (((pk + qk) // 2) * M + (pj + qj) // 2) * M + (pi + qi) // 2
+
+    mids = []
+    for a, b in ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)):
+        mm = mid(lv[a], lv[b])
+        coords[mm] = 0.5 * (coords[lv[a]] + coords[lv[b]])
+        mids.append(mm)
+    elems = np.stack(lv + mids, axis=1).astype(np.int32)
+    return Mesh(coords=coords, elems=elems, n=2 * n)
+
+
 def square_hierarchy(mesh: Mesh, coarsest: int = 16, order: str = "morton") -> list:
     """The meshes of n, n/2, ..., coarsest squares per side nested in `mesh`
     (a square_mesh of n squares, n / coarsest a power of two): coarse node
