@@ -16,7 +16,7 @@
  *    calls only enqueue work on it and return before it runs, except
  *    fem_plan_create and the solvers, which synchronise `stream` before
  *    returning.
- *  - Layouts (structure of arrays, n_b = dim + 1, or 6 for quadratic triangles):
+ *  - Layouts (structure of arrays, n_b = dim + 1, or 6 / 10 for quadratic triangles / tetrahedra):
  *      coordinates      double [dim][n_nodes]
  *      connectivity     int32  [n_b][n_elems], 0-based node ids
  *      element matrices [n_b*n_b][n_elems]: entry (i,j) of element e at
@@ -97,16 +97,20 @@ int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_c
                     const int32_t *d_conn, const int32_t *d_dirichlet, int64_t n_dirichlet,
                     int chunk_elems, void *stream, fem_plan **out);
 
-/* The same for quadratic (P2) triangles, the higher-order elements of the
- * paper's outlook: dim 2, connectivity int32 [6][n_elems] listing each
- * triangle's vertices, then the midpoints of its edges (0,1), (1,2), (2,0)
- * (straight edges).  Element matrices are [36][n_elems] in the same layouts;
- * fem_build_local_matrices integrates the six quadratic Lagrange functions
- * exactly.  The residual, diagonal, right-hand side and fem_pcg_solve (stored
- * FEM_F64 / FEM_F32X2 / FEM_F32 matrices, FP64 vectors) accept such a plan;
- * the matrix-free operator, the iterations, flexible CG, multigrid and the
- * batched solver return FEM_EINVAL.  chunk_elems: 64 ... 1024 (default 1024). */
-int fem_plan_create_p2(int64_t n_nodes, int64_t n_elems, const double *d_coords, const int32_t *d_conn,
+/* The same for quadratic (P2) elements, the higher-order elements of the
+ * paper's outlook, with straight edges.  dim 2: triangles, connectivity int32
+ * [6][n_elems] listing each triangle's vertices, then the midpoints of its
+ * edges (0,1), (1,2), (2,0); chunk_elems 64 ... 1024 (default 1024).  dim 3:
+ * tetrahedra, connectivity int32 [10][n_elems] listing the vertices, then the
+ * midpoints of the edges (0,1), (0,2), (0,3), (1,2), (1,3), (2,3);
+ * chunk_elems 64 ... 512 (default 512).  Element matrices are [n_b^2][n_elems]
+ * in the same layouts; fem_build_local_matrices integrates the quadratic
+ * Lagrange functions exactly.  The residual, diagonal, right-hand side and
+ * fem_pcg_solve (stored FEM_F64 / FEM_F32X2 / FEM_F32 matrices, FP64 vectors)
+ * accept such a plan; the matrix-free operator, the iterations, flexible CG,
+ * multigrid and the batched solver return FEM_EINVAL.  FEM_EINVAL for dim
+ * other than 2 or 3. */
+int fem_plan_create_p2(int dim, int64_t n_nodes, int64_t n_elems, const double *d_coords, const int32_t *d_conn,
                        const int32_t *d_dirichlet, int64_t n_dirichlet, int chunk_elems, void *stream,
                        fem_plan **out);
 

@@ -159,9 +159,10 @@ int plan_create(int dim, int nb, int64_t n_nodes, int64_t n_elems, const double 
     if (n_dirichlet < 0 || (n_dirichlet > 0 && !d_dirichlet)) return set_error(FEM_EINVAL, "bad Dirichlet list");
     if (chunk_elems == 0) chunk_elems = fem::default_chunk_elems(nb);
     if (!fem::valid_chunk_elems(nb, chunk_elems))
-        return set_error(FEM_EINVAL, nb == 3   ? "chunk_elems must be one of 64, 128, 256, 512, 1024, 1536, 2048"
-                                     : nb == 4 ? "chunk_elems must be one of 64, 128, 256, 512, 1024, 1536"
-                                               : "chunk_elems must be one of 64, 128, 256, 512, 1024");
+        return set_error(FEM_EINVAL, nb == 3    ? "chunk_elems must be one of 64, 128, 256, 512, 1024, 1536, 2048"
+                                     : nb == 4  ? "chunk_elems must be one of 64, 128, 256, 512, 1024, 1536"
+                                     : nb == 6  ? "chunk_elems must be one of 64, 128, 256, 512, 1024"
+                                                : "chunk_elems must be one of 64, 128, 256, 512");
     hipStream_t s = S(stream);
     std::vector<double> coords((size_t)dim * n_nodes);
     std::vector<int32_t> conn((size_t)nb * n_elems);
@@ -289,11 +290,16 @@ int fem_plan_create(int dim, int64_t n_nodes, int64_t n_elems, const double *d_c
                        stream, out);
 }
 
-int fem_plan_create_p2(int64_t n_nodes, int64_t n_elems, const double *d_coords, const int32_t *d_conn,
+int fem_plan_create_p2(int dim, int64_t n_nodes, int64_t n_elems, const double *d_coords, const int32_t *d_conn,
                        const int32_t *d_dirichlet, int64_t n_dirichlet, int chunk_elems, void *stream,
                        fem_plan **out) {
-    return plan_create(2, 6, n_nodes, n_elems, d_coords, d_conn, d_dirichlet, n_dirichlet, chunk_elems, stream,
-                       out);
+    if (dim != 2 && dim != 3) {
+        fem::last_error().clear();
+        if (out) *out = nullptr;
+        return set_error(FEM_EINVAL, "dim must be 2 or 3");
+    }
+    return plan_create(dim, dim == 2 ? 6 : 10, n_nodes, n_elems, d_coords, d_conn, d_dirichlet, n_dirichlet,
+                       chunk_elems, stream, out);
 }
 
 int fem_plan_check_host(int dim, int64_t n_nodes, int64_t n_elems, const double *coords, const int32_t *conn,
@@ -459,7 +465,7 @@ int fem_pcg_solve(const fem_plan *plan_c, const fem_solve_opts *o, const void *d
     if ((!d_K_e && plan->dev.n_elems > 0 && !mf) || !d_b || !d_x) return set_error(FEM_EINVAL, "NULL argument");
     if (o->nu != 0.0 && !d_M_e && !mf) return set_error(FEM_EINVAL, "nu > 0 needs M_e");
     if (mf && o->vectors != 0) return set_error(FEM_EINVAL, "the matrix-free solver keeps FP64 vectors");
-    if (plan->dev.nb == 6 && (mf || o->vectors != 0))
+    if (plan->dev.nb > 4 && (mf || o->vectors != 0))
         return set_error(FEM_EINVAL, "quadratic elements need stored matrices and FP64 vectors");
     if ((const void *)d_x == (const void *)d_b) return set_error(FEM_EINVAL, "x must not alias b");
     if (o->nu == 0.0 && plan->stats.n_dirichlet == 0)
@@ -503,7 +509,7 @@ int fem_iterate(const fem_plan *plan_c, const fem_iter_opts *o, const void *d_K_
     std::memset(info, 0, sizeof(*info));
     if (o->method < FEM_RICHARDSON || o->method > FEM_CHEBYSHEV3_LISTING)
         return set_error(FEM_EINVAL, "unknown iteration");
-    if (plan_c->dev.nb == 6) return set_error(FEM_EINVAL, "the iterations run on linear elements");
+    if (plan_c->dev.nb > 4) return set_error(FEM_EINVAL, "the iterations run on linear elements");
     if (!valid_dtype(o->dtype)) return set_error(FEM_EINVAL, "unknown dtype");
     if (!std::isfinite(o->nu) || o->nu < 0.0) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
     if (!std::isfinite(o->lam1) || !std::isfinite(o->lam2) || !(o->lam1 > 0.0) || !(o->lam2 > o->lam1))

@@ -191,13 +191,14 @@ bool valid_chunk_elems(int nb, int E) {
     return (size_t)nb * E * (8 + 2) <= (size_t)kMaxChunkLds;
 }
 
-int default_chunk_elems(int nb) { return nb == 3 ? 1024 : nb == 4 ? 1536 : 1024; }
+int default_chunk_elems(int nb) { return nb == 3 ? 1024 : nb == 4 ? 1536 : nb == 6 ? 1024 : 512; }
 
 // Quadratic triangles: two elements per thread (their 21 packed values per
 // element leave room for no more; measured at 1024-element chunks: 512
 // threads 117 us per pass, 256 threads 144 us, 1024 threads 124 us).
 int default_block(int nb, int E) {
     if (nb == 6) return E >= 1024 ? 512 : 256;
+    if (nb == 10) return E >= 512 ? 512 : 256;  // one quadratic tetrahedron (55 packed values) per thread
     return E > 1024 ? 512 : 256;
 }
 

@@ -690,13 +690,15 @@ int dispatch_ept(int E, F &&f) {
 }
 
 // Calls f(integral_constant<NB>) for the element sizes the library runs:
-// linear triangles (3), linear tetrahedra (4) and quadratic triangles (6).
+// linear triangles (3), linear tetrahedra (4), quadratic triangles (6) and
+// quadratic tetrahedra (10).
 template <class F>
 int dispatch_nb(int nb, F &&f) {
     switch (nb) {
         case 3: return f(std::integral_constant<int, 3>());
         case 4: return f(std::integral_constant<int, 4>());
         case 6: return f(std::integral_constant<int, 6>());
+        case 10: return f(std::integral_constant<int, 10>());
         default: return set_error(-1, "unsupported element size");
     }
 }

@@ -257,6 +257,171 @@ __global__ __launch_bounds__(kBlock) void k_local_matrices_p2(const double *__re
     }
 }
 
+// Quadratic (P2) tetrahedra: the ten functions phi_k = lambda_k (2 lambda_k - 1)
+// (vertices k = 0..3) and phi_{4+e} = 4 lambda_u lambda_v for the edges
+// e = (0,1), (0,2), (0,3), (1,2), (1,3), (2,3).  As for triangles, the
+// gradients are sum_a c_ka grad(lambda_a) with c_ka linear in lambda, and
+// the tables hold (1/vol) int c_ia c_jb and (1/vol) int phi_i phi_j, from
+// (1/vol) int lambda^alpha = 6 alpha! / (|alpha| + 3)!.
+struct P2TetTables {
+    double S[10][4][10][4];
+    double M[10][10];
+};
+
+// n! for n <= 8 (the largest argument is |alpha| + 3 = 7)
+struct FactTable {
+    double v[9];
+};
+constexpr FactTable fact_table() {
+    FactTable t{};
+    t.v[0] = 1.0;
+    for (int n = 1; n < 9; ++n) t.v[n] = n * t.v[n - 1];
+    return t;
+}
+
+// (1/vol) int over the tetrahedron of lambda_0^a0 .. lambda_3^a3
+constexpr double p2t_mono(const int (&a)[4]) {
+    constexpr FactTable F = fact_table();
+    return 6.0 * F.v[a[0]] * F.v[a[1]] * F.v[a[2]] * F.v[a[3]] / F.v[a[0] + a[1] + a[2] + a[3] + 3];
+}
+
+constexpr P2TetTables p2_tet_tables() {
+    P2TetTables t{};
+    const int eu[6] = {0, 0, 0, 1, 1, 2}, ev[6] = {1, 2, 3, 2, 3, 3};
+    // c_ka = sum_p A[k][a][p] lambda_p + B[k][a]
+    double A[10][4][4] = {};
+    double B[10][4] = {};
+    for (int k = 0; k < 4; ++k) {
+        A[k][k][k] = 4.0;
+        B[k][k] = -1.0;
+    }
+    for (int e = 0; e < 6; ++e) {
+        A[4 + e][eu[e]][ev[e]] = 4.0;
+        A[4 + e][ev[e]][eu[e]] = 4.0;
+    }
+    for (int i = 0; i < 10; ++i)
+        for (int a = 0; a < 4; ++a)
+            for (int j = 0; j < 10; ++j)
+                for (int b = 0; b < 4; ++b) {
+                    double v = B[i][a] * B[j][b];  // (1/vol) int 1 = 1
+                    for (int p = 0; p < 4; ++p) {
+                        int ep[4] = {0, 0, 0, 0};
+                        ep[p] = 1;
+                        v += (A[i][a][p] * B[j][b] + B[i][a] * A[j][b][p]) * p2t_mono(ep);
+                        for (int q = 0; q < 4; ++q) {
+                            int eq[4] = {ep[0], ep[1], ep[2], ep[3]};
+                            eq[q] += 1;
+                            v += A[i][a][p] * A[j][b][q] * p2t_mono(eq);
+                        }
+                    }
+                    t.S[i][a][j][b] = v;
+                }
+    // phi_k as a quadratic form in lambda (sum lambda = 1 turns the linear term into products)
+    double C[10][4][4] = {};
+    for (int k = 0; k < 4; ++k)
+        for (int m = 0; m < 4; ++m) {
+            if (m == k) C[k][k][k] = 1.0;
+            else {
+                C[k][k][m] = -0.5;
+                C[k][m][k] = -0.5;
+            }
+        }
+    for (int e = 0; e < 6; ++e) {
+        C[4 + e][eu[e]][ev[e]] = 2.0;
+        C[4 + e][ev[e]][eu[e]] = 2.0;
+    }
+    for (int i = 0; i < 10; ++i)
+        for (int j = 0; j < 10; ++j) {
+            double v = 0.0;
+            for (int p = 0; p < 4; ++p)
+                for (int q = 0; q < 4; ++q)
+                    for (int r = 0; r < 4; ++r)
+                        for (int u = 0; u < 4; ++u) {
+                            const double c = C[i][p][q] * C[j][r][u];
+                            if (c == 0.0) continue;
+                            int ex[4] = {0, 0, 0, 0};
+                            ex[p] += 1;
+                            ex[q] += 1;
+                            ex[r] += 1;
+                            ex[u] += 1;
+                            v += c * p2t_mono(ex);
+                        }
+            t.M[i][j] = v;
+        }
+    return t;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_local_matrices_p2_tet(const double *__restrict__ coords,
+                                                                  const int32_t *__restrict__ conn,
+                                                                  int64_t n_nodes, int64_t n_elems,
+                                                                  void *__restrict__ K, void *__restrict__ M,
+                                                                  double *__restrict__ vol) {
+    constexpr int NB = 10;
+    constexpr P2TetTables T = p2_tet_tables();
+    const int64_t blk = (int64_t)NB * NB * n_elems;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n_elems;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double p[4][3];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int32_t v = conn[(int64_t)a * n_elems + e];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) p[a][d] = coords[(int64_t)d * n_nodes + v];
+        }
+        double b[3][3];  // b[r][c]: component r of edge vector c
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) b[r][c] = p[c + 1][r] - p[0][r];
+        const double c00 = b[1][1] * b[2][2] - b[1][2] * b[2][1];
+        const double c01 = b[1][2] * b[2][0] - b[1][0] * b[2][2];
+        const double c02 = b[1][0] * b[2][1] - b[1][1] * b[2][0];
+        const double det = b[0][0] * c00 + b[0][1] * c01 + b[0][2] * c02;
+        // rows of B^{-1} are grad lambda_1..3 (adjugate / det); grad lambda_0 = -(their sum)
+        double G[4][3];
+        G[1][0] = c00 / det;
+        G[2][0] = c01 / det;
+        G[3][0] = c02 / det;
+        G[1][1] = (b[0][2] * b[2][1] - b[0][1] * b[2][2]) / det;
+        G[2][1] = (b[0][0] * b[2][2] - b[0][2] * b[2][0]) / det;
+        G[3][1] = (b[0][1] * b[2][0] - b[0][0] * b[2][1]) / det;
+        G[1][2] = (b[0][1] * b[1][2] - b[0][2] * b[1][1]) / det;
+        G[2][2] = (b[0][2] * b[1][0] - b[0][0] * b[1][2]) / det;
+        G[3][2] = (b[0][0] * b[1][1] - b[0][1] * b[1][0]) / det;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) G[0][d] = -(G[1][d] + G[2][d] + G[3][d]);
+        const double ve = fabs(det) / 6.0;
+        if (K) {
+            double g[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) g[a][c] = G[a][0] * G[c][0] + G[a][1] * G[c][1] + G[a][2] * G[c][2];
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            if (T.S[i][a][j][c] != 0.0) v += T.S[i][a][j][c] * g[a][c];
+                    store_entry<KIND>(K, (int64_t)(i * NB + j) * n_elems + e, blk, ve * v);
+                }
+        }
+        if (M) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+                    store_entry<KIND>(M, (int64_t)(i * NB + j) * n_elems + e, blk, ve * T.M[i][j]);
+        }
+        if (vol) vol[e] = ve;
+    }
+}
+
 template <int NB, int KIN, int KOUT>
 __global__ __launch_bounds__(kBlock) void k_combine(const void *__restrict__ K, const void *__restrict__ M,
                                                     double nu, int64_t n_elems, void *__restrict__ A) {
@@ -328,7 +493,13 @@ int launch_local_matrices(const DevPlan &P, int kind, void *K, void *M, double *
     k_local_matrices<D, KND><<<g, kBlock, 0, s>>>(P.coords, P.conn, P.n_nodes, P.n_elems, K, M, vol)
 #define FEM_LM2(KND) \
     k_local_matrices_p2<KND><<<g, kBlock, 0, s>>>(P.coords, P.conn, P.n_nodes, P.n_elems, K, M, vol)
-    if (P.nb == 6) {
+#define FEM_LM3(KND) \
+    k_local_matrices_p2_tet<KND><<<g, kBlock, 0, s>>>(P.coords, P.conn, P.n_nodes, P.n_elems, K, M, vol)
+    if (P.nb == 10) {
+        if (kind == MAT_F64) FEM_LM3(MAT_F64);
+        else if (kind == MAT_F32) FEM_LM3(MAT_F32);
+        else FEM_LM3(MAT_F32X2);
+    } else if (P.nb == 6) {
         if (kind == MAT_F64) FEM_LM2(MAT_F64);
         else if (kind == MAT_F32) FEM_LM2(MAT_F32);
         else FEM_LM2(MAT_F32X2);
@@ -343,6 +514,7 @@ int launch_local_matrices(const DevPlan &P, int kind, void *K, void *M, double *
     }
 #undef FEM_LM
 #undef FEM_LM2
+#undef FEM_LM3
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
@@ -365,7 +537,8 @@ int launch_combine(const DevPlan &P, int kin, const void *K, const void *M, doub
     } while (0)
     if (P.nb == 3) FEM_CB_IN(3);
     else if (P.nb == 4) FEM_CB_IN(4);
-    else FEM_CB_IN(6);
+    else if (P.nb == 6) FEM_CB_IN(6);
+    else FEM_CB_IN(10);
 #undef FEM_CB_IN
 #undef FEM_CB_OUT
 #undef FEM_CB
@@ -390,7 +563,8 @@ int launch_pack(const DevPlan &P, int kin, const void *K, const void *M, double 
     } while (0)
     if (P.nb == 3) FEM_PK_IN(3);
     else if (P.nb == 4) FEM_PK_IN(4);
-    else FEM_PK_IN(6);
+    else if (P.nb == 6) FEM_PK_IN(6);
+    else FEM_PK_IN(10);
 #undef FEM_PK_IN
 #undef FEM_PK_OUT
 #undef FEM_PK

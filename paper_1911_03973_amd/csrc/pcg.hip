@@ -593,6 +593,16 @@ int solve_pcg(const DevPlan &P, SolverWork &w, int dtype, int vec64, int block, 
             }
             return set_error(FEM_EINVAL, "chunk size too large for quadratic triangles");
         }
+        if (P.nb == 10) {  // quadratic tetrahedra: as quadratic triangles
+            if constexpr (EPT * BS <= 512) {
+                if (mf || v32) return set_error(FEM_EINVAL, "quadratic elements need stored matrices and FP64 vectors");
+                if (!mixed) return cg_run<10, EPT, BS, MAT_F64, double>(P, w, pk_kind, nu, b, x, rtol, max_iter, dl,
+                                                                       outer_cap, check_every, profile, info, s);
+                return cg_run<10, EPT, BS, MAT_F32, double>(P, w, pk_kind, nu, b, x, rtol, max_iter, dl, outer_cap,
+                                                            check_every, profile, info, s);
+            }
+            return set_error(FEM_EINVAL, "chunk size too large for quadratic tetrahedra");
+        }
         if constexpr (EPT * BS <= 1536 || (EPT <= 2 && BS == 1024)) {
             if (mf) return cg_run<4, EPT, BS, MAT_MF, double>(P, w, pk_kind, nu, b, x, rtol, max_iter, dl, outer_cap,
                                                              check_every, profile, info, s);

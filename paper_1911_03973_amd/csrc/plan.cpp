@@ -53,8 +53,8 @@ void parallel_for(int64_t n, F &&f) {
 int build_host_plan(int dim, int nb, int64_t n_nodes, int64_t n_elems, const double *coords,
                     const int32_t *conn, const int32_t *dirichlet, int64_t n_dir, int chunk_elems,
                     HostPlan &P, std::string &err) {
-    if (nb != dim + 1 && !(dim == 2 && nb == 6)) {
-        err = "elements must be linear simplices or quadratic triangles";
+    if (nb != dim + 1 && !(dim == 2 && nb == 6) && !(dim == 3 && nb == 10)) {
+        err = "elements must be linear or quadratic simplices";
         return -1;
     }
     P = HostPlan();
@@ -70,7 +70,7 @@ int build_host_plan(int dim, int nb, int64_t n_nodes, int64_t n_elems, const dou
     parallel_for(P.n_chunks, [&](int64_t c) {
         int64_t e0 = c * chunk_elems, e1 = std::min<int64_t>(n_elems, e0 + chunk_elems);
         for (int64_t e = e0; e < e1 && !bad[c]; ++e) {
-            int32_t v[6];
+            int32_t v[10];
             for (int a = 0; a < nb; ++a) {
                 v[a] = conn[(int64_t)a * n_elems + e];
                 if (v[a] < 0 || v[a] >= n_nodes) { bad[c] = 1; break; }

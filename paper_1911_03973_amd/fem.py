@@ -134,7 +134,7 @@ class MgOpts(ctypes.Structure):
 _vp, _i64, _int, _dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
 _SIGS = {
     "fem_plan_create": [_int, _i64, _i64, _vp, _vp, _vp, _i64, _int, _vp, ctypes.POINTER(_vp)],
-    "fem_plan_create_p2": [_i64, _i64, _vp, _vp, _vp, _i64, _int, _vp, ctypes.POINTER(_vp)],
+    "fem_plan_create_p2": [_int, _i64, _i64, _vp, _vp, _vp, _i64, _int, _vp, ctypes.POINTER(_vp)],
     "fem_plan_destroy": [_vp],
     "fem_plan_check_host": [_int, _i64, _i64, _vp, _vp, _vp, _i64, _int, ctypes.POINTER(PlanStats)],
     "fem_plan_get_stats": [_vp, ctypes.POINTER(PlanStats)],
@@ -240,12 +240,13 @@ class Plan:
     """Owns a fem_plan (chunked element -> node index of one mesh)."""
 
     def __init__(self, dim, coords_soa, conn_soa, dirichlet=None, chunk_elems=0, stream=None):
-        """conn_soa (n_b, n_elems): n_b = dim + 1, or 6 for quadratic triangles (dim 2)."""
+        """conn_soa (n_b, n_elems): n_b = dim + 1, or 6 / 10 for quadratic triangles / tetrahedra."""
         n_nodes = coords_soa.shape[1]
         n_elems = conn_soa.shape[1]
         nb = int(conn_soa.shape[0])
-        if nb != dim + 1 and not (dim == 2 and nb == 6):
-            raise ValueError("conn must list dim + 1 nodes (linear) or 6 nodes (quadratic triangles) per element")
+        if nb != dim + 1 and (dim, nb) not in ((2, 6), (3, 10)):
+            raise ValueError("conn must list dim + 1 nodes (linear) or 6 / 10 nodes (quadratic triangles / "
+                             "tetrahedra) per element")
         _need(coords_soa, torch.float64, dim * n_nodes, "coords")
         _need(conn_soa, torch.int32, nb * n_elems, "conn")
         if dirichlet is not None and dirichlet.numel() == 0:
@@ -255,8 +256,8 @@ class Plan:
         h = ctypes.c_void_p()
         nd = 0 if dirichlet is None else dirichlet.numel()
         cp = _ptr(conn_soa) if n_elems else None
-        if nb == 6:
-            _check(_lib.fem_plan_create_p2(n_nodes, n_elems, _ptr(coords_soa), cp, _ptr(dirichlet), nd, chunk_elems,
+        if nb > dim + 1:
+            _check(_lib.fem_plan_create_p2(dim, n_nodes, n_elems, _ptr(coords_soa), cp, _ptr(dirichlet), nd, chunk_elems,
                                            _stream(stream), ctypes.byref(h)))
         else:
             _check(_lib.fem_plan_create(dim, n_nodes, n_elems, _ptr(coords_soa), cp, _ptr(dirichlet), nd, chunk_elems,
