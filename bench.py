@@ -43,6 +43,10 @@ WORKLOADS = {
                name="2D quadratic (P2) triangles on 1024x1024 squares (4198401 nodes, 2097152 triangles), "
                     "jitter 0.2h, nu=1, random-sine f, Dirichlet x2=0; FP32 element matvec + FP64 refinement "
                     "to 1e-8"),
+    "p2t": dict(dim=3, n=64, jitter=0.15, jseed=0, nu=10.0, f="sine", fseed=1, dirichlet="all", dtype="f32x2",
+                order=2,
+                name="3D quadratic (P2) tetrahedra on 64^3 cubes x 6 (2146689 nodes, 1572864 tets), jitter 0.15h, "
+                     "nu=10, random-sine f, full Dirichlet; FP32 element matvec + FP64 refinement to 1e-8"),
     "c3": dict(dim=3, n=160, jitter=0.0, jseed=0, nu=10.0, f="one", fseed=0, dirichlet="all", dtype="f32x2",
                name="3D P1 160^3 cubes x 6 tets (4173281 nodes, 24576000 tets), nu=10, f=1, full Dirichlet; "
                     "FP32 element matvec + FP64 refinement to 1e-8"),
@@ -58,7 +62,9 @@ def make_problem(w):
 
     from paper_1911_03973_amd import inputs
 
-    if w.get("order") == 2:
+    if w.get("order") == 2 and w["dim"] == 3:
+        mesh = inputs.cube_mesh_p2(w["n"], jitter=w["jitter"], seed=w["jseed"])
+    elif w.get("order") == 2:
         mesh = inputs.square_mesh_p2(w["n"], jitter=w["jitter"], seed=w["jseed"])
     elif w["dim"] == 2:
         mesh = inputs.square_mesh(w["n"], jitter=w["jitter"], seed=w["jseed"])
@@ -80,6 +86,10 @@ def cpu_baseline(mesh, w, seconds):
         import oracle.p2
 
         K, M, _ = oracle.p2.local_matrices_p2(mesh.coords, mesh.elems)
+    elif mesh.nb == 10:
+        import oracle.p2
+
+        K, M, _ = oracle.p2.local_matrices_p2_tet(mesh.coords, mesh.elems)
     else:
         K, M, _ = oracle.local_matrices(mesh.coords, mesh.elems)
     t_local = time.perf_counter() - t

@@ -304,3 +304,53 @@ def test_full_size_multigrid_on_c3():
         assert info["status"] == fem.FEM_OK and info["iters"] <= 40
         r = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, bo, x.cpu().numpy(), mask)
         assert np.linalg.norm(r) / np.linalg.norm(r0) <= 1.05e-8
+
+
+def test_full_size_p2_tet_on_sampled_nodes_and_solve():
+    """The P2 tetrahedron benchmark workload (64^3 cubes, 2.1 M nodes, 1.6 M
+    quadratic tetrahedra, FP32 hi/lo storage, the bench's launch
+    configuration): local matrices on sampled elements, b and the residual on
+    sampled nodes against the oracle, and the solve to 1e-8; the oracle's
+    residual of the solution on the sampled nodes equals the library's FP64
+    residual there (the whole-mesh oracle residual takes minutes here)."""
+    import oracle.p2 as op2
+
+    mesh = inputs.cube_mesh_p2(64, jitter=0.15, seed=0)
+    nd = inputs.boundary_nodes(mesh, "all")
+    nu = 10.0
+    f = inputs.random_sine(mesh.coords, 1)
+    rng = np.random.default_rng(45)
+    plan = fem.Plan.from_mesh(mesh, nd)
+    K = plan.empty_matrix(fem.F32X2)
+    M = plan.empty_matrix(fem.F32X2)
+    fem.build_local_matrices(plan, fem.F32X2, K, M, None)
+    b = plan.empty_vector()
+    fem.assemble_rhs(plan, fem.F32X2, M, cuda(f), b)
+    x = rng.standard_normal(mesh.n_nodes)
+    r = plan.empty_vector()
+    fem.element_residual(plan, fem.F32X2, K, M, nu, b, cuda(x), r, mask=True)
+    torch.cuda.synchronize()
+    es = rng.choice(mesh.n_elems, size=SAMPLES, replace=False)
+    Ko, Mo, _ = op2.local_matrices_p2_tet(mesh.coords, mesh.elems[es])
+    assert np.abs(pair_value(K)[:, es] - to_soa(Ko)).max() <= 1e-12 * np.abs(Ko).max()
+    assert np.abs(pair_value(M)[:, es] - to_soa(Mo)).max() <= 1e-12 * np.abs(Mo).max()
+    ns = rng.choice(mesh.n_nodes, size=SAMPLES, replace=False)
+    sub = mesh.elems[_sub_elements(mesh, ns)]
+    Ks, Ms, _ = op2.local_matrices_p2_tet(mesh.coords, sub)
+    bs = oracle.rhs(mesh.n_nodes, sub, Ms, f)
+    mask = oracle.mask_from_nodes(mesh.n_nodes, nd)
+    rs = oracle.residual(mesh.n_nodes, sub, Ks, Ms, nu, bs, x, mask)
+    scale = oracle.residual_scale(mesh.n_nodes, sub, Ks, Ms, nu, bs, x)
+    bg, rg = b.cpu().numpy(), r.cpu().numpy()
+    assert np.abs(bg[ns] - bs[ns]).max() <= 1e-12 * np.abs(bs[ns]).max()
+    assert np.all(np.abs(rg[ns] - rs[ns]) <= 1e-12 * scale[ns] + 1e-300)
+    xs = torch.zeros(mesh.n_nodes, dtype=torch.float64, device="cuda")
+    info = fem.pcg_solve(plan, fem.solve_opts(dtype=fem.F32X2, nu=nu, rtol=1e-8, check_every=64), K, M, b, xs)
+    print("p2 tet", info, flush=True)
+    assert info["status"] == 0 and info["relres"] <= 1e-8
+    fem.element_residual(plan, fem.F32X2, K, M, nu, b, xs, r, mask=True)
+    torch.cuda.synchronize()
+    xsn = xs.cpu().numpy()
+    rs = oracle.residual(mesh.n_nodes, sub, Ks, Ms, nu, bs, xsn, mask)
+    scale = oracle.residual_scale(mesh.n_nodes, sub, Ks, Ms, nu, bs, xsn)
+    assert np.all(np.abs(r.cpu().numpy()[ns] - rs[ns]) <= 1e-12 * scale[ns] + 1e-300)
