@@ -187,3 +187,29 @@ def test_p2_tet_rejects_unsupported_paths():
         fem.element_residual(plan, fem.MFREE, None, None, 1.0, None, b, x)
     with pytest.raises(fem.FemError):
         fem.Plan.from_mesh(mesh, nd, chunk_elems=1024)
+
+
+def test_p2_tet_isolated_node_empty_mesh_and_bad_dim():
+    m = inputs.cube_mesh_p2(2, jitter=0.1, seed=2)
+    mesh = inputs.Mesh(np.vstack([m.coords, [[3.0, 3.0, 3.0]]]), m.elems, m.n)
+    K, M, _ = op2.local_matrices_p2_tet(mesh.coords, mesh.elems)
+    plan = fem.Plan.from_mesh(mesh, None, chunk_elems=64)
+    x = np.random.default_rng(0).standard_normal(mesh.n_nodes)
+    b = np.random.default_rng(1).standard_normal(mesh.n_nodes)
+    r = plan.empty_vector()
+    fem.element_residual(plan, fem.F64, cuda(to_soa(K)), cuda(to_soa(M)), 1.0, cuda(b), cuda(x), r, mask=False)
+    torch.cuda.synchronize()
+    ro = oracle.residual(mesh.n_nodes, mesh.elems, K, M, 1.0, b, x)
+    assert max_rel(r.cpu().numpy(), ro) <= 1e-12
+    assert r[-1].item() == b[-1]  # the isolated node keeps b
+    empty = fem.Plan(3, cuda(m.coords.T), torch.zeros((10, 0), dtype=torch.int32, device="cuda"))
+    r = empty.empty_vector()
+    fem.element_residual(empty, fem.F64, None, None, 0.0, cuda(b[: m.n_nodes]), cuda(x[: m.n_nodes]), r, mask=False)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(r.cpu().numpy(), b[: m.n_nodes])
+    # a 10-node connectivity on 2D coordinates is neither P1 nor P2
+    with pytest.raises(ValueError):
+        fem.Plan(2, cuda(m.coords[:, :2].T), cuda(m.elems.T.astype(np.int32)))
+    h = fem.ctypes.c_void_p()
+    rc = fem.library().fem_plan_create_p2(4, m.n_nodes, m.n_elems, None, None, None, 0, 0, None, fem.ctypes.byref(h))
+    assert rc == fem.FEM_EINVAL and not h.value
