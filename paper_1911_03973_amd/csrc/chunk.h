@@ -617,36 +617,61 @@ __global__ __launch_bounds__(BS) void k_chunk_affine(const DevPlan P, const Ld l
     }
 }
 
-// Shared nodes: one thread per node adds the node's partials in ascending
-// chunk order.  The op's own loads for the node (fixup_load) are issued
-// before the partials are summed, and the partial slots come from one
-// 16-byte record (DevPlan::fix_rec), so a node costs two dependent memory
-// round trips.  Dot-product partials of this kernel go to slot_base + block.
+// Partials of shared node s added in ascending chunk order; the slots come
+// from one 16-byte record (DevPlan::fix_rec), longer lists continue in
+// fix_parts.
+template <class T>
+__device__ __forceinline__ T fix_sum(const DevPlan &P, const T *__restrict__ partial, int64_t s) {
+    T acc = (T)0;
+    if (P.fix_rec) {
+        const int4 rc = reinterpret_cast<const int4 *>(P.fix_rec)[s];
+        if (rc.x >= 0) acc += partial[rc.x];
+        if (rc.y >= 0) acc += partial[rc.y];
+        if (rc.z >= 0) acc += partial[rc.z];
+        if (rc.w >= 0) {
+            acc += partial[rc.w];
+        } else if (rc.w < -1) {
+            const int k1 = P.fix_off[s + 1];
+            for (int k = -2 - rc.w; k < k1; ++k) acc += partial[P.fix_parts[k]];
+        }
+    } else {
+        const int k0 = P.fix_off[s], k1 = P.fix_off[s + 1];
+        for (int k = k0; k < k1; ++k) acc += partial[P.fix_parts[k]];
+    }
+    return acc;
+}
+
+// Ops whose fix-up workgroups start with extra work (OpIter: a share of the
+// element pass's dot partials) define fixup_begin(block, n_blocks).
+template <class Op, class = void>
+struct HasFixupBegin : std::false_type {};
+template <class Op>
+struct HasFixupBegin<Op, std::void_t<decltype(&Op::fixup_begin)>> : std::true_type {};
+
+// Shared nodes: each thread finishes two nodes, BS apart, with the op's own
+// loads (fixup_load) and the partial loads of both issued before either node
+// is stored, so a node costs two dependent memory round trips and every
+// thread has both nodes' loads in flight.  Dot-product partials of this
+// kernel go to slot_base + block.
 template <int BS, class T, class Op>
 __global__ __launch_bounds__(BS) void k_chunk_fixup(const DevPlan P, Op op, const T *__restrict__ partial,
                                                     int slot_base) {
     __shared__ RedBuf<BS> red;
     if (!op.begin()) return;
-    for (int64_t s = (int64_t)blockIdx.x * BS + threadIdx.x; s < P.n_shared; s += (int64_t)gridDim.x * BS) {
-        const int g = Op::kLocal ? -1 : P.fix_nodes[s];
-        const typename Op::Pre pre = op.fixup_load((int)s, g);
-        T acc = (T)0;
-        if (P.fix_rec) {
-            const int4 rc = reinterpret_cast<const int4 *>(P.fix_rec)[s];
-            if (rc.x >= 0) acc += partial[rc.x];
-            if (rc.y >= 0) acc += partial[rc.y];
-            if (rc.z >= 0) acc += partial[rc.z];
-            if (rc.w >= 0) {
-                acc += partial[rc.w];
-            } else if (rc.w < -1) {
-                const int k1 = P.fix_off[s + 1];
-                for (int k = -2 - rc.w; k < k1; ++k) acc += partial[P.fix_parts[k]];
-            }
-        } else {
-            const int k0 = P.fix_off[s], k1 = P.fix_off[s + 1];
-            for (int k = k0; k < k1; ++k) acc += partial[P.fix_parts[k]];
-        }
-        op.fixup_store((int)s, g, pre, acc);
+    if constexpr (HasFixupBegin<Op>::value) op.fixup_begin(blockIdx.x, gridDim.x);
+    const int64_t step = (int64_t)gridDim.x * 2 * BS;
+    for (int64_t sa = (int64_t)blockIdx.x * 2 * BS + threadIdx.x; sa < P.n_shared; sa += step) {
+        const int64_t sb = sa + BS;
+        const bool hb = sb < P.n_shared;
+        const int ga = Op::kLocal ? -1 : P.fix_nodes[sa];
+        const int gb = (Op::kLocal || !hb) ? -1 : P.fix_nodes[sb];
+        const typename Op::Pre pa = op.fixup_load((int)sa, ga);
+        typename Op::Pre pb{};
+        if (hb) pb = op.fixup_load((int)sb, gb);
+        const T aa = fix_sum(P, partial, sa);
+        const T ab = hb ? fix_sum(P, partial, sb) : (T)0;
+        op.fixup_store((int)sa, ga, pa, aa);
+        if (hb) op.fixup_store((int)sb, gb, pb, ab);
     }
     op.template end<BS>(red.v, slot_base + blockIdx.x);
 }
@@ -662,14 +687,14 @@ struct ChunkGrid {
 
 ChunkGrid chunk_grid(int64_t n_chunks, size_t lds, int bs = kBlock);
 
-// Fix-up launches: kFixBlock threads, one shared node each, grid-stride
+// Fix-up launches: kFixBlock threads, two shared nodes each, grid-stride
 // beyond `cap` workgroups.  Passes that leave one dot-product partial per
 // workgroup cap the grid at kFixDotsCap, so that the single-workgroup
 // finalize has few partials to add.
 constexpr int kFixBlock = 256;
 constexpr int kFixDotsCap = 1024;
 inline int fixup_grid(int64_t n_shared, int cap = 16384) {
-    int64_t g = (n_shared + kFixBlock - 1) / kFixBlock;
+    int64_t g = (n_shared + 2 * kFixBlock - 1) / (2 * kFixBlock);
     return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 

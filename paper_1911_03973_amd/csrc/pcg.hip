@@ -92,6 +92,7 @@ struct OpIter {
     const IterState *st;
     double *dots;  // [kDots][npart]
     int npart;
+    int n_main;  // dot slots [0, n_main) of the element pass, folded in by the fix-up
     // per-thread
     int mode;
     double alpha, beta;
@@ -162,6 +163,15 @@ struct OpIter {
     struct Pre {
         VT dv, r0, q0, x0, p0;
     };
+    // fix-up workgroup b of nb starts from the element pass's dot slots
+    // [b per, (b + 1) per): the finalize then adds the fix-up's slots only
+    __device__ __forceinline__ void fixup_begin(int b, int nb) {
+        const int per = (n_main + nb - 1) / nb;
+        const int e = min(n_main, (b + 1) * per);
+        for (int i = b * per + (int)threadIdx.x; i < e; i += (int)blockDim.x)
+#pragma unroll
+            for (int j = 0; j < kDots; ++j) d[j] += dots[(int64_t)j * npart + i];
+    }
     __device__ __forceinline__ Pre fixup_load(int s, int) const { return {sd[s], sr[s], sq[s], sx[s], sp[s]}; }
     __device__ __forceinline__ void fixup_store(int s, int, const Pre &pr, VT acc) {
         const VT dv = pr.dv;
@@ -224,9 +234,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter_x(int64_t n, const int32_t *
     }
 }
 
-// One workgroup: totals of the dot partials, then the scalar recurrence.
+// One workgroup: totals of the dot partials in slots [first, npart), then the
+// scalar recurrence.
 __global__ __launch_bounds__(kBlock) void k_finalize(IterState *st, const double *__restrict__ dots, int npart,
-                                                     double thr2, double rel2) {
+                                                     int first, double thr2, double rel2) {
     __shared__ double red[kDots * (kBlock / kWave)];
     if (st->flag) return;
     // every thread sums a fixed, strided subset of each partial list, four
@@ -234,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(IterState *st, const double
     double t[kDots];
 #pragma unroll
     for (int j = 0; j < kDots; ++j) t[j] = 0.0;
-    int k = threadIdx.x;
+    int k = first + threadIdx.x;
     for (; k + 3 * kBlock < npart; k += 4 * kBlock) {
 #pragma unroll
         for (int j = 0; j < kDots; ++j) {
@@ -435,7 +446,11 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, double nu, const double
     const LdT ld = make_ld();
     VT *sx = xv + nc, *sr = r + nc, *sp = p + nc, *sq = q + nc;
     const VT *sd = dinv + nc;
-    OpIter<VT> op{xv, r, p, q, dinv, sx, sr, sp, sq, sd, w.st, w.dots, npart, 0, 0.0, 0.0, {0, 0, 0, 0, 0, 0, 0}};
+    // with a fix-up, its workgroups fold the element pass's dot partials in
+    // and the finalize reads the fix-up's slots [cg.grid, npart) only
+    const int fin_first = gf ? cg.grid : 0;
+    OpIter<VT> op{xv, r, p, q, dinv, sx, sr, sp, sq, sd, w.st, w.dots, npart, fin_first, 0, 0.0, 0.0,
+                  {0, 0, 0, 0, 0, 0, 0}};
     auto scatter_x = [&]() { k_scatter_x<VT><<<gv, kBlock, 0, s>>>(n, w.perm, xv, x64, fold ? 1 : 0); };
 
     // refresh: finish the pending step, x back to mesh order, true FP64
@@ -483,7 +498,7 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, double nu, const double
                 FEM_HIP_CHECK(hipEventRecord(ev.b[ev.used], s));
                 ev.used++;
             }
-            k_finalize<<<1, kBlock, 0, s>>>(w.st, w.dots, npart, thr2, rel2);
+            k_finalize<<<1, kBlock, 0, s>>>(w.st, w.dots, npart, fin_first, thr2, rel2);
             FEM_HIP_CHECK(hipGetLastError());
             ++calls;
         }
