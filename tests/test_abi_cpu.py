@@ -163,3 +163,23 @@ def test_p2_mesh_lattice_and_midpoints():
     for a, b, mid in ((0, 1, 3), (1, 2, 4), (2, 0, 5)):
         np.testing.assert_allclose(c[e[:, mid]], 0.5 * (c[e[:, a]] + c[e[:, b]]), rtol=0, atol=1e-15)
     assert len(np.unique(e)) == m.n_nodes
+
+
+def test_p2_tet_mesh_lattice_and_midpoints():
+    """P2 tetrahedron nodes are the (2n+1)^3 lattice; each element lists its
+    vertices, then the midpoints of edges (0,1), (0,2), (0,3), (1,2), (1,3),
+    (2,3), at the middle of the (jittered, straight) edges; the vertices are
+    those of the linear Kuhn mesh."""
+    import numpy as np
+
+    from paper_1911_03973_amd import inputs
+
+    m = inputs.cube_mesh_p2(3, jitter=0.2, seed=3)
+    lin = inputs.cube_mesh(3, jitter=0.2, seed=3)
+    assert m.n_nodes == 7 ** 3 and m.n_elems == 6 * 27 and m.nb == 10 and m.n == 6
+    c, e = m.coords, m.elems
+    edges = ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))
+    for k, (a, b) in enumerate(edges):
+        np.testing.assert_allclose(c[e[:, 4 + k]], 0.5 * (c[e[:, a]] + c[e[:, b]]), rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(c[e[:, :4]], lin.coords[lin.elems])
+    assert len(np.unique(e)) == m.n_nodes
