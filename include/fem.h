@@ -123,6 +123,13 @@ int fem_plan_check_host(int dim, int64_t n_nodes, int64_t n_elems, const double 
                         const int32_t *conn, const int32_t *dirichlet, int64_t n_dirichlet,
                         int chunk_elems, fem_plan_stats *out);
 
+/* The same dry run for quadratic elements (conn int32 [6][n_elems] in 2D,
+ * [10][n_elems] in 3D, as fem_plan_create_p2).  FEM_EINVAL for dim other than
+ * 2 or 3. */
+int fem_plan_check_host_p2(int dim, int64_t n_nodes, int64_t n_elems, const double *coords,
+                           const int32_t *conn, const int32_t *dirichlet, int64_t n_dirichlet,
+                           int chunk_elems, fem_plan_stats *out);
+
 /* Free the plan and all device memory it owns.  NULL is accepted. */
 int fem_plan_destroy(fem_plan *plan);
 

@@ -137,6 +137,7 @@ _SIGS = {
     "fem_plan_create_p2": [_int, _i64, _i64, _vp, _vp, _vp, _i64, _int, _vp, ctypes.POINTER(_vp)],
     "fem_plan_destroy": [_vp],
     "fem_plan_check_host": [_int, _i64, _i64, _vp, _vp, _vp, _i64, _int, ctypes.POINTER(PlanStats)],
+    "fem_plan_check_host_p2": [_int, _i64, _i64, _vp, _vp, _vp, _i64, _int, ctypes.POINTER(PlanStats)],
     "fem_plan_get_stats": [_vp, ctypes.POINTER(PlanStats)],
     "fem_build_local_matrices": [_vp, _int, _vp, _vp, _vp, _vp],
     "fem_combine_local": [_vp, _int, _vp, _vp, _dbl, _int, _vp, _vp],
@@ -317,7 +318,8 @@ def plan_check_host(mesh, dirichlet=None, chunk_elems=0):
     conn = np.ascontiguousarray(mesh.elems.T, dtype=np.int32)
     d = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.int32)
     st = PlanStats()
-    _check(_lib.fem_plan_check_host(mesh.dim, coords.shape[1], conn.shape[1], coords.ctypes.data,
+    fn = _lib.fem_plan_check_host_p2 if conn.shape[0] > mesh.dim + 1 else _lib.fem_plan_check_host
+    _check(fn(mesh.dim, coords.shape[1], conn.shape[1], coords.ctypes.data,
                                     conn.ctypes.data if conn.size else None,
                                     None if d is None or d.size == 0 else d.ctypes.data,
                                     0 if d is None else d.size, chunk_elems, ctypes.byref(st)))

@@ -183,3 +183,27 @@ def test_p2_tet_mesh_lattice_and_midpoints():
         np.testing.assert_allclose(c[e[:, 4 + k]], 0.5 * (c[e[:, a]] + c[e[:, b]]), rtol=0, atol=1e-15)
     np.testing.assert_array_equal(c[e[:, :4]], lin.coords[lin.elems])
     assert len(np.unique(e)) == m.n_nodes
+
+
+def test_host_plan_for_quadratic_meshes():
+    """The host dry run of quadratic meshes: 6 or 10 nodes per element, the
+    same chunk bookkeeping as for linear elements, chunk limits of 1024 (P2
+    triangles) and 512 (P2 tetrahedra), and the usual mesh checks."""
+    for mesh, cap in ((inputs.square_mesh_p2(9, jitter=0.2, seed=1), 1024),
+                      (inputs.cube_mesh_p2(3, jitter=0.1, seed=2), 512)):
+        nb = mesh.elems.shape[1]
+        for E in (64, 128):
+            st = fem.plan_check_host(mesh, inputs.boundary_nodes(mesh), chunk_elems=E)
+            assert st["n_b"] == nb and st["n_chunks"] == -(-mesh.n_elems // E)
+            touched = np.zeros(mesh.n_nodes, np.int64)
+            for c in range(st["n_chunks"]):
+                touched[np.unique(mesh.elems[c * E:(c + 1) * E])] += 1
+            assert st["n_local"] == touched.sum()
+            assert st["n_shared"] == (touched != 1).sum()
+        assert fem.plan_check_host(mesh)["chunk_elems"] == cap
+        with pytest.raises(fem.FemError, match="chunk_elems"):
+            fem.plan_check_host(mesh, chunk_elems=2 * cap)
+        rep = inputs.Mesh(mesh.coords, mesh.elems.copy(), mesh.n)
+        rep.elems[1, nb - 1] = rep.elems[1, 0]
+        with pytest.raises(fem.FemError, match="repeats"):
+            fem.plan_check_host(rep)
