@@ -403,29 +403,49 @@ int orc_cheb3(int nb, int64_t n_nodes, int64_t n_elems, const int32_t *elems, co
     return ORC_OK;
 }
 
-/* Three-level Chebyshev in the alpha/beta form of the Section 2.2 listing
- * (kept as a variant: its first beta is (c alpha / 2)^2 with alpha = 1/d). */
+/* The three-level Chebyshev method as the Section 2.2 program runs it.
+ *
+ * The program advances a search direction with a coefficient beta and a step
+ * alpha, and starts its beta recurrence from (c / (2 d))^2 with d = (lam1+lam2)/2,
+ * c = (lam2-lam1)/2.  Eliminating the direction gives a three-term recurrence
+ * for the iterates of exactly the form of eq. (9), with the scaling factors
+ * C_k of eq. (8) -- the Chebyshev polynomials of the first kind T_k at
+ * sigma = d / c -- replaced by those of the second kind, U_k(sigma)
+ * (U_0 = 1, U_1 = 2 sigma, U_{k+1} = 2 sigma U_k - U_{k-1}): the program's
+ * first beta is rho_0^2 with rho_0 = U_0 / U_1, and every later step keeps the
+ * three-term relation.  Its error after k steps is therefore
+ *   e_k = U_k((d - A) / c) / U_k(d / c) e_0,
+ * where eq. (9) gives T_k((d - A) / c) / T_k(d / c) e_0.  The equations are
+ * taken as the method (orc_cheb3); this is the program's variant.
+ *
+ * Here it is written as that three-term recurrence:
+ *   x^1     = x^0 + (2/c) (U_0 / U_1) r_0  = x^0 + r_0 / d,
+ *   x^{k+1} = x^k + (U_{k-1} / U_{k+1}) (x^k - x^{k-1}) + (2/c) (U_k / U_{k+1}) r_k,
+ * with the ratio u_k = U_k / U_{k+1} (u_0 = 1 / (2 sigma),
+ * u_k = 1 / (2 sigma - u_{k-1})) so that nothing overflows; U_{k-1} / U_{k+1}
+ * = u_{k-1} u_k. */
 int orc_cheb3_listing(int nb, int64_t n_nodes, int64_t n_elems, const int32_t *elems,
                       const double *K, const double *M, double nu, const double *b,
                       const uint8_t *mask, double lam1, double lam2, int iters, double *x)
 {
     if (check_elems(nb, n_nodes, n_elems, elems)) return ORC_EINVAL;
-    double *r = malloc(n_nodes * sizeof(double)), *p = malloc(n_nodes * sizeof(double));
-    const double d = 0.5 * (lam2 + lam1), c = 0.5 * (lam2 - lam1);
-    double alpha = 0.0;
-    orc_residual(nb, n_nodes, n_elems, elems, K, M, nu, b, x, mask, r);
+    double *r = malloc(n_nodes * sizeof(double)), *xprev = malloc(n_nodes * sizeof(double));
+    const double c = 0.5 * (lam2 - lam1);
+    const double sigma = (lam1 + lam2) / (lam2 - lam1);
+    double u_prev = 0.0;               /* u_{k-1} */
+    double u = 1.0 / (2.0 * sigma);    /* u_k, starting at u_0 = U_0 / U_1 */
     for (int k = 0; k < iters; ++k) {
-        if (k == 0) {
-            for (int64_t i = 0; i < n_nodes; ++i) p[i] = r[i];
-            alpha = 1.0 / d;
-        } else {
-            const double beta = (c * alpha / 2.0) * (c * alpha / 2.0);
-            for (int64_t i = 0; i < n_nodes; ++i) p[i] = r[i] + beta * p[i];
-            alpha = 1.0 / (d - beta / alpha);
-        }
-        for (int64_t i = 0; i < n_nodes; ++i) x[i] += alpha * p[i];
         orc_residual(nb, n_nodes, n_elems, elems, K, M, nu, b, x, mask, r);
+        const double w_r = (2.0 / c) * u;      /* (2/c) U_k / U_{k+1} */
+        const double w_x = u_prev * u;         /* U_{k-1} / U_{k+1}, 0 at k = 0 */
+        for (int64_t i = 0; i < n_nodes; ++i) {
+            const double xn = x[i] + (k > 0 ? w_x * (x[i] - xprev[i]) : 0.0) + w_r * r[i];
+            xprev[i] = x[i];
+            x[i] = xn;
+        }
+        u_prev = u;
+        u = 1.0 / (2.0 * sigma - u);
     }
-    free(r); free(p);
+    free(r); free(xprev);
     return ORC_OK;
 }

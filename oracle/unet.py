@@ -24,6 +24,8 @@ Flat parameter layout (float, layer by layer, weights then bias):
   upconv    W[ci][a*2 + b][co], output (2y+a, 2x+b) from input (y, x)
   output    w[c], then one bias
 Loss: L = (1/B) sum_b ||y_b - t_b||^2 / ||t_b||^2.
+Optimiser: Adam (Kingma & Ba, ICLR 2015, Algorithm 1) with bias-corrected
+moments, ``adam`` below.
 
 Parity pins (tests/test_oracle_unet.py): every layer type against a library
 routine (scipy.signal.correlate for conv3x3, numpy.kron for the transposed
@@ -283,3 +285,26 @@ def grid_output(y, N, mask=None):
     if mask is not None:
         z[np.asarray(mask, dtype=bool)] = 0.0
     return z
+
+
+def adam(params, grads, lrs, beta1=0.9, beta2=0.999, eps=1e-8, history=False):
+    """Adam steps t = 1, 2, ... on a flat parameter vector (Kingma & Ba, Algorithm 1):
+        m_t = beta1 m_{t-1} + (1 - beta1) g_t,   v_t = beta2 v_{t-1} + (1 - beta2) g_t^2
+        m^_t = m_t / (1 - beta1^t),               v^_t = v_t / (1 - beta2^t)
+        theta_t = theta_{t-1} - lr_t m^_t / (sqrt(v^_t) + eps)
+    from m_0 = v_0 = 0, with grads[t-1] and lrs[t-1] the gradient and learning
+    rate of step t.  Returns theta after the last step, or every theta_t with
+    history=True."""
+    theta = np.array(params, dtype=np.float64)
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    out = []
+    for t, (g, lr) in enumerate(zip(grads, lrs), start=1):
+        g = np.asarray(g, dtype=np.float64)
+        m = beta1 * m + (1.0 - beta1) * g
+        v = beta2 * v + (1.0 - beta2) * g * g
+        mhat = m / (1.0 - beta1 ** t)
+        vhat = v / (1.0 - beta2 ** t)
+        theta = theta - lr * mhat / (np.sqrt(vhat) + eps)
+        out.append(theta.copy())
+    return out if history else theta

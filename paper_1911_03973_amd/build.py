@@ -36,7 +36,6 @@ HIP_FLAGS = [
     "--offload-arch=" + ARCH,
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-ffp-contract=fast",
-    "-munsafe-fp-atomics",
 ]
 
 

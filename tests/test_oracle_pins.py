@@ -376,10 +376,77 @@ def test_two_and_three_level_agree_after_N_steps():
     x2 = oracle.cheb2(n, mesh.elems, K, M, 0.0, b, mask, x0, l1, l2, N, N)
     x3 = oracle.cheb3(n, mesh.elems, K, M, 0.0, b, mask, x0, l1, l2, N)
     np.testing.assert_allclose(x2, x3, atol=1e-12 * np.abs(x3).max())
-    # The printed alpha/beta listing takes a different first beta and so does
+    # The printed alpha/beta program takes a different first beta and so does
     # not reproduce x^N (kept only as a variant).
     x3l = oracle.cheb3_listing(n, mesh.elems, K, M, 0.0, b, mask, x0, l1, l2, N)
     assert np.abs(x3l - x3).max() > 1e-6
+
+
+def _error_components(mesh, K, M, mask, x, u):
+    """Eigenvalues of K_II and the components of the free-node error x - u along its eigenvectors."""
+    free = mask == 0
+    A = dense_from_oracle(mesh, K, M, 0.0)[np.ix_(free, free)]
+    lam, V = np.linalg.eigh(A)
+    return lam, V.T @ (x - u)[free]
+
+
+@pytest.mark.parametrize("kind", ["equations", "program"])
+def test_chebyshev_error_is_the_scaled_chebyshev_polynomial(kind):
+    """After k steps of the three-level method the error along every eigenvector
+    of K_II is P_k(lambda) times its initial component, with
+    P_k = T_k((d - x)/c) / T_k(d/c) for eq. (9) and U_k((d - x)/c) / U_k(d/c)
+    for the alpha/beta program (second kind), d = (l1+l2)/2, c = (l2-l1)/2; the
+    polynomials come from scipy.special, independently of the recurrences."""
+    from scipy import special
+
+    mesh, K, M, b, mask, x0, u, l1, l2 = _section3_problem(17)
+    n = mesh.n_nodes
+    d, c = 0.5 * (l1 + l2), 0.5 * (l2 - l1)
+    lam, c0 = _error_components(mesh, K, M, mask, x0, u)
+    poly = special.eval_chebyt if kind == "equations" else special.eval_chebyu
+    run = oracle.cheb3 if kind == "equations" else oracle.cheb3_listing
+    for k in (1, 2, 3, 5, 8, 20, 40):
+        xk = run(n, mesh.elems, K, M, 0.0, b, mask, x0, l1, l2, k)
+        _, ck = _error_components(mesh, K, M, mask, xk, u)
+        want = poly(k, (d - lam) / c) / poly(k, d / c) * c0
+        assert np.abs(ck - want).max() <= 1e-10 * np.abs(c0).max(), (kind, k)
+    # and the two kinds differ from the second step on
+    x2 = oracle.cheb3_listing(n, mesh.elems, K, M, 0.0, b, mask, x0, l1, l2, 2)
+    _, c2 = _error_components(mesh, K, M, mask, x2, u)
+    first_kind = special.eval_chebyt(2, (d - lam) / c) / special.eval_chebyt(2, d / c) * c0
+    assert np.abs(c2 - first_kind).max() > 1e-3 * np.abs(c0).max()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_residual_scale_bounds_the_residual(dim):
+    """s = |b| + sum_e C_e^T |A_e| |x_e| bounds the residual componentwise,
+    dominates |b| + |A||x| of the assembled matrix (element absolute values are
+    never smaller than those of the sums), and is attained when no term
+    cancels (mass matrix only, x >= 0, b <= 0)."""
+    mesh = inputs.square_mesh(6, jitter=0.2, seed=3) if dim == 2 else inputs.cube_mesh(3, jitter=0.15, seed=3)
+    n = mesh.n_nodes
+    K, M, _ = oracle.local_matrices(mesh.coords, mesh.elems)
+    rng = np.random.default_rng(7)
+    nu = 0.7
+    b = rng.standard_normal(n)
+    x = rng.standard_normal(n)
+    s = oracle.residual_scale(n, mesh.elems, K, M, nu, b, x)
+    r = oracle.residual(n, mesh.elems, K, M, nu, b, x)
+    A = dense_from_oracle(mesh, K, M, nu)
+    assert np.all(s >= np.abs(r) * (1 - 1e-14))
+    assert np.all(s >= (np.abs(b) + np.abs(A) @ np.abs(x)) * (1 - 1e-14))
+    # strictly larger somewhere: the stiffness entries of shared edges cancel in the sum
+    assert np.any(s > (np.abs(b) + np.abs(A) @ np.abs(x)) * (1 + 1e-6))
+    # no cancellation: the mass part alone with x >= 0 and b <= 0 gives r = b - M x = -s
+    Z = np.zeros_like(K)
+    xp, bn = np.abs(x), -np.abs(b)
+    s_m = oracle.residual_scale(n, mesh.elems, Z, M, nu, bn, xp)
+    r_m = oracle.residual(n, mesh.elems, Z, M, nu, bn, xp)
+    np.testing.assert_allclose(s_m, -r_m, rtol=1e-14)
+    np.testing.assert_allclose(s_m, np.abs(bn) + nu * dense_from_oracle(mesh, Z, M, 1.0) @ xp, rtol=1e-13)
+    # b = NULL counts as b = 0
+    np.testing.assert_allclose(oracle.residual_scale(n, mesh.elems, K, M, nu, None, x),
+                               s - np.abs(b), rtol=1e-12, atol=1e-14)
 
 
 def test_richardson_is_chebyshev_with_one_root():
