@@ -410,7 +410,8 @@ typedef struct {
     int max_iter;       /* FCG iterations, plus as many Jacobi-PCG ones after a handover */
     int grid_n;         /* structured grid of (grid_n + 1)^2 nodes (see fem_unet_precondition) */
     double cval;        /* constant second input channel of the network */
-    int stall_iters;    /* hand over to Jacobi-PCG when ||r|| has not halved in this many iterations */
+    int stall_iters;    /* hand over to Jacobi-PCG when ||r|| has not halved in this many
+                           iterations (default 200) */
     int max_replace;    /* true-residual restarts allowed */
     int smooth;         /* 0: z = N(r); k > 0: two-level cycle with the network as
                            coarse correction: k damped-Jacobi steps
@@ -418,8 +419,13 @@ typedef struct {
                            z += s N(r - A z) with s = (n.rz)/(n.A n), then k
                            more Jacobi steps (default 4) */
     double omega;       /* Jacobi damping of the cycle, (0, 2) (default 2/3) */
-    int graph;          /* 1: the network's launches are captured once per solve into a
-                           HIP graph and replayed (default); 0: launched one by one */
+    int graph;          /* 1: one whole iteration (cycle, network and FCG update) is
+                           captured once per solve into a HIP graph and replayed
+                           (default); 0: its kernels are launched one by one */
+    int check_every;    /* iterations between two reads of the device state by the host,
+                           [1, 4096] (default 16); the scalars never leave the device */
+    int cycle_dtype;    /* FEM_F64: the cycle's element passes read the FP64 packed
+                           operator (default); FEM_F32: its FP32 heads */
 } fem_fcg_opts;
 
 typedef struct {
@@ -438,18 +444,32 @@ typedef struct {
 
 void fem_fcg_opts_default(fem_fcg_opts *o);
 
-/* Flexible CG (FCG(1)) for (K + nu M) u = b with the Dirichlet rows masked,
- * preconditioned by the network (net != NULL; the mesh must be the structured
- * 2D grid described at fem_unet_precondition), alone or inside the two-level
- * cycle of opts->smooth, or by Jacobi (net == NULL).
+/* Flexible CG (FCG(1), Notay, SIAM J. Sci. Comput. 22 (2000), with one
+ * previous direction) for (K + nu M) u = b with the Dirichlet rows masked --
+ * the problem statement of Section 1, the operator applied through the
+ * element residual of Section 2 (eq. (4), Algorithm 1) -- preconditioned by
+ * the network (net != NULL; the mesh must be the structured 2D grid described
+ * at fem_unet_precondition), alone or inside the two-level cycle of
+ * opts->smooth, or by Jacobi (net == NULL; linear triangles or tetrahedra).
  * With a network, a non-finite or zero output, p.q <= 0, or stall_iters
- * iterations without halving ||r|| hand the current iterate over to the
- * Jacobi-PCG solver (fem_pcg_solve with opts->dtype), which finishes the
- * solve.  The true FP64 residual decides convergence.  x: x0 on entry
- * (Dirichlet values included), the solution on exit.  Allocates a workspace
- * for the call; synchronises `stream`. */
+ * iterations without halving ||r|| end the FCG phase: the iterate with the
+ * smallest residual seen (x0 if none halved it) goes to the Jacobi-PCG solver
+ * (fem_pcg_solve with opts->dtype), which finishes the solve to the same
+ * absolute target.  The true FP64 residual decides convergence.  x: x0 on
+ * entry (Dirichlet values included), the solution on exit; after
+ * FEM_ENOCONV the last iterate.  Allocates a workspace for the call;
+ * synchronises `stream`. */
 int fem_fcg_solve(const fem_plan *plan, const fem_fcg_opts *opts, fem_unet *net, const void *d_K_e,
                   const void *d_M_e, const double *d_b, double *d_x, fem_fcg_info *info, void *stream);
+
+/* z = B(r) once, B the preconditioner fem_fcg_solve uses with the same
+ * opts and net: the two-level cycle (net, opts->smooth > 0), N(r)
+ * (net, smooth == 0) or D^-1 r (net == NULL); D^-1 is 0 on Dirichlet nodes.
+ * r: [n_nodes] FP64 (a masked residual: 0 on Dirichlet nodes), z: [n_nodes]
+ * FP64, caller-owned, must not alias r.  Validation as fem_fcg_solve.
+ * Allocates a workspace for the call; synchronises `stream`. */
+int fem_fcg_precondition(const fem_plan *plan, const fem_fcg_opts *opts, fem_unet *net, const void *d_K_e,
+                         const void *d_M_e, const double *d_r, double *d_z, void *stream);
 
 /* ---- Geometric multigrid on nested square and cube meshes -----------------
  * The P1 operator's condition number grows like h^-2 (the reason the Section 3

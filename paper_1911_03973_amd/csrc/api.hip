@@ -553,33 +553,35 @@ void fem_fcg_opts_default(fem_fcg_opts *o) {
     o->dtype = FEM_F64;
     o->rtol = 1e-8;
     o->max_iter = 100000;
-    o->stall_iters = 50;
+    o->stall_iters = 200;
     o->max_replace = 8;
     o->smooth = 4;
     o->omega = 2.0 / 3.0;
     o->graph = 1;
+    o->check_every = 16;
+    o->cycle_dtype = FEM_F64;
 }
 
-int fem_fcg_solve(const fem_plan *plan_c, const fem_fcg_opts *o, fem_unet *net, const void *d_K_e,
-                  const void *d_M_e, const double *d_b, double *d_x, fem_fcg_info *info, void *stream) {
-    auto t0 = std::chrono::steady_clock::now();
-    if (int rc = check_plan(plan_c)) return rc;
-    fem_plan *plan = const_cast<fem_plan *>(plan_c);
-    if (!o || !info) return set_error(FEM_EINVAL, "opts and info must not be NULL");
-    std::memset(info, 0, sizeof(*info));
-    info->fell_back = -1;
-    if (plan->dev.nb != 3) return set_error(FEM_EINVAL, "flexible CG with the network runs on linear triangles");
+namespace {
+
+// Validation shared by fem_fcg_solve and fem_fcg_precondition.
+int check_fcg(const fem_plan *plan, const fem_fcg_opts *o, fem_unet *net, const void *d_K_e, const void *d_M_e) {
+    if (net && plan->dev.nb != 3) return set_error(FEM_EINVAL, "flexible CG with the network runs on linear triangles");
+    if (plan->dev.nb != 3 && plan->dev.nb != 4)
+        return set_error(FEM_EINVAL, "flexible CG runs on linear triangles or tetrahedra");
     if (!valid_dtype(o->dtype)) return set_error(FEM_EINVAL, "unknown dtype");
     if (!std::isfinite(o->nu) || o->nu < 0.0) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
     if (!(o->rtol > 0.0) || !(o->rtol < 1.0)) return set_error(FEM_EINVAL, "rtol must be in (0, 1)");
     if (o->max_iter < 1) return set_error(FEM_EINVAL, "max_iter must be >= 1");
     if (o->stall_iters < 1 || o->max_replace < 0) return set_error(FEM_EINVAL, "stall_iters >= 1, max_replace >= 0");
     if (o->graph != 0 && o->graph != 1) return set_error(FEM_EINVAL, "graph must be 0 or 1");
+    if (o->check_every < 1 || o->check_every > 4096) return set_error(FEM_EINVAL, "check_every must be in [1, 4096]");
+    if (o->cycle_dtype != FEM_F64 && o->cycle_dtype != FEM_F32)
+        return set_error(FEM_EINVAL, "cycle_dtype: FEM_F64 or FEM_F32");
     if (o->smooth < 0 || o->smooth > 8 || !(o->omega > 0.0) || !(o->omega < 2.0))
         return set_error(FEM_EINVAL, "smooth must be in [0, 8] and omega in (0, 2)");
-    if ((!d_K_e && plan->dev.n_elems > 0) || !d_b || !d_x) return set_error(FEM_EINVAL, "NULL argument");
+    if (!d_K_e && plan->dev.n_elems > 0) return set_error(FEM_EINVAL, "NULL argument");
     if (o->nu != 0.0 && !d_M_e) return set_error(FEM_EINVAL, "nu > 0 needs M_e");
-    if ((const void *)d_x == (const void *)d_b) return set_error(FEM_EINVAL, "x must not alias b");
     if (o->nu == 0.0 && plan->stats.n_dirichlet == 0)
         return set_error(FEM_ESINGULAR, "nu = 0 needs a Dirichlet part of positive measure");
     if (plan->n_isolated_free > 0)
@@ -590,11 +592,38 @@ int fem_fcg_solve(const fem_plan *plan_c, const fem_fcg_opts *o, fem_unet *net, 
             return set_error(FEM_EINVAL, "the network needs a 2D structured grid of (grid_n + 1)^2 nodes");
         if (!std::isfinite(o->cval)) return set_error(FEM_EINVAL, "cval must be finite");
     }
+    return 0;
+}
+
+}  // namespace
+
+int fem_fcg_precondition(const fem_plan *plan, const fem_fcg_opts *o, fem_unet *net, const void *d_K_e,
+                         const void *d_M_e, const double *d_r, double *d_z, void *stream) {
+    if (int rc = check_plan(plan)) return rc;
+    if (!o) return set_error(FEM_EINVAL, "opts must not be NULL");
+    if (int rc = check_fcg(plan, o, net, d_K_e, d_M_e)) return rc;
+    if (!d_r || !d_z) return set_error(FEM_EINVAL, "NULL argument");
+    if ((const void *)d_r == (const void *)d_z) return set_error(FEM_EINVAL, "z must not alias r");
+    return fem::fcg_precondition(plan->dev, o->dtype, d_K_e, o->nu != 0.0 ? d_M_e : nullptr, o->nu, net, o->grid_n,
+                                 o->cval, o->smooth, o->omega, o->cycle_dtype == FEM_F32, d_r, d_z, S(stream));
+}
+
+int fem_fcg_solve(const fem_plan *plan_c, const fem_fcg_opts *o, fem_unet *net, const void *d_K_e,
+                  const void *d_M_e, const double *d_b, double *d_x, fem_fcg_info *info, void *stream) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (int rc = check_plan(plan_c)) return rc;
+    fem_plan *plan = const_cast<fem_plan *>(plan_c);
+    if (!o || !info) return set_error(FEM_EINVAL, "opts and info must not be NULL");
+    std::memset(info, 0, sizeof(*info));
+    info->fell_back = -1;
+    if (int rc = check_fcg(plan, o, net, d_K_e, d_M_e)) return rc;
+    if (!d_b || !d_x) return set_error(FEM_EINVAL, "NULL argument");
+    if ((const void *)d_x == (const void *)d_b) return set_error(FEM_EINVAL, "x must not alias b");
     hipStream_t s = S(stream);
     fem::FcgResult res;
     int rc = fem::solve_fcg(plan->dev, o->dtype, d_K_e, o->nu != 0.0 ? d_M_e : nullptr, o->nu, d_b, d_x, o->rtol,
                             o->max_iter, net, o->grid_n, o->cval, o->smooth, o->omega, o->stall_iters,
-                            o->max_replace, o->graph, res, s);
+                            o->max_replace, o->graph, o->check_every, o->cycle_dtype == FEM_F32, res, s);
     info->iters = res.iters;
     info->precond_calls = res.precond_calls;
     info->fell_back = res.fell_back;
@@ -603,7 +632,8 @@ int fem_fcg_solve(const fem_plan *plan_c, const fem_fcg_opts *o, fem_unet *net, 
     info->r0 = res.r0;
     info->relres = res.relres;
     if (rc == fem::kFcgHandover) {
-        // Jacobi-PCG from the current iterate to the same absolute target
+        // Jacobi-PCG from the handed-over iterate to the same absolute
+        // target (res.rnorm: the true residual norm of that iterate)
         fem_solve_opts po;
         fem_solve_opts_default(&po);
         po.dtype = o->dtype;

@@ -343,7 +343,7 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
                     pr->refreshes += pr->first ? 0 : 1;
                     if (pr->first) {
                         pr->r0 = sqrt(rr);
-                        pr->thr2 = (a.rtol * pr->r0) * (a.rtol * pr->r0);
+                        pr->thr2 = (kCertify * a.rtol * pr->r0) * (kCertify * a.rtol * pr->r0);
                     }
                     pr->rr_true = rr;
                     if (pr->broken) {

@@ -849,7 +849,7 @@ int fem_mg_solve(fem_mg *mg, const fem_mg_opts *o, const double *d_b, double *d_
     info->r0 = rn;
     if (!std::isfinite(rn)) return finish(set_error(FEM_EBREAKDOWN, "non-finite initial residual"));
     if (rn == 0.0) return finish(FEM_OK);
-    const double target = o->rtol * rn;
+    const double target = fem::kCertify * o->rtol * rn;
     bool restart = true;
     double pq_prev = 1.0;
     for (int it = 0; it < o->max_iter; ++it) {

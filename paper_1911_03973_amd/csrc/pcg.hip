@@ -479,7 +479,8 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, double nu, const double
         info->relres = 0.0;
         return FEM_OK;
     }
-    const double thr2 = (rtol * r0) * (rtol * r0);
+    const double target = kCertify * rtol * r0;
+    const double thr2 = target * target;
     const double dd = delta > 0.0 ? delta * delta : 0.0;
     double rel2 = dd * h.rr;
     EventPool ev;
@@ -515,7 +516,7 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, double nu, const double
             ++calls;
             if ((rc = read_state(w.st, h, s))) return rc;
             ++refreshes;
-            if (std::sqrt(h.rr64) <= rtol * r0) break;
+            if (std::sqrt(h.rr64) <= target) break;
             if (refreshes >= max_outer) {
                 status = FEM_ENOCONV;
                 break;

@@ -15,6 +15,14 @@ DevPlan plan_device(const fem_plan *p);
 
 enum IterMode { MODE_CONTINUE = 0, MODE_FRESH = 1, MODE_FIRST = 2 };
 
+// Every solver stops once its FP64 true residual is at most
+// kCertify * rtol * ||r_0||.  The margin covers what separates this residual
+// from an independent FP64 evaluation of b - A x: the hi + lo pair carries
+// A_e to about 2^-48 relative instead of FP64's 2^-53, and the sums run in
+// another order.  Measured at 2048^2 squares the two evaluations agree to
+// about 1e-4 relative, a hundredth of the margin.
+constexpr double kCertify = 0.99;
+
 // Scalars of the CG recurrence.  Each field has exactly one writer kernel
 // (the single-block finalize / refresh kernels); the element kernels only read
 // it, after a kernel boundary on the same stream.
@@ -115,9 +123,10 @@ __host__ __device__ constexpr int packed_count(int nb) { return nb + nb * (nb - 
 
 // Flexible CG (fcg.hip).  With a network, a non-finite or zero network
 // output, p.q <= 0, or stall_iters iterations without halving ||r|| end the
-// FCG phase with kFcgHandover (x and res.rnorm hold the current iterate and
-// its residual norm) so that the caller continues with Jacobi-PCG; without a
-// network the preconditioner is Jacobi throughout.
+// FCG phase with kFcgHandover (x holds the iterate with the smallest
+// recursive residual seen, res.rnorm its true residual norm) so that the
+// caller continues with Jacobi-PCG; without a network the preconditioner is
+// Jacobi throughout.
 struct FcgResult {
     int status, iters, precond_calls, fell_back, fallback_reason, replacements;
     double relres, r0, rnorm;
@@ -134,6 +143,11 @@ int run_iteration(const DevPlan &P, int dtype, const void *K, const void *M, dou
                   int method, double lam1, double lam2, int cycle, int iters, IterResult &res, hipStream_t s);
 int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double nu, const double *b, double *x,
               double rtol, int max_iter, fem_unet *net, int grid_n, double cval, int smooth, double omega,
-              int stall_iters, int max_replace, int graph, FcgResult &res, hipStream_t s);
+              int stall_iters, int max_replace, int graph, int check_every, int cycle_heads, FcgResult &res,
+              hipStream_t s);
+// z = B(r) once: the preconditioner of solve_fcg with the same arguments.
+int fcg_precondition(const DevPlan &P, int dtype, const void *K, const void *M, double nu, fem_unet *net, int grid_n,
+                     double cval, int smooth, double omega, int cycle_heads, const double *r, double *z,
+                     hipStream_t s);
 
 }  // namespace fem

@@ -93,7 +93,7 @@ class FcgOpts(ctypes.Structure):
         ("dtype", ctypes.c_int), ("nu", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int),
         ("grid_n", ctypes.c_int), ("cval", ctypes.c_double), ("stall_iters", ctypes.c_int),
         ("max_replace", ctypes.c_int), ("smooth", ctypes.c_int), ("omega", ctypes.c_double),
-        ("graph", ctypes.c_int),
+        ("graph", ctypes.c_int), ("check_every", ctypes.c_int), ("cycle_dtype", ctypes.c_int),
     ]
 
 
@@ -163,6 +163,7 @@ _SIGS = {
     "fem_unet_train_step": [_vp, _int, _vp, _vp, ctypes.c_float, _vp, _vp],
     "fem_unet_precondition": [_vp, _int, _vp, _dbl, _vp, _vp, _vp],
     "fem_fcg_solve": [_vp, ctypes.POINTER(FcgOpts), _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(FcgInfo), _vp],
+    "fem_fcg_precondition": [_vp, ctypes.POINTER(FcgOpts), _vp, _vp, _vp, _vp, _vp, _vp],
     "fem_iterate": [_vp, ctypes.POINTER(IterOpts), _vp, _vp, _vp, _vp, ctypes.POINTER(IterInfo), _vp],
     "fem_mg_create": [_int, _vp, _vp, _int, _vp, _vp, _dbl, _vp, ctypes.POINTER(_vp)],
     "fem_mg_destroy": [_vp],
@@ -593,6 +594,16 @@ def fcg_solve(plan, opts, net, K, M, b, x, stream=None, allow=(FEM_ENOCONV,)):
     _check(_lib.fem_fcg_solve(plan.handle, ctypes.byref(opts), net.handle if net is not None else None, _ptr(K),
                               _ptr(M), _ptr(b), _ptr(x), ctypes.byref(info), _stream(stream)), allow=allow)
     return {k: getattr(info, k) for k, _ in info._fields_}
+
+
+def fcg_precondition(plan, opts, net, K, M, r, z, stream=None):
+    """z = B(r) once through fem_fcg_precondition (net None: D^-1 r)."""
+    plan._mat(K, opts.dtype, "K_e")
+    plan._mat(M, opts.dtype, "M_e")
+    _need(r, torch.float64, plan.n_nodes, "r")
+    _need(z, torch.float64, plan.n_nodes, "z")
+    _check(_lib.fem_fcg_precondition(plan.handle, ctypes.byref(opts), net.handle if net is not None else None,
+                                     _ptr(K), _ptr(M), _ptr(r), _ptr(z), _stream(stream)))
 
 
 # ---------------------------------------------------------------------------

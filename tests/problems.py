@@ -58,3 +58,22 @@ def max_rel(a, b, scale=None):
     b = np.asarray(b, dtype=np.float64)
     s = np.abs(b).max() if scale is None else scale
     return float(np.abs(a - b).max() / max(s, 1e-300))
+
+
+def bf16_params(net):
+    """The network's parameters in the oracle's layout with the weights rounded
+    to BF16 as the kernels use them (the 1x1 output layer and all biases stay
+    FP32)."""
+    from oracle import unet as U
+
+    w = net.get_params()
+    torch.cuda.synchronize()
+    p = w.double().cpu().numpy()
+    layers = U.unpack(p, net.channels)
+    out = []
+    for k, (W, b) in enumerate(layers):
+        Wr = torch.from_numpy(W.astype(np.float32)).to(torch.bfloat16).double().numpy()
+        if k == len(layers) - 1:
+            Wr = W
+        out.append((Wr, b))
+    return U.pack(out)

@@ -25,7 +25,7 @@ def _batch(meshes, nus, fseeds, dirichlet="all", chunk=0):
     return probs, B, K, M, b
 
 
-def _check_solutions(probs, B, x, res, tol=1.05e-8):
+def _check_solutions(probs, B, x, res, tol=1e-8):
     xs = x.cpu().numpy()
     for i, p in enumerate(probs):
         xi = xs[B.node_off[i]:B.node_off[i + 1]]

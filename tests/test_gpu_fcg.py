@@ -1,15 +1,31 @@
-"""Flexible CG on the element residual: Jacobi-FCG against the oracle's
-Jacobi-PCG (FCG(1) with a fixed SPD preconditioner generates the PCG iterates
-in exact arithmetic), convergence with a network preconditioner judged by the
-oracle's own FP64 residual, and the hand-over to Jacobi-PCG."""
+"""Flexible CG on the element residual: the preconditioner application
+z = B(r) and the Jacobi-FCG iterates against the oracle's FP64 FCG(1) and
+two-level cycle (oracle/fcg.py), Jacobi-FCG against the oracle's Jacobi-PCG
+(FCG(1) with a fixed SPD preconditioner generates the PCG iterates in exact
+arithmetic), convergence with a network preconditioner judged by the oracle's
+own FP64 residual, and the hand-over to Jacobi-PCG.
+
+Tolerances: everything but the network is FP64 on both sides, with sums in
+another order, so the Jacobi parts of the cycle and the first FCG iterates
+agree to 1e-12 and 1e-10 of their size.  The network runs in BF16 with FP32
+accumulation; on the same BF16-rounded weights its output n is within 2e-2
+of the oracle's in the relative 2-norm (the forward bound of
+test_gpu_unet.py).  The cycle adds s n with s = (n.rz)/(n.A n); to first
+order an error dn with ||dn|| <= e ||n|| moves s by
+e ||n|| (||rz|| + 2 |s| ||A n||) / (n.A n) -- large when n is nearly
+orthogonal to rz, as for an untrained network -- and s n by that times ||n||
+plus |s| e ||n||.  The post-smoothing steps (I - omega D^-1 A, spectral radius
+below 1, D nearly constant on these grids) do not amplify it; the test
+allows 1.5 times this bound, computed from the oracle's n, rz and s."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
+import oracle.fcg as ofcg
 from paper_1911_03973_amd import inputs
 
-from problems import Problem, cuda
+from problems import Problem, bf16_params, cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -106,9 +122,10 @@ def test_trained_network_beats_jacobi_pcg_in_iterations():
 
 
 def test_graph_replayed_preconditioner_matches_eager_launches():
-    """The network captured into a HIP graph and replayed every iteration (with
-    the solver's eager kernels and host synchronisations between replays) gives
-    the same iterates, bit for bit, as launching its kernels one by one."""
+    """The whole iteration (cycle, network and FCG update) captured into a HIP
+    graph and replayed, with host reads of the device state between batches of
+    replays, gives the same iterates, bit for bit, as launching its kernels one
+    by one."""
     N = 32
     gp = learn.GridProblem.make(N, 40.0, 3)
     net = fem.UNet(N, N, channels=16, seed=6)
@@ -119,3 +136,132 @@ def test_graph_replayed_preconditioner_matches_eager_launches():
         xs.append((x.cpu(), info["iters"]))
     assert xs[0][1] == xs[1][1] == xs[2][1] == 25
     assert torch.equal(xs[0][0], xs[1][0]) and torch.equal(xs[1][0], xs[2][0])
+
+
+def _oracle_op(prob):
+    return ofcg.Operator(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.mask)
+
+
+def _masked_residual(prob, seed):
+    """A masked residual r = b - A x of a random x (0 on Dirichlet nodes)."""
+    x = np.random.default_rng(seed).standard_normal(prob.n)
+    return oracle.residual(prob.n, prob.mesh.elems, prob.K, prob.M, prob.nu, prob.b, x, prob.mask)
+
+
+@pytest.mark.parametrize("N,nu,smooth", [(32, 12.5, 4), (64, 70.0, 2), (32, 3.0, 1)])
+def test_cycle_without_network_output_matches_oracle(N, nu, smooth):
+    """With all network parameters zero, N(r) = 0, s = 0 and the cycle is 2k
+    damped-Jacobi steps: element by element equal to the oracle's cycle with a
+    zero coarse correction to 1e-12."""
+    prob = Problem(inputs.square_mesh(N), nu=nu, f="sine", seed=N)
+    plan, K, M, b = _gpu(prob)
+    net = fem.UNet(N, N, channels=16, seed=1)
+    net.set_params(torch.zeros(net.n_params, dtype=torch.float32, device="cuda"))
+    r = _masked_residual(prob, 5)
+    z = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    opts = fem.fcg_opts(nu=nu, grid_n=N, cval=nu / 100.0, smooth=smooth)
+    fem.fcg_precondition(plan, opts, net, K, M, cuda(r), z)
+    ref = ofcg.two_level_cycle(_oracle_op(prob), r, lambda rz: np.zeros(prob.n), smooth)
+    zs = z.cpu().numpy()
+    assert np.abs(zs - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.all(zs[prob.mask != 0] == 0.0)
+
+
+@pytest.mark.parametrize("N,nu,smooth", [(32, 25.0, 4), (64, 60.0, 4), (64, 5.0, 2), (32, 40.0, 0)])
+def test_cycle_with_network_matches_oracle_within_bf16_bound(N, nu, smooth):
+    """z = B(r) of the two-level cycle with a random network (and z = N(r) for
+    smooth = 0) against the oracle's cycle with the FP64 network on the same
+    BF16-rounded weights; the smoothing parts agree to rounding, the network's
+    correction within the BF16 forward bound."""
+    prob = Problem(inputs.square_mesh(N), nu=nu, f="sine", seed=N + 1)
+    plan, K, M, b = _gpu(prob)
+    net = fem.UNet(N, N, channels=16, seed=9)
+    r = _masked_residual(prob, 6)
+    z = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    opts = fem.fcg_opts(nu=nu, grid_n=N, cval=nu / 100.0, smooth=smooth)
+    fem.fcg_precondition(plan, opts, net, K, M, cuda(r), z)
+    zs = z.cpu().numpy()
+    coarse = ofcg.network_coarse(bf16_params(net), N, nu / 100.0, prob.mask)
+    if smooth == 0:
+        ref = coarse(r)
+        assert np.linalg.norm(zs - ref) <= 2e-2 * np.linalg.norm(ref)
+        return
+    op = _oracle_op(prob)
+    ref, s, n, z_pre = ofcg.two_level_cycle(op, r, coarse, smooth, detail=True)
+    assert s != 0.0
+    rz = r - op.apply(z_pre)
+    An = op.apply(n)
+    # first-order effect of a network error dn with ||dn|| <= e ||n||:
+    # d(s n) = ds n + s dn, ds = (dn.rz - 2 s dn.An) / (n.A n)
+    e = 2e-2
+    nn = np.linalg.norm(n)
+    ds = e * nn * (np.linalg.norm(rz) + 2.0 * abs(s) * np.linalg.norm(An)) / float(n @ An)
+    bound = ds * nn + abs(s) * e * nn
+    # the post-smoothing (I - omega D^-1 A)^k has 2-norm about 1 here (D nearly constant)
+    assert np.linalg.norm(zs - ref) <= 1.5 * bound + 1e-12 * np.linalg.norm(ref)
+    assert np.all(zs[prob.mask != 0] == 0.0)
+
+
+def test_cycle_on_fp32_heads_stays_close_to_fp64_cycle():
+    """cycle_dtype=F32 reads the FP32 heads of the packed operator in the
+    cycle's passes: with a zero network its output is the FP64 cycle's to
+    within the FP32 rounding of the operator (well below 1e-5 relative)."""
+    N, nu = 64, 30.0 / 7.0
+    # jittered nodes: on the uniform mesh this operator is exact in FP32
+    prob = Problem(inputs.square_mesh(N, jitter=0.2, seed=5), nu=nu, f="sine", seed=2)
+    plan, K, M, b = _gpu(prob)
+    net = fem.UNet(N, N, channels=16, seed=1)
+    net.set_params(torch.zeros(net.n_params, dtype=torch.float32, device="cuda"))
+    r = cuda(_masked_residual(prob, 7))
+    z64 = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    z32 = torch.empty_like(z64)
+    fem.fcg_precondition(plan, fem.fcg_opts(nu=nu, grid_n=N, smooth=4), net, K, M, r, z64)
+    fem.fcg_precondition(plan, fem.fcg_opts(nu=nu, grid_n=N, smooth=4, cycle_dtype=fem.F32), net, K, M, r, z32)
+    d = float(torch.linalg.vector_norm(z32 - z64) / torch.linalg.vector_norm(z64))
+    assert 0.0 < d < 1e-5, d
+
+
+def test_jacobi_precondition_is_diagonal_scaling():
+    prob = Problem(inputs.square_mesh(24, jitter=0.2, seed=3), nu=2.0, dirichlet="x2=0")
+    plan, K, M, b = _gpu(prob)
+    r = _masked_residual(prob, 8)
+    z = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    fem.fcg_precondition(plan, fem.fcg_opts(nu=2.0), None, K, M, cuda(r), z)
+    ref = ofcg.jacobi(_oracle_op(prob))(r)
+    assert np.abs(z.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("case", ["2d", "2d_jitter_nu", "3d"])
+def test_jacobi_fcg_iterates_match_oracle(case):
+    """The first ten Jacobi-FCG iterates x_1..x_10 (the solve stopped by
+    max_iter = k) against the oracle's FCG(1) with D^-1 at 1e-10 of ||x_k||."""
+    if case == "2d":
+        prob = Problem(inputs.square_mesh(32), nu=0.0)
+    elif case == "2d_jitter_nu":
+        prob = Problem(inputs.square_mesh(40, jitter=0.2, seed=4), nu=7.0, dirichlet="x2=0", f="sine", seed=4)
+    else:
+        prob = Problem(inputs.cube_mesh(8, jitter=0.1, seed=2), nu=3.0, f="sine", seed=2)
+    plan, K, M, b = _gpu(prob)
+    op = _oracle_op(prob)
+    _, hist = ofcg.fcg(op, prob.b, np.zeros(prob.n), ofcg.jacobi(op), iters=10, history=True)
+    for k in range(1, 11):
+        x = torch.zeros(prob.n, dtype=torch.float64, device="cuda")
+        info = fem.fcg_solve(plan, fem.fcg_opts(nu=prob.nu, rtol=1e-14, max_iter=k, check_every=3), None, K, M,
+                             b, x)
+        assert info["iters"] == k, info
+        xs = x.cpu().numpy()
+        ref = hist[k - 1]
+        assert np.linalg.norm(xs - ref) <= 1e-10 * np.linalg.norm(ref), (k, np.linalg.norm(xs - ref))
+
+
+def test_handover_starts_from_best_iterate_and_meets_target():
+    """A network that hands over after a stall: Jacobi-PCG continues from the
+    best iterate to the same absolute target, judged by the oracle."""
+    N = 32
+    gp = learn.GridProblem.make(N, 20.0, 11)
+    net = fem.UNet(N, N, channels=16, seed=2)
+    x = torch.zeros(gp.n_nodes, dtype=torch.float64, device="cuda")
+    info = gp.fcg(net, x, rtol=1e-8, stall_iters=1, check_every=1)
+    assert info["status"] == 0 and info["fell_back"] >= 0
+    prob = Problem(inputs.square_mesh(N), nu=20.0, f="sine", seed=11)
+    assert _true_relres(prob, x.cpu().numpy()) <= 1e-8

@@ -21,6 +21,8 @@ import torch
 
 from oracle import unet as U
 
+from problems import bf16_params
+
 pytestmark = pytest.mark.gpu
 
 fem = pytest.importorskip("paper_1911_03973_amd.fem")
@@ -31,17 +33,7 @@ GRAD_TOL = 5e-2
 
 def _bf16_params(net):
     """The network's parameters with the weights rounded to BF16 as the kernels use them."""
-    w = net.get_params()
-    torch.cuda.synchronize()
-    p = w.double().cpu().numpy()
-    layers = U.unpack(p, net.channels)
-    out = []
-    for k, (W, b) in enumerate(layers):
-        Wr = torch.from_numpy(W.astype(np.float32)).to(torch.bfloat16).double().numpy()
-        if k == len(layers) - 1:
-            Wr = W  # 1x1 output layer runs in FP32
-        out.append((Wr, b))
-    return U.pack(out)
+    return bf16_params(net)
 
 
 def _rel(a, b):
