@@ -480,16 +480,30 @@ def measured_traffic():
     return None
 
 
+def parse_segments(spec):
+    """"4x25,8x25" -> [4]*25 + [8]*25 (segment lengths of the pair generator)."""
+    out = []
+    for part in spec.split(","):
+        if "x" in part:
+            k, c = part.split("x")
+            out += [int(k)] * int(c)
+        else:
+            out.append(int(part))
+    return out
+
+
 def learned_fcg(args):
     """Learned-preconditioner workload: 1024^2 squares, nu ~ U(0, 100), random-sine f, u = 0 on the boundary.
 
-    Training pairs come from the plain FP64 Jacobi-PCG solver (restarted segments
-    from x0 = 0, see paper_1911_03973_amd/learn.py); the network is trained with
-    the library's BF16 MFMA kernels; then every held-out problem is solved to a
-    true relative residual of 1e-8 by (a) Jacobi-PCG with FP32 element passes and
-    FP64 refinement (the optimized solver of the main workload) and (b) learned
-    FCG on the same FP32 hi/lo element matrices.  Training time is reported
-    separately from the solve times.
+    Training pairs come from the plain FP64 Jacobi-PCG solver (restarted
+    segments from x0 = 0; the error against a multigrid reference solution, see
+    paper_1911_03973_amd/learn.py), streamed round by round into the training
+    of the network with the library's BF16 MFMA kernels; every pair is used
+    once.  Then every held-out problem is solved to a true relative residual of
+    1e-8 by (a) Jacobi-PCG with FP32 element passes and FP64 refinement (the
+    optimized solver of the main workload) and (b) learned FCG on the same FP32
+    hi/lo element matrices.  Training time is reported separately from the
+    solve times.
     """
     import numpy as np
     import torch
@@ -497,62 +511,67 @@ def learned_fcg(args):
     from paper_1911_03973_amd import fem, learn
 
     N = args.learned_n
-    segs = [int(v) for v in args.learned_segments.split(",")]
-    log(f"[bench] learned: pairs from {args.learned_problems} problems at {N}^2, segments {segs}")
-    t = time.perf_counter()
-    ins, tgs = learn.make_dataset(N, args.learned_problems, 100, segs)
-    torch.cuda.synchronize()
-    t_data = time.perf_counter() - t
+    segs = parse_segments(args.learned_segments)
+    params = learn.problem_params(args.learned_problems, 100)
+    log(f"[bench] learned: {len(params)} problems x {len(segs)} snapshots at {N}^2 in {args.learned_rounds} rounds")
+    fam = learn.GridFamily(N, fem.F64, mg=True)
     net = fem.UNet(N, N, max_batch=args.learned_batch, channels=16, seed=0)
-    log(f"[bench] learned: {ins.shape[0]} pairs in {t_data:.1f} s; training {args.learned_steps} steps")
-    t = time.perf_counter()
-    hist = learn.train(net, ins, tgs, args.learned_steps, args.learned_batch, args.learned_lr,
-                       log_every=max(args.learned_steps // 5, 1))
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t
-    n_pairs = int(ins.shape[0])
-    del ins, tgs
+    hist, n_pairs, t_data, t_train = learn.train_streaming(fam, net, params, segs, args.learned_batch,
+                                                           args.learned_lr, args.learned_rounds, log=log)
+    del fam
+    torch.cuda.empty_cache()
+    log(f"[bench] learned: {n_pairs} pairs in {t_data:.1f} s, {len(hist)} steps in {t_train:.1f} s")
+    efam = learn.GridFamily(N, fem.F32X2)
+    fopts = dict(smooth=args.learned_smooth, cycle_dtype=fem.F32 if args.learned_cycle == "f32" else fem.F64)
     rows = []
-    for nu, seed in learn.problem_params(args.learned_eval, 5000):
-        gp = learn.GridProblem.make(N, nu, seed, dtype=fem.F32X2)
+    for i, (nu, seed) in enumerate(learn.problem_params(args.learned_eval, 5000)):
+        gp = efam.problem(nu, seed)
         x = torch.zeros(gp.n_nodes, dtype=torch.float64, device="cuda")
-        gp.pcg(x)  # warm-up: workspace allocation
-        x.zero_()
+        if i == 0:  # warm-ups: workspace allocation, code loading
+            gp.pcg(x)
+            x.zero_()
+            gp.fcg(net, x, max_iter=2, **fopts)
+            x.zero_()
         a = gp.pcg(x)
         x.zero_()
-        gp.fcg(net, x, max_iter=2, smooth=args.learned_smooth)  # warm-up
-        x.zero_()
-        b = gp.fcg(net, x, smooth=args.learned_smooth)
-        x.zero_()
-        c = gp.fcg(net, x, smooth=args.learned_smooth, stall_iters=1 << 30, max_iter=args.learned_max_iter)
-        rows.append({"nu": round(nu, 3), "pcg_iters": a["iters"], "pcg_s": round(a["seconds"], 4),
-                     "pcg_relres": a["relres"], "fcg_iters": b["iters"], "fcg_pcg_iters": b["pcg_iters"],
-                     "fcg_fell_back": b["fell_back"], "fcg_s": round(b["seconds"], 4), "fcg_relres": b["relres"],
-                     "fcg_no_handover_iters": c["iters"], "fcg_no_handover_s": round(c["seconds"], 4),
-                     "fcg_no_handover_status": c["status"], "fcg_no_handover_relres": c["relres"]})
-        log(f"[bench] learned: nu {nu:.2f} Jacobi-PCG {a['iters']} it {a['seconds']:.3f} s | "
-            f"learned FCG {b['iters']}+{b['pcg_iters']} it {b['seconds']:.3f} s | "
-            f"without hand-over {c['iters']} it {c['seconds']:.3f} s")
+        b = gp.fcg(net, x, **fopts)
+        row = {"nu": round(nu, 3), "pcg_iters": a["iters"], "pcg_s": round(a["seconds"], 4),
+               "pcg_relres": a["relres"], "fcg_iters": b["iters"], "fcg_pcg_iters": b["pcg_iters"],
+               "fcg_fell_back": b["fell_back"], "fcg_s": round(b["seconds"], 4), "fcg_relres": b["relres"]}
+        msg = (f"[bench] learned: nu {nu:.2f} Jacobi-PCG {a['iters']} it {a['seconds']:.3f} s | "
+               f"learned FCG {b['iters']}+{b['pcg_iters']} it {b['seconds']:.3f} s")
+        if b["fell_back"] >= 0 and i < args.learned_nohandover:
+            x.zero_()
+            c = gp.fcg(net, x, stall_iters=1 << 30, max_iter=args.learned_max_iter, **fopts)
+            row.update({"fcg_no_handover_iters": c["iters"], "fcg_no_handover_s": round(c["seconds"], 4),
+                        "fcg_no_handover_status": c["status"], "fcg_no_handover_relres": c["relres"]})
+            msg += f" | without hand-over {c['iters']} it {c['seconds']:.3f} s"
+        rows.append(row)
+        log(msg)
         del gp
     t_pcg = float(np.median([r["pcg_s"] for r in rows]))
     t_fcg = float(np.median([r["fcg_s"] for r in rows]))
+    fcg_it = [r["fcg_iters"] + r["fcg_pcg_iters"] for r in rows]
+    fcg_only = [r["fcg_s"] / max(r["fcg_iters"], 1) for r in rows if r["fcg_fell_back"] < 0]
     return {
         "workload": f"2D P1 {N}x{N} squares ({(N + 1) ** 2} nodes, {2 * N * N} triangles), nu~U(0,100), "
                     "random-sine f, u=0 on the boundary; held-out problems",
         "network": "U-Net 4 levels, 16-128 channels, BF16 MFMA / FP32 accumulation, 482753 parameters",
         "preconditioner": f"FCG(1), two-level cycle: {args.learned_smooth} damped-Jacobi steps (omega 2/3), network "
-                          f"correction, {args.learned_smooth} Jacobi steps; hand-over to Jacobi-PCG after 50 "
-                          "iterations without halving ||r||",
-        "pairs": n_pairs,
-        "train_steps": args.learned_steps, "train_batch": args.learned_batch,
-        "train_loss_first": round(float(hist[:10].mean()), 4), "train_loss_last": round(float(hist[-20:].mean()), 4),
+                          f"correction, {args.learned_smooth} Jacobi steps, {args.learned_cycle.upper()} cycle passes; "
+                          "hand-over to Jacobi-PCG (from the best iterate) after 200 iterations without halving ||r||",
+        "pairs": n_pairs, "train_problems": len(params), "snapshots_per_problem": len(segs),
+        "eval_problems": len(rows),
+        "train_steps": len(hist), "train_batch": args.learned_batch,
+        "train_loss_first": round(float(hist[:50].mean()), 4), "train_loss_last": round(float(hist[-200:].mean()), 4),
         "data_s": round(t_data, 2), "train_s": round(t_train, 2),
         "time_to_1e8_jacobi_pcg_s": round(t_pcg, 4), "time_to_1e8_learned_fcg_s": round(t_fcg, 4),
         "speedup_vs_jacobi_pcg": round(t_pcg / t_fcg, 3),
-        "iters_jacobi_pcg": [r["pcg_iters"] for r in rows],
-        "iters_learned_fcg": [r["fcg_iters"] + r["fcg_pcg_iters"] for r in rows],
-        "iters_learned_fcg_no_handover": [r["fcg_no_handover_iters"] for r in rows],
-        "time_to_1e8_learned_fcg_no_handover_s": round(float(np.median([r["fcg_no_handover_s"] for r in rows])), 4),
+        "iters_jacobi_pcg_mean": round(float(np.mean([r["pcg_iters"] for r in rows])), 1),
+        "iters_learned_fcg_mean": round(float(np.mean(fcg_it)), 1),
+        "handovers": sum(1 for r in rows if r["fcg_fell_back"] >= 0),
+        "max_total_minus_cold_pcg_iters": int(max(t - r["pcg_iters"] for t, r in zip(fcg_it, rows))),
+        "fcg_ms_per_iter_median": round(1e3 * float(np.median(fcg_only)), 4) if fcg_only else None,
         "problems": rows,
     }
 
@@ -562,7 +581,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["unet", "cheb", "mg"], default="c2")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS) + ["unet", "cheb", "mg", "learned"], default="c2")
     ap.add_argument("--mg-base", choices=["c2", "c3"], default="c2", help="mg workload: the problem (2D or 3D)")
     ap.add_argument("--mg-coarsest", type=int, default=0,
                     help="mg workload: cells per side of the coarsest grid (0: 16 in 2D, 5 in 3D)")
@@ -597,14 +616,18 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="batched: pick the schedule with the autotuner first")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-FCG vs Jacobi-PCG comparison")
     ap.add_argument("--learned-n", type=int, default=1024)
-    ap.add_argument("--learned-problems", type=int, default=24)
-    ap.add_argument("--learned-segments", default="10,10,20,20,40,40,80,80,160,160")
-    ap.add_argument("--learned-steps", type=int, default=1000)
-    ap.add_argument("--learned-smooth", type=int, default=4)
+    ap.add_argument("--learned-problems", type=int, default=160, help="training problems")
+    ap.add_argument("--learned-segments", default="4x25,8x25,12x25,16x25,20x25",
+                    help="Jacobi-PCG segment lengths between snapshots, 'length x count' items")
+    ap.add_argument("--learned-rounds", type=int, default=10, help="rounds of pair generation + training")
+    ap.add_argument("--learned-smooth", type=int, default=2)
+    ap.add_argument("--learned-cycle", choices=["f32", "f64"], default="f32")
     ap.add_argument("--learned-max-iter", type=int, default=4000)
     ap.add_argument("--learned-batch", type=int, default=4)
     ap.add_argument("--learned-lr", type=float, default=2e-3)
-    ap.add_argument("--learned-eval", type=int, default=3)
+    ap.add_argument("--learned-eval", type=int, default=32, help="held-out problems")
+    ap.add_argument("--learned-nohandover", type=int, default=3,
+                    help="of the held-out problems that hand over, the first few are also solved without hand-over")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs its hot path on a single MI355X "
@@ -622,6 +645,9 @@ def main():
         return run_iterations(args)
     if args.workload == "mg":
         return run_multigrid(args)
+    if args.workload == "learned":
+        print(json.dumps({"learned_fcg": learned_fcg(args)}), flush=True)
+        return
     w = WORKLOADS[args.workload]
     if args.workload == "c4":
         return run_batched(args, w)

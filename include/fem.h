@@ -402,6 +402,16 @@ int fem_unet_train_step(fem_unet *net, int batch, const float *d_in, const float
  * (uint8 [n_nodes], may be NULL) get 0.  Allocates nothing. */
 int fem_unet_precondition(fem_unet *net, int grid_n, const double *d_r, double cval, const uint8_t *d_mask,
                           double *d_z, void *stream);
+/* One training pair of the learned preconditioner on the same grid (the
+ * network's image size; grid_n = H = W): d_in (float [grid_n][grid_n][2]) gets
+ * the network input of residual d_r exactly as fem_unet_precondition forms it,
+ * d_target (float [grid_n][grid_n]) the error e = d_u - d_x on the interior
+ * nodes divided by its RMS there (pixel (i-1, j-1) <- node (i, j); last row
+ * and column 0; a zero e gives a zero image).  d_r, d_u, d_x: FP64
+ * [(grid_n + 1)^2], caller-owned.  Uses the network's scratch, so calls on one
+ * network must not overlap.  Allocates nothing. */
+int fem_unet_make_pair(fem_unet *net, int grid_n, const double *d_r, const double *d_u, const double *d_x,
+                       double cval, float *d_in, float *d_target, void *stream);
 
 typedef struct {
     int dtype;          /* storage of K_e / M_e */
@@ -452,8 +462,8 @@ void fem_fcg_opts_default(fem_fcg_opts *o);
  * at fem_unet_precondition), alone or inside the two-level cycle of
  * opts->smooth, or by Jacobi (net == NULL; linear triangles or tetrahedra).
  * With a network, a non-finite or zero output, p.q <= 0, or stall_iters
- * iterations without halving ||r|| end the FCG phase: the iterate with the
- * smallest residual seen (x0 if none halved it) goes to the Jacobi-PCG solver
+ * iterations without halving ||r|| end the FCG phase: the iterate of the last
+ * halving of ||r|| (x0 if it never halved) goes to the Jacobi-PCG solver
  * (fem_pcg_solve with opts->dtype), which finishes the solve to the same
  * absolute target.  The true FP64 residual decides convergence.  x: x0 on
  * entry (Dirichlet values included), the solution on exit; after

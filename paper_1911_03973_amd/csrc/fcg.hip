@@ -29,9 +29,9 @@
 // still queued return at once (the cycle's own launches run on scratch
 // vectors and change nothing the solve keeps).
 //
-// With a network, the iterate with the smallest recursive residual so far
-// (recorded at every halving of ||r||) is kept; a hand-over to Jacobi-PCG
-// starts from it, with the true residual recomputed for it.
+// With a network, the iterate of the last halving of ||r|| (x0 before the
+// first) is kept; a hand-over to Jacobi-PCG starts from it, with the true
+// residual recomputed for it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -611,9 +611,12 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
             continue;  // the state already says: run, restart from the true residual
         }
         if (h.flag == FCG_HANDOVER) {
-            // continue from the best iterate (x0 before the first halving; the
-            // current one if it is no worse)
-            if (h.best < h.rn) FEM_HIP_CHECK(hipMemcpyAsync(x, w.xb, n * 8, hipMemcpyDeviceToDevice, s));
+            // continue from the best iterate: x0 when ||r|| never halved (an
+            // iterate that has not halved it may carry an error that is harder
+            // for Jacobi-PCG than the initial one), else the iterate of the last
+            // halving, or the current one if it is no worse
+            if (h.best_it == 0 || h.best < h.rn)
+                FEM_HIP_CHECK(hipMemcpyAsync(x, w.xb, n * 8, hipMemcpyDeviceToDevice, s));
             if (int rc = true_residual(P, w, b, x, 0, s)) return rc;
             if (int rc = read_state(w, h, s)) return rc;
             res.fallback_reason = h.reason;

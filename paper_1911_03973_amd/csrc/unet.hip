@@ -742,17 +742,24 @@ __global__ __launch_bounds__(256) void k_interior_sumsq(const double *__restrict
     s = block_sum<256>(s, red);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
-__global__ void k_grid_in(const double *__restrict__ r, const double *__restrict__ part, int nparts, int N, float cval,
-                          float *__restrict__ in2) {
-    __shared__ double inv_s;
+// inv[0] = 1 / RMS over the (N-1)^2 interior values from the per-block sums of
+// squares (fixed order), 0 for a zero vector
+__global__ __launch_bounds__(256) void k_grid_scale(const double *__restrict__ part, int nparts, int N,
+                                                    double *__restrict__ inv) {
+    __shared__ double red[4];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += 256) s += part[k];
+    s = block_sum<256>(s, red);
     if (threadIdx.x == 0) {
-        double ss = 0.0;
-        for (int k = 0; k < nparts; ++k) ss += part[k];
         const double n_int = (double)(N - 1) * (N - 1);
-        inv_s = ss > 0.0 ? 1.0 / sqrt(ss / n_int) : 0.0;
+        inv[0] = s > 0.0 ? 1.0 / sqrt(s / n_int) : 0.0;
     }
-    __syncthreads();
-    const double inv = inv_s;
+}
+// network input: pixel (x, y) <- interior node (x + 1, y + 1) scaled by inv[0];
+// last row and column 0; channel 1 = cval
+__global__ void k_grid_in(const double *__restrict__ r, const double *__restrict__ inv_p, int N, float cval,
+                          float *__restrict__ in2) {
+    const double inv = inv_p[0];
     const int64_t P = (int64_t)N * N;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(p % N), y = (int)(p / N);
@@ -760,6 +767,35 @@ __global__ void k_grid_in(const double *__restrict__ r, const double *__restrict
         if (x < N - 1 && y < N - 1) v = (float)(r[(int64_t)(y + 1) * (N + 1) + (x + 1)] * inv);
         in2[2 * p] = v;
         in2[2 * p + 1] = cval;
+    }
+}
+// e = u - x on the interior: per-block sums of squares
+__global__ __launch_bounds__(256) void k_interior_sumsq_diff(const double *__restrict__ u, const double *__restrict__ x,
+                                                             int N, double *__restrict__ part) {
+    __shared__ double red[4];
+    const int64_t n = (int64_t)(N - 1) * (N - 1);
+    double s = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const int64_t g = (p / (N - 1) + 1) * (N + 1) + p % (N - 1) + 1;
+        const double v = u[g] - x[g];
+        s += v * v;
+    }
+    s = block_sum<256>(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+// training target: pixel (x, y) <- (u - x) at interior node (x + 1, y + 1) scaled by inv[0]
+__global__ void k_grid_target(const double *__restrict__ u, const double *__restrict__ xv,
+                              const double *__restrict__ inv_p, int N, float *__restrict__ t) {
+    const double inv = inv_p[0];
+    const int64_t P = (int64_t)N * N;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(p % N), y = (int)(p / N);
+        float v = 0.f;
+        if (x < N - 1 && y < N - 1) {
+            const int64_t g = (int64_t)(y + 1) * (N + 1) + (x + 1);
+            v = (float)((u[g] - xv[g]) * inv);
+        }
+        t[p] = v;
     }
 }
 __global__ void k_grid_out(const float *__restrict__ out, int N, const uint8_t *__restrict__ mask, double *__restrict__ z) {
@@ -772,6 +808,9 @@ __global__ void k_grid_out(const float *__restrict__ out, int N, const uint8_t *
         z[g] = v;
     }
 }
+
+// slots of UNet::gpart: [0, 1024) and [1024, 2048) per-block sums, then the scales
+constexpr int kGridScale = 2048;
 
 inline int grid1(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384)); }
 
@@ -1147,10 +1186,28 @@ int unet_grid_precondition(fem_unet *net, int grid_n, const double *r, double cv
     const int64_t n_int = (int64_t)(grid_n - 1) * (grid_n - 1);
     const int parts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n_int + 255) / 256));
     k_interior_sumsq<<<parts, 256, 0, st>>>(r, grid_n, N.gpart);
-    k_grid_in<<<grid1((int64_t)grid_n * grid_n), 256, 0, st>>>(r, N.gpart, parts, grid_n, (float)cval, N.in2);
+    k_grid_scale<<<1, 256, 0, st>>>(N.gpart, parts, grid_n, N.gpart + kGridScale);
+    k_grid_in<<<grid1((int64_t)grid_n * grid_n), 256, 0, st>>>(r, N.gpart + kGridScale, grid_n, (float)cval, N.in2);
     FEM_HIP_CHECK(hipGetLastError());
     if (int rc = forward(N, 1, N.in2, st)) return rc;
     k_grid_out<<<grid1((int64_t)(grid_n + 1) * (grid_n + 1)), 256, 0, st>>>(N.out, grid_n, mask, z);
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+int unet_grid_pair(fem_unet *net, int grid_n, const double *r, const double *u, const double *x, double cval,
+                   float *in2, float *tgt, hipStream_t st) {
+    UNet &N = net->net;
+    if (grid_n != N.H || grid_n != N.W) return set_error(FEM_EINVAL, "grid size must equal the network image size");
+    const int64_t n_int = (int64_t)(grid_n - 1) * (grid_n - 1);
+    const int parts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n_int + 255) / 256));
+    const int g = grid1((int64_t)grid_n * grid_n);
+    k_interior_sumsq<<<parts, 256, 0, st>>>(r, grid_n, N.gpart);
+    k_grid_scale<<<1, 256, 0, st>>>(N.gpart, parts, grid_n, N.gpart + kGridScale);
+    k_grid_in<<<g, 256, 0, st>>>(r, N.gpart + kGridScale, grid_n, (float)cval, in2);
+    k_interior_sumsq_diff<<<parts, 256, 0, st>>>(u, x, grid_n, N.gpart + 1024);
+    k_grid_scale<<<1, 256, 0, st>>>(N.gpart + 1024, parts, grid_n, N.gpart + kGridScale + 1);
+    k_grid_target<<<g, 256, 0, st>>>(u, x, N.gpart + kGridScale + 1, grid_n, tgt);
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
@@ -1260,7 +1317,7 @@ int fem_unet_create(int H, int W, int max_batch, int channels, uint64_t seed, vo
     add((void **)&N.partial, cap * 4);
     add((void **)&N.sums, (size_t)2 * B * 8);
     add((void **)&N.lpart, (size_t)2 * B * N.loss_slices * 8);
-    add((void **)&N.gpart, 1024 * 8);
+    add((void **)&N.gpart, (fem::kGridScale + 8) * 8);
     size_t total = 0;
     std::vector<size_t> offs;
     for (auto &it : items) {
@@ -1375,6 +1432,14 @@ int fem_unet_precondition(fem_unet *net, int grid_n, const double *d_r, double c
     if (d_r == d_z) return set_error(FEM_EINVAL, "z must not alias r");
     if (!std::isfinite(cval)) return set_error(FEM_EINVAL, "cval must be finite");
     return fem::unet_grid_precondition(net, grid_n, d_r, cval, d_mask, d_z, S(stream));
+}
+
+int fem_unet_make_pair(fem_unet *net, int grid_n, const double *d_r, const double *d_u, const double *d_x,
+                       double cval, float *d_in, float *d_target, void *stream) {
+    if (int rc = check_net(net)) return rc;
+    if (!d_r || !d_u || !d_x || !d_in || !d_target) return set_error(FEM_EINVAL, "NULL argument");
+    if (!std::isfinite(cval)) return set_error(FEM_EINVAL, "cval must be finite");
+    return fem::unet_grid_pair(net, grid_n, d_r, d_u, d_x, cval, d_in, d_target, S(stream));
 }
 
 }  // extern "C"

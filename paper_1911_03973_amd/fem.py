@@ -162,6 +162,7 @@ _SIGS = {
     "fem_unet_loss_grad": [_vp, _int, _vp, _vp, _vp, _vp, _vp],
     "fem_unet_train_step": [_vp, _int, _vp, _vp, ctypes.c_float, _vp, _vp],
     "fem_unet_precondition": [_vp, _int, _vp, _dbl, _vp, _vp, _vp],
+    "fem_unet_make_pair": [_vp, _int, _vp, _vp, _vp, _dbl, _vp, _vp, _vp],
     "fem_fcg_solve": [_vp, ctypes.POINTER(FcgOpts), _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(FcgInfo), _vp],
     "fem_fcg_precondition": [_vp, ctypes.POINTER(FcgOpts), _vp, _vp, _vp, _vp, _vp, _vp],
     "fem_iterate": [_vp, ctypes.POINTER(IterOpts), _vp, _vp, _vp, _vp, ctypes.POINTER(IterInfo), _vp],
@@ -572,6 +573,18 @@ class UNet:
         _need(mask, torch.uint8, n, "mask")
         _check(_lib.fem_unet_precondition(self.handle, int(grid_n), _ptr(r), float(cval), _ptr(mask), _ptr(z),
                                           _stream(stream)))
+
+
+    def make_pair(self, grid_n, r, u, x, cval, inp, target, stream=None):
+        """Writes one training pair through fem_unet_make_pair: inp float32 [grid_n, grid_n, 2]
+        (the network input of r), target float32 [grid_n, grid_n] (u - x scaled to unit RMS)."""
+        n = (grid_n + 1) ** 2
+        for t, name in ((r, "r"), (u, "u"), (x, "x")):
+            _need(t, torch.float64, n, name)
+        _need(inp, torch.float32, grid_n * grid_n * 2, "input image")
+        _need(target, torch.float32, grid_n * grid_n, "target image")
+        _check(_lib.fem_unet_make_pair(self.handle, int(grid_n), _ptr(r), _ptr(u), _ptr(x), float(cval), _ptr(inp),
+                                       _ptr(target), _stream(stream)))
 
 
 def fcg_opts(**kw):

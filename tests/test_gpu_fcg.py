@@ -102,13 +102,14 @@ def test_trained_network_beats_jacobi_pcg_in_iterations():
     iterations of Jacobi-PCG, without handing over, to a true residual of 1e-8."""
     N = 64
     torch.manual_seed(0)
-    ins, tgs = learn.make_dataset(N, 16, 100, [4] * 30)
+    fam = learn.GridFamily(N, mg=True)
     net = fem.UNet(N, N, max_batch=8, channels=16, seed=0)
+    ins, tgs = learn.make_dataset(fam, net, 16, 100, [4] * 30)
     hist = learn.train(net, ins, tgs, 400, 8, 2e-3)
     assert hist[-20:].mean() < 0.25 * hist[:10].mean()
     it_pcg, it_fcg = [], []
     for nu, seed in learn.problem_params(3, 5000):
-        gp = learn.GridProblem.make(N, nu, seed)
+        gp = fam.problem(nu, seed)
         x = torch.zeros(gp.n_nodes, dtype=torch.float64, device="cuda")
         a = gp.pcg(x)
         x = torch.zeros(gp.n_nodes, dtype=torch.float64, device="cuda")
@@ -265,3 +266,23 @@ def test_handover_starts_from_best_iterate_and_meets_target():
     assert info["status"] == 0 and info["fell_back"] >= 0
     prob = Problem(inputs.square_mesh(N), nu=20.0, f="sine", seed=11)
     assert _true_relres(prob, x.cpu().numpy()) <= 1e-8
+
+
+def test_streamed_training_uses_every_pair_once():
+    """train_streaming: rounds of generated pairs, one Adam step per batch of a
+    round's pool, the loss falls."""
+    N = 32
+    fam = learn.GridFamily(N, mg=True)
+    net = fem.UNet(N, N, max_batch=4, channels=16, seed=3)
+    params = learn.problem_params(6, 300)
+    hist, pairs, t_data, t_train = learn.train_streaming(fam, net, params, [3] * 10, 4, 2e-3, 3)
+    assert pairs == 60 and len(hist) == 3 * (20 // 4)
+    assert np.all(np.isfinite(hist)) and hist[-3:].mean() < hist[:3].mean()
+
+
+def test_reference_solution_meets_1e12():
+    fam = learn.GridFamily(32, mg=True)
+    prob = fam.problem(17.0, 4)
+    u = fam.reference(prob)
+    p = Problem(inputs.square_mesh(32), nu=17.0, f="sine", seed=4)
+    assert _true_relres(p, u.cpu().numpy()) <= 1e-11

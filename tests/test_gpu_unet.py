@@ -167,3 +167,24 @@ def test_invalid_arguments():
         net.train_step(torch.zeros((1, 16, 16, 2), dtype=torch.float32, device="cuda"),
                        torch.zeros((1, 16, 16), dtype=torch.float32, device="cuda"), -1.0)
     del r
+
+
+def test_make_pair_matches_oracle_grid_mapping():
+    """fem_unet_make_pair: the input image is the oracle's grid_input of r, the
+    target the interior of u - x over its RMS (FP32 rounding apart)."""
+    N = 48
+    net = fem.UNet(N, N, channels=16, seed=1)
+    rng = np.random.default_rng(4)
+    n = (N + 1) ** 2
+    r, u, x = rng.standard_normal(n), rng.standard_normal(n), rng.standard_normal(n)
+    inp = torch.empty((N, N, 2), dtype=torch.float32, device="cuda")
+    tgt = torch.empty((N, N), dtype=torch.float32, device="cuda")
+    net.make_pair(N, torch.from_numpy(r).cuda(), torch.from_numpy(u).cuda(), torch.from_numpy(x).cuda(), 0.3,
+                  inp, tgt)
+    torch.cuda.synchronize()
+    ref = U.grid_input(r, N, 0.3)[0]
+    assert np.abs(inp.cpu().numpy() - ref).max() <= 1e-6 * np.abs(ref).max()
+    e = (u - x).reshape(N + 1, N + 1)[1:N, 1:N]
+    t = np.zeros((N, N))
+    t[:N - 1, :N - 1] = e / np.sqrt(np.mean(e ** 2))
+    assert np.abs(tgt.cpu().numpy() - t).max() <= 1e-6 * np.abs(t).max()
