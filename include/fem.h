@@ -162,6 +162,21 @@ int fem_element_residual(const fem_plan *plan, int dtype, const void *d_K_e, con
                          double nu, const double *d_b, const double *d_x, double *d_r,
                          int mask_dirichlet, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * residual as fem_element_residual, same arguments, validation and results
+ * bit for bit, with the shared-node partials of the element pass in a
+ * file-scope device array of the library (2^22 FP64 values, 32 MiB, held on
+ * every GPU the library runs on until the process ends) instead of the plan's
+ * workspace.  FEM_EINVAL if the plan has more than 2^22 shared-node partials
+ * (fem_plan_stats.n_partials).  Calls nothing that allocates.  Every call on
+ * one GPU uses that GPU's one array: calls that overlap on a GPU (two streams,
+ * two host threads) race and must be serialised by the caller.  No slot needs
+ * to start at zero: each one read is written earlier in the same call. */
+int fem_element_residual_noalloc(const fem_plan *plan, int dtype, const void *d_K_e, const void *d_M_e, double nu,
+                                 const double *d_b, const double *d_x, double *d_r, int mask_dirichlet,
+                                 void *stream);
+
 /* The same residual entirely in FP32: combined local matrices d_A_e (float,
  * [n_b*n_b][n_elems]), float vectors and float accumulation.  This is the
  * inner operator of the mixed-precision solver.  d_b may be NULL. */

@@ -652,3 +652,63 @@ int fem_fcg_solve(const fem_plan *plan_c, const fem_fcg_opts *o, fem_unet *net, 
 }
 
 }  // extern "C"
+
+// ---- Element residual without allocation -----------------------------------
+// The shared-node partials of the element pass live in one file-scope device
+// array instead of the plan's workspace.  In host code `scratch` names a
+// host-side stand-in; the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address reaches the kernels.
+
+namespace {
+
+constexpr int64_t kNoAllocPartials = (int64_t)1 << 22;  // FP64 partials: 32 MiB per GPU
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) double scratch[kNoAllocPartials];
+
+double *g_scratch_addr[kMaxDevices] = {};
+
+int scratch_address(double **out) {
+    int dev = 0;
+    FEM_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(FEM_EINVAL, "device index beyond the supported range");
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(FEM_EHIP, std::string("hipGetSymbolAddress of the scratch array failed: ") +
+                                           hipGetErrorString(e));
+        g_scratch_addr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fem_element_residual_noalloc(const fem_plan *plan, int dtype, const void *d_K_e, const void *d_M_e, double nu,
+                                 const double *d_b, const double *d_x, double *d_r, int mask_dirichlet,
+                                 void *stream) {
+    if (int rc = check_plan(plan)) return rc;
+    if (plan->dev.n_partials > kNoAllocPartials)
+        return set_error(FEM_EINVAL, "the plan has " + std::to_string(plan->dev.n_partials) +
+                                         " shared-node partials; the allocation-free residual holds at most " +
+                                         std::to_string(kNoAllocPartials) + " (use smaller meshes or larger chunks)");
+    const bool mf = dtype == FEM_MFREE;
+    if (!mf && !valid_dtype(dtype)) return set_error(FEM_EINVAL, "unknown dtype");
+    if ((!mf && !d_K_e && plan->dev.n_elems > 0) || !d_x || !d_r) return set_error(FEM_EINVAL, "NULL argument");
+    if ((mf || d_M_e) && (!std::isfinite(nu) || nu < 0.0)) return set_error(FEM_EINVAL, "nu must be finite and >= 0");
+    if ((const void *)d_r == (const void *)d_x || (d_b && (const void *)d_r == (const void *)d_b))
+        return set_error(FEM_EINVAL, "r must not alias x or b");
+    double *part = nullptr;
+    if (int rc = scratch_address(&part)) return rc;
+    const int mask = mask_dirichlet ? 1 : 0;
+    if (mf) return fem::launch_apply_mf(plan->dev, 1.0, nu, d_x, d_b, d_r, -1.0, mask, part, S(stream));
+    return fem::launch_apply64(plan->dev, dtype, d_K_e, (d_M_e && nu != 0.0) ? d_M_e : nullptr, nu, d_x, d_b, d_r,
+                               -1.0, mask, part, S(stream));
+}
+
+}  // extern "C"

@@ -143,6 +143,7 @@ _SIGS = {
     "fem_combine_local": [_vp, _int, _vp, _vp, _dbl, _int, _vp, _vp],
     "fem_element_residual": [_vp, _int, _vp, _vp, _dbl, _vp, _vp, _vp, _int, _vp],
     "fem_element_residual_f32": [_vp, _vp, _vp, _vp, _vp, _int, _vp],
+    "fem_element_residual_noalloc": [_vp, _int, _vp, _vp, _dbl, _vp, _vp, _vp, _int, _vp],
     "fem_jacobi_diag": [_vp, _int, _vp, _vp, _dbl, _vp, _vp],
     "fem_assemble_rhs": [_vp, _int, _vp, _vp, _vp, _vp],
     "fem_pcg_solve": [_vp, ctypes.POINTER(SolveOpts), _vp, _vp, _vp, _vp, ctypes.POINTER(SolveInfo), _vp],
@@ -350,6 +351,16 @@ def element_residual(plan, dtype, K, M, nu, b, x, r, mask=True, stream=None):
         _need(t, torch.float64, plan.n_nodes, w)
     _check(_lib.fem_element_residual(plan.handle, dtype, _ptr(K), _ptr(M), float(nu), _ptr(b), _ptr(x), _ptr(r),
                                      1 if mask else 0, _stream(stream)))
+
+
+def element_residual_noalloc(plan, dtype, K, M, nu, b, x, r, mask=True, stream=None):
+    """fem_element_residual_noalloc: element_residual with the library's static scratch (allocates nothing)."""
+    plan._mat(K, dtype, "K_e")
+    plan._mat(M, dtype, "M_e")
+    for t, w in ((b, "b"), (x, "x"), (r, "r")):
+        _need(t, torch.float64, plan.n_nodes, w)
+    _check(_lib.fem_element_residual_noalloc(plan.handle, dtype, _ptr(K), _ptr(M), float(nu), _ptr(b), _ptr(x),
+                                             _ptr(r), 1 if mask else 0, _stream(stream)))
 
 
 def element_residual_f32(plan, A, b, x, r, mask=True, stream=None):
