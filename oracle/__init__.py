@@ -53,7 +53,7 @@ def lib():
     """Load liborc.so, compiling it first if it has never been built."""
     global _LIB
     if _LIB is None:
-        path = library_path()
+        path = os.environ.get("ORACLE_LIB") or library_path()
         if not os.path.exists(path):
             build_oracle()
         L = ctypes.CDLL(path)

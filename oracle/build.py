@@ -7,15 +7,19 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def library_path() -> str:
-    return os.path.join(_HERE, "liborc.so")
+def library_path(sanitized: bool = False) -> str:
+    return os.path.join(_HERE, "liborc_san.so" if sanitized else "liborc.so")
 
 
-def build_oracle(verbose: bool = False) -> str:
+def build_oracle(verbose: bool = False, sanitized: bool = False) -> str:
+    """liborc.so, or with sanitized=True liborc_san.so built with the address
+    and undefined-behaviour sanitizers (loaded only when ORACLE_LIB names it)."""
     src = os.path.join(_HERE, "orc.c")
-    out = library_path()
+    out = library_path(sanitized)
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
+    flags = ["-O2"] if not sanitized else ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                                           "-fno-sanitize-recover=undefined"]
+    cmd = ["gcc", *flags, "-std=c99", "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter",
            src, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

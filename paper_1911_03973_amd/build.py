@@ -20,7 +20,7 @@ OBJ_DIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["plan.cpp", "local.hip", "apply.hip", "pcg.hip", "batch.hip", "api.hip", "batch_api.hip", "unet.hip",
+SOURCES = ["plan.cpp", "plan_check.cpp", "local.hip", "apply.hip", "pcg.hip", "batch.hip", "api.hip", "batch_api.hip", "unet.hip",
            "fcg.hip", "iterate.hip", "mg.hip"]
 
 COMMON = [
@@ -82,6 +82,28 @@ def build(verbose: bool = False) -> str:
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB
+
+
+# Host-only sources of the planner: plain C++, also built on their own with the
+# address and undefined-behaviour sanitizers (g++, no HIP).
+HOST_SOURCES = ("plan.cpp", "plan_check.cpp")
+SANITIZED_LIB = os.path.join(OBJ_DIR, "libplan_san.so")
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    """The host planner (fem_plan_check_host, fem_plan_check_host_p2) with
+    -fsanitize=address,undefined, for the sanitizer tests; returns its path."""
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    tmp = SANITIZED_LIB + ".tmp"
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fPIC", "-shared", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-I" + CSRC,
+           "-I" + os.path.join(ROOT, "include"), *[os.path.join(CSRC, f) for f in HOST_SOURCES], "-o", tmp,
+           "-lpthread"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, SANITIZED_LIB)
+    return SANITIZED_LIB
 
 
 if __name__ == "__main__":

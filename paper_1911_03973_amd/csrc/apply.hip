@@ -182,16 +182,6 @@ int device_cu_count() {
     return g_cu;
 }
 
-bool valid_chunk_elems(int nb, int E) {
-    switch (E) {
-        case 64: case 128: case 256: case 512: case 1024: case 1536: case 2048: break;
-        default: return false;
-    }
-    // FP64 slot buffer + uint16 slot list within kMaxChunkLds
-    return (size_t)nb * E * (8 + 2) <= (size_t)kMaxChunkLds;
-}
-
-int default_chunk_elems(int nb) { return nb == 3 ? 1024 : nb == 4 ? 1536 : nb == 6 ? 1024 : 512; }
 
 // Quadratic triangles: two elements per thread (their 21 packed values per
 // element leave room for no more; measured at 1024-element chunks: 512

@@ -7,12 +7,6 @@
 
 namespace fem {
 
-// Largest chunk the kernels accept: the FP64 slot buffer plus the uint16 slot
-// list of one chunk must fit in 64 KiB of LDS.
-constexpr int kMaxChunkLds = 65536;
-
-bool valid_chunk_elems(int nb, int E);
-int default_chunk_elems(int nb);
 // Default workgroup size of the solver's element pass for a chunk size.
 int default_block(int nb, int E);
 int device_cu_count();

@@ -7,6 +7,18 @@
 
 namespace fem {
 
+// Largest chunk the kernels accept: the FP64 slot buffer plus the uint16 slot
+// list of one chunk must fit in 64 KiB of LDS.
+constexpr int kMaxChunkLds = 65536;
+
+bool valid_chunk_elems(int nb, int E);
+int default_chunk_elems(int nb);
+
+// Thread-local message of the last failed call, and the setter every error
+// path uses (returns code).
+std::string &last_error();
+int set_error(int code, const std::string &msg);
+
 struct HostPlan {
     int dim = 0, nb = 0, E = 0;
     int64_t n_nodes = 0, n_elems = 0, n_chunks = 0;
