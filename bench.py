@@ -119,6 +119,147 @@ def cpu_baseline(mesh, w, seconds):
     }
 
 
+def host_facts():
+    """Host CPU of this run: model name, logical CPUs, CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
+
+
+def cpu_allcores(mesh, w, seconds):
+    """The FP64 oracle's element residual on every usable host core (at most 16, this machine's CPU share per
+    GPU): the element list cut into one contiguous range per thread, each range through the unchanged
+    oracle routine with b absent (ctypes releases the GIL during the call), the partial residuals added
+    pairwise in a fixed tree.  Checked against the one-thread oracle to 1e-12."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+
+    facts = host_facts()
+    T = max(1, min(16, facts["usable_cpus"]))
+    K, M, _ = oracle.local_matrices(mesh.coords, mesh.elems)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(mesh.n_nodes)
+    b = rng.standard_normal(mesh.n_nodes)
+    mask = oracle.mask_from_nodes(mesh.n_nodes, inputs_boundary(mesh, w))
+    bm = np.where(mask != 0, 0.0, b)
+    cut = np.linspace(0, mesh.n_elems, T + 1).astype(np.int64)
+    nu = w["nu"]
+
+    def part(t):
+        a, e = cut[t], cut[t + 1]
+        return oracle.residual(mesh.n_nodes, mesh.elems[a:e], K[a:e], M[a:e], nu, None, x, mask)
+
+    def add(ab):
+        ab[0] += ab[1]
+        return ab[0]
+
+    with ThreadPoolExecutor(T) as pool:
+        def call():
+            # the partials added pairwise in a fixed tree, each level's sums on the threads
+            parts = list(pool.map(part, range(T)))
+            while len(parts) > 1:
+                nxt = list(pool.map(add, [(parts[i], parts[i + 1]) for i in range(0, len(parts) - 1, 2)]))
+                parts = nxt + ([parts[-1]] if len(parts) % 2 else [])
+            return parts[0] + bm
+
+        ref = oracle.residual(mesh.n_nodes, mesh.elems, K, M, nu, b, x, mask)
+        r = call()
+        assert np.abs(r - ref).max() <= 1e-12 * np.abs(ref).max(), "threaded oracle residual differs"
+        calls, t0 = 0, time.perf_counter()
+        while True:
+            call()
+            calls += 1
+            el = time.perf_counter() - t0
+            if el >= seconds and calls >= 2:
+                break
+    per = el / calls
+    nb = mesh.nb
+    bytes_call = mesh.n_elems * (nb * nb * 8 + 4 * nb) + mesh.n_nodes * 3 * 8
+    return {"value": round(bytes_call / per / 1e9, 3), "unit": "GB/s", "cores": T, "kind": "oracle",
+            "sample": f"{calls} calls of the FP64 oracle element residual on the full mesh split over {T} threads, "
+                      f"{per * 1e3:.1f} ms each, {mesh.n_elems / per:.3e} elements/s", **facts}
+
+
+def oracle_pcg_times(seconds, c3_iters=None, c5_iters=None):
+    """The FP64 oracle's Jacobi-PCG (one host thread): C1 solved to 1e-8 in full; on C5 (1024^2, nu 35.55,
+    random-sine f seed 5002) and C3 the time per iteration from a capped run, and the time to 1e-8
+    projected with the GPU's Jacobi-PCG iteration count for the same problem."""
+    import numpy as np
+
+    import oracle
+    from paper_1911_03973_amd import inputs
+
+    out = {}
+    w = WORKLOADS["c1"]
+    mesh, nd, f = make_problem(w)
+    K, M, _ = oracle.local_matrices(mesh.coords, mesh.elems)
+    mask = oracle.mask_from_nodes(mesh.n_nodes, nd)
+    b = oracle.rhs(mesh.n_nodes, mesh.elems, M, f)
+    t = time.perf_counter()
+    _, info = oracle.pcg(mesh.n_nodes, mesh.elems, K, M, w["nu"], b, mask, np.zeros(mesh.n_nodes), rtol=1e-8)
+    out["c1"] = {"time_to_1e8_s": round(time.perf_counter() - t, 4), "iters": info["iters"],
+                 "relres": info["relres"]}
+
+    def capped(name, mesh, nd, nu, f, iters_gpu):
+        K, M, _ = oracle.local_matrices(mesh.coords, mesh.elems)
+        mask = oracle.mask_from_nodes(mesh.n_nodes, nd)
+        b = oracle.rhs(mesh.n_nodes, mesh.elems, M, f)
+        x0 = np.zeros(mesh.n_nodes)
+        t = time.perf_counter()
+        oracle.pcg(mesh.n_nodes, mesh.elems, K, M, nu, b, mask, x0, rtol=1e-30, max_iter=3, raise_on_noconv=False)
+        per = (time.perf_counter() - t) / 3
+        k = max(3, min(2000, int(seconds / max(per, 1e-9))))
+        t = time.perf_counter()
+        _, info = oracle.pcg(mesh.n_nodes, mesh.elems, K, M, nu, b, mask, x0, rtol=1e-30, max_iter=k,
+                             raise_on_noconv=False)
+        per = (time.perf_counter() - t) / max(info["iters"], 1)
+        out[name] = {"iters_run": info["iters"], "s_per_iter": round(per, 5),
+                     "gpu_jacobi_pcg_iters": iters_gpu,
+                     "projected_time_to_1e8_s": round(per * iters_gpu, 2) if iters_gpu else None}
+
+    m5 = inputs.square_mesh(1024)
+    capped("c5", m5, inputs.boundary_nodes(m5, "all"), 35.547, inputs.random_sine(m5.coords, 5002), c5_iters)
+    del m5
+    w = WORKLOADS["c3"]
+    m3, nd3, f3 = make_problem(w)
+    capped("c3", m3, nd3, w["nu"], f3, c3_iters)
+    return out
+
+
+def other_configs(args):
+    """C3, C1 and C4 on the same GPU after the headline workload (fewer timed steps)."""
+    import argparse
+
+    out = {}
+    r = measure_single(args, "c3", steps=3, warmup=1)
+    out["c3"] = {"workload": r["config"]["workload"], "fused_pass_GBps": r["value"], "frac": r["roofline"]["frac"],
+                 "matvec_us": r["matvec_us"], "matvec_bytes": r["matvec_bytes"],
+                 "elements_per_s": r["elements_per_s"], "time_to_1e8_s": r["time_to_1e8_s"],
+                 "iters": r["iters"][-1], "relres": max(r["relres"]), "converged": r["converged"],
+                 "residual_kernels": r["residual_kernels"]}
+    r = measure_single(args, "c1", steps=10, warmup=2, residual=False)
+    out["c1"] = {"workload": r["config"]["workload"], "time_to_1e8_s": r["time_to_1e8_s"], "iters": r["iters"][-1],
+                 "relres": max(r["relres"]), "converged": r["converged"],
+                 "note": "0.8 MB of element data: cache-resident, launch-latency bound"}
+    a4 = argparse.Namespace(**vars(args))
+    a4.steps, a4.warmup = 1, 1
+    r = run_batched(a4, WORKLOADS["c4"])
+    out["c4"] = {"workload": r["config"]["workload"], "time_to_1e8_s": r["time_to_1e8_s"], "GBps": r["value"],
+                 "frac": r["roofline"]["frac"], "all_converged": r["all_converged"], "max_relres": r["max_relres"],
+                 "iters_total": r["iters_total"], "schedule": r["schedule"]}
+    return out
+
+
 def residual_kernels(fem, plan, mesh, K, M, nu, dt, calls):
     """Standalone element residuals r = b - A x on the same mesh (full n_b x n_b storage)."""
     import torch
@@ -261,7 +402,7 @@ def run_batched(args, w):
                      "adaptive": args.adaptive},
         "autotune": tuned,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
@@ -615,6 +756,8 @@ def main():
                     help="batched: regroup work items as problems finish (1) or keep the fixed schedule (0)")
     ap.add_argument("--autotune", action="store_true", help="batched: pick the schedule with the autotuner first")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-FCG vs Jacobi-PCG comparison")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="c2: skip the C3 / C1 / C4 legs and the all-core and PCG oracle timings")
     ap.add_argument("--learned-n", type=int, default=1024)
     ap.add_argument("--learned-problems", type=int, default=160, help="training problems")
     ap.add_argument("--learned-segments", default="4x25,8x25,12x25,16x25,20x25",
@@ -648,15 +791,42 @@ def main():
     if args.workload == "learned":
         print(json.dumps({"learned_fcg": learned_fcg(args)}), flush=True)
         return
-    w = WORKLOADS[args.workload]
     if args.workload == "c4":
-        return run_batched(args, w)
+        print(json.dumps(run_batched(args, WORKLOADS["c4"])), flush=True)
+        return
+    torch.cuda.set_device(0)
+    out = measure_single(args, args.workload, args.steps, args.warmup)
+    out["learned_fcg"] = None if args.no_learned else learned_fcg(args)
+    if args.workload == "c2" and not args.no_extra:
+        out["other_configs"] = other_configs(args)
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        w = WORKLOADS[args.workload]
+        mesh, _, _ = make_problem(w)
+        out["cpu_baseline"] = cpu_baseline(mesh, w, args.cpu_seconds)
+        if args.workload == "c2" and not args.no_extra:
+            out["cpu_allcores"] = cpu_allcores(mesh, w, args.cpu_seconds / 2)
+            del mesh
+            c3 = (out.get("other_configs") or {}).get("c3") or {}
+            lf = out.get("learned_fcg") or {}
+            c5 = next((p["pcg_iters"] for p in lf.get("problems", []) if abs(p["nu"] - 35.547) < 1e-3), None)
+            out["oracle_pcg"] = oracle_pcg_times(args.cpu_seconds / 2, c3.get("iters"), c5)
+    print(json.dumps(out), flush=True)
+
+
+def measure_single(args, wname, steps, warmup, residual=True):
+    """One single-problem workload: `steps` timed solves after `warmup` ones; the line's fields."""
+    import numpy as np
+    import torch
+
+    from paper_1911_03973_amd import fem
+
+    w = WORKLOADS[wname]
     mfree = args.operator == "mfree"
     dt = fem.MFREE if mfree else {"f64": fem.F64, "f32x2": fem.F32X2}[w["dtype"]]
-    log(f"[bench] workload {args.workload}: building inputs")
+    log(f"[bench] workload {wname}: building inputs")
     mesh, nd, f = make_problem(w)
     log(f"[bench] mesh {mesh.n_nodes} nodes {mesh.n_elems} elements; plan")
-    torch.cuda.set_device(0)
     t = time.perf_counter()
     # matrix-free in 3D: 512-tet chunks (the coordinate table and slot index
     # of 1536-tet chunks leave one workgroup per CU)
@@ -686,19 +856,19 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    for i in range(args.warmup):
+    for i in range(warmup):
         info = step()
         log(f"[bench] warmup {i}: {info}")
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         infos.append(step())
         log(f"[bench] step {i}: iters {infos[-1]['iters']} relres {infos[-1]['relres']:.3e} "
             f"solve {infos[-1]['seconds']:.3f} s")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ms_per_step = (t1 - t0) * 1e3 / steps
     mv_ms = sum(i["matvec_ms"] for i in infos)
     mv_n = sum(i["matvec_samples"] for i in infos)
     nb = mesh.nb
@@ -714,8 +884,8 @@ def main():
     ok = all(i["status"] == 0 and i["relres"] <= 1e-8 for i in infos)
     if args.max_iter < 200000:
         log("[bench] capped iterations: a profiling run, not a time-to-1e-8 measurement")
-    resid = residual_kernels(fem, plan, mesh, K, M, w["nu"], dt, args.residual_calls)
-    rec = (measured_traffic() if args.workload == "c2" and args.vectors == 0 and args.block == 0 and not mfree
+    resid = residual_kernels(fem, plan, mesh, K, M, w["nu"], dt, args.residual_calls) if residual else None
+    rec = (measured_traffic() if wname == "c2" and args.vectors == 0 and args.block == 0 and not mfree
            else None)
     traffic = rec["bytes_per_pass"] if rec and rec.get("chunk_elems") == st["chunk_elems"] else None
     out = {
@@ -723,8 +893,8 @@ def main():
         "value": round(gbs, 2),
         "unit": "GB/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
@@ -757,16 +927,14 @@ def main():
         "relres": [i["relres"] for i in infos],
         "converged": ok,
         "plan_seconds": round(t_plan, 3),
-        "learned_fcg": None if args.no_learned else learned_fcg(args),
         "pass_kind": ("fused CG pass, matrix-free (packed form rebuilt from coordinates), FP64 vectors" if mfree
                       else "fused CG pass, packed difference form (%d values/elem, %s), %s vectors"
                       % (n_pk, "FP32 heads" if dt != fem.F64 else "FP64", "FP32" if s_v == 4 else "FP64")),
         "residual_kernels": resid,
     }
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(mesh, w, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    del K, M, plan
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":
