@@ -114,6 +114,33 @@ def test_training_step_is_bitwise_reproducible_and_adam_exact():
     assert torch.equal(runs[0][2], runs[1][2])
 
 
+def test_three_adam_steps_match_oracle_adam():
+    """Three training steps with cosine-decayed learning rates against the
+    oracle's Adam (bias-corrected moments) fed with the gradients the library
+    reports at each step's starting point: the moment recursions and the bias
+    corrections of steps 2 and 3, not only the first step's g / |g|."""
+    from paper_1911_03973_amd import learn
+
+    H, B = 32, 2
+    inp, t = _inputs(B, H, H, 5)
+    inp, t = torch.from_numpy(inp).cuda(), torch.from_numpy(t).cuda()
+    net = fem.UNet(H, H, max_batch=B, channels=16, seed=12)
+    w0 = net.get_params().double().cpu().numpy()
+    lrs = [learn._lr(s, 3, 1e-4, 5e-6) for s in range(3)]
+    grads = []
+    for lr in lrs:
+        _, g = net.loss_grad(inp, t)
+        grads.append(g.double().cpu().numpy())
+        net.train_step(inp, t, lr)
+    w3 = net.get_params().double().cpu().numpy()
+    want = U.adam(w0, grads, lrs)
+    tol = 2e-7 + 1e-6 * np.abs(want).max()
+    assert np.abs(w3 - want).max() <= tol
+    # a wrong bias correction or moment recursion moves the weights by O(lr)
+    wrong = U.adam(w0, grads, [lr * 0.8 for lr in lrs])
+    assert np.abs(wrong - want).max() > 10 * tol
+
+
 def test_training_reduces_loss():
     H, B = 32, 4
     inp, t = _inputs(B, H, H, 6)
