@@ -291,8 +291,11 @@ int fem_plan_create_p2(int dim, int64_t n_nodes, int64_t n_elems, const double *
 int fem_plan_destroy(fem_plan *plan) {
     if (!plan) return FEM_OK;
     int rc = FEM_OK;
-    for (auto &w : plan->work)
+    for (auto &w : plan->work) {
+        if (w.graph && hipGraphExecDestroy(w.graph) != hipSuccess) rc = FEM_EHIP;
+        if (w.cap && hipStreamDestroy(w.cap) != hipSuccess) rc = FEM_EHIP;
         if (w.arena && hipFree(w.arena) != hipSuccess) rc = FEM_EHIP;
+    }
     if (plan->arena && hipFree(plan->arena) != hipSuccess) rc = FEM_EHIP;
     delete plan;
     if (rc) set_error(rc, "hipFree failed");

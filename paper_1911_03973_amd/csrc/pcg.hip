@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_x(int64_t n, const int32_t *
 // One workgroup: totals of the dot partials in slots [first, npart), then the
 // scalar recurrence.
 __global__ __launch_bounds__(kBlock) void k_finalize(IterState *st, const double *__restrict__ dots, int npart,
-                                                     int first, double thr2, double rel2) {
+                                                     int first) {
     __shared__ double red[kDots * (kBlock / kWave)];
     if (st->flag) return;
     // every thread sums a fixed, strided subset of each partial list, four
@@ -276,6 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(IterState *st, const double
     st->n_updates += 1;
     st->rz_next = rzn;
     st->rr_next = rrn;
+    const double thr2 = st->thr2, rel2 = st->rel2;
     if (!(rrn > thr2) || (rel2 > 0.0 && rrn < rel2) || !(rzn > 0.0) || !isfinite(rrn)) {
         st->flag = 1;  // the host refreshes; rz stays that of the residual behind p
         return;
@@ -326,9 +327,10 @@ __global__ __launch_bounds__(kBlock) void k_init_dots(int64_t n, VT *__restrict_
 
 // One workgroup: a fresh residual's totals into the state; the next element
 // pass starts a new p (first) or continues the old one with
-// beta = r'.z' / r.z (fresh).
+// beta = r'.z' / r.z (fresh).  The refresh triggers follow: the target
+// (tscale ||r_0||)^2 at the first refresh, delta^2 r.r at every one.
 __global__ __launch_bounds__(kBlock) void k_refresh_state(IterState *st, const double *__restrict__ upd, int n_upd,
-                                                          int first) {
+                                                          int first, double tscale, double dd) {
     __shared__ double red[kBlock / kWave];
     const double rz = reduce_partials(upd, n_upd, red);
     const double rr = reduce_partials(upd + n_upd, n_upd, red);
@@ -345,6 +347,8 @@ __global__ __launch_bounds__(kBlock) void k_refresh_state(IterState *st, const d
         st->rz = rz;
         st->rr = rr;
         st->rr64 = r64;
+        if (first) st->thr2 = (tscale * sqrt(r64)) * (tscale * sqrt(r64));
+        st->rel2 = dd * rr;
         st->flag = 0;
         st->pending = 0;
         st->alpha = 0.0;
@@ -452,6 +456,7 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, double nu, const double
     OpIter<VT> op{xv, r, p, q, dinv, sx, sr, sp, sq, sd, w.st, w.dots, npart, fin_first, 0, 0.0, 0.0,
                   {0, 0, 0, 0, 0, 0, 0}};
     auto scatter_x = [&]() { k_scatter_x<VT><<<gv, kBlock, 0, s>>>(n, w.perm, xv, x64, fold ? 1 : 0); };
+    const double dd = delta > 0.0 ? delta * delta : 0.0;  // reliable-update factor (0: refresh only at the target)
 
     // refresh: finish the pending step, x back to mesh order, true FP64
     // residual of x64 into r64 -> local r, totals into the state
@@ -462,7 +467,7 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, double nu, const double
                               : launch_apply_pk64(P, pk_kind, w.Apk, x64, b, w.r64, -1.0, 1, w.part64, s);
         if (rc) return rc;
         k_init_dots<VT><<<gu, kBlock, 0, s>>>(n, r, dinv, w.r64, w.perm, w.upd);
-        k_refresh_state<<<1, kBlock, 0, s>>>(w.st, w.upd, gu, first);
+        k_refresh_state<<<1, kBlock, 0, s>>>(w.st, w.upd, gu, first, kCertify * rtol, dd);
         FEM_HIP_CHECK(hipGetLastError());
         return 0;
     };
@@ -480,16 +485,47 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, double nu, const double
         return FEM_OK;
     }
     const double target = kCertify * rtol * r0;
-    const double thr2 = target * target;
-    const double dd = delta > 0.0 ? delta * delta : 0.0;
-    double rel2 = dd * h.rr;
     EventPool ev;
     if (profile > 0 && (rc = ev.ensure(check_every))) return rc;
     int launched = 0, refreshes = 0, status = FEM_OK;
     int64_t calls = 0;
+    // one iteration: element pass, fix-up, finalize
+    auto iteration = [&](hipStream_t st) {
+        k_chunk_main<NB, EPT, BS, VT, LdT, OpIter<VT>, false><<<cg.grid, BS, lds, st>>>(P, ld, op, partv, cg.xcd);
+        if (gf) k_chunk_fixup<kFixBlock, VT, OpIter<VT>><<<gf, kFixBlock, 0, st>>>(P, op, partv, cg.grid);
+        k_finalize<<<1, kBlock, 0, st>>>(w.st, w.dots, npart, fin_first);
+    };
+    // without per-pass timing, check_every iterations replay as one HIP graph,
+    // captured once per workspace and kernel instance
+    const void *key = reinterpret_cast<const void *>(&k_chunk_main<NB, EPT, BS, VT, LdT, OpIter<VT>, false>);
+    if (profile == 0 && check_every > 1 && (w.graph_key != key || w.graph_m != check_every)) {
+        if (w.graph) {
+            FEM_HIP_CHECK(hipGraphExecDestroy(w.graph));
+            w.graph = nullptr;
+            w.graph_key = nullptr;
+        }
+        if (!w.cap) FEM_HIP_CHECK(hipStreamCreateWithFlags(&w.cap, hipStreamNonBlocking));
+        hipGraph_t g;
+        FEM_HIP_CHECK(hipStreamBeginCapture(w.cap, hipStreamCaptureModeThreadLocal));
+        for (int j = 0; j < check_every; ++j) iteration(w.cap);
+        const hipError_t e = hipStreamEndCapture(w.cap, &g);
+        if (e != hipSuccess) return set_error(FEM_EHIP, "capture of the CG iterations failed");
+        const hipError_t ei = hipGraphInstantiate(&w.graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            w.graph = nullptr;
+            return set_error(FEM_EHIP, "instantiation of the CG iteration graph failed");
+        }
+        w.graph_key = key;
+        w.graph_m = check_every;
+    }
+    const bool use_graph = profile == 0 && check_every > 1 && w.graph_key == key;
     while (true) {
         const int m = std::min(check_every, max_iter - launched);
-        for (int j = 0; j < m; ++j) {
+        if (use_graph && m == check_every) {
+            FEM_HIP_CHECK(hipGraphLaunch(w.graph, s));
+            calls += m;
+        } else for (int j = 0; j < m; ++j) {
             const bool timed = profile > 0 && ((launched + j) % profile == 0) && ev.used < (int)ev.a.size();
             if (timed) FEM_HIP_CHECK(hipEventRecord(ev.a[ev.used], s));
             k_chunk_main<NB, EPT, BS, VT, LdT, OpIter<VT>, false>
@@ -499,7 +535,7 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, double nu, const double
                 FEM_HIP_CHECK(hipEventRecord(ev.b[ev.used], s));
                 ev.used++;
             }
-            k_finalize<<<1, kBlock, 0, s>>>(w.st, w.dots, npart, fin_first, thr2, rel2);
+            k_finalize<<<1, kBlock, 0, s>>>(w.st, w.dots, npart, fin_first);
             FEM_HIP_CHECK(hipGetLastError());
             ++calls;
         }
@@ -521,7 +557,6 @@ int cg_run(const DevPlan &P, SolverWork &w, int pk_kind, double nu, const double
                 status = FEM_ENOCONV;
                 break;
             }
-            rel2 = dd * h.rr;
         }
         if (launched >= max_iter) {
             status = FEM_ENOCONV;

@@ -38,6 +38,8 @@ struct IterState {
     double rz_next, rr_next;
     double rr64;    // r.r of the FP64 residual at the last refresh
     double pq;      // last p.q
+    double thr2;    // (kCertify rtol ||r_0||)^2: a recursive r.r at or below it triggers a refresh
+    double rel2;    // delta^2 r.r at the last refresh: the reliable-update trigger (0: none)
 };
 
 struct Grids {
@@ -63,6 +65,13 @@ struct SolverWork {
     double *upd = nullptr;        // [3][gu] init partials
     IterState *st = nullptr;
     int *bad = nullptr;
+    // check_every iterations of the element pass, fix-up and finalize captured
+    // into a HIP graph (kernel arguments are all workspace pointers and plan
+    // sizes, so one capture serves every later solve with the same kernels)
+    hipStream_t cap = nullptr;
+    hipGraphExec_t graph = nullptr;
+    const void *graph_key = nullptr;
+    int graph_m = 0;
 };
 
 Grids solver_grids(const DevPlan &P, size_t elem_lds);

@@ -142,3 +142,27 @@ def test_solve_is_bitwise_reproducible():
         fem.pcg_solve(plan, fem.solve_opts(dtype=fem.F32X2, nu=1.0), K, M, cuda(prob.b), x)
         outs.append(x.cpu().numpy())
     np.testing.assert_array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("dtype,check_every", [(fem.F64, 7), (fem.F32X2, 16), (fem.F32X2, 1)])
+def test_graph_replayed_iterations_equal_eager_launches(dtype, check_every):
+    """Without per-pass timing (profile = 0) check_every iterations replay as one
+    HIP graph, captured once and reused by later solves; with profile > 0 every
+    kernel is launched on its own.  Three graph solves in a row, with the
+    refreshes and state reads between the replays, give the eager solve's
+    iterate bit for bit and its iteration count."""
+    mesh = inputs.square_mesh(48, jitter=0.2, seed=6)
+    prob = Problem(mesh, nu=2.0, dirichlet="x2=0", f="sine", seed=3)
+    plan = fem.Plan.from_mesh(mesh, prob.nd, chunk_elems=256)
+    K, M = _setup(prob, plan, dtype)
+    b = cuda(prob.b)
+    runs = []
+    for profile in (1, 0, 0, 0):
+        x = cuda(_x0(prob))
+        info = fem.pcg_solve(plan, fem.solve_opts(dtype=dtype, nu=2.0, check_every=check_every, profile=profile),
+                             K, M, b, x)
+        assert info["status"] == 0
+        runs.append((x.cpu().numpy(), info["iters"], info["relres"]))
+    for x, it, rr in runs[1:]:
+        np.testing.assert_array_equal(x, runs[0][0])
+        assert it == runs[0][1] and rr == runs[0][2]
