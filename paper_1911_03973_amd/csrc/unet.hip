@@ -45,8 +45,32 @@ namespace {
 typedef __bf16 bf16;
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPixTile = 64;   // pixels per GEMM workgroup (4 waves x 16)
+
+// Bytes of a conv tile's staged input (TY + 2) x (TX + 2) pixels x Cin BF16,
+// rounded to 16.
+__host__ __device__ constexpr size_t conv_tile_bytes(int TY, int TX, int Cin) {
+    return ((size_t)(TY + 2) * (TX + 2) * Cin * 2 + 15) & ~(size_t)15;
+}
+// Reduction blocks of weights per LDS stage of the tiled convolution (1 KiB
+// per block and column tile): all KB in one stage when they take at most
+// 16 KiB; otherwise two alternating stages of at most 16 KiB each within the
+// 64 KiB budget left by the input tile.
+__host__ __device__ constexpr int conv_kbc(int KB, int NT, size_t tile) {
+    return KB * NT <= 16 ? KB
+                         : ((int)((65536 - (tile < 65536 ? tile : 65536)) / (2 * 1024 * NT)) < 16 / NT
+                                ? ((int)((65536 - (tile < 65536 ? tile : 65536)) / (2 * 1024 * NT)) > 0
+                                       ? (int)((65536 - (tile < 65536 ? tile : 65536)) / (2 * 1024 * NT))
+                                       : 1)
+                                : (16 / NT > 0 ? 16 / NT : 1));
+}
+// LDS of the tiled convolution: input tile and one or two weight stages
+__host__ __device__ constexpr size_t conv_lds_bytes(int TY, int TX, int Cin, int KB, int NT) {
+    return conv_tile_bytes(TY, TX, Cin) +
+           (size_t)(KB * NT <= 16 ? 1 : 2) * conv_kbc(KB, NT, conv_tile_bytes(TY, TX, Cin)) * NT * 1024;
+}
 constexpr int kWSlice = 4096;  // pixels per weight-gradient slice
 
 __device__ __forceinline__ f4 mfma(bf8 a, bf8 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
@@ -193,94 +217,187 @@ __global__ __launch_bounds__(256) void k_gemm_rows(Src src, Epi epi, const bf16 
 
 // LDS-tiled 3x3 convolution forward (+ bias, ReLU).  A workgroup of 4 waves
 // owns a TY x TX pixel tile of one image: the tile's input with a one-pixel
-// halo ([C1 channels of src1 | C2 of src2]) is staged in LDS once, so every
-// input value is read once per tile instead of once per tap; the packed weight
-// fragments stream through LDS in blocks of kbc reduction blocks, shared by the
-// 4 waves.  Wave w computes tile pixels [64 MT/4 * w ...) as MT row tiles of
-// 16 pixels against all NT column tiles.  Pixels outside the image are
-// computed on zero input and not stored.
-// Cin = C1 + C2 is a power of two (2^lcin): the (tap, channel) split of a
-// reduction index and the staging loop's (pixel, channel group) split are
-// shifts and masks (runtime divisions made this kernel VALU-bound).
-template <int TY, int TX, int NT>
-__global__ __launch_bounds__(256) void k_conv_tiled(const bf16 *__restrict__ src1, const bf16 *__restrict__ src2,
-                                                    int C1, int C2, int lcin, int H, int W, int tiles_x, int tiles_y,
-                                                    const bf16 *__restrict__ Bp, int KB, int kbc,
-                                                    const float *__restrict__ bias, bf16 *__restrict__ out) {
+// halo ([C1 channels of src1 | CIN - C1 of src2]) is staged in LDS once, so
+// every input value is read once per tile instead of once per tap; the packed
+// weight fragments are staged in blocks of KBC reduction blocks (all of them
+// when they fit in 16 KiB, else two alternating stages, the next one loaded
+// while the current one is used), shared by the 4 waves.  Wave w computes tile
+// pixels [64 MT/4 * w ...) as MT tiles of 16 pixels against all NT tiles of
+// 16 output channels.  The product is taken transposed, D^T = W^T A^T: the
+// weight fragment is the MFMA's first operand (rows = output channels) and the
+// pixels its second, so that each lane ends with four consecutive output
+// channels of one pixel and stores them as one 8-byte word, sixteen lanes
+// covering 16 consecutive pixels of an NHWC row.  CIN is a template constant,
+// so the (tap, channel) of every reduction block is a shift and a mask of
+// compile-time values and the reduction loop is unrolled.  Pixels outside the
+// image are computed on zero input and not stored; reduction entries past the
+// 9 taps (padding of the last block) have zero weights and read the last
+// tap's finite inputs.
+template <int TY, int TX, int NT, int CIN>
+__global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ src1, const bf16 *__restrict__ src2, int C1,
+                                                 int H, int W, int tiles_x, int tiles_y, const bf16 *__restrict__ Bp,
+                                                 const float *__restrict__ bias, bf16 *__restrict__ out) {
     constexpr int MT = TY * TX / 64;
     constexpr int HX = TX + 2, HY = TY + 2;
+    constexpr int KB = (9 * CIN + 31) / 32;
+    constexpr int KBC = conv_kbc(KB, NT, conv_tile_bytes(TY, TX, CIN));
+    constexpr int NBLK = (KB + KBC - 1) / KBC;  // weight stages
+    constexpr int FR = (KBC * NT * 64 + 255) / 256;  // weight fragments per thread and stage
+    constexpr int CU8 = CIN / 8;
+    constexpr int N = NT * 16;
+    static_assert(CIN >= 8 && (CIN & (CIN - 1)) == 0, "CIN must be a power of two >= 8");
+    static_assert(TX % 16 == 0 && (TY * TX) % 64 == 0, "tile shape");
     extern __shared__ __align__(16) unsigned char smem[];
-    const int Cin = C1 + C2, cu8 = Cin / 8, lcu = lcin - 3;
-    bf16 *tin = reinterpret_cast<bf16 *>(smem);  // [HY][HX][Cin]
-    bf16 *tb = reinterpret_cast<bf16 *>(smem + (((size_t)HY * HX * Cin * 2 + 15) & ~(size_t)15));
+    bf16 *tin = reinterpret_cast<bf16 *>(smem);  // [HY * HX][CIN]
+    bf8 *tb0 = reinterpret_cast<bf8 *>(smem + conv_tile_bytes(TY, TX, CIN));  // [KBC][NT][64], two when NBLK > 1
+    bf8 *tb1 = tb0 + KBC * NT * 64;
+    const int C2 = CIN - C1;
     const int tile = blockIdx.x;
     const int tx = tile % tiles_x, t2 = tile / tiles_x, ty = t2 % tiles_y, b = t2 / tiles_y;
     const int y0 = ty * TY, x0 = tx * TX;
-    for (int u = threadIdx.x; u < HY * HX * cu8; u += 256) {
-        const int cu = u & (cu8 - 1), pp = u >> lcu;
+    const int64_t img = (int64_t)b * H * W;
+    for (int u = threadIdx.x; u < HY * HX * CU8; u += 256) {
+        const int cu = u % CU8, pp = u / CU8;
         const int yy = y0 + pp / HX - 1, xx = x0 + pp % HX - 1;
         bf8 v = zero8();
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-            const int64_t pix = ((int64_t)b * H + yy) * W + xx;
+        if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W) {
+            const int64_t pix = img + (int64_t)yy * W + xx;
             const int ci = cu * 8;
             v = ci < C1 ? ld8(src1 + pix * C1 + ci) : ld8(src2 + pix * C2 + (ci - C1));
         }
-        *reinterpret_cast<bf8 *>(tin + (size_t)pp * Cin + cu * 8) = v;
+        *reinterpret_cast<bf8 *>(tin + pp * CIN + cu * 8) = v;
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    f4 acc[MT][NT];
-    int hoff[MT];  // halo-tile pixel of this lane's row in each row tile
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
+    int hoff[MT];  // LDS element offset of this lane's pixel in row tile mt
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int p = (wave * MT + mt) * 16 + (lane & 15);
-        hoff[mt] = (p / TX) * HX + p % TX;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) acc[mt][t] = f4{0.f, 0.f, 0.f, 0.f};
+        hoff[mt] = ((p / TX) * HX + p % TX) * CIN;
     }
-    for (int kc = 0; kc < KB; kc += kbc) {
-        const int nkb = min(kbc, KB - kc);
-        __syncthreads();  // the input tile is staged / the previous weight block is consumed
-        const bf8 *srcB = reinterpret_cast<const bf8 *>(Bp) + (size_t)kc * NT * 64;
-        for (int u = threadIdx.x; u < nkb * NT * 64; u += 256) reinterpret_cast<bf8 *>(tb)[u] = srcB[u];
-        __syncthreads();
-        for (int kl = 0; kl < nkb; ++kl) {
-            const int k0 = (kc + kl) * 32 + 8 * (lane >> 4);
-            // past the 9 taps (the last block's padding) the packed weights are
-            // zero: read the last tap's (finite) inputs instead of selecting zeros
-            const int tap = min(k0 >> lcin, 8), ci = k0 & (Cin - 1);
-            const int toff = (tap / 3) * HX + tap % 3;
-            bf8 a[MT];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) a[mt] = *reinterpret_cast<const bf8 *>(tin + (size_t)(hoff[mt] + toff) * Cin + ci);
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const bf8 bv = *reinterpret_cast<const bf8 *>(tb + ((size_t)(kl * NT + t) * 64 + lane) * 8);
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[mt][t] = mfma(a[mt], bv, acc[mt][t]);
-            }
-        }
-    }
-    constexpr int N = NT * 16;
-    float bv[NT];  // this lane's output channels' biases, loaded once
-#pragma unroll
-    for (int t = 0; t < NT; ++t) bv[t] = bias[t * 16 + (lane & 15)];
-    const bool full = y0 + TY <= H && x0 + TX <= W;  // no pixel of the tile outside the image
-    bf16 *ob = out + (((int64_t)b * H + y0) * W + x0) * N + (lane & 15);
+    f4 acc[MT][NT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int p = (wave * MT + mt) * 16 + 4 * (lane >> 4) + i;
-            const int py = p / TX, px = p % TX;
-            if (full || (y0 + py < H && x0 + px < W)) {
-                bf16 *o = ob + ((int64_t)py * W + px) * N;
+        for (int t = 0; t < NT; ++t) acc[mt][t] = f4{0.f, 0.f, 0.f, 0.f};
+    const bf8 *wsrc = reinterpret_cast<const bf8 *>(Bp);
+    {
+        constexpr int n0 = (KBC < KB ? KBC : KB) * NT * 64;
+        for (int u = threadIdx.x; u < n0; u += 256) tb0[u] = wsrc[u];
+    }
+    __syncthreads();  // input tile and the first weight stage
+    // stage j + 1 is loaded into registers while stage j is computed, then
+    // stored into the other buffer behind one barrier
+#pragma unroll
+    for (int j = 0; j < NBLK; ++j) {
+        const int kc = j * KBC;
+        bf8 nxt[FR];
+        const int n1 = (j + 1 < NBLK) ? ((KB - kc - KBC < KBC ? KB - kc - KBC : KBC) * NT * 64) : 0;
+        if (j + 1 < NBLK) {
+#pragma unroll
+            for (int f = 0; f < FR; ++f) {
+                const int u = threadIdx.x + f * 256;
+                if (u < n1) nxt[f] = wsrc[(size_t)(kc + KBC) * NT * 64 + u];
+            }
+        }
+        const bf8 *tb = (j & 1) ? tb1 : tb0;
+#pragma unroll
+        for (int kl = 0; kl < KBC; ++kl) {
+            if (kc + kl < KB) {
+                // this lane's reduction entries (kc + kl) * 32 + 8 g .. + 7: one tap, 8 channels
+                const int k0 = (kc + kl) * 32 + 8 * g;
+                int tap = k0 / CIN;
+                tap = tap < 9 ? tap : 8;
+                const int toff = ((tap / 3) * HX + tap % 3) * CIN + (k0 % CIN);
+                bf8 a[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) a[mt] = *reinterpret_cast<const bf8 *>(tin + hoff[mt] + toff);
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
-                    const float v = acc[mt][t][i] + bv[t];
-                    o[t * 16] = (bf16)(v > 0.0f ? v : 0.0f);
+                    const bf8 wv = tb[(kl * NT + t) * 64 + lane];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) acc[mt][t] = mfma(wv, a[mt], acc[mt][t]);
                 }
             }
         }
+        if (j + 1 < NBLK) {
+            bf8 *tn = (j & 1) ? tb0 : tb1;
+#pragma unroll
+            for (int f = 0; f < FR; ++f) {
+                const int u = threadIdx.x + f * 256;
+                if (u < n1) tn[u] = nxt[f];
+            }
+            __syncthreads();  // stage j + 1 stored; every wave is done with stage j - 1's buffer
+        }
+    }
+    // lane: pixel (lane & 15) of row tile mt, output channels t * 16 + 4 g .. + 3
+    float bv[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bv[t][i] = bias[t * 16 + 4 * g + i];
+    const bool full = y0 + TY <= H && x0 + TX <= W;  // no pixel of the tile outside the image
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int p = (wave * MT + mt) * 16 + (lane & 15);
+        const int py = p / TX, px = p % TX;
+        if (full || (y0 + py < H && x0 + px < W)) {
+            bf16 *o = out + (img + (int64_t)(y0 + py) * W + (x0 + px)) * N + 4 * g;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                bf4 r;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float v = acc[mt][t][i] + bv[t][i];
+                    r[i] = (bf16)(v > 0.0f ? v : 0.0f);
+                }
+                *reinterpret_cast<bf4 *>(o + t * 16) = r;
+            }
+        }
+    }
+}
+
+// 2 x 2 stride-2 transposed convolution forward (+ bias): rows are the M
+// low-resolution pixels, columns n = q * Cout + co with q = 2 a + c the fine
+// position (2y + a, 2x + c), reduction over the Cin input channels.  As in
+// k_conv3x3 the product is taken transposed (weight fragment first), so each
+// lane ends with four consecutive output channels of one (pixel, q) and stores
+// them as one 8-byte word; the lane's low pixel is decomposed into
+// (image, y, x) once.  Cout (a multiple of 16, so the 16 columns of a tile
+// share q) and the level's H and W are powers of two: the splits are shifts.
+template <int NT>
+__global__ __launch_bounds__(256) void k_upconv(const bf16 *__restrict__ in, int Cin, int lcout, int lh, int lw, int M,
+                                                const bf16 *__restrict__ Bp, int KB, const float *__restrict__ bias,
+                                                bf16 *__restrict__ out) {
+    const int Cout = 1 << lcout, H = 1 << lh, W = 1 << lw;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4;
+    const int m0 = blockIdx.x * kPixTile + wave * 16;
+    if (m0 >= M) return;  // uniform across the wave
+    const int mr = m0 + (lane & 15);
+    const bool row_ok = mr < M;
+    f4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < KB; ++kb) {
+        const int k0 = kb * 32 + 8 * g;
+        const bf8 a = (row_ok && k0 < Cin) ? ld8(in + (int64_t)mr * Cin + k0) : zero8();
+        const bf8 *bk = reinterpret_cast<const bf8 *>(Bp) + (int64_t)kb * NT * 64 + lane;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = mfma(bk[t * 64], a, acc[t]);
+    }
+    if (!row_ok) return;
+    const int x = mr & (W - 1), yb = mr >> lw, y = yb & (H - 1), b = yb >> lh;
+    const int64_t W2 = 2 * (int64_t)W;
+    const int64_t base = ((int64_t)b * 2 * H + 2 * y) * W2 + 2 * x;  // fine pixel of q = 0
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int n0 = t * 16 + 4 * g;
+        const int q = n0 >> lcout, co = n0 & (Cout - 1);
+        const int64_t fine = base + (q >> 1) * W2 + (q & 1);
+        bf4 r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) r[i] = (bf16)(acc[t][i] + bias[co + i]);
+        *reinterpret_cast<bf4 *>(out + fine * Cout + co) = r;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -542,35 +659,45 @@ __global__ void k_sum_splits_up(const float *__restrict__ partial, int splits, i
 // ---------------------------------------------------------------------------
 // Elementwise and small kernels
 // ---------------------------------------------------------------------------
+// 2x2 average pooling, in [B][H][W][C] -> out [B][H/2][W/2][C]: one thread per
+// 8 channels of an output pixel (16-byte loads and store; C a multiple of 8)
 __global__ void k_pool_fwd(const bf16 *__restrict__ in, bf16 *__restrict__ out, int B, int H, int W, int C) {
-    // in [B][H][W][C] -> out [B][H/2][W/2][C]
-    const int64_t n = (int64_t)B * (H / 2) * (W / 2) * C;
+    const int c8 = C / 8, W2 = W / 2, H2 = H / 2;
+    const int64_t n = (int64_t)B * H2 * W2 * c8;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        int64_t t = i / C;
-        const int x = (int)(t % (W / 2));
-        t /= (W / 2);
-        const int y = (int)(t % (H / 2));
-        const int64_t b = t / (H / 2);
-        const int64_t base = ((b * H + 2 * y) * W + 2 * x) * C + c;
-        const float s = ((float)in[base] + (float)in[base + C]) +
-                        ((float)in[base + (int64_t)W * C] + (float)in[base + (int64_t)W * C + C]);
-        out[i] = (bf16)(0.25f * s);
+        const int64_t pix = i / c8;
+        const int cg = (int)(i - pix * c8);
+        const int x = (int)(pix % W2);
+        const int64_t t = pix / W2;
+        const int y = (int)(t % H2);
+        const int64_t b = t / H2;
+        const bf16 *p = in + ((b * H + 2 * y) * W + 2 * x) * C + cg * 8;
+        const bf8 a = ld8(p), bb = ld8(p + C), c = ld8(p + (int64_t)W * C), d = ld8(p + (int64_t)W * C + C);
+        bf8 r;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            r[k] = (bf16)(0.25f * (((float)a[k] + (float)bb[k]) + ((float)c[k] + (float)d[k])));
+        *reinterpret_cast<bf8 *>(out + pix * C + cg * 8) = r;
     }
 }
 
-// gin (fine) += gout (coarse) / 4
+// gin (fine) += gout (coarse) / 4: one thread per 8 channels of a fine pixel
 __global__ void k_pool_bwd(const bf16 *__restrict__ gout, bf16 *__restrict__ gin, int B, int H, int W, int C) {
-    const int64_t n = (int64_t)B * H * W * C;
+    const int c8 = C / 8;
+    const int64_t n = (int64_t)B * H * W * c8;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % C);
-        int64_t t = i / C;
-        const int x = (int)(t % W);
-        t /= W;
+        const int64_t pix = i / c8;
+        const int cg = (int)(i - pix * c8);
+        const int x = (int)(pix % W);
+        const int64_t t = pix / W;
         const int y = (int)(t % H);
         const int64_t b = t / H;
-        const float g = (float)gout[((b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
-        gin[i] = (bf16)((float)gin[i] + 0.25f * g);
+        const bf8 g = ld8(gout + ((b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + cg * 8);
+        bf16 *q = gin + pix * C + cg * 8;
+        bf8 v = ld8(q);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = (bf16)((float)v[k] + 0.25f * (float)g[k]);
+        *reinterpret_cast<bf8 *>(q) = v;
     }
 }
 
@@ -907,30 +1034,44 @@ int repack(UNet &N, hipStream_t st) {
     return 0;
 }
 
-size_t conv_tile_lds(int TY, int TX, int Cin) { return ((size_t)(TY + 2) * (TX + 2) * Cin * 2 + 15) & ~(size_t)15; }
+size_t conv_lds(int TY, int TX, int Cin, int KB, int NT) { return conv_lds_bytes(TY, TX, Cin, KB, NT); }
 
-// tile fits next to at least one 1 KiB weight block per column tile in 64 KiB of LDS
-// (and its channel count is a power of two, which the tiled kernel's index
-// arithmetic needs)
+// the tiled kernel takes power-of-two channel counts from 8 to 128 whose tile
+// and weight block fit in 64 KiB of LDS (at least two workgroups per CU)
 bool conv_tile_fits(int TY, int TX, const Layer &l) {
     const int c = l.Cin();
-    return c >= 8 && (c & (c - 1)) == 0 && conv_tile_lds(TY, TX, c) + (size_t)l.NTf * 1024 <= 65536;
+    return c >= 8 && c <= 128 && (c & (c - 1)) == 0 && conv_lds(TY, TX, c, l.KBf, l.NTf) <= 65536;
 }
 
-template <int TY, int TX, int NT>
-int launch_conv_tiled_nt(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B,
-                         hipStream_t st) {
+template <int TY, int TX, int NT, int CIN>
+int launch_conv3x3(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B,
+                   hipStream_t st) {
     const int H = N.H >> l.lvl, W = N.W >> l.lvl;
     const int tiles_x = (W + TX - 1) / TX, tiles_y = (H + TY - 1) / TY;
-    const size_t tin = conv_tile_lds(TY, TX, l.Cin());
-    const int kbc = (int)std::max<int64_t>(1, std::min<int64_t>(l.KBf, (65536 - (int64_t)tin) / (NT * 1024)));
-    const size_t lds = tin + (size_t)kbc * NT * 1024;
-    const int lcin = __builtin_ctz((unsigned)l.Cin());
-    k_conv_tiled<TY, TX, NT><<<B * tiles_x * tiles_y, 256, lds, st>>>(s1.a, s2 ? s2->a : nullptr, l.C1, l.C2, lcin, H, W,
-                                                                        tiles_x, tiles_y, l.Bf, l.KBf, kbc,
-                                                                        N.w + l.boff, y.a);
+    const size_t lds = conv_lds(TY, TX, CIN, l.KBf, NT);
+    k_conv3x3<TY, TX, NT, CIN><<<B * tiles_x * tiles_y, 256, lds, st>>>(s1.a, s2 ? s2->a : nullptr, l.C1, H, W,
+                                                                         tiles_x, tiles_y, l.Bf, N.w + l.boff, y.a);
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
+}
+
+// CIN of the layer as a template constant (conv_tile_fits has checked it)
+template <int TY, int TX, int NT>
+int launch_conv_cin(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B,
+                    hipStream_t st) {
+    switch (l.Cin()) {
+        case 8: return launch_conv3x3<TY, TX, NT, 8>(N, l, s1, s2, y, B, st);
+        case 16: return launch_conv3x3<TY, TX, NT, 16>(N, l, s1, s2, y, B, st);
+        case 32: return launch_conv3x3<TY, TX, NT, 32>(N, l, s1, s2, y, B, st);
+        case 64:
+            if constexpr ((TY + 2) * (TX + 2) * 64 * 2 <= 49152) return launch_conv3x3<TY, TX, NT, 64>(N, l, s1, s2, y, B, st);
+            break;
+        case 128:
+            if constexpr ((TY + 2) * (TX + 2) * 128 * 2 <= 49152) return launch_conv3x3<TY, TX, NT, 128>(N, l, s1, s2, y, B, st);
+            break;
+        default: break;
+    }
+    return set_error(FEM_EINVAL, "internal error: no tiled convolution for this channel count");
 }
 
 // forward conv3x3 + ReLU: 8 x 32 pixel tiles (4 row tiles per wave) on the two
@@ -941,22 +1082,22 @@ int conv_fwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const 
     // 32 output channels: 16 x 32 tiles (8 row tiles per wave) where the input
     // tile fits (measured 41.6 us against 49.6 us for 8 x 32 at 512^2; with 16
     // output channels the taller tile was slower, 81 against 70 us at 1024^2)
-    if (l.lvl <= 1 && l.NTf == 2 && conv_tile_fits(16, 32, l)) return launch_conv_tiled_nt<16, 32, 2>(N, l, s1, s2, y, B, st);
+    if (l.lvl <= 1 && l.NTf == 2 && conv_tile_fits(16, 32, l)) return launch_conv_cin<16, 32, 2>(N, l, s1, s2, y, B, st);
     if (l.lvl <= 1 && conv_tile_fits(8, 32, l)) {
         switch (l.NTf) {
-            case 1: return launch_conv_tiled_nt<8, 32, 1>(N, l, s1, s2, y, B, st);
-            case 2: return launch_conv_tiled_nt<8, 32, 2>(N, l, s1, s2, y, B, st);
-            case 4: return launch_conv_tiled_nt<8, 32, 4>(N, l, s1, s2, y, B, st);
+            case 1: return launch_conv_cin<8, 32, 1>(N, l, s1, s2, y, B, st);
+            case 2: return launch_conv_cin<8, 32, 2>(N, l, s1, s2, y, B, st);
+            case 4: return launch_conv_cin<8, 32, 4>(N, l, s1, s2, y, B, st);
             default: break;
         }
     }
     if (conv_tile_fits(4, 16, l)) {
         switch (l.NTf) {
-            case 1: return launch_conv_tiled_nt<4, 16, 1>(N, l, s1, s2, y, B, st);
-            case 2: return launch_conv_tiled_nt<4, 16, 2>(N, l, s1, s2, y, B, st);
-            case 4: return launch_conv_tiled_nt<4, 16, 4>(N, l, s1, s2, y, B, st);
-            case 8: return launch_conv_tiled_nt<4, 16, 8>(N, l, s1, s2, y, B, st);
-            case 16: return launch_conv_tiled_nt<4, 16, 16>(N, l, s1, s2, y, B, st);
+            case 1: return launch_conv_cin<4, 16, 1>(N, l, s1, s2, y, B, st);
+            case 2: return launch_conv_cin<4, 16, 2>(N, l, s1, s2, y, B, st);
+            case 4: return launch_conv_cin<4, 16, 4>(N, l, s1, s2, y, B, st);
+            case 8: return launch_conv_cin<4, 16, 8>(N, l, s1, s2, y, B, st);
+            case 16: return launch_conv_cin<4, 16, 16>(N, l, s1, s2, y, B, st);
             default: break;
         }
     }
@@ -1001,9 +1142,26 @@ int conv_bwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const 
 }
 
 int up_fwd(UNet &N, const Layer &l, const Tensor &in, const Tensor &y, int B, hipStream_t st) {
+    const int64_t M = pixels(N, l.lvl, B);
+    const int H = N.H >> l.lvl, W = N.W >> l.lvl;
+    auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
+    if (l.Cout >= 16 && pow2(l.Cout) && pow2(H) && pow2(W) && M < ((int64_t)1 << 31)) {
+        const int g = (int)((M + kPixTile - 1) / kPixTile);
+        const int lc = __builtin_ctz((unsigned)l.Cout), lh = __builtin_ctz((unsigned)H), lw = __builtin_ctz((unsigned)W);
+        const float *bias = N.w + l.boff;
+        switch (l.NTf) {
+            case 4: k_upconv<4><<<g, 256, 0, st>>>(in.a, l.C1, lc, lh, lw, (int)M, l.Bf, l.KBf, bias, y.a); break;
+            case 8: k_upconv<8><<<g, 256, 0, st>>>(in.a, l.C1, lc, lh, lw, (int)M, l.Bf, l.KBf, bias, y.a); break;
+            case 16: k_upconv<16><<<g, 256, 0, st>>>(in.a, l.C1, lc, lh, lw, (int)M, l.Bf, l.KBf, bias, y.a); break;
+            case 32: k_upconv<32><<<g, 256, 0, st>>>(in.a, l.C1, lc, lh, lw, (int)M, l.Bf, l.KBf, bias, y.a); break;
+            default: return set_error(FEM_EINVAL, "unsupported up-convolution width");
+        }
+        FEM_HIP_CHECK(hipGetLastError());
+        return 0;
+    }
     SrcRows src{in.a, l.C1};
     EpiUp epi{y.a, N.w + l.boff, l.Cout, N.H >> l.lvl, N.W >> l.lvl};
-    return launch_rows(src, epi, l.Bf, pixels(N, l.lvl, B), l.KBf, l.NTf, st);
+    return launch_rows(src, epi, l.Bf, M, l.KBf, l.NTf, st);
 }
 
 int up_bwd(UNet &N, const Layer &l, const Tensor &in, const Tensor &y, int B, hipStream_t st) {
@@ -1023,14 +1181,14 @@ int up_bwd(UNet &N, const Layer &l, const Tensor &in, const Tensor &y, int B, hi
 
 int pool(const UNet &N, const Tensor &in, const Tensor &out, int B, hipStream_t st) {
     const int H = N.H >> in.lvl, W = N.W >> in.lvl;
-    k_pool_fwd<<<grid1(pixels(N, out.lvl, B) * in.C), 256, 0, st>>>(in.a, out.a, B, H, W, in.C);
+    k_pool_fwd<<<grid1(pixels(N, out.lvl, B) * (in.C / 8)), 256, 0, st>>>(in.a, out.a, B, H, W, in.C);
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
 
 int pool_bwd(const UNet &N, const Tensor &in, const Tensor &out, int B, hipStream_t st) {
     const int H = N.H >> in.lvl, W = N.W >> in.lvl;
-    k_pool_bwd<<<grid1(pixels(N, in.lvl, B) * in.C), 256, 0, st>>>(out.g, in.g, B, H, W, in.C);
+    k_pool_bwd<<<grid1(pixels(N, in.lvl, B) * (in.C / 8)), 256, 0, st>>>(out.g, in.g, B, H, W, in.C);
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
