@@ -90,14 +90,21 @@ __device__ __forceinline__ bf8 ld8(const bf16 *p) { return *reinterpret_cast<con
 
 // conv3x3 forward: row m = pixel (b, y, x); k = tap * Cin + ci, tap = ky*3+kx;
 // channels [0, C1) from src1, [C1, C1 + C2) from src2 (concatenation).
+// Each source splits its row m once per lane (row()) and then loads the
+// reduction entries of that row (load(row, k0)), so the pixel arithmetic is not
+// repeated for every reduction block.
 struct SrcConv {
     const bf16 *src1, *src2;
     int C1, C2, H, W;
-    __device__ __forceinline__ bf8 load(int m, int k0) const {
+    struct Row {
+        int m, x, y;
+    };
+    __device__ __forceinline__ Row row(int m) const { return {m, m % W, (m / W) % H}; }
+    __device__ __forceinline__ bf8 load(const Row &rw, int k0) const {
         const int Cin = C1 + C2;
         const int tap = k0 / Cin, ci = k0 - tap * Cin;
         if (tap >= 9) return zero8();
-        const int x = m % W, t = m / W, y = t % H;
+        const int m = rw.m, x = rw.x, y = rw.y;
         const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
         if (yy < 0 || yy >= H || xx < 0 || xx >= W) return zero8();
         const int64_t pix = (int64_t)m + (int64_t)(tap / 3 - 1) * W + (tap % 3 - 1);
@@ -110,11 +117,15 @@ struct SrcConv {
 // gz[q - d_tap][co] with gz = gy * (y > 0).
 struct SrcConvBwd {
     const bf16 *gy, *y;
-    int Cout, H, W;
-    __device__ __forceinline__ bf8 load(int m, int k0) const {
-        const int tap = k0 / Cout, co = k0 - tap * Cout;
+    int Cout, lcout, H, W;  // Cout = 2^lcout
+    struct Row {
+        int m, x, yq;
+    };
+    __device__ __forceinline__ Row row(int m) const { return {m, m % W, (m / W) % H}; }
+    __device__ __forceinline__ bf8 load(const Row &rw, int k0) const {
+        const int tap = k0 >> lcout, co = k0 & (Cout - 1);
         if (tap >= 9) return zero8();
-        const int x = m % W, t = m / W, yq = t % H;
+        const int m = rw.m, x = rw.x, yq = rw.yq;
         const int dy = tap / 3 - 1, dx = tap % 3 - 1;
         const int yy = yq - dy, xx = x - dx;
         if (yy < 0 || yy >= H || xx < 0 || xx >= W) return zero8();
@@ -131,6 +142,8 @@ struct SrcConvBwd {
 struct SrcRows {
     const bf16 *src;
     int C;
+    using Row = int;
+    __device__ __forceinline__ Row row(int m) const { return m; }
     __device__ __forceinline__ bf8 load(int m, int k0) const {
         if (k0 >= C) return zero8();
         return ld8(src + (int64_t)m * C + k0);
@@ -147,6 +160,8 @@ __device__ __forceinline__ int64_t fine_pixel(int m, int q, int H, int W) {
 struct SrcUpBwd {
     const bf16 *du;
     int Cout, H, W;  // low resolution
+    using Row = int;
+    __device__ __forceinline__ Row row(int m) const { return m; }
     __device__ __forceinline__ bf8 load(int m, int k0) const {
         const int q = k0 / Cout, co = k0 - q * Cout;
         if (q >= 4) return zero8();
@@ -200,8 +215,9 @@ __global__ __launch_bounds__(256) void k_gemm_rows(Src src, Epi epi, const bf16 
     for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
     const int mr = m0 + (lane & 15);
     const bool row_ok = mr < M;
+    const typename Src::Row rw = src.row(row_ok ? mr : m0);
     for (int kb = 0; kb < KB; ++kb) {
-        const bf8 a = row_ok ? src.load(mr, kb * 32 + 8 * (lane >> 4)) : zero8();
+        const bf8 a = row_ok ? src.load(rw, kb * 32 + 8 * (lane >> 4)) : zero8();
         const bf16 *bk = Bp + ((int64_t)kb * NT * 64 + lane) * 8;
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = mfma(a, ld8(bk + (int64_t)t * 64 * 8), acc[t]);
@@ -452,6 +468,9 @@ struct WSrcConv {  // conv3x3: r = tap * Cin + ci; r == R is the bias row
 struct WGradConv {  // gy * (y > 0)
     const bf16 *gy, *y;
     int N;
+    using Prep = int;
+    __device__ __forceinline__ Prep prep(int64_t) const { return 0; }
+    __device__ __forceinline__ bf8 g8(Prep, int64_t p, int n, int64_t p1) const { return g8(p, n, p1); }
     __device__ __forceinline__ float g(int64_t pix, int n) const {
         const int64_t o = pix * N + n;
         return (float)y[o] > 0.0f ? (float)gy[o] : 0.0f;
@@ -477,6 +496,24 @@ struct WSrcUp {  // up-conv: r = ci; r == C is the bias row
 struct WGradUp {  // column n = q * Cout + co: du at the fine position q of low pixel pix
     const bf16 *du;
     int Cout, H, W;
+    // fine pixel of q = 0 for the lane's 8 low pixels p .. p + 7 (one image row
+    // when W is a multiple of 8; -1: take the entry-by-entry path), computed
+    // once per reduction step instead of once per column tile
+    using Prep = int64_t;
+    __device__ __forceinline__ Prep prep(int64_t p) const {
+        if (W & 7) return -1;
+        const int x = (int)(p % W), yb = (int)(p / W), y = yb % H, b = yb / H;
+        return ((int64_t)b * 2 * H + 2 * y) * (2 * (int64_t)W) + 2 * x;
+    }
+    __device__ __forceinline__ bf8 g8(Prep f0, int64_t p, int n, int64_t p1) const {
+        if (f0 < 0 || p + 8 > p1) return g8(p, n, p1);
+        const int q = n / Cout, co = n - q * Cout;
+        const bf16 *base = du + (f0 + (q >> 1) * 2 * (int64_t)W + (q & 1)) * Cout + co;
+        bf8 v;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = base[(int64_t)2 * i * Cout];
+        return v;
+    }
     __device__ __forceinline__ float g(int64_t pix, int n) const {
         const int q = n / Cout, co = n - q * Cout;
         return (float)du[fine_pixel((int)pix, q, H, W) * Cout + co];
@@ -512,10 +549,11 @@ __global__ __launch_bounds__(256) void k_gemm_wgrad(WS ws, WG wg, int R1, int N,
     for (int64_t pb = p0; pb < p1; pb += 32) {
         const int64_t pl = pb + 8 * (lane >> 4);  // this lane's 8 pixels
         const bf8 a = r < R1 ? ws.a8(pl, r, p1) : zero8();
+        const typename WG::Prep pr = wg.prep(pl);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int n = t * 16 + (lane & 15);
-            const bf8 bv = n < N ? wg.g8(pl, n, p1) : zero8();
+            const bf8 bv = n < N ? wg.g8(pr, pl, n, p1) : zero8();
             acc[t] = mfma(a, bv, acc[t]);
         }
     }
@@ -553,22 +591,47 @@ __global__ __launch_bounds__(256) void k_wgrad_conv(WSrcConv ws, WGradConv wg, i
     f4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    // A items (pixel pl, group rg of 8 rows): each thread keeps one pixel
+    // column and four row groups; their (tap, channel) splits do not depend on
+    // the chunk and are taken once
+    constexpr int kRG = kWChunk * 8 / 256;
+    static_assert(kWChunk * 8 % 256 == 0 && 256 % kWChunk == 0, "A items per thread");
+    const int pl = threadIdx.x % kWChunk;
+    int rdy[kRG], rdx[kRG], rci[kRG], rkind[kRG];  // kind: 0 zero row, 1 bias row, 2 data row
+#pragma unroll
+    for (int j = 0; j < kRG; ++j) {
+        const int rg = threadIdx.x / kWChunk + j * (256 / kWChunk);
+        const int r = rb + 8 * rg;
+        rkind[j] = r == ws.R ? 1 : (r < ws.R ? 2 : 0);
+        const int tap = r < ws.R ? r / Cin : 0;
+        rci[j] = r < ws.R ? r - tap * Cin : 0;
+        rdy[j] = tap / 3 - 1;
+        rdx[j] = tap % 3 - 1;
+    }
     for (int64_t cb = p0; cb < p1; cb += kWChunk) {
         __syncthreads();  // the previous chunk's operands are consumed
-        // A: items (pixel, group of 8 rows)
-        for (int it = threadIdx.x; it < kWChunk * 8; it += 256) {
-            const int pl = it % kWChunk, rg = it / kWChunk;
-            const int64_t p = cb + pl;
-            const int r = rb + 8 * rg;
+        // the chunk's pixels cb .. cb + kWChunk - 1: image row and column of
+        // the first one, once per chunk (uniform); they lie in one image row
+        // when W is a multiple of the chunk length
+        const int64_t row0 = cb / W;
+        const int xc = (int)(cb - row0 * W), yc = (int)(row0 % H);
+        const bool one_row = W % kWChunk == 0;
+        const int64_t p = cb + pl;
+        int x = xc + pl, y = yc;
+        if (!one_row) {
+            const int64_t row = p / W;
+            x = (int)(p - row * W);
+            y = (int)(row % H);
+        }
+#pragma unroll
+        for (int j = 0; j < kRG; ++j) {
+            const int rg = threadIdx.x / kWChunk + j * (256 / kWChunk);
             bf8 v = zero8();
             if (p < p1) {
-                if (r == ws.R) {
+                if (rkind[j] == 1) {
                     v[0] = (bf16)1.0f;  // bias row; rows R+1.. are beyond R1
-                } else if (r < ws.R) {
-                    const int tap = r / Cin, ci = r - tap * Cin;
-                    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-                    const int64_t row = p / W;
-                    const int x = (int)(p - row * W), y = (int)(row % H);
+                } else if (rkind[j] == 2) {
+                    const int dy = rdy[j], dx = rdx[j], ci = rci[j];
                     if (y + dy >= 0 && y + dy < H && x + dx >= 0 && x + dx < W) {
                         const int64_t q = p + (int64_t)dy * W + dx;
                         v = ci < ws.C1 ? ld8(ws.src1 + q * ws.C1 + ci) : ld8(ws.src2 + q * ws.C2 + (ci - ws.C1));
@@ -576,7 +639,7 @@ __global__ __launch_bounds__(256) void k_wgrad_conv(WSrcConv ws, WGradConv wg, i
                 }
             }
 #pragma unroll
-            for (int j = 0; j < 8; ++j) sa[(8 * rg + j) * kWPitch + pl] = v[j];
+            for (int jj = 0; jj < 8; ++jj) sa[(8 * rg + jj) * kWPitch + pl] = v[jj];
         }
         // G: items (pixel, group of 8 output channels)
         for (int it = threadIdx.x; it < kWChunk * 2 * NT; it += 256) {
@@ -782,19 +845,32 @@ __global__ void k_out_bwd(const float *__restrict__ y, const float *__restrict__
 }
 
 // 1x1 output layer weight gradient over pixel slices:
-// part[s][c] = sum_p d0[p][c] gy[p] (c < C), part[s][C] = sum_p gy[p]
-__global__ __launch_bounds__(256) void k_out_wgrad(const bf16 *__restrict__ d0, const float *__restrict__ gy, int C,
+// part[s][c] = sum_p d0[p][c] gy[p] (c < C), part[s][C] = sum_p gy[p].  Each
+// thread accumulates all C + 1 sums over its pixels (16-byte loads of 8
+// channels), then one block reduction of all of them (fixed order).
+template <int C>
+__global__ __launch_bounds__(256) void k_out_wgrad(const bf16 *__restrict__ d0, const float *__restrict__ gy,
                                                    int64_t P, float *__restrict__ part) {
-    __shared__ double red[4];
+    __shared__ double red[(C + 1) * 4];
     const int s = blockIdx.x;
     const int64_t p0 = (int64_t)s * kWSlice, p1 = std::min<int64_t>(P, p0 + kWSlice);
-    for (int c = 0; c <= C; ++c) {
-        double v = 0.0;
-        for (int64_t p = p0 + threadIdx.x; p < p1; p += 256)
-            v += (double)gy[p] * (c < C ? (double)(float)d0[p * C + c] : 1.0);
-        v = block_sum<256>(v, red);
-        if (threadIdx.x == 0) part[(int64_t)s * (C + 1) + c] = (float)v;
+    double v[C + 1];
+#pragma unroll
+    for (int c = 0; c <= C; ++c) v[c] = 0.0;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) {
+        const double g = (double)gy[p];
+#pragma unroll
+        for (int c8 = 0; c8 < C; c8 += 8) {
+            const bf8 a = ld8(d0 + p * C + c8);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[c8 + i] += g * (double)(float)a[i];
+        }
+        v[C] += g;
     }
+    block_sum_n<256, C + 1>(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c <= C; ++c) part[(int64_t)s * (C + 1) + c] = (float)v[c];
 }
 
 // Adam on the FP32 master weights; c1, c2 are the bias corrections 1 - beta^t
@@ -1112,7 +1188,8 @@ int conv_bwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const 
     const int H = N.H >> l.lvl, W = N.W >> l.lvl;
     const int64_t M = pixels(N, l.lvl, B);
     if (input_grad) {
-        SrcConvBwd src{y.g, y.a, l.Cout, H, W};
+        if (l.Cout & (l.Cout - 1)) return set_error(FEM_EINVAL, "output channel count must be a power of two");
+        SrcConvBwd src{y.g, y.a, l.Cout, __builtin_ctz((unsigned)l.Cout), H, W};
         EpiGrad epi{s1.g, s2 ? s2->g : nullptr, l.C1, l.C2};
         if (int rc = launch_rows(src, epi, l.Bb, M, l.KBb, l.NTb, st)) return rc;
     }
@@ -1236,7 +1313,8 @@ int backward(UNet &N, int B, const float *target, double *loss, hipStream_t st) 
     k_loss_fin<<<1, 64, 0, st>>>(N.lpart, B, N.loss_slices, N.sums, loss);
     k_out_bwd<<<grid1(P0), 256, 0, st>>>(N.out, target, N.sums, N.w + N.out_woff, N.c, HW, B, N.gy, N.d0.g);
     const int64_t so = wgrad_splits(P0);
-    k_out_wgrad<<<(unsigned)so, 256, 0, st>>>(N.d0.a, N.gy, N.c, P0, N.partial);
+    if (N.c == 16) k_out_wgrad<16><<<(unsigned)so, 256, 0, st>>>(N.d0.a, N.gy, P0, N.partial);
+    else k_out_wgrad<32><<<(unsigned)so, 256, 0, st>>>(N.d0.a, N.gy, P0, N.partial);
     k_sum_splits<<<1, 256, 0, st>>>(N.partial, (int)so, N.c + 1, N.g + N.out_woff);
     FEM_HIP_CHECK(hipGetLastError());
     const auto &L = N.L;
