@@ -160,8 +160,9 @@ def cpu_allcores(mesh, w, seconds):
         return oracle.residual(mesh.n_nodes, mesh.elems[a:e], K[a:e], M[a:e], nu, None, x, mask)
 
     def add(ab):
-        ab[0] += ab[1]
-        return ab[0]
+        a, b = ab
+        a += b
+        return a
 
     with ThreadPoolExecutor(T) as pool:
         def call():
