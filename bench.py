@@ -660,6 +660,10 @@ def learned_fcg(args):
     log(f"[bench] learned: {len(params)} problems x {len(segs)} snapshots at {N}^2 in {args.learned_rounds} rounds")
     fam = learn.GridFamily(N, fem.F64, mg=True)
     net = fem.UNet(N, N, max_batch=args.learned_batch, channels=16, seed=0)
+    if args.learned_loss == "energy":
+        learn.use_energy_loss(net, args.learned_out_smooth)
+    else:
+        net.set_output_smoothing(args.learned_out_smooth)
     hist, n_pairs, t_data, t_train = learn.train_streaming(fam, net, params, segs, args.learned_batch,
                                                            args.learned_lr, args.learned_rounds, log=log)
     del fam
@@ -667,6 +671,10 @@ def learned_fcg(args):
     log(f"[bench] learned: {n_pairs} pairs in {t_data:.1f} s, {len(hist)} steps in {t_train:.1f} s")
     efam = learn.GridFamily(N, fem.F32X2)
     fopts = dict(smooth=args.learned_smooth, cycle_dtype=fem.F32 if args.learned_cycle == "f32" else fem.F64)
+    # the same cycle without the network (all its parameters zero: N(r) = 0, s = 0),
+    # on the first held-out problems: what the trained network adds to the smoothing
+    net0 = fem.UNet(N, N, max_batch=1, channels=16, seed=0)
+    net0.set_params(torch.zeros(net0.n_params, dtype=torch.float32, device="cuda"))
     rows = []
     for i, (nu, seed) in enumerate(learn.problem_params(args.learned_eval, 5000)):
         gp = efam.problem(nu, seed)
@@ -684,6 +692,12 @@ def learned_fcg(args):
                "fcg_fell_back": b["fell_back"], "fcg_s": round(b["seconds"], 4), "fcg_relres": b["relres"]}
         msg = (f"[bench] learned: nu {nu:.2f} Jacobi-PCG {a['iters']} it {a['seconds']:.3f} s | "
                f"learned FCG {b['iters']}+{b['pcg_iters']} it {b['seconds']:.3f} s")
+        if i < args.learned_ablate:
+            x.zero_()
+            z = gp.fcg(net0, x, stall_iters=1 << 30, max_iter=args.learned_max_iter, **fopts)
+            row.update({"cycle_without_network_iters": z["iters"], "cycle_without_network_s": round(z["seconds"], 4),
+                        "cycle_without_network_status": z["status"]})
+            msg += f" | same cycle without the network {z['iters']} it {z['seconds']:.3f} s"
         if b["fell_back"] >= 0 and i < args.learned_nohandover:
             x.zero_()
             c = gp.fcg(net, x, stall_iters=1 << 30, max_iter=args.learned_max_iter, **fopts)
@@ -701,6 +715,9 @@ def learned_fcg(args):
         "workload": f"2D P1 {N}x{N} squares ({(N + 1) ** 2} nodes, {2 * N * N} triangles), nu~U(0,100), "
                     "random-sine f, u=0 on the boundary; held-out problems",
         "network": "U-Net 4 levels, 16-128 channels, BF16 MFMA / FP32 accumulation, 482753 parameters",
+        "loss": ("energy: 1 - (y.Ae)^2 / ((y.Ay)(e.Ae)) per pair" if args.learned_loss == "energy"
+                 else "relative L2 of the scaled error"),
+        "output_smoothing_passes": args.learned_out_smooth,
         "preconditioner": f"FCG(1), two-level cycle: {args.learned_smooth} damped-Jacobi steps (omega 2/3), network "
                           f"correction, {args.learned_smooth} Jacobi steps, {args.learned_cycle.upper()} cycle passes; "
                           "hand-over to Jacobi-PCG (from the best iterate) after 200 iterations without halving ||r||",
@@ -716,6 +733,11 @@ def learned_fcg(args):
         "handovers": sum(1 for r in rows if r["fcg_fell_back"] >= 0),
         "max_total_minus_cold_pcg_iters": int(max(t - r["pcg_iters"] for t, r in zip(fcg_it, rows))),
         "fcg_ms_per_iter_median": round(1e3 * float(np.median(fcg_only)), 4) if fcg_only else None,
+        "network_gain_iters": (round(float(np.mean([r["cycle_without_network_iters"] / max(r["fcg_iters"], 1)
+                                                    for r in rows if "cycle_without_network_iters" in r
+                                                    and r["fcg_fell_back"] < 0])), 3)
+                               if any("cycle_without_network_iters" in r and r["fcg_fell_back"] < 0 for r in rows)
+                               else None),
         "problems": rows,
     }
 
@@ -772,11 +794,16 @@ def main():
     ap.add_argument("--learned-batch", type=int, default=4)
     ap.add_argument("--learned-lr", type=float, default=2e-3)
     ap.add_argument("--learned-eval", type=int, default=32, help="held-out problems")
+    ap.add_argument("--learned-loss", choices=["energy", "l2"], default="energy")
+    ap.add_argument("--learned-out-smooth", type=int, default=2,
+                    help="binomial smoothing passes on the network output")
+    ap.add_argument("--learned-ablate", type=int, default=4,
+                    help="held-out problems also solved with the same cycle and a zero network")
     ap.add_argument("--learned-nohandover", type=int, default=3,
                     help="of the held-out problems that hand over, the first few are also solved without hand-over")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build runs its hot path on a single MI355X "
+        print("bench.py measures one GPU only: the library runs its hot path on a single MI355X "
               "(multi-GPU sharding is a design note, not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -401,9 +401,38 @@ int fem_unet_get_params(const fem_unet *net, float *d_params, void *stream);
 int fem_unet_set_params(fem_unet *net, const float *d_params, void *stream);
 /* d_in float [batch][H][W][2] (NHWC), d_out float [batch][H][W]. */
 int fem_unet_forward(fem_unet *net, int batch, const float *d_in, float *d_out, void *stream);
-/* Loss L = (1/batch) sum_b ||N(in_b) - t_b||^2 / ||t_b||^2 (d_loss: one
- * device double) and its gradient with respect to every parameter (d_grad:
- * device float [count], may be NULL).  d_target float [batch][H][W]. */
+/* Training loss (fem_unet_set_loss; FEM_UNET_LOSS_L2 at creation), with
+ * y_b = N(in_b) and t_b the target image of sample b:
+ *  FEM_UNET_LOSS_L2      L = (1/batch) sum_b ||y_b - t_b||^2 / ||t_b||^2.
+ *  FEM_UNET_LOSS_ENERGY  L = (1/batch) sum_b [1 - (y_b.A t_b)^2 / ((y_b.A y_b)(t_b.A t_b))]
+ *      = the mean over b of min_s ||s y_b - t_b||_A^2 / ||t_b||_A^2: what is
+ *      left of the error's energy after the energy-optimal step along y_b,
+ *      the step flexible CG and the two-level cycle take.  A is the P1
+ *      operator -Delta + nu I of Section 2 (eq. (4)) on the interior nodes of
+ *      the unit square cut into H x H squares, each split by its diagonal from
+ *      the lower-left to the upper-right corner, with u = 0 on the boundary:
+ *      pixel (y, x) is node (x + 1, y + 1) as in fem_unet_precondition; the
+ *      last row and column hold no node and enter neither y_b nor t_b.  On
+ *      this grid A is the 5-point Laplacian plus nu h^2 (1/2 at the node, 1/12
+ *      at its four axis and two diagonal neighbours), h = 1 / H.  nu_b =
+ *      nu_scale * in_b(0, 0, channel 1).  A sample with y.Ay <= 0 or t.At <= 0
+ *      counts 1 with zero gradient.  Needs H == W.
+ * fem_unet_set_loss: kind FEM_UNET_LOSS_L2 or FEM_UNET_LOSS_ENERGY, nu_scale
+ * finite >= 0 (ignored for L2); FEM_EINVAL otherwise. */
+enum { FEM_UNET_LOSS_L2 = 0, FEM_UNET_LOSS_ENERGY = 1 };
+int fem_unet_set_loss(fem_unet *net, int kind, double nu_scale);
+/* Output smoothing (0 passes at creation): the 1x1 layer's output is followed
+ * by `passes` (0..8) passes of the 3x3 binomial filter (1 2 1; 2 4 2; 1 2 1)/16
+ * in FP32 over the pixels x < W-1, y < H-1 (the grid layout's nodes; the last
+ * row and column are read and written as 0), in forward, loss, training and
+ * fem_unet_precondition alike.  It damps the pixel-wise rounding noise of the
+ * BF16 layers, which otherwise dominates the energy norm of a smooth output
+ * (the noise's A-norm is ~4x its L2 norm, a smooth mode's ~2 pi^2 / H^2 x).
+ * FEM_EINVAL outside [0, 8]. */
+int fem_unet_set_output_smoothing(fem_unet *net, int passes);
+/* Loss L (d_loss: one device double) and its gradient with respect to every
+ * parameter (d_grad: device float [count], may be NULL).  d_target float
+ * [batch][H][W]. */
 int fem_unet_loss_grad(fem_unet *net, int batch, const float *d_in, const float *d_target, double *d_loss,
                        float *d_grad, void *stream);
 /* One Adam step on L with learning rate lr (d_loss may be NULL). */

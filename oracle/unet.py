@@ -23,7 +23,13 @@ Flat parameter layout (float, layer by layer, weights then bias):
   conv3x3   W[ky*3 + kx][ci][co], output (y, x) reads input (y+ky-1, x+kx-1)
   upconv    W[ci][a*2 + b][co], output (2y+a, 2x+b) from input (y, x)
   output    w[c], then one bias
-Loss: L = (1/B) sum_b ||y_b - t_b||^2 / ||t_b||^2.
+Optional output filter: passes of the 3x3 binomial filter after the output
+layer (``output_filter``).
+Losses: L = (1/B) sum_b ||y_b - t_b||^2 / ||t_b||^2 (``loss``), or the
+energy loss (``energy_loss``) L = (1/B) sum_b [1 - (y_b.A t_b)^2 / ((y_b.A y_b)
+(t_b.A t_b))] with A the P1 operator -Delta + nu I of Section 2 (eq. (4)) on
+the interior nodes of the unit square's n x n diagonal-cut grid, applied here
+through the element residual of this package (``grid_operator``).
 Optimiser: Adam (Kingma & Ba, ICLR 2015, Algorithm 1) with bias-corrected
 moments, ``adam`` below.
 
@@ -170,8 +176,33 @@ def _input8(inp):
     return x
 
 
-def forward(params, inp, c, keep=False):
-    """inp (B, H, W, 2) -> y (B, H, W); with keep=True also the activations for backward."""
+def output_filter(y, passes):
+    """``passes`` passes of the 3x3 binomial filter (1 2 1; 2 4 2; 1 2 1) / 16 over
+    the pixels x < W-1, y < H-1 of each image (B, H, W); the last row and
+    column are read and written as 0.  Each output pixel is the weighted sum of
+    its (up to nine) neighbours inside that region."""
+    y = np.array(y, dtype=np.float64)
+    B, H, W = y.shape
+    wts = {-1: 1.0, 0: 2.0, 1: 1.0}
+    for _ in range(passes):
+        src = np.zeros_like(y)
+        src[:, : H - 1, : W - 1] = y[:, : H - 1, : W - 1]
+        out = np.zeros_like(y)
+        for yy in range(H - 1):
+            for xx in range(W - 1):
+                acc = np.zeros(B)
+                for dy in (-1, 0, 1):
+                    for dx in (-1, 0, 1):
+                        if 0 <= yy + dy < H - 1 and 0 <= xx + dx < W - 1:
+                            acc += wts[dy] * wts[dx] * src[:, yy + dy, xx + dx]
+                out[:, yy, xx] = acc / 16.0
+        y = out
+    return y
+
+
+def forward(params, inp, c, keep=False, smooth=0):
+    """inp (B, H, W, 2) -> y (B, H, W); with keep=True also the activations for
+    backward.  smooth: passes of ``output_filter`` after the output layer."""
     L = unpack(params, c)
     a = {"x": _input8(inp)}
     a["e0a"] = relu(conv3x3(a["x"], *L[0]))
@@ -199,6 +230,8 @@ def forward(params, inp, c, keep=False):
     a["d0"] = relu(conv3x3(a["d0a"], *L[16]))
     w, b = L[17]
     y = a["d0"] @ w + b[0]
+    if smooth:
+        y = output_filter(y, smooth)
     return (y, a) if keep else y
 
 
@@ -210,14 +243,95 @@ def loss(y, t):
     return float(sum(np.sum((y[i] - t[i]) ** 2) / np.sum(t[i] ** 2) for i in range(B)) / B)
 
 
-def loss_grad(params, inp, target, c, input_grad=False):
-    """(L, dL/dparams flat [, dL/dinput (B, H, W, 2)])."""
-    L = unpack(params, c)
+def unit_square_grid(n):
+    """The unit square cut into n x n squares, each split by its diagonal from
+    the lower-left to the upper-right corner: node i + j (n + 1) at (i/n, j/n);
+    triangles (a, a+1, a+n+2) and (a, a+n+2, a+n+1) with a = i + j (n + 1).
+    Returns (coords (n_nodes, 2), elems (2 n^2, 3), boundary node mask)."""
+    m = n + 1
+    j, i = np.divmod(np.arange(m * m), m)
+    coords = np.stack([i / n, j / n], axis=1).astype(np.float64)
+    cj, ci = np.divmod(np.arange(n * n), n)
+    a = ci + cj * m
+    elems = np.concatenate([np.stack([a, a + 1, a + m + 1], 1), np.stack([a, a + m + 1, a + m], 1)])
+    bnd = ((i == 0) | (i == n) | (j == 0) | (j == n)).astype(np.uint8)
+    return coords, elems.astype(np.int32), bnd
+
+
+def grid_operator(n, nu):
+    """v -> A v for images (n, n): pixel (y, x) is interior node (x + 1, y + 1)
+    of ``unit_square_grid(n)`` (the last row and column hold no node and are
+    read and written as 0); A v is minus the element residual of eq. (4) with
+    b = 0 and the boundary rows masked (Section 2's Dirichlet treatment)."""
+    from . import local_matrices, residual  # the oracle's element code
+
+    coords, elems, bnd = unit_square_grid(n)
+    K, M, _ = local_matrices(coords, elems)
+    nn = coords.shape[0]
+    zero = np.zeros(nn)
+
+    def apply(v):
+        x = np.zeros((n + 1, n + 1))
+        x[1:n, 1:n] = np.asarray(v, dtype=np.float64)[: n - 1, : n - 1]
+        r = -residual(nn, elems, K, M, nu, zero, x.ravel(), bnd).reshape(n + 1, n + 1)
+        out = np.zeros((n, n))
+        out[: n - 1, : n - 1] = r[1:n, 1:n]
+        return out
+
+    return apply
+
+
+def energy_loss(y, t, nus):
+    """(L, dL/dy) of the energy loss for outputs y, targets t (B, n, n) and the
+    per-sample coefficients nus: per sample with a = y.At, b = y.Ay, c = t.At
+    (y, t restricted to the interior pixels) the term is 1 - a^2 / (b c), and 1
+    with zero gradient when b <= 0 or c <= 0; dL/dy = (1/B) (2 a^2 / (b^2 c) Ay -
+    2 a / (b c) At) on the interior pixels, 0 on the last row and column."""
+    y = np.asarray(y, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    B, n, _ = y.shape
+    inner = np.zeros((n, n))
+    inner[: n - 1, : n - 1] = 1.0
+    val = 0.0
+    gy = np.zeros_like(y)
+    for k in range(B):
+        A = grid_operator(n, float(nus[k]))
+        yk, tk = y[k] * inner, t[k] * inner
+        Ay, At = A(yk), A(tk)
+        a, b, c = np.sum(yk * At), np.sum(yk * Ay), np.sum(tk * At)
+        if b > 0 and c > 0:
+            val += 1.0 - a * a / (b * c)
+            gy[k] = (2.0 * a * a / (b * b * c) * Ay - 2.0 * a / (b * c) * At) * inner / B
+        else:
+            val += 1.0
+    return val / B, gy
+
+
+def loss_grad(params, inp, target, c, input_grad=False, kind="l2", nu_scale=100.0, smooth=0):
+    """(L, dL/dparams flat [, dL/dinput (B, H, W, 2)]) for the loss ``kind``
+    ("l2" or "energy"; the energy loss takes nu_b = nu_scale * inp[b, 0, 0, 1])
+    of the network with ``smooth`` output-filter passes."""
     t = np.asarray(target, dtype=np.float64)
-    y, a = forward(params, inp, c, keep=True)
+    y, a = forward(params, inp, c, keep=True, smooth=smooth)
     B = y.shape[0]
-    val = loss(y, t)
-    gy = np.stack([2.0 * (y[i] - t[i]) / (B * np.sum(t[i] ** 2)) for i in range(B)])
+    if kind == "energy":
+        val, gy = energy_loss(y, t, [nu_scale * float(np.asarray(inp)[b, 0, 0, 1]) for b in range(B)])
+    else:
+        val = loss(y, t)
+        gy = np.stack([2.0 * (y[i] - t[i]) / (B * np.sum(t[i] ** 2)) for i in range(B)])
+    out = backward(params, a, gy, c, input_grad, smooth)
+    return (val,) + out if input_grad else (val, out)
+
+
+def backward(params, a, gy, c, input_grad=False, smooth=0):
+    """Reverse sweep from the output gradient gy (B, H, W) through the
+    activations ``a`` of ``forward(..., keep=True)``: dL/dparams flat
+    [, dL/dinput (B, H, W, 2)].  The output filter is symmetric (a masked
+    convolution with a symmetric kernel), so its passes carry gy back to the
+    output layer unchanged in form."""
+    L = unpack(params, c)
+    if smooth:
+        gy = output_filter(gy, smooth)
     G = [None] * len(L)
     w, _ = L[17]
     G[17] = ((a["d0"] * gy[..., None]).sum(axis=(0, 1, 2)), np.array([gy.sum()]))
@@ -260,8 +374,8 @@ def loss_grad(params, inp, target, c, input_grad=False):
     g = conv_relu_back(0, a["x"], a["e0a"], g)
     flat = pack(G)
     if input_grad:
-        return val, flat, g[..., :2]
-    return val, flat
+        return flat, g[..., :2]
+    return flat
 
 
 def grid_input(r, N, cval):

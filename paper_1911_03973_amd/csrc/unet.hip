@@ -826,7 +826,146 @@ __global__ void k_loss_fin(const double *__restrict__ part, int B, int slices, d
     if (loss) *loss = L / B;
 }
 
-// gy = 2 (y - t) / (B sum t^2) (FP32), gd0[p][c] = gy w[c] (BF16)
+// Energy loss on the structured grid.  An image of n x n pixels holds the
+// interior nodes of the unit square's n x n-cell grid, each cell cut by its
+// diagonal from the lower-left to the upper-right corner: pixel (y, x) is node
+// (x + 1, y + 1) and the last row and column hold no node.  With homogeneous
+// Dirichlet data the P1 operator -Delta + nu I of eq. (4) on these nodes is the
+// 5-point Laplacian plus nu h^2 times the P1 mass stencil (1/2 at the node,
+// 1/12 at its six edge neighbours: the four axis neighbours and the two along
+// the diagonal), h = 1 / n.
+__device__ __forceinline__ double grid_op(const float *__restrict__ v, int n, int y, int x, double nuh2) {
+    auto at = [&](int yy, int xx) -> double {
+        return (yy >= 0 && xx >= 0 && yy < n - 1 && xx < n - 1) ? (double)v[(int64_t)yy * n + xx] : 0.0;
+    };
+    const double c = at(y, x), ax = at(y, x + 1) + at(y, x - 1) + at(y + 1, x) + at(y - 1, x),
+                 dg = at(y + 1, x + 1) + at(y - 1, x - 1);
+    return 4.0 * c - ax + nuh2 * (0.5 * c + (ax + dg) * (1.0 / 12.0));
+}
+
+__device__ __forceinline__ double sample_nuh2(const float *__restrict__ in2, int64_t HW, int b, int n, double nu_scale) {
+    const double h = 1.0 / n;
+    return nu_scale * (double)in2[(int64_t)b * HW * 2 + 1] * h * h;
+}
+
+// per (slice, sample) over interior pixels: y.At, y.Ay, t.At -> part[b][slice][3]
+__global__ __launch_bounds__(256) void k_eloss_part(const float *__restrict__ y, const float *__restrict__ t,
+                                                    const float *__restrict__ in2, int n, double nu_scale,
+                                                    int slices, double *__restrict__ part) {
+    __shared__ double red[3 * 4];
+    const int b = blockIdx.y, s = blockIdx.x;
+    const int64_t HW = (int64_t)n * n;
+    const int64_t per = (HW + slices - 1) / slices;
+    const int64_t i0 = s * per, i1 = std::min<int64_t>(HW, i0 + per);
+    const double nuh2 = sample_nuh2(in2, HW, b, n, nu_scale);
+    const float *yb = y + b * HW, *tb = t + b * HW;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+        const int py = (int)(i / n), px = (int)(i % n);
+        if (py >= n - 1 || px >= n - 1) continue;
+        const double At = grid_op(tb, n, py, px, nuh2), Ay = grid_op(yb, n, py, px, nuh2), yv = yb[i];
+        v[0] += yv * At;
+        v[1] += yv * Ay;
+        v[2] += (double)tb[i] * At;
+    }
+    block_sum_n<256, 3>(v, red);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) part[((int64_t)b * slices + s) * 3 + k] = v[k];
+}
+
+// sums[b] = (y.At, y.Ay, t.At); loss = mean over b of 1 - (y.At)^2 / ((y.Ay)(t.At)),
+// a sample with y.Ay <= 0 or t.At <= 0 counting 1 (one thread, fixed order)
+__global__ void k_eloss_fin(const double *__restrict__ part, int B, int slices, double *__restrict__ sums,
+                            double *__restrict__ loss) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double L = 0.0;
+    for (int b = 0; b < B; ++b) {
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int s = 0; s < slices; ++s)
+            for (int k = 0; k < 3; ++k) v[k] += part[((int64_t)b * slices + s) * 3 + k];
+        for (int k = 0; k < 3; ++k) sums[3 * b + k] = v[k];
+        L += (v[1] > 0.0 && v[2] > 0.0) ? 1.0 - v[0] * v[0] / (v[1] * v[2]) : 1.0;
+    }
+    if (loss) *loss = L / B;
+}
+
+__device__ __forceinline__ void out_grad_store(float g, const float *__restrict__ w, int C, int64_t p, float *gy,
+                                               bf16 *__restrict__ gd0) {
+    gy[p] = g;
+    if (!gd0) return;
+    for (int c = 0; c < C; c += 8) {
+        bf8 v;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (bf16)(g * w[c + i]);
+        *reinterpret_cast<bf8 *>(gd0 + p * C + c) = v;
+    }
+}
+
+// gy = (1/B) (2 a^2 / (b^2 c) A y - 2 a / (b c) A t) on interior pixels, 0
+// elsewhere (a, b, c = y.At, y.Ay, t.At); gd0[p][c] = gy w[c] (BF16)
+__global__ void k_eloss_bwd(const float *__restrict__ y, const float *__restrict__ t, const float *__restrict__ in2,
+                            const double *__restrict__ sums, const float *__restrict__ w, int C, int n, int B,
+                            double nu_scale, float *__restrict__ gy, bf16 *__restrict__ gd0) {
+    const int64_t HW = (int64_t)n * n, P = HW * B;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(p / HW);
+        const int64_t i = p % HW;
+        const int py = (int)(i / n), px = (int)(i % n);
+        const double a = sums[3 * b], bb = sums[3 * b + 1], c = sums[3 * b + 2];
+        double g = 0.0;
+        if (py < n - 1 && px < n - 1 && bb > 0.0 && c > 0.0) {
+            const double nuh2 = sample_nuh2(in2, HW, b, n, nu_scale);
+            const double Ay = grid_op(y + b * HW, n, py, px, nuh2), At = grid_op(t + b * HW, n, py, px, nuh2);
+            g = (2.0 * a / (bb * c)) * (a / bb * Ay - At) / B;
+        }
+        out_grad_store((float)g, w, C, p, gy, gd0);
+    }
+}
+
+// Output smoothing: one pass of the 3x3 binomial filter (1 2 1; 2 4 2; 1 2 1) / 16
+// over the pixels x < W-1, y < H-1 of each image, the last row and column read
+// and written as 0 (they hold no node in the grid layout).  As a matrix the
+// pass is M K M with K the zero-padded symmetric convolution and M that pixel
+// mask, so it is symmetric and serves as its own adjoint in the backward pass.
+__global__ void k_binom(const float *__restrict__ in, int H, int W, int64_t P, float *__restrict__ out) {
+    const int64_t HW = (int64_t)H * W;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = p % HW;
+        const int y = (int)(i / W), x = (int)(i % W);
+        if (y >= H - 1 || x >= W - 1) {
+            out[p] = 0.f;
+            continue;
+        }
+        const float *im = in + (p - i);
+        float s = 0.f;
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int yy = y + dy;
+            if (yy < 0 || yy >= H - 1) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int xx = x + dx;
+                if (xx < 0 || xx >= W - 1) continue;
+                s += (float)((dy == 0 ? 2 : 1) * (dx == 0 ? 2 : 1)) * im[(int64_t)yy * W + xx];
+            }
+        }
+        out[p] = s * (1.f / 16.f);
+    }
+}
+
+// gd0[p][c] = gy[p] w[c] (BF16)
+__global__ void k_out_gd0(const float *__restrict__ gy, const float *__restrict__ w, int C, int64_t P,
+                          bf16 *__restrict__ gd0) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        const float g = gy[p];
+        for (int c = 0; c < C; c += 8) {
+            bf8 v;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = (bf16)(g * w[c + i]);
+            *reinterpret_cast<bf8 *>(gd0 + p * C + c) = v;
+        }
+    }
+}
+
+// gy = 2 (y - t) / (B sum t^2) (FP32), gd0[p][c] = gy w[c] (BF16; skipped when gd0 is NULL)
 __global__ void k_out_bwd(const float *__restrict__ y, const float *__restrict__ t, const double *__restrict__ sums,
                           const float *__restrict__ w, int C, int64_t HW, int B, float *__restrict__ gy,
                           bf16 *__restrict__ gd0) {
@@ -834,13 +973,7 @@ __global__ void k_out_bwd(const float *__restrict__ y, const float *__restrict__
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = p / HW;
         const float g = (float)(2.0 * ((double)y[p] - t[p]) / ((double)B * fmax(sums[2 * b], 1e-300)));
-        gy[p] = g;
-        for (int c = 0; c < C; c += 8) {
-            bf8 v;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) v[i] = (bf16)(g * w[c + i]);
-            *reinterpret_cast<bf8 *>(gd0 + p * C + c) = v;
-        }
+        out_grad_store(g, w, C, p, gy, gd0);
     }
 }
 
@@ -1049,6 +1182,10 @@ struct UNet {
     double *sums = nullptr, *lpart = nullptr, *gpart = nullptr;
     int64_t partial_cap = 0;
     int loss_slices = 64;
+    int loss_kind = FEM_UNET_LOSS_L2;
+    double nu_scale = 0.0;  // energy loss: nu = nu_scale * input channel 1
+    int out_smooth = 0;     // binomial passes on the output
+    float *ys = nullptr;    // their second buffer
 };
 
 namespace {
@@ -1300,18 +1437,46 @@ int forward(UNet &N, int B, const float *in, hipStream_t st) {
     ok(conv_fwd(N, L[15], N.u0, &N.e0, N.d0a, B, st));
     ok(conv_fwd(N, L[16], N.d0a, nullptr, N.d0, B, st));
     if (rc) return rc;
-    k_out_fwd<<<grid1(P0), 256, 0, st>>>(N.d0.a, N.w + N.out_woff, N.w + N.out_boff, N.c, P0, N.out);
+    // with k smoothing passes the 1x1 layer writes where k alternating passes end in N.out
+    float *a = (N.out_smooth & 1) ? N.ys : N.out;
+    k_out_fwd<<<grid1(P0), 256, 0, st>>>(N.d0.a, N.w + N.out_woff, N.w + N.out_boff, N.c, P0, a);
+    for (int k = 0; k < N.out_smooth; ++k) {
+        float *b = a == N.out ? N.ys : N.out;
+        k_binom<<<grid1(P0), 256, 0, st>>>(a, N.H, N.W, P0, b);
+        a = b;
+    }
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
 
-// loss and every parameter gradient (into N.g) for the forward held in N.out
-int backward(UNet &N, int B, const float *target, double *loss, hipStream_t st) {
+// loss and every parameter gradient (into N.g) for the forward of `in` held in N.out
+int backward(UNet &N, int B, const float *in, const float *target, double *loss, hipStream_t st) {
     const int64_t HW = (int64_t)N.H * N.W, P0 = HW * B;
     dim3 lg(N.loss_slices, B);
-    k_loss_part<<<lg, 256, 0, st>>>(N.out, target, HW, N.loss_slices, N.lpart);
-    k_loss_fin<<<1, 64, 0, st>>>(N.lpart, B, N.loss_slices, N.sums, loss);
-    k_out_bwd<<<grid1(P0), 256, 0, st>>>(N.out, target, N.sums, N.w + N.out_woff, N.c, HW, B, N.gy, N.d0.g);
+    // gradient of the (smoothed) output; with smoothing it is passed back
+    // through the same passes (their own adjoint), ending in N.gy, before the
+    // 1x1 layer's gradients are formed
+    const bool sm = N.out_smooth > 0;
+    float *ga = (N.out_smooth & 1) ? N.ys : N.gy;
+    bf16 *gd0 = sm ? nullptr : N.d0.g;
+    if (N.loss_kind == FEM_UNET_LOSS_ENERGY) {
+        k_eloss_part<<<lg, 256, 0, st>>>(N.out, target, in, N.H, N.nu_scale, N.loss_slices, N.lpart);
+        k_eloss_fin<<<1, 64, 0, st>>>(N.lpart, B, N.loss_slices, N.sums, loss);
+        k_eloss_bwd<<<grid1(P0), 256, 0, st>>>(N.out, target, in, N.sums, N.w + N.out_woff, N.c, N.H, B, N.nu_scale,
+                                               ga, gd0);
+    } else {
+        k_loss_part<<<lg, 256, 0, st>>>(N.out, target, HW, N.loss_slices, N.lpart);
+        k_loss_fin<<<1, 64, 0, st>>>(N.lpart, B, N.loss_slices, N.sums, loss);
+        k_out_bwd<<<grid1(P0), 256, 0, st>>>(N.out, target, N.sums, N.w + N.out_woff, N.c, HW, B, ga, gd0);
+    }
+    if (sm) {
+        for (int k = 0; k < N.out_smooth; ++k) {
+            float *gb = ga == N.gy ? N.ys : N.gy;
+            k_binom<<<grid1(P0), 256, 0, st>>>(ga, N.H, N.W, P0, gb);
+            ga = gb;
+        }
+        k_out_gd0<<<grid1(P0), 256, 0, st>>>(N.gy, N.w + N.out_woff, N.c, P0, N.d0.g);
+    }
     const int64_t so = wgrad_splits(P0);
     if (N.c == 16) k_out_wgrad<16><<<(unsigned)so, 256, 0, st>>>(N.d0.a, N.gy, P0, N.partial);
     else k_out_wgrad<32><<<(unsigned)so, 256, 0, st>>>(N.d0.a, N.gy, P0, N.partial);
@@ -1541,6 +1706,7 @@ int fem_unet_create(int H, int W, int max_batch, int channels, uint64_t seed, vo
     const int64_t P0 = fem::pixels(N, 0, B);
     add((void **)&N.out, P0 * 4);
     add((void **)&N.gy, P0 * 4);
+    add((void **)&N.ys, P0 * 4);
     add((void **)&N.in2, (size_t)H * W * 2 * 4);
     int64_t cap = fem::wgrad_splits(P0) * (c + 1);
     for (const auto &l : N.L) {
@@ -1551,8 +1717,8 @@ int fem_unet_create(int H, int W, int max_batch, int channels, uint64_t seed, vo
     }
     N.partial_cap = cap;
     add((void **)&N.partial, cap * 4);
-    add((void **)&N.sums, (size_t)2 * B * 8);
-    add((void **)&N.lpart, (size_t)2 * B * N.loss_slices * 8);
+    add((void **)&N.sums, (size_t)3 * B * 8);
+    add((void **)&N.lpart, (size_t)3 * B * N.loss_slices * 8);
     add((void **)&N.gpart, (fem::kGridScale + 8) * 8);
     size_t total = 0;
     std::vector<size_t> offs;
@@ -1637,8 +1803,31 @@ int fem_unet_loss_grad(fem_unet *net, int batch, const float *d_in, const float 
     fem::UNet &N = net->net;
     hipStream_t st = S(stream);
     if (int rc = fem::forward(N, batch, d_in, st)) return rc;
-    if (int rc = fem::backward(N, batch, d_target, d_loss, st)) return rc;
+    if (int rc = fem::backward(N, batch, d_in, d_target, d_loss, st)) return rc;
     if (d_grad) FEM_HIP_CHECK(hipMemcpyAsync(d_grad, N.g, N.nparam * 4, hipMemcpyDeviceToDevice, st));
+    return FEM_OK;
+}
+
+int fem_unet_set_loss(fem_unet *net, int kind, double nu_scale) {
+    if (int rc = check_net(net)) return rc;
+    fem::UNet &N = net->net;
+    if (kind == FEM_UNET_LOSS_L2) {
+        N.loss_kind = kind;
+        N.nu_scale = 0.0;
+        return FEM_OK;
+    }
+    if (kind != FEM_UNET_LOSS_ENERGY) return set_error(FEM_EINVAL, "unknown loss kind");
+    if (N.H != N.W) return set_error(FEM_EINVAL, "the energy loss needs square images");
+    if (!(nu_scale >= 0.0) || !std::isfinite(nu_scale)) return set_error(FEM_EINVAL, "nu_scale must be finite and >= 0");
+    N.loss_kind = kind;
+    N.nu_scale = nu_scale;
+    return FEM_OK;
+}
+
+int fem_unet_set_output_smoothing(fem_unet *net, int passes) {
+    if (int rc = check_net(net)) return rc;
+    if (passes < 0 || passes > 8) return set_error(FEM_EINVAL, "output smoothing passes must be in [0, 8]");
+    net->net.out_smooth = passes;
     return FEM_OK;
 }
 
@@ -1651,7 +1840,7 @@ int fem_unet_train_step(fem_unet *net, int batch, const float *d_in, const float
     fem::UNet &N = net->net;
     hipStream_t st = S(stream);
     if (int rc = fem::forward(N, batch, d_in, st)) return rc;
-    if (int rc = fem::backward(N, batch, d_target, d_loss, st)) return rc;
+    if (int rc = fem::backward(N, batch, d_in, d_target, d_loss, st)) return rc;
     N.step += 1;
     const double b1 = 0.9, b2 = 0.999;
     const float c1 = (float)(1.0 - std::pow(b1, (double)N.step)), c2 = (float)(1.0 - std::pow(b2, (double)N.step));

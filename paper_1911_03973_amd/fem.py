@@ -26,6 +26,7 @@ F64, F32, F32X2 = 0, 1, 2
 MFREE = 3  # matrix-free: K_e, M_e rebuilt from the coordinates in every pass
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 SMOOTH_JACOBI, SMOOTH_CHEBYSHEV = 0, 1  # multigrid smoothers
+LOSS_L2, LOSS_ENERGY = 0, 1  # U-Net training losses
 
 _STATUS = {
     FEM_EINVAL: "FEM_EINVAL",
@@ -162,6 +163,8 @@ _SIGS = {
     "fem_unet_forward": [_vp, _int, _vp, _vp, _vp],
     "fem_unet_loss_grad": [_vp, _int, _vp, _vp, _vp, _vp, _vp],
     "fem_unet_train_step": [_vp, _int, _vp, _vp, ctypes.c_float, _vp, _vp],
+    "fem_unet_set_loss": [_vp, _int, ctypes.c_double],
+    "fem_unet_set_output_smoothing": [_vp, _int],
     "fem_unet_precondition": [_vp, _int, _vp, _dbl, _vp, _vp, _vp],
     "fem_unet_make_pair": [_vp, _int, _vp, _vp, _vp, _dbl, _vp, _vp, _vp],
     "fem_fcg_solve": [_vp, ctypes.POINTER(FcgOpts), _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(FcgInfo), _vp],
@@ -562,6 +565,14 @@ class UNet:
         out = torch.empty((B, self.H, self.W), dtype=torch.float32, device="cuda")
         _check(_lib.fem_unet_forward(self.handle, B, _ptr(inp), _ptr(out), _stream(stream)))
         return out
+
+    def set_loss(self, kind, nu_scale=0.0):
+        """LOSS_L2, or LOSS_ENERGY with nu = nu_scale * input channel 1 (fem_unet_set_loss)."""
+        _check(_lib.fem_unet_set_loss(self.handle, int(kind), float(nu_scale)))
+
+    def set_output_smoothing(self, passes):
+        """Binomial smoothing passes after the output layer (fem_unet_set_output_smoothing)."""
+        _check(_lib.fem_unet_set_output_smoothing(self.handle, int(passes)))
 
     def loss_grad(self, inp, target, stream=None):
         """(loss tensor [1] float64, gradient float32 [n_params])."""

@@ -18,6 +18,11 @@ and the target, e_k scaled to unit RMS.  Flexible CG only uses the direction
 of z = N(r) (its step length is re-optimised every iteration), so the scale
 of the error is not learned.
 
+The loss is either the relative L2 error of the scaled error image or its
+energy-norm counterpart: the fraction of ||e||_A^2 left after the
+energy-optimal step along the network output, which is the step the
+preconditioner's cycle takes (fem_unet_set_loss).
+
 The training set is streamed: the problems are taken in rounds; each round's
 pairs fill a pool on the device and the network takes one Adam step per
 `batch` pairs of the pool, in a random order without repetition, so every
@@ -38,9 +43,21 @@ import torch
 from . import fem, inputs
 
 
+NU_PER_CVAL = 100.0  # nu = NU_PER_CVAL * the network's constant input channel
+
+
 def cval_of(nu):
     """Constant second input channel of the network for coefficient nu."""
-    return float(nu) / 100.0
+    return float(nu) / NU_PER_CVAL
+
+
+def use_energy_loss(net, out_smooth=2):
+    """Trains `net` on the energy loss of the learned problems' operator (the
+    constant channel carries nu / NU_PER_CVAL), with `out_smooth` binomial
+    passes on its output: they damp the BF16 rounding noise whose energy norm
+    would otherwise swamp that of the smooth errors."""
+    net.set_loss(fem.LOSS_ENERGY, NU_PER_CVAL)
+    net.set_output_smoothing(out_smooth)
 
 
 @dataclasses.dataclass

@@ -148,3 +148,149 @@ def test_grid_mapping_round_trip():
     z2 = z.reshape(N + 1, N + 1)
     assert np.all(z2[0] == 0) and np.all(z2[N] == 0) and np.all(z2[:, 0] == 0) and np.all(z2[:, N] == 0)
     np.testing.assert_allclose(z2[1:N, 1:N], img[0, :N - 1, :N - 1, 0])
+
+
+# ---------------------------------------------------------------------------
+# Energy loss
+# ---------------------------------------------------------------------------
+
+def test_unit_square_grid_is_the_learned_workload_mesh():
+    from paper_1911_03973_amd import inputs
+
+    n = 6
+    coords, elems, bnd = U.unit_square_grid(n)
+    m = inputs.square_mesh(n)
+    np.testing.assert_allclose(coords, m.coords, rtol=0, atol=1e-15)
+    as_set = lambda E: {tuple(sorted(int(v) for v in e)) for e in E}  # noqa: E731
+    assert as_set(elems) == as_set(m.elems)
+    np.testing.assert_array_equal(np.flatnonzero(bnd), np.sort(inputs.boundary_nodes(m, "all")))
+
+
+@pytest.mark.parametrize("n,nu", [(8, 0.0), (8, 37.0), (12, 100.0)])
+def test_grid_operator_is_the_p1_stencil(n, nu):
+    """On the diagonal-cut grid the assembled P1 stiffness is the 5-point
+    Laplacian (the diagonal edges have cotangent weight 0) and the mass matrix
+    has h^2/2 on the diagonal and h^2/12 for each of the six edge neighbours."""
+    rng = np.random.default_rng(1)
+    v = rng.normal(size=(n, n))
+    v[n - 1, :] = 0.0
+    v[:, n - 1] = 0.0
+    h = 1.0 / n
+    pad = np.zeros((n + 2, n + 2))
+    pad[1:n, 1:n] = v[: n - 1, : n - 1]
+    want = np.zeros((n, n))
+    for y in range(n - 1):
+        for x in range(n - 1):
+            P = lambda dy, dx: pad[y + 1 + dy, x + 1 + dx]  # noqa: E731
+            axis = P(0, 1) + P(0, -1) + P(1, 0) + P(-1, 0)
+            want[y, x] = 4 * P(0, 0) - axis + nu * h * h * (P(0, 0) / 2 + (axis + P(1, 1) + P(-1, -1)) / 12)
+    np.testing.assert_allclose(U.grid_operator(n, nu)(v), want, rtol=1e-13, atol=1e-13)
+
+
+def test_energy_loss_is_the_energy_left_after_the_optimal_step():
+    """Each term equals min_s ||s y - t||_A^2 / ||t||_A^2 found by a scalar
+    minimiser; the loss ignores the scale and sign of y, is 0 for y = t and 1
+    (zero gradient) for a zero output."""
+    from scipy.optimize import minimize_scalar
+
+    n = 8
+    rng = np.random.default_rng(2)
+    y = rng.normal(size=(2, n, n))
+    t = rng.normal(size=(2, n, n)) + 0.5 * y
+    nus = [3.0, 60.0]
+    val, _ = U.energy_loss(y, t, nus)
+    inner = np.zeros((n, n))
+    inner[: n - 1, : n - 1] = 1
+    terms = []
+    for k in range(2):
+        A = U.grid_operator(n, nus[k])
+        yk, tk = y[k] * inner, t[k] * inner
+        e = lambda s: float(np.sum((s * yk - tk) * A(s * yk - tk)))  # noqa: E731
+        best = minimize_scalar(e, bracket=(-10, 10), tol=1e-12).fun
+        terms.append(best / float(np.sum(tk * A(tk))))
+    assert val == pytest.approx(np.mean(terms), rel=1e-8)
+    assert 0.0 <= val <= 1.0
+    assert U.energy_loss(-3.7 * y, t, nus)[0] == pytest.approx(val, rel=1e-12)
+    assert U.energy_loss(y, 0.2 * t, nus)[0] == pytest.approx(val, rel=1e-12)
+    assert U.energy_loss(t, t, nus)[0] == pytest.approx(0.0, abs=1e-14)
+    v0, g0 = U.energy_loss(np.zeros_like(y), t, nus)
+    assert v0 == 1.0 and np.all(g0 == 0.0)
+    # values on the last row and column do not enter
+    y2 = y.copy()
+    y2[:, n - 1, :] = 5.0
+    y2[:, :, n - 1] = -5.0
+    assert U.energy_loss(y2, t, nus)[0] == pytest.approx(val, rel=1e-14)
+
+
+def test_energy_backward_matches_finite_differences():
+    """dL/dy and dL/dparams of the energy loss against central differences (relative 1e-6)."""
+    c = 16
+    rng = np.random.default_rng(11)
+    p = _rand_params(c, 12)
+    inp = rng.normal(size=(2, 16, 16, 2))
+    inp[0, ..., 1] = 0.3
+    inp[1, ..., 1] = 0.8
+    t = rng.normal(size=(2, 16, 16))
+    nus = [30.0, 80.0]
+    y = U.forward(p, inp, c)
+    _, gy = U.energy_loss(y, t, nus)
+    for _ in range(8):
+        i = tuple(int(v) for v in (rng.integers(2), rng.integers(16), rng.integers(16)))
+        e = np.zeros_like(y)
+        e[i] = 1e-6
+        fd = (U.energy_loss(y + e, t, nus)[0] - U.energy_loss(y - e, t, nus)[0]) / 2e-6
+        assert abs(fd - gy[i]) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(gy).max())
+    val, g = U.loss_grad(p, inp, t, c, kind="energy", nu_scale=100.0)
+    f = lambda q: U.energy_loss(U.forward(q, inp, c), t, nus)[0]  # noqa: E731
+    assert val == pytest.approx(f(p), rel=1e-14)
+    offs = np.cumsum([0] + [W.size + b.size for W, b in U.unpack(p, c)])
+    worst = 0.0
+    for k in range(len(offs) - 1):
+        for i in list(rng.integers(offs[k], offs[k + 1], size=2)) + [offs[k + 1] - 1]:
+            fd = _fd(f, p, i, 1e-6)
+            worst = max(worst, abs(fd - g[i]) / max(abs(fd), 1e-3 * np.abs(g).max()))
+    assert worst < 1e-6, worst
+
+
+def test_output_filter_matches_correlate_and_is_symmetric():
+    rng = np.random.default_rng(21)
+    y = rng.normal(size=(2, 10, 12))
+    k = np.array([[1.0, 2.0, 1.0], [2.0, 4.0, 2.0], [1.0, 2.0, 1.0]]) / 16.0
+    mask = np.zeros((10, 12))
+    mask[:9, :11] = 1.0
+    want = y.copy()
+    for _ in range(2):
+        want = np.stack([signal.correlate2d(w * mask, k, mode="same") * mask for w in want])
+    np.testing.assert_allclose(U.output_filter(y, 2), want, rtol=1e-13, atol=1e-15)
+    u, v = rng.normal(size=(2, 1, 10, 12))
+    assert np.sum(U.output_filter(u, 3) * v) == pytest.approx(np.sum(u * U.output_filter(v, 3)), rel=1e-12)
+    # a constant inside the region is kept away from its edge; the row sums are 1
+    c = np.ones((1, 10, 12))
+    assert np.allclose(U.output_filter(c, 1)[0, 2:7, 2:9], 1.0)
+
+
+def test_smoothed_network_backward_matches_finite_differences():
+    c = 16
+    rng = np.random.default_rng(13)
+    p = _rand_params(c, 14)
+    inp = rng.normal(size=(1, 16, 16, 2))
+    inp[..., 1] = 0.5
+    # a target near the output keeps the energy loss away from 1, where its
+    # gradient (proportional to y.At) is too small for difference quotients
+    y0 = U.forward(p, inp, c, smooth=2)
+    t = y0 + 0.3 * np.std(y0) * rng.normal(size=(1, 16, 16))
+    for kind in ("l2", "energy"):
+        val, g = U.loss_grad(p, inp, t, c, kind=kind, nu_scale=100.0, smooth=2)
+
+        def f(q):
+            y = U.forward(q, inp, c, smooth=2)
+            return U.energy_loss(y, t, [50.0])[0] if kind == "energy" else U.loss(y, t)
+
+        assert val == pytest.approx(f(p), rel=1e-14)
+        offs = np.cumsum([0] + [W.size + b.size for W, b in U.unpack(p, c)])
+        worst = 0.0
+        for k in (0, 8, 16, 17):
+            for i in list(rng.integers(offs[k], offs[k + 1], size=2)) + [offs[k + 1] - 1]:
+                fd = _fd(f, p, i, 1e-5)
+                worst = max(worst, abs(fd - g[i]) / max(abs(fd), 1e-3 * np.abs(g).max()))
+        assert worst < 1e-6, (kind, worst)
