@@ -16,8 +16,10 @@
 // which the network plays the coarse correction: `smooth` damped-Jacobi steps
 // z += omega D^-1 (r - A z) from z = 0, the network correction
 // z += s N(r - A z) with the energy-optimal s = (n . rz) / (n . A n), and
-// `smooth` more Jacobi steps.  The Jacobi steps after the first are fused into
-// one element pass each (the residual r - A z is never stored).
+// `smooth` more Jacobi steps.  The Jacobi steps are fused into one element
+// pass each (the residual r - A z is never stored), except the first of each
+// half: from z = 0 it is omega D^-1 r, and after the coarse correction the
+// residual is r_z - s A n from the products the correction formed already.
 //
 // The scalars live on the device: single-workgroup kernels add the per-block
 // dot partials in a fixed order and write the FCG scalars and a stop flag
@@ -236,12 +238,17 @@ __global__ __launch_bounds__(kBlock) void k_coarse_scale(const double *__restric
     sc[0] = (v[1] > 0.0 && isfinite(s)) ? s : 0.0;
 }
 
-// z += s nz
-__global__ void k_coarse_add(int64_t n, const double *__restrict__ sc, const double *__restrict__ nz,
-                             double *__restrict__ z) {
+// The coarse correction z_c = z + s nz followed by the first post-smoothing
+// step zn = z_c + omega D^-1 (r - A z_c) without an element pass: the
+// residual of z_c is r - A z - s A nz = rz - s An, both already formed
+// (0 on Dirichlet nodes, where D^-1 is 0 as well).
+__global__ void k_coarse_step(int64_t n, const double *__restrict__ sc, const double *__restrict__ nz,
+                              const double *__restrict__ rz, const double *__restrict__ An,
+                              const double *__restrict__ dinv, double omega, const double *__restrict__ z,
+                              double *__restrict__ zn) {
     const double c = sc[0];
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        z[i] += c * nz[i];
+        zn[i] = (z[i] + c * nz[i]) + omega * dinv[i] * (rz[i] - c * An[i]);
 }
 
 // out = (b ? b : 0) + sign * A x, 0 on Dirichlet nodes
@@ -442,9 +449,10 @@ int precondition(const DevPlan &P, const FcgWork &w, const CycleOpts &c, const d
     if (int rc = pass(P, A, c.heads, OpLin{w.nz, nullptr, w.An, P.mask, 1.0}, w.scratch, s)) return rc;
     k_dots<2><<<gv, kBlock, 0, s>>>(n, w.ptrs + 10, w.ptrs + 12, w.part);
     k_coarse_scale<<<1, kBlock, 0, s>>>(w.part, gv, w.sc);
-    k_coarse_add<<<gv, kBlock, 0, s>>>(n, w.sc, w.nz, cur);
+    k_coarse_step<<<gv, kBlock, 0, s>>>(n, w.sc, w.nz, w.rz, w.An, w.dinv, c.omega, cur, oth);
     FEM_HIP_CHECK(hipGetLastError());
-    for (int k = 0; k < c.smooth; ++k) {
+    std::swap(cur, oth);
+    for (int k = 1; k < c.smooth; ++k) {
         if (int rc = pass(P, A, c.heads, OpJacobiStep{cur, r, w.dinv, oth, c.omega}, w.scratch, s)) return rc;
         std::swap(cur, oth);
     }
