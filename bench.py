@@ -665,7 +665,8 @@ def learned_fcg(args):
     else:
         net.set_output_smoothing(args.learned_out_smooth)
     hist, n_pairs, t_data, t_train = learn.train_streaming(fam, net, params, segs, args.learned_batch,
-                                                           args.learned_lr, args.learned_rounds, log=log)
+                                                           args.learned_lr, args.learned_rounds, log=log,
+                                                           epochs=args.learned_epochs)
     del fam
     torch.cuda.empty_cache()
     log(f"[bench] learned: {n_pairs} pairs in {t_data:.1f} s, {len(hist)} steps in {t_train:.1f} s")
@@ -720,10 +721,10 @@ def learned_fcg(args):
         "output_smoothing_passes": args.learned_out_smooth,
         "preconditioner": f"FCG(1), two-level cycle: {args.learned_smooth} damped-Jacobi steps (omega 2/3), network "
                           f"correction, {args.learned_smooth} Jacobi steps, {args.learned_cycle.upper()} cycle passes; "
-                          "hand-over to Jacobi-PCG (from the best iterate) after 200 iterations without halving ||r||",
+                          "hand-over to Jacobi-PCG (restarted from x0) after 200 iterations without halving ||r||",
         "pairs": n_pairs, "train_problems": len(params), "snapshots_per_problem": len(segs),
         "eval_problems": len(rows),
-        "train_steps": len(hist), "train_batch": args.learned_batch,
+        "train_steps": len(hist), "train_batch": args.learned_batch, "train_epochs": args.learned_epochs,
         "train_loss_first": round(float(hist[:50].mean()), 4), "train_loss_last": round(float(hist[-200:].mean()), 4),
         "data_s": round(t_data, 2), "train_s": round(t_train, 2),
         "time_to_1e8_jacobi_pcg_s": round(t_pcg, 4), "time_to_1e8_learned_fcg_s": round(t_fcg, 4),
@@ -795,6 +796,7 @@ def main():
     ap.add_argument("--learned-lr", type=float, default=2e-3)
     ap.add_argument("--learned-eval", type=int, default=32, help="held-out problems")
     ap.add_argument("--learned-loss", choices=["energy", "l2"], default="energy")
+    ap.add_argument("--learned-epochs", type=int, default=2, help="passes over each round's pool of pairs")
     ap.add_argument("--learned-out-smooth", type=int, default=2,
                     help="binomial smoothing passes on the network output")
     ap.add_argument("--learned-ablate", type=int, default=4,

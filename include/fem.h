@@ -506,10 +506,10 @@ void fem_fcg_opts_default(fem_fcg_opts *o);
  * at fem_unet_precondition), alone or inside the two-level cycle of
  * opts->smooth, or by Jacobi (net == NULL; linear triangles or tetrahedra).
  * With a network, a non-finite or zero output, p.q <= 0, or stall_iters
- * iterations without halving ||r|| end the FCG phase: the iterate of the last
- * halving of ||r|| (x0 if it never halved) goes to the Jacobi-PCG solver
- * (fem_pcg_solve with opts->dtype), which finishes the solve to the same
- * absolute target.  The true FP64 residual decides convergence.  x: x0 on
+ * iterations without halving ||r|| end the FCG phase: x is reset to x0 and
+ * the Jacobi-PCG solver (fem_pcg_solve with opts->dtype) solves from there, so
+ * that the fallback never needs more Jacobi-PCG iterations than a cold start
+ * (from an iterate the network cycle has shaped it can need more).  The true FP64 residual decides convergence.  x: x0 on
  * entry (Dirichlet values included), the solution on exit; after
  * FEM_ENOCONV the last iterate.  Allocates a workspace for the call;
  * synchronises `stream`. */

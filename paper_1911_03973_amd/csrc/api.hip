@@ -564,8 +564,8 @@ int fem_fcg_solve(const fem_plan *plan_c, const fem_fcg_opts *o, fem_unet *net, 
     info->r0 = res.r0;
     info->relres = res.relres;
     if (rc == fem::kFcgHandover) {
-        // Jacobi-PCG from the handed-over iterate to the same absolute
-        // target (res.rnorm: the true residual norm of that iterate)
+        // Jacobi-PCG from x0 (reset by the FCG phase) to the same absolute
+        // target (res.rnorm: the true residual norm of x0)
         fem_solve_opts po;
         fem_solve_opts_default(&po);
         po.dtype = o->dtype;

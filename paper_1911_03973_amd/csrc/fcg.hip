@@ -31,9 +31,11 @@
 // still queued return at once (the cycle's own launches run on scratch
 // vectors and change nothing the solve keeps).
 //
-// With a network, the iterate of the last halving of ||r|| (x0 before the
-// first) is kept; a hand-over to Jacobi-PCG starts from it, with the true
-// residual recomputed for it.
+// With a network, x0 is kept: a hand-over to Jacobi-PCG restarts from it.
+// Measured at 1024^2, Jacobi-PCG from an iterate the network cycle had
+// shaped (even one that had halved ||r|| several times) needed 1.4-1.9x the
+// iterations of a cold start, so the fallback costs at most the FCG steps
+// already taken plus a cold Jacobi-PCG solve.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -62,7 +64,6 @@ struct FcgState {
     int iters;     // completed steps (x updated)
     int restart;   // the next direction is p = z
     int best_it;   // step of the last halving of ||r||
-    int improved;  // the last step halved ||r||: x is kept as the best iterate
     int pcalls;    // cycles whose output entered a step
     int stall;     // steps without halving that end the network phase
     int max_iter;
@@ -173,7 +174,6 @@ __global__ __launch_bounds__(kBlock) void k_fcg_check(const double *__restrict__
     const int it = st->iters + 1;
     st->iters = it;
     st->rn = rn;
-    st->improved = 0;
     if (!isfinite(rn)) {
         st->flag = FCG_BREAKDOWN;
         st->reason = 3;
@@ -182,7 +182,6 @@ __global__ __launch_bounds__(kBlock) void k_fcg_check(const double *__restrict__
     if (rn <= 0.5 * st->best) {
         st->best = rn;
         st->best_it = it;
-        st->improved = 1;
     }
     if (rn <= st->target) {
         st->flag = FCG_TARGET;
@@ -192,14 +191,6 @@ __global__ __launch_bounds__(kBlock) void k_fcg_check(const double *__restrict__
     } else if (it >= st->max_iter) {
         st->flag = FCG_LIMIT;
     }
-}
-
-// xb = x after a step that halved ||r||
-__global__ __launch_bounds__(kBlock) void k_fcg_keep(int64_t n, const double *__restrict__ x,
-                                                     double *__restrict__ xb, const FcgState *st) {
-    if (!st->improved || st->flag == FCG_BREAKDOWN) return;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-        xb[i] = x[i];
 }
 
 // True residual norm into the state; on a miss the iteration restarts from it
@@ -338,7 +329,7 @@ struct FcgWork {
     void *A32 = nullptr;   // packed operator as FP32 hi/lo pair (cycle on FP32 heads)
     double *d = nullptr, *dinv = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
     double *t = nullptr, *rz = nullptr, *nz = nullptr, *An = nullptr;  // two-level cycle
-    double *xb = nullptr;  // best iterate
+    double *xb = nullptr;  // x0, for a hand-over
     double *scratch = nullptr, *part = nullptr, *sc = nullptr;
     const double **ptrs = nullptr;  // device pointer tables of k_dots
     FcgState *st = nullptr;
@@ -486,7 +477,6 @@ int iteration(const DevPlan &P, const FcgWork &w, const CycleOpts &c, double *x,
     k_fcg_alpha<<<1, kBlock, 0, s>>>(w.part, gv, w.st);
     k_fcg_step<<<gv, kBlock, 0, s>>>(n, w.p, w.q, x, w.r, w.part, w.st);
     k_fcg_check<<<1, kBlock, 0, s>>>(w.part, gv, w.st);
-    if (c.net) k_fcg_keep<<<gv, kBlock, 0, s>>>(n, x, w.xb, w.st);
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
@@ -619,12 +609,8 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
             continue;  // the state already says: run, restart from the true residual
         }
         if (h.flag == FCG_HANDOVER) {
-            // continue from the best iterate: x0 when ||r|| never halved (an
-            // iterate that has not halved it may carry an error that is harder
-            // for Jacobi-PCG than the initial one), else the iterate of the last
-            // halving, or the current one if it is no worse
-            if (h.best_it == 0 || h.best < h.rn)
-                FEM_HIP_CHECK(hipMemcpyAsync(x, w.xb, n * 8, hipMemcpyDeviceToDevice, s));
+            // restart from x0 (see the head of this file)
+            FEM_HIP_CHECK(hipMemcpyAsync(x, w.xb, n * 8, hipMemcpyDeviceToDevice, s));
             if (int rc = true_residual(P, w, b, x, 0, s)) return rc;
             if (int rc = read_state(w, h, s)) return rc;
             res.fallback_reason = h.reason;

@@ -132,10 +132,9 @@ __host__ __device__ constexpr int packed_count(int nb) { return nb + nb * (nb - 
 
 // Flexible CG (fcg.hip).  With a network, a non-finite or zero network
 // output, p.q <= 0, or stall_iters iterations without halving ||r|| end the
-// FCG phase with kFcgHandover (x holds the iterate with the smallest
-// recursive residual seen, res.rnorm its true residual norm) so that the
-// caller continues with Jacobi-PCG; without a network the preconditioner is
-// Jacobi throughout.
+// FCG phase with kFcgHandover (x reset to x0, res.rnorm its true residual
+// norm) so that the caller continues with Jacobi-PCG; without a network the
+// preconditioner is Jacobi throughout.
 struct FcgResult {
     int status, iters, precond_calls, fell_back, fallback_reason, replacements;
     double relres, r0, rnorm;

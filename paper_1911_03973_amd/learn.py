@@ -204,11 +204,11 @@ def train(net, ins, tgs, steps, batch, lr, seed=0, lr_final=None, log_every=0):
     return hist.cpu().numpy()
 
 
-def train_streaming(fam, net, params, segments, batch, lr, rounds, seed=0, lr_final=None, log=None):
+def train_streaming(fam, net, params, segments, batch, lr, rounds, seed=0, lr_final=None, log=None, epochs=1):
     """Generates the pairs of the (nu, seed) problems round by round and trains on
-    each round's pool once, in a random order (one Adam step per `batch` pairs;
-    a last partial batch is dropped).  Returns (losses, pairs, data seconds,
-    training seconds)."""
+    each round's pool `epochs` times, each time in a fresh random order (one
+    Adam step per `batch` pairs; a last partial batch is dropped).  Returns
+    (losses, pairs, data seconds, training seconds)."""
     S = len(segments)
     per_round = (len(params) + rounds - 1) // rounds
     pool = per_round * S
@@ -216,7 +216,7 @@ def train_streaming(fam, net, params, segments, batch, lr, rounds, seed=0, lr_fi
     tgs = torch.empty((pool, fam.N, fam.N), dtype=torch.float32, device="cuda")
     xb = torch.empty((batch, fam.N, fam.N, 2), dtype=torch.float32, device="cuda")
     tb = torch.empty((batch, fam.N, fam.N), dtype=torch.float32, device="cuda")
-    total_steps = sum((min(per_round, len(params) - i) * S) // batch for i in range(0, len(params), per_round))
+    total_steps = epochs * sum((min(per_round, len(params) - i) * S) // batch for i in range(0, len(params), per_round))
     lr_final = lr * 0.05 if lr_final is None else lr_final
     gen = torch.Generator().manual_seed(seed)
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -234,14 +234,15 @@ def train_streaming(fam, net, params, segments, batch, lr, rounds, seed=0, lr_fi
         t_data += time.perf_counter() - t
         pairs += n
         t = time.perf_counter()
-        order = torch.randperm(n, generator=gen).cuda()
-        for k in range(n // batch):
-            idx = order[k * batch:(k + 1) * batch]
-            torch.index_select(ins[:n], 0, idx, out=xb)
-            torch.index_select(tgs[:n], 0, idx, out=tb)
-            net.train_step(xb, tb, _lr(step, total_steps, lr, lr_final), loss)
-            hist[step] = loss[0]
-            step += 1
+        for _ in range(epochs):
+            order = torch.randperm(n, generator=gen).cuda()
+            for k in range(n // batch):
+                idx = order[k * batch:(k + 1) * batch]
+                torch.index_select(ins[:n], 0, idx, out=xb)
+                torch.index_select(tgs[:n], 0, idx, out=tb)
+                net.train_step(xb, tb, _lr(step, total_steps, lr, lr_final), loss)
+                hist[step] = loss[0]
+                step += 1
         torch.cuda.synchronize()
         t_train += time.perf_counter() - t
         if log:

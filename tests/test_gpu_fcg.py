@@ -255,15 +255,21 @@ def test_jacobi_fcg_iterates_match_oracle(case):
         assert np.linalg.norm(xs - ref) <= 1e-10 * np.linalg.norm(ref), (k, np.linalg.norm(xs - ref))
 
 
-def test_handover_starts_from_best_iterate_and_meets_target():
-    """A network that hands over after a stall: Jacobi-PCG continues from the
-    best iterate to the same absolute target, judged by the oracle."""
+@pytest.mark.parametrize("check_every", [1, 16])
+def test_handover_restarts_from_x0_and_meets_target(check_every):
+    """A network that hands over after a stall: Jacobi-PCG restarts from x0, so
+    it takes exactly the iterations of a cold Jacobi-PCG solve and ends on the
+    same iterate; the oracle judges the result."""
     N = 32
     gp = learn.GridProblem.make(N, 20.0, 11)
     net = fem.UNet(N, N, channels=16, seed=2)
     x = torch.zeros(gp.n_nodes, dtype=torch.float64, device="cuda")
-    info = gp.fcg(net, x, rtol=1e-8, stall_iters=1, check_every=1)
-    assert info["status"] == 0 and info["fell_back"] >= 0
+    info = gp.fcg(net, x, rtol=1e-8, stall_iters=1, check_every=check_every)
+    assert info["status"] == 0 and info["fell_back"] >= 0 and info["iters"] >= 1
+    cold = torch.zeros_like(x)
+    ci = gp.pcg(cold, rtol=1e-8)
+    assert info["pcg_iters"] == ci["iters"]
+    assert torch.equal(x, cold)
     prob = Problem(inputs.square_mesh(N), nu=20.0, f="sine", seed=11)
     assert _true_relres(prob, x.cpu().numpy()) <= 1e-8
 
