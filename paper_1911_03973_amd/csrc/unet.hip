@@ -36,6 +36,7 @@
 
 #include "common.h"
 #include "fem.h"
+#include "kernels.h"
 #include "unet.h"
 
 namespace fem {
@@ -249,10 +250,14 @@ __global__ __launch_bounds__(256) void k_gemm_rows(Src src, Epi epi, const bf16 
 // image are computed on zero input and not stored; reduction entries past the
 // 9 taps (padding of the last block) have zero weights and read the last
 // tap's finite inputs.
-template <int TY, int TX, int NT, int CIN>
+template <int TY, int TX, int NTA, int CIN, int NS = 1>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ src1, const bf16 *__restrict__ src2, int C1,
                                                  int H, int W, int tiles_x, int tiles_y, const bf16 *__restrict__ Bp,
                                                  const float *__restrict__ bias, bf16 *__restrict__ out) {
+    // NS workgroups share a pixel tile, each computing NT = NTA / NS of its
+    // NTA column tiles (output channels [split * 16 NT, (split + 1) * 16 NT))
+    constexpr int NT = NTA / NS;
+    static_assert(NT * NS == NTA && NT >= 1, "column split");
     constexpr int MT = TY * TX / 64;
     constexpr int HX = TX + 2, HY = TY + 2;
     constexpr int KB = (9 * CIN + 31) / 32;
@@ -260,7 +265,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ src1, 
     constexpr int NBLK = (KB + KBC - 1) / KBC;  // weight stages
     constexpr int FR = (KBC * NT * 64 + 255) / 256;  // weight fragments per thread and stage
     constexpr int CU8 = CIN / 8;
-    constexpr int N = NT * 16;
+    constexpr int N = NTA * 16;  // output channels (the NHWC pitch)
     static_assert(CIN >= 8 && (CIN & (CIN - 1)) == 0, "CIN must be a power of two >= 8");
     static_assert(TX % 16 == 0 && (TY * TX) % 64 == 0, "tile shape");
     extern __shared__ __align__(16) unsigned char smem[];
@@ -268,7 +273,9 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ src1, 
     bf8 *tb0 = reinterpret_cast<bf8 *>(smem + conv_tile_bytes(TY, TX, CIN));  // [KBC][NT][64], two when NBLK > 1
     bf8 *tb1 = tb0 + KBC * NT * 64;
     const int C2 = CIN - C1;
-    const int tile = blockIdx.x;
+    const int split = NS > 1 ? (int)(blockIdx.x % NS) : 0;
+    const int tile = NS > 1 ? (int)(blockIdx.x / NS) : (int)blockIdx.x;
+    const int c0 = split * NT * 16;  // first output channel of this workgroup
     const int tx = tile % tiles_x, t2 = tile / tiles_x, ty = t2 % tiles_y, b = t2 / tiles_y;
     const int y0 = ty * TY, x0 = tx * TX;
     const int64_t img = (int64_t)b * H * W;
@@ -296,9 +303,19 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ src1, 
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[mt][t] = f4{0.f, 0.f, 0.f, 0.f};
     const bf8 *wsrc = reinterpret_cast<const bf8 *>(Bp);
+    // stage element u = (kb - kc) NT 64 + t 64 + lane of reduction block kb
+    // comes from packed fragment (kb NTA + split NT + t) 64 + lane
+    auto wsel = [&](int kc, int u) -> size_t {
+        if constexpr (NS == 1) {
+            return (size_t)kc * NT * 64 + u;
+        } else {
+            const int kr = u / (NT * 64), rem = u - kr * (NT * 64);
+            return ((size_t)(kc + kr) * NTA + split * NT) * 64 + rem;
+        }
+    };
     {
         constexpr int n0 = (KBC < KB ? KBC : KB) * NT * 64;
-        for (int u = threadIdx.x; u < n0; u += 256) tb0[u] = wsrc[u];
+        for (int u = threadIdx.x; u < n0; u += 256) tb0[u] = wsrc[wsel(0, u)];
     }
     __syncthreads();  // input tile and the first weight stage
     // stage j + 1 is loaded into registers while stage j is computed, then
@@ -312,7 +329,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ src1, 
 #pragma unroll
             for (int f = 0; f < FR; ++f) {
                 const int u = threadIdx.x + f * 256;
-                if (u < n1) nxt[f] = wsrc[(size_t)(kc + KBC) * NT * 64 + u];
+                if (u < n1) nxt[f] = wsrc[wsel(kc + KBC, u)];
             }
         }
         const bf8 *tb = (j & 1) ? tb1 : tb0;
@@ -350,14 +367,14 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ src1, 
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bv[t][i] = bias[t * 16 + 4 * g + i];
+        for (int i = 0; i < 4; ++i) bv[t][i] = bias[c0 + t * 16 + 4 * g + i];
     const bool full = y0 + TY <= H && x0 + TX <= W;  // no pixel of the tile outside the image
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int p = (wave * MT + mt) * 16 + (lane & 15);
         const int py = p / TX, px = p % TX;
         if (full || (y0 + py < H && x0 + px < W)) {
-            bf16 *o = out + (img + (int64_t)(y0 + py) * W + (x0 + px)) * N + 4 * g;
+            bf16 *o = out + (img + (int64_t)(y0 + py) * W + (x0 + px)) * N + c0 + 4 * g;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 bf4 r;
@@ -1256,14 +1273,28 @@ bool conv_tile_fits(int TY, int TX, const Layer &l) {
     return c >= 8 && c <= 128 && (c & (c - 1)) == 0 && conv_lds(TY, TX, c, l.KBf, l.NTf) <= 65536;
 }
 
+// Tiles of fewer workgroups than twice the CU count (the coarsest level at
+// batch 1: 256 tiles of 64 pixels) split their output channels over two
+// workgroups when each keeps at least four column tiles: twice the
+// workgroups, each with half the weight stages.
 template <int TY, int TX, int NT, int CIN>
 int launch_conv3x3(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B,
                    hipStream_t st) {
     const int H = N.H >> l.lvl, W = N.W >> l.lvl;
     const int tiles_x = (W + TX - 1) / TX, tiles_y = (H + TY - 1) / TY;
+    const int64_t tiles = (int64_t)B * tiles_x * tiles_y;
+    if constexpr (NT >= 8) {
+        if (tiles < 2 * device_cu_count()) {
+            const size_t lds = conv_lds(TY, TX, CIN, l.KBf, NT / 2);
+            k_conv3x3<TY, TX, NT, CIN, 2><<<(unsigned)(2 * tiles), 256, lds, st>>>(
+                s1.a, s2 ? s2->a : nullptr, l.C1, H, W, tiles_x, tiles_y, l.Bf, N.w + l.boff, y.a);
+            FEM_HIP_CHECK(hipGetLastError());
+            return 0;
+        }
+    }
     const size_t lds = conv_lds(TY, TX, CIN, l.KBf, NT);
-    k_conv3x3<TY, TX, NT, CIN><<<B * tiles_x * tiles_y, 256, lds, st>>>(s1.a, s2 ? s2->a : nullptr, l.C1, H, W,
-                                                                         tiles_x, tiles_y, l.Bf, N.w + l.boff, y.a);
+    k_conv3x3<TY, TX, NT, CIN><<<(unsigned)tiles, 256, lds, st>>>(s1.a, s2 ? s2->a : nullptr, l.C1, H, W, tiles_x,
+                                                                   tiles_y, l.Bf, N.w + l.boff, y.a);
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
