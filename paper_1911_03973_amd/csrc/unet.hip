@@ -805,6 +805,72 @@ __global__ void k_out_fwd(const bf16 *__restrict__ d0, const float *__restrict__
     }
 }
 
+// The 1x1 output layer and PASSES output smoothing passes in one launch: a
+// workgroup owns a kHeadY x kHeadX tile of one image, evaluates the layer on
+// the tile and a halo of PASSES pixels into LDS, runs the passes there (each
+// on a region one pixel narrower per side) and stores the tile.  Every value
+// is formed by the same expressions in the same order as in k_out_fwd
+// followed by PASSES launches of k_binom, which it replaces.
+constexpr int kHeadY = 16, kHeadX = 64;
+template <int PASSES>
+__global__ __launch_bounds__(256) void k_out_head(const bf16 *__restrict__ d0, const float *__restrict__ w,
+                                                  const float *__restrict__ bias, int C, int H, int W, int tiles_x,
+                                                  int tiles_y, float *__restrict__ out) {
+    constexpr int RY = kHeadY + 2 * PASSES, RX = kHeadX + 2 * PASSES;
+    __shared__ float buf[2][RY * RX];
+    const int tile = blockIdx.x;
+    const int tx = tile % tiles_x, t2 = tile / tiles_x, ty = t2 % tiles_y, b = t2 / tiles_y;
+    const int gy0 = ty * kHeadY - PASSES, gx0 = tx * kHeadX - PASSES;  // image position of region pixel (0, 0)
+    const int64_t img = (int64_t)b * H * W;
+    for (int i = threadIdx.x; i < RY * RX; i += 256) {
+        const int gy = gy0 + i / RX, gx = gx0 + i % RX;
+        float s = 0.f;
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+            const int64_t p = img + (int64_t)gy * W + gx;
+            s = bias[0];
+            for (int c = 0; c < C; c += 8) {
+                const bf8 v = ld8(d0 + p * C + c);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) s += (float)v[j] * w[c + j];
+            }
+        }
+        buf[0][i] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PASSES; ++k) {
+        const float *src = buf[k & 1];
+        float *dst = buf[(k + 1) & 1];
+        const int m = k + 1;  // this pass fills the region at margin m
+        for (int i = threadIdx.x; i < RY * RX; i += 256) {
+            const int ry = i / RX, rx = i % RX;
+            if (ry < m || ry >= RY - m || rx < m || rx >= RX - m) continue;
+            const int gy = gy0 + ry, gx = gx0 + rx;
+            if (gy < 0 || gx < 0 || gy >= H - 1 || gx >= W - 1) {
+                dst[i] = 0.f;
+                continue;
+            }
+            float s = 0.f;
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int yy = gy + dy;
+                if (yy < 0 || yy >= H - 1) continue;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int xx = gx + dx;
+                    if (xx < 0 || xx >= W - 1) continue;
+                    s += (float)((dy == 0 ? 2 : 1) * (dx == 0 ? 2 : 1)) * src[(ry + dy) * RX + rx + dx];
+                }
+            }
+            dst[i] = s * (1.f / 16.f);
+        }
+        __syncthreads();
+    }
+    const float *res = buf[PASSES & 1];
+    for (int i = threadIdx.x; i < kHeadY * kHeadX; i += 256) {
+        const int gy = ty * kHeadY + i / kHeadX, gx = tx * kHeadX + i % kHeadX;
+        if (gy < H && gx < W) out[img + (int64_t)gy * W + gx] = res[(i / kHeadX + PASSES) * RX + i % kHeadX + PASSES];
+    }
+}
+
 // per (slice, sample): sums of t^2 and (y - t)^2 -> part[b][slice][2]
 __global__ __launch_bounds__(256) void k_loss_part(const float *__restrict__ y, const float *__restrict__ t,
                                                    int64_t HW, int slices, double *__restrict__ part) {
@@ -1468,6 +1534,18 @@ int forward(UNet &N, int B, const float *in, hipStream_t st) {
     ok(conv_fwd(N, L[15], N.u0, &N.e0, N.d0a, B, st));
     ok(conv_fwd(N, L[16], N.d0a, nullptr, N.d0, B, st));
     if (rc) return rc;
+    if (N.out_smooth >= 1 && N.out_smooth <= 3) {
+        const int tx = (N.W + kHeadX - 1) / kHeadX, ty = (N.H + kHeadY - 1) / kHeadY;
+        const unsigned g = (unsigned)((int64_t)B * tx * ty);
+        const float *wo = N.w + N.out_woff, *bo = N.w + N.out_boff;
+        switch (N.out_smooth) {
+            case 1: k_out_head<1><<<g, 256, 0, st>>>(N.d0.a, wo, bo, N.c, N.H, N.W, tx, ty, N.out); break;
+            case 2: k_out_head<2><<<g, 256, 0, st>>>(N.d0.a, wo, bo, N.c, N.H, N.W, tx, ty, N.out); break;
+            default: k_out_head<3><<<g, 256, 0, st>>>(N.d0.a, wo, bo, N.c, N.H, N.W, tx, ty, N.out); break;
+        }
+        FEM_HIP_CHECK(hipGetLastError());
+        return 0;
+    }
     // with k smoothing passes the 1x1 layer writes where k alternating passes end in N.out
     float *a = (N.out_smooth & 1) ? N.ys : N.out;
     k_out_fwd<<<grid1(P0), 256, 0, st>>>(N.d0.a, N.w + N.out_woff, N.w + N.out_boff, N.c, P0, a);

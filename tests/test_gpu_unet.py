@@ -251,6 +251,24 @@ def test_smoothed_forward_matches_oracle(H, W, B):
     assert _rel(y0.cpu().numpy(), U.forward(_bf16_params(net), inp.astype(np.float64), 16)) < FWD_TOL
 
 
+@pytest.mark.parametrize("passes", [1, 2, 3, 4])
+def test_output_smoothing_is_the_filter_of_the_plain_output(passes):
+    """The smoothed output equals the oracle's output filter applied to the
+    same network's plain FP32 output, up to FP32 rounding (1-3 passes run
+    fused with the output layer, more as separate passes; 48 x 80 leaves
+    partial tiles in both directions)."""
+    H, W, B = 48, 80, 2
+    net = fem.UNet(H, W, max_batch=B, channels=16, seed=13)
+    inp, _ = _inputs(B, H, W, 3)
+    it = torch.from_numpy(inp).cuda()
+    y0 = net.forward(it).double().cpu().numpy()
+    net.set_output_smoothing(passes)
+    y = net.forward(it).double().cpu().numpy()
+    want = U.output_filter(y0, passes)
+    assert np.abs(y - want).max() <= 1e-6 * np.abs(want).max()
+    assert np.all(y[:, H - 1, :] == 0) and np.all(y[:, :, W - 1] == 0)
+
+
 def test_set_loss_rejects_invalid_arguments():
     net = fem.UNet(32, 32, max_batch=1, channels=16, seed=1)
     with pytest.raises(fem.FemError):
