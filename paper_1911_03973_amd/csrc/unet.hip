@@ -552,13 +552,13 @@ struct WGradUp {  // column n = q * Cout + co: du at the fine position q of low 
 };
 
 template <class WS, class WG, int NT>
-__global__ __launch_bounds__(256) void k_gemm_wgrad(WS ws, WG wg, int R1, int N, int64_t P,
+__global__ __launch_bounds__(256) void k_gemm_wgrad(WS ws, WG wg, int R1, int N, int64_t P, int64_t slice,
                                                     float *__restrict__ partial) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r0 = blockIdx.x * 64 + wave * 16;
     if (r0 >= R1) return;
     const int s = blockIdx.y;
-    const int64_t p0 = (int64_t)s * kWSlice, p1 = std::min<int64_t>(P, p0 + kWSlice);
+    const int64_t p0 = (int64_t)s * slice, p1 = std::min<int64_t>(P, p0 + slice);
     f4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
@@ -595,7 +595,7 @@ constexpr int kWChunk = 128;
 constexpr int kWPitch = kWChunk + 8;  // LDS row pitch in bf16 (272 bytes: 16-byte aligned rows)
 
 template <int NT>
-__global__ __launch_bounds__(256) void k_wgrad_conv(WSrcConv ws, WGradConv wg, int R1, int N, int64_t P,
+__global__ __launch_bounds__(256) void k_wgrad_conv(WSrcConv ws, WGradConv wg, int R1, int N, int64_t P, int64_t slice,
                                                     float *__restrict__ partial) {
     __shared__ __align__(16) bf16 sa[64 * kWPitch];
     __shared__ __align__(16) bf16 sg[NT * 16 * kWPitch];
@@ -603,7 +603,7 @@ __global__ __launch_bounds__(256) void k_wgrad_conv(WSrcConv ws, WGradConv wg, i
     const int rb = blockIdx.x * 64;
     const int r0 = rb + wave * 16;
     const int s = blockIdx.y;
-    const int64_t p0 = (int64_t)s * kWSlice, p1 = std::min<int64_t>(P, p0 + kWSlice);
+    const int64_t p0 = (int64_t)s * slice, p1 = std::min<int64_t>(P, p0 + slice);
     const int Cin = ws.C1 + ws.C2, H = ws.H, W = ws.W;
     f4 acc[NT];
 #pragma unroll
@@ -1292,22 +1292,38 @@ int launch_rows(const Src &s, const Epi &e, const bf16 *Bp, int64_t M, int KB, i
     return 0;
 }
 
-int64_t wgrad_splits(int64_t P) { return std::max<int64_t>(1, (P + kWSlice - 1) / kWSlice); }
+int64_t wgrad_splits(int64_t P, int64_t slice = kWSlice) { return std::max<int64_t>(1, (P + slice - 1) / slice); }
 
+// Pixels per weight-gradient slice of a GEMM with R1 rows: kWSlice, halved
+// (down to 128, a multiple of k_wgrad_conv's chunk) while the launch would
+// have fewer than kWGradTarget workgroups, so that the coarse levels, whose
+// operands are gathered with long latency chains, fill the GPU.
+constexpr int kWGradTarget = 1024;
+int64_t wgrad_slice(int64_t P, int R1) {
+    const int64_t rb = (R1 + 63) / 64;
+    int64_t s = kWSlice;
+    while (s > 128 && wgrad_splits(P, s) * rb < kWGradTarget) s /= 2;
+    return s;
+}
+
+// launches the weight-gradient GEMM; *splits receives its slice count
 template <class WS, class WG>
-int launch_wgrad(UNet &N, const WS &ws, const WG &wg, int R1, int Nc, int64_t P, hipStream_t st) {
-    const int64_t splits = wgrad_splits(P);
+int launch_wgrad(UNet &N, const WS &ws, const WG &wg, int R1, int Nc, int64_t P, int64_t *splits_out,
+                 hipStream_t st) {
+    const int64_t slice = wgrad_slice(P, R1);
+    const int64_t splits = wgrad_splits(P, slice);
     if (splits * R1 * Nc > N.partial_cap || splits > 65535)
         return set_error(FEM_EINVAL, "weight-gradient scratch too small");
+    *splits_out = splits;
     const int NT = (Nc + 15) / 16;
     dim3 grid((R1 + 63) / 64, (unsigned)splits);
     switch (NT) {
-        case 1: k_gemm_wgrad<WS, WG, 1><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, N.partial); break;
-        case 2: k_gemm_wgrad<WS, WG, 2><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, N.partial); break;
-        case 4: k_gemm_wgrad<WS, WG, 4><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, N.partial); break;
-        case 8: k_gemm_wgrad<WS, WG, 8><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, N.partial); break;
-        case 16: k_gemm_wgrad<WS, WG, 16><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, N.partial); break;
-        case 32: k_gemm_wgrad<WS, WG, 32><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, N.partial); break;
+        case 1: k_gemm_wgrad<WS, WG, 1><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, slice, N.partial); break;
+        case 2: k_gemm_wgrad<WS, WG, 2><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, slice, N.partial); break;
+        case 4: k_gemm_wgrad<WS, WG, 4><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, slice, N.partial); break;
+        case 8: k_gemm_wgrad<WS, WG, 8><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, slice, N.partial); break;
+        case 16: k_gemm_wgrad<WS, WG, 16><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, slice, N.partial); break;
+        case 32: k_gemm_wgrad<WS, WG, 32><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, slice, N.partial); break;
         default: return set_error(FEM_EINVAL, "unsupported GEMM width");
     }
     FEM_HIP_CHECK(hipGetLastError());
@@ -1431,23 +1447,25 @@ int conv_bwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const 
     WSrcConv ws{s1.a, s2 ? s2->a : nullptr, l.C1, l.C2, H, W, R};
     WGradConv wg{y.g, y.a, l.Cout};
     const int NTw = l.Cout / 16;
+    int64_t splits = 0;
     if (l.C1 % 8 == 0 && l.C2 % 8 == 0 && l.Cout % 16 == 0 && (NTw == 1 || NTw == 2 || NTw == 4 || NTw == 8)) {
-        const int64_t splits = wgrad_splits(M);
+        const int64_t slice = wgrad_slice(M, R + 1);
+        splits = wgrad_splits(M, slice);
         if (splits * (R + 1) * l.Cout > N.partial_cap || splits > 65535)
             return set_error(FEM_EINVAL, "weight-gradient scratch too small");
         dim3 grid((R + 1 + 63) / 64, (unsigned)splits);
         switch (NTw) {
-            case 1: k_wgrad_conv<1><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, N.partial); break;
-            case 2: k_wgrad_conv<2><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, N.partial); break;
-            case 4: k_wgrad_conv<4><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, N.partial); break;
-            default: k_wgrad_conv<8><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, N.partial); break;
+            case 1: k_wgrad_conv<1><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, slice, N.partial); break;
+            case 2: k_wgrad_conv<2><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, slice, N.partial); break;
+            case 4: k_wgrad_conv<4><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, slice, N.partial); break;
+            default: k_wgrad_conv<8><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, slice, N.partial); break;
         }
         FEM_HIP_CHECK(hipGetLastError());
-    } else if (int rc = launch_wgrad(N, ws, wg, R + 1, l.Cout, M, st)) {
+    } else if (int rc = launch_wgrad(N, ws, wg, R + 1, l.Cout, M, &splits, st)) {
         return rc;
     }
     const int64_t n = (int64_t)(R + 1) * l.Cout;  // weights [tap][ci][co] then the bias: contiguous
-    k_sum_splits<<<grid1(n), 256, 0, st>>>(N.partial, (int)wgrad_splits(M), n, N.g + l.woff);
+    k_sum_splits<<<grid1(n), 256, 0, st>>>(N.partial, (int)splits, n, N.g + l.woff);
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
@@ -1483,9 +1501,10 @@ int up_bwd(UNet &N, const Layer &l, const Tensor &in, const Tensor &y, int B, hi
     if (int rc = launch_rows(src, epi, l.Bb, M, l.KBb, l.NTb, st)) return rc;
     WSrcUp ws{in.a, l.C1};
     WGradUp wg{y.g, l.Cout, H, W};
-    if (int rc = launch_wgrad(N, ws, wg, l.C1 + 1, 4 * l.Cout, M, st)) return rc;
+    int64_t splits = 0;
+    if (int rc = launch_wgrad(N, ws, wg, l.C1 + 1, 4 * l.Cout, M, &splits, st)) return rc;
     const int64_t n = (int64_t)l.C1 * 4 * l.Cout + l.Cout;
-    k_sum_splits_up<<<grid1(n), 256, 0, st>>>(N.partial, (int)wgrad_splits(M), l.C1, l.Cout, N.g + l.woff);
+    k_sum_splits_up<<<grid1(n), 256, 0, st>>>(N.partial, (int)splits, l.C1, l.Cout, N.g + l.woff);
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
@@ -1820,9 +1839,9 @@ int fem_unet_create(int H, int W, int max_batch, int channels, uint64_t seed, vo
     int64_t cap = fem::wgrad_splits(P0) * (c + 1);
     for (const auto &l : N.L) {
         const int64_t M = fem::pixels(N, l.lvl, B);
-        const int64_t need =
-            l.kind == CONV ? (int64_t)(9 * l.Cin() + 1) * l.Cout : (int64_t)(l.C1 + 1) * 4 * l.Cout;
-        cap = std::max(cap, fem::wgrad_splits(M) * need);
+        const int R1 = l.kind == CONV ? 9 * l.Cin() + 1 : l.C1 + 1;
+        const int64_t need = l.kind == CONV ? (int64_t)R1 * l.Cout : (int64_t)R1 * 4 * l.Cout;
+        cap = std::max(cap, fem::wgrad_splits(M, fem::wgrad_slice(M, R1)) * need);
     }
     N.partial_cap = cap;
     add((void **)&N.partial, cap * 4);
