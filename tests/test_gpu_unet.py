@@ -219,6 +219,29 @@ def test_energy_gradients_against_oracle_sanity(H, B, smooth):
     assert cos > 0.98, cos
 
 
+def test_energy_loss_zero_target_counts_one_with_zero_gradient():
+    """t = 0 (an error image of zeros) gives t.At = 0: the sample counts 1 and
+    contributes no gradient, in a batch with an ordinary sample."""
+    H = 32
+    net = fem.UNet(H, H, max_batch=2, channels=16, seed=3)
+    net.set_loss(fem.LOSS_ENERGY, 100.0)
+    inp, t = _energy_inputs(2, H, 8)
+    t[1] = 0.0
+    it, tt = torch.from_numpy(inp).cuda(), torch.from_numpy(t).cuda()
+    loss, g = net.loss_grad(it, tt)
+    y = net.forward(it).double().cpu().numpy()
+    val, _ = U.energy_loss(y, t.astype(np.float64), [15.0, 75.0])
+    assert loss.item() == pytest.approx(val, rel=1e-12)
+    one, _ = U.energy_loss(y[:1], t[:1].astype(np.float64), [15.0])
+    assert val == pytest.approx((one + 1.0) / 2, rel=1e-12)
+    # the gradient is half the one-sample gradient (mean over the batch of two)
+    net1 = fem.UNet(H, H, max_batch=2, channels=16, seed=3)
+    net1.set_loss(fem.LOSS_ENERGY, 100.0)
+    _, g1 = net1.loss_grad(it[:1].contiguous(), tt[:1].contiguous())
+    assert torch.allclose(g, 0.5 * g1, rtol=1e-5, atol=1e-7 * float(g1.abs().max()))
+    assert torch.isfinite(g).all()
+
+
 def test_energy_training_reduces_loss():
     H = 64
     net = fem.UNet(H, H, max_batch=2, channels=16, seed=9)
