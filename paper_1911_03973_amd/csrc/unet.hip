@@ -712,27 +712,55 @@ __device__ __forceinline__ float ordered_sum(const float *__restrict__ x, int sp
     return v;
 }
 
-// out[i] = sum_s partial[s][i], s in order
+// Split sums with eight lanes per output: lane j adds, in order, the splits
+// of its contiguous eighth of [0, splits), and the eight sums are combined by
+// a fixed xor butterfly (commutative additions, so every lane of the group
+// ends with the same value): the order is fixed for a given split count.
+// Launch with kSumLanes threads per output (blockDim a multiple of 8).
+constexpr int kSumLanes = 8;
+__device__ __forceinline__ float lane_group_sum(float v) {
+    v += __shfl_xor(v, 4, kSumLanes);
+    v += __shfl_xor(v, 2, kSumLanes);
+    v += __shfl_xor(v, 1, kSumLanes);
+    return v;
+}
+
+// out[i] = sum_s partial[s][i]
 __global__ void k_sum_splits(const float *__restrict__ partial, int splits, int64_t n, float *__restrict__ out) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = ordered_sum(partial + i, splits, n);
+    const int j = threadIdx.x % kSumLanes;
+    const int chunk = (splits + kSumLanes - 1) / kSumLanes;
+    const int s0 = std::min(splits, j * chunk), s1 = std::min(splits, s0 + chunk);
+    // the eight lanes of a group share i, so they run the same loop trips
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSumLanes; i < n;
+         i += (int64_t)gridDim.x * blockDim.x / kSumLanes) {
+        const float v = lane_group_sum(ordered_sum(partial + (int64_t)s0 * n + i, s1 - s0, n));
+        if (j == 0) out[i] = v;
+    }
 }
 
 // up-conv: rows [0, Cin) of partial[s][Cin+1][4 Cout] are the weights; the
 // bias row is summed over the 4 positions into out[Cin*4Cout + co]
+// The same for the up-convolutions (the bias entries: the lane's splits for
+// each of the four positions q in turn).
 __global__ void k_sum_splits_up(const float *__restrict__ partial, int splits, int Cin, int Cout,
                                 float *__restrict__ out) {
     const int64_t nw = (int64_t)Cin * 4 * Cout, n = nw + Cout, per = nw + 4 * Cout;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int j = threadIdx.x % kSumLanes;
+    const int chunk = (splits + kSumLanes - 1) / kSumLanes;
+    const int s0 = std::min(splits, j * chunk), s1 = std::min(splits, s0 + chunk);
+    // every lane of a group runs the same number of loop trips (n is the same
+    // for all of them), so the shuffles see all eight lanes
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kSumLanes; i < n;
+         i += (int64_t)gridDim.x * blockDim.x / kSumLanes) {
         float v = 0.f;
         if (i < nw) {
-            v = ordered_sum(partial + i, splits, per);
+            v = ordered_sum(partial + (int64_t)s0 * per + i, s1 - s0, per);
         } else {
             const int co = (int)(i - nw);
-            for (int s = 0; s < splits; ++s)
-                for (int q = 0; q < 4; ++q) v += partial[(int64_t)s * per + nw + q * Cout + co];
+            for (int q = 0; q < 4; ++q) v += ordered_sum(partial + (int64_t)s0 * per + nw + q * Cout + co, s1 - s0, per);
         }
-        out[i] = v;
+        v = lane_group_sum(v);
+        if (j == 0) out[i] = v;
     }
 }
 
@@ -1465,7 +1493,7 @@ int conv_bwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const 
         return rc;
     }
     const int64_t n = (int64_t)(R + 1) * l.Cout;  // weights [tap][ci][co] then the bias: contiguous
-    k_sum_splits<<<grid1(n), 256, 0, st>>>(N.partial, (int)splits, n, N.g + l.woff);
+    k_sum_splits<<<grid1(n * kSumLanes), 256, 0, st>>>(N.partial, (int)splits, n, N.g + l.woff);
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
@@ -1504,7 +1532,7 @@ int up_bwd(UNet &N, const Layer &l, const Tensor &in, const Tensor &y, int B, hi
     int64_t splits = 0;
     if (int rc = launch_wgrad(N, ws, wg, l.C1 + 1, 4 * l.Cout, M, &splits, st)) return rc;
     const int64_t n = (int64_t)l.C1 * 4 * l.Cout + l.Cout;
-    k_sum_splits_up<<<grid1(n), 256, 0, st>>>(N.partial, (int)splits, l.C1, l.Cout, N.g + l.woff);
+    k_sum_splits_up<<<grid1(n * kSumLanes), 256, 0, st>>>(N.partial, (int)splits, l.C1, l.Cout, N.g + l.woff);
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
