@@ -551,13 +551,35 @@ struct WGradUp {  // column n = q * Cout + co: du at the fine position q of low 
     }
 };
 
+// XCD-aware decomposition of a weight-gradient grid into (row block, slice).
+// Workgroups are dealt to the kXcds XCDs in turn, so block b runs on XCD
+// b % kXcds; the row blocks of one slice get ids that share b % kXcds and
+// follow each other on that XCD (k = b / kXcds runs over the row blocks
+// first), so that the slice's output-gradient and input tiles, which every
+// row block reads, come through that XCD's L2 instead of from HBM once per
+// row block.  The grid has nrb * ceil(splits / kXcds) * kXcds blocks; those
+// past the last slice return at once.
+constexpr int kXcds = 8;
+struct WTile {
+    int rb, s;
+};
+__device__ __forceinline__ WTile wgrad_tile(int nrb) {
+    const int b = blockIdx.x, x = b % kXcds, k = b / kXcds;
+    return {k % nrb, (k / nrb) * kXcds + x};
+}
+inline unsigned wgrad_grid(int nrb, int64_t splits) {
+    return (unsigned)((int64_t)nrb * ((splits + kXcds - 1) / kXcds) * kXcds);
+}
+
 template <class WS, class WG, int NT>
 __global__ __launch_bounds__(256) void k_gemm_wgrad(WS ws, WG wg, int R1, int N, int64_t P, int64_t slice,
                                                     float *__restrict__ partial) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r0 = blockIdx.x * 64 + wave * 16;
+    const WTile tl = wgrad_tile((R1 + 63) / 64);
+    if ((int64_t)tl.s * slice >= P) return;
+    const int r0 = tl.rb * 64 + wave * 16;
     if (r0 >= R1) return;
-    const int s = blockIdx.y;
+    const int s = tl.s;
     const int64_t p0 = (int64_t)s * slice, p1 = std::min<int64_t>(P, p0 + slice);
     f4 acc[NT];
 #pragma unroll
@@ -600,9 +622,11 @@ __global__ __launch_bounds__(256) void k_wgrad_conv(WSrcConv ws, WGradConv wg, i
     __shared__ __align__(16) bf16 sa[64 * kWPitch];
     __shared__ __align__(16) bf16 sg[NT * 16 * kWPitch];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int rb = blockIdx.x * 64;
+    const WTile tl = wgrad_tile((R1 + 63) / 64);
+    if ((int64_t)tl.s * slice >= P) return;  // uniform: before any barrier
+    const int rb = tl.rb * 64;
     const int r0 = rb + wave * 16;
-    const int s = blockIdx.y;
+    const int s = tl.s;
     const int64_t p0 = (int64_t)s * slice, p1 = std::min<int64_t>(P, p0 + slice);
     const int Cin = ws.C1 + ws.C2, H = ws.H, W = ws.W;
     f4 acc[NT];
@@ -1344,7 +1368,7 @@ int launch_wgrad(UNet &N, const WS &ws, const WG &wg, int R1, int Nc, int64_t P,
         return set_error(FEM_EINVAL, "weight-gradient scratch too small");
     *splits_out = splits;
     const int NT = (Nc + 15) / 16;
-    dim3 grid((R1 + 63) / 64, (unsigned)splits);
+    const unsigned grid = wgrad_grid((R1 + 63) / 64, splits);
     switch (NT) {
         case 1: k_gemm_wgrad<WS, WG, 1><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, slice, N.partial); break;
         case 2: k_gemm_wgrad<WS, WG, 2><<<grid, 256, 0, st>>>(ws, wg, R1, Nc, P, slice, N.partial); break;
@@ -1481,7 +1505,7 @@ int conv_bwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const 
         splits = wgrad_splits(M, slice);
         if (splits * (R + 1) * l.Cout > N.partial_cap || splits > 65535)
             return set_error(FEM_EINVAL, "weight-gradient scratch too small");
-        dim3 grid((R + 1 + 63) / 64, (unsigned)splits);
+        const unsigned grid = wgrad_grid((R + 1 + 63) / 64, splits);
         switch (NTw) {
             case 1: k_wgrad_conv<1><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, slice, N.partial); break;
             case 2: k_wgrad_conv<2><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, slice, N.partial); break;
