@@ -127,10 +127,12 @@ struct SrcConvBwd {
         const int tap = k0 >> lcout, co = k0 & (Cout - 1);
         if (tap >= 9) return zero8();
         const int m = rw.m, x = rw.x, yq = rw.yq;
+        // tap t of the packed (flipped) weights reads pixel (y + t/3 - 1, x + t%3 - 1),
+        // the geometry of the forward convolution
         const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        const int yy = yq - dy, xx = x - dx;
+        const int yy = yq + dy, xx = x + dx;
         if (yy < 0 || yy >= H || xx < 0 || xx >= W) return zero8();
-        const int64_t off = ((int64_t)m - (int64_t)dy * W - dx) * Cout + co;
+        const int64_t off = ((int64_t)m + (int64_t)dy * W + dx) * Cout + co;
         bf8 g = ld8(gy + off);
         const bf8 v = ld8(y + off);
 #pragma unroll
@@ -250,10 +252,11 @@ __global__ __launch_bounds__(256) void k_gemm_rows(Src src, Epi epi, const bf16 
 // image are computed on zero input and not stored; reduction entries past the
 // 9 taps (padding of the last block) have zero weights and read the last
 // tap's finite inputs.
-template <int TY, int TX, int NTA, int CIN, int NS = 1>
+template <int TY, int TX, int NTA, int CIN, int NS = 1, bool BWD = false>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ src1, const bf16 *__restrict__ src2, int C1,
                                                  int H, int W, int tiles_x, int tiles_y, const bf16 *__restrict__ Bp,
-                                                 const float *__restrict__ bias, bf16 *__restrict__ out) {
+                                                 const float *__restrict__ bias, bf16 *__restrict__ out,
+                                                 bf16 *__restrict__ out2, int C1o) {
     // NS workgroups share a pixel tile, each computing NT = NTA / NS of its
     // NTA column tiles (output channels [split * 16 NT, (split + 1) * 16 NT))
     constexpr int NT = NTA / NS;
@@ -286,7 +289,15 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ src1, 
         if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W) {
             const int64_t pix = img + (int64_t)yy * W + xx;
             const int ci = cu * 8;
-            v = ci < C1 ? ld8(src1 + pix * C1 + ci) : ld8(src2 + pix * C2 + (ci - C1));
+            if constexpr (BWD) {
+                // the output gradient where the layer's ReLU passed (src2: its output)
+                v = ld8(src1 + pix * CIN + ci);
+                const bf8 a = ld8(src2 + pix * CIN + ci);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[i] = ((float)a[i] > 0.0f) ? v[i] : (bf16)0.0f;
+            } else {
+                v = ci < C1 ? ld8(src1 + pix * C1 + ci) : ld8(src2 + pix * C2 + (ci - C1));
+            }
         }
         *reinterpret_cast<bf8 *>(tin + pp * CIN + cu * 8) = v;
     }
@@ -363,27 +374,51 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ src1, 
         }
     }
     // lane: pixel (lane & 15) of row tile mt, output channels t * 16 + 4 g .. + 3
-    float bv[NT][4];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) bv[t][i] = bias[c0 + t * 16 + 4 * g + i];
     const bool full = y0 + TY <= H && x0 + TX <= W;  // no pixel of the tile outside the image
+    if constexpr (BWD) {
+        // input gradient, no bias or ReLU: channels [0, C1o) -> out (pitch C1o),
+        // the rest -> out2 (pitch N - C1o); C1o is a multiple of 16, so each
+        // column tile lies in one of them
+        const int C2o = N - C1o;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        const int p = (wave * MT + mt) * 16 + (lane & 15);
-        const int py = p / TX, px = p % TX;
-        if (full || (y0 + py < H && x0 + px < W)) {
-            bf16 *o = out + (img + (int64_t)(y0 + py) * W + (x0 + px)) * N + c0 + 4 * g;
+        for (int mt = 0; mt < MT; ++mt) {
+            const int p = (wave * MT + mt) * 16 + (lane & 15);
+            const int py = p / TX, px = p % TX;
+            if (full || (y0 + py < H && x0 + px < W)) {
+                const int64_t pix = img + (int64_t)(y0 + py) * W + (x0 + px);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                bf4 r;
+                for (int t = 0; t < NT; ++t) {
+                    const int c = c0 + t * 16 + 4 * g;
+                    bf4 r;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float v = acc[mt][t][i] + bv[t][i];
-                    r[i] = (bf16)(v > 0.0f ? v : 0.0f);
+                    for (int i = 0; i < 4; ++i) r[i] = (bf16)acc[mt][t][i];
+                    if (c < C1o) *reinterpret_cast<bf4 *>(out + pix * C1o + c) = r;
+                    else if (out2) *reinterpret_cast<bf4 *>(out2 + pix * C2o + (c - C1o)) = r;
                 }
-                *reinterpret_cast<bf4 *>(o + t * 16) = r;
+            }
+        }
+    } else {
+        float bv[NT][4];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bv[t][i] = bias[c0 + t * 16 + 4 * g + i];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int p = (wave * MT + mt) * 16 + (lane & 15);
+            const int py = p / TX, px = p % TX;
+            if (full || (y0 + py < H && x0 + px < W)) {
+                bf16 *o = out + (img + (int64_t)(y0 + py) * W + (x0 + px)) * N + c0 + 4 * g;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    bf4 r;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float v = acc[mt][t][i] + bv[t][i];
+                        r[i] = (bf16)(v > 0.0f ? v : 0.0f);
+                    }
+                    *reinterpret_cast<bf4 *>(o + t * 16) = r;
+                }
             }
         }
     }
@@ -1160,13 +1195,13 @@ struct MapConvFwd {  // k = tap*Cin + ci, n = co: W[tap][ci][co]
     int Cin, Cout;
     __device__ float operator()(int k, int n) const { return k < 9 * Cin ? w[(int64_t)k * Cout + n] : 0.f; }
 };
-struct MapConvBwd {  // k = tap*Cout + co, n = ci: W[tap][ci][co]
+struct MapConvBwd {  // k = tap*Cout + co, n = ci: W[8 - tap][ci][co] (the transposed convolution's taps)
     const float *w;
     int Cin, Cout;
     __device__ float operator()(int k, int n) const {
         const int tap = k / Cout, co = k - tap * Cout;
         if (tap >= 9 || n >= Cin) return 0.f;
-        return w[((int64_t)tap * Cin + n) * Cout + co];
+        return w[((int64_t)(8 - tap) * Cin + n) * Cout + co];
     }
 };
 struct MapUpFwd {  // k = ci, n = q*Cout + co: W[ci][q][co]
@@ -1421,14 +1456,14 @@ int launch_conv3x3(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, 
         if (tiles < 2 * device_cu_count()) {
             const size_t lds = conv_lds(TY, TX, CIN, l.KBf, NT / 2);
             k_conv3x3<TY, TX, NT, CIN, 2><<<(unsigned)(2 * tiles), 256, lds, st>>>(
-                s1.a, s2 ? s2->a : nullptr, l.C1, H, W, tiles_x, tiles_y, l.Bf, N.w + l.boff, y.a);
+                s1.a, s2 ? s2->a : nullptr, l.C1, H, W, tiles_x, tiles_y, l.Bf, N.w + l.boff, y.a, nullptr, 0);
             FEM_HIP_CHECK(hipGetLastError());
             return 0;
         }
     }
     const size_t lds = conv_lds(TY, TX, CIN, l.KBf, NT);
     k_conv3x3<TY, TX, NT, CIN><<<(unsigned)tiles, 256, lds, st>>>(s1.a, s2 ? s2->a : nullptr, l.C1, H, W, tiles_x,
-                                                                   tiles_y, l.Bf, N.w + l.boff, y.a);
+                                                                   tiles_y, l.Bf, N.w + l.boff, y.a, nullptr, 0);
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
 }
@@ -1484,6 +1519,67 @@ int conv_fwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const 
     return launch_rows(src, epi, l.Bf, pixels(N, l.lvl, B), l.KBf, l.NTf, st);
 }
 
+// Input gradient of a 3x3 convolution through the LDS-tiled kernel: the
+// convolution, with the flipped packed weights Bb, of the output gradient
+// masked by the layer's ReLU (CO = Cout staged channels, NT = Cin / 16 output
+// column tiles, split over s1.g and s2->g at C1).
+template <int TY, int TX, int NT, int CO>
+int launch_conv_bwd3x3(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B,
+                       hipStream_t st) {
+    const int H = N.H >> l.lvl, W = N.W >> l.lvl;
+    const int tiles_x = (W + TX - 1) / TX, tiles_y = (H + TY - 1) / TY;
+    const int64_t tiles = (int64_t)B * tiles_x * tiles_y;
+    const size_t lds = conv_lds(TY, TX, CO, l.KBb, NT);
+    k_conv3x3<TY, TX, NT, CO, 1, true><<<(unsigned)tiles, 256, lds, st>>>(
+        y.g, y.a, CO, H, W, tiles_x, tiles_y, l.Bb, nullptr, s1.g, s2 ? s2->g : nullptr, l.C1);
+    FEM_HIP_CHECK(hipGetLastError());
+    return 0;
+}
+
+template <int TY, int TX, int NT>
+int launch_conv_bwd_co(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B,
+                       hipStream_t st) {
+    switch (l.Cout) {
+        case 16: return launch_conv_bwd3x3<TY, TX, NT, 16>(N, l, s1, s2, y, B, st);
+        case 32: return launch_conv_bwd3x3<TY, TX, NT, 32>(N, l, s1, s2, y, B, st);
+        case 64:
+            if constexpr ((TY + 2) * (TX + 2) * 64 * 2 <= 49152) return launch_conv_bwd3x3<TY, TX, NT, 64>(N, l, s1, s2, y, B, st);
+            break;
+        case 128:
+            if constexpr ((TY + 2) * (TX + 2) * 128 * 2 <= 49152)
+                return launch_conv_bwd3x3<TY, TX, NT, 128>(N, l, s1, s2, y, B, st);
+            break;
+        default: break;
+    }
+    return 1;
+}
+
+// 1 when the tiled kernel does not apply (the row GEMM takes the layer)
+int conv_bwd_data_tiled(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B,
+                        hipStream_t st) {
+    const int Cin = l.Cin(), co = l.Cout;
+    if (Cin % 16 || l.C1 % 16 || co < 16 || co > 128 || (co & (co - 1)) || l.NTb * 16 != Cin) return 1;
+    auto fits = [&](int TY, int TX) { return conv_lds(TY, TX, co, l.KBb, l.NTb) <= 65536; };
+    if (l.lvl <= 1 && fits(8, 32)) {
+        switch (l.NTb) {
+            case 1: return launch_conv_bwd_co<8, 32, 1>(N, l, s1, s2, y, B, st);
+            case 2: return launch_conv_bwd_co<8, 32, 2>(N, l, s1, s2, y, B, st);
+            case 4: return launch_conv_bwd_co<8, 32, 4>(N, l, s1, s2, y, B, st);
+            default: break;
+        }
+    }
+    if (fits(4, 16)) {
+        switch (l.NTb) {
+            case 1: return launch_conv_bwd_co<4, 16, 1>(N, l, s1, s2, y, B, st);
+            case 2: return launch_conv_bwd_co<4, 16, 2>(N, l, s1, s2, y, B, st);
+            case 4: return launch_conv_bwd_co<4, 16, 4>(N, l, s1, s2, y, B, st);
+            case 8: return launch_conv_bwd_co<4, 16, 8>(N, l, s1, s2, y, B, st);
+            default: break;
+        }
+    }
+    return 1;
+}
+
 // conv3x3 + ReLU backward: input gradients into s1.g (and s2->g), overwritten; weight gradients
 int conv_bwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, bool input_grad, int B,
              hipStream_t st) {
@@ -1491,9 +1587,13 @@ int conv_bwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const 
     const int64_t M = pixels(N, l.lvl, B);
     if (input_grad) {
         if (l.Cout & (l.Cout - 1)) return set_error(FEM_EINVAL, "output channel count must be a power of two");
-        SrcConvBwd src{y.g, y.a, l.Cout, __builtin_ctz((unsigned)l.Cout), H, W};
-        EpiGrad epi{s1.g, s2 ? s2->g : nullptr, l.C1, l.C2};
-        if (int rc = launch_rows(src, epi, l.Bb, M, l.KBb, l.NTb, st)) return rc;
+        const int rt = conv_bwd_data_tiled(N, l, s1, s2, y, B, st);
+        if (rt < 0) return rt;
+        if (rt == 1) {
+            SrcConvBwd src{y.g, y.a, l.Cout, __builtin_ctz((unsigned)l.Cout), H, W};
+            EpiGrad epi{s1.g, s2 ? s2->g : nullptr, l.C1, l.C2};
+            if (int rc = launch_rows(src, epi, l.Bb, M, l.KBb, l.NTb, st)) return rc;
+        }
     }
     const int R = 9 * l.Cin();
     WSrcConv ws{s1.a, s2 ? s2->a : nullptr, l.C1, l.C2, H, W, R};
