@@ -651,26 +651,30 @@ __global__ __launch_bounds__(256) void k_gemm_wgrad(WS ws, WG wg, int R1, int N,
 constexpr int kWChunk = 128;
 constexpr int kWPitch = kWChunk + 8;  // LDS row pitch in bf16 (272 bytes: 16-byte aligned rows)
 
-template <int NT>
+// RT row tiles of 16 per wave: a workgroup covers 64 RT im2col rows, so the
+// masked output gradient staged per chunk serves RT times as many MFMAs.
+template <int NT, int RT = 1>
 __global__ __launch_bounds__(256) void k_wgrad_conv(WSrcConv ws, WGradConv wg, int R1, int N, int64_t P, int64_t slice,
                                                     float *__restrict__ partial) {
-    __shared__ __align__(16) bf16 sa[64 * kWPitch];
+    __shared__ __align__(16) bf16 sa[64 * RT * kWPitch];
     __shared__ __align__(16) bf16 sg[NT * 16 * kWPitch];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const WTile tl = wgrad_tile((R1 + 63) / 64);
+    const WTile tl = wgrad_tile((R1 + 64 * RT - 1) / (64 * RT));
     if ((int64_t)tl.s * slice >= P) return;  // uniform: before any barrier
-    const int rb = tl.rb * 64;
-    const int r0 = rb + wave * 16;
+    const int rb = tl.rb * 64 * RT;
+    const int r0 = rb + wave * RT * 16;  // first row of this wave's RT row tiles
     const int s = tl.s;
     const int64_t p0 = (int64_t)s * slice, p1 = std::min<int64_t>(P, p0 + slice);
     const int Cin = ws.C1 + ws.C2, H = ws.H, W = ws.W;
-    f4 acc[NT];
+    f4 acc[RT][NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[rt][t] = f4{0.f, 0.f, 0.f, 0.f};
     // A items (pixel pl, group rg of 8 rows): each thread keeps one pixel
-    // column and four row groups; their (tap, channel) splits do not depend on
+    // column and 4 RT row groups; their (tap, channel) splits do not depend on
     // the chunk and are taken once
-    constexpr int kRG = kWChunk * 8 / 256;
+    constexpr int kRG = kWChunk * 8 * RT / 256;
     static_assert(kWChunk * 8 % 256 == 0 && 256 % kWChunk == 0, "A items per thread");
     const int pl = threadIdx.x % kWChunk;
     int rdy[kRG], rdx[kRG], rci[kRG], rkind[kRG];  // kind: 0 zero row, 1 bias row, 2 data row
@@ -735,23 +739,32 @@ __global__ __launch_bounds__(256) void k_wgrad_conv(WSrcConv ws, WGradConv wg, i
             const int nks = (int)((std::min<int64_t>(p1 - cb, kWChunk) + 31) / 32);  // steps that start before p1
             for (int ks = 0; ks < nks; ++ks) {
                 const int col = ks * 32 + 8 * (lane >> 4);
-                const bf8 a = *reinterpret_cast<const bf8 *>(sa + (wave * 16 + (lane & 15)) * kWPitch + col);
+                bf8 bv[NT];
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    const bf8 bv = *reinterpret_cast<const bf8 *>(sg + (t * 16 + (lane & 15)) * kWPitch + col);
-                    acc[t] = mfma(a, bv, acc[t]);
+                for (int t = 0; t < NT; ++t)
+                    bv[t] = *reinterpret_cast<const bf8 *>(sg + (t * 16 + (lane & 15)) * kWPitch + col);
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    if (r0 + rt * 16 >= R1) break;  // uniform across the wave
+                    const bf8 a =
+                        *reinterpret_cast<const bf8 *>(sa + ((wave * RT + rt) * 16 + (lane & 15)) * kWPitch + col);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) acc[rt][t] = mfma(a, bv[t], acc[rt][t]);
                 }
             }
         }
     }
-    if (r0 >= R1) return;
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int rt = 0; rt < RT; ++rt) {
+        if (r0 + rt * 16 >= R1) break;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int rr = r0 + 4 * (lane >> 4) + i, n = t * 16 + (lane & 15);
-            if (rr < R1 && n < N) partial[((int64_t)s * R1 + rr) * N + n] = acc[t][i];
-        }
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int rr = r0 + rt * 16 + 4 * (lane >> 4) + i, n = t * 16 + (lane & 15);
+                if (rr < R1 && n < N) partial[((int64_t)s * R1 + rr) * N + n] = acc[rt][t][i];
+            }
+    }
 }
 
 // sum_s x[s * stride], s = 0 .. splits-1 in order; kSumAhead loads are issued
@@ -1386,12 +1399,19 @@ int64_t wgrad_splits(int64_t P, int64_t slice = kWSlice) { return std::max<int64
 // have fewer than kWGradTarget workgroups, so that the coarse levels, whose
 // operands are gathered with long latency chains, fill the GPU.
 constexpr int kWGradTarget = 1024;
-int64_t wgrad_slice(int64_t P, int R1) {
-    const int64_t rb = (R1 + 63) / 64;
+int64_t wgrad_slice(int64_t P, int R1, int rows_per_block = 64) {
+    const int64_t rb = (R1 + rows_per_block - 1) / rows_per_block;
     int64_t s = kWSlice;
     while (s > 128 && wgrad_splits(P, s) * rb < kWGradTarget) s /= 2;
     return s;
 }
+
+// im2col rows per workgroup of k_wgrad_conv for NT output column tiles: two
+// row tiles per wave for 64 output channels (their layers have 289-1153 rows,
+// and the staged gradient serves twice the MFMAs; 52 KiB of static LDS);
+// measured slower for 16 and 32 channels (fewer rows to share it, lower
+// occupancy), and 128 channels would exceed 64 KiB
+inline int conv_wgrad_rows(int NT) { return NT == 4 ? 128 : 64; }
 
 // launches the weight-gradient GEMM; *splits receives its slice count
 template <class WS, class WG>
@@ -1601,16 +1621,17 @@ int conv_bwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const 
     const int NTw = l.Cout / 16;
     int64_t splits = 0;
     if (l.C1 % 8 == 0 && l.C2 % 8 == 0 && l.Cout % 16 == 0 && (NTw == 1 || NTw == 2 || NTw == 4 || NTw == 8)) {
-        const int64_t slice = wgrad_slice(M, R + 1);
+        const int rpb = conv_wgrad_rows(NTw);
+        const int64_t slice = wgrad_slice(M, R + 1, rpb);
         splits = wgrad_splits(M, slice);
         if (splits * (R + 1) * l.Cout > N.partial_cap || splits > 65535)
             return set_error(FEM_EINVAL, "weight-gradient scratch too small");
-        const unsigned grid = wgrad_grid((R + 1 + 63) / 64, splits);
+        const unsigned grid = wgrad_grid((R + 1 + rpb - 1) / rpb, splits);
         switch (NTw) {
-            case 1: k_wgrad_conv<1><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, slice, N.partial); break;
-            case 2: k_wgrad_conv<2><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, slice, N.partial); break;
-            case 4: k_wgrad_conv<4><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, slice, N.partial); break;
-            default: k_wgrad_conv<8><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, slice, N.partial); break;
+            case 1: k_wgrad_conv<1, 1><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, slice, N.partial); break;
+            case 2: k_wgrad_conv<2, 1><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, slice, N.partial); break;
+            case 4: k_wgrad_conv<4, 2><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, slice, N.partial); break;
+            default: k_wgrad_conv<8, 1><<<grid, 256, 0, st>>>(ws, wg, R + 1, l.Cout, M, slice, N.partial); break;
         }
         FEM_HIP_CHECK(hipGetLastError());
     } else if (int rc = launch_wgrad(N, ws, wg, R + 1, l.Cout, M, &splits, st)) {
@@ -1993,6 +2014,9 @@ int fem_unet_create(int H, int W, int max_batch, int channels, uint64_t seed, vo
         const int64_t M = fem::pixels(N, l.lvl, B);
         const int R1 = l.kind == CONV ? 9 * l.Cin() + 1 : l.C1 + 1;
         const int64_t need = l.kind == CONV ? (int64_t)R1 * l.Cout : (int64_t)R1 * 4 * l.Cout;
+        const int rpb = l.kind == CONV ? fem::conv_wgrad_rows(l.Cout / 16) : 64;
+        // the row GEMM fallback of a convolution uses 64-row blocks: the larger of the two counts
+        cap = std::max(cap, fem::wgrad_splits(M, fem::wgrad_slice(M, R1, rpb)) * need);
         cap = std::max(cap, fem::wgrad_splits(M, fem::wgrad_slice(M, R1)) * need);
     }
     N.partial_cap = cap;
