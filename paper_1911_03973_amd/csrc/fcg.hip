@@ -578,9 +578,16 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
         res.status = status;
         return status;
     };
-    int launched = 0;
+    // Batches of up to check_every iterations between state reads.  Once the
+    // device has raised its flag the queued iterations' FCG kernels return at
+    // once but their cycles still run, so near the target the batch is cut to
+    // the iterations that the last batch's rate of decrease of ||r|| predicts
+    // (at least 2).  The iterates do not depend on the batch sizes: the device
+    // stops itself.
+    int launched = 0, est = check_every, m_prev = 0, it_prev = 0;
+    double rn_prev = r0;
     while (true) {
-        const int m = std::max(1, std::min(check_every, max_iter - launched));
+        const int m = std::max(1, std::min(std::min(check_every, est), max_iter - launched));
         for (int j = 0; j < m; ++j) {
             if (graph) {
                 FEM_HIP_CHECK(hipGraphLaunch(ig.exec, s));
@@ -589,7 +596,17 @@ int solve_fcg(const DevPlan &P, int dtype, const void *K, const void *M, double 
             }
         }
         launched += m;
+        m_prev = m;
         if (int rc = read_state(w, h, s)) return rc;
+        est = check_every;
+        const int done = h.iters - it_prev;
+        if (h.flag == FCG_RUN && done == m_prev && h.rn > h.target && h.rn < rn_prev && rn_prev > 0.0) {
+            const double rate = std::pow(h.rn / rn_prev, 1.0 / done);
+            const double k = std::log(h.target / h.rn) / std::log(rate);
+            if (std::isfinite(k)) est = std::max(2, (int)std::min<double>(check_every, std::ceil(k)));
+        }
+        rn_prev = h.rn;
+        it_prev = h.iters;
         if (h.flag == FCG_RUN) {
             if (launched < max_iter) continue;
             h.flag = FCG_LIMIT;
