@@ -252,7 +252,7 @@ __global__ __launch_bounds__(256) void k_gemm_rows(Src src, Epi epi, const bf16 
 // image are computed on zero input and not stored; reduction entries past the
 // 9 taps (padding of the last block) have zero weights and read the last
 // tap's finite inputs.
-template <int TY, int TX, int NTA, int CIN, int NS = 1, bool BWD = false>
+template <int TY, int TX, int NTA, int CIN, int NS = 1, bool BWD = false, bool POOL = false>
 __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ src1, const bf16 *__restrict__ src2, int C1,
                                                  int H, int W, int tiles_x, int tiles_y, const bf16 *__restrict__ Bp,
                                                  const float *__restrict__ bias, bf16 *__restrict__ out,
@@ -419,6 +419,46 @@ __global__ __launch_bounds__(256) void k_conv3x3(const bf16 *__restrict__ src1, 
                     }
                     *reinterpret_cast<bf4 *>(o + t * 16) = r;
                 }
+            }
+        }
+        if constexpr (POOL) {
+            // 2 x 2 average pooling of the tile into out2 ((H/2) x (W/2), N
+            // channels), from the same BF16 values and with the expression of
+            // k_pool_fwd: the tile's outputs go to LDS once every wave is done
+            // with the input tile
+            static_assert(NS == 1 && TY % 2 == 0 && TX % 2 == 0, "pooling needs the whole tile");
+            __syncthreads();
+            bf16 *tout = tin;  // [TY * TX][N]
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int p = (wave * MT + mt) * 16 + (lane & 15);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    bf4 r;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float v = acc[mt][t][i] + bv[t][i];
+                        r[i] = (bf16)(v > 0.0f ? v : 0.0f);
+                    }
+                    *reinterpret_cast<bf4 *>(tout + p * N + t * 16 + 4 * g) = r;
+                }
+            }
+            __syncthreads();
+            const int H2 = H / 2, W2 = W / 2;
+            constexpr int c8 = N / 8;
+            for (int i = threadIdx.x; i < (TY / 2) * (TX / 2) * c8; i += 256) {
+                const int cg = i % c8, pp = i / c8, px = pp % (TX / 2), py = pp / (TX / 2);
+                const int Y = y0 / 2 + py, X = x0 / 2 + px;
+                if (Y >= H2 || X >= W2) continue;
+                const bf16 *q = tout + ((2 * py) * TX + 2 * px) * N + cg * 8;
+                const bf8 a = *reinterpret_cast<const bf8 *>(q), bb = *reinterpret_cast<const bf8 *>(q + N),
+                          c = *reinterpret_cast<const bf8 *>(q + TX * N),
+                          d = *reinterpret_cast<const bf8 *>(q + TX * N + N);
+                bf8 r;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    r[k] = (bf16)(0.25f * (((float)a[k] + (float)bb[k]) + ((float)c[k] + (float)d[k])));
+                *reinterpret_cast<bf8 *>(out2 + (((int64_t)b * H2 + Y) * W2 + X) * N + cg * 8) = r;
             }
         }
     }
@@ -1468,10 +1508,22 @@ bool conv_tile_fits(int TY, int TX, const Layer &l) {
 // workgroups, each with half the weight stages.
 template <int TY, int TX, int NT, int CIN>
 int launch_conv3x3(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B,
-                   hipStream_t st) {
+                   hipStream_t st, const Tensor *pool = nullptr, bool *pooled = nullptr) {
     const int H = N.H >> l.lvl, W = N.W >> l.lvl;
     const int tiles_x = (W + TX - 1) / TX, tiles_y = (H + TY - 1) / TY;
     const int64_t tiles = (int64_t)B * tiles_x * tiles_y;
+    // with a pooled output: the pooling in the epilogue when the tile's outputs
+    // fit where its input was staged
+    if constexpr (TY % 2 == 0 && TX % 2 == 0 && NT <= 4) {
+        if (pool && pooled && conv_tile_bytes(TY, TX, CIN) >= (size_t)TY * TX * NT * 16 * 2) {
+            const size_t lds = conv_lds(TY, TX, CIN, l.KBf, NT);
+            k_conv3x3<TY, TX, NT, CIN, 1, false, true><<<(unsigned)tiles, 256, lds, st>>>(
+                s1.a, s2 ? s2->a : nullptr, l.C1, H, W, tiles_x, tiles_y, l.Bf, N.w + l.boff, y.a, pool->a, 0);
+            FEM_HIP_CHECK(hipGetLastError());
+            *pooled = true;
+            return 0;
+        }
+    }
     if constexpr (NT >= 8) {
         if (tiles < 2 * device_cu_count()) {
             const size_t lds = conv_lds(TY, TX, CIN, l.KBf, NT / 2);
@@ -1491,16 +1543,18 @@ int launch_conv3x3(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, 
 // CIN of the layer as a template constant (conv_tile_fits has checked it)
 template <int TY, int TX, int NT>
 int launch_conv_cin(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B,
-                    hipStream_t st) {
+                    hipStream_t st, const Tensor *pool = nullptr, bool *pooled = nullptr) {
     switch (l.Cin()) {
-        case 8: return launch_conv3x3<TY, TX, NT, 8>(N, l, s1, s2, y, B, st);
-        case 16: return launch_conv3x3<TY, TX, NT, 16>(N, l, s1, s2, y, B, st);
-        case 32: return launch_conv3x3<TY, TX, NT, 32>(N, l, s1, s2, y, B, st);
+        case 8: return launch_conv3x3<TY, TX, NT, 8>(N, l, s1, s2, y, B, st, pool, pooled);
+        case 16: return launch_conv3x3<TY, TX, NT, 16>(N, l, s1, s2, y, B, st, pool, pooled);
+        case 32: return launch_conv3x3<TY, TX, NT, 32>(N, l, s1, s2, y, B, st, pool, pooled);
         case 64:
-            if constexpr ((TY + 2) * (TX + 2) * 64 * 2 <= 49152) return launch_conv3x3<TY, TX, NT, 64>(N, l, s1, s2, y, B, st);
+            if constexpr ((TY + 2) * (TX + 2) * 64 * 2 <= 49152)
+                return launch_conv3x3<TY, TX, NT, 64>(N, l, s1, s2, y, B, st, pool, pooled);
             break;
         case 128:
-            if constexpr ((TY + 2) * (TX + 2) * 128 * 2 <= 49152) return launch_conv3x3<TY, TX, NT, 128>(N, l, s1, s2, y, B, st);
+            if constexpr ((TY + 2) * (TX + 2) * 128 * 2 <= 49152)
+                return launch_conv3x3<TY, TX, NT, 128>(N, l, s1, s2, y, B, st, pool, pooled);
             break;
         default: break;
     }
@@ -1511,24 +1565,28 @@ int launch_conv_cin(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2,
 // fine levels (16 x 32 for 32 output channels), 4 x 16 on the coarse ones,
 // each where its input tile fits the LDS budget; otherwise the row GEMM
 // reading the input directly
-int conv_fwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B, hipStream_t st) {
+// (pool, pooled: when the tiled kernel runs with the layer's 2 x 2 average
+// pooling into pool in its epilogue, *pooled is set)
+int conv_fwd(UNet &N, const Layer &l, const Tensor &s1, const Tensor *s2, const Tensor &y, int B, hipStream_t st,
+             const Tensor *pool = nullptr, bool *pooled = nullptr) {
     // 32 output channels: 16 x 32 tiles (8 row tiles per wave) where the input
     // tile fits (measured 41.6 us against 49.6 us for 8 x 32 at 512^2; with 16
     // output channels the taller tile was slower, 81 against 70 us at 1024^2)
-    if (l.lvl <= 1 && l.NTf == 2 && conv_tile_fits(16, 32, l)) return launch_conv_cin<16, 32, 2>(N, l, s1, s2, y, B, st);
+    if (l.lvl <= 1 && l.NTf == 2 && conv_tile_fits(16, 32, l))
+        return launch_conv_cin<16, 32, 2>(N, l, s1, s2, y, B, st, pool, pooled);
     if (l.lvl <= 1 && conv_tile_fits(8, 32, l)) {
         switch (l.NTf) {
-            case 1: return launch_conv_cin<8, 32, 1>(N, l, s1, s2, y, B, st);
-            case 2: return launch_conv_cin<8, 32, 2>(N, l, s1, s2, y, B, st);
-            case 4: return launch_conv_cin<8, 32, 4>(N, l, s1, s2, y, B, st);
+            case 1: return launch_conv_cin<8, 32, 1>(N, l, s1, s2, y, B, st, pool, pooled);
+            case 2: return launch_conv_cin<8, 32, 2>(N, l, s1, s2, y, B, st, pool, pooled);
+            case 4: return launch_conv_cin<8, 32, 4>(N, l, s1, s2, y, B, st, pool, pooled);
             default: break;
         }
     }
     if (conv_tile_fits(4, 16, l)) {
         switch (l.NTf) {
-            case 1: return launch_conv_cin<4, 16, 1>(N, l, s1, s2, y, B, st);
-            case 2: return launch_conv_cin<4, 16, 2>(N, l, s1, s2, y, B, st);
-            case 4: return launch_conv_cin<4, 16, 4>(N, l, s1, s2, y, B, st);
+            case 1: return launch_conv_cin<4, 16, 1>(N, l, s1, s2, y, B, st, pool, pooled);
+            case 2: return launch_conv_cin<4, 16, 2>(N, l, s1, s2, y, B, st, pool, pooled);
+            case 4: return launch_conv_cin<4, 16, 4>(N, l, s1, s2, y, B, st, pool, pooled);
             case 8: return launch_conv_cin<4, 16, 8>(N, l, s1, s2, y, B, st);
             case 16: return launch_conv_cin<4, 16, 16>(N, l, s1, s2, y, B, st);
             default: break;
@@ -1706,14 +1764,17 @@ int forward(UNet &N, int B, const float *in, hipStream_t st) {
         if (!rc) rc = r;
     };
     ok(conv_fwd(N, L[0], N.x8, nullptr, N.e0a, B, st));
-    ok(conv_fwd(N, L[1], N.e0a, nullptr, N.e0, B, st));
-    ok(pool(N, N.e0, N.p0, B, st));
+    bool pooled = false;
+    ok(conv_fwd(N, L[1], N.e0a, nullptr, N.e0, B, st, &N.p0, &pooled));
+    if (!pooled) ok(pool(N, N.e0, N.p0, B, st));
     ok(conv_fwd(N, L[2], N.p0, nullptr, N.e1a, B, st));
-    ok(conv_fwd(N, L[3], N.e1a, nullptr, N.e1, B, st));
-    ok(pool(N, N.e1, N.p1, B, st));
+    pooled = false;
+    ok(conv_fwd(N, L[3], N.e1a, nullptr, N.e1, B, st, &N.p1, &pooled));
+    if (!pooled) ok(pool(N, N.e1, N.p1, B, st));
     ok(conv_fwd(N, L[4], N.p1, nullptr, N.e2a, B, st));
-    ok(conv_fwd(N, L[5], N.e2a, nullptr, N.e2, B, st));
-    ok(pool(N, N.e2, N.p2, B, st));
+    pooled = false;
+    ok(conv_fwd(N, L[5], N.e2a, nullptr, N.e2, B, st, &N.p2, &pooled));
+    if (!pooled) ok(pool(N, N.e2, N.p2, B, st));
     ok(conv_fwd(N, L[6], N.p2, nullptr, N.ma, B, st));
     ok(conv_fwd(N, L[7], N.ma, nullptr, N.mm, B, st));
     ok(up_fwd(N, L[8], N.mm, N.u2, B, st));
