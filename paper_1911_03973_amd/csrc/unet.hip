@@ -1328,6 +1328,33 @@ __global__ void k_grid_in(const double *__restrict__ r, const double *__restrict
         in2[2 * p + 1] = cval;
     }
 }
+// FP32 -> BF16 rounding to nearest even, written on the bits: the conversion
+// the (bf16) cast performs on finite values, but as integer operations on the
+// stored FP32 value, so that it cannot be merged with a preceding FP64 -> FP32
+// rounding (one rounding from FP64 can differ from the two).  NaN: the cast.
+__device__ __forceinline__ bf16 bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16)f;
+    const uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+    return __builtin_bit_cast(bf16, (uint16_t)(r >> 16));
+}
+// k_grid_in and k_make_input in one pass: the network's BF16 input (8
+// channels, 2 used) of the scaled interior residual, the values k_make_input
+// forms from k_grid_in's FP32 image
+__global__ void k_grid_in8(const double *__restrict__ r, const double *__restrict__ inv_p, int N, float cval,
+                           bf16 *__restrict__ x8) {
+    const double inv = inv_p[0];
+    const int64_t P = (int64_t)N * N;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(p % N), y = (int)(p / N);
+        float v = 0.f;
+        if (x < N - 1 && y < N - 1) v = (float)(r[(int64_t)(y + 1) * (N + 1) + (x + 1)] * inv);
+        bf8 o = zero8();
+        o[0] = bf16_rne(v);
+        o[1] = bf16_rne(cval);
+        *reinterpret_cast<bf8 *>(x8 + p * 8) = o;
+    }
+}
 // e = u - x on the interior: per-block sums of squares
 __global__ __launch_bounds__(256) void k_interior_sumsq_diff(const double *__restrict__ u, const double *__restrict__ x,
                                                              int N, double *__restrict__ part) {
@@ -1401,7 +1428,7 @@ struct UNet {
     void *arena = nullptr;
     float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
     Tensor x8, e0a, e0, p0, e1a, e1, p1, e2a, e2, p2, ma, mm, u2, d2a, d2, u1, d1a, d1, u0, d0a, d0;
-    float *out = nullptr, *gy = nullptr, *in2 = nullptr, *partial = nullptr;
+    float *out = nullptr, *gy = nullptr, *partial = nullptr;
     double *sums = nullptr, *lpart = nullptr, *gpart = nullptr;
     int64_t partial_cap = 0;
     int loss_slices = 64;
@@ -1755,9 +1782,9 @@ int pool_bwd(const UNet &N, const Tensor &in, const Tensor &out, int B, hipStrea
 }
 
 // forward of input [B][H][W][2] (FP32) into N.out [B][H][W]
-int forward(UNet &N, int B, const float *in, hipStream_t st) {
+// forward from the BF16 input already in N.x8
+int forward_x8(UNet &N, int B, hipStream_t st) {
     const int64_t P0 = pixels(N, 0, B);
-    k_make_input<<<grid1(P0), 256, 0, st>>>(in, N.x8.a, P0);
     const auto &L = N.L;
     int rc = 0;
     auto ok = [&](int r) {
@@ -1809,6 +1836,13 @@ int forward(UNet &N, int B, const float *in, hipStream_t st) {
     }
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
+}
+
+int forward(UNet &N, int B, const float *in, hipStream_t st) {
+    const int64_t P0 = pixels(N, 0, B);
+    k_make_input<<<grid1(P0), 256, 0, st>>>(in, N.x8.a, P0);
+    FEM_HIP_CHECK(hipGetLastError());
+    return forward_x8(N, B, st);
 }
 
 // loss and every parameter gradient (into N.g) for the forward of `in` held in N.out
@@ -1950,9 +1984,10 @@ int unet_grid_precondition(fem_unet *net, int grid_n, const double *r, double cv
     const int parts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n_int + 255) / 256));
     k_interior_sumsq<<<parts, 256, 0, st>>>(r, grid_n, N.gpart);
     k_grid_scale<<<1, 256, 0, st>>>(N.gpart, parts, grid_n, N.gpart + kGridScale);
-    k_grid_in<<<grid1((int64_t)grid_n * grid_n), 256, 0, st>>>(r, N.gpart + kGridScale, grid_n, (float)cval, N.in2);
+    k_grid_in8<<<grid1((int64_t)grid_n * grid_n), 256, 0, st>>>(r, N.gpart + kGridScale, grid_n, (float)cval,
+                                                                 N.x8.a);
     FEM_HIP_CHECK(hipGetLastError());
-    if (int rc = forward(N, 1, N.in2, st)) return rc;
+    if (int rc = forward_x8(N, 1, st)) return rc;
     k_grid_out<<<grid1((int64_t)(grid_n + 1) * (grid_n + 1)), 256, 0, st>>>(N.out, grid_n, mask, z);
     FEM_HIP_CHECK(hipGetLastError());
     return 0;
@@ -2069,7 +2104,6 @@ int fem_unet_create(int H, int W, int max_batch, int channels, uint64_t seed, vo
     add((void **)&N.out, P0 * 4);
     add((void **)&N.gy, P0 * 4);
     add((void **)&N.ys, P0 * 4);
-    add((void **)&N.in2, (size_t)H * W * 2 * 4);
     int64_t cap = fem::wgrad_splits(P0) * (c + 1);
     for (const auto &l : N.L) {
         const int64_t M = fem::pixels(N, l.lvl, B);
