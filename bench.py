@@ -774,7 +774,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n-problems", type=int, default=256, help="batched workload: number of problems")
     ap.add_argument("--group", type=int, default=0, help="batched: chunks per work item (0 = per-problem schedule)")
-    ap.add_argument("--items", type=int, default=16, help="batched: target work items per problem phase")
+    ap.add_argument("--items", type=int, default=4, help="batched: target work items per problem phase")
     ap.add_argument("--batch-chunk", type=int, default=2048, help="batched: elements per chunk")
     ap.add_argument("--inline-segs", type=int, default=64,
                     help="batched: fix-up segments the last chunk item of a phase runs itself")

@@ -287,7 +287,8 @@ typedef struct {
     int group;               /* chunks per work item, 0 = per-problem schedule */
     int items_per_phase;     /* per-problem schedule: target work items per
                                 phase (a problem of n chunks takes
-                                ceil(n / items_per_phase) chunks per item) */
+                                ceil(n / items_per_phase) chunks per item;
+                                default 4) */
     int inline_segments;     /* a problem with at most this many shared-node
                                 segments (1024 nodes each) has its fix-up and
                                 scalar step run by the workgroup finishing its

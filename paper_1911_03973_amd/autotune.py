@@ -60,7 +60,7 @@ def autotune_solver(mesh, dirichlet, nu, dtype=fem.F32X2, chunks=None, blocks=BL
 
 
 def autotune_batch(meshes, dirichlets, nus, b_fn, dtype=fem.F32X2, chunks=(1024, 2048), blocks=(256, 512),
-                   items=(8, 16, 32), iters=40):
+                   items=(4, 8, 16), iters=40):
     """Pick (chunk_elems, block, items_per_phase) for fem_batch_solve.
 
     b_fn(batch, K, M) -> b must return the right-hand side on the batch's node

@@ -213,7 +213,7 @@ void fem_batch_opts_default(fem_batch_opts *o) {
     o->watchdog_seconds = 30.0;
     o->use_graph = 1;
     o->group = 0;
-    o->items_per_phase = 32;
+    o->items_per_phase = 4;
     o->inline_segments = 64;
     o->adaptive = 1;
 }

@@ -138,7 +138,7 @@ def test_full_size_batch_of_256_problems():
     b = torch.empty(B.n_nodes, dtype=torch.float64, device="cuda")
     B.assemble_rhs(fem.F32X2, M, torch.from_numpy(np.concatenate(fs)).cuda(), b)
     x = torch.zeros(B.n_nodes, dtype=torch.float64, device="cuda")
-    rc, res, sec = B.solve(fem.batch_opts(rtol=1e-8, use_graph=1, watchdog_seconds=60.0, items_per_phase=16), K, M,
+    rc, res, sec = B.solve(fem.batch_opts(rtol=1e-8, use_graph=1, watchdog_seconds=60.0, items_per_phase=4), K, M,
                            nus, b, x)
     assert rc == 0
     sizes = np.array([m.n_elems for m in meshes])
