@@ -242,6 +242,78 @@ __device__ void store_dots(double (&d)[kBDots], double *red, double *dst) {
         for (int j = 0; j < kBDots; ++j) dst[j] = d[j];
 }
 
+// The element pass of chunks c_first .. c_first + n - 1 of one problem (the
+// phases of chunk_pass), each chunk's dot partials to cdots[c].  The union
+// plan of the batch has ragged chunks, so a chunk's element range is a load
+// that its matrix fetch depends on; it is requested one chunk ahead, and only
+// the first chunk of the item waits for it.
+template <int NB, int EPT, int BS, class Ld, class Op>
+__device__ __forceinline__ void batch_chunks(const DevPlan &P, const Ld &ld, Op &op, double *__restrict__ partial,
+                                             int64_t c_first, int n, double *buf, uint16_t *sl, double *red,
+                                             double *cdots) {
+    static_assert(Op::kLocal, "the batched ops address vectors in the solver-local node order");
+    int64_t e0n = 0;
+    int nen = 0;
+    if (n > 0) chunk_range(P, c_first, e0n, nen);
+    for (int i = 0; i < n; ++i) {
+        const int64_t c = c_first + i;
+        const int64_t e0 = e0n;
+        const int ne = nen;
+        typename Ld::Regs R[EPT];
+#pragma unroll
+        for (int t = 0; t < EPT; ++t) {
+            const int le = t * BS + threadIdx.x;
+            if (le < ne) ld.fetch(e0 + le, R[t]);
+        }
+        if (i + 1 < n) chunk_range(P, c + 1, e0n, nen);
+        __syncthreads();  // every thread is done with buf / sl of the previous chunk
+        const int nb0 = P.chunk_node_off[c];
+        const int nl = P.chunk_node_off[c + 1] - nb0;
+        const int ncomp = P.chunk_info[2 * c];
+        const int pbase = P.chunk_info[2 * c + 1];
+        const int coff = P.comp_off[c];
+        {
+            const uint4 *src = reinterpret_cast<const uint4 *>(P.slots + c * (int64_t)NB * P.E);
+            uint4 *dst = reinterpret_cast<uint4 *>(sl);
+            const int nv = (ne * NB + 7) >> 3;
+            for (int k = threadIdx.x; k < nv; k += BS) dst[k] = src[k];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nl; k += BS) {
+            const int g = k < ncomp ? coff + k : -1;
+            const int s0 = k ? P.loc_end[nb0 + k - 1] : 0;
+            const int s1 = P.loc_end[nb0 + k];
+            const double v = op.gather(g, k < ncomp ? -1 : P.part_owner[pbase + (k - ncomp)]);
+            for (int s = s0; s < s1; ++s) buf[sl[s]] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < EPT; ++t) {
+            const int le = t * BS + threadIdx.x;
+            if (le < ne) {
+                double xe[NB], y[NB];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) xe[j] = buf[le * NB + j];
+                Ld::apply(R[t], xe, y);
+#pragma unroll
+                for (int j = 0; j < NB; ++j) buf[le * NB + j] = y[j];
+            }
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nl; k += BS) {
+            const int s0 = k ? P.loc_end[nb0 + k - 1] : 0;
+            const int s1 = P.loc_end[nb0 + k];
+            double acc = 0.0;
+            for (int s = s0; s < s1; ++s) acc += buf[sl[s]];
+            if (k < ncomp) op.finish(coff + k, acc);
+            else partial[pbase + (k - ncomp)] = acc;
+        }
+        store_dots<BS>(op.d, red, cdots + c * kBDots);
+#pragma unroll
+        for (int t = 0; t < kBDots; ++t) op.d[t] = 0.0;
+    }
+}
+
 // ---- the persistent kernel -------------------------------------------------
 template <int NB, int EPT, int BS>
 __global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
@@ -417,28 +489,14 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
                 BOpIter op{a.x, a.r, a.p, a.q, a.dinv, a.sx, a.sr, a.sp, a.sq, a.sd, pr->mode, pr->alpha, pr->beta,
                            {0, 0, 0, 0, 0, 0, 0}};
                 LdPk<NB, MAT_F32> ld{a.A, P.n_elems};
-                const int cj1 = min(nch, (j + 1) * grp);
-                for (int cj = j * grp; cj < cj1; ++cj) {
-#pragma unroll
-                    for (int t = 0; t < kBDots; ++t) op.d[t] = 0.0;
-                    __syncthreads();
-                    chunk_pass<NB, EPT, BS, double, LdPk<NB, MAT_F32>, BOpIter, false>(P, ld, op, a.part, c0 + cj,
-                                                                                      buf, sl);
-                    store_dots<BS>(op.d, red.v, a.cdots + (int64_t)(c0 + cj) * kBDots);
-                }
+                const int cj0 = j * grp, cj1 = min(nch, (j + 1) * grp);
+                batch_chunks<NB, EPT, BS>(P, ld, op, a.part, c0 + cj0, cj1 - cj0, buf, sl, red.v, a.cdots);
             } else {
                 BOpRefresh op{a.x, a.r, a.p, a.dinv, a.b, a.sx, a.sr, a.sp, a.sd, a.sb,
                               pr->pending ? pr->alpha : 0.0, {0, 0, 0, 0, 0, 0, 0}};
                 LdPk<NB, MAT_F32X2> ld{a.A, P.n_elems};
-                const int cj1 = min(nch, (j + 1) * grp);
-                for (int cj = j * grp; cj < cj1; ++cj) {
-#pragma unroll
-                    for (int t = 0; t < kBDots; ++t) op.d[t] = 0.0;
-                    __syncthreads();
-                    chunk_pass<NB, EPT, BS, double, LdPk<NB, MAT_F32X2>, BOpRefresh, false>(P, ld, op, a.part,
-                                                                                           c0 + cj, buf, sl);
-                    store_dots<BS>(op.d, red.v, a.cdots + (int64_t)(c0 + cj) * kBDots);
-                }
+                const int cj0 = j * grp, cj1 = min(nch, (j + 1) * grp);
+                batch_chunks<NB, EPT, BS>(P, ld, op, a.part, c0 + cj0, cj1 - cj0, buf, sl, red.v, a.cdots);
             }
             if (phase_done<BS>(a, p, nci, &s_last)) {
                 // the last CHUNK item of the phase: a few fix-up segments and the
