@@ -16,7 +16,7 @@
 // problem costs one or two trips through the queue instead of three.  With
 // `adaptive`, once fewer problems are left than the grid can keep busy, a
 // problem's next phase is cut into more CHUNK items (down to one chunk each,
-// aiming at two items per workgroup over the live problems) and its fix-up
+// aiming at one item per workgroup over the live problems) and its fix-up
 // goes to FIX items instead of running inline; partials are per chunk and
 // per segment, so the grouping never changes a result.
 // Nothing ever waits for another workgroup: a workgroup only waits for the
@@ -460,10 +460,12 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
                 }
                 int items = (nch + pr->grp - 1) / pr->grp;
                 if (next != 0 && a.adaptive) {
-                    // aim at two items per workgroup over the problems still live
+                    // aim at one item per workgroup over the problems still live
+                    // (longer items cost fewer queue trips; two or four per
+                    // workgroup were measured slower)
                     const int live = max(1, a.nprob - __hip_atomic_load(a.ndone, __ATOMIC_RELAXED,
                                                                          __HIP_MEMORY_SCOPE_AGENT));
-                    const int want = (int)((2 * gridDim.x + live - 1) / live);
+                    const int want = (int)((gridDim.x + live - 1) / live);
                     const int base = (nch + a.pgroup[p] - 1) / a.pgroup[p];
                     items = min(nch, max(base, want));
                     pr->grp = (nch + items - 1) / items;
