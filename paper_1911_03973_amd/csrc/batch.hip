@@ -503,10 +503,12 @@ __global__ __launch_bounds__(BS) void k_batch(const BatchArgs a) {
             if (phase_done<BS>(a, p, nci, &s_last)) {
                 // the last CHUNK item of the phase: a few fix-up segments and the
                 // scalar step run here, so the phase costs one queue trip --
-                // unless few problems are left, when parallel FIX items are faster
+                // unless few problems are left (fewer than one per eight
+                // workgroups; one per two to one per 64 measured), when
+                // parallel FIX items are faster
                 if (threadIdx.x == 0)
                     s_few = a.adaptive && nseg > 1 &&
-                            4 * (a.nprob - __hip_atomic_load(a.ndone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) <
+                            8 * (a.nprob - __hip_atomic_load(a.ndone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) <
                                 (int)gridDim.x;
                 __syncthreads();
                 if (nseg > a.inline_segs || s_few) {
