@@ -60,12 +60,16 @@ def autotune_solver(mesh, dirichlet, nu, dtype=fem.F32X2, chunks=None, blocks=BL
 
 
 def autotune_batch(meshes, dirichlets, nus, b_fn, dtype=fem.F32X2, chunks=(1024, 2048), blocks=(256, 512),
-                   items=(4, 8, 16), iters=40):
+                   items=(4, 8, 16), iters=None, rtol=1e-8):
     """Pick (chunk_elems, block, items_per_phase) for fem_batch_solve.
 
     b_fn(batch, K, M) -> b must return the right-hand side on the batch's node
-    numbering.  Each candidate runs every problem for at most `iters` CG
-    iterations inside one persistent launch; the score is its wall time.
+    numbering.  Each candidate solves every problem to `rtol` inside one
+    persistent launch (with `iters`, at most that many CG iterations per
+    problem instead) and the score is its wall time.  Whole solves are the
+    default because a short run keeps every problem live and never shows the
+    tail in which only the largest problems are left, where long work items
+    and few queue trips win.
     Returns {"chunk_elems", "block", "items_per_phase", "seconds", "table"}.
     """
     table = []
@@ -80,8 +84,8 @@ def autotune_batch(meshes, dirichlets, nus, b_fn, dtype=fem.F32X2, chunks=(1024,
                 continue
             for it in items:
                 x = torch.zeros(B.n_nodes, dtype=torch.float64, device="cuda")
-                opts = fem.batch_opts(dtype=dtype, max_iter=iters, block=BS, items_per_phase=it, use_graph=0,
-                                      watchdog_seconds=60.0)
+                opts = fem.batch_opts(dtype=dtype, rtol=rtol, max_iter=iters if iters else 100000, block=BS,
+                                      items_per_phase=it, use_graph=0, watchdog_seconds=60.0)
                 torch.cuda.synchronize()
                 t = time.perf_counter()
                 B.solve(opts, K, M, nus, b, x, allow=(fem.FEM_ENOCONV, fem.FEM_OK))

@@ -109,6 +109,9 @@ def test_autotuners_return_valid_schedules():
 
     rb = autotune.autotune_batch(meshes, dirs, [1.0, 0.1], b_fn, chunks=(256,), blocks=(256,), items=(1, 4), iters=10)
     assert rb["items_per_phase"] in (1, 4) and len(rb["table"]) == 2
+    # default: every candidate is scored on whole solves
+    rb = autotune.autotune_batch(meshes, dirs, [1.0, 0.1], b_fn, chunks=(256,), blocks=(256,), items=(2, 4))
+    assert rb["items_per_phase"] in (2, 4) and len(rb["table"]) == 2 and all(t["seconds"] > 0 for t in rb["table"])
 
 
 def test_adaptive_grouping_gives_identical_bits():
